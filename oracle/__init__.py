@@ -1,0 +1,246 @@
+"""CPU FP64 oracle for the Langevin droplet-aggregation model (arXiv:2501.04456).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code with
+the GPU library: the C source (``ldo.c``) has its own header, its own Philox,
+its own parameter struct, and this binding defines its own ctypes layout.
+
+Each wrapper below cites the passage of the paper it follows; the formulas
+themselves are in ``ldo.c``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libldo.so")
+MAX_TYPES = 8
+
+CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+          "-Wall", "-Wextra"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile ldo.c into libldo.so with gcc (generic x86-64, no fast-math)."""
+    srcs = [os.path.join(_HERE, f) for f in ("ldo.c", "ldo_ff.c")]
+    srcs = [s for s in srcs if os.path.exists(s)]
+    cmd = ["gcc", *CFLAGS, "-o", _LIB_PATH, *srcs, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("n_types", C.c_int32), ("use_eps_matrix", C.c_int32),
+        ("sigma", C.c_double * MAX_TYPES), ("eps", C.c_double * MAX_TYPES),
+        ("mass", C.c_double * MAX_TYPES), ("gamma", C.c_double * MAX_TYPES),
+        ("k_wall", C.c_double * MAX_TYPES), ("wall_offset", C.c_double * MAX_TYPES),
+        ("eps_matrix", C.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("lj_cut", C.c_double), ("coul_cut", C.c_double), ("bjerrum", C.c_double),
+        ("kT", C.c_double), ("gravity", C.c_double * 3), ("omega", C.c_double),
+        ("rotation", C.c_int32), ("wall_band", C.c_int32), ("noise", C.c_int32),
+        ("reserved", C.c_int32), ("jump_max", C.c_double),
+    ]
+
+
+class _Radius(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("R0", C.c_double),
+                ("R1", C.c_double), ("T", C.c_double), ("a", C.c_double),
+                ("R_min", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.ldo_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                        C.POINTER(C.c_uint32)]
+        L.ldo_gauss3.argtypes = [C.c_int64, C.c_int64, C.c_uint64, C.c_uint32, dp]
+        L.ldo_radius_at.argtypes = [C.POINTER(_Radius), C.c_double]
+        L.ldo_radius_at.restype = C.c_double
+        L.ldo_pair_forces.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp,
+                                      C.POINTER(_Params), C.POINTER(C.c_int64), C.c_int64,
+                                      dp, dp, dp]
+        L.ldo_external_force.argtypes = [dp, C.c_int32, C.POINTER(_Params), C.c_double, dp]
+        L.ldo_run.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp, C.POINTER(C.c_int64),
+                              C.POINTER(_Params), C.POINTER(_Radius), C.c_double, C.c_int64,
+                              C.c_uint64, C.POINTER(C.c_int64), dp]
+        L.ldo_run.restype = C.c_int64
+        L.ldo_diagnostics.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp,
+                                      C.POINTER(_Params), C.c_double, dp]
+        L.ldo_rdf.argtypes = [C.c_int64, dp, C.c_double, C.c_int32, C.c_double, dp,
+                              C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), dp, dp]
+        L.ldo_fractal.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_double,
+                                  C.c_int32, dp, C.POINTER(C.c_int64)]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _lp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def make_params(p) -> _Params:
+    """Marshal a workloads.Params into the oracle's own struct."""
+    s = _Params()
+    T = len(p.sigma)
+    s.n_types = T
+    for name in ("sigma", "eps", "mass", "gamma", "k_wall", "wall_offset"):
+        arr = getattr(s, name)
+        for t, v in enumerate(getattr(p, name)):
+            arr[t] = float(v)
+    if p.eps_matrix is not None:
+        s.use_eps_matrix = 1
+        for a in range(T):
+            for b in range(T):
+                s.eps_matrix[a * MAX_TYPES + b] = float(p.eps_matrix[a][b])
+    s.lj_cut = p.lj_cut
+    s.coul_cut = p.coul_cut
+    s.bjerrum = p.bjerrum
+    s.kT = p.kT
+    for c in range(3):
+        s.gravity[c] = float(p.gravity[c])
+    s.omega = p.omega
+    s.rotation = p.rotation
+    s.wall_band = p.wall_band
+    s.noise = p.noise
+    s.jump_max = p.jump_max
+    return s
+
+
+def make_radius(r) -> _Radius:
+    s = _Radius()
+    s.kind, s.R0, s.R1, s.T, s.a, s.R_min = r.kind, r.R0, r.R1, r.T, r.a, r.R_min
+    return s
+
+
+# ---------------------------------------------------------------------------
+# Wrappers
+# ---------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """Philox4x32-10 block (the counter-based noise generator)."""
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().ldo_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def gauss3(pid: int, step: int, seed: int, tag: int = 0) -> np.ndarray:
+    out = np.zeros(3)
+    lib().ldo_gauss3(pid, step, seed, tag, _dp(out))
+    return out
+
+
+def radius_at(radius, t: float) -> float:
+    """Droplet radius at time t (section 2.1; section 2.2 step (iii))."""
+    return lib().ldo_radius_at(C.byref(make_radius(radius)), t)
+
+
+def pair_forces(pos, type_, charge, params, rows=None):
+    """Pair forces (section 2.2 step (ii)): returns (F [m,3], S [m], U [2])."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    type_ = np.ascontiguousarray(type_, dtype=np.int32)
+    q = np.ascontiguousarray(charge, dtype=np.float64)
+    n = len(type_)
+    rows_a = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    m = n if rows is None else len(rows_a)
+    F = np.zeros((m, 3))
+    S = np.zeros(m)
+    U = np.zeros(2)
+    p = make_params(params)
+    lib().ldo_pair_forces(n, _dp(pos), _ip(type_), _dp(q), C.byref(p), _lp(rows_a), m,
+                          _dp(F), _dp(S), _dp(U))
+    return F, S, U
+
+
+def external_force(x, t: int, params, R: float) -> np.ndarray:
+    """External force (section 2.2 steps (iv)-(v)) on one particle."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    F = np.zeros(3)
+    lib().ldo_external_force(_dp(x), int(t), C.byref(make_params(params)), R, _dp(F))
+    return F
+
+
+class State:
+    """Oracle trajectory state: FP64 positions, step counter and time."""
+
+    def __init__(self, w, pos=None, ids=None):
+        self.w = w
+        self.x = np.array(w.pos if pos is None else pos, dtype=np.float64).reshape(-1, 3).copy()
+        self.type = np.ascontiguousarray(w.type, dtype=np.int32)
+        self.q = np.ascontiguousarray(w.charge, dtype=np.float64)
+        self.ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.int64)
+        self.step = 0
+        self.t = 0.0
+        self.params = w.params
+        self.radius = w.radius
+        self.seed = w.seed
+
+    def run(self, n_steps: int, dt: float = None) -> int:
+        """Overdamped Euler-Maruyama steps (section 2.2 step (vi))."""
+        dt = self.w.dt if dt is None else dt
+        st = C.c_int64(self.step)
+        tt = C.c_double(self.t)
+        bad = lib().ldo_run(len(self.type), _dp(self.x), _ip(self.type), _dp(self.q),
+                            _lp(self.ids), C.byref(make_params(self.params)),
+                            C.byref(make_radius(self.radius)), dt, n_steps, self.seed,
+                            C.byref(st), C.byref(tt))
+        self.step = st.value
+        self.t = tt.value
+        return bad
+
+    def diagnostics(self, R=None) -> np.ndarray:
+        R = radius_at(self.radius, self.t) if R is None else R
+        out = np.zeros(10)
+        lib().ldo_diagnostics(len(self.type), _dp(self.x), _ip(self.type), _dp(self.q),
+                              C.byref(make_params(self.params)), R, _dp(out))
+        return out
+
+
+def rdf(x, r_max: float, n_bins: int, V: float, centre=(0.0, 0.0, 0.0)):
+    """RDF Eq. (6) and radial concentration Eq. (8) (section 3.2).
+    Returns (pair counts, centre counts, g, cbar)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    n = len(x)
+    counts = np.zeros(n_bins, dtype=np.uint64)
+    cc = np.zeros(n_bins, dtype=np.uint64)
+    g = np.zeros(n_bins)
+    cbar = np.zeros(n_bins)
+    ctr = np.ascontiguousarray(centre, dtype=np.float64)
+    lib().ldo_rdf(n, _dp(x), r_max, n_bins, V, _dp(ctr),
+                  counts.ctypes.data_as(C.POINTER(C.c_uint64)),
+                  cc.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(g), _dp(cbar))
+    return counts, cc, g, cbar
+
+
+def fractal(x, k_f: float, d: float, eps0: float, max_scales: int = 32):
+    """Eqs. (2)-(4) and box counting (section 3.1).
+    Returns (R_g, D_f, D_box, n_scales, box_counts)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(4)
+    bc = np.zeros(max_scales, dtype=np.int64)
+    lib().ldo_fractal(len(x), _dp(x), k_f, d, eps0, max_scales, _dp(out), _lp(bc))
+    K = int(out[3])
+    return out[0], out[1], out[2], K, bc[:K].copy()

@@ -1,0 +1,139 @@
+/*
+ * ldo.h -- CPU FP64 oracle for the Langevin droplet-aggregation model of
+ * Derkachov et al., "A numerical toy model of Langevin dynamics provides
+ * real-time visualization of colloidal microdroplet evaporation"
+ * (arXiv:2501.04456).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously-correct reference
+ * that the GPU library is checked against.  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it.  It shares no
+ * code, header, table or helper with the GPU library; neither side includes
+ * or links the other.
+ *
+ * Everything is plain scalar C in double precision.  Sums over particles run
+ * in ascending index order with Neumaier compensation, so results do not
+ * depend on the number of OpenMP threads.
+ *
+ * Units are reduced: lengths in units of the type-0 diameter, energies in kT
+ * units where kT is a parameter, charges in elementary charges.
+ *
+ * Parity status per function is stated next to each declaration.  Every
+ * function below is pinned by CPU tests against closed forms, invariants,
+ * brute force or an independent implementation, unless it says
+ * "parity unpinned".
+ */
+#ifndef LDO_H
+#define LDO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LDO_MAX_TYPES 8
+
+/* Physical parameters of one droplet (section 2.1 lists the interactions:
+ * LJ and Coulomb between NPs; viscosity, centrifugal force, gravity and the
+ * surface spring as external forces; Brownian motion). */
+typedef struct {
+    int32_t n_types;
+    int32_t use_eps_matrix;          /* 0: Lorentz-Berthelot eps_ij = sqrt(eps_i eps_j) */
+    double sigma[LDO_MAX_TYPES];     /* LJ size = contact diameter; NP radius = sigma/2 */
+    double eps[LDO_MAX_TYPES];       /* LJ well depth per type */
+    double mass[LDO_MAX_TYPES];      /* buoyancy-corrected mass (gravity, centrifugal) */
+    double gamma[LDO_MAX_TYPES];     /* Stokes drag coefficient; mobility = 1/gamma */
+    double k_wall[LDO_MAX_TYPES];    /* surface spring constant per type */
+    double wall_offset[LDO_MAX_TYPES]; /* spring equilibrium distance inside the surface */
+    double eps_matrix[LDO_MAX_TYPES * LDO_MAX_TYPES];
+    double lj_cut;                   /* LJ range in units of sigma_ij (truncated, not shifted) */
+    double coul_cut;                 /* <= 0: Coulomb over all pairs; > 0: truncated at this r */
+    double bjerrum;                  /* Bjerrum length l_B */
+    double kT;                       /* thermal energy; sets the Coulomb scale and noise */
+    double gravity[3];               /* acceleration vector; force = mass * gravity */
+    double omega;                    /* effective rotation rate */
+    int32_t rotation;                /* 0: isotropic centrifugal m w^2 x; 1: about z axis */
+    int32_t wall_band;               /* 1: spring acts only for | |x| - R | < sigma/2 */
+    int32_t noise;                   /* 0: off, 1: Gaussian, 2: fixed magnitude, random direction */
+    int32_t reserved;
+    double jump_max;                 /* per-step displacement component flagged as a blow-up */
+} ldo_params;
+
+/* Droplet radius schedule (section 2.1: radius-square law with a freely set
+ * rate; section 2.2 step (iii)). */
+enum { LDO_R_CONST = 0, LDO_R_LINEAR = 1, LDO_R_SQUARE_LAW = 2 };
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double R0, R1, T;   /* linear: R0 -> R1 over time T, then constant */
+    double a;           /* square law: R^2 = R0^2 - 2 a t (a < 0: condensation) */
+    double R_min;       /* square law: clamp R >= R_min (dry aggregate) */
+} ldo_radius;
+
+/* --- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Pinned against
+ *     rocRAND's independent host implementation and by statistics. */
+void ldo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Three standard normal variates for particle `id` at step `step` with the
+ * given seed and stream tag (Box-Muller on Philox output).  Pinned by
+ * moments and by the uniform mapping's exactness. */
+void ldo_gauss3(int64_t id, int64_t step, uint64_t seed, uint32_t tag, double xi[3]);
+
+/* R(t).  Pinned by closed forms. */
+double ldo_radius_at(const ldo_radius* R, double t);
+
+/* Pair forces (section 2.2 step (ii)) on the particles listed in rows
+ * (rows == NULL: all n, in order).  pos is [n*3] FP64.  Outputs per listed
+ * row: F[r*3..] (FP64), S[r] = sum_j |f_LJ,ij| + |f_C,ij| (conditioning
+ * scale), and U[0..1] += per-row half-sums of LJ and Coulomb energies (so
+ * that with rows == NULL they are the total pair energies).  Any output may
+ * be NULL.  Pinned by closed forms, Newton's third law, F = -grad U and brute
+ * force. */
+void ldo_pair_forces(int64_t n, const double* pos, const int32_t* type, const double* q,
+                     const ldo_params* p, const int64_t* rows, int64_t n_rows,
+                     double* F, double* S, double* U);
+
+/* External force on one particle at position x, type t, droplet radius R
+ * (section 2.2 steps (iv)-(v)): surface spring, gravity, centrifugal.  Drag
+ * enters the update through the mobility.  Pinned by closed forms. */
+void ldo_external_force(const double x[3], int32_t t, const ldo_params* p, double R,
+                        double F[3]);
+
+/* Overdamped Langevin (Euler-Maruyama) steps (section 2.2 step (vi), read in
+ * the overdamped limit):
+ *   x <- x + mu dt (F_pair + F_ext(R(t + dt))) + sqrt(2 kT mu dt) xi
+ * x is [n*3] FP64, updated in place.  ids[i] is the Philox stream id of
+ * particle i (NULL: i).  *step and *t are the global step counter and time,
+ * advanced in place.  Returns the first step index whose update was
+ * non-finite or exceeded jump_max, or -1.  Pinned by settling, relaxation,
+ * centrifugal growth, free diffusion and equipartition. */
+int64_t ldo_run(int64_t n, double* x, const int32_t* type, const double* q,
+                const int64_t* ids, const ldo_params* p, const ldo_radius* R,
+                double dt, int64_t n_steps, uint64_t seed, int64_t* step, double* t);
+
+/* Diagnostics (FP64): out[0] U_LJ, out[1] U_C, out[2] U_wall, out[3] U_grav,
+ * out[4] U_centrifugal, out[5..7] net pair force, out[8] max |F_pair_i|,
+ * out[9] max |x_i|.  R is the radius used for the wall. */
+void ldo_diagnostics(int64_t n, const double* x, const int32_t* type, const double* q,
+                     const ldo_params* p, double R, double out[10]);
+
+/* Radial distribution function, Eq. (6), and radial concentration, Eq. (8).
+ * Bins are [b*dr, (b+1)*dr) with dr = r_max / n_bins.  counts[b] is the
+ * number of unordered pairs in bin b; ccounts[b] the number of particles at
+ * distance from `centre` in bin b.  V is the sample volume.  g and cbar may
+ * be NULL.  Pinned by brute force, lattice shells and the uniform ball. */
+void ldo_rdf(int64_t n, const double* x, double r_max, int32_t n_bins, double V,
+             const double centre[3], uint64_t* counts, uint64_t* ccounts,
+             double* g, double* cbar);
+
+/* Fractal dimension from the radius of gyration, Eqs. (2)-(4), with
+ * prefactor k_f and mean NP diameter d: out[0] = R_g, out[1] = D_f.
+ * Box counting: out[2] = D_box, out[3] = number of scales used; occupied-box
+ * counts at eps_k = eps0 * 2^k go to box_counts[k] (k < max_scales).
+ * Pinned by Eq. (2) round trip and lattice / Sierpinski fractals. */
+void ldo_fractal(int64_t n, const double* x, double k_f, double d, double eps0,
+                 int32_t max_scales, double out[4], int64_t* box_counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

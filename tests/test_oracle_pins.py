@@ -1,0 +1,505 @@
+"""Pins for the CPU FP64 oracle.
+
+Each test checks the oracle against something other than itself: an
+independent implementation (rocRAND's Philox), closed forms of the physics
+(LJ minimum, cutoff force, Coulomb's law through the shell theorem, settling,
+relaxation, diffusion, discrete equipartition), invariants (Newton's third
+law, translation / rotation covariance, F = -grad U), library routines
+(pdist + histogram for the RDF) and textbook fractals for box counting.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2501_04456_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def one_type(**kw):
+    p = W.Params(sigma=[1.0], eps=[1.0], mass=[1.0], gamma=[1.0], k_wall=[0.0],
+                 wall_offset=[0.0], bjerrum=0.7, kT=1.0, noise=W.NOISE_OFF)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+# ---------------------------------------------------------------------------
+# Philox
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    if shutil.which("hipcc") is None or not os.path.exists("/opt/rocm/include/rocrand"):
+        pytest.skip("hipcc / rocRAND headers not available")
+    out = tmp_path_factory.mktemp("prr") / "prr"
+    subprocess.run(["hipcc", "--offload-arch=gfx950", "-O1",
+                    os.path.join(HERE, "helpers", "philox_rocrand_ref.cpp"), "-o", str(out)],
+                   check=True, cwd=str(out.parent))
+    return str(out)
+
+
+def test_philox_matches_rocrand(oracle_lib, rocrand_ref):
+    rng = np.random.default_rng(7)
+    cases = [(0, 0, 0, 0, 0, 0), (1, 0, 0, 0, 0, 0), (0, 1, 0, 0, 0, 0),
+             (123, 456, 789, 3, 0xDEADBEEF, 0x01234567)]
+    for _ in range(60):
+        c = rng.integers(0, 2**32, size=6, dtype=np.uint64)
+        c[1] %= 2**30   # rocRAND's offset argument is 4 * (c1:c0) in 64 bits
+        cases.append(tuple(int(v) for v in c))
+    txt = "".join("%x %x %x %x %x %x\n" % c for c in cases)
+    res = subprocess.run([rocrand_ref], input=txt, capture_output=True, text=True, check=True)
+    lines = res.stdout.strip().split("\n")
+    assert len(lines) == len(cases)
+    for c, line in zip(cases, lines):
+        ref = [int(v, 16) for v in line.split()]
+        got = oracle_lib.philox4x32_10(c[:4], c[4:])
+        assert list(got) == ref, (c, [hex(v) for v in got], line)
+
+
+def test_gauss3_statistics(oracle_lib):
+    from scipy import stats
+    xs = np.array([oracle_lib.gauss3(i, 17, 99) for i in range(40000)])
+    assert abs(xs.mean()) < 4 * 1 / math.sqrt(xs.size)
+    assert abs(xs.var() - 1.0) < 4 * math.sqrt(2.0 / xs.size)
+    for c in range(3):
+        assert stats.kstest(xs[:, c], "norm").pvalue > 1e-3
+    # components independent
+    cc = np.corrcoef(xs.T)
+    assert np.all(np.abs(cc - np.eye(3)) < 0.03)
+    # distinct steps, seeds and ids give distinct streams
+    assert not np.allclose(oracle_lib.gauss3(5, 0, 1), oracle_lib.gauss3(5, 1, 1))
+    assert not np.allclose(oracle_lib.gauss3(5, 0, 1), oracle_lib.gauss3(5, 0, 2))
+    assert not np.allclose(oracle_lib.gauss3(5, 0, 1), oracle_lib.gauss3(6, 0, 1))
+
+
+# ---------------------------------------------------------------------------
+# Radius schedule
+# ---------------------------------------------------------------------------
+
+def test_radius_closed_forms(oracle_lib):
+    r = W.Radius(kind=W.RADIUS_LINEAR, R0=40.0, R1=15.0, T=1.0)
+    assert oracle_lib.radius_at(r, 0.0) == 40.0
+    assert oracle_lib.radius_at(r, 0.5) == pytest.approx(27.5, abs=1e-14)
+    assert oracle_lib.radius_at(r, 1.0) == 15.0
+    assert oracle_lib.radius_at(r, 3.0) == 15.0
+    s = W.Radius(kind=W.RADIUS_SQUARE_LAW, R0=10.0, a=2.0, R_min=3.0)
+    # dR/dt = -a/R  <=>  R^2 = R0^2 - 2 a t
+    t = 5.0
+    assert oracle_lib.radius_at(s, t) == pytest.approx(math.sqrt(100 - 20), rel=1e-15)
+    dt = 1e-6
+    dRdt = (oracle_lib.radius_at(s, t + dt) - oracle_lib.radius_at(s, t - dt)) / (2 * dt)
+    assert dRdt == pytest.approx(-2.0 / oracle_lib.radius_at(s, t), rel=1e-6)
+    assert oracle_lib.radius_at(s, 100.0) == 3.0
+    c = W.Radius(kind=W.RADIUS_SQUARE_LAW, R0=10.0, a=-1.0, R_min=3.0)  # condensation
+    assert oracle_lib.radius_at(c, 2.0) > 10.0
+    k = W.Radius(kind=W.RADIUS_CONST, R0=7.0)
+    assert oracle_lib.radius_at(k, 123.0) == 7.0
+
+
+# ---------------------------------------------------------------------------
+# Pair forces
+# ---------------------------------------------------------------------------
+
+def two_body(oracle_lib, r, p, q=(0.0, 0.0), types=(0, 0)):
+    pos = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
+    F, S, U = oracle_lib.pair_forces(pos, np.array(types), np.array(q), p)
+    return F, S, U
+
+
+def test_lj_minimum_and_depth(oracle_lib):
+    p = one_type()
+    rmin = 2 ** (1 / 6)
+    F, S, U = two_body(oracle_lib, rmin, p)
+    assert np.max(np.abs(F)) < 1e-12
+    assert U[0] == pytest.approx(-1.0, rel=1e-13)
+    # stiffness at the minimum: U'' = 36 * 2^(2/3) eps / sigma^2 = 57.146
+    h = 1e-5
+    Fp, _, _ = two_body(oracle_lib, rmin + h, p)
+    Fm, _, _ = two_body(oracle_lib, rmin - h, p)
+    k = -(Fp[1, 0] - Fm[1, 0]) / (2 * h)
+    assert k == pytest.approx(57.146, rel=1e-4)
+    # repulsive inside, attractive outside the minimum
+    F, _, _ = two_body(oracle_lib, 1.0, p)
+    assert F[1, 0] > 0 and F[0, 0] < 0
+    F, _, _ = two_body(oracle_lib, 1.5, p)
+    assert F[1, 0] < 0
+
+
+def test_lj_cutoff_truncated_not_shifted(oracle_lib):
+    p = one_type()
+    F, _, U = two_body(oracle_lib, 2.5 - 1e-12, p)
+    # force just inside the cutoff: 24 (2 * 2.5^-13 - 2.5^-7) = -0.03900
+    assert F[1, 0] == pytest.approx(-0.039000, abs=2e-6)
+    assert U[0] == pytest.approx(4 * (2.5 ** -12 - 2.5 ** -6), rel=1e-9)
+    F, _, U = two_body(oracle_lib, 2.5, p)  # strict cutoff
+    assert np.all(F == 0) and U[0] == 0.0
+    F, _, _ = two_body(oracle_lib, 3.0, p)
+    assert np.all(F == 0)
+
+
+def test_lj_mixing(oracle_lib):
+    p = W.Params(sigma=[1.0, 2.0], eps=[1.0, 4.0], mass=[1, 1], gamma=[1, 1], k_wall=[0, 0],
+                 wall_offset=[0, 0], noise=0)
+    rmin = 2 ** (1 / 6) * 1.5
+    F, _, U = two_body(oracle_lib, rmin, p, types=(0, 1))
+    assert np.max(np.abs(F)) < 1e-12
+    assert U[0] == pytest.approx(-2.0, rel=1e-13)   # sqrt(1 * 4)
+    p.eps_matrix = [[1.0, 0.3], [0.3, 4.0]]
+    F, _, U = two_body(oracle_lib, rmin, p, types=(0, 1))
+    assert U[0] == pytest.approx(-0.3, rel=1e-13)
+    F, _, U = two_body(oracle_lib, 2 ** (1 / 6) * 2.0, p, types=(1, 1))
+    assert U[0] == pytest.approx(-4.0, rel=1e-13)
+
+
+def test_coulomb_shell_theorem(oracle_lib):
+    """Charges spread evenly over a sphere act on a probe like a point charge
+    at the centre when outside, and nearly cancel inside (Gauss's law)."""
+    M = 4000
+    k = np.arange(M) + 0.5
+    th = np.arccos(1 - 2 * k / M)
+    ph = np.pi * (1 + 5 ** 0.5) * k
+    Rs = 20.0
+    shell = Rs * np.stack([np.cos(ph) * np.sin(th), np.sin(ph) * np.sin(th), np.cos(th)], 1)
+    p = one_type(eps=[0.0], bjerrum=0.9, kT=1.3)
+    qs = 0.01
+    for probe_r, expect in [(60.0, None), (3.0, 0.0)]:
+        pos = np.vstack([shell, [[probe_r, 0.0, 0.0]]])
+        q = np.full(M + 1, qs)
+        q[-1] = 1.0
+        F, S, _ = oracle_lib.pair_forces(pos, np.zeros(M + 1, np.int32), q, p, rows=[M])
+        if expect is None:
+            Fexp = 1.3 * 0.9 * (M * qs) * 1.0 / probe_r ** 2
+            assert F[0, 0] == pytest.approx(Fexp, rel=1e-4)
+            assert abs(F[0, 1]) < 1e-4 * Fexp and abs(F[0, 2]) < 1e-4 * Fexp
+        else:
+            assert np.linalg.norm(F[0]) < 2e-3 * S[0]
+
+
+def test_coulomb_sign_and_range(oracle_lib):
+    p = one_type(eps=[0.0])
+    F, _, U = two_body(oracle_lib, 4.0, p, q=(1.0, 1.0))
+    assert F[1, 0] > 0 and F[0, 0] < 0          # like charges repel
+    assert U[1] > 0
+    F2, _, _ = two_body(oracle_lib, 8.0, p, q=(1.0, 1.0))
+    assert F[1, 0] / F2[1, 0] == pytest.approx(4.0, rel=1e-13)   # inverse square
+    F3, _, _ = two_body(oracle_lib, 4.0, p, q=(1.0, -2.0))
+    assert F3[1, 0] == pytest.approx(-2 * F[1, 0], rel=1e-14)
+    p.coul_cut = 5.0
+    F4, _, _ = two_body(oracle_lib, 6.0, p, q=(1.0, 1.0))
+    assert np.all(F4 == 0)
+
+
+def random_system(n, seed, R=6.0):
+    w = W.config_large(n=n, seed=seed)
+    return w
+
+
+def test_newton_third_law_and_symmetries(oracle_lib):
+    w = W.config_large(n=300, seed=11)
+    x = w.pos.astype(np.float64)
+    F, S, U = oracle_lib.pair_forces(x, w.type, w.charge, w.params)
+    net = F.sum(0)
+    assert np.all(np.abs(net) < 1e-12 * S.sum())
+    # translation invariance
+    F2, _, U2 = oracle_lib.pair_forces(x + np.array([3.25, -1.5, 0.75]), w.type, w.charge,
+                                       w.params)
+    assert np.all(np.abs(F2 - F) <= 1e-12 * S[:, None])
+    assert U2 == pytest.approx(U, rel=1e-12)
+    # rotation covariance
+    a, b = 0.7, -0.4
+    Rz = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
+    Rx = np.array([[1, 0, 0], [0, math.cos(b), -math.sin(b)], [0, math.sin(b), math.cos(b)]])
+    Rm = Rx @ Rz
+    F3, _, _ = oracle_lib.pair_forces(x @ Rm.T, w.type, w.charge, w.params)
+    assert np.all(np.abs(F3 - F @ Rm.T) <= 1e-12 * S[:, None])
+    # rows subset equals full
+    rows = [5, 17, 299, 0]
+    Fr, Sr, _ = oracle_lib.pair_forces(x, w.type, w.charge, w.params, rows=rows)
+    assert np.array_equal(Fr, F[rows]) and np.array_equal(Sr, S[rows])
+
+
+def test_force_is_minus_energy_gradient(oracle_lib):
+    w = W.config_large(n=64, seed=5)
+    # a jittered lattice: many pairs inside the LJ range, none overlapping
+    rng = np.random.default_rng(2)
+    g_ = np.arange(4) * 1.8
+    x = np.stack(np.meshgrid(g_, g_, g_, indexing="ij"), -1).reshape(-1, 3)
+    x = x + rng.uniform(-0.25, 0.25, size=x.shape)
+    from scipy.spatial.distance import pdist
+    assert pdist(x).min() > 1.0
+    F, _, _ = oracle_lib.pair_forces(x, w.type, w.charge, w.params)
+    h = 1e-6
+    sig = np.array(w.params.sigma)[w.type]
+    cut = w.params.lj_cut * 0.5 * (sig[:, None] + sig[None, :])
+    d = np.linalg.norm(x[:, None] - x[None], axis=-1)
+    checked = 0
+    for i in range(0, 64, 5):
+        # skip particles with a neighbour within 1e-3 of a cutoff (U jumps there)
+        if np.any(np.abs(np.delete(d[i] - cut[i], i)) < 1e-3):
+            continue
+        for c in range(3):
+            xp = x.copy(); xp[i, c] += h
+            xm = x.copy(); xm[i, c] -= h
+            Up = oracle_lib.pair_forces(xp, w.type, w.charge, w.params)[2].sum()
+            Um = oracle_lib.pair_forces(xm, w.type, w.charge, w.params)[2].sum()
+            g = -(Up - Um) / (2 * h)
+            assert g == pytest.approx(F[i, c], rel=1e-6, abs=1e-6)
+        checked += 1
+    assert checked >= 4
+
+
+def test_conditioning_scale(oracle_lib):
+    w = W.config_large(n=200, seed=3)
+    x = w.pos.astype(np.float64)
+    F, S, _ = oracle_lib.pair_forces(x, w.type, w.charge, w.params)
+    assert np.all(np.linalg.norm(F, axis=1) <= S * (1 + 1e-12))
+    # neutral particles with no LJ neighbour have S = 0 only if all others are
+    # out of range and q = 0
+    assert np.all(S[w.charge != 0] > 0)
+
+
+# ---------------------------------------------------------------------------
+# External forces and the integrator
+# ---------------------------------------------------------------------------
+
+def single(oracle_lib, p, R, x0, steps, dt, seed=1):
+    w = W.Workload("t", len(x0), np.zeros(len(x0), np.int32), np.zeros(len(x0)),
+                   np.asarray(x0, np.float64), p, R, dt, steps, seed)
+    st = oracle_lib.State(w)
+    bad = st.run(steps, dt)
+    return st, bad
+
+
+def independent(oracle_lib, p, R, x0, steps, dt, seed):
+    """Run each particle as its own one-particle system (no pair sum), with
+    Philox stream id equal to its index, as the integrator would for
+    non-interacting particles."""
+    out = np.empty_like(np.asarray(x0, np.float64))
+    for i, xi in enumerate(np.asarray(x0, np.float64)):
+        w = W.Workload("t", 1, np.zeros(1, np.int32), np.zeros(1), xi[None], p, R, dt,
+                       steps, seed)
+        st = oracle_lib.State(w, ids=[i])
+        assert st.run(steps, dt) == -1
+        out[i] = st.x[0]
+    return out
+
+
+def test_settling_velocity(oracle_lib):
+    p = one_type(mass=[2.0], gamma=[4.0], gravity=(0.0, 0.0, -0.05), eps=[0.0])
+    R = W.Radius(kind=W.RADIUS_CONST, R0=1e6)
+    st, bad = single(oracle_lib, p, R, [[1.0, 2.0, 3.0]], 1000, 1e-3)
+    assert bad == -1
+    # terminal velocity m g / gamma
+    assert st.x[0, 2] == pytest.approx(3.0 - 1000 * 1e-3 * 2.0 * 0.05 / 4.0, rel=1e-12)
+    assert st.x[0, 0] == 1.0 and st.x[0, 1] == 2.0
+    assert st.step == 1000 and st.t == pytest.approx(1.0, rel=1e-12)
+
+
+def test_wall_relaxation(oracle_lib):
+    """A wall at R_w = 0 is a full harmonic trap: x_n = (1 - k dt/gamma)^n x_0."""
+    p = one_type(k_wall=[50.0], gamma=[2.0], eps=[0.0])
+    R = W.Radius(kind=W.RADIUS_CONST, R0=0.0)
+    x0 = np.array([[0.3, -0.2, 0.5]])
+    st, _ = single(oracle_lib, p, R, x0, 200, 1e-3)
+    f = (1 - 50 * 1e-3 / 2.0) ** 200
+    assert np.allclose(st.x[0], f * x0[0], rtol=1e-12, atol=0)
+    # continuum limit exp(-k t / gamma): the log differs by the EM error
+    # n * (k dt / gamma)^2 / 2 to leading order
+    lg = np.log(st.x[0] / x0[0])
+    lead = 200 * (50 * 1e-3 / 2.0) ** 2 / 2
+    assert np.allclose(lg + 50 * 0.2 / 2.0, -lead, rtol=0.05)
+
+
+def test_wall_one_sided_and_band(oracle_lib):
+    p = one_type(k_wall=[10.0], eps=[0.0], wall_offset=[0.5])
+    F = oracle_lib.external_force([3.0, 0, 0], 0, p, 5.0)    # inside R_w = 4.5
+    assert np.all(F == 0)
+    F = oracle_lib.external_force([0, 6.0, 0], 0, p, 5.0)
+    assert F[1] == pytest.approx(-10.0 * 1.5) and F[0] == 0
+    p.wall_band = 1      # acts only within +-sigma/2 of R
+    F = oracle_lib.external_force([0, 6.0, 0], 0, p, 5.0)
+    assert np.all(F == 0)
+    F = oracle_lib.external_force([0, 0, 5.2], 0, p, 5.0)
+    assert F[2] == pytest.approx(-10.0 * 0.7)
+
+
+def test_centrifugal_growth_and_axis(oracle_lib):
+    p = one_type(omega=0.5, mass=[3.0], gamma=[2.0], eps=[0.0])
+    R = W.Radius(kind=W.RADIUS_CONST, R0=1e6)
+    x0 = np.array([[1.0, -2.0, 0.5]])
+    st, _ = single(oracle_lib, p, R, x0, 100, 1e-2)
+    f = (1 + 3.0 * 0.25 * 1e-2 / 2.0) ** 100
+    assert np.allclose(st.x[0], f * x0[0], rtol=1e-12)
+    p.rotation = 1
+    st, _ = single(oracle_lib, p, R, x0, 100, 1e-2)
+    assert np.allclose(st.x[0, :2], f * x0[0, :2], rtol=1e-12) and st.x[0, 2] == 0.5
+
+
+def test_free_diffusion_msd(oracle_lib):
+    """No forces: MSD = 6 D t with D = kT / gamma."""
+    n = 6000
+    p = one_type(eps=[0.0], gamma=[2.0], kT=1.5, noise=W.NOISE_GAUSS)
+    R = W.Radius(kind=W.RADIUS_CONST, R0=1e9)
+    x0 = np.zeros((n, 3))
+    x = independent(oracle_lib, p, R, x0, 20, 5e-3, seed=42)
+    msd = np.mean(np.sum((x - x0) ** 2, axis=1))
+    expect = 6 * (1.5 / 2.0) * 20 * 5e-3
+    assert msd / expect == pytest.approx(1.0, abs=3 * math.sqrt(2 / (3 * n)))
+    # the pair sum is inert for far-apart neutral particles: the same
+    # trajectories come out of one many-particle run
+    x0f = np.zeros((50, 3))
+    x0f[:, 0] = np.arange(50) * 1e3
+    w = W.Workload("t", 50, np.zeros(50, np.int32), np.zeros(50), x0f, p, R, 5e-3, 20, 42)
+    st = oracle_lib.State(w)
+    st.run(20)
+    assert np.allclose(st.x - x0f, x[:50] - x0[:50], rtol=0, atol=1e-9)
+    # fixed-magnitude kicks: every displacement has length sqrt(6 D dt)
+    p.noise = W.NOISE_FIXED
+    x1 = independent(oracle_lib, p, R, x0[:100], 1, 5e-3, seed=42)
+    step = np.linalg.norm(x1 - x0[:100], axis=1)
+    assert np.allclose(step, math.sqrt(6 * 0.75 * 5e-3), rtol=1e-12)
+
+
+def test_discrete_equipartition(oracle_lib):
+    """EM in a harmonic trap F = -k x has the stationary per-dimension
+    variance kT / (k (1 - k dt / (2 gamma))) exactly."""
+    n = 6000
+    k, dt, g, kT = 50.0, 1e-3, 1.0, 1.0
+    p = one_type(eps=[0.0], k_wall=[k], gamma=[g], kT=kT, noise=W.NOISE_GAUSS, jump_max=0)
+    R = W.Radius(kind=W.RADIUS_CONST, R0=0.0)   # wall at the centre: a full trap
+    x = independent(oracle_lib, p, R, np.zeros((n, 3)), 200, dt, seed=9)
+    samples = []
+    for blk in range(12):
+        # continue each particle's own stream: steps 200 + 40 blk ...
+        xs = np.empty_like(x)
+        for i in range(n):
+            w = W.Workload("t", 1, np.zeros(1, np.int32), np.zeros(1), x[i][None], p, R, dt,
+                           40, 9)
+            st = oracle_lib.State(w, ids=[i])
+            st.step = 200 + 40 * blk
+            st.run(40, dt)
+            xs[i] = st.x[0]
+        x = xs
+        samples.append(x.var(axis=0).mean())
+    v = float(np.mean(samples))
+    exact = kT / (k * (1 - k * dt / (2 * g)))
+    se = exact * math.sqrt(2 / (3 * n * 12))
+    assert abs(v - exact) < 4 * se
+    assert abs(v - kT / k) > 4 * se       # resolves the O(dt) correction
+
+
+def test_jump_flag(oracle_lib):
+    p = one_type(eps=[1.0], jump_max=0.5)
+    R = W.Radius(kind=W.RADIUS_CONST, R0=1e6)
+    x0 = [[0.0, 0.0, 0.0], [0.5, 0.0, 0.0]]    # deep overlap -> huge LJ force
+    st, bad = single(oracle_lib, p, R, x0, 3, 1e-3)
+    assert bad == 0
+
+
+# ---------------------------------------------------------------------------
+# RDF and concentration
+# ---------------------------------------------------------------------------
+
+def test_rdf_matches_pdist_histogram(oracle_lib):
+    from scipy.spatial.distance import pdist
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-5, 5, size=(300, 3))
+    counts, cc, g, cbar = oracle_lib.rdf(x, 4.0, 40, 1000.0, centre=(0.5, 0, 0))
+    ref, _ = np.histogram(pdist(x), bins=40, range=(0, 4.0))
+    assert np.array_equal(counts, ref)
+    refc, _ = np.histogram(np.linalg.norm(x - [0.5, 0, 0], axis=1), bins=40, range=(0, 4.0))
+    assert np.array_equal(cc, refc)
+
+
+def test_rdf_lattice_shells(oracle_lib):
+    L = 6
+    a = 1.0
+    g_ = np.arange(L) * a
+    x = np.stack(np.meshgrid(g_, g_, g_, indexing="ij"), -1).reshape(-1, 3)
+    counts, _, _, _ = oracle_lib.rdf(x, 1.8, 18, 1.0)
+    # nearest, face-diagonal and body-diagonal neighbour pairs of an L^3 cube
+    assert counts[10] == 3 * L * L * (L - 1)                  # r = 1
+    assert counts[14] == 6 * L * (L - 1) ** 2                 # r = sqrt 2
+    assert counts[17] == 4 * (L - 1) ** 3                     # r = sqrt 3
+    assert counts.sum() == counts[10] + counts[14] + counts[17]
+
+
+def test_rdf_uniform_ball(oracle_lib):
+    """Uniform points in a ball: with V the ball volume, g(r) is the ball's
+    normalised set covariance 1 - 3r/(4R) + r^3/(16R^3); C-bar is 1."""
+    rng = np.random.default_rng(11)
+    n, R = 6000, 10.0
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    x = v * (R * rng.random(n) ** (1 / 3))[:, None]
+    V = 4 / 3 * math.pi * R ** 3
+    counts, cc, g, cbar = oracle_lib.rdf(x, 8.0, 16, V)
+    edges = np.arange(17) * 0.5
+    dV = 4 / 3 * math.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    # expected pair counts from the covariance, integrated over each bin
+    rr = np.linspace(0, 8.0, 16 * 200 + 1)
+    cov = 1 - 3 * rr / (4 * R) + rr ** 3 / (16 * R ** 3)
+    dens = 4 * math.pi * rr ** 2 * cov * n * (n - 1) / (2 * V)
+    E = np.array([np.trapezoid(dens[200 * b:200 * b + 201], rr[200 * b:200 * b + 201])
+                  for b in range(16)])
+    assert np.all(np.abs(counts - E) < 5 * np.sqrt(E) + 1)
+    # C-bar: expected particle count n dV / V per bin
+    Ec = n * dV / V
+    assert np.all(np.abs(cc - Ec) < 5 * np.sqrt(Ec) + 1)
+    # and the normalisations of Eq. (6) / Eq. (8) turn those counts into ~1
+    assert np.all(np.abs(cbar[6:] - 1.0) < 5 / np.sqrt(Ec[6:]))
+    ref_g = np.interp((edges[:-1] + edges[1:]) / 2, rr, cov)
+    assert np.all(np.abs(g[4:] - ref_g[4:]) < 5 / np.sqrt(E[4:]) + 0.01)
+
+
+# ---------------------------------------------------------------------------
+# Fractal dimension
+# ---------------------------------------------------------------------------
+
+def test_fractal_equation_round_trip(oracle_lib):
+    """Build N points with a prescribed R_g, then Eq. (2) must return the D_f
+    that produced that R_g."""
+    rng = np.random.default_rng(1)
+    N, kf, d, Df = 5000, 1.593, 1.0, 2.3
+    Rg = 0.5 * d * (N / kf) ** (1 / Df)
+    v = rng.standard_normal((N, 3))
+    v -= v.mean(0)
+    v *= Rg / math.sqrt(np.mean(np.sum(v ** 2, 1)))
+    v += [10.0, -3.0, 2.0]
+    Rg_o, Df_o, _, _, _ = oracle_lib.fractal(v, kf, d, 1.0)
+    assert Rg_o == pytest.approx(Rg, rel=1e-12)
+    assert Df_o == pytest.approx(Df, rel=1e-12)
+
+
+def lattice(dim, L):
+    g_ = np.arange(L, dtype=np.float64) + 0.5
+    axes = [g_] * dim + [np.array([0.5])] * (3 - dim)
+    return np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, 3)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_box_counting_lattices(oracle_lib, dim):
+    L = {1: 4096, 2: 256, 3: 64}[dim]
+    x = lattice(dim, L)
+    _, _, Db, K, bc = oracle_lib.fractal(x, 1.593, 1.0, 1.0)
+    assert K >= 4
+    assert Db == pytest.approx(dim, abs=0.02)
+
+
+def test_box_counting_sierpinski_tetrahedron(oracle_lib):
+    """Level-L Sierpinski tetrahedron: D = ln 4 / ln 2 = 2."""
+    verts = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+    pts = np.zeros((1, 3))
+    L = 8
+    for lev in range(L):
+        s = 2.0 ** lev
+        pts = np.concatenate([pts + s * v for v in verts])
+    pts += 0.5
+    _, _, Db, K, bc = oracle_lib.fractal(pts, 1.593, 1.0, 1.0)
+    assert K >= 4
+    assert Db == pytest.approx(2.0, abs=0.05)
