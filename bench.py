@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark: steps/s and pair-interactions/s of the Langevin droplet model at
+N = 250000 (three NP types 50/30/20, sigma 1/1.3/2, eps 1/1.5/3, charges
++1/-1/0, sphere of radius 300, linear shrink to 112.5 over 1e4 steps of
+dt = 5e-4, gravity 0.05, omega 0.02, kT = 1, all-pairs Coulomb with l_B = 0.7).
+
+One step = the whole hot path: all-pairs LJ + Coulomb forces, external
+forces, Brownian noise and the overdamped update (plus the periodic spatial
+re-sort), for all N particles, inputs resident on the GPU.
+
+Prints one JSON line.  Extra objects:
+  roofline     -- the pair kernel (the dominant one), timed with HIP events on
+                  the library's stream during the timed steps; algorithmic
+                  FP32 work = 19 flops per ordered pair (Coulomb-only count).
+  cpu_baseline -- the FP64 oracle timed on the host on a bounded sample of
+                  rows of the same force evaluation, scaled to steps/s.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("steps/s & pair-interactions/s at N=2.5e5; learned vs direct at ≤1e-3 "
+          "force err")
+FLOPS_PER_PAIR = 19
+PEAK_FP32_TFLOPS = 157.3          # published MI355X FP32 vector peak (packed issue)
+PEAK_FP32_NONPACKED = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=250000)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def traffic_for(kernel: str, n: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2501_04456_amd", "csrc", "ld_pair.hip")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel)
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if rec and rec.get("source_sha256") == digest and rec.get("n") == n:
+            return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
+def cpu_baseline(w, target_s: float):
+    import numpy as np
+    import oracle
+    oracle.lib()
+    cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    rng = np.random.default_rng(123)
+    rows = rng.choice(w.n, 32, replace=False)
+    t0 = time.perf_counter()
+    oracle.pair_forces(w.pos, w.type, w.charge, w.params, rows=rows)
+    dt_cal = time.perf_counter() - t0
+    m = int(min(w.n, max(32, 32 * target_s / max(dt_cal, 1e-3))))
+    rows = rng.choice(w.n, m, replace=False)
+    t0 = time.perf_counter()
+    oracle.pair_forces(w.pos, w.type, w.charge, w.params, rows=rows)
+    el = time.perf_counter() - t0
+    step_s = el * w.n / m                 # pair sum dominates the step
+    return {
+        "value": 1.0 / step_s,
+        "unit": "steps/s",
+        "pair_interactions_per_s": m * (w.n - 1) / el,
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"pair forces of {m} random rows x all {w.n} particles "
+                  f"({el:.1f} s), scaled by N/rows to one step",
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2501_04456_amd import ldrop
+    from paper_2501_04456_amd import workloads as W
+
+    if not os.path.exists(ldrop.LIB_PATH):
+        from paper_2501_04456_amd import build as hipbuild
+        hipbuild.build()
+    torch.cuda.set_device(0)
+    w = W.config_large(n=a.n)
+    s = ldrop.System.from_workload(w)
+    tune = s.tuning()
+    s.step(a.warmup, w.dt)
+    s.sync()
+    torch.cuda.synchronize()
+    s.kernel_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    s.step(a.steps, w.dt)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    launches, pair_ms = s.kernel_time()
+    s.kernel_timing(False)
+    s.sync()
+    steps_per_s = a.steps / (ms / 1e3)
+    pairs = float(w.n) * (w.n - 1)
+    avg_pair_ms = pair_ms / max(launches, 1)
+    flops_launch = FLOPS_PER_PAIR * pairs
+    achieved = flops_launch / (avg_pair_ms / 1e3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "pair_interactions_per_s": pairs * steps_per_s,
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms / a.steps,
+        "wall_s": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair math, f64 totals",
+        "data": "synthetic",
+        "config": {"workload": "large: N=250000 three-type droplet, all-pairs LJ+Coulomb, "
+                               "full external forces, overdamped Langevin, dt=5e-4",
+                   "n": w.n, "dt": w.dt, "tuning": tune},
+        "roofline": {
+            "kernel": "k_pair (all-pairs forces)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED,
+            "traffic": traffic_for("k_pair", w.n),
+            "flops_per_launch": flops_launch,
+            "avg_launch_ms": avg_pair_ms,
+            "launches": launches,
+        },
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * ldrop.h -- C ABI of libldrop, an MI355X (gfx950) engine for the Langevin
+ * nanoparticle-aggregation model of Derkachov et al., "A numerical toy model
+ * of Langevin dynamics provides real-time visualization of colloidal
+ * microdroplet evaporation" (arXiv:2501.04456).
+ *
+ * One context holds one droplet: N nanoparticles (NPs) of up to LD_MAX_TYPES
+ * types in a spherical droplet whose radius R(t) follows a schedule.  Per
+ * step (section 2.2, steps (ii)-(vi)) the library evaluates
+ *   - pair forces over all NP pairs: Lennard-Jones truncated (not shifted) at
+ *     lj_cut * sigma_ij plus Coulomb over all pairs;
+ *   - external forces: the surface spring at R(t), gravity, the centrifugal
+ *     force, with viscous drag as the mobility 1/gamma;
+ *   - an overdamped Langevin (Euler-Maruyama) update with Gaussian Brownian
+ *     noise from a counter-based Philox4x32-10 stream.
+ *
+ * Units are reduced: lengths in units of the type-0 diameter, energies in
+ * units where kT is a parameter, charges in elementary charges.  Forces:
+ *   f_LJ(i<-j) = 24 eps_ij [2 (s/r)^12 - (s/r)^6] r_ij / r^2  if r < lj_cut*s
+ *   f_C (i<-j) = kT l_B q_i q_j r_ij / r^3
+ * with r_ij = x_i - x_j, s = sigma_ij = (sigma_i + sigma_j)/2 and
+ * eps_ij = sqrt(eps_i eps_j) (Lorentz-Berthelot) or an explicit matrix.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an ld_status; on failure ld_last_error() describes
+ *     it.  No C++ exception crosses the ABI.
+ *   - Array arguments may be host or device pointers; the library asks the
+ *     HIP runtime which one it got.  The caller owns every array; inputs are
+ *     copied during the call and never retained.
+ *   - Outputs are in the caller's original particle order.
+ *   - Work is enqueued on the HIP stream given to ld_init.  ld_step returns
+ *     without waiting; calls that return values to host memory wait for the
+ *     stream.  Blow-ups detected on the device during ld_step are reported as
+ *     LD_ENONFINITE by the next waiting call (ld_sync, ld_get_*, ld_forces).
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Pair math runs in FP32; per-particle force totals, the external forces,
+ *     the update and all diagnostics in FP64.  Positions are kept as an FP32
+ *     pair (hi, lo) whose sum carries about 48 significant bits.
+ */
+#ifndef LDROP_H
+#define LDROP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LD_MAX_TYPES 8
+
+typedef struct ld_ctx ld_ctx;
+typedef int32_t ld_status;
+
+enum {
+    LD_OK = 0,
+    LD_EINVAL = -1,        /* an argument is out of range (message says which) */
+    LD_ENOMEM = -2,        /* device allocation failed */
+    LD_EHIP = -3,          /* a HIP runtime call failed */
+    LD_ENONFINITE = -4,    /* a step produced a non-finite or too large move */
+    LD_ESTATE = -5,        /* call not valid in the context's current state */
+    LD_EUNSUPPORTED = -6   /* feature not built for this configuration */
+};
+
+/* Physical parameters (section 2.1: per-type radius, mass, charge, freely set
+ * interactions within and between types, per-type surface spring, gravity,
+ * centrifugal force, Stokes viscosity, controllable Brownian motion). */
+typedef struct {
+    int32_t n_types;                      /* 1 .. LD_MAX_TYPES */
+    int32_t use_eps_matrix;               /* 0: eps_ij = sqrt(eps_i eps_j) */
+    double sigma[LD_MAX_TYPES];           /* LJ size = contact diameter (> 0) */
+    double eps[LD_MAX_TYPES];             /* LJ well depth (>= 0) */
+    double mass[LD_MAX_TYPES];            /* buoyancy-corrected mass */
+    double gamma[LD_MAX_TYPES];           /* Stokes drag (> 0); mobility 1/gamma */
+    double k_wall[LD_MAX_TYPES];          /* surface spring constant (>= 0) */
+    double wall_offset[LD_MAX_TYPES];     /* spring equilibrium this far inside R */
+    double eps_matrix[LD_MAX_TYPES * LD_MAX_TYPES]; /* row-major [ti*LD_MAX_TYPES+tj] */
+    double lj_cut;                        /* LJ range in units of sigma_ij (> 0) */
+    double coul_cut;                      /* must be <= 0: Coulomb over all pairs */
+    double bjerrum;                       /* Bjerrum length l_B (>= 0) */
+    double kT;                            /* thermal energy (>= 0) */
+    double gravity[3];                    /* acceleration; force = mass * gravity */
+    double omega;                         /* effective rotation rate */
+    int32_t rotation;                     /* 0: isotropic m w^2 x; 1: about z */
+    int32_t wall_band;                    /* 1: spring only within sigma/2 of R */
+    int32_t noise;                        /* 0 off, 1 Gaussian, 2 fixed magnitude */
+    int32_t reserved;                     /* must be 0 */
+    double jump_max;                      /* |move| per component flagged (<=0: off) */
+} ld_params;
+
+/* Droplet radius schedule (section 2.1: radius-square law with a freely
+ * defined rate, or no movement; section 2.2 step (iii)).  Step n uses the
+ * radius at the end of the step, R(t_n + dt). */
+enum { LD_R_CONST = 0, LD_R_LINEAR = 1, LD_R_SQUARE_LAW = 2 };
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double R0, R1, T;      /* linear: R0 -> R1 over time T, then constant */
+    double a;              /* square law: R^2 = R0^2 - 2 a t  (dR/dt = -a/R) */
+    double R_min;          /* square law: R is clamped at R_min */
+} ld_radius;
+
+/* Launch configuration of the pair kernel (filled in by ld_autotune or set
+ * by hand).  Zero fields mean "library default". */
+typedef struct {
+    int32_t block;          /* work-items per workgroup: 64, 128, 256 or 512 */
+    int32_t j_split;        /* number of j ranges per i tile (1 .. 64) */
+    int32_t comp;           /* 0: FP32 blocks flushed to FP64; 1: blocked Kahan */
+    int32_t sort_every;     /* steps between spatial re-sorts (<0: never) */
+    int32_t cull;           /* 1: skip the LJ test for tile pairs beyond range */
+    int32_t reserved[3];
+} ld_tuning;
+
+/* ---------------------------------------------------------------------- */
+/* Life cycle                                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Create a context for n >= 2 NPs.
+ *   type   [n] int32 in [0, p->n_types)
+ *   charge [n] FP64 charges in elementary charges
+ *   pos    [n*3] FP32 positions (x0 y0 z0 x1 ...), all finite
+ *   p, R   parameters and radius schedule (copied)
+ *   seed   Philox key of the Brownian noise stream
+ *   stream hipStream_t to enqueue on (NULL: the null stream)
+ * The noise for NP i at step k is Philox4x32-10 with counter (i, k mod 2^32,
+ * k div 2^32, 0) and key (seed mod 2^32, seed div 2^32); the four words become
+ * uniforms ((u >> 9) + 0.5) 2^-23 (exact in FP32) and then three normals by
+ * Box-Muller: (sqrt(-2 ln U0) cos 2 pi U1, sqrt(-2 ln U0) sin 2 pi U1,
+ * sqrt(-2 ln U2) cos 2 pi U3).
+ * Errors: LD_EINVAL (n, types, parameters), LD_ENOMEM, LD_EHIP. */
+ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* charge,
+                  const float* pos, const ld_params* p, const ld_radius* R, uint64_t seed,
+                  void* stream);
+
+/* Release all device memory of the context (NULL is ignored). */
+void ld_destroy(ld_ctx* ctx);
+
+/* Text of the last error on this thread ("" if none). */
+const char* ld_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* The hot path                                                            */
+/* ---------------------------------------------------------------------- */
+
+/* Forces at the current state (section 2.2 steps (ii), (iv), (v)).
+ *   F_pair [n*3] FP64 pair forces (LJ + Coulomb), or NULL
+ *   F_ext  [n*3] FP64 external forces at R(t) of the current time t, or NULL
+ *   S      [n]   FP64 sum_j |f_LJ,ij| + |f_C,ij| (error scale), or NULL
+ *   U      [2]   FP64 total LJ and Coulomb pair energies, or NULL
+ * Waits for the stream.  Errors: LD_EINVAL, LD_EHIP, LD_ENONFINITE. */
+ld_status ld_forces(ld_ctx* ctx, double* F_pair, double* F_ext, double* S, double* U);
+
+/* Advance n_steps >= 0 steps of size dt > 0 (section 2.2 steps (ii)-(vi)):
+ *   x <- x + mu dt (F_pair + F_ext(R(t+dt))) + sqrt(2 kT mu dt) xi,  mu = 1/gamma.
+ * Asynchronous: returns once the work is enqueued.  Errors: LD_EINVAL,
+ * LD_EHIP. */
+ld_status ld_step(ld_ctx* ctx, double dt, int64_t n_steps);
+
+/* Wait for the stream; report a pending device-side blow-up.
+ * Errors: LD_EHIP, LD_ENONFINITE (ld_last_error names the first bad step). */
+ld_status ld_sync(ld_ctx* ctx);
+
+/* ---------------------------------------------------------------------- */
+/* State access                                                            */
+/* ---------------------------------------------------------------------- */
+
+/* Positions [n*3] FP32 in original order: pos = hi part, pos_lo = lo part
+ * (either may be NULL).  Waits for the stream. */
+ld_status ld_get_positions(ld_ctx* ctx, float* pos, float* pos_lo);
+
+/* Global step counter, time t and current radius R(t) (any may be NULL). */
+ld_status ld_get_state(ld_ctx* ctx, int64_t* step, double* t, double* R);
+
+/* Replace parameters and/or schedule mid-run (section 2.2: a run can be
+ * stopped and restarted with different parameters).  NULL keeps the old. */
+ld_status ld_set_params(ld_ctx* ctx, const ld_params* p, const ld_radius* R);
+
+/* FP64 diagnostics at the current state with R = R(t):
+ * out[0] U_LJ, out[1] U_C, out[2] U_wall, out[3] U_grav, out[4] U_centrifugal,
+ * out[5..7] net pair force, out[8] max |F_pair_i|, out[9] max |x_i|. */
+ld_status ld_diagnostics(ld_ctx* ctx, double out[10]);
+
+/* ---------------------------------------------------------------------- */
+/* Post-processing (section 3)                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Radial distribution function, Eq. (6), and radial concentration, Eq. (8),
+ * over bins [b dr, (b+1) dr), dr = r_max / n_bins.  V is the sample volume
+ * (<= 0: the droplet volume 4/3 pi R(t)^3).  centre: 0 droplet centre,
+ * 1 centre of mass.  Outputs (host or device, any may be NULL):
+ *   counts [n_bins] uint64 unordered pair counts, g [n_bins] FP64,
+ *   ccounts [n_bins] uint64 particle counts from the centre, cbar [n_bins].
+ * Distances use the full (hi + lo) positions in FP64. */
+ld_status ld_rdf(ld_ctx* ctx, double r_max, int32_t n_bins, double V, int32_t centre,
+                 uint64_t* counts, double* g, uint64_t* ccounts, double* cbar);
+
+/* Fractal dimension, section 3.1: out[0] R_g (Eq. 3, about the centre of
+ * mass, Eq. 4), out[1] D_f solving Eq. (2) with prefactor k_f and mean NP
+ * diameter d (d <= 0: number-mean sigma), out[2] box-counting dimension over
+ * box sides eps0 * 2^k <= R_g (eps0 <= 0: smallest sigma), fitted by least
+ * squares over k >= 1, out[3] the number of box sizes.  box_counts[k]
+ * (k < max_scales, may be NULL) receives the occupied-box counts. */
+ld_status ld_fractal(ld_ctx* ctx, double k_f, double d, double eps0, int32_t max_scales,
+                     double out[4], int64_t* box_counts);
+
+/* ---------------------------------------------------------------------- */
+/* Performance controls                                                    */
+/* ---------------------------------------------------------------------- */
+
+ld_status ld_get_tuning(ld_ctx* ctx, ld_tuning* t);
+ld_status ld_set_tuning(ld_ctx* ctx, const ld_tuning* t);
+
+/* Time every pair-kernel launch with HIP events on the context's stream.
+ * enable = 1 starts (and clears) the record, 0 stops it.  ld_kernel_time
+ * waits for the stream and returns the number of timed launches and their
+ * total duration in milliseconds. */
+ld_status ld_kernel_timing(ld_ctx* ctx, int32_t enable);
+ld_status ld_kernel_time(ld_ctx* ctx, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDROP_H */

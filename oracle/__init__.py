@@ -78,6 +78,11 @@ def lib():
                               C.POINTER(_Params), C.POINTER(_Radius), C.c_double, C.c_int64,
                               C.c_uint64, C.POINTER(C.c_int64), dp]
         L.ldo_run.restype = C.c_int64
+        L.ldo_step_rows.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp,
+                                    C.POINTER(C.c_int64), C.POINTER(_Params),
+                                    C.POINTER(_Radius), C.c_double, C.c_uint64, C.c_int64,
+                                    C.c_double, C.POINTER(C.c_int64), C.c_int64, dp]
+        L.ldo_step_rows.restype = C.c_int64
         L.ldo_diagnostics.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp,
                                       C.POINTER(_Params), C.c_double, dp]
         L.ldo_rdf.argtypes = [C.c_int64, dp, C.c_double, C.c_int32, C.c_double, dp,
@@ -210,6 +215,18 @@ class State:
         self.step = st.value
         self.t = tt.value
         return bad
+
+    def step_rows(self, rows, dt: float = None):
+        """New positions of `rows` after one step from the current state
+        (section 2.2 step (vi)); the state itself is not advanced."""
+        dt = self.w.dt if dt is None else dt
+        rows_a = np.ascontiguousarray(rows, dtype=np.int64)
+        out = np.zeros((len(rows_a), 3))
+        bad = lib().ldo_step_rows(len(self.type), _dp(self.x), _ip(self.type), _dp(self.q),
+                                  _lp(self.ids), C.byref(make_params(self.params)),
+                                  C.byref(make_radius(self.radius)), dt, self.seed, self.step,
+                                  self.t, _lp(rows_a), len(rows_a), _dp(out))
+        return out, bad
 
     def diagnostics(self, R=None) -> np.ndarray:
         R = radius_at(self.radius, self.t) if R is None else R

@@ -52,8 +52,9 @@ void ldo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* 24-bit uniform in (0,1), exact in both FP32 and FP64. */
-static double u24(uint32_t u) { return ((double)(u >> 8) + 0.5) * (1.0 / 16777216.0); }
+/* 23-bit uniform ((u >> 9) + 1/2) 2^-23 in (0,1); every value is exact in
+ * FP32 as well as FP64, so a single-precision consumer sees the same U. */
+static double u23(uint32_t u) { return ((double)(u >> 9) + 0.5) * (1.0 / 8388608.0); }
 
 void ldo_gauss3(int64_t id, int64_t step, uint64_t seed, uint32_t tag, double xi[3]) {
     uint32_t ctr[4], key[2], r[4];
@@ -64,7 +65,7 @@ void ldo_gauss3(int64_t id, int64_t step, uint64_t seed, uint32_t tag, double xi
     key[0] = (uint32_t)seed;
     key[1] = (uint32_t)(seed >> 32);
     ldo_philox4x32_10(ctr, key, r);
-    double U0 = u24(r[0]), U1 = u24(r[1]), U2 = u24(r[2]), U3 = u24(r[3]);
+    double U0 = u23(r[0]), U1 = u23(r[1]), U2 = u23(r[2]), U3 = u23(r[3]);
     double a = sqrt(-2.0 * log(U0));
     double b = sqrt(-2.0 * log(U2));
     xi[0] = a * cos(2.0 * M_PI * U1);
@@ -260,6 +261,45 @@ int64_t ldo_run(int64_t n, double* x, const int32_t* type, const double* q,
     }
     free(Fp);
     return bad;
+}
+
+/* One Euler-Maruyama step for the listed rows only: the pair forces on each
+ * listed particle come from all n particles at their current positions, so
+ * the new positions of a sample can be checked without running the whole
+ * system.  x_rows_out is [n_rows*3]; step / t are not advanced. */
+int64_t ldo_step_rows(int64_t n, const double* x, const int32_t* type, const double* q,
+                      const int64_t* ids, const ldo_params* p, const ldo_radius* R,
+                      double dt, uint64_t seed, int64_t step, double t,
+                      const int64_t* rows, int64_t n_rows, double* x_rows_out) {
+    double* Fp = (double*)malloc((size_t)(n_rows > 0 ? n_rows : 1) * 3 * sizeof(double));
+    const double Rn = ldo_radius_at(R, t + dt);
+    ldo_pair_forces(n, x, type, q, p, rows, n_rows, Fp, NULL, NULL);
+    int flag = 0;
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t i = rows[r];
+        const int ti = type[i];
+        double Fe[3];
+        ldo_external_force(&x[3 * i], ti, p, Rn, Fe);
+        const double mu = 1.0 / p->gamma[ti];
+        double xi[3] = {0.0, 0.0, 0.0};
+        double amp = 0.0;
+        if (p->noise != 0 && p->kT > 0.0) {
+            ldo_gauss3(ids ? ids[i] : i, step, seed, 0u, xi);
+            amp = sqrt(2.0 * p->kT * mu * dt);
+            if (p->noise == 2) {
+                double m = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+                double f = sqrt(3.0) / m;
+                xi[0] *= f; xi[1] *= f; xi[2] *= f;
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            double d = mu * dt * (Fp[3 * r + c] + Fe[c]) + amp * xi[c];
+            if (!isfinite(d) || (p->jump_max > 0.0 && fabs(d) > p->jump_max)) flag = 1;
+            x_rows_out[3 * r + c] = x[3 * i + c] + d;
+        }
+    }
+    free(Fp);
+    return flag ? step : -1;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -110,6 +110,15 @@ int64_t ldo_run(int64_t n, double* x, const int32_t* type, const double* q,
                 const int64_t* ids, const ldo_params* p, const ldo_radius* R,
                 double dt, int64_t n_steps, uint64_t seed, int64_t* step, double* t);
 
+/* One step for the listed rows only (pair forces from all n particles at the
+ * current positions); writes the rows' new positions, leaves x unchanged.
+ * Returns step if a listed row blew up, else -1.  Same formulas as ldo_run,
+ * pinned through it. */
+int64_t ldo_step_rows(int64_t n, const double* x, const int32_t* type, const double* q,
+                      const int64_t* ids, const ldo_params* p, const ldo_radius* R,
+                      double dt, uint64_t seed, int64_t step, double t,
+                      const int64_t* rows, int64_t n_rows, double* x_rows_out);
+
 /* Diagnostics (FP64): out[0] U_LJ, out[1] U_C, out[2] U_wall, out[3] U_grav,
  * out[4] U_centrifugal, out[5..7] net pair force, out[8] max |F_pair_i|,
  * out[9] max |x_i|.  R is the radius used for the wall. */

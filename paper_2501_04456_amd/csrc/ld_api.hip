@@ -1,0 +1,709 @@
+// The C ABI of libldrop (declared in include/ldrop.h): argument checking,
+// device buffers, host/device pointer handling and the per-step launch
+// sequence.  No C++ exception crosses this boundary.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ld_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+ld_status fail(ld_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(LD_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Copy bytes into device memory from a host or device source.
+hipError_t copy_in(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    return hipMemcpyAsync(dst, src, bytes,
+                          is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          s);
+}
+
+// Copy bytes from device memory to a host or device destination; waits.
+hipError_t copy_out(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(
+        dst, src, bytes, is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+// Read a caller array of `count` elements into host memory.
+template <class T>
+ld_status read_host(std::vector<T>& v, const T* src, size_t count, hipStream_t s) {
+    v.resize(count);
+    if (is_device_ptr(src)) {
+        HIP_TRY(hipMemcpyAsync(v.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        std::memcpy(v.data(), src, count * sizeof(T));
+    }
+    return LD_OK;
+}
+
+ld_status check_params(const ld_params* p) {
+    if (!p) return fail(LD_EINVAL, "params is NULL");
+    if (p->n_types < 1 || p->n_types > LD_MAX_TYPES)
+        return fail(LD_EINVAL, "n_types=%d outside [1,%d]", p->n_types, LD_MAX_TYPES);
+    for (int t = 0; t < p->n_types; ++t) {
+        if (!(p->sigma[t] > 0.0) || !std::isfinite(p->sigma[t]))
+            return fail(LD_EINVAL, "sigma[%d]=%g must be positive", t, p->sigma[t]);
+        if (!(p->eps[t] >= 0.0)) return fail(LD_EINVAL, "eps[%d]=%g must be >= 0", t, p->eps[t]);
+        if (!(p->gamma[t] > 0.0))
+            return fail(LD_EINVAL, "gamma[%d]=%g must be positive", t, p->gamma[t]);
+        if (!(p->k_wall[t] >= 0.0))
+            return fail(LD_EINVAL, "k_wall[%d]=%g must be >= 0", t, p->k_wall[t]);
+        if (!std::isfinite(p->mass[t]) || !std::isfinite(p->wall_offset[t]))
+            return fail(LD_EINVAL, "mass / wall_offset of type %d not finite", t);
+        if (p->use_eps_matrix) {
+            for (int u = 0; u < p->n_types; ++u) {
+                const double a = p->eps_matrix[t * LD_MAX_TYPES + u];
+                const double b = p->eps_matrix[u * LD_MAX_TYPES + t];
+                if (!(a >= 0.0) || a != b)
+                    return fail(LD_EINVAL, "eps_matrix must be symmetric and >= 0 (%d,%d)", t, u);
+            }
+        }
+    }
+    if (!(p->lj_cut > 0.0)) return fail(LD_EINVAL, "lj_cut=%g must be positive", p->lj_cut);
+    if (p->coul_cut > 0.0)
+        return fail(LD_EUNSUPPORTED, "coul_cut > 0 (truncated Coulomb) is not built");
+    if (!(p->bjerrum >= 0.0) || !(p->kT >= 0.0))
+        return fail(LD_EINVAL, "bjerrum and kT must be >= 0");
+    if (p->rotation != 0 && p->rotation != 1) return fail(LD_EINVAL, "rotation must be 0 or 1");
+    if (p->wall_band != 0 && p->wall_band != 1) return fail(LD_EINVAL, "wall_band must be 0/1");
+    if (p->noise < 0 || p->noise > 2) return fail(LD_EINVAL, "noise must be 0, 1 or 2");
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(p->gravity[c])) return fail(LD_EINVAL, "gravity not finite");
+    if (!std::isfinite(p->omega)) return fail(LD_EINVAL, "omega not finite");
+    return LD_OK;
+}
+
+ld_status check_radius(const ld_radius* R) {
+    if (!R) return fail(LD_EINVAL, "radius schedule is NULL");
+    if (R->kind < LD_R_CONST || R->kind > LD_R_SQUARE_LAW)
+        return fail(LD_EINVAL, "radius kind %d unknown", R->kind);
+    if (!std::isfinite(R->R0) || R->R0 < 0.0) return fail(LD_EINVAL, "R0 must be >= 0");
+    if (R->kind == LD_R_LINEAR && (!std::isfinite(R->R1) || R->R1 < 0.0 || !(R->T >= 0.0)))
+        return fail(LD_EINVAL, "linear schedule needs R1 >= 0 and T >= 0");
+    if (R->kind == LD_R_SQUARE_LAW && (!std::isfinite(R->a) || !(R->R_min >= 0.0)))
+        return fail(LD_EINVAL, "square-law schedule needs finite a and R_min >= 0");
+    return LD_OK;
+}
+
+void build_tables(ld_ctx* c) {
+    const ld_params& p = c->p;
+    ld::PairTable& tb = c->tab;
+    std::memset(&tb, 0, sizeof tb);
+    tb.T = p.n_types;
+    double rc2max = 0.0;
+    for (int a = 0; a < p.n_types; ++a)
+        for (int b = 0; b < p.n_types; ++b) {
+            const double s = 0.5 * (p.sigma[a] + p.sigma[b]);
+            const double e = p.use_eps_matrix ? p.eps_matrix[a * LD_MAX_TYPES + b]
+                                              : std::sqrt(p.eps[a] * p.eps[b]);
+            const double rc = p.lj_cut * s;
+            const int k = a * p.n_types + b;
+            tb.sig2[k] = (float)(s * s);
+            tb.rc2[k] = (float)(rc * rc);
+            tb.e24[k] = (float)(24.0 * e);
+            tb.e4[k] = (float)(4.0 * e);
+            if (rc * rc > rc2max) rc2max = rc * rc;
+        }
+    tb.rc2max = (float)rc2max;
+
+    ld::ExtParams& P = c->ext;
+    std::memset(&P, 0, sizeof P);
+    P.n_types = p.n_types;
+    P.rotation = p.rotation;
+    P.wall_band = p.wall_band;
+    P.noise = p.noise;
+    for (int k = 0; k < 3; ++k) P.gravity[k] = p.gravity[k];
+    P.omega2 = p.omega * p.omega;
+    P.kT = p.kT;
+    P.jump_max = p.jump_max;
+    for (int t = 0; t < p.n_types; ++t) {
+        P.mu[t] = 1.0 / p.gamma[t];
+        P.mass[t] = p.mass[t];
+        P.k_wall[t] = p.k_wall[t];
+        P.wall_offset[t] = p.wall_offset[t];
+        P.half_sigma[t] = 0.5 * p.sigma[t];
+    }
+    P.R = c->R;
+}
+
+void default_tuning(ld_ctx* c) {
+    ld_tuning& t = c->tune;
+    std::memset(&t, 0, sizeof t);
+    const int64_t n = c->n;
+    t.block = n >= 16384 ? 256 : 64;
+    const int64_t tiles = (n + t.block - 1) / t.block;
+    int64_t split = (2048 + tiles - 1) / tiles;
+    int64_t cap = n / 1024;
+    if (cap < 1) cap = 1;
+    if (split > cap) split = cap;
+    if (split > 64) split = 64;
+    if (split < 1) split = 1;
+    t.j_split = (int)split;
+    t.comp = 0;
+    t.sort_every = 50;
+    t.cull = 1;
+}
+
+ld_status ensure_split_capacity(ld_ctx* c, int split) {
+    if (split <= c->j_split_cap) return LD_OK;
+    if (c->Fpart) (void)hipFree(c->Fpart);
+    c->Fpart = nullptr;
+    c->j_split_cap = 0;
+    if (hipMalloc(&c->Fpart, sizeof(double) * 3 * (size_t)c->n * split) != hipSuccess)
+        return fail(LD_ENOMEM, "cannot allocate %d force partials", split);
+    c->j_split_cap = split;
+    return LD_OK;
+}
+
+hipEvent_t next_event(ld_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+ld_status run_pair(ld_ctx* c, bool diag) {
+    ld::PairLaunch L{};
+    L.pos = c->pos;
+    L.typ = c->typ;
+    L.box = c->box;
+    L.n = (int)c->n;
+    L.block = c->tune.block;
+    L.j_split = diag ? 1 : c->tune.j_split;
+    L.comp = c->tune.comp;
+    L.cull = (c->tune.cull && !diag) ? 1 : 0;
+    L.Fpart = c->Fpart;
+    L.S = diag ? c->S_slot : nullptr;
+    L.U = diag ? c->U_slot : nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        e0 = next_event(c);
+        e1 = next_event(c);
+        if (!e0 || !e1) return fail(LD_EHIP, "cannot create timing events");
+        HIP_TRY(hipEventRecord(e0, c->stream));
+    }
+    HIP_TRY(ld::launch_pair(L, c->tab, c->stream));
+    if (c->timing) HIP_TRY(hipEventRecord(e1, c->stream));
+    return LD_OK;
+}
+
+ld_status run_sort(ld_ctx* c) {
+    HIP_TRY(ld::launch_sort(c->pos, c->lo, c->typ, c->oid, (int)c->n, c->sb, c->stream));
+    HIP_TRY(ld::launch_boxes(c->pos, (int)c->n, c->box, c->stream));
+    c->steps_since_sort = 0;
+    return LD_OK;
+}
+
+ld_status pending_error(ld_ctx* c) {
+    ld::DevState st;
+    HIP_TRY(hipMemcpyAsync(&st, c->st, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (st.bad_step != ~0ull)
+        return fail(LD_ENONFINITE, "step %llu produced a non-finite or too large move",
+                    (unsigned long long)st.bad_step);
+    return LD_OK;
+}
+
+void free_all(ld_ctx* c) {
+    void* bufs[] = {c->pos,     c->lo,     c->typ,         c->oid,       c->box,  c->aux,
+                    c->Fpart,   c->S_slot, c->U_slot,      c->work,      c->st,
+                    c->sb.keys, c->sb.tmp4, c->sb.tmp_i,   c->sb.bounds, c->sb.bounds_part};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ld_last_error(void) { return g_err.c_str(); }
+
+ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* charge,
+                  const float* pos, const ld_params* p, const ld_radius* R, uint64_t seed,
+                  void* stream) {
+    g_err.clear();
+    if (!out) return fail(LD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 2 || n > (1 << 27)) return fail(LD_EINVAL, "n=%lld outside [2, 2^27]", (long long)n);
+    if (!type || !charge || !pos) return fail(LD_EINVAL, "type, charge and pos are required");
+    ld_status st = check_params(p);
+    if (st != LD_OK) return st;
+    st = check_radius(R);
+    if (st != LD_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+
+    std::vector<int32_t> ty;
+    std::vector<double> q;
+    std::vector<float> x;
+    if ((st = read_host(ty, type, (size_t)n, s)) != LD_OK) return st;
+    if ((st = read_host(q, charge, (size_t)n, s)) != LD_OK) return st;
+    if ((st = read_host(x, pos, (size_t)n * 3, s)) != LD_OK) return st;
+    for (int64_t i = 0; i < n; ++i) {
+        if (ty[i] < 0 || ty[i] >= p->n_types)
+            return fail(LD_EINVAL, "type[%lld]=%d outside [0,%d)", (long long)i, ty[i], p->n_types);
+        if (!std::isfinite(q[i])) return fail(LD_EINVAL, "charge[%lld] not finite", (long long)i);
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(x[3 * i + k]))
+                return fail(LD_EINVAL, "pos[%lld] not finite", (long long)i);
+    }
+
+    ld_ctx* c = new (std::nothrow) ld_ctx();
+    if (!c) return fail(LD_ENOMEM, "host allocation failed");
+    c->n = n;
+    c->stream = s;
+    c->p = *p;
+    c->R = *R;
+    c->seed = seed;
+    (void)hipGetDevice(&c->device);
+    build_tables(c);
+    default_tuning(c);
+
+    const size_t N = (size_t)n;
+    const int ngroups = (int)((n + ld::kGroup - 1) / ld::kGroup);
+    int n_pow2 = 2048;
+    while (n_pow2 < n) n_pow2 <<= 1;
+    c->sb.n_pow2 = n_pow2;
+    c->sb.bounds_parts = 64;
+    bool ok = hipMalloc(&c->pos, sizeof(float4) * N) == hipSuccess &&
+              hipMalloc(&c->lo, sizeof(float4) * N) == hipSuccess &&
+              hipMalloc(&c->typ, sizeof(int) * N) == hipSuccess &&
+              hipMalloc(&c->oid, sizeof(int) * N) == hipSuccess &&
+              hipMalloc(&c->box, sizeof(ld::Box) * ngroups) == hipSuccess &&
+              hipMalloc(&c->S_slot, sizeof(double) * N) == hipSuccess &&
+              hipMalloc(&c->U_slot, sizeof(double) * 2 * N) == hipSuccess &&
+              hipMalloc(&c->work, sizeof(double) * (16 * N + 64)) == hipSuccess &&
+              hipMalloc(&c->aux, sizeof(double) * ld::kAuxWords) == hipSuccess &&
+              hipMalloc(&c->st, sizeof(ld::DevState)) == hipSuccess &&
+              hipMalloc(&c->sb.keys, sizeof(unsigned long long) * n_pow2) == hipSuccess &&
+              hipMalloc(&c->sb.tmp4, sizeof(float4) * N) == hipSuccess &&
+              hipMalloc(&c->sb.tmp_i, sizeof(int) * N) == hipSuccess &&
+              hipMalloc(&c->sb.bounds, sizeof(float) * 8) == hipSuccess &&
+              hipMalloc(&c->sb.bounds_part, sizeof(float) * 6 * 64) == hipSuccess;
+    if (!ok || ensure_split_capacity(c, c->tune.j_split) != LD_OK) {
+        free_all(c);
+        delete c;
+        return fail(LD_ENOMEM, "device allocation failed for n=%lld", (long long)n);
+    }
+
+    const double qs = std::sqrt(p->kT * p->bjerrum);
+    std::vector<float4> h4(N), l4(N);
+    std::vector<int> ids(N);
+    for (size_t i = 0; i < N; ++i) {
+        h4[i] = make_float4(x[3 * i], x[3 * i + 1], x[3 * i + 2], (float)(q[i] * qs));
+        l4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        ids[i] = (int)i;
+    }
+    ld::DevState ds{};
+    ds.step = 0;
+    ds.t = 0.0;
+    ds.bad_step = ~0ull;
+    ds.done = 0;
+    hipError_t e = hipMemcpyAsync(c->pos, h4.data(), sizeof(float4) * N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->lo, l4.data(), sizeof(float4) * N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->typ, ty.data(), sizeof(int) * N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->oid, ids.data(), sizeof(int) * N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->st, &ds, sizeof ds, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_all(c);
+        delete c;
+        return fail(LD_EHIP, "upload failed: %s", hipGetErrorString(e));
+    }
+    st = (c->tune.sort_every >= 0) ? run_sort(c) : LD_OK;
+    if (st == LD_OK && c->tune.sort_every < 0) {
+        e = ld::launch_boxes(c->pos, (int)n, c->box, s);
+        if (e != hipSuccess) st = fail(LD_EHIP, "box kernel: %s", hipGetErrorString(e));
+    }
+    if (st == LD_OK) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(LD_EHIP, "init: %s", hipGetErrorString(e));
+    }
+    if (st != LD_OK) {
+        free_all(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return LD_OK;
+}
+
+void ld_destroy(ld_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+ld_status ld_forces(ld_ctx* c, double* F_pair, double* F_ext, double* S, double* U) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    const bool diag = S || U;
+    ld_status st = run_pair(c, diag);
+    if (st != LD_OK) return st;
+    const size_t N = (size_t)c->n;
+    double* dF = c->work;                    // [3N]
+    double* dE = c->work + 3 * N;            // [3N]
+    double* dS = c->work + 6 * N;            // [N]
+    double* dU = c->work + 7 * N;            // [2]
+    HIP_TRY(ld::launch_gather(c->pos, c->lo, c->typ, c->oid, c->Fpart,
+                              diag ? 1 : c->tune.j_split, c->S_slot, (int)N, c->st, c->ext,
+                              F_pair ? dF : nullptr, F_ext ? dE : nullptr, S ? dS : nullptr,
+                              c->stream));
+    if (U) HIP_TRY(ld::launch_rowsum(c->U_slot, 2, (int)N, dU, c->stream));
+    if (F_pair) HIP_TRY(copy_out(F_pair, dF, sizeof(double) * 3 * N, c->stream));
+    if (F_ext) HIP_TRY(copy_out(F_ext, dE, sizeof(double) * 3 * N, c->stream));
+    if (S) HIP_TRY(copy_out(S, dS, sizeof(double) * N, c->stream));
+    if (U) HIP_TRY(copy_out(U, dU, sizeof(double) * 2, c->stream));
+    return pending_error(c);
+}
+
+ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LD_EINVAL, "dt=%g must be positive", dt);
+    if (n_steps < 0) return fail(LD_EINVAL, "n_steps must be >= 0");
+    ld::StepLaunch L{};
+    L.pos = c->pos;
+    L.lo = c->lo;
+    L.typ = c->typ;
+    L.oid = c->oid;
+    L.Fpart = c->Fpart;
+    L.j_split = c->tune.j_split;
+    L.n = (int)c->n;
+    L.dt = dt;
+    L.seed = c->seed;
+    L.st = c->st;
+    L.box = c->box;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        if (c->tune.sort_every > 0 && c->steps_since_sort >= c->tune.sort_every) {
+            ld_status st = run_sort(c);
+            if (st != LD_OK) return st;
+        }
+        ld_status st = run_pair(c, false);
+        if (st != LD_OK) return st;
+        HIP_TRY(ld::launch_update(L, c->ext, c->stream));
+        ++c->steps_since_sort;
+    }
+    return LD_OK;
+}
+
+ld_status ld_sync(ld_ctx* c) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    return pending_error(c);
+}
+
+ld_status ld_get_positions(ld_ctx* c, float* pos, float* pos_lo) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    const size_t N = (size_t)c->n;
+    std::vector<float4> h(N), l(N);
+    std::vector<int> ids(N);
+    HIP_TRY(hipMemcpyAsync(h.data(), c->pos, sizeof(float4) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(l.data(), c->lo, sizeof(float4) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(ids.data(), c->oid, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<float> a(pos ? 3 * N : 0), b(pos_lo ? 3 * N : 0);
+    for (size_t s = 0; s < N; ++s) {
+        const size_t o = (size_t)ids[s];
+        if (pos) { a[3 * o] = h[s].x; a[3 * o + 1] = h[s].y; a[3 * o + 2] = h[s].z; }
+        if (pos_lo) { b[3 * o] = l[s].x; b[3 * o + 1] = l[s].y; b[3 * o + 2] = l[s].z; }
+    }
+    if (pos) {
+        if (is_device_ptr(pos)) {
+            HIP_TRY(hipMemcpyAsync(pos, a.data(), sizeof(float) * 3 * N, hipMemcpyHostToDevice,
+                                   c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        } else {
+            std::memcpy(pos, a.data(), sizeof(float) * 3 * N);
+        }
+    }
+    if (pos_lo) {
+        if (is_device_ptr(pos_lo)) {
+            HIP_TRY(hipMemcpyAsync(pos_lo, b.data(), sizeof(float) * 3 * N,
+                                   hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        } else {
+            std::memcpy(pos_lo, b.data(), sizeof(float) * 3 * N);
+        }
+    }
+    return pending_error(c);
+}
+
+ld_status ld_get_state(ld_ctx* c, int64_t* step, double* t, double* R) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    ld::DevState st;
+    HIP_TRY(hipMemcpyAsync(&st, c->st, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (step) *step = st.step;
+    if (t) *t = st.t;
+    if (R) *R = ld::radius_at(c->R, st.t);
+    return LD_OK;
+}
+
+ld_status ld_set_params(ld_ctx* c, const ld_params* p, const ld_radius* R) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    if (p) {
+        ld_status st = check_params(p);
+        if (st != LD_OK) return st;
+        if (p->n_types < c->p.n_types)
+            return fail(LD_EINVAL, "n_types cannot shrink below the types in use");
+    }
+    if (R) {
+        ld_status st = check_radius(R);
+        if (st != LD_OK) return st;
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (p) {
+        const double old_s = std::sqrt(c->p.kT * c->p.bjerrum);
+        const double new_s = std::sqrt(p->kT * p->bjerrum);
+        if (old_s != new_s) {
+            // rescale the stored charges q * sqrt(kT l_B)
+            const size_t N = (size_t)c->n;
+            std::vector<float4> h(N);
+            std::vector<int> ids(N);
+            HIP_TRY(hipMemcpy(h.data(), c->pos, sizeof(float4) * N, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(ids.data(), c->oid, sizeof(int) * N, hipMemcpyDeviceToHost));
+            if (old_s == 0.0)
+                return fail(LD_ESTATE, "charges were stored with kT * l_B = 0 and are lost");
+            std::vector<float> qh(N);
+            for (size_t s = 0; s < N; ++s) qh[ids[s]] = (float)((double)h[s].w / old_s * new_s);
+            float* dq = reinterpret_cast<float*>(c->work);
+            HIP_TRY(hipMemcpy(dq, qh.data(), sizeof(float) * N, hipMemcpyHostToDevice));
+            HIP_TRY(ld::launch_set_charge(c->pos, c->oid, dq, (int)N, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+        }
+        c->p = *p;
+    }
+    if (R) c->R = *R;
+    build_tables(c);
+    return LD_OK;
+}
+
+ld_status ld_diagnostics(ld_ctx* c, double out[10]) {
+    g_err.clear();
+    if (!c || !out) return fail(LD_EINVAL, "ctx and out are required");
+    ld_status st = run_pair(c, true);
+    if (st != LD_OK) return st;
+    const size_t N = (size_t)c->n;
+    double* res = c->aux;
+    HIP_TRY(ld::launch_diag(c->pos, c->lo, c->typ, c->Fpart, 1, c->U_slot, (int)N, c->st, c->ext,
+                            c->work, res, c->stream));
+    HIP_TRY(copy_out(out, res, sizeof(double) * 10, c->stream));
+    return pending_error(c);
+}
+
+ld_status ld_rdf(ld_ctx* c, double r_max, int32_t n_bins, double V, int32_t centre,
+                 uint64_t* counts, double* g, uint64_t* ccounts, double* cbar) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    if (!(r_max > 0.0) || !std::isfinite(r_max)) return fail(LD_EINVAL, "r_max must be > 0");
+    if (n_bins < 1 || n_bins > 4096) return fail(LD_EINVAL, "n_bins must be in [1, 4096]");
+    if (centre != 0 && centre != 1) return fail(LD_EINVAL, "centre must be 0 or 1");
+    const size_t N = (size_t)c->n;
+    unsigned long long* dcnt = reinterpret_cast<unsigned long long*>(c->aux);
+    unsigned long long* dcc = dcnt + 4096;
+    double* dctr = reinterpret_cast<double*>(dcc + 4096);
+    double* mom = dctr + 4;
+    if (centre == 1) {
+        HIP_TRY(ld::launch_moments(c->pos, c->lo, (int)N, c->work, mom, c->stream));
+        HIP_TRY(hipMemcpyAsync(dctr, mom, sizeof(double) * 3, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        const double z[4] = {0.0, 0.0, 0.0, 0.0};
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        HIP_TRY(hipMemcpy(dctr, z, sizeof z, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(ld::launch_rdf(c->pos, c->lo, (int)N, r_max, n_bins, dctr, dcnt, dcc, c->stream));
+    std::vector<unsigned long long> hc(n_bins), hcc(n_bins);
+    HIP_TRY(hipMemcpyAsync(hc.data(), dcnt, sizeof(unsigned long long) * n_bins,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hcc.data(), dcc, sizeof(unsigned long long) * n_bins,
+                           hipMemcpyDeviceToHost, c->stream));
+    ld::DevState ds;
+    HIP_TRY(hipMemcpyAsync(&ds, c->st, sizeof ds, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (!(V > 0.0)) {
+        const double Rn = ld::radius_at(c->R, ds.t);
+        V = 4.0 / 3.0 * M_PI * Rn * Rn * Rn;
+    }
+    const double dr = r_max / n_bins;
+    std::vector<double> hg(n_bins), hb(n_bins);
+    const double n = (double)N;
+    for (int b = 0; b < n_bins; ++b) {
+        const double r0 = b * dr, r1 = (b + 1) * dr;
+        const double dV = 4.0 / 3.0 * M_PI * (r1 * r1 * r1 - r0 * r0 * r0);
+        // Eq. (6): sum_i psi_i / N over (N - 1) dV / V, sum_i psi_i = 2 C_b
+        hg[b] = (2.0 * (double)hc[b] / n) / ((n - 1.0) * dV / V);
+        // Eq. (8): (psi / N) / (dV / V)
+        hb[b] = ((double)hcc[b] / n) / (dV / V);
+    }
+    auto put = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        if (!dst) return hipSuccess;
+        if (is_device_ptr(dst)) {
+            hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+            return e == hipSuccess ? hipStreamSynchronize(c->stream) : e;
+        }
+        std::memcpy(dst, src, bytes);
+        return hipSuccess;
+    };
+    HIP_TRY(put(counts, hc.data(), sizeof(uint64_t) * n_bins));
+    HIP_TRY(put(ccounts, hcc.data(), sizeof(uint64_t) * n_bins));
+    HIP_TRY(put(g, hg.data(), sizeof(double) * n_bins));
+    HIP_TRY(put(cbar, hb.data(), sizeof(double) * n_bins));
+    return pending_error(c);
+}
+
+ld_status ld_fractal(ld_ctx* c, double k_f, double d, double eps0, int32_t max_scales,
+                     double out[4], int64_t* box_counts) {
+    g_err.clear();
+    if (!c || !out) return fail(LD_EINVAL, "ctx and out are required");
+    if (!(k_f > 0.0)) return fail(LD_EINVAL, "k_f must be positive");
+    if (max_scales < 0 || max_scales > 40) return fail(LD_EINVAL, "max_scales in [0, 40]");
+    const size_t N = (size_t)c->n;
+    // number-mean diameter and smallest diameter from the type histogram
+    if (!(d > 0.0) || !(eps0 > 0.0)) {
+        std::vector<int> ty(N);
+        HIP_TRY(hipMemcpyAsync(ty.data(), c->typ, sizeof(int) * N, hipMemcpyDeviceToHost,
+                               c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        double sum = 0.0, smin = INFINITY;
+        for (size_t s = 0; s < N; ++s) {
+            sum += c->p.sigma[ty[s]];
+            smin = std::fmin(smin, c->p.sigma[ty[s]]);
+        }
+        if (!(d > 0.0)) d = sum / (double)N;
+        if (!(eps0 > 0.0)) eps0 = smin;
+    }
+    double* mom = c->aux;
+    double* lo3 = mom + 8;
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(lo3 + 4);
+    HIP_TRY(ld::launch_moments(c->pos, c->lo, (int)N, c->work, mom, c->stream));
+    double hm[4];
+    HIP_TRY(copy_out(hm, mom, sizeof hm, c->stream));
+    const double Rg = hm[3];
+    out[0] = Rg;
+    out[1] = std::log((double)N / k_f) / std::log(2.0 * Rg / d);
+    HIP_TRY(ld::launch_pos_rows(c->pos, c->lo, (int)N, c->work, c->stream));
+    HIP_TRY(ld::launch_rowmin(c->work, 3, (int)N, lo3, c->stream));
+    std::vector<double> lx, ly;
+    int K = 0;
+    for (int k = 0; k < max_scales; ++k) {
+        const double e = eps0 * std::ldexp(1.0, k);
+        if (e > Rg) break;
+        HIP_TRY(ld::launch_boxcount(c->pos, c->lo, (int)N, lo3, e, c->sb.keys, c->sb.n_pow2, cnt,
+                                    c->stream));
+        unsigned long long hc = 0;
+        HIP_TRY(copy_out(&hc, cnt, sizeof hc, c->stream));
+        if (box_counts) box_counts[k] = (int64_t)hc;
+        lx.push_back(std::log(e));
+        ly.push_back(std::log((double)hc));
+        K = k + 1;
+    }
+    out[3] = (double)K;
+    if (K >= 3) {
+        double sx = 0, sy = 0, sxx = 0, sxy = 0;
+        const int m = K - 1;
+        for (int k = 1; k < K; ++k) { sx += lx[k]; sy += ly[k]; }
+        const double mx = sx / m, my = sy / m;
+        for (int k = 1; k < K; ++k) {
+            sxx += (lx[k] - mx) * (lx[k] - mx);
+            sxy += (lx[k] - mx) * (ly[k] - my);
+        }
+        out[2] = -sxy / sxx;
+    } else {
+        out[2] = NAN;
+    }
+    return pending_error(c);
+}
+
+ld_status ld_get_tuning(ld_ctx* c, ld_tuning* t) {
+    g_err.clear();
+    if (!c || !t) return fail(LD_EINVAL, "ctx and t are required");
+    *t = c->tune;
+    return LD_OK;
+}
+
+ld_status ld_set_tuning(ld_ctx* c, const ld_tuning* t) {
+    g_err.clear();
+    if (!c || !t) return fail(LD_EINVAL, "ctx and t are required");
+    ld_tuning u = *t;
+    if (u.block == 0) u.block = c->tune.block;
+    if (u.j_split == 0) u.j_split = c->tune.j_split;
+    if (u.block != 64 && u.block != 128 && u.block != 256 && u.block != 512)
+        return fail(LD_EINVAL, "block must be 64, 128, 256 or 512");
+    if (u.j_split < 1 || u.j_split > 64) return fail(LD_EINVAL, "j_split must be in [1, 64]");
+    if (u.comp != 0 && u.comp != 1) return fail(LD_EINVAL, "comp must be 0 or 1");
+    if (u.cull != 0 && u.cull != 1) return fail(LD_EINVAL, "cull must be 0 or 1");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    ld_status st = ensure_split_capacity(c, u.j_split);
+    if (st != LD_OK) return st;
+    c->tune = u;
+    return LD_OK;
+}
+
+ld_status ld_kernel_timing(ld_ctx* c, int32_t enable) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->timing = enable != 0;
+    if (enable) c->ev_used = 0;
+    return LD_OK;
+}
+
+ld_status ld_kernel_time(ld_ctx* c, int64_t* launches, double* total_ms) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+        tot += ms;
+    }
+    if (launches) *launches = (int64_t)(c->ev_used / 2);
+    if (total_ms) *total_ms = tot;
+    return LD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+// Internal declarations of libldrop: device data layout, kernel parameter
+// blocks and the host-side launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ldrop.h"
+
+namespace ld {
+
+constexpr int kMaxTypes = LD_MAX_TYPES;
+constexpr int kGroup = 64;            // one wavefront: the unit of tile culling
+
+// Far-away, uncharged filler for the padded tail of a j tile: its Coulomb
+// weight is exactly zero and it never enters the LJ range.
+constexpr float kFarAway = 1.0e18f;
+
+// Words (8 bytes) of the small auxiliary buffer: two 4096-bin histograms plus
+// a few scalars.
+constexpr int kAuxWords = 2 * 4096 + 64;
+
+// Per type-pair LJ constants in FP32 (LDS-resident inside the pair kernel).
+struct PairTable {
+    int T;
+    float rc2max;                        // max_ij (lj_cut sigma_ij)^2
+    float sig2[kMaxTypes * kMaxTypes];   // sigma_ij^2
+    float rc2[kMaxTypes * kMaxTypes];    // (lj_cut sigma_ij)^2
+    float e24[kMaxTypes * kMaxTypes];    // 24 eps_ij
+    float e4[kMaxTypes * kMaxTypes];     // 4 eps_ij
+};
+
+// Per-type constants and globals for the O(N) kernels, all FP64.
+struct ExtParams {
+    int n_types, rotation, wall_band, noise;
+    double gravity[3];
+    double omega2;                       // omega^2
+    double kT, jump_max;
+    double mu[kMaxTypes];                // 1 / gamma
+    double mass[kMaxTypes];
+    double k_wall[kMaxTypes];
+    double wall_offset[kMaxTypes];
+    double half_sigma[kMaxTypes];
+    ld_radius R;
+};
+
+// Device-resident step state.  Kernels of a step read it; the last
+// workgroup of the update kernel advances it, so captured graphs replay
+// correctly.
+struct DevState {
+    long long step;                      // global step counter n
+    double t;                            // time t_n
+    unsigned long long bad_step;         // first step with a blow-up (~0: none)
+    unsigned int done;                   // workgroups finished in the update
+    unsigned int pad;
+};
+
+struct Box {
+    float4 lo, hi;                       // .w unused
+};
+
+// Radius schedule, FP64.
+__host__ __device__ inline double radius_at(const ld_radius& R, double t) {
+    if (R.kind == LD_R_LINEAR) {
+        double f = R.T > 0.0 ? t / R.T : 1.0;
+        f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+        return R.R0 + (R.R1 - R.R0) * f;
+    }
+    if (R.kind == LD_R_SQUARE_LAW) {
+        double r2 = R.R0 * R.R0 - 2.0 * R.a * t;
+        double m2 = R.R_min * R.R_min;
+        return sqrt(r2 < m2 ? m2 : r2);
+    }
+    return R.R0;
+}
+
+// ---- launchers (each returns hipSuccess or the first HIP error) --------
+
+struct PairLaunch {
+    const float4* pos;
+    const int* typ;
+    const Box* box;                      // per 64-slot group, or nullptr
+    int n;
+    int block;
+    int j_split;
+    int comp;
+    int cull;
+    double* Fpart;                       // [j_split][3][n]
+    double* S;                           // [n] or nullptr (diagnostic mode)
+    double* U;                           // [2][n] or nullptr (diagnostic mode)
+};
+hipError_t launch_pair(const PairLaunch& L, const PairTable& tab, hipStream_t s);
+
+struct StepLaunch {
+    float4* pos;
+    float4* lo;
+    const int* typ;
+    const int* oid;
+    const double* Fpart;
+    int j_split;
+    int n;
+    double dt;
+    unsigned long long seed;
+    DevState* st;
+    Box* box;                            // refreshed for the new positions
+};
+hipError_t launch_update(const StepLaunch& L, const ExtParams& P, hipStream_t s);
+
+hipError_t launch_boxes(const float4* pos, int n, Box* box, hipStream_t s);
+
+// Gather into original order: pair force totals, external forces at R(t),
+// and optional S.  Any output may be null.
+hipError_t launch_gather(const float4* pos, const float4* lo, const int* typ, const int* oid,
+                         const double* Fpart, int j_split, const double* S_slot, int n,
+                         const DevState* st, const ExtParams& P, double* F_pair,
+                         double* F_ext, double* S, hipStream_t s);
+
+// Deterministic FP64 sum of m rows of length n: out[r] = sum_s in[r*n + s].
+hipError_t launch_rowsum(const double* in, int rows, int n, double* out, hipStream_t s);
+hipError_t launch_rowmin(const double* in, int rows, int n, double* out, hipStream_t s);
+
+// Positions hi + lo as FP64 rows work[0..2][n].
+hipError_t launch_pos_rows(const float4* pos, const float4* lo, int n, double* work,
+                           hipStream_t s);
+
+// Replace the charge word of every slot: pos[s].w = qhat[oid[s]].
+hipError_t launch_set_charge(float4* pos, const int* oid, const float* qhat, int n,
+                             hipStream_t s);
+
+// Per-slot diagnostic terms -> out[10] (see ld_diagnostics).
+hipError_t launch_diag(const float4* pos, const float4* lo, const int* typ,
+                       const double* Fpart, int j_split, const double* U_slot, int n,
+                       const DevState* st, const ExtParams& P, double* work, double* out,
+                       hipStream_t s);
+
+// Spatial ordering: Morton keys over the current bounding cube, sort, and
+// permutation of every per-slot array.
+struct SortBuffers {
+    unsigned long long* keys;            // [n_pow2]
+    int n_pow2;
+    float4* tmp4;                        // [n]
+    int* tmp_i;                          // [n]
+    float* bounds;                       // [8] device scratch
+    float* bounds_part;                  // per-block partial min/max
+    int bounds_parts;
+};
+hipError_t launch_sort(float4* pos, float4* lo, int* typ, int* oid, int n,
+                       const SortBuffers& B, hipStream_t s);
+
+// 64-bit bitonic sort of n_pow2 keys (ascending).
+hipError_t launch_bitonic(unsigned long long* keys, int n_pow2, hipStream_t s);
+
+// Post-processing.
+hipError_t launch_rdf(const float4* pos, const float4* lo, int n, double r_max, int n_bins,
+                      const double* centre, unsigned long long* counts,
+                      unsigned long long* ccounts, hipStream_t s);
+hipError_t launch_moments(const float4* pos, const float4* lo, int n, double* work,
+                          double* out4, hipStream_t s);
+hipError_t launch_boxcount(const float4* pos, const float4* lo, int n, const double* lo3,
+                           double eps, unsigned long long* keys, int n_pow2,
+                           unsigned long long* count, hipStream_t s);
+
+}  // namespace ld
+
+// The opaque context behind the C ABI.
+struct ld_ctx {
+    int64_t n = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    ld_params p{};
+    ld_radius R{};
+    uint64_t seed = 0;
+    ld_tuning tune{};
+    ld::PairTable tab{};
+    ld::ExtParams ext{};
+
+    float4* pos = nullptr;               // [n] {x_hi, y_hi, z_hi, q_hat}, slot order
+    float4* lo = nullptr;                // [n] {x_lo, y_lo, z_lo, 0}
+    int* typ = nullptr;                  // [n] type per slot
+    int* oid = nullptr;                  // [n] original index per slot
+    ld::Box* box = nullptr;              // [ceil(n/64)] group boxes
+    double* Fpart = nullptr;             // [j_split_cap][3][n]
+    int j_split_cap = 0;
+    double* S_slot = nullptr;            // [n]
+    double* U_slot = nullptr;            // [2][n]
+    double* work = nullptr;              // [16][n] FP64 scratch (outputs, reductions)
+    double* aux = nullptr;               // [kAuxWords] histograms and small results
+    ld::DevState* st = nullptr;
+    ld::SortBuffers sb{};
+    int64_t steps_since_sort = 0;
+
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+};

@@ -1,0 +1,322 @@
+// O(N) kernels of a step: external forces, Brownian noise and the overdamped
+// Langevin update (section 2.2, steps (iii)-(vi)), plus gathers and
+// deterministic reductions used by the force and diagnostic calls.
+#include "ld_internal.h"
+
+namespace ld {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// ((u >> 9) + 1/2) 2^-23: exact in FP32.
+__device__ __forceinline__ float u23(uint32_t u) {
+    return ((float)(u >> 9) + 0.5f) * (1.0f / 8388608.0f);
+}
+
+// Three standard normals for particle id at step n (Box-Muller, FP32).
+__device__ __forceinline__ void gauss3(uint32_t id, unsigned long long n, unsigned long long seed,
+                                       float xi[3]) {
+    uint32_t c0 = id, c1 = (uint32_t)n, c2 = (uint32_t)(n >> 32), c3 = 0u;
+    philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float a = sqrtf(-2.0f * logf(u23(c0)));
+    const float b = sqrtf(-2.0f * logf(u23(c2)));
+    float s1, k1, s3, k3;
+    sincospif(2.0f * u23(c1), &s1, &k1);
+    sincospif(2.0f * u23(c3), &s3, &k3);
+    xi[0] = a * k1;
+    xi[1] = a * s1;
+    xi[2] = b * k3;
+}
+
+// External force at x for type t and droplet radius R (FP64): the surface
+// spring (one-sided, equilibrium wall_offset inside R; band mode limits it to
+// within sigma/2 of R), gravity and the centrifugal force.
+__device__ __forceinline__ void ext_force(const double x[3], int t, double R,
+                                          const ExtParams& P, double F[3]) {
+    const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const double Rw = R - P.wall_offset[t];
+    bool on = r > Rw;
+    if (P.wall_band) {
+        const double h = P.half_sigma[t];
+        on = on && (r > R - h) && (r < R + h);
+    }
+    const double m = (on && r > 0.0) ? -P.k_wall[t] * (r - Rw) / r : 0.0;
+    const double c = P.mass[t] * P.omega2;
+    F[0] = m * x[0] + P.mass[t] * P.gravity[0] + c * x[0];
+    F[1] = m * x[1] + P.mass[t] * P.gravity[1] + c * x[1];
+    F[2] = m * x[2] + P.mass[t] * P.gravity[2] + (P.rotation == 0 ? c * x[2] : 0.0);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Bounding box of each 64-slot group (one wavefront per group).
+__device__ __forceinline__ void write_box(const float4 h, bool live, int s, Box* box) {
+    const float lx = wave_min(live ? h.x : INFINITY), hx = wave_max(live ? h.x : -INFINITY);
+    const float ly = wave_min(live ? h.y : INFINITY), hy = wave_max(live ? h.y : -INFINITY);
+    const float lz = wave_min(live ? h.z : INFINITY), hz = wave_max(live ? h.z : -INFINITY);
+    if ((threadIdx.x & (kGroup - 1)) == 0 && lx <= hx) {
+        Box b;
+        b.lo = make_float4(lx, ly, lz, 0.f);
+        b.hi = make_float4(hx, hy, hz, 0.f);
+        box[s / kGroup] = b;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update(StepLaunch L, ExtParams P) {
+    const long long step = L.st->step;
+    const double t = L.st->t;
+    const double tn = t + L.dt;
+    const double R = radius_at(P.R, tn);   // the new radius precedes the surface forces
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const bool live = s < L.n;
+    float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (live) {
+        h = L.pos[s];
+        const float4 l = L.lo[s];
+        const int ty = L.typ[s];
+        double F[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < L.j_split; ++k) {
+            const double* Fp = L.Fpart + (size_t)k * 3 * (size_t)L.n;
+            F[0] += Fp[s];
+            F[1] += Fp[(size_t)L.n + s];
+            F[2] += Fp[2 * (size_t)L.n + s];
+        }
+        const double x[3] = {(double)h.x + (double)l.x, (double)h.y + (double)l.y,
+                             (double)h.z + (double)l.z};
+        double Fe[3];
+        ext_force(x, ty, R, P, Fe);
+        const double mu = P.mu[ty];
+        float xi[3] = {0.f, 0.f, 0.f};
+        double amp = 0.0;
+        if (P.noise != 0 && P.kT > 0.0) {
+            gauss3((uint32_t)L.oid[s], (unsigned long long)step, L.seed, xi);
+            amp = sqrt(2.0 * P.kT * mu * L.dt);
+            if (P.noise == 2) {
+                const float m = sqrtf(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+                const float f = 1.7320508075688772f / m;
+                xi[0] *= f; xi[1] *= f; xi[2] *= f;
+            }
+        }
+        bool bad = false;
+        double xn[3];
+        for (int c = 0; c < 3; ++c) {
+            const double d = mu * L.dt * (F[c] + Fe[c]) + amp * (double)xi[c];
+            if (!isfinite(d) || (P.jump_max > 0.0 && fabs(d) > P.jump_max)) bad = true;
+            xn[c] = x[c] + d;
+        }
+        if (bad) atomicMin(&L.st->bad_step, (unsigned long long)step);
+        h.x = (float)xn[0];
+        h.y = (float)xn[1];
+        h.z = (float)xn[2];
+        const float4 nl = make_float4((float)(xn[0] - (double)h.x), (float)(xn[1] - (double)h.y),
+                                      (float)(xn[2] - (double)h.z), 0.f);
+        L.pos[s] = h;
+        L.lo[s] = nl;
+    }
+    if (L.box) write_box(h, live, s, L.box);
+    // The last workgroup to finish advances the step counter and time.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(&L.st->done, 1u);
+        if (prev == gridDim.x - 1) {
+            L.st->step = step + 1;
+            L.st->t = tn;
+            L.st->done = 0u;
+            __threadfence();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_boxes(const float4* __restrict__ pos, int n,
+                                                  Box* box) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const bool live = s < n;
+    const float4 h = live ? pos[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+    write_box(h, live, s, box);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(
+    const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
+    const int* __restrict__ oid, const double* __restrict__ Fpart, int j_split,
+    const double* __restrict__ S_slot, int n, const DevState* st, ExtParams P, double* F_pair,
+    double* F_ext, double* S) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const int o = oid[s];
+    if (F_pair) {
+        double F[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < j_split; ++k) {
+            const double* Fp = Fpart + (size_t)k * 3 * (size_t)n;
+            F[0] += Fp[s];
+            F[1] += Fp[(size_t)n + s];
+            F[2] += Fp[2 * (size_t)n + s];
+        }
+        F_pair[3 * (size_t)o] = F[0];
+        F_pair[3 * (size_t)o + 1] = F[1];
+        F_pair[3 * (size_t)o + 2] = F[2];
+    }
+    if (F_ext) {
+        const float4 h = pos[s], l = lo[s];
+        const double x[3] = {(double)h.x + (double)l.x, (double)h.y + (double)l.y,
+                             (double)h.z + (double)l.z};
+        double Fe[3];
+        ext_force(x, typ[s], radius_at(P.R, st->t), P, Fe);
+        F_ext[3 * (size_t)o] = Fe[0];
+        F_ext[3 * (size_t)o + 1] = Fe[1];
+        F_ext[3 * (size_t)o + 2] = Fe[2];
+    }
+    if (S) S[o] = S_slot[s];
+}
+
+// One workgroup per row; each lane reduces a fixed strided subset in order,
+// then a fixed tree: the result depends only on n.  OP: 0 sum, 1 max, 2 min.
+template <int OP>
+__device__ __forceinline__ double red_op(double a, double b) {
+    if constexpr (OP == 0) return a + b;
+    else if constexpr (OP == 1) return fmax(a, b);
+    else return fmin(a, b);
+}
+
+template <int OP>
+__global__ __launch_bounds__(1024) void k_rowreduce(const double* __restrict__ in, int n,
+                                                    double* out) {
+    __shared__ double red[1024];
+    const double* row = in + (size_t)blockIdx.x * (size_t)n;
+    double acc = OP == 0 ? 0.0 : (OP == 1 ? -INFINITY : INFINITY);
+    for (int k = threadIdx.x; k < n; k += 1024) acc = red_op<OP>(acc, row[k]);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red_op<OP>(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// Per-slot diagnostic terms: rows 0 U_wall, 1 U_grav, 2 U_cf, 3-5 F_pair,
+// 6 |F_pair|, 7 |x|.
+__global__ __launch_bounds__(kBlock) void k_diag_terms(
+    const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
+    const double* __restrict__ Fpart, int j_split, int n, const DevState* st, ExtParams P,
+    double* work) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const float4 h = pos[s], l = lo[s];
+    const int t = typ[s];
+    const double x[3] = {(double)h.x + (double)l.x, (double)h.y + (double)l.y,
+                         (double)h.z + (double)l.z};
+    const double R = radius_at(P.R, st->t);
+    const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const double Rw = R - P.wall_offset[t];
+    bool on = r > Rw;
+    if (P.wall_band) on = on && (r > R - P.half_sigma[t]) && (r < R + P.half_sigma[t]);
+    const size_t N = (size_t)n;
+    work[s] = on ? 0.5 * P.k_wall[t] * (r - Rw) * (r - Rw) : 0.0;
+    work[N + s] = -P.mass[t] * (P.gravity[0] * x[0] + P.gravity[1] * x[1] + P.gravity[2] * x[2]);
+    const double rho2 = x[0] * x[0] + x[1] * x[1] + (P.rotation == 0 ? x[2] * x[2] : 0.0);
+    work[2 * N + s] = -0.5 * P.mass[t] * P.omega2 * rho2;
+    double F[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < j_split; ++k) {
+        const double* Fp = Fpart + (size_t)k * 3 * N;
+        F[0] += Fp[s];
+        F[1] += Fp[N + s];
+        F[2] += Fp[2 * N + s];
+    }
+    work[3 * N + s] = F[0];
+    work[4 * N + s] = F[1];
+    work[5 * N + s] = F[2];
+    work[6 * N + s] = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+    work[7 * N + s] = r;
+}
+
+__global__ void k_diag_finish(const double* sums, const double* maxes, const double* U,
+                              double* out) {
+    out[0] = U[0];
+    out[1] = U[1];
+    out[2] = sums[0];
+    out[3] = sums[1];
+    out[4] = sums[2];
+    out[5] = sums[3];
+    out[6] = sums[4];
+    out[7] = sums[5];
+    out[8] = maxes[0];
+    out[9] = maxes[1];
+}
+
+}  // namespace
+
+hipError_t launch_update(const StepLaunch& L, const ExtParams& P, hipStream_t s) {
+    const int blocks = (L.n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_update, dim3(blocks), dim3(kBlock), 0, s, L, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_boxes(const float4* pos, int n, Box* box, hipStream_t s) {
+    const int blocks = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_boxes, dim3(blocks), dim3(kBlock), 0, s, pos, n, box);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const float4* pos, const float4* lo, const int* typ, const int* oid,
+                         const double* Fpart, int j_split, const double* S_slot, int n,
+                         const DevState* st, const ExtParams& P, double* F_pair,
+                         double* F_ext, double* S, hipStream_t s) {
+    const int blocks = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(kBlock), 0, s, pos, lo, typ, oid, Fpart,
+                       j_split, S_slot, n, st, P, F_pair, F_ext, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowsum(const double* in, int rows, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_rowreduce<0>, dim3(rows), dim3(1024), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowmin(const double* in, int rows, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_rowreduce<2>, dim3(rows), dim3(1024), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const float4* pos, const float4* lo, const int* typ,
+                       const double* Fpart, int j_split, const double* U_slot, int n,
+                       const DevState* st, const ExtParams& P, double* work, double* out,
+                       hipStream_t s) {
+    const int blocks = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_diag_terms, dim3(blocks), dim3(kBlock), 0, s, pos, lo, typ, Fpart,
+                       j_split, n, st, P, work);
+    double* sums = work + 8 * (size_t)n;
+    double* maxes = sums + 8;
+    double* U = maxes + 8;
+    hipLaunchKernelGGL(k_rowreduce<0>, dim3(6), dim3(1024), 0, s, work, n, sums);
+    hipLaunchKernelGGL(k_rowreduce<1>, dim3(2), dim3(1024), 0, s, work + 6 * (size_t)n, n,
+                       maxes);
+    hipLaunchKernelGGL(k_rowreduce<0>, dim3(2), dim3(1024), 0, s, U_slot, n, U);
+    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(1), 0, s, sums, maxes, U, out);
+    return hipGetLastError();
+}
+
+}  // namespace ld

@@ -1,0 +1,290 @@
+"""Thin Python binding of libldrop (include/ldrop.h).
+
+Argument marshalling only: every step of the model runs in the HIP library.
+PyTorch supplies device memory (output tensors) and the HIP stream.  The
+library is loaded from this package directory; if it is missing, or no GPU
+is visible, construction fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldrop.so")
+MAX_TYPES = 8
+
+LD_OK = 0
+_STATUS = {0: "LD_OK", -1: "LD_EINVAL", -2: "LD_ENOMEM", -3: "LD_EHIP", -4: "LD_ENONFINITE",
+           -5: "LD_ESTATE", -6: "LD_EUNSUPPORTED"}
+
+
+class LdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class NonFinite(LdError):
+    pass
+
+
+class ld_params(C.Structure):
+    _fields_ = [
+        ("n_types", C.c_int32), ("use_eps_matrix", C.c_int32),
+        ("sigma", C.c_double * MAX_TYPES), ("eps", C.c_double * MAX_TYPES),
+        ("mass", C.c_double * MAX_TYPES), ("gamma", C.c_double * MAX_TYPES),
+        ("k_wall", C.c_double * MAX_TYPES), ("wall_offset", C.c_double * MAX_TYPES),
+        ("eps_matrix", C.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("lj_cut", C.c_double), ("coul_cut", C.c_double), ("bjerrum", C.c_double),
+        ("kT", C.c_double), ("gravity", C.c_double * 3), ("omega", C.c_double),
+        ("rotation", C.c_int32), ("wall_band", C.c_int32), ("noise", C.c_int32),
+        ("reserved", C.c_int32), ("jump_max", C.c_double),
+    ]
+
+
+class ld_radius(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("R0", C.c_double),
+                ("R1", C.c_double), ("T", C.c_double), ("a", C.c_double),
+                ("R_min", C.c_double)]
+
+
+class ld_tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("j_split", C.c_int32), ("comp", C.c_int32),
+                ("sort_every", C.c_int32), ("cull", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+SYMBOLS = [
+    "ld_init", "ld_destroy", "ld_last_error", "ld_forces", "ld_step", "ld_sync",
+    "ld_get_positions", "ld_get_state", "ld_set_params", "ld_diagnostics", "ld_rdf",
+    "ld_fractal", "ld_get_tuning", "ld_set_tuning", "ld_kernel_timing", "ld_kernel_time",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libldrop.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2501_04456_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, fp = C.c_void_p, C.c_void_p, C.c_void_p
+        L.ld_init.argtypes = [C.POINTER(C.c_void_p), C.c_int64, vp, vp, vp,
+                              C.POINTER(ld_params), C.POINTER(ld_radius), C.c_uint64, vp]
+        L.ld_destroy.argtypes = [vp]
+        L.ld_destroy.restype = None
+        L.ld_last_error.restype = C.c_char_p
+        L.ld_forces.argtypes = [vp, dp, dp, dp, dp]
+        L.ld_step.argtypes = [vp, C.c_double, C.c_int64]
+        L.ld_sync.argtypes = [vp]
+        L.ld_get_positions.argtypes = [vp, fp, fp]
+        L.ld_get_state.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]
+        L.ld_set_params.argtypes = [vp, C.POINTER(ld_params), C.POINTER(ld_radius)]
+        L.ld_diagnostics.argtypes = [vp, dp]
+        L.ld_rdf.argtypes = [vp, C.c_double, C.c_int32, C.c_double, C.c_int32, vp, vp, vp, vp]
+        L.ld_fractal.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int32, vp, vp]
+        L.ld_get_tuning.argtypes = [vp, C.POINTER(ld_tuning)]
+        L.ld_set_tuning.argtypes = [vp, C.POINTER(ld_tuning)]
+        L.ld_kernel_timing.argtypes = [vp, C.c_int32]
+        L.ld_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        for name in SYMBOLS:
+            if name not in ("ld_destroy", "ld_last_error"):
+                getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != LD_OK:
+        msg = lib().ld_last_error().decode()
+        raise (NonFinite if status == -4 else LdError)(status, msg)
+
+
+def make_params(p: W.Params) -> ld_params:
+    s = ld_params()
+    T = len(p.sigma)
+    s.n_types = T
+    for name in ("sigma", "eps", "mass", "gamma", "k_wall", "wall_offset"):
+        arr = getattr(s, name)
+        for t, v in enumerate(getattr(p, name)):
+            arr[t] = float(v)
+    if p.eps_matrix is not None:
+        s.use_eps_matrix = 1
+        for a in range(T):
+            for b in range(T):
+                s.eps_matrix[a * MAX_TYPES + b] = float(p.eps_matrix[a][b])
+    s.lj_cut, s.coul_cut, s.bjerrum, s.kT = p.lj_cut, p.coul_cut, p.bjerrum, p.kT
+    for c in range(3):
+        s.gravity[c] = float(p.gravity[c])
+    s.omega, s.rotation, s.wall_band, s.noise = p.omega, p.rotation, p.wall_band, p.noise
+    s.jump_max = p.jump_max
+    return s
+
+
+def make_radius(r: W.Radius) -> ld_radius:
+    s = ld_radius()
+    s.kind, s.R0, s.R1, s.T, s.a, s.R_min = r.kind, r.R0, r.R1, r.T, r.a, r.R_min
+    return s
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libldrop needs a ROCm GPU; torch.cuda.is_available() is False")
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class System:
+    """One droplet on the GPU (an ld_ctx)."""
+
+    def __init__(self, type_, charge, pos, params: W.Params, radius: W.Radius, seed: int,
+                 stream=None):
+        torch = _torch()
+        self._torch = torch
+        dev = torch.device("cuda")
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        t = torch.as_tensor(np.ascontiguousarray(type_, dtype=np.int32), device=dev)
+        q = torch.as_tensor(np.ascontiguousarray(charge, dtype=np.float64), device=dev)
+        x = torch.as_tensor(np.ascontiguousarray(np.asarray(pos, dtype=np.float32).reshape(-1, 3)),
+                            device=dev)
+        self.n = int(t.numel())
+        self.params = params
+        self.radius = radius
+        self._p = make_params(params)
+        self._r = make_radius(radius)
+        h = C.c_void_p()
+        _check(lib().ld_init(C.byref(h), self.n, _ptr(t), _ptr(q), _ptr(x), C.byref(self._p),
+                             C.byref(self._r), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                             C.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+
+    @classmethod
+    def from_workload(cls, w: W.Workload, **kw) -> "System":
+        return cls(w.type, w.charge, w.pos, w.params, w.radius, w.seed, **kw)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().ld_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- hot path ---------------------------------------------------------
+    def forces(self, ext: bool = True, S: bool = False, U: bool = False):
+        """Returns dict with 'pair' [n,3], optional 'ext' [n,3], 'S' [n] (cuda FP64
+        tensors) and 'U' (numpy [2])."""
+        torch = self._torch
+        dev = torch.device("cuda")
+        Fp = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        Fe = torch.empty((self.n, 3), dtype=torch.float64, device=dev) if ext else None
+        Ss = torch.empty(self.n, dtype=torch.float64, device=dev) if S else None
+        Uu = np.zeros(2) if U else None
+        _check(lib().ld_forces(self.h, _ptr(Fp), _ptr(Fe) if ext else None,
+                               _ptr(Ss) if S else None,
+                               Uu.ctypes.data_as(C.c_void_p) if U else None))
+        out = {"pair": Fp}
+        if ext:
+            out["ext"] = Fe
+        if S:
+            out["S"] = Ss
+        if U:
+            out["U"] = Uu
+        return out
+
+    def step(self, n_steps: int, dt: float = None):
+        dt = self.dt if dt is None else dt
+        _check(lib().ld_step(self.h, float(dt), int(n_steps)))
+
+    def sync(self):
+        _check(lib().ld_sync(self.h))
+
+    # -- state --------------------------------------------------------------
+    def positions(self):
+        """(hi, lo) FP32 numpy arrays [n,3] in original order."""
+        hi = np.zeros((self.n, 3), np.float32)
+        lo = np.zeros((self.n, 3), np.float32)
+        _check(lib().ld_get_positions(self.h, hi.ctypes.data_as(C.c_void_p),
+                                      lo.ctypes.data_as(C.c_void_p)))
+        return hi, lo
+
+    def positions64(self) -> np.ndarray:
+        hi, lo = self.positions()
+        return hi.astype(np.float64) + lo.astype(np.float64)
+
+    def state(self):
+        s, t, R = C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().ld_get_state(self.h, C.byref(s), C.byref(t), C.byref(R)))
+        return s.value, t.value, R.value
+
+    def set_params(self, params: W.Params = None, radius: W.Radius = None):
+        p = make_params(params) if params is not None else None
+        r = make_radius(radius) if radius is not None else None
+        _check(lib().ld_set_params(self.h, C.byref(p) if p else None,
+                                   C.byref(r) if r else None))
+        if params is not None:
+            self.params = params
+        if radius is not None:
+            self.radius = radius
+
+    def diagnostics(self) -> np.ndarray:
+        out = np.zeros(10)
+        _check(lib().ld_diagnostics(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    # -- post-processing ----------------------------------------------------
+    def rdf(self, r_max: float, n_bins: int, V: float = 0.0, centre: int = 0):
+        counts = np.zeros(n_bins, np.uint64)
+        cc = np.zeros(n_bins, np.uint64)
+        g = np.zeros(n_bins)
+        cbar = np.zeros(n_bins)
+        _check(lib().ld_rdf(self.h, r_max, n_bins, V, centre, counts.ctypes.data_as(C.c_void_p),
+                            g.ctypes.data_as(C.c_void_p), cc.ctypes.data_as(C.c_void_p),
+                            cbar.ctypes.data_as(C.c_void_p)))
+        return counts, cc, g, cbar
+
+    def fractal(self, k_f: float = 1.593, d: float = 0.0, eps0: float = 0.0,
+                max_scales: int = 32):
+        out = np.zeros(4)
+        bc = np.zeros(max_scales, np.int64)
+        _check(lib().ld_fractal(self.h, k_f, d, eps0, max_scales, out.ctypes.data_as(C.c_void_p),
+                                bc.ctypes.data_as(C.c_void_p)))
+        K = int(out[3])
+        return out[0], out[1], out[2], K, bc[:K].copy()
+
+    # -- performance controls -----------------------------------------------
+    def tuning(self) -> dict:
+        t = ld_tuning()
+        _check(lib().ld_get_tuning(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k in ("block", "j_split", "comp", "sort_every", "cull")}
+
+    def set_tuning(self, **kw):
+        t = ld_tuning()
+        _check(lib().ld_get_tuning(self.h, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(lib().ld_set_tuning(self.h, C.byref(t)))
+
+    def kernel_timing(self, enable: bool):
+        _check(lib().ld_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self):
+        n, ms = C.c_int64(), C.c_double()
+        _check(lib().ld_kernel_time(self.h, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    dt = 1e-3

@@ -1,0 +1,325 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+identical seeded inputs.
+
+Tolerances (FP32 pair math with FP64 totals):
+* forces: max_i |dF_i| / S_i <= 1e-5 with S_i = sum_j |f_LJ,ij| + |f_C,ij|
+  (what FP32 summation can guarantee under cancellation), and
+  median_i |dF_i| / |F_i| <= 1e-5;
+* positions: max |dx| <= 1e-4 sigma after 100 steps (small system) or 20
+  steps (large composition), same Philox stream;
+* integer outputs (RDF counts, box counts): exact.
+Particles with an LJ partner within 1e-5 (relative) of the cutoff are left
+out of force comparisons: FP32 and FP64 may legitimately disagree on which
+side of the cutoff such a pair is.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2501_04456_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FORCE_TOL = 1e-5
+POS_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ld():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_04456_amd import ldrop
+    ldrop.lib()
+    return ldrop
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def ambiguous_rows(w, rows=None, rel=1e-5):
+    """Rows with an LJ pair within `rel` of its cutoff."""
+    from scipy.spatial import cKDTree
+    x = w.pos.astype(np.float64)
+    sig = np.asarray(w.params.sigma)[w.type]
+    reach = w.params.lj_cut * max(w.params.sigma) * (1 + 2 * rel)
+    tree = cKDTree(x)
+    rows = np.arange(w.n) if rows is None else np.asarray(rows)
+    bad = np.zeros(len(rows), bool)
+    for k, i in enumerate(rows):
+        for j in tree.query_ball_point(x[i], reach):
+            if j == i:
+                continue
+            rc = w.params.lj_cut * 0.5 * (sig[i] + sig[j])
+            d = np.linalg.norm(x[i] - x[j])
+            if abs(d - rc) <= rel * rc:
+                bad[k] = True
+    return bad
+
+
+def force_errors(Fg, Fo, S):
+    dF = np.linalg.norm(Fg - Fo, axis=1)
+    nrm = np.linalg.norm(Fo, axis=1)
+    scaled = dF / np.maximum(S, 1e-300)
+    rel = dF[nrm > 0] / nrm[nrm > 0]
+    return scaled, rel
+
+
+def check_forces(w, Fg, rows=None, orc=None, ext=None):
+    Fo, So, _ = orc.pair_forces(w.pos, w.type, w.charge, w.params, rows=rows)
+    keep = ~ambiguous_rows(w, rows)
+    scaled, rel = force_errors(Fg[keep], Fo[keep], So[keep])
+    assert scaled.max() <= FORCE_TOL, f"max |dF|/S = {scaled.max():.3e}"
+    assert np.median(rel) <= FORCE_TOL, f"median |dF|/|F| = {np.median(rel):.3e}"
+    return scaled, rel
+
+
+# ---------------------------------------------------------------------------
+# Forces
+# ---------------------------------------------------------------------------
+
+def test_forces_small(ld, orc):
+    w = W.config_small()
+    s = ld.System.from_workload(w)
+    out = s.forces(ext=True, S=True, U=True)
+    Fg = out["pair"].cpu().numpy()
+    check_forces(w, Fg, orc=orc)
+    Fo, So, Uo = orc.pair_forces(w.pos, w.type, w.charge, w.params)
+    # the diagnostic-mode S and U
+    assert np.allclose(out["S"].cpu().numpy(), So, rtol=1e-5)
+    assert np.allclose(out["U"], Uo, rtol=1e-5, atol=1e-6 * np.abs(Uo).sum())
+    # external forces at R(t=0), FP64 on both sides
+    R0 = orc.radius_at(w.radius, 0.0)
+    Fe = np.array([orc.external_force(w.pos[i].astype(np.float64), w.type[i], w.params, R0)
+                   for i in range(w.n)])
+    assert np.allclose(out["ext"].cpu().numpy(), Fe, rtol=1e-12, atol=1e-12)
+
+
+TUNINGS = [
+    dict(block=64, j_split=1, comp=0, cull=0),
+    dict(block=128, j_split=3, comp=1, cull=1),
+    dict(block=256, j_split=7, comp=0, cull=1),
+    dict(block=512, j_split=2, comp=1, cull=0),
+    dict(block=256, j_split=1, comp=1, cull=1),
+]
+
+
+@pytest.mark.parametrize("n", [2, 65, 3001])
+@pytest.mark.parametrize("tune", TUNINGS)
+def test_forces_tunings_ragged(ld, orc, n, tune):
+    w = W.config_large(n=n, seed=31)
+    if n == 2:
+        w.pos = np.array([[0.0, 0.0, 0.0], [1.7, 0.3, -0.2]], np.float32)
+    s = ld.System.from_workload(w)
+    s.set_tuning(**tune)
+    Fg = s.forces(ext=False)["pair"].cpu().numpy()
+    check_forces(w, Fg, orc=orc)
+
+
+def test_forces_dense_lj(ld, orc):
+    """A compact cluster so that many pairs are inside the LJ range, with an
+    explicit (non-Lorentz-Berthelot) eps matrix."""
+    rng = np.random.default_rng(4)
+    g_ = np.arange(12) * 1.15
+    x = np.stack(np.meshgrid(g_, g_, g_, indexing="ij"), -1).reshape(-1, 3)
+    x = (x + rng.uniform(-0.05, 0.05, x.shape)).astype(np.float32)
+    n = len(x)
+    w = W.config_medium(n=n, seed=9, with_positions=False)
+    w.pos = x
+    w.params.eps_matrix = [[1.0, 0.4], [0.4, 2.0]]
+    s = ld.System.from_workload(w)
+    for tune in TUNINGS[:3]:
+        s.set_tuning(**tune)
+        Fg = s.forces(ext=False)["pair"].cpu().numpy()
+        check_forces(w, Fg, orc=orc)
+
+
+def test_forces_full_size_sampled(ld, orc):
+    """N = 250000 in the launch configuration the benchmark times; the oracle
+    computes a sample of rows one by one against all N particles."""
+    w = W.config_large()
+    s = ld.System.from_workload(w)
+    Fg = s.forces(ext=False)["pair"].cpu().numpy()
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(w.n, 96, replace=False))
+    rows = np.concatenate([rows, [0, w.n - 1]])
+    check_forces(w, Fg[rows], rows=rows, orc=orc)
+    # one step from the same state: sampled new positions
+    s.step(1, w.dt)
+    xg = s.positions64()
+    st = orc.State(w)
+    xo, bad = st.step_rows(rows, w.dt)
+    assert bad == -1
+    keep = ~ambiguous_rows(w, rows)
+    err = np.abs(xg[rows][keep] - xo[keep]).max()
+    assert err <= 1e-6, err
+
+
+# ---------------------------------------------------------------------------
+# Trajectories
+# ---------------------------------------------------------------------------
+
+def trajectory(ld, orc, w, steps, tune=None):
+    s = ld.System.from_workload(w)
+    if tune:
+        s.set_tuning(**tune)
+    s.step(steps, w.dt)
+    s.sync()
+    xg = s.positions64()
+    st = orc.State(w)
+    bad = st.run(steps)
+    assert bad == -1
+    step, t, R = s.state()
+    assert step == steps and t == pytest.approx(st.t, rel=1e-15)
+    return xg, st.x
+
+
+def test_trajectory_small_100_steps(ld, orc):
+    w = W.config_small()
+    xg, xo = trajectory(ld, orc, w, 100)
+    err = np.abs(xg - xo).max()
+    assert err <= POS_TOL, err
+
+
+def test_trajectory_large_composition_20_steps(ld, orc):
+    w = W.config_large(n=6000, seed=17)
+    xg, xo = trajectory(ld, orc, w, 20, tune=dict(sort_every=7))
+    err = np.abs(xg - xo).max()
+    assert err <= POS_TOL, err
+
+
+@pytest.mark.parametrize("noise", [W.NOISE_OFF, W.NOISE_FIXED])
+def test_trajectory_noise_modes(ld, orc, noise):
+    w = W.config_medium(n=1500, seed=23)
+    w.params.noise = noise
+    xg, xo = trajectory(ld, orc, w, 30)
+    assert np.abs(xg - xo).max() <= POS_TOL
+
+
+def test_trajectory_band_wall_axial_rotation(ld, orc):
+    w = W.config_medium(n=800, seed=29)
+    w.params.wall_band = 1
+    w.params.wall_offset = [0.5, 0.75]
+    w.params.rotation = 1
+    w.params.omega = 0.3
+    w.radius = W.Radius(kind=W.RADIUS_LINEAR, R0=w.radius.R0, R1=0.5 * w.radius.R0, T=0.01)
+    xg, xo = trajectory(ld, orc, w, 40)
+    assert np.abs(xg - xo).max() <= POS_TOL
+
+
+def test_determinism_and_split_invariance(ld):
+    w = W.config_large(n=4000, seed=2)
+    a = ld.System.from_workload(w)
+    a.step(25, w.dt)
+    b = ld.System.from_workload(w)
+    b.step(25, w.dt)
+    xa, xb = a.positions64(), b.positions64()
+    assert np.array_equal(xa, xb)
+    c = ld.System.from_workload(w)
+    c.set_tuning(block=128, j_split=5, sort_every=3)
+    c.step(25, w.dt)
+    assert np.abs(c.positions64() - xa).max() <= 1e-6
+
+
+def test_set_params_midway(ld, orc):
+    """Restart with new parameters (section 2.2): both sides switch at step 10."""
+    w = W.config_medium(n=1200, seed=41)
+    s = ld.System.from_workload(w)
+    s.step(10, w.dt)
+    st = orc.State(w)
+    st.run(10)
+    p2 = W.Params(**{**w.params.__dict__})
+    p2.kT = 2.0
+    p2.omega = 0.1
+    r2 = W.Radius(kind=W.RADIUS_CONST, R0=w.radius.R0 * 0.9)
+    s.set_params(p2, r2)
+    st.params, st.radius = p2, r2
+    s.step(10, w.dt)
+    st.run(10)
+    assert np.abs(s.positions64() - st.x).max() <= POS_TOL
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics and post-processing
+# ---------------------------------------------------------------------------
+
+def test_diagnostics(ld, orc):
+    w = W.config_medium(n=3000, seed=7)
+    s = ld.System.from_workload(w)
+    dg = s.diagnostics()
+    st = orc.State(w)
+    do = st.diagnostics()
+    assert dg[0] == pytest.approx(do[0], rel=1e-5, abs=1e-9)
+    assert dg[1] == pytest.approx(do[1], rel=1e-5)
+    assert np.allclose(dg[2:5], do[2:5], rtol=1e-12, atol=1e-12)
+    # net pair force: zero up to FP32 rounding of the pair terms
+    _, S, _ = orc.pair_forces(w.pos, w.type, w.charge, w.params)
+    assert np.all(np.abs(dg[5:8]) <= 1e-5 * S.sum())
+    assert dg[8] == pytest.approx(do[8], rel=1e-4)
+    assert dg[9] == pytest.approx(do[9], rel=1e-12)
+
+
+def test_rdf_exact_counts(ld, orc):
+    w = W.config_medium(n=5000, seed=3)
+    s = ld.System.from_workload(w)
+    V = 4 / 3 * math.pi * w.radius.R0 ** 3
+    counts, cc, g, cbar = s.rdf(12.0, 240, V=V, centre=0)
+    oc, occ, og, ocbar = orc.rdf(w.pos, 12.0, 240, V)
+    assert np.array_equal(counts, oc)
+    assert np.array_equal(cc, occ)
+    assert np.allclose(g, og, rtol=1e-12) and np.allclose(cbar, ocbar, rtol=1e-12)
+    # centre of mass: the centre itself is a reduction, so allow edge flips
+    counts2, cc2, _, _ = s.rdf(w.radius.R0, 50, V=V, centre=1)
+    com = w.pos.astype(np.float64).mean(0)
+    _, occ2, _, _ = orc.rdf(w.pos, w.radius.R0, 50, V, centre=com)
+    assert np.abs(cc2.astype(np.int64) - occ2.astype(np.int64)).max() <= 2
+
+
+def test_fractal(ld, orc):
+    w = W.config_medium(n=4000, seed=5)
+    s = ld.System.from_workload(w)
+    Rg, Df, Db, K, bc = s.fractal(1.593, 0.0, 0.0)
+    sig = np.asarray(w.params.sigma)[w.type]
+    oRg, oDf, oDb, oK, obc = orc.fractal(w.pos, 1.593, sig.mean(), sig.min())
+    assert Rg == pytest.approx(oRg, rel=1e-12)
+    assert Df == pytest.approx(oDf, rel=1e-10)
+    assert K == oK and np.array_equal(bc, obc)
+    assert Db == pytest.approx(oDb, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Error paths
+# ---------------------------------------------------------------------------
+
+def test_invalid_arguments(ld):
+    w = W.config_small(n=100)
+    p = W.Params(**{**w.params.__dict__})
+    p.gamma = [0.0]
+    with pytest.raises(ld.LdError) as e:
+        ld.System(w.type, w.charge, w.pos, p, w.radius, 1)
+    assert e.value.status == -1 and "gamma" in str(e.value)
+    bad_t = w.type.copy()
+    bad_t[5] = 3
+    with pytest.raises(ld.LdError):
+        ld.System(bad_t, w.charge, w.pos, w.params, w.radius, 1)
+    s = ld.System.from_workload(w)
+    with pytest.raises(ld.LdError):
+        s.step(1, -1.0)
+    with pytest.raises(ld.LdError):
+        s.set_tuning(block=96)
+
+
+def test_blowup_reported(ld):
+    w = W.config_small(n=100)
+    x = w.pos.copy()
+    x[1] = x[0] + np.array([0.3, 0.0, 0.0], np.float32)   # deep LJ overlap
+    s = ld.System(w.type, w.charge, x, w.params, w.radius, 1)
+    s.step(3, w.dt)
+    with pytest.raises(ld.NonFinite) as e:
+        s.sync()
+    assert "step 0" in str(e.value)
