@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -103,6 +105,17 @@ def main():
         from paper_2501_04456_amd import build as hipbuild
         hipbuild.build()
     torch.cuda.set_device(0)
+    if a.copy_calibration > 0:
+        # a plain copy of known size: what the HBM byte counters read for it
+        # scales the pair kernel's counter readings
+        nbytes = a.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written", flush=True)
+        del src, dst
     w = W.config_large(n=a.n)
     s = ldrop.System.from_workload(w)
     tune = s.tuning()

@@ -30,8 +30,9 @@
  *   - Outputs are in the caller's original particle order.
  *   - Work is enqueued on the HIP stream given to ld_init.  ld_step returns
  *     without waiting; calls that return values to host memory wait for the
- *     stream.  Blow-ups detected on the device during ld_step are reported as
- *     LD_ENONFINITE by the next waiting call (ld_sync, ld_get_*, ld_forces).
+ *     stream.  A step whose move is non-finite or larger than jump_max sets a
+ *     device-side flag; ld_sync reports the first such step once as
+ *     LD_ENONFINITE and clears the flag (the state stays readable).
  *   - A context is not thread-safe; distinct contexts are independent.
  *   - Pair math runs in FP32; per-particle force totals, the external forces,
  *     the update and all diagnostics in FP64.  Positions are kept as an FP32
@@ -146,7 +147,7 @@ const char* ld_last_error(void);
  *   F_ext  [n*3] FP64 external forces at R(t) of the current time t, or NULL
  *   S      [n]   FP64 sum_j |f_LJ,ij| + |f_C,ij| (error scale), or NULL
  *   U      [2]   FP64 total LJ and Coulomb pair energies, or NULL
- * Waits for the stream.  Errors: LD_EINVAL, LD_EHIP, LD_ENONFINITE. */
+ * Waits for the stream.  Errors: LD_EINVAL, LD_EHIP. */
 ld_status ld_forces(ld_ctx* ctx, double* F_pair, double* F_ext, double* S, double* U);
 
 /* Advance n_steps >= 0 steps of size dt > 0 (section 2.2 steps (ii)-(vi)):
@@ -155,8 +156,9 @@ ld_status ld_forces(ld_ctx* ctx, double* F_pair, double* F_ext, double* S, doubl
  * LD_EHIP. */
 ld_status ld_step(ld_ctx* ctx, double dt, int64_t n_steps);
 
-/* Wait for the stream; report a pending device-side blow-up.
- * Errors: LD_EHIP, LD_ENONFINITE (ld_last_error names the first bad step). */
+/* Wait for the stream; report a pending device-side blow-up once and clear
+ * it.  Errors: LD_EHIP, LD_ENONFINITE (ld_last_error names the first bad
+ * step since the previous report). */
 ld_status ld_sync(ld_ctx* ctx);
 
 /* ---------------------------------------------------------------------- */

@@ -228,13 +228,22 @@ ld_status run_sort(ld_ctx* c) {
     return LD_OK;
 }
 
-ld_status pending_error(ld_ctx* c) {
+ld_status wait_stream(ld_ctx* c) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LD_OK;
+}
+
+// Report (once) and clear the device-side blow-up flag.
+ld_status take_pending_error(ld_ctx* c) {
     ld::DevState st;
     HIP_TRY(hipMemcpyAsync(&st, c->st, sizeof st, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    if (st.bad_step != ~0ull)
+    if (st.bad_step != ~0ull) {
+        const unsigned long long none = ~0ull;
+        HIP_TRY(hipMemcpy(&c->st->bad_step, &none, sizeof none, hipMemcpyHostToDevice));
         return fail(LD_ENONFINITE, "step %llu produced a non-finite or too large move",
                     (unsigned long long)st.bad_step);
+    }
     return LD_OK;
 }
 
@@ -393,7 +402,7 @@ ld_status ld_forces(ld_ctx* c, double* F_pair, double* F_ext, double* S, double*
     if (F_ext) HIP_TRY(copy_out(F_ext, dE, sizeof(double) * 3 * N, c->stream));
     if (S) HIP_TRY(copy_out(S, dS, sizeof(double) * N, c->stream));
     if (U) HIP_TRY(copy_out(U, dU, sizeof(double) * 2, c->stream));
-    return pending_error(c);
+    return wait_stream(c);
 }
 
 ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
@@ -429,7 +438,7 @@ ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
 ld_status ld_sync(ld_ctx* c) {
     g_err.clear();
     if (!c) return fail(LD_EINVAL, "ctx is NULL");
-    return pending_error(c);
+    return take_pending_error(c);
 }
 
 ld_status ld_get_positions(ld_ctx* c, float* pos, float* pos_lo) {
@@ -466,7 +475,7 @@ ld_status ld_get_positions(ld_ctx* c, float* pos, float* pos_lo) {
             std::memcpy(pos_lo, b.data(), sizeof(float) * 3 * N);
         }
     }
-    return pending_error(c);
+    return wait_stream(c);
 }
 
 ld_status ld_get_state(ld_ctx* c, int64_t* step, double* t, double* R) {
@@ -531,7 +540,7 @@ ld_status ld_diagnostics(ld_ctx* c, double out[10]) {
     HIP_TRY(ld::launch_diag(c->pos, c->lo, c->typ, c->Fpart, 1, c->U_slot, (int)N, c->st, c->ext,
                             c->work, res, c->stream));
     HIP_TRY(copy_out(out, res, sizeof(double) * 10, c->stream));
-    return pending_error(c);
+    return wait_stream(c);
 }
 
 ld_status ld_rdf(ld_ctx* c, double r_max, int32_t n_bins, double V, int32_t centre,
@@ -591,7 +600,7 @@ ld_status ld_rdf(ld_ctx* c, double r_max, int32_t n_bins, double V, int32_t cent
     HIP_TRY(put(ccounts, hcc.data(), sizeof(uint64_t) * n_bins));
     HIP_TRY(put(g, hg.data(), sizeof(double) * n_bins));
     HIP_TRY(put(cbar, hb.data(), sizeof(double) * n_bins));
-    return pending_error(c);
+    return wait_stream(c);
 }
 
 ld_status ld_fractal(ld_ctx* c, double k_f, double d, double eps0, int32_t max_scales,
@@ -654,7 +663,7 @@ ld_status ld_fractal(ld_ctx* c, double k_f, double d, double eps0, int32_t max_s
     } else {
         out[2] = NAN;
     }
-    return pending_error(c);
+    return wait_stream(c);
 }
 
 ld_status ld_get_tuning(ld_ctx* c, ld_tuning* t) {

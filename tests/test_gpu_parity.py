@@ -165,15 +165,21 @@ def test_forces_full_size_sampled(ld, orc):
 # ---------------------------------------------------------------------------
 
 def trajectory(ld, orc, w, steps, tune=None):
+    """Run both sides from the same state; both must flag the same first
+    oversized move (if any)."""
     s = ld.System.from_workload(w)
     if tune:
         s.set_tuning(**tune)
     s.step(steps, w.dt)
-    s.sync()
+    gbad = -1
+    try:
+        s.sync()
+    except ld.NonFinite as e:
+        gbad = int(str(e).split("step ")[1].split()[0])
     xg = s.positions64()
     st = orc.State(w)
     bad = st.run(steps)
-    assert bad == -1
+    assert gbad == bad
     step, t, R = s.state()
     assert step == steps and t == pytest.approx(st.t, rel=1e-15)
     return xg, st.x
