@@ -108,7 +108,10 @@ typedef struct {
     int32_t comp;           /* 0: FP32 blocks flushed to FP64; 1: blocked Kahan */
     int32_t sort_every;     /* steps between spatial re-sorts (<0: never) */
     int32_t cull;           /* 1: skip the LJ test for tile pairs beyond range */
-    int32_t reserved[3];
+    int32_t graph_steps;    /* > 0: replay steps from a captured HIP graph; a
+                               chunk is sort_every steps starting with the
+                               re-sort (graph_steps steps when sorting is off) */
+    int32_t reserved[2];
 } ld_tuning;
 
 /* ---------------------------------------------------------------------- */
@@ -211,12 +214,69 @@ ld_status ld_fractal(ld_ctx* ctx, double k_f, double d, double eps0, int32_t max
 ld_status ld_get_tuning(ld_ctx* ctx, ld_tuning* t);
 ld_status ld_set_tuning(ld_ctx* ctx, const ld_tuning* t);
 
+/* Search the pair kernel's launch shape (workgroup size 128/256/512 x j
+ * split 1..16) by timing launches on the current state with HIP events, keep
+ * the fastest, and return the resulting tuning in *out (may be NULL).
+ * compensation, culling, sorting and graph settings are kept.  cache_path
+ * (may be NULL) is a text file of "key block j_split ms" lines, keyed by GPU
+ * architecture, size bucket (quarter octaves of n), type count and mode; a
+ * hit is applied without timing unless force != 0.  Leaves positions and
+ * the step state unchanged.  Errors: LD_EINVAL, LD_EHIP. */
+ld_status ld_autotune(ld_ctx* ctx, const char* cache_path, int32_t force, ld_tuning* out);
+
 /* Time every pair-kernel launch with HIP events on the context's stream.
  * enable = 1 starts (and clears) the record, 0 stops it.  ld_kernel_time
  * waits for the stream and returns the number of timed launches and their
  * total duration in milliseconds. */
 ld_status ld_kernel_timing(ld_ctx* ctx, int32_t enable);
 ld_status ld_kernel_time(ld_ctx* ctx, int64_t* launches, double* total_ms);
+
+/* ---------------------------------------------------------------------- */
+/* Ensembles of independent droplets                                       */
+/* ---------------------------------------------------------------------- */
+
+typedef struct ld_ens ld_ens;
+
+/* Create n_drop >= 1 independent droplets that step together.  Droplet d
+ * owns particles [offsets[d], offsets[d+1]) (offsets: host int64
+ * [n_drop+1], offsets[0] = 0, at least 2 particles per droplet) of the
+ * concatenated arrays type [total] int32, charge [total] FP64 and pos
+ * [total*3] FP32 (host or device).  p, R and seeds are host arrays of
+ * n_drop entries: each droplet has its own parameters, radius schedule and
+ * noise seed.  Particle i of droplet d draws the noise it would draw alone,
+ * i.e. Philox counter (i - offsets[d], step, 0) with key seeds[d].  All
+ * droplets share the step counter and time.  Pair forces couple particles of
+ * the same droplet only.  Errors: LD_EINVAL, LD_ENOMEM, LD_EHIP. */
+ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, const int32_t* type,
+                      const double* charge, const float* pos, const ld_params* p,
+                      const ld_radius* R, const uint64_t* seeds, void* stream);
+void ld_ens_destroy(ld_ens* e);
+
+/* Launch shape of the persistent pair kernel (workgroups of 256 work-items;
+ * 0 keeps the current count), compensation mode (0 FP64 flush, 1 blocked
+ * Kahan), and the number of steps captured in one HIP graph (0: no graph).
+ * Captured steps replay with the dt they were captured with. */
+ld_status ld_ens_set_tuning(ld_ens* e, int32_t workgroups, int32_t comp, int32_t graph_steps);
+
+/* Advance all droplets n_steps >= 0 steps of size dt > 0 (asynchronous). */
+ld_status ld_ens_step(ld_ens* e, double dt, int64_t n_steps);
+
+/* Pair forces [total*3] FP64 of every particle at the current state. */
+ld_status ld_ens_forces(ld_ens* e, double* F_pair);
+
+/* Positions [total*3] FP32 hi and lo parts (either may be NULL). */
+ld_status ld_ens_get_positions(ld_ens* e, float* pos, float* pos_lo);
+
+/* Shared step counter and time. */
+ld_status ld_ens_get_state(ld_ens* e, int64_t* step, double* t);
+
+/* Wait; report a pending blow-up once (LD_ENONFINITE) and clear it. */
+ld_status ld_ens_sync(ld_ens* e);
+
+/* HIP-event timing of every persistent pair launch (see ld_kernel_timing);
+ * timing disables graph replay while it is on. */
+ld_status ld_ens_kernel_timing(ld_ens* e, int32_t enable);
+ld_status ld_ens_kernel_time(ld_ens* e, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

@@ -7,9 +7,10 @@
 #include <cstring>
 #include <new>
 
-#include "ld_internal.h"
+#include "ld_host.h"
 
-namespace {
+namespace ld {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -22,13 +23,6 @@ ld_status fail(ld_status s, const char* fmt, ...) {
     g_err = buf;
     return s;
 }
-
-#define HIP_TRY(expr)                                                                   \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(LD_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
-    } while (0)
 
 bool is_device_ptr(const void* p) {
     if (!p) return false;
@@ -53,19 +47,6 @@ hipError_t copy_out(void* dst, const void* src, size_t bytes, hipStream_t s) {
         dst, src, bytes, is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(s);
-}
-
-// Read a caller array of `count` elements into host memory.
-template <class T>
-ld_status read_host(std::vector<T>& v, const T* src, size_t count, hipStream_t s) {
-    v.resize(count);
-    if (is_device_ptr(src)) {
-        HIP_TRY(hipMemcpyAsync(v.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    } else {
-        std::memcpy(v.data(), src, count * sizeof(T));
-    }
-    return LD_OK;
 }
 
 ld_status check_params(const ld_params* p) {
@@ -117,9 +98,7 @@ ld_status check_radius(const ld_radius* R) {
     return LD_OK;
 }
 
-void build_tables(ld_ctx* c) {
-    const ld_params& p = c->p;
-    ld::PairTable& tb = c->tab;
+void make_tables(const ld_params& p, const ld_radius& R, PairTable& tb, ExtParams& P) {
     std::memset(&tb, 0, sizeof tb);
     tb.T = p.n_types;
     double rc2max = 0.0;
@@ -138,7 +117,6 @@ void build_tables(ld_ctx* c) {
         }
     tb.rc2max = (float)rc2max;
 
-    ld::ExtParams& P = c->ext;
     std::memset(&P, 0, sizeof P);
     P.n_types = p.n_types;
     P.rotation = p.rotation;
@@ -155,8 +133,17 @@ void build_tables(ld_ctx* c) {
         P.wall_offset[t] = p.wall_offset[t];
         P.half_sigma[t] = 0.5 * p.sigma[t];
     }
-    P.R = c->R;
+    P.R = R;
 }
+
+}  // namespace host
+}  // namespace ld
+
+namespace {
+
+using namespace ld::host;
+
+void build_tables(ld_ctx* c) { make_tables(c->p, c->R, c->tab, c->ext); }
 
 void default_tuning(ld_ctx* c) {
     ld_tuning& t = c->tune;
@@ -176,8 +163,18 @@ void default_tuning(ld_ctx* c) {
     t.cull = 1;
 }
 
+// A captured graph bakes in buffer pointers and parameter tables: drop it
+// whenever either changes.
+void invalidate_graph(ld_ctx* c) {
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+}
+
 ld_status ensure_split_capacity(ld_ctx* c, int split) {
     if (split <= c->j_split_cap) return LD_OK;
+    invalidate_graph(c);
     if (c->Fpart) (void)hipFree(c->Fpart);
     c->Fpart = nullptr;
     c->j_split_cap = 0;
@@ -196,7 +193,7 @@ hipEvent_t next_event(ld_ctx* c) {
     return c->ev_pool[c->ev_used++];
 }
 
-ld_status run_pair(ld_ctx* c, bool diag) {
+ld_status run_pair(ld_ctx* c, bool diag, hipStream_t s, bool timed) {
     ld::PairLaunch L{};
     L.pos = c->pos;
     L.typ = c->typ;
@@ -210,22 +207,89 @@ ld_status run_pair(ld_ctx* c, bool diag) {
     L.S = diag ? c->S_slot : nullptr;
     L.U = diag ? c->U_slot : nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    if (timed) {
         e0 = next_event(c);
         e1 = next_event(c);
         if (!e0 || !e1) return fail(LD_EHIP, "cannot create timing events");
-        HIP_TRY(hipEventRecord(e0, c->stream));
+        HIP_TRY(hipEventRecord(e0, s));
     }
-    HIP_TRY(ld::launch_pair(L, c->tab, c->stream));
-    if (c->timing) HIP_TRY(hipEventRecord(e1, c->stream));
+    HIP_TRY(ld::launch_pair(L, c->tab, s));
+    if (timed) HIP_TRY(hipEventRecord(e1, s));
     return LD_OK;
 }
 
-ld_status run_sort(ld_ctx* c) {
-    HIP_TRY(ld::launch_sort(c->pos, c->lo, c->typ, c->oid, (int)c->n, c->sb, c->stream));
-    HIP_TRY(ld::launch_boxes(c->pos, (int)c->n, c->box, c->stream));
+ld_status run_pair(ld_ctx* c, bool diag) { return run_pair(c, diag, c->stream, c->timing); }
+
+ld_status run_sort(ld_ctx* c, hipStream_t s) {
+    HIP_TRY(ld::launch_sort(c->pos, c->lo, c->typ, c->oid, (int)c->n, c->sb, s));
+    HIP_TRY(ld::launch_boxes(c->pos, (int)c->n, c->box, s));
     c->steps_since_sort = 0;
     return LD_OK;
+}
+
+ld_status run_sort(ld_ctx* c) { return run_sort(c, c->stream); }
+
+ld::StepLaunch step_launch(ld_ctx* c, double dt) {
+    ld::StepLaunch L{};
+    L.pos = c->pos;
+    L.lo = c->lo;
+    L.typ = c->typ;
+    L.oid = c->oid;
+    L.Fpart = c->Fpart;
+    L.j_split = c->tune.j_split;
+    L.n = (int)c->n;
+    L.dt = dt;
+    L.seed = c->seed;
+    L.st = c->st;
+    L.box = c->box;
+    return L;
+}
+
+// One step (re-sorting first when due) on stream s.
+ld_status enqueue_step(ld_ctx* c, double dt, hipStream_t s, bool timed) {
+    if (c->tune.sort_every > 0 && c->steps_since_sort >= c->tune.sort_every) {
+        ld_status st = run_sort(c, s);
+        if (st != LD_OK) return st;
+    }
+    ld_status st = run_pair(c, false, s, timed);
+    if (st != LD_OK) return st;
+    HIP_TRY(ld::launch_update(step_launch(c, dt), c->ext, s));
+    ++c->steps_since_sort;
+    return LD_OK;
+}
+
+// Capture `len` steps (a re-sort first when sorting is on) into a graph.
+ld_status capture_chunk(ld_ctx* c, double dt, int len) {
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const int64_t saved = c->steps_since_sort;
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    ld_status st = LD_OK;
+    if (c->tune.sort_every > 0) c->steps_since_sort = c->tune.sort_every;
+    for (int k = 0; k < len && st == LD_OK; ++k) st = enqueue_step(c, dt, c->cap_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t err = hipStreamEndCapture(c->cap_stream, &g);
+    c->steps_since_sort = saved;
+    if (st != LD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (err != hipSuccess) return fail(LD_EHIP, "stream capture: %s", hipGetErrorString(err));
+    err = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) return fail(LD_EHIP, "graph instantiate: %s", hipGetErrorString(err));
+    c->graph_dt = dt;
+    c->graph_len = len;
+    c->graph_key = c->tune;
+    return LD_OK;
+}
+
+bool same_tuning(const ld_tuning& a, const ld_tuning& b) {
+    return a.block == b.block && a.j_split == b.j_split && a.comp == b.comp &&
+           a.sort_every == b.sort_every && a.cull == b.cull && a.graph_steps == b.graph_steps;
 }
 
 ld_status wait_stream(ld_ctx* c) {
@@ -254,6 +318,8 @@ void free_all(ld_ctx* c) {
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
 }
 
 }  // namespace
@@ -410,27 +476,27 @@ ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
     if (!c) return fail(LD_EINVAL, "ctx is NULL");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LD_EINVAL, "dt=%g must be positive", dt);
     if (n_steps < 0) return fail(LD_EINVAL, "n_steps must be >= 0");
-    ld::StepLaunch L{};
-    L.pos = c->pos;
-    L.lo = c->lo;
-    L.typ = c->typ;
-    L.oid = c->oid;
-    L.Fpart = c->Fpart;
-    L.j_split = c->tune.j_split;
-    L.n = (int)c->n;
-    L.dt = dt;
-    L.seed = c->seed;
-    L.st = c->st;
-    L.box = c->box;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        if (c->tune.sort_every > 0 && c->steps_since_sort >= c->tune.sort_every) {
-            ld_status st = run_sort(c);
-            if (st != LD_OK) return st;
+    int64_t left = n_steps;
+    const bool use_graph = c->tune.graph_steps > 0 && !c->timing;
+    const int len = c->tune.sort_every > 0 ? c->tune.sort_every : c->tune.graph_steps;
+    while (left > 0) {
+        // A captured chunk starts with a re-sort when sorting is on, so it is
+        // used once the current sort interval is used up.
+        const bool at_chunk = c->tune.sort_every <= 0 || c->steps_since_sort >= c->tune.sort_every;
+        if (use_graph && at_chunk && left >= len) {
+            if (!c->graph || c->graph_dt != dt || c->graph_len != len ||
+                !same_tuning(c->graph_key, c->tune)) {
+                ld_status st = capture_chunk(c, dt, len);
+                if (st != LD_OK) return st;
+            }
+            HIP_TRY(hipGraphLaunch(c->graph, c->stream));
+            c->steps_since_sort = c->tune.sort_every > 0 ? len : 0;
+            left -= len;
+            continue;
         }
-        ld_status st = run_pair(c, false);
+        ld_status st = enqueue_step(c, dt, c->stream, c->timing);
         if (st != LD_OK) return st;
-        HIP_TRY(ld::launch_update(L, c->ext, c->stream));
-        ++c->steps_since_sort;
+        --left;
     }
     return LD_OK;
 }
@@ -526,6 +592,7 @@ ld_status ld_set_params(ld_ctx* c, const ld_params* p, const ld_radius* R) {
         c->p = *p;
     }
     if (R) c->R = *R;
+    invalidate_graph(c);
     build_tables(c);
     return LD_OK;
 }
@@ -684,10 +751,114 @@ ld_status ld_set_tuning(ld_ctx* c, const ld_tuning* t) {
     if (u.j_split < 1 || u.j_split > 64) return fail(LD_EINVAL, "j_split must be in [1, 64]");
     if (u.comp != 0 && u.comp != 1) return fail(LD_EINVAL, "comp must be 0 or 1");
     if (u.cull != 0 && u.cull != 1) return fail(LD_EINVAL, "cull must be 0 or 1");
+    if (u.graph_steps < 0 || u.graph_steps > 4096)
+        return fail(LD_EINVAL, "graph_steps must be in [0, 4096]");
+    if (u.sort_every > 4096) return fail(LD_EINVAL, "sort_every must be <= 4096");
     HIP_TRY(hipStreamSynchronize(c->stream));
     ld_status st = ensure_split_capacity(c, u.j_split);
     if (st != LD_OK) return st;
     c->tune = u;
+    invalidate_graph(c);
+    return LD_OK;
+}
+
+ld_status ld_autotune(ld_ctx* c, const char* cache_path, int32_t force, ld_tuning* out) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    // cache key: architecture, size bucket (quarter octaves), types, mode
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, c->device));
+    char arch[64];
+    std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    for (char* q = arch; *q; ++q)
+        if (*q == ':' || *q == ' ') *q = '_';
+    const int bucket = (int)std::floor(std::log2((double)c->n) * 4.0);
+    char key[160];
+    std::snprintf(key, sizeof key, "%s/nb%d/T%d/cull%d/comp%d", arch, bucket, c->p.n_types,
+                  c->tune.cull, c->tune.comp);
+    std::vector<std::string> lines;
+    if (cache_path && !force) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char k[160];
+            int b = 0, js = 0;
+            double ms = 0.0;
+            while (std::fscanf(f, "%159s %d %d %lf", k, &b, &js, &ms) == 4) {
+                if (std::strcmp(k, key) == 0) {
+                    std::fclose(f);
+                    ld_tuning u = c->tune;
+                    u.block = b;
+                    u.j_split = js;
+                    ld_status st = ld_set_tuning(c, &u);
+                    if (st != LD_OK) return st;
+                    if (out) *out = c->tune;
+                    return LD_OK;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    const ld_tuning saved = c->tune;
+    const bool saved_timing = c->timing;
+    c->timing = false;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int blocks[] = {128, 256, 512};
+    const int splits[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    int64_t cap = c->n / 1024;
+    if (cap < 1) cap = 1;
+    double best_ms = INFINITY;
+    ld_tuning best = saved;
+    ld_status st = LD_OK;
+    for (int b : blocks) {
+        for (int js : splits) {
+            if (js > cap || (c->n + b - 1) / b * (int64_t)js > 65535 * 8) continue;
+            if (ensure_split_capacity(c, js) != LD_OK) continue;
+            c->tune.block = b;
+            c->tune.j_split = js;
+            double ms_min = INFINITY;
+            for (int rep = 0; rep < 4 && st == LD_OK; ++rep) {
+                if (hipEventRecord(e0, c->stream) != hipSuccess) st = LD_EHIP;
+                if (st == LD_OK) st = run_pair(c, false, c->stream, false);
+                if (st == LD_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = LD_EHIP;
+                if (st == LD_OK && hipEventSynchronize(e1) != hipSuccess) st = LD_EHIP;
+                float ms = 0.f;
+                if (st == LD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = LD_EHIP;
+                if (rep > 0 && ms < ms_min) ms_min = ms;   // first launch is a warm-up
+            }
+            if (st != LD_OK) break;
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                best = c->tune;
+            }
+        }
+        if (st != LD_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = saved_timing;
+    if (st != LD_OK) {
+        c->tune = saved;
+        return fail(LD_EHIP, "autotune launch failed");
+    }
+    c->tune = best;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char buf[256];
+            while (std::fgets(buf, sizeof buf, f)) {
+                if (std::strncmp(buf, key, std::strlen(key)) != 0 || buf[std::strlen(key)] != ' ')
+                    lines.emplace_back(buf);
+            }
+            std::fclose(f);
+        }
+        if (FILE* f = std::fopen(cache_path, "w")) {
+            for (const std::string& l : lines) std::fputs(l.c_str(), f);
+            std::fprintf(f, "%s %d %d %.6f\n", key, best.block, best.j_split, best_ms);
+            std::fclose(f);
+        }
+    }
+    if (out) *out = c->tune;
     return LD_OK;
 }
 

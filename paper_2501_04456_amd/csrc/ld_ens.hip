@@ -1,0 +1,517 @@
+// Ensembles of independent droplets in one persistent launch.
+//
+// Every droplet d owns a contiguous slot range [off[d], off[d+1]) with its own
+// parameters, radius schedule and noise seed.  The pair sum is split into
+// work items (droplet, 64-particle i tile); an item costs 64 x N_d pairs.
+// Items are ordered longest first and pulled from one atomic counter by
+// resident wavefronts, so a few large droplets cannot leave the chip idle at
+// the end of the step.  Each wavefront stages j tiles of its item's droplet
+// in its own LDS slice.  The update runs over all slots of all droplets in
+// one launch.  A droplet's noise is keyed by its seed and the particle's
+// index inside the droplet, so each droplet follows exactly the stream it
+// would follow alone.
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "ld_host.h"
+#include "ld_pair_core.h"
+#include "ld_update_core.h"
+
+using namespace ld;
+using namespace ld::host;
+
+namespace {
+
+constexpr int kWaves = 4;                 // wavefronts per workgroup
+constexpr int kEnsBlock = kWaves * kGroup;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void k_ens_reset(unsigned* counter) { *counter = 0u; }
+
+template <int COMP>
+__global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
+    const float4* __restrict__ pos, const int* __restrict__ typ, const int* __restrict__ off,
+    const int2* __restrict__ items, int W, unsigned* counter, const PairTable* __restrict__ tabs,
+    double* __restrict__ F, int total) {
+    __shared__ float4 sp[kWaves][kGroup];
+    __shared__ int stp[kWaves][kGroup];
+    __shared__ float ttab[kWaves][4 * kMaxTypes * kMaxTypes];
+    const int w = threadIdx.x / kGroup;
+    const int lane = threadIdx.x % kGroup;
+    for (;;) {
+        unsigned item = 0u;
+        if (lane == 0) item = atomicAdd(counter, 1u);
+        item = (unsigned)__shfl((int)item, 0);
+        if (item >= (unsigned)W) break;
+        const int2 it = items[item];
+        const int d = it.x;
+        const int o = off[d];
+        const int nd = off[d + 1] - o;
+        const PairTable* tb = tabs + d;
+        wave_sync();
+        ttab[w][lane] = tb->sig2[lane];
+        ttab[w][kMaxTypes * kMaxTypes + lane] = tb->rc2[lane];
+        ttab[w][2 * kMaxTypes * kMaxTypes + lane] = tb->e24[lane];
+        ttab[w][3 * kMaxTypes * kMaxTypes + lane] = tb->e4[lane];
+        const int T = tb->T;
+        const float rc2max = tb->rc2max;
+        const int i = it.y + lane;
+        const bool live = i < nd;
+        const float4 pi = live ? pos[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const int ti = live ? typ[o + i] : 0;
+        pair::Acc a;
+        for (int jt = 0; jt < nd; jt += kGroup) {
+            wave_sync();
+            const int j = jt + lane;
+            if (j < nd) {
+                sp[w][lane] = pos[o + j];
+                stp[w][lane] = typ[o + j];
+            } else {
+                sp[w][lane] = make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+                stp[w][lane] = 0;
+            }
+            wave_sync();
+            pair::group_near<COMP, false>(sp[w], stp[w], ttab[w], T, rc2max, jt, i, ti, pi, a);
+        }
+        if constexpr (COMP == 1) {
+            a.Fx = (double)a.sx - (double)a.cx;
+            a.Fy = (double)a.sy - (double)a.cy;
+            a.Fz = (double)a.sz - (double)a.cz;
+        }
+        if (live) {
+            const double qi = (double)pi.w;
+            const size_t s = (size_t)(o + i);
+            F[s] = -qi * a.Fx - a.Lx;
+            F[(size_t)total + s] = -qi * a.Fy - a.Ly;
+            F[2 * (size_t)total + s] = -qi * a.Fz - a.Lz;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ens_update(float4* pos, float4* lo,
+                                                    const int* __restrict__ typ,
+                                                    const int* __restrict__ did,
+                                                    const int* __restrict__ lid,
+                                                    const double* __restrict__ F, int total,
+                                                    const ExtParams* __restrict__ ext,
+                                                    const unsigned long long* __restrict__ seeds,
+                                                    double dt, DevState* st) {
+    const long long step = st->step;
+    const double tn = st->t + dt;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s < total) {
+        const int d = did[s];
+        const ExtParams& P = ext[d];
+        const double R = radius_at(P.R, tn);
+        float4 h = pos[s], l = lo[s];
+        const double Fs[3] = {F[s], F[(size_t)total + s], F[2 * (size_t)total + s]};
+        if (!upd::advance(h, l, Fs, typ[s], R, dt, P, (uint32_t)lid[s],
+                          (unsigned long long)step, seeds[d]))
+            atomicMin(&st->bad_step, (unsigned long long)step);
+        pos[s] = h;
+        lo[s] = l;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(&st->done, 1u);
+        if (prev == gridDim.x - 1) {
+            st->step = step + 1;
+            st->t = tn;
+            st->done = 0u;
+            __threadfence();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ens_gather(const float4* __restrict__ pos,
+                                                    const float4* __restrict__ lo, int total,
+                                                    float* hi_out, float* lo_out) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= total) return;
+    const float4 h = pos[s], l = lo[s];
+    hi_out[3 * (size_t)s] = h.x;
+    hi_out[3 * (size_t)s + 1] = h.y;
+    hi_out[3 * (size_t)s + 2] = h.z;
+    lo_out[3 * (size_t)s] = l.x;
+    lo_out[3 * (size_t)s + 1] = l.y;
+    lo_out[3 * (size_t)s + 2] = l.z;
+}
+
+__global__ __launch_bounds__(256) void k_ens_forces_aos(const double* __restrict__ F, int total,
+                                                        double* out) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= total) return;
+    out[3 * (size_t)s] = F[s];
+    out[3 * (size_t)s + 1] = F[(size_t)total + s];
+    out[3 * (size_t)s + 2] = F[2 * (size_t)total + s];
+}
+
+}  // namespace
+
+struct ld_ens {
+    int n_drop = 0;
+    int total = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::vector<int> off_h;
+    float4* pos = nullptr;
+    float4* lo = nullptr;
+    int* typ = nullptr;
+    int* did = nullptr;
+    int* lid = nullptr;
+    int* off = nullptr;
+    int2* items = nullptr;
+    int W = 0;
+    unsigned* counter = nullptr;
+    PairTable* tabs = nullptr;
+    ExtParams* ext = nullptr;
+    unsigned long long* seeds = nullptr;
+    double* F = nullptr;
+    double* work = nullptr;              // [3 * total] output staging
+    DevState* st = nullptr;
+    int workgroups = 0;
+    int comp = 0;
+    int graph_steps = 0;
+    hipGraphExec_t graph = nullptr;
+    double graph_dt = 0.0;
+    int graph_len = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+};
+
+namespace {
+
+void ens_free(ld_ens* e) {
+    void* bufs[] = {e->pos, e->lo,  e->typ,   e->did, e->lid, e->off, e->items,
+                    e->counter, e->tabs, e->ext, e->seeds, e->F, e->work, e->st};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (e->graph) (void)hipGraphExecDestroy(e->graph);
+    if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
+    for (hipEvent_t v : e->ev) (void)hipEventDestroy(v);
+}
+
+ld_status enqueue_pair(ld_ens* e, hipStream_t s) {
+    hipLaunchKernelGGL(k_ens_reset, dim3(1), dim3(1), 0, s, e->counter);
+    if (e->comp == 0)
+        hipLaunchKernelGGL(k_ens_pair<0>, dim3(e->workgroups), dim3(kEnsBlock), 0, s, e->pos,
+                           e->typ, e->off, e->items, e->W, e->counter, e->tabs, e->F, e->total);
+    else
+        hipLaunchKernelGGL(k_ens_pair<1>, dim3(e->workgroups), dim3(kEnsBlock), 0, s, e->pos,
+                           e->typ, e->off, e->items, e->W, e->counter, e->tabs, e->F, e->total);
+    HIP_TRY(hipGetLastError());
+    return LD_OK;
+}
+
+ld_status enqueue_step(ld_ens* e, double dt, hipStream_t s, bool timed) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timed) {
+        while (e->ev.size() < e->ev_used + 2) {
+            hipEvent_t v;
+            HIP_TRY(hipEventCreate(&v));
+            e->ev.push_back(v);
+        }
+        a = e->ev[e->ev_used++];
+        b = e->ev[e->ev_used++];
+        HIP_TRY(hipEventRecord(a, s));
+    }
+    ld_status st = enqueue_pair(e, s);
+    if (st != LD_OK) return st;
+    if (timed) HIP_TRY(hipEventRecord(b, s));
+    hipLaunchKernelGGL(k_ens_update, dim3((e->total + 255) / 256), dim3(256), 0, s, e->pos,
+                       e->lo, e->typ, e->did, e->lid, e->F, e->total, e->ext, e->seeds, dt,
+                       e->st);
+    HIP_TRY(hipGetLastError());
+    return LD_OK;
+}
+
+ld_status capture(ld_ens* e, double dt, int steps) {
+    if (e->graph) {
+        (void)hipGraphExecDestroy(e->graph);
+        e->graph = nullptr;
+    }
+    if (!e->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
+    ld_status st = LD_OK;
+    for (int k = 0; k < steps && st == LD_OK; ++k) st = enqueue_step(e, dt, e->cap_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t err = hipStreamEndCapture(e->cap_stream, &g);
+    if (st != LD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (err != hipSuccess) return fail(LD_EHIP, "stream capture: %s", hipGetErrorString(err));
+    err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) return fail(LD_EHIP, "graph instantiate: %s", hipGetErrorString(err));
+    e->graph_dt = dt;
+    e->graph_len = steps;
+    return LD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, const int32_t* type,
+                      const double* charge, const float* pos, const ld_params* p,
+                      const ld_radius* R, const uint64_t* seeds, void* stream) {
+    g_err.clear();
+    if (!out) return fail(LD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_drop < 1) return fail(LD_EINVAL, "n_drop must be >= 1");
+    if (!offsets || !type || !charge || !pos || !p || !R || !seeds)
+        return fail(LD_EINVAL, "offsets, type, charge, pos, p, R and seeds are required");
+    std::vector<int64_t> offs((size_t)n_drop + 1);
+    std::memcpy(offs.data(), offsets, sizeof(int64_t) * offs.size());
+    if (offs[0] != 0) return fail(LD_EINVAL, "offsets[0] must be 0");
+    for (int d = 0; d < n_drop; ++d) {
+        if (offs[d + 1] - offs[d] < 2)
+            return fail(LD_EINVAL, "droplet %d has fewer than 2 particles", d);
+        ld_status st = check_params(&p[d]);
+        if (st != LD_OK) return st;
+        st = check_radius(&R[d]);
+        if (st != LD_OK) return st;
+    }
+    const int64_t total = offs[n_drop];
+    if (total > (1 << 27)) return fail(LD_EINVAL, "total particles %lld > 2^27", (long long)total);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> ty;
+    std::vector<double> q;
+    std::vector<float> x;
+    ld_status st;
+    if ((st = read_host(ty, type, (size_t)total, s)) != LD_OK) return st;
+    if ((st = read_host(q, charge, (size_t)total, s)) != LD_OK) return st;
+    if ((st = read_host(x, pos, (size_t)total * 3, s)) != LD_OK) return st;
+
+    ld_ens* e = new (std::nothrow) ld_ens();
+    if (!e) return fail(LD_ENOMEM, "host allocation failed");
+    e->n_drop = n_drop;
+    e->total = (int)total;
+    e->stream = s;
+    e->off_h.assign(offs.begin(), offs.end());
+    std::vector<float4> h4(total), l4(total);
+    std::vector<int> dids(total), lids(total);
+    std::vector<PairTable> tabs(n_drop);
+    std::vector<ExtParams> exts(n_drop);
+    std::vector<unsigned long long> sd(n_drop);
+    std::vector<int2> items;
+    for (int d = 0; d < n_drop; ++d) {
+        make_tables(p[d], R[d], tabs[d], exts[d]);
+        sd[d] = seeds[d];
+        const double qs = std::sqrt(p[d].kT * p[d].bjerrum);
+        for (int64_t i = offs[d]; i < offs[d + 1]; ++i) {
+            if (ty[i] < 0 || ty[i] >= p[d].n_types) {
+                ens_free(e);
+                delete e;
+                return fail(LD_EINVAL, "type[%lld] outside droplet %d's types", (long long)i, d);
+            }
+            for (int k = 0; k < 3; ++k)
+                if (!std::isfinite(x[3 * i + k]) || !std::isfinite(q[i])) {
+                    ens_free(e);
+                    delete e;
+                    return fail(LD_EINVAL, "particle %lld not finite", (long long)i);
+                }
+            h4[i] = make_float4(x[3 * i], x[3 * i + 1], x[3 * i + 2], (float)(q[i] * qs));
+            l4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            dids[i] = d;
+            lids[i] = (int)(i - offs[d]);
+        }
+        for (int64_t i0 = 0; i0 < offs[d + 1] - offs[d]; i0 += kGroup)
+            items.push_back(make_int2(d, (int)i0));
+    }
+    // longest item first: an item costs N_d pairs per lane
+    std::stable_sort(items.begin(), items.end(), [&](const int2& a, const int2& b) {
+        return (offs[a.x + 1] - offs[a.x]) > (offs[b.x + 1] - offs[b.x]);
+    });
+    e->W = (int)items.size();
+    std::vector<int> off32(offs.begin(), offs.end());
+    const size_t N = (size_t)total;
+    bool ok = hipMalloc(&e->pos, sizeof(float4) * N) == hipSuccess &&
+              hipMalloc(&e->lo, sizeof(float4) * N) == hipSuccess &&
+              hipMalloc(&e->typ, sizeof(int) * N) == hipSuccess &&
+              hipMalloc(&e->did, sizeof(int) * N) == hipSuccess &&
+              hipMalloc(&e->lid, sizeof(int) * N) == hipSuccess &&
+              hipMalloc(&e->off, sizeof(int) * (n_drop + 1)) == hipSuccess &&
+              hipMalloc(&e->items, sizeof(int2) * items.size()) == hipSuccess &&
+              hipMalloc(&e->counter, sizeof(unsigned)) == hipSuccess &&
+              hipMalloc(&e->tabs, sizeof(PairTable) * n_drop) == hipSuccess &&
+              hipMalloc(&e->ext, sizeof(ExtParams) * n_drop) == hipSuccess &&
+              hipMalloc(&e->seeds, sizeof(unsigned long long) * n_drop) == hipSuccess &&
+              hipMalloc(&e->F, sizeof(double) * 3 * N) == hipSuccess &&
+              hipMalloc(&e->work, sizeof(double) * 3 * N) == hipSuccess &&
+              hipMalloc(&e->st, sizeof(DevState)) == hipSuccess;
+    if (!ok) {
+        ens_free(e);
+        delete e;
+        return fail(LD_ENOMEM, "device allocation failed for %lld particles", (long long)total);
+    }
+    DevState ds{};
+    ds.bad_step = ~0ull;
+    const unsigned zero = 0u;
+    hipError_t err = hipSuccess;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (err == hipSuccess) err = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    up(e->pos, h4.data(), sizeof(float4) * N);
+    up(e->lo, l4.data(), sizeof(float4) * N);
+    up(e->typ, ty.data(), sizeof(int) * N);
+    up(e->did, dids.data(), sizeof(int) * N);
+    up(e->lid, lids.data(), sizeof(int) * N);
+    up(e->off, off32.data(), sizeof(int) * (n_drop + 1));
+    up(e->items, items.data(), sizeof(int2) * items.size());
+    up(e->counter, &zero, sizeof zero);
+    up(e->tabs, tabs.data(), sizeof(PairTable) * n_drop);
+    up(e->ext, exts.data(), sizeof(ExtParams) * n_drop);
+    up(e->seeds, sd.data(), sizeof(unsigned long long) * n_drop);
+    up(e->st, &ds, sizeof ds);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) {
+        ens_free(e);
+        delete e;
+        return fail(LD_EHIP, "upload failed: %s", hipGetErrorString(err));
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    e->workgroups = std::max(1, std::min(cus * 8, (e->W + kWaves - 1) / kWaves));
+    *out = e;
+    return LD_OK;
+}
+
+void ld_ens_destroy(ld_ens* e) {
+    if (!e) return;
+    (void)hipStreamSynchronize(e->stream);
+    ens_free(e);
+    delete e;
+}
+
+ld_status ld_ens_set_tuning(ld_ens* e, int32_t workgroups, int32_t comp, int32_t graph_steps) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    if (workgroups < 0 || workgroups > 65536) return fail(LD_EINVAL, "workgroups in [0, 65536]");
+    if (comp != 0 && comp != 1) return fail(LD_EINVAL, "comp must be 0 or 1");
+    if (graph_steps < 0 || graph_steps > 4096) return fail(LD_EINVAL, "graph_steps in [0, 4096]");
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    if (workgroups > 0) e->workgroups = workgroups;
+    e->comp = comp;
+    e->graph_steps = graph_steps;
+    if (e->graph) {
+        (void)hipGraphExecDestroy(e->graph);
+        e->graph = nullptr;
+    }
+    return LD_OK;
+}
+
+ld_status ld_ens_step(ld_ens* e, double dt, int64_t n_steps) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LD_EINVAL, "dt=%g must be positive", dt);
+    if (n_steps < 0) return fail(LD_EINVAL, "n_steps must be >= 0");
+    int64_t left = n_steps;
+    if (e->graph_steps > 0 && !e->timing) {
+        const int len = e->graph_steps;
+        if (left >= len) {
+            if (!e->graph || e->graph_dt != dt || e->graph_len != len) {
+                ld_status st = capture(e, dt, len);
+                if (st != LD_OK) return st;
+            }
+            while (left >= len) {
+                HIP_TRY(hipGraphLaunch(e->graph, e->stream));
+                left -= len;
+            }
+        }
+    }
+    for (int64_t k = 0; k < left; ++k) {
+        ld_status st = enqueue_step(e, dt, e->stream, e->timing);
+        if (st != LD_OK) return st;
+    }
+    return LD_OK;
+}
+
+ld_status ld_ens_forces(ld_ens* e, double* F_pair) {
+    g_err.clear();
+    if (!e || !F_pair) return fail(LD_EINVAL, "ensemble and F_pair are required");
+    ld_status st = enqueue_pair(e, e->stream);
+    if (st != LD_OK) return st;
+    hipLaunchKernelGGL(k_ens_forces_aos, dim3((e->total + 255) / 256), dim3(256), 0, e->stream,
+                       e->F, e->total, e->work);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(copy_out(F_pair, e->work, sizeof(double) * 3 * (size_t)e->total, e->stream));
+    return LD_OK;
+}
+
+ld_status ld_ens_get_positions(ld_ens* e, float* pos, float* pos_lo) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    const size_t N = (size_t)e->total;
+    float* hi = reinterpret_cast<float*>(e->work);
+    float* lo = hi + 3 * N;
+    hipLaunchKernelGGL(k_ens_gather, dim3((e->total + 255) / 256), dim3(256), 0, e->stream,
+                       e->pos, e->lo, e->total, hi, lo);
+    HIP_TRY(hipGetLastError());
+    if (pos) HIP_TRY(copy_out(pos, hi, sizeof(float) * 3 * N, e->stream));
+    if (pos_lo) HIP_TRY(copy_out(pos_lo, lo, sizeof(float) * 3 * N, e->stream));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    return LD_OK;
+}
+
+ld_status ld_ens_get_state(ld_ens* e, int64_t* step, double* t) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    DevState ds;
+    HIP_TRY(hipMemcpyAsync(&ds, e->st, sizeof ds, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    if (step) *step = ds.step;
+    if (t) *t = ds.t;
+    return LD_OK;
+}
+
+ld_status ld_ens_sync(ld_ens* e) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    DevState ds;
+    HIP_TRY(hipMemcpyAsync(&ds, e->st, sizeof ds, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    if (ds.bad_step != ~0ull) {
+        const unsigned long long none = ~0ull;
+        HIP_TRY(hipMemcpy(&e->st->bad_step, &none, sizeof none, hipMemcpyHostToDevice));
+        return fail(LD_ENONFINITE, "step %llu produced a non-finite or too large move",
+                    (unsigned long long)ds.bad_step);
+    }
+    return LD_OK;
+}
+
+ld_status ld_ens_kernel_timing(ld_ens* e, int32_t enable) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    e->timing = enable != 0;
+    if (enable) e->ev_used = 0;
+    return LD_OK;
+}
+
+ld_status ld_ens_kernel_time(ld_ens* e, int64_t* launches, double* total_ms) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < e->ev_used; k += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e->ev[k], e->ev[k + 1]));
+        tot += ms;
+    }
+    if (launches) *launches = (int64_t)(e->ev_used / 2);
+    if (total_ms) *total_ms = tot;
+    return LD_OK;
+}
+
+}  // extern "C"

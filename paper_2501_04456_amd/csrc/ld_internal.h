@@ -195,4 +195,11 @@ struct ld_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
+
+    // captured step chunk (HIP graph)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    double graph_dt = 0.0;
+    int graph_len = 0;
+    ld_tuning graph_key{};
 };

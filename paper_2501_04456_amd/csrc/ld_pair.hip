@@ -21,123 +21,12 @@
 // or into a blocked Kahan pair (COMP=1, flushed to FP64 at the end).  The
 // worst-case rounding of a 32-term FP32 block is 31 u sum|f| ~ 1.8e-6 of the
 // conditioning scale S_i = sum_j |f_ij|.
-#include "ld_internal.h"
+#include "ld_pair_core.h"
 
 namespace ld {
 namespace {
 
-constexpr int KB = 32;
-
-struct Acc {
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0;   // sum_j q_j r^-3 (x_j - x_i), FP64
-    float sx = 0.f, sy = 0.f, sz = 0.f;    // Kahan sums (COMP == 1)
-    float cx = 0.f, cy = 0.f, cz = 0.f;    // Kahan compensations
-    double Lx = 0.0, Ly = 0.0, Lz = 0.0;   // sum_j g_ij (x_j - x_i), LJ
-    double S = 0.0, Uc = 0.0, Ul = 0.0;    // diagnostic mode only
-};
-
-template <int COMP>
-__device__ __forceinline__ void flush(Acc& a, float bx, float by, float bz) {
-    if constexpr (COMP == 0) {
-        a.Fx += (double)bx;
-        a.Fy += (double)by;
-        a.Fz += (double)bz;
-    } else {
-        float y, t;
-        y = bx - a.cx; t = a.sx + y; a.cx = (t - a.sx) - y; a.sx = t;
-        y = by - a.cy; t = a.sy + y; a.cy = (t - a.sy) - y; a.sy = t;
-        y = bz - a.cz; t = a.sz + y; a.cz = (t - a.sz) - y; a.sz = t;
-    }
-}
-
-// 64 j particles with no LJ partner in range and no self pair: Coulomb only.
-template <int COMP>
-__device__ __forceinline__ void group_far(const float4* __restrict__ sp, const float4 pi,
-                                          Acc& a) {
-#pragma unroll
-    for (int kb = 0; kb < kGroup; kb += KB) {
-        float bx = 0.f, by = 0.f, bz = 0.f;
-#pragma unroll 16
-        for (int k = 0; k < KB; ++k) {
-            const float4 pj = sp[kb + k];
-            const float dx = pj.x - pi.x;
-            const float dy = pj.y - pi.y;
-            const float dz = pj.z - pi.z;
-            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float ri = __builtin_amdgcn_rsqf(r2);
-            const float w = (pj.w * ri) * (ri * ri);
-            bx = fmaf(w, dx, bx);
-            by = fmaf(w, dy, by);
-            bz = fmaf(w, dz, bz);
-        }
-        flush<COMP>(a, bx, by, bz);
-    }
-}
-
-// 64 j particles that may hold LJ partners or i itself.
-template <int COMP, bool DIAG>
-__device__ __forceinline__ void group_near(const float4* __restrict__ sp,
-                                           const int* __restrict__ stp,
-                                           const float* __restrict__ ttab, int T, float rc2max,
-                                           int jbase, int i, int ti, const float4 pi, Acc& a) {
-    const float* sig2 = ttab;
-    const float* rc2 = ttab + kMaxTypes * kMaxTypes;
-    const float* e24 = ttab + 2 * kMaxTypes * kMaxTypes;
-    const float* e4 = ttab + 3 * kMaxTypes * kMaxTypes;
-#pragma unroll
-    for (int kb = 0; kb < kGroup; kb += KB) {
-        float bx = 0.f, by = 0.f, bz = 0.f;
-#pragma unroll 4
-        for (int k = 0; k < KB; ++k) {
-            const float4 pj = sp[kb + k];
-            const float dx = pj.x - pi.x;
-            const float dy = pj.y - pi.y;
-            const float dz = pj.z - pi.z;
-            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float ri = __builtin_amdgcn_rsqf(r2);
-            float w = (pj.w * ri) * (ri * ri);
-            const int j = jbase + kb + k;
-            if (r2 < rc2max) {
-                if (j == i) {
-                    w = 0.f;
-                } else {
-                    const int pidx = ti * T + stp[kb + k];
-                    if (r2 < rc2[pidx]) {
-                        const float ir2 = 1.0f / r2;
-                        const float s2 = sig2[pidx] * ir2;
-                        const float s6 = s2 * s2 * s2;
-                        const float g = e24[pidx] * s6 * (2.0f * s6 - 1.0f) * ir2;
-                        a.Lx += (double)(g * dx);
-                        a.Ly += (double)(g * dy);
-                        a.Lz += (double)(g * dz);
-                        if constexpr (DIAG) {
-                            a.S += (double)fabsf(g) * (double)(r2 * ri);
-                            a.Ul += 0.5 * (double)(e4[pidx] * s6 * (s6 - 1.0f));
-                        }
-                    }
-                }
-            }
-            if constexpr (DIAG) {
-                if (j != i) {
-                    const float qq = pi.w * pj.w;
-                    a.S += (double)(fabsf(qq) * ri * ri);
-                    a.Uc += 0.5 * (double)(qq * ri);
-                }
-            }
-            bx = fmaf(w, dx, bx);
-            by = fmaf(w, dy, by);
-            bz = fmaf(w, dz, bz);
-        }
-        flush<COMP>(a, bx, by, bz);
-    }
-}
-
-__device__ __forceinline__ float box_dist2(const Box& a, const Box& b) {
-    const float gx = fmaxf(0.f, fmaxf(b.lo.x - a.hi.x, a.lo.x - b.hi.x));
-    const float gy = fmaxf(0.f, fmaxf(b.lo.y - a.hi.y, a.lo.y - b.hi.y));
-    const float gz = fmaxf(0.f, fmaxf(b.lo.z - a.hi.z, a.lo.z - b.hi.z));
-    return gx * gx + gy * gy + gz * gz;
-}
+using namespace pair;
 
 template <int BLOCK, int COMP, bool DIAG, bool CULL>
 __global__ __launch_bounds__(BLOCK) void k_pair(const float4* __restrict__ pos,

@@ -55,13 +55,21 @@ class ld_radius(C.Structure):
 
 class ld_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("j_split", C.c_int32), ("comp", C.c_int32),
-                ("sort_every", C.c_int32), ("cull", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("sort_every", C.c_int32), ("cull", C.c_int32), ("graph_steps", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+
+
+TUNING_FIELDS = ("block", "j_split", "comp", "sort_every", "cull", "graph_steps")
 
 
 SYMBOLS = [
     "ld_init", "ld_destroy", "ld_last_error", "ld_forces", "ld_step", "ld_sync",
     "ld_get_positions", "ld_get_state", "ld_set_params", "ld_diagnostics", "ld_rdf",
     "ld_fractal", "ld_get_tuning", "ld_set_tuning", "ld_kernel_timing", "ld_kernel_time",
+    "ld_autotune",
+    "ld_ens_init", "ld_ens_destroy", "ld_ens_set_tuning", "ld_ens_step", "ld_ens_forces",
+    "ld_ens_get_positions", "ld_ens_get_state", "ld_ens_sync", "ld_ens_kernel_timing",
+    "ld_ens_kernel_time",
 ]
 
 _lib = None
@@ -94,8 +102,21 @@ def lib():
         L.ld_set_tuning.argtypes = [vp, C.POINTER(ld_tuning)]
         L.ld_kernel_timing.argtypes = [vp, C.c_int32]
         L.ld_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.ld_autotune.argtypes = [vp, C.c_char_p, C.c_int32, C.POINTER(ld_tuning)]
+        L.ld_ens_init.argtypes = [C.POINTER(C.c_void_p), C.c_int32, vp, vp, vp, vp, vp, vp, vp,
+                                  vp]
+        L.ld_ens_destroy.argtypes = [vp]
+        L.ld_ens_destroy.restype = None
+        L.ld_ens_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.ld_ens_step.argtypes = [vp, C.c_double, C.c_int64]
+        L.ld_ens_forces.argtypes = [vp, vp]
+        L.ld_ens_get_positions.argtypes = [vp, vp, vp]
+        L.ld_ens_get_state.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.ld_ens_sync.argtypes = [vp]
+        L.ld_ens_kernel_timing.argtypes = [vp, C.c_int32]
+        L.ld_ens_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         for name in SYMBOLS:
-            if name not in ("ld_destroy", "ld_last_error"):
+            if name not in ("ld_destroy", "ld_last_error", "ld_ens_destroy"):
                 getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -270,7 +291,13 @@ class System:
     def tuning(self) -> dict:
         t = ld_tuning()
         _check(lib().ld_get_tuning(self.h, C.byref(t)))
-        return {k: getattr(t, k) for k in ("block", "j_split", "comp", "sort_every", "cull")}
+        return {k: getattr(t, k) for k in TUNING_FIELDS}
+
+    def autotune(self, cache_path: str = None, force: bool = False) -> dict:
+        t = ld_tuning()
+        _check(lib().ld_autotune(self.h, cache_path.encode() if cache_path else None,
+                                 1 if force else 0, C.byref(t)))
+        return {k: getattr(t, k) for k in TUNING_FIELDS}
 
     def set_tuning(self, **kw):
         t = ld_tuning()
@@ -288,3 +315,78 @@ class System:
         return n.value, ms.value
 
     dt = 1e-3
+
+
+class Ensemble:
+    """Independent droplets stepped together (an ld_ens)."""
+
+    def __init__(self, droplets, stream=None):
+        torch = _torch()
+        self._torch = torch
+        dev = torch.device("cuda")
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        self.droplets = list(droplets)
+        nd = len(self.droplets)
+        off = np.zeros(nd + 1, dtype=np.int64)
+        off[1:] = np.cumsum([d.n for d in self.droplets])
+        self.offsets = off
+        self.total = int(off[-1])
+        t = torch.as_tensor(np.concatenate([d.type for d in self.droplets]).astype(np.int32),
+                            device=dev)
+        q = torch.as_tensor(np.concatenate([d.charge for d in self.droplets]).astype(np.float64),
+                            device=dev)
+        x = torch.as_tensor(np.concatenate([np.asarray(d.pos, np.float32).reshape(-1, 3)
+                                            for d in self.droplets]), device=dev)
+        P = (ld_params * nd)(*[make_params(d.params) for d in self.droplets])
+        R = (ld_radius * nd)(*[make_radius(d.radius) for d in self.droplets])
+        S = (C.c_uint64 * nd)(*[int(d.seed) & 0xFFFFFFFFFFFFFFFF for d in self.droplets])
+        h = C.c_void_p()
+        _check(lib().ld_ens_init(C.byref(h), nd, off.ctypes.data_as(C.c_void_p), _ptr(t), _ptr(q),
+                                 _ptr(x), C.cast(P, C.c_void_p), C.cast(R, C.c_void_p),
+                                 C.cast(S, C.c_void_p), C.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().ld_ens_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, workgroups: int = 0, comp: int = 0, graph_steps: int = 0):
+        _check(lib().ld_ens_set_tuning(self.h, workgroups, comp, graph_steps))
+
+    def step(self, n_steps: int, dt: float):
+        _check(lib().ld_ens_step(self.h, float(dt), int(n_steps)))
+
+    def sync(self):
+        _check(lib().ld_ens_sync(self.h))
+
+    def forces(self):
+        F = self._torch.empty((self.total, 3), dtype=self._torch.float64, device="cuda")
+        _check(lib().ld_ens_forces(self.h, _ptr(F)))
+        return F
+
+    def positions64(self):
+        hi = np.zeros((self.total, 3), np.float32)
+        lo = np.zeros((self.total, 3), np.float32)
+        _check(lib().ld_ens_get_positions(self.h, hi.ctypes.data_as(C.c_void_p),
+                                          lo.ctypes.data_as(C.c_void_p)))
+        return hi.astype(np.float64) + lo.astype(np.float64)
+
+    def state(self):
+        s, t = C.c_int64(), C.c_double()
+        _check(lib().ld_ens_get_state(self.h, C.byref(s), C.byref(t)))
+        return s.value, t.value
+
+    def kernel_timing(self, enable: bool):
+        _check(lib().ld_ens_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self):
+        n, ms = C.c_int64(), C.c_double()
+        _check(lib().ld_ens_kernel_time(self.h, C.byref(n), C.byref(ms)))
+        return n.value, ms.value

@@ -1,0 +1,142 @@
+"""GPU tests of the ensemble path (independent droplets in one persistent
+launch), captured step graphs, and the launch-shape autotuner.
+
+Each ensemble droplet is compared with the FP64 oracle run of that droplet
+alone (its own seed; noise keyed by the index inside the droplet)."""
+import numpy as np
+import pytest
+
+from paper_2501_04456_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ld():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_04456_amd import ldrop
+    ldrop.lib()
+    return ldrop
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def small_ensemble():
+    return W.config_ensemble(n_drop=7, n_min=70, n_max=1500, seed=11)
+
+
+def test_ensemble_forces_per_droplet(ld, orc, small_ensemble):
+    ens = ld.Ensemble(small_ensemble.droplets)
+    F = ens.forces().cpu().numpy()
+    off = ens.offsets
+    for d, w in enumerate(small_ensemble.droplets):
+        Fo, So, _ = orc.pair_forces(w.pos, w.type, w.charge, w.params)
+        Fg = F[off[d]:off[d + 1]]
+        err = (np.linalg.norm(Fg - Fo, axis=1) / So).max()
+        assert err <= 1e-5, (d, err)
+
+
+@pytest.mark.parametrize("comp", [0, 1])
+def test_ensemble_trajectories(ld, orc, small_ensemble, comp):
+    ens = ld.Ensemble(small_ensemble.droplets)
+    ens.set_tuning(workgroups=37, comp=comp, graph_steps=0)
+    steps = 20
+    ens.step(steps, small_ensemble.dt)
+    ens.sync()
+    xg = ens.positions64()
+    off = ens.offsets
+    for d, w in enumerate(small_ensemble.droplets):
+        st = orc.State(w)
+        assert st.run(steps, small_ensemble.dt) == -1
+        err = np.abs(xg[off[d]:off[d + 1]] - st.x).max()
+        assert err <= 1e-4, (d, err)
+    step, t = ens.state()
+    assert step == steps and t == pytest.approx(steps * small_ensemble.dt, rel=1e-12)
+
+
+def test_ensemble_graph_replay_matches_eager(ld, small_ensemble):
+    a = ld.Ensemble(small_ensemble.droplets)
+    a.step(24, small_ensemble.dt)
+    xa = a.positions64()
+    b = ld.Ensemble(small_ensemble.droplets)
+    b.set_tuning(graph_steps=8)
+    for _ in range(3):
+        b.step(8, small_ensemble.dt)      # one replay each
+        _ = b.forces()                    # eager work between replays
+        b.sync()
+    assert np.array_equal(b.positions64(), xa)
+    assert b.state()[0] == 24
+
+
+def test_ensemble_uneven_sizes_and_single_droplet(ld, orc):
+    """One tiny and one larger droplet; and a one-droplet ensemble equals the
+    single-droplet context."""
+    e = W.config_ensemble(n_drop=2, n_min=2, n_max=3000, seed=5)
+    e.droplets[0] = W.config_small(n=2, seed=3)
+    e.droplets[0].pos = np.array([[0, 0, 0], [1.4, 0.2, 0.0]], np.float32)
+    ens = ld.Ensemble(e.droplets)
+    ens.step(10, 1e-3)
+    ens.sync()
+    xg = ens.positions64()
+    off = ens.offsets
+    for d, w in enumerate(e.droplets):
+        st = orc.State(w)
+        st.run(10, 1e-3)
+        assert np.abs(xg[off[d]:off[d + 1]] - st.x).max() <= 1e-4
+    w = e.droplets[1]
+    one = ld.Ensemble([w])
+    one.step(10, 1e-3)
+    s = ld.System.from_workload(w)
+    s.set_tuning(sort_every=-1, cull=0)
+    s.step(10, 1e-3)
+    assert np.abs(one.positions64() - s.positions64()).max() <= 1e-6
+
+
+def test_single_droplet_graph_matches_eager(ld):
+    w = W.config_small()
+    a = ld.System.from_workload(w)
+    a.set_tuning(sort_every=10)
+    a.step(60, w.dt)
+    xa = a.positions64()
+    b = ld.System.from_workload(w)
+    b.set_tuning(sort_every=10, graph_steps=1)
+    for k in range(3):
+        b.step(20, w.dt)                 # partial chunk, then replays
+        _ = b.forces(ext=False)          # eager work between replays
+    assert np.array_equal(b.positions64(), xa)
+    assert b.state()[0] == 60
+    c = ld.System.from_workload(w)
+    c.set_tuning(sort_every=-1, graph_steps=16)
+    c.step(40, w.dt)
+    d = ld.System.from_workload(w)
+    d.set_tuning(sort_every=-1)
+    d.step(40, w.dt)
+    assert np.array_equal(c.positions64(), d.positions64())
+
+
+def test_autotune_and_cache(ld, orc, tmp_path):
+    w = W.config_large(n=20000, seed=8)
+    s = ld.System.from_workload(w)
+    before = s.forces(ext=False)["pair"].cpu().numpy()
+    cache = str(tmp_path / "tune.txt")
+    t1 = s.autotune(cache_path=cache)
+    assert t1["block"] in (128, 256, 512) and 1 <= t1["j_split"] <= 16
+    after = s.forces(ext=False)["pair"].cpu().numpy()
+    rows = np.arange(0, w.n, 997)
+    Fo, So, _ = orc.pair_forces(w.pos, w.type, w.charge, w.params, rows=rows)
+    for F in (before, after):
+        dF = np.linalg.norm(F[rows] - Fo, axis=1)
+        assert np.all(dF <= 1e-5 * So)   # neutral, isolated particles: S = F = 0
+    text = open(cache).read()
+    assert f" {t1['block']} {t1['j_split']} " in text
+    s2 = ld.System.from_workload(w)
+    t2 = s2.autotune(cache_path=cache)
+    assert (t2["block"], t2["j_split"]) == (t1["block"], t1["j_split"])
