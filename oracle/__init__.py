@@ -89,6 +89,19 @@ def lib():
                               C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), dp, dp]
         L.ldo_fractal.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_double,
                                   C.c_int32, dp, C.POINTER(C.c_int64)]
+        L.ldo_bf16.argtypes = [C.c_double]
+        L.ldo_bf16.restype = C.c_double
+        L.ldo_ff_moments.argtypes = [C.c_int64, dp, dp, C.c_int, C.c_double, dp]
+        L.ldo_ff_coarse.argtypes = [C.c_int, C.c_double, C.c_int, dp, dp]
+        L.ldo_ff_split.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp, C.POINTER(_Params),
+                                   C.c_double, C.POINTER(C.c_int64), C.c_int64, dp, dp]
+        L.ldo_ff_features.argtypes = [C.c_int64, dp, C.c_int, C.c_double, C.c_int, dp,
+                                      C.c_double, dp]
+        L.ldo_mlp_forward.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp,
+                                      dp, dp, C.c_int, dp, dp, dp, dp, dp]
+        L.ldo_mlp_backward.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp,
+                                       dp, dp, dp, C.c_int, dp, dp, dp, dp, dp, dp]
+        L.ldo_mlp_backward.restype = C.c_double
         _lib = L
     return _lib
 
@@ -261,3 +274,85 @@ def fractal(x, k_f: float, d: float, eps0: float, max_scales: int = 32):
     lib().ldo_fractal(len(x), _dp(x), k_f, d, eps0, max_scales, _dp(out), _lp(bc))
     K = int(out[3])
     return out[0], out[1], out[2], K, bc[:K].copy()
+
+
+# ---------------------------------------------------------------------------
+# Learned far field (the residual model of the far Coulomb sum)
+# ---------------------------------------------------------------------------
+
+def bf16(v: float) -> float:
+    return lib().ldo_bf16(float(v))
+
+
+def qhat(charge, params):
+    """Charges in field units: q sqrt(kT l_B)."""
+    return np.asarray(charge, np.float64) * np.sqrt(params.kT * params.bjerrum)
+
+
+def ff_moments(x, qh, G: int, L: float) -> np.ndarray:
+    """(Q, Px, Py, Pz) per cell of the G^3 grid over [-L, L]^3."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    qh = np.ascontiguousarray(qh, np.float64)
+    out = np.zeros((G ** 3, 4))
+    lib().ldo_ff_moments(len(x), _dp(x), _dp(qh), G, L, _dp(out))
+    return out
+
+
+def ff_coarse(mom, G: int, L: float, B: int = 5) -> np.ndarray:
+    """Field at every cell centre from the cells outside its B^3 block."""
+    mom = np.ascontiguousarray(mom, np.float64)
+    E = np.zeros((G ** 3, 3))
+    lib().ldo_ff_coarse(G, L, B, _dp(mom), _dp(E))
+    return E
+
+
+def ff_split(x, type_, charge, params, rc: float, rows=None):
+    """(F_near [m,3], E_far [m,3]) split at rc."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(type_, np.int32)
+    q = np.ascontiguousarray(charge, np.float64)
+    rows_a = None if rows is None else np.ascontiguousarray(rows, np.int64)
+    m = len(t) if rows is None else len(rows_a)
+    Fn = np.zeros((m, 3))
+    Ef = np.zeros((m, 3))
+    lib().ldo_ff_split(len(t), _dp(x), _ip(t), _dp(q), C.byref(make_params(params)), rc,
+                       _lp(rows_a), m, _dp(Fn), _dp(Ef))
+    return Fn, Ef
+
+
+def ff_features(x, G: int, L: float, B: int, mom, sq: float) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    mom = np.ascontiguousarray(mom, np.float64)
+    K = 4 * B ** 3 + 3
+    X = np.zeros((len(x), K))
+    lib().ldo_ff_features(len(x), _dp(x), G, L, B, _dp(mom), sq, _dp(X))
+    return X
+
+
+def mlp_forward(X, W, bf16_mode: bool = False, save: bool = False):
+    """W = dict(W1 [K,H], b1, W2 [H,H], b2, W3 [H,O], b3)."""
+    X = np.ascontiguousarray(X, np.float64)
+    m, K = X.shape
+    H = W["W1"].shape[1]
+    O = W["W3"].shape[1]
+    ws = [np.ascontiguousarray(W[k], np.float64) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+    Y = np.zeros((m, O))
+    sv = [np.zeros((m, H)) for _ in range(4)] if save else [None] * 4
+    lib().ldo_mlp_forward(m, K, H, O, _dp(X), *[_dp(w) for w in ws], 1 if bf16_mode else 0,
+                          _dp(Y), *[_dp(a) for a in sv])
+    return (Y, sv) if save else Y
+
+
+def mlp_backward(X, T, W, bf16_mode: bool = False):
+    """(loss, grads dict) for the mean-squared loss."""
+    X = np.ascontiguousarray(X, np.float64)
+    T = np.ascontiguousarray(T, np.float64)
+    m, K = X.shape
+    H = W["W1"].shape[1]
+    O = W["W3"].shape[1]
+    ws = [np.ascontiguousarray(W[k], np.float64) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+    g = {k: np.zeros_like(v) for k, v in zip(("W1", "b1", "W2", "b2", "W3", "b3"), ws)}
+    loss = lib().ldo_mlp_backward(m, K, H, O, _dp(X), _dp(T), *[_dp(w) for w in ws],
+                                  1 if bf16_mode else 0,
+                                  *[_dp(g[k]) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+    return loss, g

@@ -142,6 +142,47 @@ void ldo_rdf(int64_t n, const double* x, double r_max, int32_t n_bins, double V,
 void ldo_fractal(int64_t n, const double* x, double k_f, double d, double eps0,
                  int32_t max_scales, double out[4], int64_t* box_counts);
 
+/* ---- learned far field (ldo_ff.c) ------------------------------------- */
+
+/* BF16 round-to-nearest-even of v (through its FP32 value).  Pinned against
+ * torch's bfloat16 conversion. */
+double ldo_bf16(double v);
+
+/* Cell moments of the G^3 grid over [-L, L]^3: out[4*cell] = (Q, Px, Py, Pz)
+ * with Q = sum q_hat and P = sum q_hat (x - cell centre); cell index
+ * (iz*G + iy)*G + ix; positions outside the cube clamp to the edge cells.
+ * Pinned by charge conservation and single-particle dipoles. */
+void ldo_ff_moments(int64_t n, const double* x, const double* qhat, int G, double L,
+                    double* out);
+
+/* Field at each cell centre from the monopole + dipole of every cell outside
+ * the B^3 block around it.  Pinned against exact point-charge sums. */
+void ldo_ff_coarse(int G, double L, int B, const double* mom, double* E);
+
+/* Pair forces of pairs closer than rc (LJ + Coulomb) and the Coulomb field
+ * sum_{j: r >= rc} q_hat_j r_ij / r^3 for the listed rows.  Pinned by
+ * F_near + q_hat E_far = the full pair force. */
+void ldo_ff_split(int64_t n, const double* x, const int32_t* type, const double* q,
+                  const ldo_params* p, double rc, const int64_t* rows, int64_t n_rows,
+                  double* F_near, double* E_far);
+
+/* MLP features [n * (4 B^3 + 3)]: normalised moments of the B^3 block
+ * around each particle's cell (dz-major), then its offset / h. */
+void ldo_ff_features(int64_t n, const double* x, int G, double L, int B, const double* mom,
+                     double sq, double* X);
+
+/* Three-layer SiLU MLP forward (optionally with BF16 operands) and its FP64
+ * backpropagation for the mean-squared loss.  Pinned against torch (CPU,
+ * FP64) and finite differences. */
+void ldo_mlp_forward(int64_t m, int K, int H, int O, const double* X, const double* W1,
+                     const double* b1, const double* W2, const double* b2, const double* W3,
+                     const double* b3, int bf16, double* Y, double* Z1, double* A1, double* Z2,
+                     double* A2);
+double ldo_mlp_backward(int64_t m, int K, int H, int O, const double* X, const double* T,
+                        const double* W1, const double* b1, const double* W2, const double* b2,
+                        const double* W3, const double* b3, int bf16, double* dW1, double* db1,
+                        double* dW2, double* db2, double* dW3, double* db3);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,303 @@
+/*
+ * ldo_ff.c -- CPU FP64 oracle for the learned far field (test infrastructure
+ * only; see ldo.h for the rules it follows).
+ *
+ * The pair sum is split at a near cutoff r_c: pairs with r < r_c are summed
+ * exactly (LJ + Coulomb); the Coulomb sum over r >= r_c is the "far field".
+ * The far field is modelled as
+ *     E_far(i) ~ E_coarse(cell of i) + E_mlp(features of i)
+ * where E_coarse is the field at the centre of i's grid cell from the
+ * monopole and dipole moments of every grid cell outside the B x B x B block
+ * around that cell, and the MLP sees the normalised moments of the B^3 block
+ * plus i's offset inside its cell.  Fields are in units of sqrt(kT l_B) per
+ * unit length squared, so the force is q_hat_i E with q_hat = q sqrt(kT l_B).
+ *
+ * Everything here is FP64.  The MLP forward can emulate the GPU's BF16
+ * operands: inputs, weights and hidden activations are rounded to BF16
+ * (round to nearest even) before each matrix product; products and sums stay
+ * FP64.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "ldo.h"
+
+/* BF16 round-to-nearest-even of an FP64 value (via its FP32 rounding, as a
+ * device converting an FP32 register would see it). */
+double ldo_bf16(double v) {
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (double)f;   /* inf / nan */
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    u &= 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static void cell_of(const double x[3], int G, double L, int c[3]) {
+    const double h = 2.0 * L / G;
+    for (int k = 0; k < 3; ++k) {
+        int v = (int)floor((x[k] + L) / h);
+        if (v < 0) v = 0;
+        if (v > G - 1) v = G - 1;
+        c[k] = v;
+    }
+}
+
+static double centre(int ci, int G, double L) { return -L + (ci + 0.5) * (2.0 * L / G); }
+
+/* Moments of the G^3 grid over [-L, L]^3: per cell Q = sum q_hat, P = sum
+ * q_hat (x - centre).  out is [G^3 * 4], cell index (iz * G + iy) * G + ix. */
+void ldo_ff_moments(int64_t n, const double* x, const double* qhat, int G, double L,
+                    double* out) {
+    memset(out, 0, sizeof(double) * 4 * (size_t)G * G * G);
+    for (int64_t i = 0; i < n; ++i) {
+        int c[3];
+        cell_of(&x[3 * i], G, L, c);
+        const size_t k = ((size_t)c[2] * G + c[1]) * G + c[0];
+        out[4 * k] += qhat[i];
+        out[4 * k + 1] += qhat[i] * (x[3 * i] - centre(c[0], G, L));
+        out[4 * k + 2] += qhat[i] * (x[3 * i + 1] - centre(c[1], G, L));
+        out[4 * k + 3] += qhat[i] * (x[3 * i + 2] - centre(c[2], G, L));
+    }
+}
+
+/* Field at every cell centre from the monopole + dipole of every cell
+ * outside the B^3 block (Chebyshev cell distance > B/2) around it:
+ *   E = Q r / r^3 + (3 (P.r) r / r^2 - P) / r^3,  r = target - source. */
+void ldo_ff_coarse(int G, double L, int B, const double* mom, double* E) {
+    const int half = B / 2;
+    const size_t M = (size_t)G * G * G;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (size_t t = 0; t < M; ++t) {
+        const int tx = (int)(t % G), ty = (int)((t / G) % G), tz = (int)(t / ((size_t)G * G));
+        double ex = 0.0, ey = 0.0, ez = 0.0;
+        for (size_t s = 0; s < M; ++s) {
+            const int sx = (int)(s % G), sy = (int)((s / G) % G), sz = (int)(s / ((size_t)G * G));
+            if (abs(sx - tx) <= half && abs(sy - ty) <= half && abs(sz - tz) <= half) continue;
+            const double Q = mom[4 * s], Px = mom[4 * s + 1], Py = mom[4 * s + 2],
+                         Pz = mom[4 * s + 3];
+            if (Q == 0.0 && Px == 0.0 && Py == 0.0 && Pz == 0.0) continue;
+            const double rx = centre(tx, G, L) - centre(sx, G, L);
+            const double ry = centre(ty, G, L) - centre(sy, G, L);
+            const double rz = centre(tz, G, L) - centre(sz, G, L);
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double r = sqrt(r2);
+            const double r3 = r2 * r;
+            const double pr = Px * rx + Py * ry + Pz * rz;
+            ex += Q * rx / r3 + (3.0 * pr * rx / r2 - Px) / r3;
+            ey += Q * ry / r3 + (3.0 * pr * ry / r2 - Py) / r3;
+            ez += Q * rz / r3 + (3.0 * pr * rz / r2 - Pz) / r3;
+        }
+        E[3 * t] = ex;
+        E[3 * t + 1] = ey;
+        E[3 * t + 2] = ez;
+    }
+}
+
+/* Pair forces (LJ + Coulomb, as ldo_pair_forces) restricted to pairs with
+ * r < r_c, and the far Coulomb field sum_{j: r >= r_c} q_hat_j r_ij / r^3
+ * (without the q_hat_i factor), for the listed rows (NULL: all). */
+void ldo_ff_split(int64_t n, const double* x, const int32_t* type, const double* q,
+                  const ldo_params* p, double rc, const int64_t* rows, int64_t n_rows,
+                  double* F_near, double* E_far) {
+    if (rows == NULL) n_rows = n;
+    const double s = sqrt(p->kT * p->bjerrum);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t i = rows ? rows[r] : r;
+        double fx = 0, fy = 0, fz = 0, ex = 0, ey = 0, ez = 0;
+        double cfx = 0, cfy = 0, cfz = 0, cex = 0, cey = 0, cez = 0;  /* Kahan terms */
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = x[3 * i] - x[3 * j], dy = x[3 * i + 1] - x[3 * j + 1],
+                         dz = x[3 * i + 2] - x[3 * j + 2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double rr = sqrt(r2);
+            double gx = 0, gy = 0, gz = 0;
+            if (rr < rc) {
+                const int ti = type[i], tj = type[j];
+                const double sg = 0.5 * (p->sigma[ti] + p->sigma[tj]);
+                const double e = p->use_eps_matrix ? p->eps_matrix[ti * LDO_MAX_TYPES + tj]
+                                                   : sqrt(p->eps[ti] * p->eps[tj]);
+                if (r2 < (p->lj_cut * sg) * (p->lj_cut * sg)) {
+                    const double sr2 = sg * sg / r2, sr6 = sr2 * sr2 * sr2;
+                    const double g = 24.0 * e * (2.0 * sr6 * sr6 - sr6) / r2;
+                    gx += g * dx; gy += g * dy; gz += g * dz;
+                }
+                const double k = p->kT * p->bjerrum * q[i] * q[j] / (r2 * rr);
+                gx += k * dx; gy += k * dy; gz += k * dz;
+                double y, t;
+                y = gx - cfx; t = fx + y; cfx = (t - fx) - y; fx = t;
+                y = gy - cfy; t = fy + y; cfy = (t - fy) - y; fy = t;
+                y = gz - cfz; t = fz + y; cfz = (t - fz) - y; fz = t;
+            } else {
+                const double k = s * q[j] / (r2 * rr);
+                double y, t;
+                y = k * dx - cex; t = ex + y; cex = (t - ex) - y; ex = t;
+                y = k * dy - cey; t = ey + y; cey = (t - ey) - y; ey = t;
+                y = k * dz - cez; t = ez + y; cez = (t - ez) - y; ez = t;
+            }
+        }
+        if (F_near) { F_near[3 * r] = fx; F_near[3 * r + 1] = fy; F_near[3 * r + 2] = fz; }
+        if (E_far) { E_far[3 * r] = ex; E_far[3 * r + 1] = ey; E_far[3 * r + 2] = ez; }
+    }
+}
+
+/* MLP features of each particle: the B^3 block of cell moments around its
+ * cell (cells outside the grid read as zero), ordered dz-major then dy then
+ * dx, each cell as (Q / sq, Px / (sq h), Py / (sq h), Pz / (sq h)), then the
+ * offset (x - centre) / h.  X is [n * (4 B^3 + 3)]. */
+void ldo_ff_features(int64_t n, const double* x, int G, double L, int B, const double* mom,
+                     double sq, double* X) {
+    const double h = 2.0 * L / G;
+    const int half = B / 2;
+    const int K = 4 * B * B * B + 3;
+    for (int64_t i = 0; i < n; ++i) {
+        int c[3];
+        cell_of(&x[3 * i], G, L, c);
+        double* row = X + (size_t)i * K;
+        int f = 0;
+        for (int dz = -half; dz <= half; ++dz)
+            for (int dy = -half; dy <= half; ++dy)
+                for (int dx = -half; dx <= half; ++dx) {
+                    const int cx = c[0] + dx, cy = c[1] + dy, cz = c[2] + dz;
+                    if (cx < 0 || cy < 0 || cz < 0 || cx >= G || cy >= G || cz >= G) {
+                        row[f] = row[f + 1] = row[f + 2] = row[f + 3] = 0.0;
+                    } else {
+                        const size_t k = ((size_t)cz * G + cy) * G + cx;
+                        row[f] = mom[4 * k] / sq;
+                        row[f + 1] = mom[4 * k + 1] / (sq * h);
+                        row[f + 2] = mom[4 * k + 2] / (sq * h);
+                        row[f + 3] = mom[4 * k + 3] / (sq * h);
+                    }
+                    f += 4;
+                }
+        for (int k = 0; k < 3; ++k) row[f + k] = (x[3 * i + k] - centre(c[k], G, L)) / h;
+    }
+}
+
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+static double dsilu(double z) {
+    const double s = 1.0 / (1.0 + exp(-z));
+    return s * (1.0 + z * (1.0 - s));
+}
+
+/* y = W3 silu(W2 silu(W1 x + b1) + b2) + b3 for m rows of X [m*K].  Weights
+ * are row-major [in][out]: W1 [K*H], W2 [H*H], W3 [H*O].  bf16 != 0 rounds x,
+ * the weights and both hidden activations to BF16 before each product.
+ * Optional saves: Z1, A1, Z2, A2 [m*H] (pre-activations and activations as
+ * fed to the next product). */
+void ldo_mlp_forward(int64_t m, int K, int H, int O, const double* X, const double* W1,
+                     const double* b1, const double* W2, const double* b2, const double* W3,
+                     const double* b3, int bf16, double* Y, double* Z1, double* A1, double* Z2,
+                     double* A2) {
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < m; ++r) {
+        double* z1 = (double*)malloc(sizeof(double) * H);
+        double* a1 = (double*)malloc(sizeof(double) * H);
+        double* z2 = (double*)malloc(sizeof(double) * H);
+        double* a2 = (double*)malloc(sizeof(double) * H);
+        const double* xr = X + (size_t)r * K;
+        for (int j = 0; j < H; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < K; ++k) {
+                const double a = bf16 ? ldo_bf16(xr[k]) : xr[k];
+                const double w = bf16 ? ldo_bf16(W1[(size_t)k * H + j]) : W1[(size_t)k * H + j];
+                acc += a * w;
+            }
+            z1[j] = acc + b1[j];
+            a1[j] = silu(z1[j]);
+            if (bf16) a1[j] = ldo_bf16(a1[j]);
+        }
+        for (int j = 0; j < H; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < H; ++k) {
+                const double w = bf16 ? ldo_bf16(W2[(size_t)k * H + j]) : W2[(size_t)k * H + j];
+                acc += a1[k] * w;
+            }
+            z2[j] = acc + b2[j];
+            a2[j] = silu(z2[j]);
+            if (bf16) a2[j] = ldo_bf16(a2[j]);
+        }
+        for (int j = 0; j < O; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < H; ++k) {
+                const double w = bf16 ? ldo_bf16(W3[(size_t)k * O + j]) : W3[(size_t)k * O + j];
+                acc += a2[k] * w;
+            }
+            Y[(size_t)r * O + j] = acc + b3[j];
+        }
+        if (Z1) memcpy(Z1 + (size_t)r * H, z1, sizeof(double) * H);
+        if (A1) memcpy(A1 + (size_t)r * H, a1, sizeof(double) * H);
+        if (Z2) memcpy(Z2 + (size_t)r * H, z2, sizeof(double) * H);
+        if (A2) memcpy(A2 + (size_t)r * H, a2, sizeof(double) * H);
+        free(z1); free(a1); free(z2); free(a2);
+    }
+}
+
+/* Loss L = mean over the m x O outputs of (y - t)^2 and its gradients with
+ * respect to every weight and bias (manual backpropagation through the
+ * forward above, same bf16 mode; derivatives are FP64).  Returns L. */
+double ldo_mlp_backward(int64_t m, int K, int H, int O, const double* X, const double* T,
+                        const double* W1, const double* b1, const double* W2, const double* b2,
+                        const double* W3, const double* b3, int bf16, double* dW1, double* db1,
+                        double* dW2, double* db2, double* dW3, double* db3) {
+    double* Y = (double*)malloc(sizeof(double) * (size_t)m * O);
+    double* Z1 = (double*)malloc(sizeof(double) * (size_t)m * H);
+    double* A1 = (double*)malloc(sizeof(double) * (size_t)m * H);
+    double* Z2 = (double*)malloc(sizeof(double) * (size_t)m * H);
+    double* A2 = (double*)malloc(sizeof(double) * (size_t)m * H);
+    ldo_mlp_forward(m, K, H, O, X, W1, b1, W2, b2, W3, b3, bf16, Y, Z1, A1, Z2, A2);
+    memset(dW1, 0, sizeof(double) * (size_t)K * H);
+    memset(db1, 0, sizeof(double) * H);
+    memset(dW2, 0, sizeof(double) * (size_t)H * H);
+    memset(db2, 0, sizeof(double) * H);
+    memset(dW3, 0, sizeof(double) * (size_t)H * O);
+    memset(db3, 0, sizeof(double) * O);
+    double loss = 0.0;
+    double* dy = (double*)malloc(sizeof(double) * O);
+    double* d2 = (double*)malloc(sizeof(double) * H);
+    double* d1 = (double*)malloc(sizeof(double) * H);
+    const double norm = 1.0 / ((double)m * O);
+    for (int64_t r = 0; r < m; ++r) {
+        const double* xr = X + (size_t)r * K;
+        for (int j = 0; j < O; ++j) {
+            const double e = Y[(size_t)r * O + j] - T[(size_t)r * O + j];
+            loss += e * e * norm;
+            dy[j] = 2.0 * e * norm;
+            db3[j] += dy[j];
+        }
+        for (int k = 0; k < H; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < O; ++j) {
+                dW3[(size_t)k * O + j] += A2[(size_t)r * H + k] * dy[j];
+                const double w = bf16 ? ldo_bf16(W3[(size_t)k * O + j]) : W3[(size_t)k * O + j];
+                acc += w * dy[j];
+            }
+            d2[k] = acc * dsilu(Z2[(size_t)r * H + k]);
+            db2[k] += d2[k];
+        }
+        for (int k = 0; k < H; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < H; ++j) {
+                dW2[(size_t)k * H + j] += A1[(size_t)r * H + k] * d2[j];
+                const double w = bf16 ? ldo_bf16(W2[(size_t)k * H + j]) : W2[(size_t)k * H + j];
+                acc += w * d2[j];
+            }
+            d1[k] = acc * dsilu(Z1[(size_t)r * H + k]);
+            db1[k] += d1[k];
+        }
+        for (int k = 0; k < K; ++k) {
+            const double a = bf16 ? ldo_bf16(xr[k]) : xr[k];
+            for (int j = 0; j < H; ++j) dW1[(size_t)k * H + j] += a * d1[j];
+        }
+    }
+    free(dy); free(d2); free(d1);
+    free(Y); free(Z1); free(A1); free(Z2); free(A2);
+    return loss;
+}

@@ -1,0 +1,202 @@
+"""Pins for the learned-far-field part of the oracle: BF16 rounding against
+torch, moments against conservation and single-particle dipoles, the coarse
+multipole field against exact point-charge sums, the near/far split against
+the (pinned) full pair sum, the feature layout, and the MLP forward /
+backward against torch (CPU, FP64) and finite differences."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2501_04456_amd import workloads as W
+
+
+def test_bf16_matches_torch(oracle_lib):
+    rng = np.random.default_rng(0)
+    vals = np.concatenate([rng.standard_normal(3000) * 10.0 ** rng.integers(-6, 6, 3000),
+                           [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, -(1.0 + 2 ** -8),
+                            0.0, 65504.0, 1e30, -3.5e-20]])
+    ref = torch.tensor(vals, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([oracle_lib.bf16(v) for v in vals])
+    assert np.array_equal(got, ref)
+
+
+def ball(n, R, seed):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v * (R * rng.random(n) ** (1 / 3))[:, None]
+
+
+def test_moments_conservation_and_dipole(oracle_lib):
+    x = ball(2000, 30.0, 1)
+    q = np.where(np.arange(2000) % 3 == 0, 1.0, -0.5)
+    G, L = 8, 32.0
+    m = oracle_lib.ff_moments(x, q, G, L)
+    assert m[:, 0].sum() == pytest.approx(q.sum(), abs=1e-9)
+    # total dipole about the origin = sum over cells (P_c + Q_c centre_c)
+    h = 2 * L / G
+    idx = np.arange(G ** 3)
+    cen = np.stack([(idx % G + 0.5) * h - L, ((idx // G) % G + 0.5) * h - L,
+                    (idx // G ** 2 + 0.5) * h - L], 1)
+    tot = (m[:, 1:] + m[:, :1] * cen).sum(0)
+    assert np.allclose(tot, (q[:, None] * x).sum(0), rtol=1e-10, atol=1e-8)
+    # a single particle: its cell holds q and q * offset
+    one = oracle_lib.ff_moments(np.array([[3.0, -5.0, 12.0]]), np.array([2.0]), G, L)
+    k = np.flatnonzero(one[:, 0])
+    assert len(k) == 1
+    c = cen[k[0]]
+    assert np.allclose(one[k[0], 1:], 2.0 * (np.array([3.0, -5.0, 12.0]) - c))
+
+
+def test_coarse_field_equals_point_charges_at_centres(oracle_lib):
+    """Charges sitting exactly at cell centres have no dipole: the coarse
+    field at a cell centre is the exact field of every charge outside the
+    5^3 block around it (the far sum of ldo_ff_split with r_c = 0)."""
+    G, L = 12, 24.0
+    h = 2 * L / G
+    rng = np.random.default_rng(2)
+    cells = rng.choice(G ** 3, 300, replace=False)
+    cen = lambda k: np.array([(k % G + 0.5) * h - L, ((k // G) % G + 0.5) * h - L,
+                              (k // G ** 2 + 0.5) * h - L])
+    x = np.array([cen(k) for k in cells])
+    q = rng.uniform(-1, 1, len(cells))
+    p = W.Params(sigma=[1e-3], eps=[0.0], mass=[1], gamma=[1], k_wall=[0], wall_offset=[0],
+                 kT=1.0, bjerrum=1.0)
+    m = oracle_lib.ff_moments(x, q, G, L)
+    assert np.abs(m[:, 1:]).max() < 1e-12
+    E = oracle_lib.ff_coarse(m, G, L, 5)
+    for t in [0, 77, 500, G ** 3 - 1, int(cells[5])]:
+        ct = cen(t)
+        tz, ty, tx = t // G ** 2, (t // G) % G, t % G
+        far = [i for i, k in enumerate(cells)
+               if max(abs(k % G - tx), abs((k // G) % G - ty), abs(k // G ** 2 - tz)) > 2]
+        xs = np.vstack([x[far], ct[None]])
+        qs = np.concatenate([q[far], [0.0]])
+        _, Ef = oracle_lib.ff_split(xs, np.zeros(len(xs), np.int32), qs, p, 0.0,
+                                    rows=[len(xs) - 1])
+        assert np.allclose(E[t], Ef[0], rtol=1e-12, atol=1e-14)
+
+
+def test_coarse_dipole_accuracy(oracle_lib):
+    """A +q/-q pair of small separation d in a distant cell: the dipole term
+    reproduces the exact field to O((d/r)^2)."""
+    G, L = 16, 32.0
+    h = 2 * L / G
+    src = np.array([[20.3, -7.1, 3.3], [20.3 + 0.4, -7.1 - 0.3, 3.3 + 0.2]])
+    q = np.array([1.0, -1.0])
+    m = oracle_lib.ff_moments(src, q, G, L)
+    E = oracle_lib.ff_coarse(m, G, L, 5)
+    t = (G // 2) * G * G + (G // 2) * G + 1          # a cell far from the pair
+    ct = np.array([(1 + 0.5) * h - L, (G // 2 + 0.5) * h - L, (G // 2 + 0.5) * h - L])
+    p = W.Params(sigma=[1e-3], eps=[0.0], mass=[1], gamma=[1], k_wall=[0], wall_offset=[0],
+                 kT=1.0, bjerrum=1.0)
+    _, Ef = oracle_lib.ff_split(np.vstack([src, ct[None]]), np.zeros(3, np.int32),
+                                np.array([1.0, -1.0, 0.0]), p, 0.0, rows=[2])
+    r = np.linalg.norm(src.mean(0) - ct)
+    # the pair's dipole sits off the cell centre: error O((a/r)) relative, with
+    # a the distance from the cell centre (below half a cell diagonal)
+    assert np.linalg.norm(E[t] - Ef[0]) <= np.linalg.norm(Ef[0]) * 4 * (0.9 * h / r)
+
+
+def test_split_sums_to_full_pair_force(oracle_lib):
+    w = W.config_medium(n=400, seed=3)
+    x = w.pos.astype(np.float64)
+    F, S, _ = oracle_lib.pair_forces(x, w.type, w.charge, w.params)
+    qh = oracle_lib.qhat(w.charge, w.params)
+    # any cut beyond the largest LJ range (2.5 x 1.5) splits the sum exactly
+    for rc in (3.76, 8.0, 20.0, 1e9):
+        Fn, Ef = oracle_lib.ff_split(x, w.type, w.charge, w.params, rc)
+        assert np.all(np.abs(Fn + qh[:, None] * Ef - F) <= 1e-12 * S[:, None] + 1e-15)
+    # r_c = 0: everything is far, and the far sum is the pure Coulomb force
+    Fn, Ef = oracle_lib.ff_split(x, w.type, w.charge, w.params, 0.0)
+    assert np.all(Fn == 0)
+    pc = W.Params(**{**w.params.__dict__})
+    pc.eps = [0.0, 0.0]
+    Fc, Sc, _ = oracle_lib.pair_forces(x, w.type, w.charge, pc)
+    assert np.all(np.abs(qh[:, None] * Ef - Fc) <= 1e-12 * Sc[:, None] + 1e-15)
+    Fn, Ef = oracle_lib.ff_split(x, w.type, w.charge, w.params, 1e9)
+    assert np.all(Ef == 0)
+
+
+def test_feature_layout(oracle_lib):
+    G, L, B = 8, 16.0, 5
+    h = 2 * L / G
+    x = np.array([[1.3, -2.2, 5.9]])
+    m = oracle_lib.ff_moments(x, np.array([0.7]), G, L)
+    X = oracle_lib.ff_features(x, G, L, B, m, 0.5)
+    assert X.shape == (1, 4 * 125 + 3)
+    # the centre cell of the 5^3 block is entry 62 (dz = dy = dx = 0)
+    k = np.flatnonzero(m[:, 0])[0]
+    assert X[0, 4 * 62] == pytest.approx(0.7 / 0.5)
+    assert np.allclose(X[0, 4 * 62 + 1:4 * 62 + 4], m[k, 1:] / (0.5 * h))
+    nz = np.flatnonzero(X[0, :500])
+    assert set(nz) <= {248, 249, 250, 251}
+    cx = (np.floor((x[0] + L) / h) + 0.5) * h - L
+    assert np.allclose(X[0, 500:], (x[0] - cx) / h)
+    # a particle in the corner cell sees zeros outside the grid
+    y = np.array([[-L + 0.1, -L + 0.1, -L + 0.1]])
+    Xc = oracle_lib.ff_features(y, G, L, B, oracle_lib.ff_moments(y, np.array([1.0]), G, L),
+                                1.0)
+    assert Xc[0, 4 * 62] == 1.0 and np.count_nonzero(Xc[0, :500]) <= 4
+
+
+def random_mlp(K, H, O, seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return {"W1": rng.standard_normal((K, H)) * scale / math.sqrt(K),
+            "b1": rng.standard_normal(H) * 0.1,
+            "W2": rng.standard_normal((H, H)) * scale / math.sqrt(H),
+            "b2": rng.standard_normal(H) * 0.1,
+            "W3": rng.standard_normal((H, O)) * scale / math.sqrt(H),
+            "b3": rng.standard_normal(O) * 0.1}
+
+
+def torch_mlp(X, W, bf16=False):
+    r = (lambda t: t.float().to(torch.bfloat16).double()) if bf16 else (lambda t: t)
+    T = {k: torch.tensor(v, dtype=torch.float64) for k, v in W.items()}
+    a = r(torch.tensor(X, dtype=torch.float64))
+    z1 = a @ r(T["W1"]) + T["b1"]
+    a1 = r(torch.nn.functional.silu(z1))
+    z2 = a1 @ r(T["W2"]) + T["b2"]
+    a2 = r(torch.nn.functional.silu(z2))
+    return (a2 @ r(T["W3"]) + T["b3"]).numpy()
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_mlp_forward_matches_torch(oracle_lib, bf16):
+    W_ = random_mlp(503, 128, 3, 1)
+    X = np.random.default_rng(2).standard_normal((64, 503))
+    Y = oracle_lib.mlp_forward(X, W_, bf16_mode=bf16)
+    assert np.allclose(Y, torch_mlp(X, W_, bf16), rtol=1e-12, atol=1e-13)
+
+
+def test_mlp_backward_finite_differences(oracle_lib):
+    K, H, O = 11, 7, 3
+    W_ = random_mlp(K, H, O, 4, scale=1.0)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((9, K))
+    T = rng.standard_normal((9, O))
+    loss, g = oracle_lib.mlp_backward(X, T, W_)
+    Y = oracle_lib.mlp_forward(X, W_)
+    assert loss == pytest.approx(np.mean((Y - T) ** 2), rel=1e-13)
+    eps = 1e-6
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        flat = W_[name].reshape(-1)
+        for k in range(0, flat.size, max(1, flat.size // 12)):
+            Wp = {kk: v.copy() for kk, v in W_.items()}
+            Wm = {kk: v.copy() for kk, v in W_.items()}
+            Wp[name].reshape(-1)[k] += eps
+            Wm[name].reshape(-1)[k] -= eps
+            lp = np.mean((oracle_lib.mlp_forward(X, Wp) - T) ** 2)
+            lm = np.mean((oracle_lib.mlp_forward(X, Wm) - T) ** 2)
+            assert g[name].reshape(-1)[k] == pytest.approx((lp - lm) / (2 * eps), rel=1e-6,
+                                                           abs=1e-9)
+    # and agrees with torch autograd
+    Tw = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in W_.items()}
+    a1 = torch.nn.functional.silu(torch.tensor(X) @ Tw["W1"] + Tw["b1"])
+    a2 = torch.nn.functional.silu(a1 @ Tw["W2"] + Tw["b2"])
+    L_ = ((a2 @ Tw["W3"] + Tw["b3"] - torch.tensor(T)) ** 2).mean()
+    L_.backward()
+    for k in Tw:
+        assert np.allclose(g[k], Tw[k].grad.numpy(), rtol=1e-11, atol=1e-13)
