@@ -232,6 +232,99 @@ ld_status ld_kernel_timing(ld_ctx* ctx, int32_t enable);
 ld_status ld_kernel_time(ld_ctx* ctx, int64_t* launches, double* total_ms);
 
 /* ---------------------------------------------------------------------- */
+/* Learned far field                                                        */
+/* ---------------------------------------------------------------------- */
+
+/* The pair sum split at near_cut r_c: pairs with r < r_c are summed exactly
+ * (LJ + Coulomb) over a cell list of side >= r_c; the Coulomb sum over
+ * r >= r_c is replaced by q_i (E_coarse + E_mlp).  E_coarse is the field at
+ * the centre of i's cell of a grid^3 grid over the cube [-L, L]^3,
+ * L = max_i max(|x_i|, |y_i|, |z_i|) (1 + 2^-10) in FP32, from the monopole
+ * Q = sum q_hat and dipole P = sum q_hat (x - centre) of every cell outside
+ * the block^3 neighbourhood of that cell.  The MLP (K = 4 block^3 + 3 inputs
+ * -> hidden -> hidden -> 3, SiLU, BF16 operands, FP32 accumulation) reads
+ * the neighbourhood's (Q / sq, P / (sq h)) (cells ordered z-major, then y,
+ * then x; zero outside the grid) and the offset (x - centre) / h, and
+ * predicts the remaining far field divided by out_scale.  q_hat = q sqrt(kT
+ * l_B). */
+typedef struct {
+    double near_cut;        /* r_c (>= the largest LJ range) */
+    int32_t grid;           /* G, 4..64 */
+    int32_t block;          /* B, odd, 1..7 */
+    int32_t hidden;         /* H, multiple of 16, 16..256 */
+    int32_t judge_every;    /* steps between judge evaluations (mode 2) */
+    double judge_tol;       /* median relative force error allowed */
+} ld_ff_config;
+
+typedef struct {
+    int32_t epochs;
+    int32_t batch;          /* 16..65536 */
+    double lr;              /* Adam learning rate */
+    uint64_t seed;          /* shuffle stream (Philox, tag 3) */
+    double val_fraction;    /* last fraction of the samples held out */
+    int32_t reset_scale;    /* 1: set out_scale to the RMS of the targets */
+    int32_t reserved;
+} ld_ff_train_cfg;
+
+typedef struct {
+    int64_t samples, iterations;
+    double final_loss;      /* MSE of the scaled residual, last batch */
+    double val_rel_rms;     /* relative RMS error of the residual, held out */
+    double out_scale;
+} ld_ff_train_report;
+
+/* Allocate the learned far field for this context (weights get small
+ * deterministic initial values; sq = largest |q_hat|).  Errors: LD_EINVAL,
+ * LD_ENOMEM. */
+ld_status ld_ff_enable(ld_ctx* ctx, const ld_ff_config* cfg);
+
+/* 0: direct summation; 1: learned far field every step; 2: learned with a
+ * judge every judge_every steps that falls back to direct summation for the
+ * next window when the median relative error of the pair forces exceeds
+ * judge_tol. */
+ld_status ld_ff_mode(ld_ctx* ctx, int32_t mode);
+
+/* Number of packed FP32 weights: W1 [Kp x H] (Kp = K rounded up to 32; rows
+ * >= K unused), b1 [H], W2 [H x H], b2 [H], W3 [H x 16] (columns >= 3
+ * unused), b3 [16]; all row-major [in][out]. */
+int64_t ld_ff_weights_size(ld_ctx* ctx);
+ld_status ld_ff_set_weights(ld_ctx* ctx, const float* w, int64_t count, double sq,
+                            double out_scale);
+ld_status ld_ff_get_weights(ld_ctx* ctx, float* w, int64_t count, double* sq, double* out_scale);
+
+/* The cube half width L and near cells per axis for the current positions. */
+ld_status ld_ff_grid(ld_ctx* ctx, double* L, int32_t* near_cells);
+
+/* Parts of the learned pair force at the current state, [n*3] FP64 in
+ * original order: 0 near (exact, r < r_c), 1 q E_coarse, 2 q E_mlp, 3 their
+ * sum (the learned pair force), 4 the exact far force (all r >= r_c). */
+ld_status ld_ff_forces(ld_ctx* ctx, int32_t part, double* out);
+
+/* MLP output [m*3] for m feature rows X [m*K] (FP32, host or device). */
+ld_status ld_ff_mlp(ld_ctx* ctx, const float* X, int64_t m, float* Y);
+
+/* Mean-squared loss of the MLP on (X [m*K], T [m*3]) and its gradients in
+ * the packed weight layout. */
+ld_status ld_ff_grads(ld_ctx* ctx, const float* X, const float* T, int64_t m, float* grads,
+                      double* loss);
+
+/* Append one training snapshot of the current state: for every particle
+ * its cell, offset and target (exact far field minus the coarse field).
+ * reset = 1 starts a new store with room for max_snapshots snapshots. */
+ld_status ld_ff_collect(ld_ctx* ctx, int32_t reset, int32_t max_snapshots);
+
+/* Train the MLP on the stored samples with Adam (forward and backward on the
+ * matrix cores). */
+ld_status ld_ff_train(ld_ctx* ctx, const ld_ff_train_cfg* cfg, ld_ff_train_report* report);
+
+/* Median relative error of the learned pair forces against direct
+ * summation at the current state. */
+ld_status ld_ff_judge(ld_ctx* ctx, double* median_rel_err);
+
+/* out = {judges, fallbacks, learned steps, direct steps}; last judge error. */
+ld_status ld_ff_stats(ld_ctx* ctx, int64_t out[4], double* last_err);
+
+/* ---------------------------------------------------------------------- */
 /* Ensembles of independent droplets                                       */
 /* ---------------------------------------------------------------------- */
 

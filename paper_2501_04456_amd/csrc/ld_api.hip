@@ -251,6 +251,16 @@ ld_status enqueue_step(ld_ctx* c, double dt, hipStream_t s, bool timed) {
         ld_status st = run_sort(c, s);
         if (st != LD_OK) return st;
     }
+    if (ld::ff_active(c)) {
+        int js = 1;
+        ld_status st = ld::ff_step_forces(c, s, &js);
+        if (st != LD_OK) return st;
+        ld::StepLaunch L = step_launch(c, dt);
+        L.j_split = js;
+        HIP_TRY(ld::launch_update(L, c->ext, s));
+        ++c->steps_since_sort;
+        return LD_OK;
+    }
     ld_status st = run_pair(c, false, s, timed);
     if (st != LD_OK) return st;
     HIP_TRY(ld::launch_update(step_launch(c, dt), c->ext, s));
@@ -320,6 +330,7 @@ void free_all(ld_ctx* c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    ld::ff_free(c);
 }
 
 }  // namespace
@@ -477,7 +488,7 @@ ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LD_EINVAL, "dt=%g must be positive", dt);
     if (n_steps < 0) return fail(LD_EINVAL, "n_steps must be >= 0");
     int64_t left = n_steps;
-    const bool use_graph = c->tune.graph_steps > 0 && !c->timing;
+    const bool use_graph = c->tune.graph_steps > 0 && !c->timing && !ld::ff_active(c);
     const int len = c->tune.sort_every > 0 ? c->tune.sort_every : c->tune.graph_steps;
     while (left > 0) {
         // A captured chunk starts with a re-sort when sorting is on, so it is

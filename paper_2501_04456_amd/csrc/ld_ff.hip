@@ -1,0 +1,1280 @@
+// Learned far field: the all-pairs sum split at a near cutoff r_c.
+//
+//   near (r < r_c)  exact LJ + Coulomb over a cell list of side >= r_c
+//   far  (r >= r_c) q_i (E_coarse(cell) + E_mlp(features))
+//
+// E_coarse is the field at the centre of the particle's cell of a G^3 grid
+// over the droplet from the monopole + dipole of every cell outside the
+// B^3 block around it.  The MLP (4 B^3 + 3 -> H -> H -> 3, SiLU, BF16
+// operands on the matrix cores, FP32 accumulation) sees the normalised
+// moments of that B^3 block and the particle's offset in its cell, and
+// predicts the rest of the far field.  Its first layer is evaluated once per
+// occupied cell (the moment part of the input depends only on the cell) and
+// finished per particle with the three offset columns.
+//
+// Training targets come from the exact far field (all pairs with r >= r_c)
+// minus the coarse term, on snapshots of the running system; the network is
+// trained on the GPU by the same MFMA products (forward, backward) and Adam.
+// Every judge_every steps a judge compares the learned pair forces with
+// direct summation on the same state; if the median relative error exceeds
+// the tolerance the next window runs direct summation.
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "ld_gemm.h"
+#include "ld_host.h"
+#include "ld_pair_core.h"
+
+using namespace ld;
+using namespace ld::host;
+
+namespace ld {
+
+constexpr int kMaxNearCells = 64;      // near cell list: at most 64^3 cells
+
+struct FFGrid {
+    double L;       // half width of the cube [-L, L]^3 covering every particle
+    double h;       // moment grid cell side 2L / G
+    double hn;      // near cell side 2L / Gn (>= r_c)
+    int Gn;         // near cells per axis
+    int pad;
+};
+
+struct FarField {
+    ld_ff_config cfg{};
+    int K = 0, Kp = 0, Op = 16, H = 0;
+    size_t offW1 = 0, offb1 = 0, offW2 = 0, offb2 = 0, offW3 = 0, offb3 = 0, nW = 0;
+    float sq = 1.f, out_scale = 1.f;
+    int mode = 0;                      // 0 direct, 1 learned, 2 learned + judge
+    bool active = true;                // judge verdict for the current window
+    int64_t window_steps = 0;
+    double last_err = NAN;
+    int64_t judges = 0, fallbacks = 0, learned_steps = 0, direct_steps = 0;
+
+    FFGrid* grid = nullptr;            // device
+    int* cstart = nullptr;             // [kMaxNearCells^3]
+    int* cend = nullptr;
+    double* Fnear = nullptr;           // [3][n]
+    double* mom = nullptr;             // [G^3 * 4]
+    int* count = nullptr;              // [G^3] particles per cell
+    int* occ = nullptr;                // [G^3] compacted occupied cells
+    int* cell2occ = nullptr;           // [G^3]
+    int* nocc = nullptr;               // [1]
+    double* Ecell = nullptr;           // [G^3 * 3]
+    float* Xc = nullptr;               // [G^3 * Kp]
+    float* Ac = nullptr;               // [G^3 * H]
+    float* h1 = nullptr;               // [n * H]
+    float* h2 = nullptr;               // [n * H]
+    float* y = nullptr;                // [n * Op]
+    float* W = nullptr;                // packed FP32 master weights
+    float* grad = nullptr;             // packed gradients
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    int adam_step = 0;
+    double* rel = nullptr;             // [n] judge errors
+    double* Efar = nullptr;            // [3][n] exact far field (training, tests)
+
+    // training store
+    int snap_cap = 0, snaps = 0;
+    int64_t sample_cap = 0, samples = 0;
+    float* snap_mom = nullptr;         // [snap_cap][G^3 * 4] normalised moments
+    int* s_snap = nullptr;             // [sample_cap]
+    int* s_cell = nullptr;
+    float* s_off = nullptr;            // [sample_cap * 3]
+    float* s_tgt = nullptr;            // [sample_cap * 3]
+    // batch buffers
+    int batch_cap = 0;
+    float *bX = nullptr, *bT = nullptr, *bZ1 = nullptr, *bA1 = nullptr, *bZ2 = nullptr,
+          *bA2 = nullptr, *bY = nullptr, *bdY = nullptr, *bd2 = nullptr, *bd1 = nullptr;
+    int* bidx = nullptr;
+    double* loss_part = nullptr;
+};
+
+}  // namespace ld
+
+namespace {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+
+__device__ __forceinline__ __bf16 bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __builtin_bit_cast(__bf16, (unsigned short)(u >> 16));
+}
+__device__ __forceinline__ float bf16_round(float f) { return (float)bf16_rne(f); }
+
+// ---- grid --------------------------------------------------------------
+
+__global__ __launch_bounds__(kB) void k_absmax_part(const float4* __restrict__ pos, int n,
+                                                    float* part) {
+    __shared__ float red[kB];
+    float m = 0.f;
+    for (int s = blockIdx.x * kB + threadIdx.x; s < n; s += gridDim.x * kB) {
+        const float4 h = pos[s];
+        m = fmaxf(m, fmaxf(fabsf(h.x), fmaxf(fabsf(h.y), fabsf(h.z))));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kB / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// L = max |coordinate| x (1 + 2^-10) in FP32, then the cell sides.
+__global__ void k_grid(const float* part, int nparts, double rc, int G, FFGrid* g) {
+    float m = 0.f;
+    for (int b = 0; b < nparts; ++b) m = fmaxf(m, part[b]);
+    m = fmaxf(m, 1e-3f);
+    const float Lf = m * 1.0009765625f;
+    const double L = (double)Lf;
+    int Gn = (int)floor(2.0 * L / rc);
+    Gn = Gn < 1 ? 1 : (Gn > kMaxNearCells ? kMaxNearCells : Gn);
+    g->L = L;
+    g->h = 2.0 * L / G;
+    g->hn = 2.0 * L / Gn;
+    g->Gn = Gn;
+}
+
+__device__ __forceinline__ int cell1(double x, double L, double h, int G) {
+    int c = (int)floor((x + L) / h);
+    return c < 0 ? 0 : (c > G - 1 ? G - 1 : c);
+}
+
+// ---- near cell list ------------------------------------------------------
+
+__global__ __launch_bounds__(kB) void k_near_keys(const float4* __restrict__ pos, int n,
+                                                  int n_pow2, const FFGrid* g,
+                                                  unsigned long long* keys) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n_pow2) return;
+    if (s >= n) {
+        keys[s] = ~0ull;
+        return;
+    }
+    const float4 h = pos[s];
+    const int Gn = g->Gn;
+    const int cx = cell1(h.x, g->L, g->hn, Gn), cy = cell1(h.y, g->L, g->hn, Gn),
+              cz = cell1(h.z, g->L, g->hn, Gn);
+    const unsigned c = (unsigned)((cz * Gn + cy) * Gn + cx);
+    keys[s] = ((unsigned long long)c << 32) | (unsigned)s;
+}
+
+__global__ __launch_bounds__(kB) void k_zero_i(int* a, int m) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k < m) a[k] = 0;
+}
+
+__global__ __launch_bounds__(kB) void k_zero_d(double* a, int m) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k < m) a[k] = 0.0;
+}
+
+__global__ __launch_bounds__(kB) void k_cell_ranges(const unsigned long long* __restrict__ keys,
+                                                    int n, int* cstart, int* cend) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    const unsigned c = (unsigned)(keys[s] >> 32);
+    if (s == 0 || (unsigned)(keys[s - 1] >> 32) != c) cstart[c] = s;
+    if (s == n - 1 || (unsigned)(keys[s + 1] >> 32) != c) cend[c] = s + 1;
+}
+
+// Exact pair forces of all pairs closer than rc (the near field), FP32 pair
+// terms in 32-term blocks, FP64 totals.  Slots are in cell order.
+__global__ __launch_bounds__(kB) void k_near(const float4* __restrict__ pos,
+                                             const int* __restrict__ typ, int n,
+                                             const FFGrid* g, const int* __restrict__ cstart,
+                                             const int* __restrict__ cend, float rc2,
+                                             PairTable tab, double* F) {
+    __shared__ float ttab[4 * kMaxTypes * kMaxTypes];
+    for (int k = threadIdx.x; k < kMaxTypes * kMaxTypes; k += kB) {
+        ttab[k] = tab.sig2[k];
+        ttab[kMaxTypes * kMaxTypes + k] = tab.rc2[k];
+        ttab[2 * kMaxTypes * kMaxTypes + k] = tab.e24[k];
+    }
+    __syncthreads();
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= n) return;
+    const float4 pi = pos[i];
+    const int ti = typ[i];
+    const int T = tab.T;
+    const int Gn = g->Gn;
+    const int cx = cell1(pi.x, g->L, g->hn, Gn), cy = cell1(pi.y, g->L, g->hn, Gn),
+              cz = cell1(pi.z, g->L, g->hn, Gn);
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, Lx = 0.0, Ly = 0.0, Lz = 0.0;
+    float bx = 0.f, by = 0.f, bz = 0.f;
+    int cnt = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z = cz + dz;
+        if (z < 0 || z >= Gn) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yv = cy + dy;
+            if (yv < 0 || yv >= Gn) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int xv = cx + dx;
+                if (xv < 0 || xv >= Gn) continue;
+                const int c = (z * Gn + yv) * Gn + xv;
+                const int j1 = cend[c];
+                for (int j = cstart[c]; j < j1; ++j) {
+                    if (j == i) continue;
+                    const float4 pj = pos[j];
+                    const float ddx = pj.x - pi.x, ddy = pj.y - pi.y, ddz = pj.z - pi.z;
+                    const float r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+                    if (r2 >= rc2) continue;
+                    const float ri = __builtin_amdgcn_rsqf(r2);
+                    const float w = (pj.w * ri) * (ri * ri);
+                    bx = fmaf(w, ddx, bx);
+                    by = fmaf(w, ddy, by);
+                    bz = fmaf(w, ddz, bz);
+                    const int pidx = ti * T + typ[j];
+                    if (r2 < ttab[kMaxTypes * kMaxTypes + pidx]) {
+                        const float ir2 = 1.0f / r2;
+                        const float s2 = ttab[pidx] * ir2;
+                        const float s6 = s2 * s2 * s2;
+                        const float gg =
+                            ttab[2 * kMaxTypes * kMaxTypes + pidx] * s6 * (2.0f * s6 - 1.0f) * ir2;
+                        Lx += (double)(gg * ddx);
+                        Ly += (double)(gg * ddy);
+                        Lz += (double)(gg * ddz);
+                    }
+                    if (++cnt == 32) {
+                        Fx += (double)bx; Fy += (double)by; Fz += (double)bz;
+                        bx = by = bz = 0.f;
+                        cnt = 0;
+                    }
+                }
+            }
+        }
+    }
+    Fx += (double)bx; Fy += (double)by; Fz += (double)bz;
+    const double qi = (double)pi.w;
+    F[i] = -qi * Fx - Lx;
+    F[(size_t)n + i] = -qi * Fy - Ly;
+    F[2 * (size_t)n + i] = -qi * Fz - Lz;
+}
+
+// ---- moments, occupancy, coarse field -----------------------------------
+
+__global__ __launch_bounds__(kB) void k_moments(const float4* __restrict__ pos,
+                                                const float4* __restrict__ lo, int n, int G,
+                                                const FFGrid* g, double* mom, int* count) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    const float4 h = pos[s], l = lo[s];
+    const double x = (double)h.x + (double)l.x, y = (double)h.y + (double)l.y,
+                 z = (double)h.z + (double)l.z;
+    const double L = g->L, hh = g->h;
+    const int cx = cell1(x, L, hh, G), cy = cell1(y, L, hh, G), cz = cell1(z, L, hh, G);
+    const int c = (cz * G + cy) * G + cx;
+    const double q = (double)h.w;
+    atomicAdd(&mom[4 * c], q);
+    atomicAdd(&mom[4 * c + 1], q * (x - (-L + (cx + 0.5) * hh)));
+    atomicAdd(&mom[4 * c + 2], q * (y - (-L + (cy + 0.5) * hh)));
+    atomicAdd(&mom[4 * c + 3], q * (z - (-L + (cz + 0.5) * hh)));
+    atomicAdd(&count[c], 1);
+}
+
+// Deterministic compaction of occupied cells (one workgroup of 1024).
+__global__ __launch_bounds__(1024) void k_compact(const int* __restrict__ count, int M, int* occ,
+                                                  int* cell2occ, int* nocc) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (M + 1023) / 1024;
+    const int c0 = t * per, c1 = min(M, c0 + per);
+    int mine = 0;
+    for (int c = c0; c < c1; ++c) mine += count[c] > 0;
+    part[t] = mine;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {     // inclusive scan (Hillis-Steele)
+        const int v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int k = part[t] - mine;
+    for (int c = c0; c < c1; ++c) {
+        if (count[c] > 0) {
+            occ[k] = c;
+            cell2occ[c] = k++;
+        } else {
+            cell2occ[c] = -1;
+        }
+    }
+    if (t == 1023) *nocc = part[1023];
+}
+
+// Field at every occupied cell centre from the monopole + dipole of every
+// occupied cell outside its B^3 block.  FP32 terms, FP64 totals.
+__global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
+                                               const int* __restrict__ occ,
+                                               const int* __restrict__ nocc, int G, int B,
+                                               const FFGrid* g, double* E) {
+    __shared__ float4 sm[kB];
+    __shared__ int sc[kB];
+    const int no = *nocc;
+    const int t = blockIdx.x * kB + threadIdx.x;
+    const bool live = t < no;
+    const int tc = live ? occ[t] : 0;
+    const int tx = tc % G, ty = (tc / G) % G, tz = tc / (G * G);
+    const float h = (float)g->h;
+    const int half = B / 2;
+    double Ex = 0.0, Ey = 0.0, Ez = 0.0;
+    for (int j0 = 0; j0 < no; j0 += kB) {
+        __syncthreads();
+        const int j = j0 + threadIdx.x;
+        if (j < no) {
+            const int c = occ[j];
+            sm[threadIdx.x] = make_float4((float)mom[4 * c], (float)mom[4 * c + 1],
+                                          (float)mom[4 * c + 2], (float)mom[4 * c + 3]);
+            sc[threadIdx.x] = c;
+        }
+        __syncthreads();
+        const int m = min(kB, no - j0);
+        float ex = 0.f, ey = 0.f, ez = 0.f;
+        for (int k = 0; k < m; ++k) {
+            const int c = sc[k];
+            const int sx = c % G, sy = (c / G) % G, sz = c / (G * G);
+            if (abs(sx - tx) <= half && abs(sy - ty) <= half && abs(sz - tz) <= half) continue;
+            const float4 q = sm[k];
+            const float rx = (float)(tx - sx) * h, ry = (float)(ty - sy) * h,
+                        rz = (float)(tz - sz) * h;
+            const float r2 = rx * rx + ry * ry + rz * rz;
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float ri2 = ri * ri, ri3 = ri2 * ri;
+            const float pr3 = 3.0f * (q.y * rx + q.z * ry + q.w * rz) * ri2;
+            ex += (q.x * rx + pr3 * rx - q.y) * ri3;
+            ey += (q.x * ry + pr3 * ry - q.z) * ri3;
+            ez += (q.x * rz + pr3 * rz - q.w) * ri3;
+        }
+        Ex += (double)ex; Ey += (double)ey; Ez += (double)ez;
+    }
+    if (live) {
+        E[3 * tc] = Ex;
+        E[3 * tc + 1] = Ey;
+        E[3 * tc + 2] = Ez;
+    }
+}
+
+// Moment rows of the B^3 block around each occupied cell (first 4 B^3
+// features of every particle in that cell), zero-padded to Kp.
+__global__ __launch_bounds__(kB) void k_cell_features(const double* __restrict__ mom,
+                                                      const int* __restrict__ occ,
+                                                      const int* __restrict__ nocc, int G, int B,
+                                                      const FFGrid* g, float sq, int Kp,
+                                                      float* Xc) {
+    const int oc = blockIdx.x;
+    if (oc >= *nocc) return;
+    const int c = occ[oc];
+    const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+    const int half = B / 2;
+    const double sh = (double)sq * g->h;
+    float* row = Xc + (size_t)oc * Kp;
+    for (int f = threadIdx.x; f < Kp; f += kB) {
+        float v = 0.f;
+        if (f < 4 * B * B * B) {
+            const int cell = f / 4, comp = f % 4;
+            const int dx = cell % B - half, dy = (cell / B) % B - half, dz = cell / (B * B) - half;
+            const int x = cx + dx, y = cy + dy, z = cz + dz;
+            if (x >= 0 && y >= 0 && z >= 0 && x < G && y < G && z < G) {
+                const double m = mom[4 * ((z * G + y) * G + x) + comp];
+                v = (float)(comp == 0 ? m / sq : m / sh);
+            }
+        }
+        row[f] = v;
+    }
+}
+
+__device__ __forceinline__ void particle_cell(const float4 h, const float4 l, int G,
+                                              const FFGrid* g, int* c, float off[3]) {
+    const double x = (double)h.x + (double)l.x, y = (double)h.y + (double)l.y,
+                 z = (double)h.z + (double)l.z;
+    const double L = g->L, hh = g->h;
+    const int cx = cell1(x, L, hh, G), cy = cell1(y, L, hh, G), cz = cell1(z, L, hh, G);
+    *c = (cz * G + cy) * G + cx;
+    off[0] = (float)((x - (-L + (cx + 0.5) * hh)) / hh);
+    off[1] = (float)((y - (-L + (cy + 0.5) * hh)) / hh);
+    off[2] = (float)((z - (-L + (cz + 0.5) * hh)) / hh);
+}
+
+// First layer finished per particle: z1 = A_cell + W1[offset rows] o + b1.
+__global__ __launch_bounds__(kB) void k_layer1(const float4* __restrict__ pos,
+                                               const float4* __restrict__ lo, int n, int G,
+                                               const FFGrid* g, const int* __restrict__ cell2occ,
+                                               const float* __restrict__ Ac,
+                                               const float* __restrict__ W1o,
+                                               const float* __restrict__ b1, int H, float* h1) {
+    const int s = blockIdx.x;
+    if (s >= n) return;
+    int c;
+    float off[3];
+    particle_cell(pos[s], lo[s], G, g, &c, off);
+    const int oc = cell2occ[c];
+    if (oc < 0) {   // cannot happen: the particle's own cell is occupied
+        for (int j = threadIdx.x; j < H; j += kB) h1[(size_t)s * H + j] = 0.f;
+        return;
+    }
+    const float o0 = bf16_round(off[0]), o1 = bf16_round(off[1]), o2 = bf16_round(off[2]);
+    for (int j = threadIdx.x; j < H; j += kB) {
+        const float z = Ac[(size_t)oc * H + j] + o0 * bf16_round(W1o[j]) +
+                        o1 * bf16_round(W1o[H + j]) + o2 * bf16_round(W1o[2 * H + j]) + b1[j];
+        h1[(size_t)s * H + j] = silu_f(z);
+    }
+}
+
+// F = F_near + q (E_cell + scale y) into Fpart (slot order) and optional parts.
+__global__ __launch_bounds__(kB) void k_combine(const float4* __restrict__ pos,
+                                                const float4* __restrict__ lo, int n, int G,
+                                                const FFGrid* g, const double* __restrict__ Fn,
+                                                const double* __restrict__ Ecell,
+                                                const float* __restrict__ y, int Op, float scale,
+                                                double* Fpart, double* Fc, double* Fm) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    const float4 h = pos[s];
+    int c;
+    float off[3];
+    particle_cell(h, lo[s], G, g, &c, off);
+    const double q = (double)h.w;
+    for (int k = 0; k < 3; ++k) {
+        const double ec = q * Ecell[3 * c + k];
+        const double em = q * (double)scale * (double)y[(size_t)s * Op + k];
+        Fpart[(size_t)k * n + s] = Fn[(size_t)k * n + s] + ec + em;
+        if (Fc) Fc[(size_t)k * n + s] = ec;
+        if (Fm) Fm[(size_t)k * n + s] = em;
+    }
+}
+
+// Exact far field sum_{j: r >= rc} q_j (x_i - x_j) / r^3 (no q_i factor).
+__global__ __launch_bounds__(kB) void k_far_exact(const float4* __restrict__ pos, int n,
+                                                  float rc2, double* E) {
+    __shared__ float4 sp[kB];
+    const int i = blockIdx.x * kB + threadIdx.x;
+    const float4 pi = i < n ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    double Ex = 0.0, Ey = 0.0, Ez = 0.0;
+    for (int j0 = 0; j0 < n; j0 += kB) {
+        __syncthreads();
+        const int j = j0 + threadIdx.x;
+        sp[threadIdx.x] = j < n ? pos[j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+        __syncthreads();
+        float ex = 0.f, ey = 0.f, ez = 0.f;
+#pragma unroll 8
+        for (int k = 0; k < kB; ++k) {
+            const float4 pj = sp[k];
+            const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float w = r2 >= rc2 ? (pj.w * ri) * (ri * ri) : 0.f;
+            ex = fmaf(w, dx, ex);
+            ey = fmaf(w, dy, ey);
+            ez = fmaf(w, dz, ez);
+        }
+        Ex += (double)ex; Ey += (double)ey; Ez += (double)ez;
+    }
+    if (i < n) {
+        E[i] = -Ex;
+        E[(size_t)n + i] = -Ey;
+        E[2 * (size_t)n + i] = -Ez;
+    }
+}
+
+// Training samples of the current snapshot: (snapshot, cell, offset,
+// target = E_far - E_cell) appended at base.
+__global__ __launch_bounds__(kB) void k_collect(const float4* __restrict__ pos,
+                                                const float4* __restrict__ lo, int n, int G,
+                                                const FFGrid* g, const double* __restrict__ Efar,
+                                                const double* __restrict__ Ecell, int snap,
+                                                int64_t base, int* s_snap, int* s_cell,
+                                                float* s_off, float* s_tgt) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    int c;
+    float off[3];
+    particle_cell(pos[s], lo[s], G, g, &c, off);
+    const int64_t k = base + s;
+    s_snap[k] = snap;
+    s_cell[k] = c;
+    for (int d = 0; d < 3; ++d) {
+        s_off[3 * k + d] = off[d];
+        s_tgt[3 * k + d] = (float)(Efar[(size_t)d * n + s] - Ecell[3 * c + d]);
+    }
+}
+
+// Normalised moment grid of a snapshot (for feature gathers at train time).
+__global__ __launch_bounds__(kB) void k_snap_mom(const double* __restrict__ mom, int M,
+                                                 const FFGrid* g, float sq, float* out) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k >= 4 * M) return;
+    const double sh = (double)sq * g->h;
+    out[k] = (float)((k % 4 == 0) ? mom[k] / sq : mom[k] / sh);
+}
+
+// Batch features and scaled targets from the sample store.
+__global__ __launch_bounds__(kB) void k_gather_batch(const int* __restrict__ idx, int B_,
+                                                     const int* __restrict__ s_snap,
+                                                     const int* __restrict__ s_cell,
+                                                     const float* __restrict__ s_off,
+                                                     const float* __restrict__ s_tgt,
+                                                     const float* __restrict__ snap_mom, int G,
+                                                     int Bk, int Kp, float inv_scale, float* X,
+                                                     float* T) {
+    const int b = blockIdx.x;
+    if (b >= B_) return;
+    const int64_t k = idx[b];
+    const int snap = s_snap[k], c = s_cell[k];
+    const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+    const int half = Bk / 2;
+    const float* mg = snap_mom + (size_t)snap * 4 * G * G * G;
+    float* row = X + (size_t)b * Kp;
+    const int nm = 4 * Bk * Bk * Bk;
+    for (int f = threadIdx.x; f < Kp; f += kB) {
+        float v = 0.f;
+        if (f < nm) {
+            const int cell = f / 4, comp = f % 4;
+            const int x = cx + cell % Bk - half, y = cy + (cell / Bk) % Bk - half,
+                      z = cz + cell / (Bk * Bk) - half;
+            if (x >= 0 && y >= 0 && z >= 0 && x < G && y < G && z < G)
+                v = mg[4 * ((z * G + y) * G + x) + comp];
+        } else if (f < nm + 3) {
+            v = s_off[3 * k + (f - nm)];
+        }
+        row[f] = v;
+    }
+    if (threadIdx.x < 3) T[3 * b + threadIdx.x] = s_tgt[3 * k + threadIdx.x] * inv_scale;
+}
+
+// Copy rows of m x K features (host layout, K = 4B^3+3) into a Kp-wide buffer.
+__global__ __launch_bounds__(kB) void k_pad_rows(const float* __restrict__ X, int m, int K,
+                                                 int Kp, float* out) {
+    const int r = blockIdx.x;
+    if (r >= m) return;
+    for (int f = threadIdx.x; f < Kp; f += kB) out[(size_t)r * Kp + f] = f < K ? X[(size_t)r * K + f] : 0.f;
+}
+
+// F = q E (slot order [3][n]).
+__global__ __launch_bounds__(kB) void k_q_times(const float4* __restrict__ pos, int n,
+                                                const double* __restrict__ E, double* F) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    const double q = (double)pos[s].w;
+    for (int k = 0; k < 3; ++k) F[(size_t)k * n + s] = q * E[(size_t)k * n + s];
+}
+
+__global__ __launch_bounds__(kB) void k_rel_err(const double* __restrict__ Fa,
+                                                const double* __restrict__ Fb, int n,
+                                                double* rel) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    double d2 = 0.0, b2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double a = Fa[(size_t)k * n + s], b = Fb[(size_t)k * n + s];
+        d2 += (a - b) * (a - b);
+        b2 += b * b;
+    }
+    rel[s] = b2 > 0.0 ? sqrt(d2 / b2) : (d2 > 0.0 ? INFINITY : 0.0);
+}
+
+__global__ __launch_bounds__(kB) void k_sum_parts(const double* __restrict__ F, int parts, int n,
+                                                  double* out) {
+    const int e = blockIdx.x * kB + threadIdx.x;
+    if (e >= 3 * n) return;
+    double v = 0.0;
+    for (int p = 0; p < parts; ++p) v += F[(size_t)p * 3 * n + e];
+    out[e] = v;
+}
+
+__global__ __launch_bounds__(kB) void k_to_orig(const double* __restrict__ F, const int* oid,
+                                                int n, double* out) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    const size_t o = (size_t)oid[s];
+    for (int k = 0; k < 3; ++k) out[3 * o + k] = F[(size_t)k * n + s];
+}
+
+// ---- host side ------------------------------------------------------------
+
+FarField* FF(ld_ctx* c) { return c->ff; }
+
+template <class T>
+bool dalloc(T** p, size_t count) {
+    return hipMalloc(p, sizeof(T) * (count > 0 ? count : 1)) == hipSuccess;
+}
+
+void ff_free_bufs(FarField* f) {
+    void* b[] = {f->grid, f->cstart, f->cend, f->Fnear, f->mom, f->count, f->occ, f->cell2occ,
+                 f->nocc, f->Ecell, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->grad, f->adam_m,
+                 f->adam_v, f->rel, f->Efar, f->snap_mom, f->s_snap, f->s_cell, f->s_off,
+                 f->s_tgt, f->bX, f->bT, f->bZ1, f->bA1, f->bZ2, f->bA2, f->bY, f->bdY, f->bd2,
+                 f->bd1, f->bidx, f->loss_part};
+    for (void* p : b)
+        if (p) (void)hipFree(p);
+}
+
+#define KLAUNCH(kernel, grid, block, ...)                                                 \
+    do {                                                                                  \
+        hipLaunchKernelGGL(kernel, grid, block, 0, __VA_ARGS__);                          \
+        HIP_TRY(hipGetLastError());                                                       \
+    } while (0)
+
+// Grid, moments, occupancy and coarse field at the current positions.
+ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
+    FarField* f = FF(c);
+    const int n = (int)c->n;
+    const int G = f->cfg.grid, M = G * G * G;
+    KLAUNCH(k_absmax_part, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
+    KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, f->cfg.near_cut, G, f->grid);
+    KLAUNCH(k_zero_d, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, 4 * M);
+    KLAUNCH(k_zero_i, dim3((M + kB - 1) / kB), dim3(kB), s, f->count, M);
+    KLAUNCH(k_moments, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid, f->mom,
+            f->count);
+    KLAUNCH(k_compact, dim3(1), dim3(1024), s, f->count, M, f->occ, f->cell2occ, f->nocc);
+    KLAUNCH(k_coarse, dim3((M + kB - 1) / kB), dim3(kB), s, f->mom, f->occ, f->nocc, G,
+            f->cfg.block, f->grid, f->Ecell);
+    return LD_OK;
+}
+
+// Near cell list (re-sorts the slots by cell) and the exact near forces.
+ld_status ff_near(ld_ctx* c, hipStream_t s) {
+    FarField* f = FF(c);
+    const int n = (int)c->n;
+    KLAUNCH(k_absmax_part, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
+    KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, f->cfg.near_cut, f->cfg.grid,
+            f->grid);
+    KLAUNCH(k_near_keys, dim3((c->sb.n_pow2 + kB - 1) / kB), dim3(kB), s, c->pos, n, c->sb.n_pow2,
+            f->grid, c->sb.keys);
+    HIP_TRY(ld::launch_sort_by_keys(c->pos, c->lo, c->typ, c->oid, n, c->sb, s));
+    const int NC = kMaxNearCells * kMaxNearCells * kMaxNearCells;
+    KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cstart, NC);
+    KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cend, NC);
+    KLAUNCH(k_cell_ranges, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, f->cstart, f->cend);
+    const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
+    KLAUNCH(k_near, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->typ, n, f->grid, f->cstart,
+            f->cend, rc2, c->tab, f->Fnear);
+    c->steps_since_sort = 0;
+    return LD_OK;
+}
+
+ld_status gemm(hipStream_t s, const float* A, int lda, int tA, const float* B, int ldb, int tB,
+               float* C, int ldc, int M, int N, int K, const float* bias, int act, float* Z,
+               int ldz, int acc, const int* M_dev) {
+    ld::GemmArgs g{};
+    g.A = A; g.lda = lda; g.transA = tA;
+    g.B = B; g.ldb = ldb; g.transB = tB;
+    g.C = C; g.ldc = ldc;
+    g.bias = bias; g.Z = Z; g.ldz = ldz;
+    g.M = M; g.N = N; g.K = K;
+    g.act = act; g.accumulate = acc; g.M_dev = M_dev;
+    HIP_TRY(ld::launch_gemm(g, s));
+    return LD_OK;
+}
+
+// The learned pair forces of every slot into Fpart[0] (and optional parts).
+ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
+    FarField* f = FF(c);
+    const int n = (int)c->n;
+    const int G = f->cfg.grid, M = G * G * G, H = f->H;
+    ld_status st = ff_near(c, s);
+    if (st != LD_OK) return st;
+    st = ff_grid_and_coarse(c, s);
+    if (st != LD_OK) return st;
+    KLAUNCH(k_cell_features, dim3(M), dim3(kB), s, f->mom, f->occ, f->nocc, G, f->cfg.block,
+            f->grid, f->sq, f->Kp, f->Xc);
+    // layer 1, moment part, once per occupied cell (no bias: added per particle)
+    st = gemm(s, f->Xc, f->Kp, 0, f->W + f->offW1, H, 0, f->Ac, H, M, H, f->Kp, nullptr, 0,
+              nullptr, 0, 0, f->nocc);
+    if (st != LD_OK) return st;
+    KLAUNCH(k_layer1, dim3(n), dim3(kB), s, c->pos, c->lo, n, G, f->grid, f->cell2occ, f->Ac,
+            f->W + f->offW1 + (size_t)(f->K - 3) * H, f->W + f->offb1, H, f->h1);
+    st = gemm(s, f->h1, H, 0, f->W + f->offW2, H, 0, f->h2, H, n, H, H, f->W + f->offb2, 1,
+              nullptr, 0, 0, nullptr);
+    if (st != LD_OK) return st;
+    st = gemm(s, f->h2, H, 0, f->W + f->offW3, f->Op, 0, f->y, f->Op, n, f->Op, H,
+              f->W + f->offb3, 0, nullptr, 0, 0, nullptr);
+    if (st != LD_OK) return st;
+    KLAUNCH(k_combine, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid,
+            f->Fnear, f->Ecell, f->y, f->Op, f->out_scale, c->Fpart, Fc, Fm);
+    HIP_TRY(ld::launch_boxes(c->pos, n, c->box, s));
+    return LD_OK;
+}
+
+// Direct pair forces summed into one slot-order array dst [3][n].
+ld_status ff_direct_total(ld_ctx* c, hipStream_t s, double* dst) {
+    ld::PairLaunch L{};
+    L.pos = c->pos; L.typ = c->typ; L.box = c->box; L.n = (int)c->n;
+    L.block = c->tune.block; L.j_split = c->tune.j_split; L.comp = c->tune.comp;
+    L.cull = c->tune.cull; L.Fpart = c->Fpart;
+    HIP_TRY(ld::launch_pair(L, c->tab, s));
+    KLAUNCH(k_sum_parts, dim3((3 * (int)c->n + kB - 1) / kB), dim3(kB), s, c->Fpart,
+            c->tune.j_split, (int)c->n, dst);
+    return LD_OK;
+}
+
+// Median relative error of the learned pair forces against direct summation.
+ld_status ff_judge_now(ld_ctx* c, double* med) {
+    FarField* f = FF(c);
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    ld_status st = ff_learned_forces(c, s, nullptr, nullptr);   // re-sorts, Fpart[0]
+    if (st != LD_OK) return st;
+    double* Fl = c->work;                  // [3][n]
+    double* Fd = c->work + 3 * (size_t)n;  // [3][n]
+    HIP_TRY(hipMemcpyAsync(Fl, c->Fpart, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    st = ff_direct_total(c, s, Fd);
+    if (st != LD_OK) return st;
+    KLAUNCH(k_rel_err, dim3((n + kB - 1) / kB), dim3(kB), s, Fl, Fd, n, f->rel);
+    std::vector<double> h(n);
+    HIP_TRY(hipMemcpyAsync(h.data(), f->rel, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::nth_element(h.begin(), h.begin() + n / 2, h.end());
+    *med = h[n / 2];
+    f->last_err = *med;
+    ++f->judges;
+    return LD_OK;
+}
+
+void init_layout(FarField* f) {
+    const int B = f->cfg.block;
+    f->H = f->cfg.hidden;
+    f->K = 4 * B * B * B + 3;
+    f->Kp = (f->K + 31) / 32 * 32;
+    f->Op = 16;
+    size_t o = 0;
+    f->offW1 = o; o += (size_t)f->Kp * f->H;
+    f->offb1 = o; o += f->H;
+    f->offW2 = o; o += (size_t)f->H * f->H;
+    f->offb2 = o; o += f->H;
+    f->offW3 = o; o += (size_t)f->H * f->Op;
+    f->offb3 = o; o += f->Op;
+    f->nW = o;
+}
+
+ld_status ensure_batch(FarField* f, int B_) {
+    if (B_ <= f->batch_cap) return LD_OK;
+    float** bufs[] = {&f->bX, &f->bT, &f->bZ1, &f->bA1, &f->bZ2, &f->bA2, &f->bY, &f->bdY,
+                      &f->bd2, &f->bd1};
+    for (float** b : bufs)
+        if (*b) { (void)hipFree(*b); *b = nullptr; }
+    if (f->bidx) { (void)hipFree(f->bidx); f->bidx = nullptr; }
+    if (f->loss_part) { (void)hipFree(f->loss_part); f->loss_part = nullptr; }
+    const size_t H = f->H;
+    bool ok = dalloc(&f->bX, (size_t)B_ * f->Kp) && dalloc(&f->bT, (size_t)B_ * 3) &&
+              dalloc(&f->bZ1, B_ * H) && dalloc(&f->bA1, B_ * H) && dalloc(&f->bZ2, B_ * H) &&
+              dalloc(&f->bA2, B_ * H) && dalloc(&f->bY, (size_t)B_ * f->Op) &&
+              dalloc(&f->bdY, (size_t)B_ * f->Op) && dalloc(&f->bd2, B_ * H) &&
+              dalloc(&f->bd1, B_ * H) && dalloc(&f->bidx, (size_t)B_) &&
+              dalloc(&f->loss_part, (size_t)B_ * f->Op / kB + 8);
+    if (!ok) return fail(LD_ENOMEM, "cannot allocate training batch of %d", B_);
+    f->batch_cap = B_;
+    return LD_OK;
+}
+
+// Forward (saving activations) + loss + backward into f->grad for the batch
+// in bX / bT (B_ rows, targets already scaled).  Returns the loss.
+ld_status fwd_bwd(FarField* f, int B_, hipStream_t s, double* loss) {
+    const int H = f->H, Op = f->Op, Kp = f->Kp;
+    float* W = f->W;
+    float* gW = f->grad;
+    ld_status st;
+#define TRY(x) do { st = (x); if (st != LD_OK) return st; } while (0)
+    TRY(gemm(s, f->bX, Kp, 0, W + f->offW1, H, 0, f->bA1, H, B_, H, Kp, W + f->offb1, 1, f->bZ1,
+             H, 0, nullptr));
+    TRY(gemm(s, f->bA1, H, 0, W + f->offW2, H, 0, f->bA2, H, B_, H, H, W + f->offb2, 1, f->bZ2,
+             H, 0, nullptr));
+    TRY(gemm(s, f->bA2, H, 0, W + f->offW3, Op, 0, f->bY, Op, B_, Op, H, W + f->offb3, 0,
+             nullptr, 0, 0, nullptr));
+    int nparts = 0;
+    HIP_TRY(ld::launch_mse(f->bY, Op, f->bT, B_, 3, f->bdY, f->loss_part, &nparts, s));
+    // layer 3
+    TRY(gemm(s, f->bA2, H, 1, f->bdY, Op, 0, gW + f->offW3, Op, H, Op, B_, nullptr, 0, nullptr, 0,
+             0, nullptr));
+    HIP_TRY(ld::launch_colsum(f->bdY, B_, Op, gW + f->offb3, s));
+    TRY(gemm(s, f->bdY, Op, 0, W + f->offW3, Op, 1, f->bd2, H, B_, H, Op, nullptr, 0, nullptr, 0,
+             0, nullptr));
+    HIP_TRY(ld::launch_silu_bwd(f->bZ2, f->bd2, B_, H, nullptr, s));
+    // layer 2
+    TRY(gemm(s, f->bA1, H, 1, f->bd2, H, 0, gW + f->offW2, H, H, H, B_, nullptr, 0, nullptr, 0, 0,
+             nullptr));
+    HIP_TRY(ld::launch_colsum(f->bd2, B_, H, gW + f->offb2, s));
+    TRY(gemm(s, f->bd2, H, 0, W + f->offW2, H, 1, f->bd1, H, B_, H, H, nullptr, 0, nullptr, 0, 0,
+             nullptr));
+    HIP_TRY(ld::launch_silu_bwd(f->bZ1, f->bd1, B_, H, nullptr, s));
+    // layer 1
+    TRY(gemm(s, f->bX, Kp, 1, f->bd1, H, 0, gW + f->offW1, H, Kp, H, B_, nullptr, 0, nullptr, 0, 0,
+             nullptr));
+    HIP_TRY(ld::launch_colsum(f->bd1, B_, H, gW + f->offb1, s));
+#undef TRY
+    if (loss) {
+        std::vector<double> parts(nparts);
+        HIP_TRY(hipMemcpyAsync(parts.data(), f->loss_part, sizeof(double) * nparts,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double l = 0.0;
+        for (double v : parts) l += v;
+        *loss = l;
+    }
+    return LD_OK;
+}
+
+// Philox4x32-10 on the host for training shuffles (stream tag 3).
+uint32_t philox_word(uint64_t seed, uint64_t ctr, int word) {
+    uint32_t c0 = (uint32_t)ctr, c1 = (uint32_t)(ctr >> 32), c2 = 0u, c3 = 3u;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    const uint32_t w[4] = {c0, c1, c2, c3};
+    return w[word & 3];
+}
+
+}  // namespace
+
+namespace ld {
+
+void ff_free(ld_ctx* c) {
+    if (!c->ff) return;
+    ff_free_bufs(c->ff);
+    delete c->ff;
+    c->ff = nullptr;
+}
+
+bool ff_active(const ld_ctx* c) { return c->ff && c->ff->mode != 0; }
+
+ld_status ff_step_forces(ld_ctx* c, hipStream_t s, int* j_split_used) {
+    FarField* f = c->ff;
+    if (f->mode == 2 && f->window_steps % f->cfg.judge_every == 0) {
+        double med = 0.0;
+        ld_status st = ff_judge_now(c, &med);
+        if (st != LD_OK) return st;
+        f->active = med <= f->cfg.judge_tol;
+        if (!f->active) ++f->fallbacks;
+    }
+    ++f->window_steps;
+    if (f->mode == 1 || f->active) {
+        ld_status st = ff_learned_forces(c, s, nullptr, nullptr);
+        if (st != LD_OK) return st;
+        *j_split_used = 1;
+        ++f->learned_steps;
+    } else {
+        ld::PairLaunch L{};
+        L.pos = c->pos; L.typ = c->typ; L.box = c->box; L.n = (int)c->n;
+        L.block = c->tune.block; L.j_split = c->tune.j_split; L.comp = c->tune.comp;
+        L.cull = c->tune.cull; L.Fpart = c->Fpart;
+        HIP_TRY(ld::launch_pair(L, c->tab, s));
+        *j_split_used = c->tune.j_split;
+        ++f->direct_steps;
+    }
+    return LD_OK;
+}
+
+}  // namespace ld
+
+extern "C" {
+
+ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
+    g_err.clear();
+    if (!c || !cfg) return fail(LD_EINVAL, "ctx and cfg are required");
+    if (!(cfg->near_cut > 0.0)) return fail(LD_EINVAL, "near_cut must be positive");
+    if (cfg->grid < 4 || cfg->grid > 64) return fail(LD_EINVAL, "grid must be in [4, 64]");
+    if (cfg->block < 1 || cfg->block > 7 || cfg->block % 2 == 0)
+        return fail(LD_EINVAL, "block must be odd, 1..7");
+    if (cfg->hidden < 16 || cfg->hidden > 256 || cfg->hidden % 16)
+        return fail(LD_EINVAL, "hidden must be a multiple of 16 in [16, 256]");
+    if (cfg->judge_every < 1) return fail(LD_EINVAL, "judge_every must be >= 1");
+    if (!(cfg->judge_tol > 0.0)) return fail(LD_EINVAL, "judge_tol must be positive");
+    double maxlj = 0.0;
+    for (int a = 0; a < c->p.n_types; ++a)
+        for (int b = 0; b < c->p.n_types; ++b)
+            maxlj = std::max(maxlj, c->p.lj_cut * 0.5 * (c->p.sigma[a] + c->p.sigma[b]));
+    if (cfg->near_cut < maxlj)
+        return fail(LD_EINVAL, "near_cut %.3g is below the largest LJ range %.3g", cfg->near_cut,
+                    maxlj);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    ld::ff_free(c);
+    FarField* f = new (std::nothrow) FarField();
+    if (!f) return fail(LD_ENOMEM, "host allocation failed");
+    f->cfg = *cfg;
+    init_layout(f);
+    const size_t n = (size_t)c->n;
+    const size_t M = (size_t)cfg->grid * cfg->grid * cfg->grid;
+    const size_t NC = (size_t)kMaxNearCells * kMaxNearCells * kMaxNearCells;
+    double qmax = 0.0;
+    {
+        std::vector<float4> h(n);
+        HIP_TRY(hipMemcpy(h.data(), c->pos, sizeof(float4) * n, hipMemcpyDeviceToHost));
+        for (const float4& v : h) qmax = std::max(qmax, (double)std::fabs(v.w));
+    }
+    f->sq = (float)(qmax > 0.0 ? qmax : 1.0);
+    bool ok = dalloc(&f->grid, 1) && dalloc(&f->cstart, NC) && dalloc(&f->cend, NC) &&
+              dalloc(&f->Fnear, 3 * n) && dalloc(&f->mom, 4 * M) && dalloc(&f->count, M) &&
+              dalloc(&f->occ, M) && dalloc(&f->cell2occ, M) && dalloc(&f->nocc, 1) &&
+              dalloc(&f->Ecell, 3 * M) && dalloc(&f->Xc, M * f->Kp) && dalloc(&f->Ac, M * f->H) &&
+              dalloc(&f->h1, n * f->H) && dalloc(&f->h2, n * f->H) && dalloc(&f->y, n * f->Op) &&
+              dalloc(&f->W, f->nW) && dalloc(&f->grad, f->nW) && dalloc(&f->adam_m, f->nW) &&
+              dalloc(&f->adam_v, f->nW) && dalloc(&f->rel, n) && dalloc(&f->Efar, 3 * n);
+    if (!ok) {
+        ff_free_bufs(f);
+        delete f;
+        return fail(LD_ENOMEM, "cannot allocate the learned far field");
+    }
+    // deterministic small initial weights (Philox, tag 3), zero biases
+    std::vector<float> w(f->nW, 0.f);
+    auto init = [&](size_t off, int rows, int valid_rows, int cols, int valid_cols, double sc) {
+        for (int r = 0; r < valid_rows; ++r)
+            for (int q = 0; q < valid_cols; ++q) {
+                const uint64_t k = off + (size_t)r * cols + q;
+                const double u = ((philox_word(0x5EEDull, k, 0) >> 9) + 0.5) / 8388608.0;
+                w[off + (size_t)r * cols + q] = (float)((2.0 * u - 1.0) * sc);
+            }
+        (void)rows;
+    };
+    init(f->offW1, f->Kp, f->K, f->H, f->H, std::sqrt(3.0 / f->K));
+    init(f->offW2, f->H, f->H, f->H, f->H, std::sqrt(3.0 / f->H));
+    init(f->offW3, f->H, f->H, f->Op, 3, std::sqrt(3.0 / f->H) * 0.1);
+    HIP_TRY(hipMemcpy(f->W, w.data(), sizeof(float) * f->nW, hipMemcpyHostToDevice));
+    std::vector<float> zero(f->nW, 0.f);
+    HIP_TRY(hipMemcpy(f->adam_m, zero.data(), sizeof(float) * f->nW, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(f->adam_v, zero.data(), sizeof(float) * f->nW, hipMemcpyHostToDevice));
+    f->out_scale = 1.f;
+    f->mode = 0;
+    c->ff = f;
+    return LD_OK;
+}
+
+ld_status ld_ff_mode(ld_ctx* c, int32_t mode) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    if (mode < 0 || mode > 2) return fail(LD_EINVAL, "mode must be 0, 1 or 2");
+    if (mode != 0 && !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    if (c->ff) {
+        c->ff->mode = mode;
+        c->ff->window_steps = 0;
+        c->ff->active = true;
+    }
+    return LD_OK;
+}
+
+int64_t ld_ff_weights_size(ld_ctx* c) { return (c && c->ff) ? (int64_t)c->ff->nW : 0; }
+
+ld_status ld_ff_set_weights(ld_ctx* c, const float* w, int64_t count, double sq,
+                            double out_scale) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    if (!w || count != (int64_t)c->ff->nW)
+        return fail(LD_EINVAL, "weights need exactly %lld floats", (long long)c->ff->nW);
+    if (!(sq > 0.0) || !(out_scale > 0.0)) return fail(LD_EINVAL, "scales must be positive");
+    HIP_TRY(copy_in(c->ff->W, w, sizeof(float) * count, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->ff->sq = (float)sq;
+    c->ff->out_scale = (float)out_scale;
+    return LD_OK;
+}
+
+ld_status ld_ff_get_weights(ld_ctx* c, float* w, int64_t count, double* sq, double* out_scale) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    if (w) {
+        if (count != (int64_t)c->ff->nW)
+            return fail(LD_EINVAL, "weights need exactly %lld floats", (long long)c->ff->nW);
+        HIP_TRY(copy_out(w, c->ff->W, sizeof(float) * count, c->stream));
+    }
+    if (sq) *sq = c->ff->sq;
+    if (out_scale) *out_scale = c->ff->out_scale;
+    return LD_OK;
+}
+
+ld_status ld_ff_grid(ld_ctx* c, double* L, int32_t* near_cells) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    hipStream_t s = c->stream;
+    KLAUNCH(k_absmax_part, dim3(64), dim3(kB), s, c->pos, (int)c->n, c->sb.bounds_part);
+    KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, c->ff->cfg.near_cut,
+            c->ff->cfg.grid, c->ff->grid);
+    FFGrid g;
+    HIP_TRY(copy_out(&g, c->ff->grid, sizeof g, s));
+    if (L) *L = g.L;
+    if (near_cells) *near_cells = g.Gn;
+    return LD_OK;
+}
+
+ld_status ld_ff_forces(ld_ctx* c, int32_t part, double* out) {
+    g_err.clear();
+    if (!c || !c->ff || !out) return fail(LD_EINVAL, "ctx (with ld_ff_enable) and out required");
+    if (part < 0 || part > 4) return fail(LD_EINVAL, "part must be 0..4");
+    FarField* f = c->ff;
+    hipStream_t s = c->stream;
+    const int n = (int)c->n;
+    double* Fc = c->work;                    // [3][n]
+    double* Fm = c->work + 3 * (size_t)n;    // [3][n]
+    double* dst = c->work + 6 * (size_t)n;   // [3n] original order
+    const double* src = nullptr;
+    if (part == 4) {
+        const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
+        KLAUNCH(k_far_exact, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, rc2, f->Efar);
+        KLAUNCH(k_q_times, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, f->Efar, Fc);
+        src = Fc;
+    } else {
+        ld_status st = ff_learned_forces(c, s, Fc, Fm);
+        if (st != LD_OK) return st;
+        src = part == 0 ? f->Fnear : part == 1 ? Fc : part == 2 ? Fm : c->Fpart;
+    }
+    KLAUNCH(k_to_orig, dim3((n + kB - 1) / kB), dim3(kB), s, src, c->oid, n, dst);
+    HIP_TRY(copy_out(out, dst, sizeof(double) * 3 * n, s));
+    return LD_OK;
+}
+
+ld_status ld_ff_mlp(ld_ctx* c, const float* X, int64_t m, float* Y) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    if (!X || !Y || m < 1 || m > (1 << 22)) return fail(LD_EINVAL, "X, Y and 1 <= m <= 2^22");
+    FarField* f = c->ff;
+    hipStream_t s = c->stream;
+    ld_status st = ensure_batch(f, (int)m);
+    if (st != LD_OK) return st;
+    // stage the caller's m x K rows, then pad to Kp
+    float* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, sizeof(float) * (size_t)m * f->K));
+    hipError_t e = copy_in(tmp, X, sizeof(float) * (size_t)m * f->K, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)m), dim3(kB), 0, s, tmp, (int)m, f->K, f->Kp,
+                           f->bX);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(LD_EHIP, "staging features: %s", hipGetErrorString(e));
+    const int H = f->H, Op = f->Op;
+    st = gemm(s, f->bX, f->Kp, 0, f->W + f->offW1, H, 0, f->bA1, H, (int)m, H, f->Kp,
+              f->W + f->offb1, 1, nullptr, 0, 0, nullptr);
+    if (st == LD_OK)
+        st = gemm(s, f->bA1, H, 0, f->W + f->offW2, H, 0, f->bA2, H, (int)m, H, H, f->W + f->offb2,
+                  1, nullptr, 0, 0, nullptr);
+    if (st == LD_OK)
+        st = gemm(s, f->bA2, H, 0, f->W + f->offW3, Op, 0, f->bY, Op, (int)m, Op, H,
+                  f->W + f->offb3, 0, nullptr, 0, 0, nullptr);
+    if (st != LD_OK) return st;
+    std::vector<float> y((size_t)m * Op), o((size_t)m * 3);
+    HIP_TRY(hipMemcpyAsync(y.data(), f->bY, sizeof(float) * y.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t r = 0; r < m; ++r)
+        for (int k = 0; k < 3; ++k) o[3 * r + k] = y[r * Op + k];
+    HIP_TRY(put_out(Y, o.data(), sizeof(float) * o.size(), s));
+    return LD_OK;
+}
+
+ld_status ld_ff_grads(ld_ctx* c, const float* X, const float* T, int64_t m, float* grads,
+                      double* loss) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    if (!X || !T || !grads || m < 1 || m > (1 << 20))
+        return fail(LD_EINVAL, "X, T, grads and 1 <= m <= 2^20 required");
+    FarField* f = c->ff;
+    hipStream_t s = c->stream;
+    ld_status st = ensure_batch(f, (int)m);
+    if (st != LD_OK) return st;
+    float* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, sizeof(float) * (size_t)m * f->K));
+    hipError_t e = copy_in(tmp, X, sizeof(float) * (size_t)m * f->K, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)m), dim3(kB), 0, s, tmp, (int)m, f->K, f->Kp,
+                           f->bX);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = copy_in(f->bT, T, sizeof(float) * (size_t)m * 3, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(LD_EHIP, "staging batch: %s", hipGetErrorString(e));
+    st = fwd_bwd(f, (int)m, s, loss);
+    if (st != LD_OK) return st;
+    HIP_TRY(copy_out(grads, f->grad, sizeof(float) * f->nW, s));
+    return LD_OK;
+}
+
+ld_status ld_ff_collect(ld_ctx* c, int32_t reset, int32_t max_snapshots) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    FarField* f = c->ff;
+    hipStream_t s = c->stream;
+    const int n = (int)c->n;
+    const int G = f->cfg.grid, M = G * G * G;
+    if (reset || !f->s_snap) {
+        const int cap = std::max(1, max_snapshots);
+        if (f->snap_mom) { (void)hipFree(f->snap_mom); f->snap_mom = nullptr; }
+        int** ib[] = {&f->s_snap, &f->s_cell};
+        for (int** b : ib)
+            if (*b) { (void)hipFree(*b); *b = nullptr; }
+        float** fb[] = {&f->s_off, &f->s_tgt};
+        for (float** b : fb)
+            if (*b) { (void)hipFree(*b); *b = nullptr; }
+        f->snap_cap = cap;
+        f->sample_cap = (int64_t)cap * n;
+        if (!(dalloc(&f->snap_mom, (size_t)cap * 4 * M) && dalloc(&f->s_snap, f->sample_cap) &&
+              dalloc(&f->s_cell, f->sample_cap) && dalloc(&f->s_off, 3 * f->sample_cap) &&
+              dalloc(&f->s_tgt, 3 * f->sample_cap)))
+            return fail(LD_ENOMEM, "cannot allocate %d training snapshots", cap);
+        f->snaps = 0;
+        f->samples = 0;
+    }
+    if (f->snaps >= f->snap_cap) return fail(LD_ESTATE, "training store is full");
+    // the far field is judged on the same cell assignment as inference
+    ld_status st = ff_near(c, s);
+    if (st != LD_OK) return st;
+    st = ff_grid_and_coarse(c, s);
+    if (st != LD_OK) return st;
+    const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
+    KLAUNCH(k_far_exact, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, rc2, f->Efar);
+    KLAUNCH(k_snap_mom, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, M, f->grid, f->sq,
+            f->snap_mom + (size_t)f->snaps * 4 * M);
+    KLAUNCH(k_collect, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid,
+            f->Efar, f->Ecell, f->snaps, f->samples, f->s_snap, f->s_cell, f->s_off, f->s_tgt);
+    HIP_TRY(hipStreamSynchronize(s));
+    f->snaps += 1;
+    f->samples += n;
+    return LD_OK;
+}
+
+ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* rep) {
+    g_err.clear();
+    if (!c || !c->ff || !tc) return fail(LD_EINVAL, "ctx (with ld_ff_enable) and cfg required");
+    FarField* f = c->ff;
+    if (f->samples < 2) return fail(LD_ESTATE, "collect training snapshots first");
+    if (tc->epochs < 0 || tc->batch < 16 || tc->batch > (1 << 16) || !(tc->lr > 0.0))
+        return fail(LD_EINVAL, "epochs >= 0, 16 <= batch <= 65536, lr > 0");
+    if (!(tc->val_fraction >= 0.0 && tc->val_fraction < 0.9))
+        return fail(LD_EINVAL, "val_fraction in [0, 0.9)");
+    hipStream_t s = c->stream;
+    const int B_ = tc->batch;
+    ld_status st = ensure_batch(f, B_);
+    if (st != LD_OK) return st;
+    // output scale: RMS of the targets
+    std::vector<float> tg(3 * (size_t)f->samples);
+    HIP_TRY(hipMemcpyAsync(tg.data(), f->s_tgt, sizeof(float) * tg.size(), hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double ss = 0.0;
+    for (float v : tg) ss += (double)v * v;
+    const double rms = std::sqrt(ss / (double)tg.size());
+    if (tc->reset_scale || f->out_scale == 1.f) f->out_scale = (float)(rms > 0.0 ? rms : 1.0);
+    const float inv_scale = 1.0f / f->out_scale;
+    // split: the last val_fraction of the samples is held out
+    const int64_t nval = (int64_t)(tc->val_fraction * (double)f->samples);
+    const int64_t ntr = f->samples - nval;
+    std::vector<int> perm(ntr);
+    for (int64_t k = 0; k < ntr; ++k) perm[k] = (int)k;
+    int* dperm = nullptr;
+    HIP_TRY(hipMalloc(&dperm, sizeof(int) * std::max<int64_t>(std::max<int64_t>(ntr, 1), B_)));
+    double last = 0.0;
+    int64_t iters = 0;
+    const int G = f->cfg.grid;
+    for (int ep = 0; ep < tc->epochs && st == LD_OK; ++ep) {
+        // Fisher-Yates with Philox words (stream tag 3)
+        for (int64_t k = ntr - 1; k > 0; --k) {
+            const uint64_t ctr = ((uint64_t)ep << 40) ^ (uint64_t)k;
+            const int64_t j = (int64_t)(philox_word(tc->seed, ctr, 0) % (uint64_t)(k + 1));
+            std::swap(perm[k], perm[j]);
+        }
+        if (hipMemcpy(dperm, perm.data(), sizeof(int) * ntr, hipMemcpyHostToDevice) != hipSuccess) {
+            st = fail(LD_EHIP, "upload permutation");
+            break;
+        }
+        double ep_loss = 0.0;
+        int nb = 0;
+        for (int64_t b0 = 0; b0 + B_ <= ntr && st == LD_OK; b0 += B_) {
+            hipLaunchKernelGGL(k_gather_batch, dim3(B_), dim3(kB), 0, s, dperm + b0, B_, f->s_snap,
+                               f->s_cell, f->s_off, f->s_tgt, f->snap_mom, G, f->cfg.block, f->Kp,
+                               inv_scale, f->bX, f->bT);
+            if (hipGetLastError() != hipSuccess) { st = fail(LD_EHIP, "gather"); break; }
+            double l = 0.0;
+            const bool want = (b0 + 2 * B_ > ntr);   // last batch of the epoch
+            st = fwd_bwd(f, B_, s, want ? &l : nullptr);
+            if (st != LD_OK) break;
+            ++f->adam_step;
+            if (ld::launch_adam(f->W, f->grad, f->adam_m, f->adam_v, (int)f->nW, (float)tc->lr,
+                                f->adam_step, s) != hipSuccess) {
+                st = fail(LD_EHIP, "adam");
+                break;
+            }
+            if (want) { ep_loss = l; nb = 1; }
+            ++iters;
+        }
+        if (nb) last = ep_loss;
+    }
+    // validation: relative RMS error of the residual on the held-out samples
+    double val_rel = NAN;
+    if (st == LD_OK && nval >= 16) {
+        double num = 0.0, den = 0.0;
+        std::vector<int> vidx;
+        for (int64_t k = ntr; k < f->samples; ++k) vidx.push_back((int)k);
+        for (size_t v0 = 0; v0 + 16 <= vidx.size() && st == LD_OK; v0 += B_) {
+            const int bsz = (int)std::min<size_t>(B_, vidx.size() - v0);
+            if (hipMemcpy(dperm, vidx.data() + v0, sizeof(int) * bsz, hipMemcpyHostToDevice) !=
+                hipSuccess) { st = fail(LD_EHIP, "upload"); break; }
+            hipLaunchKernelGGL(k_gather_batch, dim3(bsz), dim3(kB), 0, s, dperm, bsz, f->s_snap,
+                               f->s_cell, f->s_off, f->s_tgt, f->snap_mom, G, f->cfg.block, f->Kp,
+                               inv_scale, f->bX, f->bT);
+            const int H = f->H, Op = f->Op;
+            st = gemm(s, f->bX, f->Kp, 0, f->W + f->offW1, H, 0, f->bA1, H, bsz, H, f->Kp,
+                      f->W + f->offb1, 1, nullptr, 0, 0, nullptr);
+            if (st == LD_OK)
+                st = gemm(s, f->bA1, H, 0, f->W + f->offW2, H, 0, f->bA2, H, bsz, H, H,
+                          f->W + f->offb2, 1, nullptr, 0, 0, nullptr);
+            if (st == LD_OK)
+                st = gemm(s, f->bA2, H, 0, f->W + f->offW3, Op, 0, f->bY, Op, bsz, Op, H,
+                          f->W + f->offb3, 0, nullptr, 0, 0, nullptr);
+            if (st != LD_OK) break;
+            std::vector<float> y((size_t)bsz * Op), t((size_t)bsz * 3);
+            if (hipMemcpyAsync(y.data(), f->bY, sizeof(float) * y.size(), hipMemcpyDeviceToHost,
+                               s) != hipSuccess ||
+                hipMemcpyAsync(t.data(), f->bT, sizeof(float) * t.size(), hipMemcpyDeviceToHost,
+                               s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) { st = fail(LD_EHIP, "readback"); break; }
+            for (int r = 0; r < bsz; ++r)
+                for (int k = 0; k < 3; ++k) {
+                    const double d = (double)y[(size_t)r * Op + k] - t[3 * r + k];
+                    num += d * d;
+                    den += (double)t[3 * r + k] * t[3 * r + k];
+                }
+        }
+        if (den > 0.0) val_rel = std::sqrt(num / den);
+    }
+    (void)hipFree(dperm);
+    if (st != LD_OK) return st;
+    if (rep) {
+        rep->samples = f->samples;
+        rep->iterations = iters;
+        rep->final_loss = last;
+        rep->val_rel_rms = val_rel;
+        rep->out_scale = f->out_scale;
+    }
+    return LD_OK;
+}
+
+ld_status ld_ff_judge(ld_ctx* c, double* median_rel_err) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    double med = 0.0;
+    ld_status st = ff_judge_now(c, &med);
+    if (st != LD_OK) return st;
+    if (median_rel_err) *median_rel_err = med;
+    return LD_OK;
+}
+
+ld_status ld_ff_stats(ld_ctx* c, int64_t out[4], double* last_err) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    if (out) {
+        out[0] = c->ff->judges;
+        out[1] = c->ff->fallbacks;
+        out[2] = c->ff->learned_steps;
+        out[3] = c->ff->direct_steps;
+    }
+    if (last_err) *last_err = c->ff->last_err;
+    return LD_OK;
+}
+
+}  // extern "C"

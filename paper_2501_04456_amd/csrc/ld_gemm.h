@@ -1,0 +1,39 @@
+// Launchers of the BF16-MFMA matrix products and training helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ld {
+
+// C[M x N] (= or +=) act(op(A)[M x K] op(B)[K x N] + bias).  op(A) = A
+// (row-major, leading dimension lda) or its transpose (A stored K x M);
+// likewise B.  Z (optional) receives the pre-activation values.  If M_dev is
+// set, rows at or beyond *M_dev are skipped (a device-side row count).
+struct GemmArgs {
+    const float* A;
+    int lda;
+    int transA;
+    const float* B;
+    int ldb;
+    int transB;
+    float* C;
+    int ldc;
+    const float* bias;
+    float* Z;
+    int ldz;
+    int M, N, K;
+    int act;          // 0 none, 1 SiLU
+    int accumulate;   // 1: C += result
+    const int* M_dev;
+};
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
+hipError_t launch_silu_bwd(const float* Z, float* dA, int rows, int cols, const int* rows_dev,
+                           hipStream_t s);
+hipError_t launch_colsum(const float* dZ, int rows, int cols, float* db, hipStream_t s);
+hipError_t launch_mse(const float* Y, int ld, const float* T, int rows, int out, float* dY,
+                      double* part, int* nparts, hipStream_t s);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int n, float lr, int step,
+                       hipStream_t s);
+
+}  // namespace ld

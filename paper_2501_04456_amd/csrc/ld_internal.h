@@ -150,6 +150,11 @@ struct SortBuffers {
 hipError_t launch_sort(float4* pos, float4* lo, int* typ, int* oid, int n,
                        const SortBuffers& B, hipStream_t s);
 
+// Sort B.keys (filled by the caller: high word = sort key, low word = slot;
+// padding keys ~0) and permute the slot arrays accordingly.
+hipError_t launch_sort_by_keys(float4* pos, float4* lo, int* typ, int* oid, int n,
+                               const SortBuffers& B, hipStream_t s);
+
 // 64-bit bitonic sort of n_pow2 keys (ascending).
 hipError_t launch_bitonic(unsigned long long* keys, int n_pow2, hipStream_t s);
 
@@ -162,6 +167,8 @@ hipError_t launch_moments(const float4* pos, const float4* lo, int n, double* wo
 hipError_t launch_boxcount(const float4* pos, const float4* lo, int n, const double* lo3,
                            double eps, unsigned long long* keys, int n_pow2,
                            unsigned long long* count, hipStream_t s);
+
+struct FarField;
 
 }  // namespace ld
 
@@ -202,4 +209,16 @@ struct ld_ctx {
     double graph_dt = 0.0;
     int graph_len = 0;
     ld_tuning graph_key{};
+
+    // learned far field (null until ld_ff_enable)
+    ld::FarField* ff = nullptr;
 };
+
+namespace ld {
+// Learned far field hooks used by the step loop (defined in ld_ff.hip).
+void ff_free(ld_ctx* c);
+bool ff_active(const ld_ctx* c);
+// Pair forces of one step into Fpart: the learned path (one partial) or the
+// direct path; *j_split_used says how many partials the update must sum.
+ld_status ff_step_forces(ld_ctx* c, hipStream_t s, int* j_split_used);
+}  // namespace ld

@@ -150,6 +150,11 @@ hipError_t launch_sort(float4* pos, float4* lo, int* typ, int* oid, int n, const
                        B.bounds_part);
     hipLaunchKernelGGL(k_morton, dim3((B.n_pow2 + 255) / 256), dim3(256), 0, s, pos, n, B.n_pow2,
                        B.bounds_part, B.bounds_parts, B.keys);
+    return launch_sort_by_keys(pos, lo, typ, oid, n, B, s);
+}
+
+hipError_t launch_sort_by_keys(float4* pos, float4* lo, int* typ, int* oid, int n,
+                               const SortBuffers& B, hipStream_t s) {
     hipError_t e = launch_bitonic(B.keys, B.n_pow2, s);
     if (e != hipSuccess) return e;
     const dim3 g((n + 255) / 256);

@@ -62,11 +62,33 @@ class ld_tuning(C.Structure):
 TUNING_FIELDS = ("block", "j_split", "comp", "sort_every", "cull", "graph_steps")
 
 
+class ld_ff_config(C.Structure):
+    _fields_ = [("near_cut", C.c_double), ("grid", C.c_int32), ("block", C.c_int32),
+                ("hidden", C.c_int32), ("judge_every", C.c_int32), ("judge_tol", C.c_double)]
+
+
+class ld_ff_train_cfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+                ("seed", C.c_uint64), ("val_fraction", C.c_double), ("reset_scale", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class ld_ff_train_report(C.Structure):
+    _fields_ = [("samples", C.c_int64), ("iterations", C.c_int64), ("final_loss", C.c_double),
+                ("val_rel_rms", C.c_double), ("out_scale", C.c_double)]
+
+
+FF_DEFAULT = dict(near_cut=8.0, grid=32, block=5, hidden=128, judge_every=500, judge_tol=1e-3)
+
+
 SYMBOLS = [
     "ld_init", "ld_destroy", "ld_last_error", "ld_forces", "ld_step", "ld_sync",
     "ld_get_positions", "ld_get_state", "ld_set_params", "ld_diagnostics", "ld_rdf",
     "ld_fractal", "ld_get_tuning", "ld_set_tuning", "ld_kernel_timing", "ld_kernel_time",
     "ld_autotune",
+    "ld_ff_enable", "ld_ff_mode", "ld_ff_weights_size", "ld_ff_set_weights", "ld_ff_get_weights",
+    "ld_ff_grid", "ld_ff_forces", "ld_ff_mlp", "ld_ff_grads", "ld_ff_collect", "ld_ff_train",
+    "ld_ff_judge", "ld_ff_stats",
     "ld_ens_init", "ld_ens_destroy", "ld_ens_set_tuning", "ld_ens_step", "ld_ens_forces",
     "ld_ens_get_positions", "ld_ens_get_state", "ld_ens_sync", "ld_ens_kernel_timing",
     "ld_ens_kernel_time",
@@ -115,8 +137,24 @@ def lib():
         L.ld_ens_sync.argtypes = [vp]
         L.ld_ens_kernel_timing.argtypes = [vp, C.c_int32]
         L.ld_ens_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.ld_ff_enable.argtypes = [vp, C.POINTER(ld_ff_config)]
+        L.ld_ff_mode.argtypes = [vp, C.c_int32]
+        L.ld_ff_weights_size.argtypes = [vp]
+        L.ld_ff_weights_size.restype = C.c_int64
+        L.ld_ff_set_weights.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double]
+        L.ld_ff_get_weights.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
+        L.ld_ff_grid.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.ld_ff_forces.argtypes = [vp, C.c_int32, vp]
+        L.ld_ff_mlp.argtypes = [vp, vp, C.c_int64, vp]
+        L.ld_ff_grads.argtypes = [vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double)]
+        L.ld_ff_collect.argtypes = [vp, C.c_int32, C.c_int32]
+        L.ld_ff_train.argtypes = [vp, C.POINTER(ld_ff_train_cfg), C.POINTER(ld_ff_train_report)]
+        L.ld_ff_judge.argtypes = [vp, C.POINTER(C.c_double)]
+        L.ld_ff_stats.argtypes = [vp, vp, C.POINTER(C.c_double)]
         for name in SYMBOLS:
-            if name not in ("ld_destroy", "ld_last_error", "ld_ens_destroy"):
+            if name not in ("ld_destroy", "ld_last_error", "ld_ens_destroy",
+                            "ld_ff_weights_size"):
                 getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -305,6 +343,79 @@ class System:
         for k, v in kw.items():
             setattr(t, k, int(v))
         _check(lib().ld_set_tuning(self.h, C.byref(t)))
+
+    # -- learned far field --------------------------------------------------
+    def ff_enable(self, **kw):
+        cfg = dict(FF_DEFAULT, **kw)
+        c = ld_ff_config(**cfg)
+        _check(lib().ld_ff_enable(self.h, C.byref(c)))
+        self.ff_cfg = cfg
+
+    def ff_mode(self, mode: int):
+        _check(lib().ld_ff_mode(self.h, int(mode)))
+
+    def ff_weights(self):
+        n = lib().ld_ff_weights_size(self.h)
+        w = np.zeros(n, np.float32)
+        sq, sc = C.c_double(), C.c_double()
+        _check(lib().ld_ff_get_weights(self.h, w.ctypes.data_as(C.c_void_p), n, C.byref(sq),
+                                       C.byref(sc)))
+        return w, sq.value, sc.value
+
+    def ff_set_weights(self, w, sq: float, out_scale: float):
+        w = np.ascontiguousarray(w, np.float32)
+        _check(lib().ld_ff_set_weights(self.h, w.ctypes.data_as(C.c_void_p), w.size, sq,
+                                       out_scale))
+
+    def ff_grid(self):
+        L, g = C.c_double(), C.c_int32()
+        _check(lib().ld_ff_grid(self.h, C.byref(L), C.byref(g)))
+        return L.value, g.value
+
+    def ff_forces(self, part: int) -> np.ndarray:
+        out = np.zeros((self.n, 3))
+        _check(lib().ld_ff_forces(self.h, int(part), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def ff_mlp(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(X, np.float32)
+        Y = np.zeros((X.shape[0], 3), np.float32)
+        _check(lib().ld_ff_mlp(self.h, X.ctypes.data_as(C.c_void_p), X.shape[0],
+                               Y.ctypes.data_as(C.c_void_p)))
+        return Y
+
+    def ff_grads(self, X, T):
+        X = np.ascontiguousarray(X, np.float32)
+        T = np.ascontiguousarray(T, np.float32)
+        g = np.zeros(lib().ld_ff_weights_size(self.h), np.float32)
+        loss = C.c_double()
+        _check(lib().ld_ff_grads(self.h, X.ctypes.data_as(C.c_void_p),
+                                 T.ctypes.data_as(C.c_void_p), X.shape[0],
+                                 g.ctypes.data_as(C.c_void_p), C.byref(loss)))
+        return loss.value, g
+
+    def ff_collect(self, reset: bool = False, max_snapshots: int = 16):
+        _check(lib().ld_ff_collect(self.h, 1 if reset else 0, int(max_snapshots)))
+
+    def ff_train(self, epochs=20, batch=8192, lr=1e-3, seed=105, val_fraction=0.1,
+                 reset_scale=True) -> dict:
+        c = ld_ff_train_cfg(epochs=epochs, batch=batch, lr=lr, seed=seed,
+                            val_fraction=val_fraction, reset_scale=1 if reset_scale else 0)
+        r = ld_ff_train_report()
+        _check(lib().ld_ff_train(self.h, C.byref(c), C.byref(r)))
+        return {k: getattr(r, k) for k, _ in r._fields_}
+
+    def ff_judge(self) -> float:
+        v = C.c_double()
+        _check(lib().ld_ff_judge(self.h, C.byref(v)))
+        return v.value
+
+    def ff_stats(self):
+        out = np.zeros(4, np.int64)
+        e = C.c_double()
+        _check(lib().ld_ff_stats(self.h, out.ctypes.data_as(C.c_void_p), C.byref(e)))
+        return {"judges": int(out[0]), "fallbacks": int(out[1]), "learned_steps": int(out[2]),
+                "direct_steps": int(out[3]), "last_err": e.value}
 
     def kernel_timing(self, enable: bool):
         _check(lib().ld_kernel_timing(self.h, 1 if enable else 0))

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "ldrop.h")
 def declared_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:ld_status|void|const char\s*\*)\s+(ld_\w+)\s*\(", txt, flags=re.M)
+    names = re.findall(r"^\s*(?:ld_status|void|int64_t|const char\s*\*)\s+(ld_\w+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 
