@@ -215,7 +215,7 @@ ld_status ld_get_tuning(ld_ctx* ctx, ld_tuning* t);
 ld_status ld_set_tuning(ld_ctx* ctx, const ld_tuning* t);
 
 /* Search the pair kernel's launch shape (workgroup size 128/256/512 x j
- * split 1..16) by timing launches on the current state with HIP events, keep
+ x j split 1..32) by timing launches on the current state with HIP events, keep
  * the fastest, and return the resulting tuning in *out (may be NULL).
  * compensation, culling, sorting and graph settings are kept.  cache_path
  * (may be NULL) is a text file of "key block j_split ms" lines, keyed by GPU

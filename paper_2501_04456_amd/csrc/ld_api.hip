@@ -149,13 +149,15 @@ void default_tuning(ld_ctx* c) {
     ld_tuning& t = c->tune;
     std::memset(&t, 0, sizeof t);
     const int64_t n = c->n;
+    // Enough workgroups to fill 256 CUs many times over (a short tail), but
+    // at least 256 j per split so each workgroup streams whole LDS tiles.
     t.block = n >= 16384 ? 256 : 64;
     const int64_t tiles = (n + t.block - 1) / t.block;
-    int64_t split = (2048 + tiles - 1) / tiles;
-    int64_t cap = n / 1024;
+    int64_t split = (16384 + tiles - 1) / tiles;
+    int64_t cap = n / 256;
     if (cap < 1) cap = 1;
     if (split > cap) split = cap;
-    if (split > 64) split = 64;
+    if (split > 16) split = 16;
     if (split < 1) split = 1;
     t.j_split = (int)split;
     t.comp = 0;
@@ -816,8 +818,8 @@ ld_status ld_autotune(ld_ctx* c, const char* cache_path, int32_t force, ld_tunin
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const int blocks[] = {128, 256, 512};
-    const int splits[] = {1, 2, 3, 4, 6, 8, 12, 16};
-    int64_t cap = c->n / 1024;
+    const int splits[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+    int64_t cap = c->n / 256;
     if (cap < 1) cap = 1;
     double best_ms = INFINITY;
     ld_tuning best = saved;
