@@ -313,15 +313,15 @@ __global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
                                                const int* __restrict__ occ,
                                                const int* __restrict__ nocc, int G, int B,
                                                const FFGrid* g, double* E) {
-    __shared__ float4 sm[kB];
-    __shared__ int sc[kB];
+    __shared__ float4 sm[kB];          // (Q, Px, Py, Pz)
+    __shared__ float4 sc[kB];          // cell index (x, y, z) as floats
     const int no = *nocc;
     const int t = blockIdx.x * kB + threadIdx.x;
     const bool live = t < no;
     const int tc = live ? occ[t] : 0;
-    const int tx = tc % G, ty = (tc / G) % G, tz = tc / (G * G);
+    const float tx = (float)(tc % G), ty = (float)((tc / G) % G), tz = (float)(tc / (G * G));
     const float h = (float)g->h;
-    const int half = B / 2;
+    const float half = (float)(B / 2) + 0.5f;
     double Ex = 0.0, Ey = 0.0, Ez = 0.0;
     for (int j0 = 0; j0 < no; j0 += kB) {
         __syncthreads();
@@ -330,25 +330,30 @@ __global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
             const int c = occ[j];
             sm[threadIdx.x] = make_float4((float)mom[4 * c], (float)mom[4 * c + 1],
                                           (float)mom[4 * c + 2], (float)mom[4 * c + 3]);
-            sc[threadIdx.x] = c;
+            sc[threadIdx.x] = make_float4((float)(c % G), (float)((c / G) % G),
+                                          (float)(c / (G * G)), 0.f);
+        } else {
+            sm[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+            sc[threadIdx.x] = make_float4(1e6f, 1e6f, 1e6f, 0.f);
         }
         __syncthreads();
-        const int m = min(kB, no - j0);
         float ex = 0.f, ey = 0.f, ez = 0.f;
-        for (int k = 0; k < m; ++k) {
-            const int c = sc[k];
-            const int sx = c % G, sy = (c / G) % G, sz = c / (G * G);
-            if (abs(sx - tx) <= half && abs(sy - ty) <= half && abs(sz - tz) <= half) continue;
+#pragma unroll 4
+        for (int k = 0; k < kB; ++k) {
+            const float4 cs = sc[k];
+            const float dx = tx - cs.x, dy = ty - cs.y, dz = tz - cs.z;
+            // cells of the B^3 block (and the padding) contribute nothing
+            const bool outside = fmaxf(fabsf(dx), fmaxf(fabsf(dy), fabsf(dz))) > half;
             const float4 q = sm[k];
-            const float rx = (float)(tx - sx) * h, ry = (float)(ty - sy) * h,
-                        rz = (float)(tz - sz) * h;
-            const float r2 = rx * rx + ry * ry + rz * rz;
-            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float rx = dx * h, ry = dy * h, rz = dz * h;
+            const float r2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+            const float ri = outside ? __builtin_amdgcn_rsqf(r2) : 0.f;
             const float ri2 = ri * ri, ri3 = ri2 * ri;
-            const float pr3 = 3.0f * (q.y * rx + q.z * ry + q.w * rz) * ri2;
-            ex += (q.x * rx + pr3 * rx - q.y) * ri3;
-            ey += (q.x * ry + pr3 * ry - q.z) * ri3;
-            ez += (q.x * rz + pr3 * rz - q.w) * ri3;
+            const float pr3 = 3.0f * fmaf(q.w, rz, fmaf(q.z, ry, q.y * rx)) * ri2;
+            const float a = q.x + pr3;
+            ex = fmaf(fmaf(a, rx, -q.y), ri3, ex);
+            ey = fmaf(fmaf(a, ry, -q.z), ri3, ey);
+            ez = fmaf(fmaf(a, rz, -q.w), ri3, ez);
         }
         Ex += (double)ex; Ey += (double)ey; Ez += (double)ez;
     }
@@ -400,29 +405,29 @@ __device__ __forceinline__ void particle_cell(const float4 h, const float4 l, in
     off[2] = (float)((z - (-L + (cz + 0.5) * hh)) / hh);
 }
 
-// First layer finished per particle: z1 = A_cell + W1[offset rows] o + b1.
+// First layer finished per particle: z1 = A_cell + W1[offset rows] o + b1;
+// one work-item per (particle, hidden unit).
 __global__ __launch_bounds__(kB) void k_layer1(const float4* __restrict__ pos,
                                                const float4* __restrict__ lo, int n, int G,
                                                const FFGrid* g, const int* __restrict__ cell2occ,
                                                const float* __restrict__ Ac,
                                                const float* __restrict__ W1o,
                                                const float* __restrict__ b1, int H, float* h1) {
-    const int s = blockIdx.x;
-    if (s >= n) return;
+    const size_t e = (size_t)blockIdx.x * kB + threadIdx.x;
+    if (e >= (size_t)n * H) return;
+    const int s = (int)(e / H), j = (int)(e % H);
     int c;
     float off[3];
     particle_cell(pos[s], lo[s], G, g, &c, off);
     const int oc = cell2occ[c];
     if (oc < 0) {   // cannot happen: the particle's own cell is occupied
-        for (int j = threadIdx.x; j < H; j += kB) h1[(size_t)s * H + j] = 0.f;
+        h1[e] = 0.f;
         return;
     }
-    const float o0 = bf16_round(off[0]), o1 = bf16_round(off[1]), o2 = bf16_round(off[2]);
-    for (int j = threadIdx.x; j < H; j += kB) {
-        const float z = Ac[(size_t)oc * H + j] + o0 * bf16_round(W1o[j]) +
-                        o1 * bf16_round(W1o[H + j]) + o2 * bf16_round(W1o[2 * H + j]) + b1[j];
-        h1[(size_t)s * H + j] = silu_f(z);
-    }
+    const float z = Ac[(size_t)oc * H + j] + bf16_round(off[0]) * bf16_round(W1o[j]) +
+                    bf16_round(off[1]) * bf16_round(W1o[H + j]) +
+                    bf16_round(off[2]) * bf16_round(W1o[2 * H + j]) + b1[j];
+    h1[e] = silu_f(z);
 }
 
 // F = F_near + q (E_cell + scale y) into Fpart (slot order) and optional parts.
@@ -686,7 +691,8 @@ ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
     st = gemm(s, f->Xc, f->Kp, 0, f->W + f->offW1, H, 0, f->Ac, H, M, H, f->Kp, nullptr, 0,
               nullptr, 0, 0, f->nocc);
     if (st != LD_OK) return st;
-    KLAUNCH(k_layer1, dim3(n), dim3(kB), s, c->pos, c->lo, n, G, f->grid, f->cell2occ, f->Ac,
+    KLAUNCH(k_layer1, dim3((unsigned)(((size_t)n * H + kB - 1) / kB)), dim3(kB), s, c->pos, c->lo,
+            n, G, f->grid, f->cell2occ, f->Ac,
             f->W + f->offW1 + (size_t)(f->K - 3) * H, f->W + f->offb1, H, f->h1);
     st = gemm(s, f->h1, H, 0, f->W + f->offW2, H, 0, f->h2, H, n, H, H, f->W + f->offb2, 1,
               nullptr, 0, 0, nullptr);

@@ -89,7 +89,15 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const float4* __restrict__ pos,
             if constexpr (CULL) {
                 const int gj = jg / kGroup;
                 near = false;
-                if (jg < j1 && gj < ngroups) near = box_dist2(bi, box[gj]) < cull2;
+                bool coulomb = false;
+                if (jg < j1 && gj < ngroups) {
+                    const Box bj = box[gj];
+                    near = box_dist2(bi, bj) < cull2;
+                    // a far pair of groups one of which is uncharged has no
+                    // force at all: skip it
+                    coulomb = bi.lo.w != 0.f && bj.lo.w != 0.f;
+                }
+                if (!near && !__builtin_amdgcn_readfirstlane((int)coulomb)) continue;
             }
             if constexpr (DIAG) near = true;
             if (__builtin_amdgcn_readfirstlane((int)near)) {

@@ -110,7 +110,11 @@ __global__ __launch_bounds__(256) void k_morton(const float4* __restrict__ pos, 
     const unsigned qy = (unsigned)fminf(1023.f, fmaxf(0.f, (h.y - lo[1]) * scale));
     const unsigned qz = (unsigned)fminf(1023.f, fmaxf(0.f, (h.z - lo[2]) * scale));
     const unsigned code = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
-    keys[s] = ((unsigned long long)code << 32) | (unsigned)s;
+    // Uncharged particles go after all charged ones (bit 62), so 64-slot
+    // groups are charge-homogeneous and the pair kernel can skip far group
+    // pairs whose Coulomb term is identically zero.
+    const unsigned long long neutral = (h.w == 0.f) ? 1ull : 0ull;
+    keys[s] = (neutral << 62) | ((unsigned long long)code << 32) | (unsigned)s;
 }
 
 __global__ __launch_bounds__(256) void k_permute4(const unsigned long long* __restrict__ keys,

@@ -72,14 +72,16 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// Bounding box of each 64-slot group (one wavefront per group).
+// Bounding box of each 64-slot group (one wavefront per group); lo.w = 1 if
+// the group holds a charged particle, else 0.
 __device__ __forceinline__ void write_box(const float4 h, bool live, int s, Box* box) {
     const float lx = wave_min(live ? h.x : INFINITY), hx = wave_max(live ? h.x : -INFINITY);
     const float ly = wave_min(live ? h.y : INFINITY), hy = wave_max(live ? h.y : -INFINITY);
     const float lz = wave_min(live ? h.z : INFINITY), hz = wave_max(live ? h.z : -INFINITY);
+    const bool charged = __any(live && h.w != 0.f);
     if ((threadIdx.x & (kGroup - 1)) == 0 && lx <= hx) {
         Box b;
-        b.lo = make_float4(lx, ly, lz, 0.f);
+        b.lo = make_float4(lx, ly, lz, charged ? 1.f : 0.f);
         b.hi = make_float4(hx, hy, hz, 0.f);
         box[s / kGroup] = b;
     }
