@@ -179,6 +179,19 @@ ld_status ld_get_state(ld_ctx* ctx, int64_t* step, double* t, double* R);
  * stopped and restarted with different parameters).  NULL keeps the old. */
 ld_status ld_set_params(ld_ctx* ctx, const ld_params* p, const ld_radius* R);
 
+/* Save the complete state (parameters, schedule, seed, tuning, step counter,
+ * time, and the slot-ordered positions hi/lo, types and original indices) to
+ * a little-endian binary file (section 2.2: a run can be stopped and
+ * restarted from the saved configuration).  A context loaded from it
+ * continues bit for bit as the saved one would have.  The learned far field
+ * is not saved.  Errors: LD_EINVAL, LD_EHIP, LD_ESTATE (file I/O). */
+ld_status ld_checkpoint_save(ld_ctx* ctx, const char* path);
+
+/* Create a context from a checkpoint on the given stream.  Errors:
+ * LD_EINVAL (not a checkpoint / wrong version), LD_ENOMEM, LD_EHIP,
+ * LD_ESTATE (file I/O). */
+ld_status ld_checkpoint_load(ld_ctx** out, const char* path, void* stream);
+
 /* FP64 diagnostics at the current state with R = R(t):
  * out[0] U_LJ, out[1] U_C, out[2] U_wall, out[3] U_grav, out[4] U_centrifugal,
  * out[5..7] net pair force, out[8] max |F_pair_i|, out[9] max |x_i|. */

@@ -775,6 +775,124 @@ ld_status ld_set_tuning(ld_ctx* c, const ld_tuning* t) {
     return LD_OK;
 }
 
+namespace {
+constexpr char kMagic[8] = {'L', 'D', 'R', 'O', 'P', 'C', 'K', '1'};
+}
+
+ld_status ld_checkpoint_save(ld_ctx* c, const char* path) {
+    g_err.clear();
+    if (!c || !path) return fail(LD_EINVAL, "ctx and path are required");
+    const size_t N = (size_t)c->n;
+    std::vector<float4> h(N), l(N);
+    std::vector<int> ty(N), ids(N);
+    ld::DevState ds;
+    HIP_TRY(hipMemcpyAsync(h.data(), c->pos, sizeof(float4) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(l.data(), c->lo, sizeof(float4) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(ty.data(), c->typ, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(ids.data(), c->oid, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&ds, c->st, sizeof ds, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(LD_ESTATE, "cannot open %s for writing", path);
+    const int64_t n64 = c->n, sss = c->steps_since_sort;
+    bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(&n64, 8, 1, f) == 1 &&
+              std::fwrite(&c->p, sizeof c->p, 1, f) == 1 &&
+              std::fwrite(&c->R, sizeof c->R, 1, f) == 1 &&
+              std::fwrite(&c->seed, 8, 1, f) == 1 &&
+              std::fwrite(&c->tune, sizeof c->tune, 1, f) == 1 &&
+              std::fwrite(&ds.step, 8, 1, f) == 1 && std::fwrite(&ds.t, 8, 1, f) == 1 &&
+              std::fwrite(&sss, 8, 1, f) == 1 &&
+              std::fwrite(h.data(), sizeof(float4), N, f) == N &&
+              std::fwrite(l.data(), sizeof(float4), N, f) == N &&
+              std::fwrite(ty.data(), sizeof(int), N, f) == N &&
+              std::fwrite(ids.data(), sizeof(int), N, f) == N;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(LD_ESTATE, "writing %s failed", path);
+    return LD_OK;
+}
+
+ld_status ld_checkpoint_load(ld_ctx** out, const char* path, void* stream) {
+    g_err.clear();
+    if (!out || !path) return fail(LD_EINVAL, "out and path are required");
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(LD_ESTATE, "cannot open %s", path);
+    char magic[8];
+    int64_t n64 = 0, step = 0, sss = 0;
+    double t = 0.0;
+    ld_params p;
+    ld_radius R;
+    uint64_t seed = 0;
+    ld_tuning tune;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+              std::fread(&n64, 8, 1, f) == 1 && n64 >= 2 && n64 <= (1 << 27) &&
+              std::fread(&p, sizeof p, 1, f) == 1 && std::fread(&R, sizeof R, 1, f) == 1 &&
+              std::fread(&seed, 8, 1, f) == 1 && std::fread(&tune, sizeof tune, 1, f) == 1 &&
+              std::fread(&step, 8, 1, f) == 1 && std::fread(&t, 8, 1, f) == 1 &&
+              std::fread(&sss, 8, 1, f) == 1;
+    const size_t N = ok ? (size_t)n64 : 0;
+    std::vector<float4> h(N), l(N);
+    std::vector<int> ty(N), ids(N);
+    ok = ok && std::fread(h.data(), sizeof(float4), N, f) == N &&
+         std::fread(l.data(), sizeof(float4), N, f) == N &&
+         std::fread(ty.data(), sizeof(int), N, f) == N &&
+         std::fread(ids.data(), sizeof(int), N, f) == N;
+    std::fclose(f);
+    if (!ok) return fail(LD_EINVAL, "%s is not a complete checkpoint of this version", path);
+    // a context in original order, then overwrite its slot arrays and clock
+    std::vector<int32_t> ty_orig(N);
+    std::vector<double> q_orig(N);
+    std::vector<float> x_orig(3 * N);
+    const double qs = std::sqrt(p.kT * p.bjerrum);
+    std::vector<bool> seen(N, false);
+    for (size_t s = 0; s < N; ++s) {
+        const int o = ids[s];
+        if (o < 0 || (size_t)o >= N || seen[o])
+            return fail(LD_EINVAL, "%s: slot permutation is corrupt", path);
+        seen[o] = true;
+        ty_orig[o] = ty[s];
+        q_orig[o] = qs > 0.0 ? (double)h[s].w / qs : 0.0;
+        x_orig[3 * o] = h[s].x;
+        x_orig[3 * o + 1] = h[s].y;
+        x_orig[3 * o + 2] = h[s].z;
+    }
+    ld_ctx* c = nullptr;
+    ld_status st = ld_init(&c, n64, ty_orig.data(), q_orig.data(), x_orig.data(), &p, &R, seed,
+                           stream);
+    if (st != LD_OK) return st;
+    ld::DevState ds{};
+    ds.step = step;
+    ds.t = t;
+    ds.bad_step = ~0ull;
+    hipError_t e = hipMemcpyAsync(c->pos, h.data(), sizeof(float4) * N, hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->lo, l.data(), sizeof(float4) * N, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->typ, ty.data(), sizeof(int) * N, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->oid, ids.data(), sizeof(int) * N, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->st, &ds, sizeof ds, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        ld_destroy(c);
+        return fail(LD_EHIP, "restoring state: %s", hipGetErrorString(e));
+    }
+    st = ld_set_tuning(c, &tune);
+    if (st == LD_OK) {
+        e = ld::launch_boxes(c->pos, (int)N, c->box, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) st = fail(LD_EHIP, "boxes: %s", hipGetErrorString(e));
+    }
+    if (st != LD_OK) {
+        ld_destroy(c);
+        return st;
+    }
+    c->steps_since_sort = sss;
+    *out = c;
+    return LD_OK;
+}
+
 ld_status ld_autotune(ld_ctx* c, const char* cache_path, int32_t force, ld_tuning* out) {
     g_err.clear();
     if (!c) return fail(LD_EINVAL, "ctx is NULL");

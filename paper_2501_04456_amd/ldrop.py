@@ -85,7 +85,7 @@ SYMBOLS = [
     "ld_init", "ld_destroy", "ld_last_error", "ld_forces", "ld_step", "ld_sync",
     "ld_get_positions", "ld_get_state", "ld_set_params", "ld_diagnostics", "ld_rdf",
     "ld_fractal", "ld_get_tuning", "ld_set_tuning", "ld_kernel_timing", "ld_kernel_time",
-    "ld_autotune",
+    "ld_autotune", "ld_checkpoint_save", "ld_checkpoint_load",
     "ld_ff_enable", "ld_ff_mode", "ld_ff_weights_size", "ld_ff_set_weights", "ld_ff_get_weights",
     "ld_ff_grid", "ld_ff_forces", "ld_ff_mlp", "ld_ff_grads", "ld_ff_collect", "ld_ff_train",
     "ld_ff_judge", "ld_ff_stats",
@@ -125,6 +125,8 @@ def lib():
         L.ld_kernel_timing.argtypes = [vp, C.c_int32]
         L.ld_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.ld_autotune.argtypes = [vp, C.c_char_p, C.c_int32, C.POINTER(ld_tuning)]
+        L.ld_checkpoint_save.argtypes = [vp, C.c_char_p]
+        L.ld_checkpoint_load.argtypes = [C.POINTER(C.c_void_p), C.c_char_p, vp]
         L.ld_ens_init.argtypes = [C.POINTER(C.c_void_p), C.c_int32, vp, vp, vp, vp, vp, vp, vp,
                                   vp]
         L.ld_ens_destroy.argtypes = [vp]
@@ -227,6 +229,27 @@ class System:
                              C.byref(self._r), int(seed) & 0xFFFFFFFFFFFFFFFF,
                              C.c_void_p(self.stream.cuda_stream)))
         self.h = h
+
+    def checkpoint(self, path: str):
+        """Save the full state (section 2.2: stop and restart)."""
+        _check(lib().ld_checkpoint_save(self.h, path.encode()))
+
+    @classmethod
+    def load(cls, path: str, w: W.Workload, stream=None) -> "System":
+        """A context restored from a checkpoint of workload w (the file's
+        parameters, schedule, seed and state are used; w supplies n and the
+        Python-side description)."""
+        torch = _torch()
+        self = cls.__new__(cls)
+        self._torch = torch
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = C.c_void_p()
+        _check(lib().ld_checkpoint_load(C.byref(h), path.encode(),
+                                        C.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+        self.n = w.n
+        self.params, self.radius = w.params, w.radius
+        return self
 
     @classmethod
     def from_workload(cls, w: W.Workload, **kw) -> "System":

@@ -232,6 +232,29 @@ def test_determinism_and_split_invariance(ld):
     assert np.abs(c.positions64() - xa).max() <= 1e-6
 
 
+def test_checkpoint_resume_bitwise(ld, tmp_path):
+    """Stop and restart from a saved configuration (section 2.2): 30 steps in
+    one go equal 12 steps, save, load into a fresh context, 18 steps."""
+    w = W.config_large(n=5000, seed=19)
+    a = ld.System.from_workload(w)
+    a.set_tuning(sort_every=7)
+    a.step(30, w.dt)
+    b = ld.System.from_workload(w)
+    b.set_tuning(sort_every=7)
+    b.step(12, w.dt)
+    path = str(tmp_path / "ck.bin")
+    b.checkpoint(path)
+    del b
+    c = ld.System.load(path, w)
+    assert c.state()[0] == 12
+    c.step(18, w.dt)
+    assert np.array_equal(c.positions64(), a.positions64())
+    assert c.state()[1] == a.state()[1]
+    with pytest.raises(ld.LdError):
+        open(str(tmp_path / "bad.bin"), "wb").write(b"not a checkpoint")
+        ld.System.load(str(tmp_path / "bad.bin"), w)
+
+
 def test_set_params_midway(ld, orc):
     """Restart with new parameters (section 2.2): both sides switch at step 10."""
     w = W.config_medium(n=1200, seed=41)
