@@ -95,6 +95,11 @@ def lib():
         L.ldo_ff_coarse.argtypes = [C.c_int, C.c_double, C.c_int, dp, dp]
         L.ldo_ff_split.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp, C.POINTER(_Params),
                                    C.c_double, C.POINTER(C.c_int64), C.c_int64, dp, dp]
+        L.ldo_ff_split_block.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp,
+                                         C.POINTER(_Params), C.c_int, C.c_double, C.c_int,
+                                         C.POINTER(C.c_int64), C.c_int64, dp, dp]
+        L.ldo_ff_local.argtypes = [C.c_int, C.c_double, C.c_int, dp, dp]
+        L.ldo_ff_local_eval.argtypes = [C.c_int64, dp, C.c_int, C.c_double, dp, dp]
         L.ldo_ff_features.argtypes = [C.c_int64, dp, C.c_int, C.c_double, C.c_int, dp,
                                       C.c_double, dp]
         L.ldo_mlp_forward.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp,
@@ -318,6 +323,39 @@ def ff_split(x, type_, charge, params, rc: float, rows=None):
     lib().ldo_ff_split(len(t), _dp(x), _ip(t), _dp(q), C.byref(make_params(params)), rc,
                        _lp(rows_a), m, _dp(Fn), _dp(Ef))
     return Fn, Ef
+
+
+def ff_split_block(x, type_, charge, params, G: int, L: float, B: int = 5, rows=None):
+    """(F_near [m,3], E_far [m,3]) with the near region = the B^3 block of
+    grid cells around each particle's cell."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(type_, np.int32)
+    q = np.ascontiguousarray(charge, np.float64)
+    rows_a = None if rows is None else np.ascontiguousarray(rows, np.int64)
+    m = len(t) if rows is None else len(rows_a)
+    Fn = np.zeros((m, 3))
+    Ef = np.zeros((m, 3))
+    lib().ldo_ff_split_block(len(t), _dp(x), _ip(t), _dp(q), C.byref(make_params(params)), G,
+                             L, B, _lp(rows_a), m, _dp(Fn), _dp(Ef))
+    return Fn, Ef
+
+
+def ff_local(mom, G: int, L: float, B: int = 5) -> np.ndarray:
+    """[G^3, 19]: E, J (xx xy xz yy yz zz), H (xxx xxy xxz xyy xyz xzz yyy yyz
+    yzz zzz) of the far cells' monopole + dipole field at every cell centre."""
+    mom = np.ascontiguousarray(mom, np.float64)
+    out = np.zeros((G ** 3, 19))
+    lib().ldo_ff_local(G, L, B, _dp(mom), _dp(out))
+    return out
+
+
+def ff_local_eval(x, G: int, L: float, loc) -> np.ndarray:
+    """Second-order local expansion evaluated at the points x [m,3]."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    loc = np.ascontiguousarray(loc, np.float64)
+    E = np.zeros((len(x), 3))
+    lib().ldo_ff_local_eval(len(x), _dp(x), G, L, _dp(loc), _dp(E))
+    return E
 
 
 def ff_features(x, G: int, L: float, B: int, mom, sq: float) -> np.ndarray:

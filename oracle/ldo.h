@@ -166,6 +166,27 @@ void ldo_ff_split(int64_t n, const double* x, const int32_t* type, const double*
                   const ldo_params* p, double rc, const int64_t* rows, int64_t n_rows,
                   double* F_near, double* E_far);
 
+/* Block split: pairs whose cells lie within the B^3 block (Chebyshev cell
+ * distance <= B/2) are summed exactly (LJ + Coulomb); LJ of pairs outside the
+ * block but within LJ range is added to F_near too; E_far is the Coulomb
+ * field sum over j outside the block (without q_hat_i).  Pinned by
+ * F_near + q_hat E_far = the full pair force and brute-force block
+ * membership. */
+void ldo_ff_split_block(int64_t n, const double* x, const int32_t* type, const double* q,
+                        const ldo_params* p, int G, double L, int B, const int64_t* rows,
+                        int64_t n_rows, double* F_near, double* E_far);
+
+/* Second-order local expansion at every cell centre of the monopole + dipole
+ * field of every cell outside the B^3 block: out[19*cell] = E (x, y, z),
+ * J = dE_c/dx_d (xx, xy, xz, yy, yz, zz), H = d2E_c/dx_d dx_e (xxx, xxy,
+ * xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz).  Pinned by finite differences of
+ * point-charge and point-dipole fields and by Laplace's equation. */
+void ldo_ff_local(int G, double L, int B, const double* mom, double* out);
+
+/* E(x) = E + J d + (1/2) H d d, d = x - centre of x's cell, for n points. */
+void ldo_ff_local_eval(int64_t n, const double* x, int G, double L, const double* loc,
+                       double* E);
+
 /* MLP features [n * (4 B^3 + 3)]: normalised moments of the B^3 block
  * around each particle's cell (dz-major), then its offset / h. */
 void ldo_ff_features(int64_t n, const double* x, int G, double L, int B, const double* mom,

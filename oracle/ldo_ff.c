@@ -148,6 +148,186 @@ void ldo_ff_split(int64_t n, const double* x, const int32_t* type, const double*
     }
 }
 
+/* The split with the near region = the B^3 block of grid cells around i's
+ * cell (the cell of a particle as in ldo_ff_moments).  Coulomb of pairs in
+ * the block and LJ of every pair within its LJ range go to F_near; the
+ * Coulomb field of the particles outside the block goes to E_far. */
+void ldo_ff_split_block(int64_t n, const double* x, const int32_t* type, const double* q,
+                        const ldo_params* p, int G, double L, int B, const int64_t* rows,
+                        int64_t n_rows, double* F_near, double* E_far) {
+    if (rows == NULL) n_rows = n;
+    const double s = sqrt(p->kT * p->bjerrum);
+    const int half = B / 2;
+    int* cell = (int*)malloc(sizeof(int) * 3 * (size_t)(n > 0 ? n : 1));
+    for (int64_t j = 0; j < n; ++j) cell_of(&x[3 * j], G, L, &cell[3 * j]);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t i = rows ? rows[r] : r;
+        double fx = 0, fy = 0, fz = 0, ex = 0, ey = 0, ez = 0;
+        double cfx = 0, cfy = 0, cfz = 0, cex = 0, cey = 0, cez = 0;  /* Kahan terms */
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = x[3 * i] - x[3 * j], dy = x[3 * i + 1] - x[3 * j + 1],
+                         dz = x[3 * i + 2] - x[3 * j + 2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double rr = sqrt(r2);
+            const int inblock = abs(cell[3 * j] - cell[3 * i]) <= half &&
+                                abs(cell[3 * j + 1] - cell[3 * i + 1]) <= half &&
+                                abs(cell[3 * j + 2] - cell[3 * i + 2]) <= half;
+            const int ti = type[i], tj = type[j];
+            const double sg = 0.5 * (p->sigma[ti] + p->sigma[tj]);
+            double gx = 0, gy = 0, gz = 0;
+            int near = 0;
+            if (r2 < (p->lj_cut * sg) * (p->lj_cut * sg)) {
+                const double e = p->use_eps_matrix ? p->eps_matrix[ti * LDO_MAX_TYPES + tj]
+                                                   : sqrt(p->eps[ti] * p->eps[tj]);
+                const double sr2 = sg * sg / r2, sr6 = sr2 * sr2 * sr2;
+                const double g = 24.0 * e * (2.0 * sr6 * sr6 - sr6) / r2;
+                gx += g * dx; gy += g * dy; gz += g * dz;
+                near = 1;
+            }
+            if (inblock) {
+                const double k = p->kT * p->bjerrum * q[i] * q[j] / (r2 * rr);
+                gx += k * dx; gy += k * dy; gz += k * dz;
+                near = 1;
+            } else {
+                const double k = s * q[j] / (r2 * rr);
+                double y, t;
+                y = k * dx - cex; t = ex + y; cex = (t - ex) - y; ex = t;
+                y = k * dy - cey; t = ey + y; cey = (t - ey) - y; ey = t;
+                y = k * dz - cez; t = ez + y; cez = (t - ez) - y; ez = t;
+            }
+            if (near) {
+                double y, t;
+                y = gx - cfx; t = fx + y; cfx = (t - fx) - y; fx = t;
+                y = gy - cfy; t = fy + y; cfy = (t - fy) - y; fy = t;
+                y = gz - cfz; t = fz + y; cfz = (t - fz) - y; fz = t;
+            }
+        }
+        if (F_near) { F_near[3 * r] = fx; F_near[3 * r + 1] = fy; F_near[3 * r + 2] = fz; }
+        if (E_far) { E_far[3 * r] = ex; E_far[3 * r + 1] = ey; E_far[3 * r + 2] = ez; }
+    }
+    free(cell);
+}
+
+/* Derivative tensors of g(R) = 1/|R| up to fourth order at R (full,
+ * symmetric; T1[a], T2[a][b], T3[a][b][c], T4[a][b][c][d]):
+ *   d_a g       = -R_a / R^3
+ *   d_ab g      = (3 R_a R_b - R^2 delta_ab) / R^5
+ *   d_abc g     = -15 R_a R_b R_c / R^7 + 3 (delta_ab R_c + delta_ac R_b + delta_bc R_a) / R^5
+ *   d_abcd g    = 105 R_a R_b R_c R_d / R^9
+ *                 - 15 (delta_ab R_c R_d + delta_ac R_b R_d + delta_ad R_b R_c
+ *                       + delta_bc R_a R_d + delta_bd R_a R_c + delta_cd R_a R_b) / R^7
+ *                 + 3 (delta_ab delta_cd + delta_ac delta_bd + delta_ad delta_bc) / R^5 */
+static void inv_r_derivs(const double R[3], double T1[3], double T2[3][3], double T3[3][3][3],
+                         double T4[3][3][3][3]) {
+    const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+    const double r = sqrt(r2);
+    const double i3 = 1.0 / (r2 * r), i5 = i3 / r2, i7 = i5 / r2, i9 = i7 / r2;
+#define D(a, b) ((a) == (b) ? 1.0 : 0.0)
+    for (int a = 0; a < 3; ++a) {
+        T1[a] = -R[a] * i3;
+        for (int b = 0; b < 3; ++b) {
+            T2[a][b] = 3.0 * R[a] * R[b] * i5 - r2 * D(a, b) * i5;
+            for (int c = 0; c < 3; ++c) {
+                T3[a][b][c] = -15.0 * R[a] * R[b] * R[c] * i7 +
+                              3.0 * (D(a, b) * R[c] + D(a, c) * R[b] + D(b, c) * R[a]) * i5;
+                for (int d = 0; d < 3; ++d)
+                    T4[a][b][c][d] =
+                        105.0 * R[a] * R[b] * R[c] * R[d] * i9 -
+                        15.0 * (D(a, b) * R[c] * R[d] + D(a, c) * R[b] * R[d] +
+                                D(a, d) * R[b] * R[c] + D(b, c) * R[a] * R[d] +
+                                D(b, d) * R[a] * R[c] + D(c, d) * R[a] * R[b]) * i7 +
+                        3.0 * (D(a, b) * D(c, d) + D(a, c) * D(b, d) + D(a, d) * D(b, c)) * i5;
+            }
+        }
+    }
+#undef D
+}
+
+/* Local expansion at each cell centre.  A source cell with moments (Q, P)
+ * about its centre c_s has the potential phi(x) = Q g(R) - P_a d_a g(R),
+ * R = x - c_s (the expansion of sum q_hat / |x - x_j| to dipole order), so
+ *   E_c  = -d_c phi    = -Q d_c g   + P_a d_ac g
+ *   J_cd = d_d E_c     = -Q d_cd g  + P_a d_acd g
+ *   H_cde = d_de E_c   = -Q d_cde g + P_a d_acde g
+ * evaluated at R = c_t - c_s and summed over the cells outside the block. */
+void ldo_ff_local(int G, double L, int B, const double* mom, double* out) {
+    const int half = B / 2;
+    const size_t M = (size_t)G * G * G;
+    static const int J_IDX[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    static const int H_IDX[10][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2},
+                                     {0, 2, 2}, {1, 1, 1}, {1, 1, 2}, {1, 2, 2}, {2, 2, 2}};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (size_t t = 0; t < M; ++t) {
+        const int tc[3] = {(int)(t % G), (int)((t / G) % G), (int)(t / ((size_t)G * G))};
+        double E[3] = {0, 0, 0}, J[3][3] = {{0}}, H[3][3][3] = {{{0}}};
+        for (size_t s = 0; s < M; ++s) {
+            const int sc[3] = {(int)(s % G), (int)((s / G) % G), (int)(s / ((size_t)G * G))};
+            if (abs(sc[0] - tc[0]) <= half && abs(sc[1] - tc[1]) <= half &&
+                abs(sc[2] - tc[2]) <= half)
+                continue;
+            const double Q = mom[4 * s], P[3] = {mom[4 * s + 1], mom[4 * s + 2], mom[4 * s + 3]};
+            if (Q == 0.0 && P[0] == 0.0 && P[1] == 0.0 && P[2] == 0.0) continue;
+            double R[3], T1[3], T2[3][3], T3[3][3][3], T4[3][3][3][3];
+            for (int k = 0; k < 3; ++k) R[k] = centre(tc[k], G, L) - centre(sc[k], G, L);
+            inv_r_derivs(R, T1, T2, T3, T4);
+            for (int c = 0; c < 3; ++c) {
+                E[c] += -Q * T1[c];
+                for (int a = 0; a < 3; ++a) E[c] += P[a] * T2[a][c];
+                for (int d = 0; d < 3; ++d) {
+                    J[c][d] += -Q * T2[c][d];
+                    for (int a = 0; a < 3; ++a) J[c][d] += P[a] * T3[a][c][d];
+                    for (int e = 0; e < 3; ++e) {
+                        H[c][d][e] += -Q * T3[c][d][e];
+                        for (int a = 0; a < 3; ++a) H[c][d][e] += P[a] * T4[a][c][d][e];
+                    }
+                }
+            }
+        }
+        double* o = out + 19 * t;
+        for (int k = 0; k < 3; ++k) o[k] = E[k];
+        for (int k = 0; k < 6; ++k) o[3 + k] = J[J_IDX[k][0]][J_IDX[k][1]];
+        for (int k = 0; k < 10; ++k) o[9 + k] = H[H_IDX[k][0]][H_IDX[k][1]][H_IDX[k][2]];
+    }
+}
+
+void ldo_ff_local_eval(int64_t n, const double* x, int G, double L, const double* loc,
+                       double* E) {
+    static const int J_OF[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    for (int64_t i = 0; i < n; ++i) {
+        int c[3];
+        cell_of(&x[3 * i], G, L, c);
+        const double* o = loc + 19 * (((size_t)c[2] * G + c[1]) * G + c[0]);
+        const double d[3] = {x[3 * i] - centre(c[0], G, L), x[3 * i + 1] - centre(c[1], G, L),
+                             x[3 * i + 2] - centre(c[2], G, L)};
+        for (int a = 0; a < 3; ++a) {
+            double v = o[a];
+            for (int b = 0; b < 3; ++b) {
+                /* J[a][b] is dE_a/dx_b; the packed J is symmetric */
+                v += o[3 + J_OF[a][b]] * d[b];
+                for (int e = 0; e < 3; ++e) {
+                    /* H[a][b][e]: sort the three indices to find the packed slot */
+                    int k[3] = {a, b, e}, tmp;
+                    if (k[0] > k[1]) { tmp = k[0]; k[0] = k[1]; k[1] = tmp; }
+                    if (k[1] > k[2]) { tmp = k[1]; k[1] = k[2]; k[2] = tmp; }
+                    if (k[0] > k[1]) { tmp = k[0]; k[0] = k[1]; k[1] = tmp; }
+                    int slot = 0;
+                    for (int u = 0; u <= 2; ++u)
+                        for (int w = u; w <= 2; ++w)
+                            for (int z = w; z <= 2; ++z) {
+                                if (u == k[0] && w == k[1] && z == k[2]) goto found;
+                                ++slot;
+                            }
+                found:
+                    v += 0.5 * o[9 + slot] * d[b] * d[e];
+                }
+            }
+            E[3 * i + a] = v;
+        }
+    }
+}
+
 /* MLP features of each particle: the B^3 block of cell moments around its
  * cell (cells outside the grid read as zero), ordered dz-major then dy then
  * dx, each cell as (Q / sq, Px / (sq h), Py / (sq h), Pz / (sq h)), then the

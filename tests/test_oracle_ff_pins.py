@@ -1,8 +1,10 @@
 """Pins for the learned-far-field part of the oracle: BF16 rounding against
 torch, moments against conservation and single-particle dipoles, the coarse
-multipole field against exact point-charge sums, the near/far split against
-the (pinned) full pair sum, the feature layout, and the MLP forward /
-backward against torch (CPU, FP64) and finite differences."""
+multipole field against exact point-charge sums, the near/far splits (radial
+and block) against the (pinned) full pair sum and brute force, the local
+expansion against finite differences of Coulomb's law, Laplace's equation
+and its Taylor remainder, the feature layout, and the MLP forward / backward
+against torch (CPU, FP64) and finite differences."""
 import math
 
 import numpy as np
@@ -118,6 +120,165 @@ def test_split_sums_to_full_pair_force(oracle_lib):
     assert np.all(np.abs(qh[:, None] * Ef - Fc) <= 1e-12 * Sc[:, None] + 1e-15)
     Fn, Ef = oracle_lib.ff_split(x, w.type, w.charge, w.params, 1e9)
     assert np.all(Ef == 0)
+
+
+def test_split_block_partition_and_membership(oracle_lib):
+    """The block split partitions the pair sum (F_near + q_hat E_far = the
+    pinned full pair force), and E_far is the brute-force Coulomb field of
+    exactly the particles whose cells lie outside the B^3 block."""
+    w = W.config_medium(n=600, seed=4)
+    x = w.pos.astype(np.float64)
+    F, S, _ = oracle_lib.pair_forces(x, w.type, w.charge, w.params)
+    qh = oracle_lib.qhat(w.charge, w.params)
+    L = float(np.abs(x).max()) * 1.001
+    for G, B in ((8, 5), (16, 3), (6, 1), (4, 7)):
+        Fn, Ef = oracle_lib.ff_split_block(x, w.type, w.charge, w.params, G, L, B)
+        assert np.all(np.abs(Fn + qh[:, None] * Ef - F) <= 1e-12 * S[:, None] + 1e-15)
+        h = 2 * L / G
+        cell = np.clip(np.floor((x + L) / h).astype(int), 0, G - 1)
+        for i in (0, 17, 333, 599):
+            out = np.abs(cell - cell[i]).max(1) > B // 2
+            d = x[i] - x[out]
+            r = np.linalg.norm(d, axis=1)
+            ref = (qh[out, None] * d / r[:, None] ** 3).sum(0)
+            assert np.allclose(Ef[i], ref, rtol=1e-11, atol=1e-14)
+    # a block covering the whole grid: nothing is far
+    Fn, Ef = oracle_lib.ff_split_block(x, w.type, w.charge, w.params, 4, L, 7)
+    assert np.all(Ef == 0)
+
+
+def _cell_centre(k, G, L):
+    h = 2 * L / G
+    return np.array([(k % G + 0.5) * h - L, ((k // G) % G + 0.5) * h - L,
+                     (k // G ** 2 + 0.5) * h - L])
+
+
+def _fd_derivs(field, c, eps):
+    """Central finite differences of a vector field: E(c), J[a][b] = dE_a/dx_b
+    and H[a][b][e] = d2E_a/dx_b dx_e."""
+    I = np.eye(3)
+    E0 = field(c)
+    J = np.zeros((3, 3))
+    H = np.zeros((3, 3, 3))
+    for b in range(3):
+        J[:, b] = (field(c + eps * I[b]) - field(c - eps * I[b])) / (2 * eps)
+        for e in range(3):
+            H[:, b, e] = (field(c + eps * (I[b] + I[e])) - field(c + eps * (I[b] - I[e]))
+                          - field(c - eps * (I[b] - I[e])) + field(c - eps * (I[b] + I[e]))) \
+                / (4 * eps * eps)
+    return E0, J, H
+
+
+_JI = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+_HI = [(0, 0, 0), (0, 0, 1), (0, 0, 2), (0, 1, 1), (0, 1, 2), (0, 2, 2), (1, 1, 1), (1, 1, 2),
+       (1, 2, 2), (2, 2, 2)]
+
+
+def _unpack(o):
+    J = np.array([o[3 + _JI.index(tuple(sorted((a, b))))] for a in range(3) for b in range(3)])
+    H = np.array([o[9 + _HI.index(tuple(sorted((a, b, e))))]
+                  for a in range(3) for b in range(3) for e in range(3)])
+    return o[:3], J.reshape(3, 3), H.reshape(3, 3, 3)
+
+
+@pytest.mark.parametrize("kind", ["charge", "dipole"])
+def test_local_expansion_matches_finite_differences(oracle_lib, kind):
+    """A point charge at a cell centre (monopole only) and a tight +q/-q pair
+    about a cell centre (dipole only): the local expansion's E, J and H at a
+    distant cell centre are the exact field's value and its first and second
+    derivatives there (central finite differences of Coulomb's law)."""
+    G, L = 16, 32.0
+    h = 2 * L / G
+    s = 3 * G * G + 4 * G + 5
+    cs = _cell_centre(s, G, L)
+    if kind == "charge":
+        src, q = cs[None], np.array([1.7])
+    else:
+        d = np.array([0.3, -0.2, 0.25]) * 1e-3 * h
+        src, q = np.stack([cs + d / 2, cs - d / 2]), np.array([2.0, -2.0])
+    m = oracle_lib.ff_moments(src, q, G, L)
+    loc = oracle_lib.ff_local(m, G, L, 5)
+
+    def field(pt):
+        r = pt[None] - src
+        return (q[:, None] * r / np.linalg.norm(r, axis=1)[:, None] ** 3).sum(0)
+
+    for t in (12 * G * G + 9 * G + 13, 3 * G * G + 4 * G + 11, 0, G ** 3 - 1):
+        ct = _cell_centre(t, G, L)
+        E, J, H = _unpack(loc[t])
+        E0, J0, H0 = _fd_derivs(field, ct, 0.005 * h)
+        # finite-difference truncation is O((eps / r)^2) ~ 1e-5 of each tensor
+        assert np.allclose(E, E0, rtol=0, atol=1e-7 * np.abs(E0).max())
+        assert np.allclose(J, J0, rtol=0, atol=1e-4 * np.abs(J0).max())
+        assert np.allclose(H, H0, rtol=0, atol=1e-4 * np.abs(H0).max())
+    # inside the block: nothing
+    assert np.all(loc[s] == 0)
+
+
+def test_local_expansion_is_harmonic_and_converges(oracle_lib):
+    """The far field is divergence- and curl-free at every cell centre
+    (J traceless and symmetric by construction, H traces zero), and the
+    expansion evaluated at an offset d from the centre of a cell far from a
+    single source has error O(|d|^3)."""
+    G, L = 12, 30.0
+    x = ball(3000, 28.0, 8)
+    q = np.where(np.arange(3000) % 2 == 0, 1.0, -0.7)
+    m = oracle_lib.ff_moments(x, q, G, L)
+    loc = oracle_lib.ff_local(m, G, L, 5)
+    occ = np.flatnonzero(np.abs(loc).sum(1))
+    for t in occ[::37]:
+        E, J, H = _unpack(loc[t])
+        scale_j = np.abs(J).max()
+        scale_h = np.abs(H).max()
+        assert abs(np.trace(J)) <= 1e-12 * scale_j
+        for d in range(3):
+            assert abs(H[0, 0, d] + H[1, 1, d] + H[2, 2, d]) <= 1e-12 * scale_h
+    # Taylor remainder: one source charge, target cell 5 cells away
+    G, L = 16, 32.0
+    h = 2 * L / G
+    s = 8 * G * G + 8 * G + 2
+    cs = _cell_centre(s, G, L)
+    m = oracle_lib.ff_moments(cs[None], np.array([1.0]), G, L)
+    loc = oracle_lib.ff_local(m, G, L, 5)
+    t = 8 * G * G + 8 * G + 7
+    ct = _cell_centre(t, G, L)
+    u = np.array([0.31, -0.22, 0.4])
+    errs = []
+    for f in (0.4, 0.2, 0.1):
+        pt = ct + f * h * u
+        approx = oracle_lib.ff_local_eval(pt[None], G, L, loc)[0]
+        r = pt - cs
+        exact = r / np.linalg.norm(r) ** 3
+        errs.append(np.linalg.norm(approx - exact))
+    # cubic remainder: halving d divides the error by about 8
+    assert 6.0 < errs[0] / errs[1] < 10.0 and 6.0 < errs[1] / errs[2] < 10.0
+    assert np.allclose(oracle_lib.ff_local_eval(ct[None], G, L, loc)[0], loc[t, :3], rtol=1e-15)
+
+
+def test_local_expansion_accuracy_on_a_droplet(oracle_lib):
+    """The method's own error: exact block near field plus the local
+    expansion of the far cells' monopoles and dipoles reproduces the exact
+    Coulomb force within the dipole-truncation bound (median well below
+    1e-2 of the force, at a few cells per block half width)."""
+    w = W.config_medium(n=6000, seed=6)
+    x = w.pos.astype(np.float64)
+    qh = oracle_lib.qhat(w.charge, w.params)
+    L = float(np.float32(np.abs(w.pos).max()) * np.float32(1 + 2 ** -10))
+    G, B = 12, 5
+    rows = np.arange(0, 6000, 7)
+    Fn, Ef = oracle_lib.ff_split_block(x, w.type, w.charge, w.params, G, L, B, rows=rows)
+    m = oracle_lib.ff_moments(x, qh, G, L)
+    loc = oracle_lib.ff_local(m, G, L, B)
+    El = oracle_lib.ff_local_eval(x[rows], G, L, loc)
+    F = Fn + qh[rows, None] * Ef
+    rel = np.linalg.norm(qh[rows, None] * (El - Ef), axis=1) / np.linalg.norm(F, axis=1)
+    # the centre-only coarse field is far worse: the expansion is doing work
+    Ec = oracle_lib.ff_coarse(m, G, L, B)
+    cell = np.clip(np.floor((x[rows] + L) / (2 * L / G)).astype(int), 0, G - 1)
+    k = (cell[:, 2] * G + cell[:, 1]) * G + cell[:, 0]
+    relc = np.linalg.norm(qh[rows, None] * (Ec[k] - Ef), axis=1) / np.linalg.norm(F, axis=1)
+    assert np.median(rel) < 3e-3
+    assert np.median(relc) > 3 * np.median(rel)
 
 
 def test_feature_layout(oracle_lib):
