@@ -50,6 +50,8 @@ def parse():
                     help="learned: direct steps between training snapshots")
     ap.add_argument("--epochs", type=int, default=20, help="learned: training epochs")
     ap.add_argument("--near-cut", type=float, default=8.0, help="learned: near cutoff r_c")
+    ap.add_argument("--near-mode", default="block", choices=["block", "radial"],
+                    help="learned: exact near part over the 5^3 block of grid cells, or r < r_c")
     ap.add_argument("--autotune", action="store_true",
                     help="search the pair kernel launch shape before timing")
     ap.add_argument("--graph", type=int, default=0,
@@ -182,7 +184,8 @@ def bench_learned(a, torch, ldrop, W):
     t0 = time.perf_counter()
     wt = W.config_learned(n=a.n, seed=105)
     tr = ldrop.System.from_workload(wt)
-    tr.ff_enable(near_cut=a.near_cut)
+    mode = ldrop.NEAR_BLOCK if a.near_mode == "block" else ldrop.NEAR_RADIAL
+    tr.ff_enable(near_cut=a.near_cut, near_mode=mode)
     tr.ff_collect(reset=True, max_snapshots=a.snapshots)
     for _ in range(a.snapshots - 1):
         tr.step(a.snap_every, wt.dt)
@@ -195,7 +198,7 @@ def bench_learned(a, torch, ldrop, W):
     del tr
     we = W.config_learned(n=a.n, seed=5)
     ev = ldrop.System.from_workload(we)
-    ev.ff_enable(near_cut=a.near_cut)
+    ev.ff_enable(near_cut=a.near_cut, near_mode=mode)
     ev.ff_set_weights(weights, sq, scale)
     ev.step(a.warmup, we.dt)
     ms_direct = timed(ev, a.steps, we.dt)
@@ -220,9 +223,11 @@ def bench_learned(a, torch, ldrop, W):
         "judge_tol": 1e-3, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "higher_is_better": True, "dtype": "f32 pair math, bf16 MLP, f64 totals",
         "data": "synthetic",
-        "config": {"workload": "learned: N=250000 medium composition, near cell list r_c, "
-                               "32^3 moments, 5^3 block, MLP 503-128-128-3",
-                   "near_cut": a.near_cut, "snapshots": a.snapshots,
+        "config": {"workload": "learned: N=250000 medium composition, 32^3 moments, 5^3 block, "
+                               "MLP 503-128-128-3",
+                   "near_mode": a.near_mode,
+                   "near_cut": a.near_cut if a.near_mode == "radial" else None,
+                   "snapshots": a.snapshots,
                    "snap_every": a.snap_every, "epochs": a.epochs},
         "training": {**rep, "collect_s": collect_s, "train_s": train_s},
         "direct_pair_interactions_per_s": pairs * 1e3 / ms_direct,

@@ -248,25 +248,38 @@ ld_status ld_kernel_time(ld_ctx* ctx, int64_t* launches, double* total_ms);
 /* Learned far field                                                        */
 /* ---------------------------------------------------------------------- */
 
-/* The pair sum split at near_cut r_c: pairs with r < r_c are summed exactly
- * (LJ + Coulomb) over a cell list of side >= r_c; the Coulomb sum over
- * r >= r_c is replaced by q_i (E_coarse + E_mlp).  E_coarse is the field at
- * the centre of i's cell of a grid^3 grid over the cube [-L, L]^3,
- * L = max_i max(|x_i|, |y_i|, |z_i|) (1 + 2^-10) in FP32, from the monopole
- * Q = sum q_hat and dipole P = sum q_hat (x - centre) of every cell outside
- * the block^3 neighbourhood of that cell.  The MLP (K = 4 block^3 + 3 inputs
- * -> hidden -> hidden -> 3, SiLU, BF16 operands, FP32 accumulation) reads
- * the neighbourhood's (Q / sq, P / (sq h)) (cells ordered z-major, then y,
- * then x; zero outside the grid) and the offset (x - centre) / h, and
- * predicts the remaining far field divided by out_scale.  q_hat = q sqrt(kT
- * l_B). */
+/* The pair sum split into an exact near part and a far Coulomb part,
+ * F_i = F_near + q_hat_i (E_coarse + E_mlp), on a grid^3 grid over the cube
+ * [-L, L]^3, L = max_i max(|x_i|, |y_i|, |z_i|) (1 + 2^-10) in FP32; a
+ * particle's cell is floor((x + L) / h), h = 2L / grid, clamped to the grid.
+ * Cell moments: Q = sum q_hat and dipole P = sum q_hat (x - centre).
+ *
+ * near_mode 0 (radial): pairs with r < r_c are summed exactly (LJ +
+ *   Coulomb) over a cell list of side >= r_c; E_coarse is the field at the
+ *   centre of i's cell from the monopole + dipole of every cell outside the
+ *   block^3 neighbourhood of that cell; the network predicts the rest of the
+ *   Coulomb field of the pairs with r >= r_c.
+ * near_mode 1 (block): the Coulomb pairs with j in i's block^3 neighbourhood
+ *   (and every LJ pair) are summed exactly; E_coarse is the second-order
+ *   Taylor expansion about i's cell centre of the monopole + dipole field of
+ *   every cell outside the neighbourhood, evaluated at x_i; the network
+ *   predicts the rest of the field of the particles outside the block.
+ *   near_cut is unused.
+ *
+ * The MLP (K = 4 block^3 + 3 inputs -> hidden -> hidden -> 3, SiLU, BF16
+ * operands, FP32 accumulation) reads the neighbourhood's (Q / sq,
+ * P / (sq h)) (cells ordered z-major, then y, then x; zero outside the grid)
+ * and the offset (x - centre) / h, and predicts the remaining far field
+ * divided by out_scale.  q_hat = q sqrt(kT l_B). */
 typedef struct {
-    double near_cut;        /* r_c (>= the largest LJ range) */
+    double near_cut;        /* r_c (>= the largest LJ range), near_mode 0 */
     int32_t grid;           /* G, 4..64 */
     int32_t block;          /* B, odd, 1..7 */
     int32_t hidden;         /* H, multiple of 16, 16..256 */
     int32_t judge_every;    /* steps between judge evaluations (mode 2) */
     double judge_tol;       /* median relative force error allowed */
+    int32_t near_mode;      /* 0 radial cutoff r_c, 1 the block^3 cells */
+    int32_t reserved;       /* 0 */
 } ld_ff_config;
 
 typedef struct {
@@ -309,8 +322,9 @@ ld_status ld_ff_get_weights(ld_ctx* ctx, float* w, int64_t count, double* sq, do
 ld_status ld_ff_grid(ld_ctx* ctx, double* L, int32_t* near_cells);
 
 /* Parts of the learned pair force at the current state, [n*3] FP64 in
- * original order: 0 near (exact, r < r_c), 1 q E_coarse, 2 q E_mlp, 3 their
- * sum (the learned pair force), 4 the exact far force (all r >= r_c). */
+ * original order: 0 near (exact), 1 q E_coarse, 2 q E_mlp, 3 their sum (the
+ * learned pair force), 4 the exact far force (the Coulomb force of the pairs
+ * not in the near part). */
 ld_status ld_ff_forces(ld_ctx* ctx, int32_t part, double* out);
 
 /* MLP output [m*3] for m feature rows X [m*K] (FP32, host or device). */

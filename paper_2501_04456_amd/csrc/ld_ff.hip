@@ -1,23 +1,35 @@
-// Learned far field: the all-pairs sum split at a near cutoff r_c.
+// Learned far field: the all-pairs sum split into an exact near part and a
+// far Coulomb part on a G^3 grid over the droplet,
 //
-//   near (r < r_c)  exact LJ + Coulomb over a cell list of side >= r_c
-//   far  (r >= r_c) q_i (E_coarse(cell) + E_mlp(features))
+//   F_i = F_near(i) + q_i (E_coarse(i) + E_mlp(features of i)).
 //
-// E_coarse is the field at the centre of the particle's cell of a G^3 grid
-// over the droplet from the monopole + dipole of every cell outside the
-// B^3 block around it.  The MLP (4 B^3 + 3 -> H -> H -> 3, SiLU, BF16
-// operands on the matrix cores, FP32 accumulation) sees the normalised
-// moments of that B^3 block and the particle's offset in its cell, and
-// predicts the rest of the far field.  Its first layer is evaluated once per
-// occupied cell (the moment part of the input depends only on the cell) and
-// finished per particle with the three offset columns.
+// Radial mode: F_near sums the pairs with r < r_c over a cell list of side
+// >= r_c; E_coarse is the field at the centre of i's grid cell from the
+// monopole + dipole of every cell outside the B^3 block around it.
 //
-// Training targets come from the exact far field (all pairs with r >= r_c)
-// minus the coarse term, on snapshots of the running system; the network is
-// trained on the GPU by the same MFMA products (forward, backward) and Adam.
-// Every judge_every steps a judge compares the learned pair forces with
-// direct summation on the same state; if the median relative error exceeds
-// the tolerance the next window runs direct summation.
+// Block mode: F_near sums the Coulomb pairs whose j lies in the B^3 block of
+// grid cells around i's cell (and every LJ pair); E_coarse is the
+// second-order Taylor expansion about the centre of i's cell of the
+// monopole + dipole field of every cell outside the block, evaluated at x_i.
+// The near part runs over row tiles: slots are sorted by grid cell (z, y, x),
+// so the cells x0..x1 of one (y, z) row are one contiguous slot range, and a
+// tile of at most 64 slots of one row needs only the (2W+1)^2 rows around it,
+// each as one contiguous range streamed through LDS.
+//
+// The MLP (4 B^3 + 3 -> H -> H -> 3, SiLU, BF16 operands on the matrix cores,
+// FP32 accumulation) sees the normalised moments of the B^3 block and the
+// particle's offset in its cell, and predicts the rest of the far field.  Its
+// first layer is evaluated once per occupied cell (the moment part of the
+// input depends only on the cell) and finished per particle with the three
+// offset columns.
+//
+// Training targets come from the exact far field (the Coulomb field of the
+// pairs outside the near part) minus the coarse term, on snapshots of the
+// running system; the network is trained on the GPU by the same MFMA products
+// (forward, backward) and Adam.  Every judge_every steps a judge compares
+// the learned pair forces with direct summation on the same state; if the
+// median relative error exceeds the tolerance the next window runs direct
+// summation.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -36,13 +48,16 @@ constexpr int kMaxNearCells = 64;      // near cell list: at most 64^3 cells
 struct FFGrid {
     double L;       // half width of the cube [-L, L]^3 covering every particle
     double h;       // moment grid cell side 2L / G
-    double hn;      // near cell side 2L / Gn (>= r_c)
-    int Gn;         // near cells per axis
-    int pad;
+    double hn;      // near cell side: 2L / Gn (>= r_c), or h in block mode
+    int Gn;         // near cells per axis (G in block mode)
+    int W;          // block mode: rows searched around a tile (>= B/2, covers LJ)
 };
+
+constexpr int kLoc = 19;               // E (3), J (6), H (10) per cell
 
 struct FarField {
     ld_ff_config cfg{};
+    double rlj = 0.0;                  // largest LJ range
     int K = 0, Kp = 0, Op = 16, H = 0;
     size_t offW1 = 0, offb1 = 0, offW2 = 0, offb2 = 0, offW3 = 0, offb3 = 0, nW = 0;
     float sq = 1.f, out_scale = 1.f;
@@ -61,7 +76,12 @@ struct FarField {
     int* occ = nullptr;                // [G^3] compacted occupied cells
     int* cell2occ = nullptr;           // [G^3]
     int* nocc = nullptr;               // [1]
-    double* Ecell = nullptr;           // [G^3 * 3]
+    double* Ecell = nullptr;           // [G^3 * 3] centre field, or [G^3 * 19] expansion
+    double* Ep = nullptr;              // [3][n] coarse field at each particle
+    int* cfirst = nullptr;             // [G^3 + 1] first slot of each cell (block mode)
+    int4* tiles = nullptr;             // row tiles (block mode)
+    int* ntiles = nullptr;
+    int max_tiles = 0;
     float* Xc = nullptr;               // [G^3 * Kp]
     float* Ac = nullptr;               // [G^3 * H]
     float* h1 = nullptr;               // [n * H]
@@ -125,19 +145,32 @@ __global__ __launch_bounds__(kB) void k_absmax_part(const float4* __restrict__ p
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// L = max |coordinate| x (1 + 2^-10) in FP32, then the cell sides.
-__global__ void k_grid(const float* part, int nparts, double rc, int G, FFGrid* g) {
+// L = max |coordinate| x (1 + 2^-10) in FP32, then the cell sides.  In
+// block mode the near cells are the grid cells and W rows around a tile
+// cover both the block (B/2) and the largest LJ range rlj.
+__global__ void k_grid(const float* part, int nparts, double rc, int G, int block_mode, int B,
+                       double rlj, FFGrid* g) {
     float m = 0.f;
     for (int b = 0; b < nparts; ++b) m = fmaxf(m, part[b]);
     m = fmaxf(m, 1e-3f);
     const float Lf = m * 1.0009765625f;
     const double L = (double)Lf;
-    int Gn = (int)floor(2.0 * L / rc);
-    Gn = Gn < 1 ? 1 : (Gn > kMaxNearCells ? kMaxNearCells : Gn);
+    const double h = 2.0 * L / G;
     g->L = L;
-    g->h = 2.0 * L / G;
-    g->hn = 2.0 * L / Gn;
-    g->Gn = Gn;
+    g->h = h;
+    if (block_mode) {
+        int W = (int)ceil(rlj / h);
+        W = W < B / 2 ? B / 2 : W;
+        g->W = W > G ? G : W;
+        g->hn = h;
+        g->Gn = G;
+    } else {
+        int Gn = (int)floor(2.0 * L / rc);
+        Gn = Gn < 1 ? 1 : (Gn > kMaxNearCells ? kMaxNearCells : Gn);
+        g->hn = 2.0 * L / Gn;
+        g->Gn = Gn;
+        g->W = 0;
+    }
 }
 
 __device__ __forceinline__ int cell1(double x, double L, double h, int G) {
@@ -147,7 +180,10 @@ __device__ __forceinline__ int cell1(double x, double L, double h, int G) {
 
 // ---- near cell list ------------------------------------------------------
 
-__global__ __launch_bounds__(kB) void k_near_keys(const float4* __restrict__ pos, int n,
+// Cell keys from the FP64 positions (hi + lo), so that cell membership
+// agrees with the moments and offsets.
+__global__ __launch_bounds__(kB) void k_near_keys(const float4* __restrict__ pos,
+                                                  const float4* __restrict__ lo, int n,
                                                   int n_pow2, const FFGrid* g,
                                                   unsigned long long* keys) {
     const int s = blockIdx.x * kB + threadIdx.x;
@@ -156,10 +192,11 @@ __global__ __launch_bounds__(kB) void k_near_keys(const float4* __restrict__ pos
         keys[s] = ~0ull;
         return;
     }
-    const float4 h = pos[s];
+    const float4 h = pos[s], l = lo[s];
     const int Gn = g->Gn;
-    const int cx = cell1(h.x, g->L, g->hn, Gn), cy = cell1(h.y, g->L, g->hn, Gn),
-              cz = cell1(h.z, g->L, g->hn, Gn);
+    const int cx = cell1((double)h.x + (double)l.x, g->L, g->hn, Gn),
+              cy = cell1((double)h.y + (double)l.y, g->L, g->hn, Gn),
+              cz = cell1((double)h.z + (double)l.z, g->L, g->hn, Gn);
     const unsigned c = (unsigned)((cz * Gn + cy) * Gn + cx);
     keys[s] = ((unsigned long long)c << 32) | (unsigned)s;
 }
@@ -255,6 +292,165 @@ __global__ __launch_bounds__(kB) void k_near(const float4* __restrict__ pos,
     F[i] = -qi * Fx - Lx;
     F[(size_t)n + i] = -qi * Fy - Ly;
     F[2 * (size_t)n + i] = -qi * Fz - Lz;
+}
+
+// ---- block mode: row tiles and the block near field ----------------------
+
+// One workgroup of 1024: cfirst[c] = slots in cells before c (cfirst[M] = n),
+// then the row tiles: every (y, z) row's slot range cut into pieces of at
+// most 64 slots, tile = (row, first slot, end slot).
+__global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cstart,
+                                                      const int* __restrict__ cend, int G,
+                                                      int* cfirst, int4* tiles, int* ntiles) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int M = G * G * G, R = G * G;
+    // exclusive scan of the cell counts
+    const int per = (M + 1023) / 1024;
+    const int c0 = min(M, t * per), c1 = min(M, c0 + per);
+    int mine = 0;
+    for (int c = c0; c < c1; ++c) mine += cend[c] - cstart[c];
+    part[t] = mine;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - mine;
+    for (int c = c0; c < c1; ++c) {
+        cfirst[c] = run;
+        run += cend[c] - cstart[c];
+    }
+    if (t == 1023) cfirst[M] = part[1023];
+    __syncthreads();
+    // tiles per row, scanned the same way
+    const int rper = (R + 1023) / 1024;
+    const int r0 = min(R, t * rper), r1 = min(R, r0 + rper);
+    int nt = 0;
+    for (int r = r0; r < r1; ++r) nt += (cfirst[(r + 1) * G] - cfirst[r * G] + 63) / 64;
+    __syncthreads();
+    part[t] = nt;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int k = part[t] - nt;
+    for (int r = r0; r < r1; ++r) {
+        const int a = cfirst[r * G], b = cfirst[(r + 1) * G];
+        for (int s0 = a; s0 < b; s0 += 64) tiles[k++] = make_int4(r, s0, min(b, s0 + 64), 0);
+    }
+    if (t == 1023) *ntiles = part[1023];
+}
+
+// Block near field, one wavefront per row tile: Coulomb of every j in the
+// B^3 block of i's cell, LJ of every pair within its range.  The tile's
+// lanes share one (y, z) row, so the rows dy, dz in [-W, W] around it hold
+// every partner; cells x_first - W .. x_last + W of such a row are one
+// contiguous slot range.  FP32 pair terms in blocks of at most 32, FP64
+// totals; LJ terms go to FP64 directly (rare).
+__global__ __launch_bounds__(64) void k_near_block(const float4* __restrict__ pos,
+                                                   const int* __restrict__ typ,
+                                                   const unsigned long long* __restrict__ keys,
+                                                   const FFGrid* g, int G, int half,
+                                                   const int* __restrict__ cfirst,
+                                                   const int4* __restrict__ tiles,
+                                                   const int* __restrict__ ntiles, int n,
+                                                   PairTable tab, double* F) {
+    __shared__ float4 sp[64];
+    __shared__ int sx[64];
+    __shared__ int st[64];
+    __shared__ float ttab[3 * kMaxTypes * kMaxTypes];
+    const int lane = threadIdx.x;
+    if ((int)blockIdx.x >= *ntiles) return;            // uniform per workgroup
+    for (int k = lane; k < kMaxTypes * kMaxTypes; k += 64) {
+        ttab[k] = tab.sig2[k];
+        ttab[kMaxTypes * kMaxTypes + k] = tab.rc2[k];
+        ttab[2 * kMaxTypes * kMaxTypes + k] = tab.e24[k];
+    }
+    const int4 tl = tiles[blockIdx.x];
+    const int row = tl.x, s0 = tl.y, s1 = tl.z;
+    const int i = s0 + lane;
+    const bool live = i < s1;
+    const float4 pi = live ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int ti = live ? typ[i] : 0;
+    const int ix = (int)((unsigned)((live ? keys[i] : keys[s0]) >> 32) % (unsigned)G);
+    const int x_first = (int)((unsigned)(keys[s0] >> 32) % (unsigned)G);
+    const int x_last = (int)((unsigned)(keys[s1 - 1] >> 32) % (unsigned)G);
+    const int ry = row % G, rz = row / G;
+    const int W = g->W;
+    const int T = tab.T;
+    const float rc2max = tab.rc2max;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, Lx = 0.0, Ly = 0.0, Lz = 0.0;
+    for (int dz = -W; dz <= W; ++dz) {
+        const int z = rz + dz;
+        if (z < 0 || z >= G) continue;
+        for (int dy = -W; dy <= W; ++dy) {
+            const int y = ry + dy;
+            if (y < 0 || y >= G) continue;
+            const bool row_in = abs(dy) <= half && abs(dz) <= half;
+            const int base = (z * G + y) * G;
+            const int j0 = cfirst[base + max(0, x_first - W)];
+            const int j1 = cfirst[base + min(G - 1, x_last + W) + 1];
+            for (int jt = j0; jt < j1; jt += 64) {
+                __syncthreads();
+                const int j = jt + lane;
+                if (j < j1) {
+                    sp[lane] = pos[j];
+                    sx[lane] = (int)((unsigned)(keys[j] >> 32) % (unsigned)G);
+                    st[lane] = typ[j];
+                } else {
+                    sp[lane] = make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+                    sx[lane] = -(1 << 20);
+                    st[lane] = 0;
+                }
+                __syncthreads();
+                const int cnt = min(64, j1 - jt);
+                for (int kb = 0; kb < cnt; kb += 32) {
+                    const int ke = min(cnt, kb + 32);
+                    float bx = 0.f, by = 0.f, bz = 0.f;
+                    for (int k = kb; k < ke; ++k) {
+                        const float4 pj = sp[k];
+                        const float ddx = pj.x - pi.x, ddy = pj.y - pi.y, ddz = pj.z - pi.z;
+                        const float r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+                        const bool self = jt + k == i;
+                        const bool inb = row_in && abs(sx[k] - ix) <= half && !self;
+                        const float ri = __builtin_amdgcn_rsqf(r2);
+                        const float w = inb ? (pj.w * ri) * (ri * ri) : 0.f;
+                        bx = fmaf(w, ddx, bx);
+                        by = fmaf(w, ddy, by);
+                        bz = fmaf(w, ddz, bz);
+                        if (r2 < rc2max && !self) {
+                            const int pidx = ti * T + st[k];
+                            if (r2 < ttab[kMaxTypes * kMaxTypes + pidx]) {
+                                const float ir2 = 1.0f / r2;
+                                const float s2 = ttab[pidx] * ir2;
+                                const float s6 = s2 * s2 * s2;
+                                const float gg = ttab[2 * kMaxTypes * kMaxTypes + pidx] * s6 *
+                                                 (2.0f * s6 - 1.0f) * ir2;
+                                Lx += (double)(gg * ddx);
+                                Ly += (double)(gg * ddy);
+                                Lz += (double)(gg * ddz);
+                            }
+                        }
+                    }
+                    Fx += (double)bx;
+                    Fy += (double)by;
+                    Fz += (double)bz;
+                }
+            }
+        }
+    }
+    if (live) {
+        const double qi = (double)pi.w;
+        F[i] = -qi * Fx - Lx;
+        F[(size_t)n + i] = -qi * Fy - Ly;
+        F[2 * (size_t)n + i] = -qi * Fz - Lz;
+    }
 }
 
 // ---- moments, occupancy, coarse field -----------------------------------
@@ -364,6 +560,146 @@ __global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
     }
 }
 
+// Block mode: second-order local expansion at every occupied cell centre of
+// the monopole + dipole field of every occupied cell outside its B^3 block.
+// With R = c_t - c_s, u = 1/|R|, p = P.R, the field of one source cell and
+// its first and second derivatives at c_t are
+//   E_c   = a R_c - u^3 P_c,                         a = Q u^3 + 3 p u^5
+//   J_cd  = b R_c R_d + 3u^5 (P_c R_d + P_d R_c) + a delta_cd,
+//                                                    b = -3 Q u^5 - 15 p u^7
+//   H_cde = c R_c R_d R_e - 15 u^7 (P_c R_d R_e + P_d R_c R_e + P_e R_c R_d)
+//           + delta_cd U_e + delta_ce U_d + delta_de U_c,
+//                                                    c = 15 Q u^7 + 105 p u^9,
+//                                                    U = b R + 3 u^5 P
+// (E = -grad of Q/|R| + P.R/|R|^3; J and H its derivatives).  Stored per
+// cell: E (3), J (xx xy xz yy yz zz), H (xxx xxy xxz xyy xyz xzz yyy yyz yzz
+// zzz).  FP32 terms summed over one LDS tile, FP64 totals.
+constexpr int kLB = 128;
+__global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__ mom,
+                                                      const int* __restrict__ occ,
+                                                      const int* __restrict__ nocc, int G, int B,
+                                                      const FFGrid* g, double* out) {
+    __shared__ float4 sm[kLB];         // (Q, Px, Py, Pz)
+    __shared__ float4 sc[kLB];         // cell index (x, y, z) as floats
+    const int no = *nocc;
+    const int t = blockIdx.x * kLB + threadIdx.x;
+    const bool live = t < no;
+    const int tc = live ? occ[t] : 0;
+    const float tx = (float)(tc % G), ty = (float)((tc / G) % G), tz = (float)(tc / (G * G));
+    const float h = (float)g->h;
+    const float half = (float)(B / 2) + 0.5f;
+    double acc[kLoc];
+#pragma unroll
+    for (int k = 0; k < kLoc; ++k) acc[k] = 0.0;
+    for (int j0 = 0; j0 < no; j0 += kLB) {
+        __syncthreads();
+        const int j = j0 + threadIdx.x;
+        if (j < no) {
+            const int c = occ[j];
+            sm[threadIdx.x] = make_float4((float)mom[4 * c], (float)mom[4 * c + 1],
+                                          (float)mom[4 * c + 2], (float)mom[4 * c + 3]);
+            sc[threadIdx.x] = make_float4((float)(c % G), (float)((c / G) % G),
+                                          (float)(c / (G * G)), 0.f);
+        } else {
+            sm[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+            sc[threadIdx.x] = make_float4(1e6f, 1e6f, 1e6f, 0.f);
+        }
+        __syncthreads();
+        float f[kLoc];
+#pragma unroll
+        for (int k = 0; k < kLoc; ++k) f[k] = 0.f;
+        const int cnt = min(kLB, no - j0);
+        for (int k = 0; k < cnt; ++k) {
+            const float4 cs = sc[k];
+            const float dx = tx - cs.x, dy = ty - cs.y, dz = tz - cs.z;
+            const bool outside = fmaxf(fabsf(dx), fmaxf(fabsf(dy), fabsf(dz))) > half;
+            const float4 m = sm[k];
+            const float Rx = dx * h, Ry = dy * h, Rz = dz * h;
+            const float r2 = fmaf(Rz, Rz, fmaf(Ry, Ry, Rx * Rx));
+            const float u = outside ? __builtin_amdgcn_rsqf(r2) : 0.f;
+            const float u2 = u * u, u3 = u2 * u, u5 = u3 * u2, u7 = u5 * u2, u9 = u7 * u2;
+            const float p = fmaf(m.w, Rz, fmaf(m.z, Ry, m.y * Rx));
+            const float a = fmaf(3.0f * p, u5, m.x * u3);
+            const float b = fmaf(-15.0f * p, u7, -3.0f * m.x * u5);
+            const float c = fmaf(105.0f * p, u9, 15.0f * m.x * u7);
+            const float t5 = 3.0f * u5, c2 = 15.0f * u7;
+            // E
+            f[0] = fmaf(a, Rx, fmaf(-u3, m.y, f[0]));
+            f[1] = fmaf(a, Ry, fmaf(-u3, m.z, f[1]));
+            f[2] = fmaf(a, Rz, fmaf(-u3, m.w, f[2]));
+            // J: (b R_c + 3u^5 P_c) R_d + 3u^5 P_d R_c (+ a on the diagonal)
+            const float Tx = t5 * m.y, Ty = t5 * m.z, Tz = t5 * m.w;
+            const float Ux = fmaf(b, Rx, Tx), Uy = fmaf(b, Ry, Ty), Uz = fmaf(b, Rz, Tz);
+            f[3] += fmaf(Ux, Rx, fmaf(Tx, Rx, a));
+            f[4] += fmaf(Ux, Ry, Ty * Rx);
+            f[5] += fmaf(Ux, Rz, Tz * Rx);
+            f[6] += fmaf(Uy, Ry, fmaf(Ty, Ry, a));
+            f[7] += fmaf(Uy, Rz, Tz * Ry);
+            f[8] += fmaf(Uz, Rz, fmaf(Tz, Rz, a));
+            // H: S_cd Y_e - W_c S_de - W_d S_ce + delta terms, S = R R^T,
+            // W = 15 u^7 P, Y = c R - W
+            const float Wx = c2 * m.y, Wy = c2 * m.z, Wz = c2 * m.w;
+            const float Yx = fmaf(c, Rx, -Wx), Yy = fmaf(c, Ry, -Wy), Yz = fmaf(c, Rz, -Wz);
+            const float Sxx = Rx * Rx, Sxy = Rx * Ry, Sxz = Rx * Rz, Syy = Ry * Ry, Syz = Ry * Rz,
+                        Szz = Rz * Rz;
+            f[9] += fmaf(Sxx, Yx, fmaf(-2.0f * Wx, Sxx, 3.0f * Ux));            // xxx
+            f[10] += fmaf(Sxx, Yy, fmaf(-2.0f * Wx, Sxy, Uy));                 // xxy
+            f[11] += fmaf(Sxx, Yz, fmaf(-2.0f * Wx, Sxz, Uz));                 // xxz
+            f[12] += fmaf(Sxy, Yy, fmaf(-Wx, Syy, fmaf(-Wy, Sxy, Ux)));        // xyy
+            f[13] += fmaf(Sxy, Yz, fmaf(-Wx, Syz, -Wy * Sxz));                 // xyz
+            f[14] += fmaf(Sxz, Yz, fmaf(-Wx, Szz, fmaf(-Wz, Sxz, Ux)));        // xzz
+            f[15] += fmaf(Syy, Yy, fmaf(-2.0f * Wy, Syy, 3.0f * Uy));          // yyy
+            f[16] += fmaf(Syy, Yz, fmaf(-2.0f * Wy, Syz, Uz));                 // yyz
+            f[17] += fmaf(Syz, Yz, fmaf(-Wy, Szz, fmaf(-Wz, Syz, Uy)));        // yzz
+            f[18] += fmaf(Szz, Yz, fmaf(-2.0f * Wz, Szz, 3.0f * Uz));          // zzz
+        }
+#pragma unroll
+        for (int k = 0; k < kLoc; ++k) acc[k] += (double)f[k];
+    }
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < kLoc; ++k) out[(size_t)kLoc * tc + k] = acc[k];
+    }
+}
+
+// Coarse field at every particle: the centre value of its cell (radial mode)
+// or the cell's local expansion at its offset d = x - centre (block mode):
+// E_a + J_ab d_b + (1/2) H_abe d_b d_e.  Out: [3][n] slot order.
+__global__ __launch_bounds__(kB) void k_coarse_eval(const float4* __restrict__ pos,
+                                                    const float4* __restrict__ lo, int n, int G,
+                                                    const FFGrid* g, const double* __restrict__ Ec,
+                                                    int block_mode, double* Ep) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    const float4 hv = pos[s], l = lo[s];
+    const double x = (double)hv.x + (double)l.x, y = (double)hv.y + (double)l.y,
+                 z = (double)hv.z + (double)l.z;
+    const double L = g->L, hh = g->h;
+    const int cx = cell1(x, L, hh, G), cy = cell1(y, L, hh, G), cz = cell1(z, L, hh, G);
+    const size_t c = ((size_t)cz * G + cy) * G + cx;
+    double E[3];
+    if (!block_mode) {
+        E[0] = Ec[3 * c]; E[1] = Ec[3 * c + 1]; E[2] = Ec[3 * c + 2];
+    } else {
+        const double* o = Ec + kLoc * c;
+        const double dx = x - (-L + (cx + 0.5) * hh), dy = y - (-L + (cy + 0.5) * hh),
+                     dz = z - (-L + (cz + 0.5) * hh);
+        const double xx = 0.5 * dx * dx, yy = 0.5 * dy * dy, zz = 0.5 * dz * dz;
+        const double xy = dx * dy, xz = dx * dz, yz = dy * dz;
+        // J: 3 xx, 4 xy, 5 xz, 6 yy, 7 yz, 8 zz
+        // H: 9 xxx, 10 xxy, 11 xxz, 12 xyy, 13 xyz, 14 xzz, 15 yyy, 16 yyz, 17 yzz, 18 zzz
+        E[0] = o[0] + o[3] * dx + o[4] * dy + o[5] * dz + o[9] * xx + o[12] * yy + o[14] * zz +
+               o[10] * xy + o[11] * xz + o[13] * yz;
+        E[1] = o[1] + o[4] * dx + o[6] * dy + o[7] * dz + o[10] * xx + o[15] * yy + o[17] * zz +
+               o[12] * xy + o[13] * xz + o[16] * yz;
+        E[2] = o[2] + o[5] * dx + o[7] * dy + o[8] * dz + o[11] * xx + o[16] * yy + o[18] * zz +
+               o[13] * xy + o[14] * xz + o[17] * yz;
+    }
+    Ep[s] = E[0];
+    Ep[(size_t)n + s] = E[1];
+    Ep[2 * (size_t)n + s] = E[2];
+}
+
 // Moment rows of the B^3 block around each occupied cell (first 4 B^3
 // features of every particle in that cell), zero-padded to Kp.
 __global__ __launch_bounds__(kB) void k_cell_features(const double* __restrict__ mom,
@@ -430,22 +766,18 @@ __global__ __launch_bounds__(kB) void k_layer1(const float4* __restrict__ pos,
     h1[e] = silu_f(z);
 }
 
-// F = F_near + q (E_cell + scale y) into Fpart (slot order) and optional parts.
-__global__ __launch_bounds__(kB) void k_combine(const float4* __restrict__ pos,
-                                                const float4* __restrict__ lo, int n, int G,
-                                                const FFGrid* g, const double* __restrict__ Fn,
-                                                const double* __restrict__ Ecell,
+// F = F_near + q (E_coarse + scale y) into Fpart (slot order) and optional
+// parts.
+__global__ __launch_bounds__(kB) void k_combine(const float4* __restrict__ pos, int n,
+                                                const double* __restrict__ Fn,
+                                                const double* __restrict__ Ep,
                                                 const float* __restrict__ y, int Op, float scale,
                                                 double* Fpart, double* Fc, double* Fm) {
     const int s = blockIdx.x * kB + threadIdx.x;
     if (s >= n) return;
-    const float4 h = pos[s];
-    int c;
-    float off[3];
-    particle_cell(h, lo[s], G, g, &c, off);
-    const double q = (double)h.w;
+    const double q = (double)pos[s].w;
     for (int k = 0; k < 3; ++k) {
-        const double ec = q * Ecell[3 * c + k];
+        const double ec = q * Ep[(size_t)k * n + s];
         const double em = q * (double)scale * (double)y[(size_t)s * Op + k];
         Fpart[(size_t)k * n + s] = Fn[(size_t)k * n + s] + ec + em;
         if (Fc) Fc[(size_t)k * n + s] = ec;
@@ -486,12 +818,59 @@ __global__ __launch_bounds__(kB) void k_far_exact(const float4* __restrict__ pos
     }
 }
 
+// Exact Coulomb field of the particles outside the B^3 block of each
+// particle's cell (no q_i factor); cells from the sorted keys.
+__global__ __launch_bounds__(kB) void k_far_exact_block(const float4* __restrict__ pos,
+                                                        const unsigned long long* __restrict__ keys,
+                                                        int n, int G, int half, double* E) {
+    __shared__ float4 sp[kB];
+    __shared__ int4 sc[kB];
+    const int i = blockIdx.x * kB + threadIdx.x;
+    const float4 pi = i < n ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const unsigned ci = i < n ? (unsigned)(keys[i] >> 32) : 0u;
+    const int ix = (int)(ci % G), iy = (int)((ci / G) % G), iz = (int)(ci / (G * G));
+    double Ex = 0.0, Ey = 0.0, Ez = 0.0;
+    for (int j0 = 0; j0 < n; j0 += kB) {
+        __syncthreads();
+        const int j = j0 + threadIdx.x;
+        if (j < n) {
+            const unsigned cj = (unsigned)(keys[j] >> 32);
+            sp[threadIdx.x] = pos[j];
+            sc[threadIdx.x] = make_int4((int)(cj % G), (int)((cj / G) % G), (int)(cj / (G * G)), 0);
+        } else {
+            sp[threadIdx.x] = make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+            sc[threadIdx.x] = make_int4(-(1 << 20), -(1 << 20), -(1 << 20), 0);
+        }
+        __syncthreads();
+        float ex = 0.f, ey = 0.f, ez = 0.f;
+#pragma unroll 8
+        for (int k = 0; k < kB; ++k) {
+            const float4 pj = sp[k];
+            const int4 cj = sc[k];
+            const bool far = abs(cj.x - ix) > half || abs(cj.y - iy) > half || abs(cj.z - iz) > half;
+            const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float w = far ? (pj.w * ri) * (ri * ri) : 0.f;
+            ex = fmaf(w, dx, ex);
+            ey = fmaf(w, dy, ey);
+            ez = fmaf(w, dz, ez);
+        }
+        Ex += (double)ex; Ey += (double)ey; Ez += (double)ez;
+    }
+    if (i < n) {
+        E[i] = -Ex;
+        E[(size_t)n + i] = -Ey;
+        E[2 * (size_t)n + i] = -Ez;
+    }
+}
+
 // Training samples of the current snapshot: (snapshot, cell, offset,
-// target = E_far - E_cell) appended at base.
+// target = E_far - E_coarse) appended at base.
 __global__ __launch_bounds__(kB) void k_collect(const float4* __restrict__ pos,
                                                 const float4* __restrict__ lo, int n, int G,
                                                 const FFGrid* g, const double* __restrict__ Efar,
-                                                const double* __restrict__ Ecell, int snap,
+                                                const double* __restrict__ Ep, int snap,
                                                 int64_t base, int* s_snap, int* s_cell,
                                                 float* s_off, float* s_tgt) {
     const int s = blockIdx.x * kB + threadIdx.x;
@@ -504,7 +883,7 @@ __global__ __launch_bounds__(kB) void k_collect(const float4* __restrict__ pos,
     s_cell[k] = c;
     for (int d = 0; d < 3; ++d) {
         s_off[3 * k + d] = off[d];
-        s_tgt[3 * k + d] = (float)(Efar[(size_t)d * n + s] - Ecell[3 * c + d]);
+        s_tgt[3 * k + d] = (float)(Efar[(size_t)d * n + s] - Ep[(size_t)d * n + s]);
     }
 }
 
@@ -610,7 +989,7 @@ bool dalloc(T** p, size_t count) {
 
 void ff_free_bufs(FarField* f) {
     void* b[] = {f->grid, f->cstart, f->cend, f->Fnear, f->mom, f->count, f->occ, f->cell2occ,
-                 f->nocc, f->Ecell, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->grad, f->adam_m,
+                 f->nocc, f->Ecell, f->Ep, f->cfirst, f->tiles, f->ntiles, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->grad, f->adam_m,
                  f->adam_v, f->rel, f->Efar, f->snap_mom, f->s_snap, f->s_cell, f->s_off,
                  f->s_tgt, f->bX, f->bT, f->bZ1, f->bA1, f->bZ2, f->bA2, f->bY, f->bdY, f->bd2,
                  f->bd1, f->bidx, f->loss_part};
@@ -630,14 +1009,22 @@ ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
     const int n = (int)c->n;
     const int G = f->cfg.grid, M = G * G * G;
     KLAUNCH(k_absmax_part, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
-    KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, f->cfg.near_cut, G, f->grid);
+    KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, f->cfg.near_cut, G,
+            f->cfg.near_mode, f->cfg.block, f->rlj, f->grid);
     KLAUNCH(k_zero_d, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, 4 * M);
     KLAUNCH(k_zero_i, dim3((M + kB - 1) / kB), dim3(kB), s, f->count, M);
     KLAUNCH(k_moments, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid, f->mom,
             f->count);
     KLAUNCH(k_compact, dim3(1), dim3(1024), s, f->count, M, f->occ, f->cell2occ, f->nocc);
-    KLAUNCH(k_coarse, dim3((M + kB - 1) / kB), dim3(kB), s, f->mom, f->occ, f->nocc, G,
-            f->cfg.block, f->grid, f->Ecell);
+    if (f->cfg.near_mode == 1) {
+        KLAUNCH(k_coarse_local, dim3((M + kLB - 1) / kLB), dim3(kLB), s, f->mom, f->occ, f->nocc,
+                G, f->cfg.block, f->grid, f->Ecell);
+    } else {
+        KLAUNCH(k_coarse, dim3((M + kB - 1) / kB), dim3(kB), s, f->mom, f->occ, f->nocc, G,
+                f->cfg.block, f->grid, f->Ecell);
+    }
+    KLAUNCH(k_coarse_eval, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid,
+            f->Ecell, f->cfg.near_mode, f->Ep);
     return LD_OK;
 }
 
@@ -647,18 +1034,43 @@ ld_status ff_near(ld_ctx* c, hipStream_t s) {
     const int n = (int)c->n;
     KLAUNCH(k_absmax_part, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
     KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, f->cfg.near_cut, f->cfg.grid,
-            f->grid);
-    KLAUNCH(k_near_keys, dim3((c->sb.n_pow2 + kB - 1) / kB), dim3(kB), s, c->pos, n, c->sb.n_pow2,
-            f->grid, c->sb.keys);
+            f->cfg.near_mode, f->cfg.block, f->rlj, f->grid);
+    KLAUNCH(k_near_keys, dim3((c->sb.n_pow2 + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n,
+            c->sb.n_pow2, f->grid, c->sb.keys);
     HIP_TRY(ld::launch_sort_by_keys(c->pos, c->lo, c->typ, c->oid, n, c->sb, s));
     const int NC = kMaxNearCells * kMaxNearCells * kMaxNearCells;
     KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cstart, NC);
     KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cend, NC);
     KLAUNCH(k_cell_ranges, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, f->cstart, f->cend);
-    const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
-    KLAUNCH(k_near, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->typ, n, f->grid, f->cstart,
-            f->cend, rc2, c->tab, f->Fnear);
+    if (f->cfg.near_mode == 1) {
+        const int G = f->cfg.grid;
+        KLAUNCH(k_block_tiles, dim3(1), dim3(1024), s, f->cstart, f->cend, G, f->cfirst, f->tiles,
+                f->ntiles);
+        KLAUNCH(k_near_block, dim3(f->max_tiles), dim3(64), s, c->pos, c->typ, c->sb.keys, f->grid,
+                G, f->cfg.block / 2, f->cfirst, f->tiles, f->ntiles, n, c->tab, f->Fnear);
+    } else {
+        const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
+        KLAUNCH(k_near, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->typ, n, f->grid,
+                f->cstart, f->cend, rc2, c->tab, f->Fnear);
+    }
     c->steps_since_sort = 0;
+    return LD_OK;
+}
+
+// Exact far field into f->Efar for the current slot order (the cell keys of
+// the last ff_near sort in block mode).
+ld_status ff_far_exact(ld_ctx* c, hipStream_t s) {
+    FarField* f = FF(c);
+    const int n = (int)c->n;
+    if (f->cfg.near_mode == 1) {
+        ld_status st = ff_near(c, s);
+        if (st != LD_OK) return st;
+        KLAUNCH(k_far_exact_block, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->sb.keys, n,
+                f->cfg.grid, f->cfg.block / 2, f->Efar);
+    } else {
+        const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
+        KLAUNCH(k_far_exact, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, rc2, f->Efar);
+    }
     return LD_OK;
 }
 
@@ -700,8 +1112,8 @@ ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
     st = gemm(s, f->h2, H, 0, f->W + f->offW3, f->Op, 0, f->y, f->Op, n, f->Op, H,
               f->W + f->offb3, 0, nullptr, 0, 0, nullptr);
     if (st != LD_OK) return st;
-    KLAUNCH(k_combine, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid,
-            f->Fnear, f->Ecell, f->y, f->Op, f->out_scale, c->Fpart, Fc, Fm);
+    KLAUNCH(k_combine, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, f->Fnear, f->Ep, f->y,
+            f->Op, f->out_scale, c->Fpart, Fc, Fm);
     HIP_TRY(ld::launch_boxes(c->pos, n, c->box, s));
     return LD_OK;
 }
@@ -893,11 +1305,14 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
         return fail(LD_EINVAL, "hidden must be a multiple of 16 in [16, 256]");
     if (cfg->judge_every < 1) return fail(LD_EINVAL, "judge_every must be >= 1");
     if (!(cfg->judge_tol > 0.0)) return fail(LD_EINVAL, "judge_tol must be positive");
+    if (cfg->near_mode != 0 && cfg->near_mode != 1)
+        return fail(LD_EINVAL, "near_mode must be 0 (radial) or 1 (block)");
+    if (cfg->reserved != 0) return fail(LD_EINVAL, "reserved must be 0");
     double maxlj = 0.0;
     for (int a = 0; a < c->p.n_types; ++a)
         for (int b = 0; b < c->p.n_types; ++b)
             maxlj = std::max(maxlj, c->p.lj_cut * 0.5 * (c->p.sigma[a] + c->p.sigma[b]));
-    if (cfg->near_cut < maxlj)
+    if (cfg->near_mode == 0 && cfg->near_cut < maxlj)
         return fail(LD_EINVAL, "near_cut %.3g is below the largest LJ range %.3g", cfg->near_cut,
                     maxlj);
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -905,6 +1320,7 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
     FarField* f = new (std::nothrow) FarField();
     if (!f) return fail(LD_ENOMEM, "host allocation failed");
     f->cfg = *cfg;
+    f->rlj = maxlj;
     init_layout(f);
     const size_t n = (size_t)c->n;
     const size_t M = (size_t)cfg->grid * cfg->grid * cfg->grid;
@@ -919,7 +1335,9 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
     bool ok = dalloc(&f->grid, 1) && dalloc(&f->cstart, NC) && dalloc(&f->cend, NC) &&
               dalloc(&f->Fnear, 3 * n) && dalloc(&f->mom, 4 * M) && dalloc(&f->count, M) &&
               dalloc(&f->occ, M) && dalloc(&f->cell2occ, M) && dalloc(&f->nocc, 1) &&
-              dalloc(&f->Ecell, 3 * M) && dalloc(&f->Xc, M * f->Kp) && dalloc(&f->Ac, M * f->H) &&
+              dalloc(&f->Ecell, kLoc * M) && dalloc(&f->Ep, 3 * n) && dalloc(&f->cfirst, M + 1) &&
+              dalloc(&f->tiles, (n + 63) / 64 + (size_t)cfg->grid * cfg->grid) &&
+              dalloc(&f->ntiles, 1) && dalloc(&f->Xc, M * f->Kp) && dalloc(&f->Ac, M * f->H) &&
               dalloc(&f->h1, n * f->H) && dalloc(&f->h2, n * f->H) && dalloc(&f->y, n * f->Op) &&
               dalloc(&f->W, f->nW) && dalloc(&f->grad, f->nW) && dalloc(&f->adam_m, f->nW) &&
               dalloc(&f->adam_v, f->nW) && dalloc(&f->rel, n) && dalloc(&f->Efar, 3 * n);
@@ -946,6 +1364,7 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
     std::vector<float> zero(f->nW, 0.f);
     HIP_TRY(hipMemcpy(f->adam_m, zero.data(), sizeof(float) * f->nW, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(f->adam_v, zero.data(), sizeof(float) * f->nW, hipMemcpyHostToDevice));
+    f->max_tiles = (int)((n + 63) / 64 + (size_t)cfg->grid * cfg->grid);
     f->out_scale = 1.f;
     f->mode = 0;
     c->ff = f;
@@ -1000,7 +1419,7 @@ ld_status ld_ff_grid(ld_ctx* c, double* L, int32_t* near_cells) {
     hipStream_t s = c->stream;
     KLAUNCH(k_absmax_part, dim3(64), dim3(kB), s, c->pos, (int)c->n, c->sb.bounds_part);
     KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, c->ff->cfg.near_cut,
-            c->ff->cfg.grid, c->ff->grid);
+            c->ff->cfg.grid, c->ff->cfg.near_mode, c->ff->cfg.block, c->ff->rlj, c->ff->grid);
     FFGrid g;
     HIP_TRY(copy_out(&g, c->ff->grid, sizeof g, s));
     if (L) *L = g.L;
@@ -1020,8 +1439,8 @@ ld_status ld_ff_forces(ld_ctx* c, int32_t part, double* out) {
     double* dst = c->work + 6 * (size_t)n;   // [3n] original order
     const double* src = nullptr;
     if (part == 4) {
-        const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
-        KLAUNCH(k_far_exact, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, rc2, f->Efar);
+        ld_status st = ff_far_exact(c, s);
+        if (st != LD_OK) return st;
         KLAUNCH(k_q_times, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, f->Efar, Fc);
         src = Fc;
     } else {
@@ -1132,12 +1551,12 @@ ld_status ld_ff_collect(ld_ctx* c, int32_t reset, int32_t max_snapshots) {
     if (st != LD_OK) return st;
     st = ff_grid_and_coarse(c, s);
     if (st != LD_OK) return st;
-    const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
-    KLAUNCH(k_far_exact, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, rc2, f->Efar);
+    st = ff_far_exact(c, s);
+    if (st != LD_OK) return st;
     KLAUNCH(k_snap_mom, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, M, f->grid, f->sq,
             f->snap_mom + (size_t)f->snaps * 4 * M);
     KLAUNCH(k_collect, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid,
-            f->Efar, f->Ecell, f->snaps, f->samples, f->s_snap, f->s_cell, f->s_off, f->s_tgt);
+            f->Efar, f->Ep, f->snaps, f->samples, f->s_snap, f->s_cell, f->s_off, f->s_tgt);
     HIP_TRY(hipStreamSynchronize(s));
     f->snaps += 1;
     f->samples += n;

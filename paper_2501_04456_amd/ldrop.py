@@ -64,7 +64,8 @@ TUNING_FIELDS = ("block", "j_split", "comp", "sort_every", "cull", "graph_steps"
 
 class ld_ff_config(C.Structure):
     _fields_ = [("near_cut", C.c_double), ("grid", C.c_int32), ("block", C.c_int32),
-                ("hidden", C.c_int32), ("judge_every", C.c_int32), ("judge_tol", C.c_double)]
+                ("hidden", C.c_int32), ("judge_every", C.c_int32), ("judge_tol", C.c_double),
+                ("near_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ld_ff_train_cfg(C.Structure):
@@ -78,7 +79,9 @@ class ld_ff_train_report(C.Structure):
                 ("val_rel_rms", C.c_double), ("out_scale", C.c_double)]
 
 
-FF_DEFAULT = dict(near_cut=8.0, grid=32, block=5, hidden=128, judge_every=500, judge_tol=1e-3)
+FF_DEFAULT = dict(near_cut=8.0, grid=32, block=5, hidden=128, judge_every=500, judge_tol=1e-3,
+                  near_mode=0)
+NEAR_RADIAL, NEAR_BLOCK = 0, 1
 
 
 SYMBOLS = [

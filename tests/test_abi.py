@@ -43,7 +43,9 @@ def test_struct_layouts_match_header():
     from paper_2501_04456_amd import ldrop
     txt = open(HEADER).read()
     for cname, py in (("ld_params", ldrop.ld_params), ("ld_radius", ldrop.ld_radius),
-                      ("ld_tuning", ldrop.ld_tuning)):
+                      ("ld_tuning", ldrop.ld_tuning), ("ld_ff_config", ldrop.ld_ff_config),
+                      ("ld_ff_train_cfg", ldrop.ld_ff_train_cfg),
+                      ("ld_ff_train_report", ldrop.ld_ff_train_report)):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", txt).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = []
@@ -51,12 +53,13 @@ def test_struct_layouts_match_header():
             decl = decl.strip()
             if not decl:
                 continue
-            decl = re.sub(r"^(int32_t|double)\s+", "", decl)
+            decl = re.sub(r"^(int32_t|int64_t|uint64_t|double)\s+", "", decl)
             for f in decl.split(","):
                 fields.append(re.sub(r"\[.*\]", "", f).strip())
         assert [f[0] for f in py._fields_] == fields, cname
     assert C.sizeof(ldrop.ld_params) == 8 + 6 * 8 * 8 + 64 * 8 + 4 * 8 + 3 * 8 + 8 + 16 + 8
     assert C.sizeof(ldrop.ld_radius) == 48
+    assert C.sizeof(ldrop.ld_ff_config) == 40
 
 
 def test_no_torch_in_signatures():

@@ -71,6 +71,73 @@ def test_near_and_far_exact_parts(ld, orc, sysw):
     assert np.all(np.linalg.norm(Ff_g - qh[:, None] * Ef, axis=1) <= 1e-5 * S)
 
 
+@pytest.mark.parametrize("block", [5, 3, 1])
+def test_block_near_and_far_exact_parts(ld, orc, sysw, block):
+    """Block mode: exact Coulomb inside the block^3 cells and every LJ pair
+    (block 1 has W = 1 > block/2: LJ partners outside the block), and the
+    exact far field of the particles outside the block."""
+    s = ld.System.from_workload(sysw)
+    s.ff_enable(grid=G, block=block, hidden=64, near_mode=ld.NEAR_BLOCK)
+    L, gn = s.ff_grid()
+    assert L == grid_L(sysw.pos) and gn == G
+    Fn_g = s.ff_forces(0)
+    Ff_g = s.ff_forces(4)
+    x = sysw.pos.astype(np.float64)
+    Fn, Ef = orc.ff_split_block(x, sysw.type, sysw.charge, sysw.params, G, L, block)
+    _, S, _ = orc.pair_forces(x, sysw.type, sysw.charge, sysw.params)
+    qh = orc.qhat(sysw.charge, sysw.params)
+    assert np.all(np.linalg.norm(Fn_g - Fn, axis=1) <= 1e-5 * S)
+    assert np.all(np.linalg.norm(Ff_g - qh[:, None] * Ef, axis=1) <= 1e-5 * S)
+
+
+def test_block_near_ragged_small(ld, orc):
+    """A few hundred particles, coarse and fine grids: tiles that end inside
+    a row, rows with one particle, the grid edge."""
+    w = W.config_small()
+    w = w.replace(n=333, type=w.type[:333], charge=w.charge[:333], pos=w.pos[:333])
+    x = w.pos.astype(np.float64)
+    _, S, _ = orc.pair_forces(x, w.type, w.charge, w.params)
+    for grid in (4, 9, 32):
+        s = ld.System.from_workload(w)
+        s.ff_enable(grid=grid, block=3, hidden=16, near_mode=ld.NEAR_BLOCK)
+        L, _ = s.ff_grid()
+        Fn, Ef = orc.ff_split_block(x, w.type, w.charge, w.params, grid, L, 3)
+        assert np.all(np.linalg.norm(s.ff_forces(0) - Fn, axis=1) <= 1e-5 * S), grid
+
+
+def test_block_coarse_part(ld, orc, sysw):
+    """Block mode: q times the second-order local expansion of the far cells'
+    monopole + dipole field at every particle."""
+    s = ld.System.from_workload(sysw)
+    s.ff_enable(grid=G, block=B, hidden=64, near_mode=ld.NEAR_BLOCK)
+    Fc_g = s.ff_forces(1)
+    x = sysw.pos.astype(np.float64)
+    L = grid_L(sysw.pos)
+    qh = orc.qhat(sysw.charge, sysw.params)
+    mom = orc.ff_moments(x, qh, G, L)
+    loc = orc.ff_local(mom, G, L, B)
+    Fc = qh[:, None] * orc.ff_local_eval(x, G, L, loc)
+    scale = np.sqrt(np.mean(np.sum(Fc ** 2, 1)))
+    assert np.abs(Fc_g - Fc).max() <= 1e-4 * scale
+
+
+def test_block_mode_accuracy_without_network(ld, sysw):
+    """Exact block near field + local expansion alone (network output zero)
+    already reproduces direct summation to the dipole-truncation level."""
+    s = ld.System.from_workload(sysw)
+    s.ff_enable(grid=G, block=B, hidden=64, near_mode=ld.NEAR_BLOCK)
+    wts, sq, _ = s.ff_weights()
+    K, H = 4 * B ** 3 + 3, 64
+    o = (K + 31) // 32 * 32 * H + H + H * H + H
+    wts[o:] = 0.0
+    s.ff_set_weights(wts, sq, 1.0)
+    err = s.ff_judge()
+    assert err < 5e-3, err
+    tot = s.ff_forces(3)
+    parts = s.ff_forces(0) + s.ff_forces(1) + s.ff_forces(2)
+    assert np.allclose(tot, parts, rtol=0, atol=1e-9 * np.abs(tot).max())
+
+
 def test_coarse_part(ld, orc, sysw):
     s = make_sys(ld, sysw)
     Fc_g = s.ff_forces(1)
