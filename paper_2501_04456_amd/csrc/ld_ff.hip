@@ -80,6 +80,8 @@ struct FarField {
     double* Ep = nullptr;              // [3][n] coarse field at each particle
     int* cfirst = nullptr;             // [G^3 + 1] first slot of each cell (block mode)
     int4* tiles = nullptr;             // row tiles (block mode)
+    double* loc_part = nullptr;        // [loc_split][G^3][19] partial expansions
+    int loc_split = 1;
     int* ntiles = nullptr;
     int max_tiles = 0;
     float* Xc = nullptr;               // [G^3 * Kp]
@@ -573,15 +575,22 @@ __global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
 //                                                    U = b R + 3 u^5 P
 // (E = -grad of Q/|R| + P.R/|R|^3; J and H its derivatives).  Stored per
 // cell: E (3), J (xx xy xz yy yz zz), H (xxx xxy xxz xyy xyz xzz yyy yyz yzz
-// zzz).  FP32 terms summed over one LDS tile, FP64 totals.
+// zzz).  FP32 terms summed over one LDS tile, FP64 totals.  The sources are
+// split over gridDim.y workgroups (one partial sum each, reduced in a fixed
+// order by k_loc_reduce) so that a few hundred target tiles still fill the
+// chip.
 constexpr int kLB = 128;
 __global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__ mom,
                                                       const int* __restrict__ occ,
                                                       const int* __restrict__ nocc, int G, int B,
-                                                      const FFGrid* g, double* out) {
+                                                      const FFGrid* g, int M, double* part) {
     __shared__ float4 sm[kLB];         // (Q, Px, Py, Pz)
     __shared__ float4 sc[kLB];         // cell index (x, y, z) as floats
     const int no = *nocc;
+    if ((int)blockIdx.x * kLB >= no) return;           // uniform per workgroup
+    const int nsplit = gridDim.y;
+    const int per = ((no + nsplit - 1) / nsplit + kLB - 1) / kLB * kLB;
+    const int jb = blockIdx.y * per, je = min(no, jb + per);
     const int t = blockIdx.x * kLB + threadIdx.x;
     const bool live = t < no;
     const int tc = live ? occ[t] : 0;
@@ -591,10 +600,10 @@ __global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__
     double acc[kLoc];
 #pragma unroll
     for (int k = 0; k < kLoc; ++k) acc[k] = 0.0;
-    for (int j0 = 0; j0 < no; j0 += kLB) {
+    for (int j0 = jb; j0 < je; j0 += kLB) {
         __syncthreads();
         const int j = j0 + threadIdx.x;
-        if (j < no) {
+        if (j < je) {
             const int c = occ[j];
             sm[threadIdx.x] = make_float4((float)mom[4 * c], (float)mom[4 * c + 1],
                                           (float)mom[4 * c + 2], (float)mom[4 * c + 3]);
@@ -608,7 +617,7 @@ __global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__
         float f[kLoc];
 #pragma unroll
         for (int k = 0; k < kLoc; ++k) f[k] = 0.f;
-        const int cnt = min(kLB, no - j0);
+        const int cnt = min(kLB, je - j0);
         for (int k = 0; k < cnt; ++k) {
             const float4 cs = sc[k];
             const float dx = tx - cs.x, dy = ty - cs.y, dz = tz - cs.z;
@@ -657,9 +666,25 @@ __global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__
         for (int k = 0; k < kLoc; ++k) acc[k] += (double)f[k];
     }
     if (live) {
+        double* o = part + ((size_t)blockIdx.y * M + tc) * kLoc;
 #pragma unroll
-        for (int k = 0; k < kLoc; ++k) out[(size_t)kLoc * tc + k] = acc[k];
+        for (int k = 0; k < kLoc; ++k) o[k] = acc[k];
     }
+}
+
+// out[cell] = sum over the source splits of the partial expansions, in split
+// order, for every occupied cell.
+__global__ __launch_bounds__(kB) void k_loc_reduce(const double* __restrict__ part,
+                                                   const int* __restrict__ occ,
+                                                   const int* __restrict__ nocc, int M, int nsplit,
+                                                   double* out) {
+    const int e = blockIdx.x * kB + threadIdx.x;
+    if (e >= *nocc * kLoc) return;
+    const size_t c = (size_t)occ[e / kLoc];
+    const int k = e % kLoc;
+    double v = 0.0;
+    for (int p = 0; p < nsplit; ++p) v += part[((size_t)p * M + c) * kLoc + k];
+    out[c * kLoc + k] = v;
 }
 
 // Coarse field at every particle: the centre value of its cell (radial mode)
@@ -989,7 +1014,7 @@ bool dalloc(T** p, size_t count) {
 
 void ff_free_bufs(FarField* f) {
     void* b[] = {f->grid, f->cstart, f->cend, f->Fnear, f->mom, f->count, f->occ, f->cell2occ,
-                 f->nocc, f->Ecell, f->Ep, f->cfirst, f->tiles, f->ntiles, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->grad, f->adam_m,
+                 f->nocc, f->Ecell, f->Ep, f->cfirst, f->tiles, f->ntiles, f->loc_part, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->grad, f->adam_m,
                  f->adam_v, f->rel, f->Efar, f->snap_mom, f->s_snap, f->s_cell, f->s_off,
                  f->s_tgt, f->bX, f->bT, f->bZ1, f->bA1, f->bZ2, f->bA2, f->bY, f->bdY, f->bd2,
                  f->bd1, f->bidx, f->loss_part};
@@ -1017,8 +1042,10 @@ ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
             f->count);
     KLAUNCH(k_compact, dim3(1), dim3(1024), s, f->count, M, f->occ, f->cell2occ, f->nocc);
     if (f->cfg.near_mode == 1) {
-        KLAUNCH(k_coarse_local, dim3((M + kLB - 1) / kLB), dim3(kLB), s, f->mom, f->occ, f->nocc,
-                G, f->cfg.block, f->grid, f->Ecell);
+        KLAUNCH(k_coarse_local, dim3((M + kLB - 1) / kLB, f->loc_split), dim3(kLB), s, f->mom,
+                f->occ, f->nocc, G, f->cfg.block, f->grid, M, f->loc_part);
+        KLAUNCH(k_loc_reduce, dim3((M * kLoc + kB - 1) / kB), dim3(kB), s, f->loc_part, f->occ,
+                f->nocc, M, f->loc_split, f->Ecell);
     } else {
         KLAUNCH(k_coarse, dim3((M + kB - 1) / kB), dim3(kB), s, f->mom, f->occ, f->nocc, G,
                 f->cfg.block, f->grid, f->Ecell);
@@ -1322,6 +1349,12 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
     f->cfg = *cfg;
     f->rlj = maxlj;
     init_layout(f);
+    // source splits of the local expansion: up to 16, partials within 128 MB
+    {
+        const size_t Mc = (size_t)cfg->grid * cfg->grid * cfg->grid;
+        const size_t cap = ((size_t)128 << 20) / (sizeof(double) * kLoc * Mc);
+        f->loc_split = cfg->near_mode == 1 ? (int)std::max<size_t>(1, std::min<size_t>(16, cap)) : 1;
+    }
     const size_t n = (size_t)c->n;
     const size_t M = (size_t)cfg->grid * cfg->grid * cfg->grid;
     const size_t NC = (size_t)kMaxNearCells * kMaxNearCells * kMaxNearCells;
@@ -1337,7 +1370,9 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
               dalloc(&f->occ, M) && dalloc(&f->cell2occ, M) && dalloc(&f->nocc, 1) &&
               dalloc(&f->Ecell, kLoc * M) && dalloc(&f->Ep, 3 * n) && dalloc(&f->cfirst, M + 1) &&
               dalloc(&f->tiles, (n + 63) / 64 + (size_t)cfg->grid * cfg->grid) &&
-              dalloc(&f->ntiles, 1) && dalloc(&f->Xc, M * f->Kp) && dalloc(&f->Ac, M * f->H) &&
+              dalloc(&f->ntiles, 1) &&
+              dalloc(&f->loc_part, cfg->near_mode == 1 ? (size_t)f->loc_split * M * kLoc : 1) &&
+              dalloc(&f->Xc, M * f->Kp) && dalloc(&f->Ac, M * f->H) &&
               dalloc(&f->h1, n * f->H) && dalloc(&f->h2, n * f->H) && dalloc(&f->y, n * f->Op) &&
               dalloc(&f->W, f->nW) && dalloc(&f->grad, f->nW) && dalloc(&f->adam_m, f->nW) &&
               dalloc(&f->adam_v, f->nW) && dalloc(&f->rel, n) && dalloc(&f->Efar, 3 * n);
