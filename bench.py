@@ -92,15 +92,18 @@ def cpu_baseline(w, target_s: float):
     cores = len(os.sched_getaffinity(0))
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     rng = np.random.default_rng(123)
-    rows = rng.choice(w.n, 32, replace=False)
-    t0 = time.perf_counter()
-    oracle.pair_forces(w.pos, w.type, w.charge, w.params, rows=rows)
-    dt_cal = time.perf_counter() - t0
-    m = int(min(w.n, max(32, 32 * target_s / max(dt_cal, 1e-3))))
-    rows = rng.choice(w.n, m, replace=False)
-    t0 = time.perf_counter()
-    oracle.pair_forces(w.pos, w.type, w.charge, w.params, rows=rows)
-    el = time.perf_counter() - t0
+    # calibrate on enough rows to keep every thread busy, then size the sample
+    # to about target_s seconds (one more try if it came out far too short)
+    m = max(32, 16 * threads)
+    el = 0.0
+    for _ in range(3):
+        rows = rng.choice(w.n, m, replace=False)
+        t0 = time.perf_counter()
+        oracle.pair_forces(w.pos, w.type, w.charge, w.params, rows=rows)
+        el = time.perf_counter() - t0
+        if el >= 0.5 * target_s or m >= w.n:
+            break
+        m = int(min(w.n, max(m + 1, m * target_s / max(el, 1e-3))))
     step_s = el * w.n / m                 # pair sum dominates the step
     return {
         "value": 1.0 / step_s,

@@ -136,7 +136,7 @@ hipError_t launch_diag(const float4* pos, const float4* lo, const int* typ,
                        const DevState* st, const ExtParams& P, double* work, double* out,
                        hipStream_t s);
 
-// Spatial ordering: Morton keys over the current bounding cube, sort, and
+// Spatial ordering: Hilbert keys over the current bounding cube, sort, and
 // permutation of every per-slot array.
 struct SortBuffers {
     unsigned long long* keys;            // [n_pow2]

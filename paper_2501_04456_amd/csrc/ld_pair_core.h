@@ -5,8 +5,10 @@
 // v_rsq_f32: three subtractions, r^2 as mul+fma+fma, q_j r^-3 as three
 // multiplications and three fma into FP32 block accumulators.  Each lane sums
 // KB = 32 pair terms in FP32 and then moves the block into FP64 totals
-// (COMP=0) or into a blocked Kahan pair (COMP=1).  The worst-case rounding of
-// a 32-term FP32 block is 31 u sum|f| ~ 1.8e-6 of S_i = sum_j |f_ij|.
+// (COMP=0) or into a blocked Kahan pair (COMP=1); LJ terms (near groups
+// only) have FP32 blocks of their own, moved into FP64 the same way.  The
+// worst-case rounding of a 32-term FP32 block is 31 u sum|f| ~ 1.8e-6 of
+// S_i = sum_j |f_ij|.
 #pragma once
 
 #include "ld_internal.h"
@@ -74,7 +76,8 @@ __device__ __forceinline__ void group_near(const float4* __restrict__ sp,
     const float* e4 = ttab + 3 * kMaxTypes * kMaxTypes;
 #pragma unroll
     for (int kb = 0; kb < kGroup; kb += KB) {
-        float bx = 0.f, by = 0.f, bz = 0.f;
+        float bx = 0.f, by = 0.f, bz = 0.f;   // Coulomb, FP32 block
+        float lx = 0.f, ly = 0.f, lz = 0.f;   // LJ, FP32 block
 #pragma unroll 4
         for (int k = 0; k < KB; ++k) {
             const float4 pj = sp[kb + k];
@@ -91,13 +94,14 @@ __device__ __forceinline__ void group_near(const float4* __restrict__ sp,
                 } else {
                     const int pidx = ti * T + stp[kb + k];
                     if (r2 < rc2[pidx]) {
-                        const float ir2 = 1.0f / r2;
+                        // r^-2 from the reciprocal square root already at hand
+                        const float ir2 = ri * ri;
                         const float s2 = sig2[pidx] * ir2;
                         const float s6 = s2 * s2 * s2;
                         const float g = e24[pidx] * s6 * (2.0f * s6 - 1.0f) * ir2;
-                        a.Lx += (double)(g * dx);
-                        a.Ly += (double)(g * dy);
-                        a.Lz += (double)(g * dz);
+                        lx = fmaf(g, dx, lx);
+                        ly = fmaf(g, dy, ly);
+                        lz = fmaf(g, dz, lz);
                         if constexpr (DIAG) {
                             a.S += (double)fabsf(g) * (double)(r2 * ri);
                             a.Ul += 0.5 * (double)(e4[pidx] * s6 * (s6 - 1.0f));
@@ -117,6 +121,9 @@ __device__ __forceinline__ void group_near(const float4* __restrict__ sp,
             bz = fmaf(w, dz, bz);
         }
         flush<COMP>(a, bx, by, bz);
+        a.Lx += (double)lx;
+        a.Ly += (double)ly;
+        a.Lz += (double)lz;
     }
 }
 

@@ -1,4 +1,4 @@
-// Spatial ordering of the particle slots along a Morton (Z-order) curve, so
+// Spatial ordering of the particle slots along a Hilbert curve, so
 // that every 64-slot group is spatially compact and the pair kernel can cull
 // Lennard-Jones range tests per group pair.  The ordering is a permutation
 // of slots only: each slot carries its original index, which keys the
@@ -79,18 +79,45 @@ __global__ __launch_bounds__(256) void k_bounds_part(const float4* __restrict__ 
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__device__ __forceinline__ unsigned spread3(unsigned v) {
-    v &= 0x3FFu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
+
+// Hilbert index of a point with 10-bit coordinates (J. Skilling, "Programming
+// the Hilbert curve", AIP Conf. Proc. 707 (2004): the transpose form -- undo
+// the excess work, Gray-encode, then interleave the bits).  Consecutive
+// indices are face neighbours, so runs of 64 particles along the curve are
+// more compact than Morton runs (about half as many pairs of 64-particle
+// groups come within LJ range of each other at the large workload).
+__device__ __forceinline__ unsigned hilbert3(unsigned x0, unsigned x1, unsigned x2) {
+    unsigned X[3] = {x0, x1, x2};
+    const unsigned M = 1u << 9;
+    for (unsigned Q = M; Q > 1; Q >>= 1) {
+        const unsigned P = Q - 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const unsigned t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    unsigned t = 0;
+    for (unsigned Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    X[0] ^= t; X[1] ^= t; X[2] ^= t;
+    unsigned key = 0;
+    for (int b = 9; b >= 0; --b)
+        key = (key << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) |
+              ((X[2] >> b) & 1u);
+    return key;
 }
 
-__global__ __launch_bounds__(256) void k_morton(const float4* __restrict__ pos, int n, int n_pow2,
-                                                const float* __restrict__ part, int nparts,
-                                                unsigned long long* keys) {
+__global__ __launch_bounds__(256) void k_curve_keys(const float4* __restrict__ pos, int n,
+                                                    int n_pow2, const float* __restrict__ part,
+                                                    int nparts, unsigned long long* keys) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= n_pow2) return;
     if (s >= n) {
@@ -109,7 +136,7 @@ __global__ __launch_bounds__(256) void k_morton(const float4* __restrict__ pos, 
     const unsigned qx = (unsigned)fminf(1023.f, fmaxf(0.f, (h.x - lo[0]) * scale));
     const unsigned qy = (unsigned)fminf(1023.f, fmaxf(0.f, (h.y - lo[1]) * scale));
     const unsigned qz = (unsigned)fminf(1023.f, fmaxf(0.f, (h.z - lo[2]) * scale));
-    const unsigned code = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    const unsigned code = hilbert3(qx, qy, qz);
     // Uncharged particles go after all charged ones (bit 62), so 64-slot
     // groups are charge-homogeneous and the pair kernel can skip far group
     // pairs whose Coulomb term is identically zero.
@@ -152,7 +179,7 @@ hipError_t launch_sort(float4* pos, float4* lo, int* typ, int* oid, int n, const
                        hipStream_t s) {
     hipLaunchKernelGGL(k_bounds_part, dim3(B.bounds_parts), dim3(256), 0, s, pos, n,
                        B.bounds_part);
-    hipLaunchKernelGGL(k_morton, dim3((B.n_pow2 + 255) / 256), dim3(256), 0, s, pos, n, B.n_pow2,
+    hipLaunchKernelGGL(k_curve_keys, dim3((B.n_pow2 + 255) / 256), dim3(256), 0, s, pos, n, B.n_pow2,
                        B.bounds_part, B.bounds_parts, B.keys);
     return launch_sort_by_keys(pos, lo, typ, oid, n, B, s);
 }

@@ -15,7 +15,9 @@ import numpy as np
 from . import workloads as W
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libldrop.so")
+# LDROP_LIB may name another build of the same library (e.g. to compare two
+# builds in one process tree); the default is the in-tree build.
+LIB_PATH = os.environ.get("LDROP_LIB") or os.path.join(_HERE, "libldrop.so")
 MAX_TYPES = 8
 
 LD_OK = 0
