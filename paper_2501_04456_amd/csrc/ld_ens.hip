@@ -10,6 +10,15 @@
 // one launch.  A droplet's noise is keyed by its seed and the particle's
 // index inside the droplet, so each droplet follows exactly the stream it
 // would follow alone.
+//
+// Every sort interval each droplet's slots are re-ordered along a Hilbert
+// curve over the droplet's own bounding cube (uncharged particles last), and
+// every step each 64-slot tile of a droplet gets a bounding box and a charged
+// flag.  The pair kernel then treats a pair of tiles like the single-droplet
+// kernel treats a pair of groups: careful loop when the boxes come within the
+// largest LJ range, Coulomb-only loop when they do not, nothing when one
+// side is uncharged.  Outputs are mapped back to the original order through
+// the per-droplet index, which travels with the particle.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -25,6 +34,7 @@ namespace {
 
 constexpr int kWaves = 4;                 // wavefronts per workgroup
 constexpr int kEnsBlock = kWaves * kGroup;
+constexpr int kEnsSortEvery = 50;         // sort interval without graphs
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -34,11 +44,12 @@ __device__ __forceinline__ void wave_sync() {
 
 __global__ void k_ens_reset(unsigned* counter) { *counter = 0u; }
 
-template <int COMP>
+template <int COMP, bool CULL>
 __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
     const float4* __restrict__ pos, const int* __restrict__ typ, const int* __restrict__ off,
     const int2* __restrict__ items, int W, unsigned* counter, const PairTable* __restrict__ tabs,
-    double* __restrict__ F, int total) {
+    const Box* __restrict__ box, const int* __restrict__ tbase, double* __restrict__ F,
+    int total) {
     __shared__ float4 sp[kWaves][kGroup];
     __shared__ int stp[kWaves][kGroup];
     __shared__ float ttab[kWaves][4 * kMaxTypes * kMaxTypes];
@@ -66,7 +77,23 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
         const float4 pi = live ? pos[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
         const int ti = live ? typ[o + i] : 0;
         pair::Acc a;
+        Box bi;
+        int t0 = 0;
+        if constexpr (CULL) {
+            t0 = tbase[d];
+            bi = box[t0 + it.y / kGroup];
+        }
+        const float cull2 = rc2max * 1.0001f;
         for (int jt = 0; jt < nd; jt += kGroup) {
+            bool near = true;
+            if constexpr (CULL) {
+                // box values are uniform across the wavefront
+                const Box bj = box[t0 + jt / kGroup];
+                near = __builtin_amdgcn_readfirstlane((int)(pair::box_dist2(bi, bj) < cull2));
+                const bool coulomb =
+                    __builtin_amdgcn_readfirstlane((int)(bi.lo.w != 0.f && bj.lo.w != 0.f));
+                if (!near && !coulomb) continue;
+            }
             wave_sync();
             const int j = jt + lane;
             if (j < nd) {
@@ -77,7 +104,10 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
                 stp[w][lane] = 0;
             }
             wave_sync();
-            pair::group_near<COMP, false>(sp[w], stp[w], ttab[w], T, rc2max, jt, i, ti, pi, a);
+            if (near)
+                pair::group_near<COMP, false>(sp[w], stp[w], ttab[w], T, rc2max, jt, i, ti, pi, a);
+            else
+                pair::group_far<COMP>(sp[w], pi, a);
         }
         if constexpr (COMP == 1) {
             a.Fx = (double)a.sx - (double)a.cx;
@@ -130,27 +160,109 @@ __global__ __launch_bounds__(256) void k_ens_update(float4* pos, float4* lo,
     }
 }
 
+// Bounding box and charged flag of every 64-slot tile (one wavefront each).
+__global__ __launch_bounds__(256) void k_ens_boxes(const float4* __restrict__ pos,
+                                                   const int* __restrict__ off,
+                                                   const int2* __restrict__ tiles, int ntiles,
+                                                   Box* box) {
+    const int g = blockIdx.x * 4 + threadIdx.x / kGroup;
+    if (g >= ntiles) return;                           // uniform per wavefront
+    const int2 t = tiles[g];
+    const int s = t.y + (int)(threadIdx.x % kGroup);
+    const bool live = s < off[t.x + 1];
+    const float4 h = live ? pos[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float lx = upd::wave_min(live ? h.x : INFINITY), hx = upd::wave_max(live ? h.x : -INFINITY);
+    const float ly = upd::wave_min(live ? h.y : INFINITY), hy = upd::wave_max(live ? h.y : -INFINITY);
+    const float lz = upd::wave_min(live ? h.z : INFINITY), hz = upd::wave_max(live ? h.z : -INFINITY);
+    const bool charged = __any(live && h.w != 0.f);
+    if (threadIdx.x % kGroup == 0) {
+        Box b;
+        b.lo = make_float4(lx, ly, lz, charged ? 1.f : 0.f);
+        b.hi = make_float4(hx, hy, hz, 0.f);
+        box[g] = b;
+    }
+}
+
+// Bounding box of every droplet (one workgroup each), [n_drop][6].
+__global__ __launch_bounds__(256) void k_ens_bounds(const float4* __restrict__ pos,
+                                                    const int* __restrict__ off, float* out) {
+    __shared__ float red[6][256];
+    const int d = blockIdx.x;
+    float m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int s = off[d] + threadIdx.x; s < off[d + 1]; s += 256) {
+        const float4 h = pos[s];
+        m[0] = fminf(m[0], h.x); m[1] = fminf(m[1], h.y); m[2] = fminf(m[2], h.z);
+        m[3] = fmaxf(m[3], h.x); m[4] = fmaxf(m[4], h.y); m[5] = fmaxf(m[5], h.z);
+    }
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = m[c];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 6; ++c)
+                red[c][threadIdx.x] = c < 3 ? fminf(red[c][threadIdx.x], red[c][threadIdx.x + w])
+                                            : fmaxf(red[c][threadIdx.x], red[c][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[6 * d + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Sort keys: droplet (bits 51..63), uncharged flag (50), 18-bit Hilbert
+// index over the droplet's bounding cube (32..49), slot (0..31; the permute
+// kernels read the source slot from the low 32 bits).
+__global__ __launch_bounds__(256) void k_ens_keys(const float4* __restrict__ pos,
+                                                  const int* __restrict__ did,
+                                                  const float* __restrict__ bounds, int total,
+                                                  int n_pow2, unsigned long long* keys) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n_pow2) return;
+    if (s >= total) {
+        keys[s] = ~0ull;
+        return;
+    }
+    const int d = did[s];
+    const float* b = bounds + 6 * d;
+    const float ext = fmaxf(fmaxf(b[3] - b[0], b[4] - b[1]), fmaxf(b[5] - b[2], 1e-30f));
+    const float scale = 63.0f / ext;
+    const float4 h = pos[s];
+    const unsigned qx = (unsigned)fminf(63.f, fmaxf(0.f, (h.x - b[0]) * scale));
+    const unsigned qy = (unsigned)fminf(63.f, fmaxf(0.f, (h.y - b[1]) * scale));
+    const unsigned qz = (unsigned)fminf(63.f, fmaxf(0.f, (h.z - b[2]) * scale));
+    const unsigned long long code = hilbert_index<6>(qx, qy, qz);
+    const unsigned long long neutral = h.w == 0.f ? 1ull : 0ull;
+    keys[s] = ((unsigned long long)d << 51) | (neutral << 50) | (code << 32) | (unsigned)s;
+}
+
+// Positions and forces in the original order: slot s holds particle lid[s]
+// of droplet did[s].
 __global__ __launch_bounds__(256) void k_ens_gather(const float4* __restrict__ pos,
-                                                    const float4* __restrict__ lo, int total,
+                                                    const float4* __restrict__ lo,
+                                                    const int* __restrict__ did,
+                                                    const int* __restrict__ lid,
+                                                    const int* __restrict__ off, int total,
                                                     float* hi_out, float* lo_out) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= total) return;
+    const size_t o = (size_t)off[did[s]] + (size_t)lid[s];
     const float4 h = pos[s], l = lo[s];
-    hi_out[3 * (size_t)s] = h.x;
-    hi_out[3 * (size_t)s + 1] = h.y;
-    hi_out[3 * (size_t)s + 2] = h.z;
-    lo_out[3 * (size_t)s] = l.x;
-    lo_out[3 * (size_t)s + 1] = l.y;
-    lo_out[3 * (size_t)s + 2] = l.z;
+    hi_out[3 * o] = h.x;
+    hi_out[3 * o + 1] = h.y;
+    hi_out[3 * o + 2] = h.z;
+    lo_out[3 * o] = l.x;
+    lo_out[3 * o + 1] = l.y;
+    lo_out[3 * o + 2] = l.z;
 }
 
-__global__ __launch_bounds__(256) void k_ens_forces_aos(const double* __restrict__ F, int total,
+__global__ __launch_bounds__(256) void k_ens_forces_aos(const double* __restrict__ F,
+                                                        const int* __restrict__ did,
+                                                        const int* __restrict__ lid,
+                                                        const int* __restrict__ off, int total,
                                                         double* out) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= total) return;
-    out[3 * (size_t)s] = F[s];
-    out[3 * (size_t)s + 1] = F[(size_t)total + s];
-    out[3 * (size_t)s + 2] = F[2 * (size_t)total + s];
+    const size_t o = (size_t)off[did[s]] + (size_t)lid[s];
+    out[3 * o] = F[s];
+    out[3 * o + 1] = F[(size_t)total + s];
+    out[3 * o + 2] = F[2 * (size_t)total + s];
 }
 
 }  // namespace
@@ -185,13 +297,24 @@ struct ld_ens {
     bool timing = false;
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
+    // spatial ordering and tile culling
+    bool cull = false;                   // off when droplets or slots exceed the key fields
+    Box* box = nullptr;                  // [ntiles]
+    int* tbase = nullptr;                // [n_drop] first tile of each droplet
+    int2* tiles = nullptr;               // [ntiles] (droplet, first slot)
+    int ntiles = 0;
+    float* dbounds = nullptr;            // [n_drop * 6]
+    ld::SortBuffers sb{};
+    int64_t steps_since_sort = 0;
 };
 
 namespace {
 
 void ens_free(ld_ens* e) {
-    void* bufs[] = {e->pos, e->lo,  e->typ,   e->did, e->lid, e->off, e->items,
-                    e->counter, e->tabs, e->ext, e->seeds, e->F, e->work, e->st};
+    void* bufs[] = {e->pos,   e->lo,   e->typ,   e->did,     e->lid,   e->off,
+                    e->items, e->counter, e->tabs, e->ext,   e->seeds, e->F,
+                    e->work,  e->st,   e->box,   e->tbase,   e->tiles, e->dbounds,
+                    e->sb.keys, e->sb.tmp4, e->sb.tmp_i};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (e->graph) (void)hipGraphExecDestroy(e->graph);
@@ -199,19 +322,55 @@ void ens_free(ld_ens* e) {
     for (hipEvent_t v : e->ev) (void)hipEventDestroy(v);
 }
 
+// Sort interval: the graph chunk length when graphs are on (every chunk
+// starts with a sort, so eager steps and replays sort at the same steps).
+int sort_interval(const ld_ens* e) {
+    return e->graph_steps > 0 ? e->graph_steps : kEnsSortEvery;
+}
+
+// Re-order every droplet's slots along its Hilbert curve.
+ld_status enqueue_sort(ld_ens* e, hipStream_t s) {
+    hipLaunchKernelGGL(k_ens_bounds, dim3(e->n_drop), dim3(256), 0, s, e->pos, e->off,
+                       e->dbounds);
+    hipLaunchKernelGGL(k_ens_keys, dim3((e->sb.n_pow2 + 255) / 256), dim3(256), 0, s, e->pos,
+                       e->did, e->dbounds, e->total, e->sb.n_pow2, e->sb.keys);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(ld::launch_sort_by_keys(e->pos, e->lo, e->typ, e->lid, e->total, e->sb, s));
+    return LD_OK;
+}
+
+template <int COMP>
+void launch_ens_pair(ld_ens* e, hipStream_t s) {
+    if (e->cull)
+        hipLaunchKernelGGL((k_ens_pair<COMP, true>), dim3(e->workgroups), dim3(kEnsBlock), 0, s,
+                           e->pos, e->typ, e->off, e->items, e->W, e->counter, e->tabs, e->box,
+                           e->tbase, e->F, e->total);
+    else
+        hipLaunchKernelGGL((k_ens_pair<COMP, false>), dim3(e->workgroups), dim3(kEnsBlock), 0, s,
+                           e->pos, e->typ, e->off, e->items, e->W, e->counter, e->tabs, e->box,
+                           e->tbase, e->F, e->total);
+}
+
 ld_status enqueue_pair(ld_ens* e, hipStream_t s) {
+    if (e->cull)
+        hipLaunchKernelGGL(k_ens_boxes, dim3((e->ntiles + 3) / 4), dim3(256), 0, s, e->pos,
+                           e->off, e->tiles, e->ntiles, e->box);
     hipLaunchKernelGGL(k_ens_reset, dim3(1), dim3(1), 0, s, e->counter);
     if (e->comp == 0)
-        hipLaunchKernelGGL(k_ens_pair<0>, dim3(e->workgroups), dim3(kEnsBlock), 0, s, e->pos,
-                           e->typ, e->off, e->items, e->W, e->counter, e->tabs, e->F, e->total);
+        launch_ens_pair<0>(e, s);
     else
-        hipLaunchKernelGGL(k_ens_pair<1>, dim3(e->workgroups), dim3(kEnsBlock), 0, s, e->pos,
-                           e->typ, e->off, e->items, e->W, e->counter, e->tabs, e->F, e->total);
+        launch_ens_pair<1>(e, s);
     HIP_TRY(hipGetLastError());
     return LD_OK;
 }
 
 ld_status enqueue_step(ld_ens* e, double dt, hipStream_t s, bool timed) {
+    if (e->cull && e->steps_since_sort >= sort_interval(e)) {
+        ld_status st = enqueue_sort(e, s);
+        if (st != LD_OK) return st;
+        e->steps_since_sort = 0;
+    }
+    ++e->steps_since_sort;
     hipEvent_t a = nullptr, b = nullptr;
     if (timed) {
         while (e->ev.size() < e->ev_used + 2) {
@@ -239,11 +398,15 @@ ld_status capture(ld_ens* e, double dt, int steps) {
         e->graph = nullptr;
     }
     if (!e->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking));
+    // the chunk starts with a sort: it is replayed at sort boundaries only
+    const int64_t saved = e->steps_since_sort;
+    e->steps_since_sort = sort_interval(e);
     HIP_TRY(hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
     ld_status st = LD_OK;
     for (int k = 0; k < steps && st == LD_OK; ++k) st = enqueue_step(e, dt, e->cap_stream, false);
     hipGraph_t g = nullptr;
     hipError_t err = hipStreamEndCapture(e->cap_stream, &g);
+    e->steps_since_sort = saved;
     if (st != LD_OK) {
         if (g) (void)hipGraphDestroy(g);
         return st;
@@ -303,7 +466,8 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
     std::vector<PairTable> tabs(n_drop);
     std::vector<ExtParams> exts(n_drop);
     std::vector<unsigned long long> sd(n_drop);
-    std::vector<int2> items;
+    std::vector<int2> items, tiles;
+    std::vector<int> tbase(n_drop);
     for (int d = 0; d < n_drop; ++d) {
         make_tables(p[d], R[d], tabs[d], exts[d]);
         sd[d] = seeds[d];
@@ -325,8 +489,11 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
             dids[i] = d;
             lids[i] = (int)(i - offs[d]);
         }
-        for (int64_t i0 = 0; i0 < offs[d + 1] - offs[d]; i0 += kGroup)
+        tbase[d] = (int)tiles.size();
+        for (int64_t i0 = 0; i0 < offs[d + 1] - offs[d]; i0 += kGroup) {
             items.push_back(make_int2(d, (int)i0));
+            tiles.push_back(make_int2(d, (int)(offs[d] + i0)));
+        }
     }
     // longest item first: an item costs N_d pairs per lane
     std::stable_sort(items.begin(), items.end(), [&](const int2& a, const int2& b) {
@@ -349,6 +516,20 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
               hipMalloc(&e->F, sizeof(double) * 3 * N) == hipSuccess &&
               hipMalloc(&e->work, sizeof(double) * 3 * N) == hipSuccess &&
               hipMalloc(&e->st, sizeof(DevState)) == hipSuccess;
+    // spatial ordering needs the droplet index in 13 bits
+    e->cull = n_drop <= (1 << 13);
+    e->ntiles = (int)tiles.size();
+    int n_pow2 = 2048;                                   // the bitonic sort's smallest size
+    while (n_pow2 < (int)total) n_pow2 <<= 1;
+    e->sb.n_pow2 = n_pow2;
+    if (ok && e->cull)
+        ok = hipMalloc(&e->box, sizeof(Box) * tiles.size()) == hipSuccess &&
+             hipMalloc(&e->tbase, sizeof(int) * n_drop) == hipSuccess &&
+             hipMalloc(&e->tiles, sizeof(int2) * tiles.size()) == hipSuccess &&
+             hipMalloc(&e->dbounds, sizeof(float) * 6 * n_drop) == hipSuccess &&
+             hipMalloc(&e->sb.keys, sizeof(unsigned long long) * n_pow2) == hipSuccess &&
+             hipMalloc(&e->sb.tmp4, sizeof(float4) * N) == hipSuccess &&
+             hipMalloc(&e->sb.tmp_i, sizeof(int) * N) == hipSuccess;
     if (!ok) {
         ens_free(e);
         delete e;
@@ -373,6 +554,10 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
     up(e->ext, exts.data(), sizeof(ExtParams) * n_drop);
     up(e->seeds, sd.data(), sizeof(unsigned long long) * n_drop);
     up(e->st, &ds, sizeof ds);
+    if (e->cull) {
+        up(e->tbase, tbase.data(), sizeof(int) * n_drop);
+        up(e->tiles, tiles.data(), sizeof(int2) * tiles.size());
+    }
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) {
         ens_free(e);
@@ -383,6 +568,7 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     e->workgroups = std::max(1, std::min(cus * 8, (e->W + kWaves - 1) / kWaves));
+    e->steps_since_sort = sort_interval(e);              // sort before the first step
     *out = e;
     return LD_OK;
 }
@@ -404,6 +590,7 @@ ld_status ld_ens_set_tuning(ld_ens* e, int32_t workgroups, int32_t comp, int32_t
     if (workgroups > 0) e->workgroups = workgroups;
     e->comp = comp;
     e->graph_steps = graph_steps;
+    e->steps_since_sort = sort_interval(e);              // new interval: sort next step
     if (e->graph) {
         (void)hipGraphExecDestroy(e->graph);
         e->graph = nullptr;
@@ -417,22 +604,25 @@ ld_status ld_ens_step(ld_ens* e, double dt, int64_t n_steps) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LD_EINVAL, "dt=%g must be positive", dt);
     if (n_steps < 0) return fail(LD_EINVAL, "n_steps must be >= 0");
     int64_t left = n_steps;
-    if (e->graph_steps > 0 && !e->timing) {
-        const int len = e->graph_steps;
-        if (left >= len) {
+    const bool use_graph = e->graph_steps > 0 && !e->timing;
+    const int len = e->graph_steps;
+    while (left > 0) {
+        // a captured chunk starts with a sort, so it is used at sort
+        // boundaries only; eager steps fill up to the next boundary
+        const bool at_chunk = !e->cull || e->steps_since_sort >= sort_interval(e);
+        if (use_graph && at_chunk && left >= len) {
             if (!e->graph || e->graph_dt != dt || e->graph_len != len) {
                 ld_status st = capture(e, dt, len);
                 if (st != LD_OK) return st;
             }
-            while (left >= len) {
-                HIP_TRY(hipGraphLaunch(e->graph, e->stream));
-                left -= len;
-            }
+            HIP_TRY(hipGraphLaunch(e->graph, e->stream));
+            e->steps_since_sort = len;
+            left -= len;
+            continue;
         }
-    }
-    for (int64_t k = 0; k < left; ++k) {
         ld_status st = enqueue_step(e, dt, e->stream, e->timing);
         if (st != LD_OK) return st;
+        --left;
     }
     return LD_OK;
 }
@@ -443,7 +633,7 @@ ld_status ld_ens_forces(ld_ens* e, double* F_pair) {
     ld_status st = enqueue_pair(e, e->stream);
     if (st != LD_OK) return st;
     hipLaunchKernelGGL(k_ens_forces_aos, dim3((e->total + 255) / 256), dim3(256), 0, e->stream,
-                       e->F, e->total, e->work);
+                       e->F, e->did, e->lid, e->off, e->total, e->work);
     HIP_TRY(hipGetLastError());
     HIP_TRY(copy_out(F_pair, e->work, sizeof(double) * 3 * (size_t)e->total, e->stream));
     return LD_OK;
@@ -456,7 +646,7 @@ ld_status ld_ens_get_positions(ld_ens* e, float* pos, float* pos_lo) {
     float* hi = reinterpret_cast<float*>(e->work);
     float* lo = hi + 3 * N;
     hipLaunchKernelGGL(k_ens_gather, dim3((e->total + 255) / 256), dim3(256), 0, e->stream,
-                       e->pos, e->lo, e->total, hi, lo);
+                       e->pos, e->lo, e->did, e->lid, e->off, e->total, hi, lo);
     HIP_TRY(hipGetLastError());
     if (pos) HIP_TRY(copy_out(pos, hi, sizeof(float) * 3 * N, e->stream));
     if (pos_lo) HIP_TRY(copy_out(pos_lo, lo, sizeof(float) * 3 * N, e->stream));

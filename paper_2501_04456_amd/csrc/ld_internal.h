@@ -136,6 +136,43 @@ hipError_t launch_diag(const float4* pos, const float4* lo, const int* typ,
                        const DevState* st, const ExtParams& P, double* work, double* out,
                        hipStream_t s);
 
+// Hilbert index of a point with BITS-bit coordinates (J. Skilling,
+// "Programming the Hilbert curve", AIP Conf. Proc. 707 (2004): the transpose
+// form -- undo the excess work, Gray-encode, then interleave the bits).
+// Consecutive indices are face neighbours, so runs of 64 particles along the
+// curve are more compact than Morton runs (about half as many pairs of
+// 64-particle groups come within LJ range of each other at the large
+// workload).
+template <int BITS>
+__device__ __forceinline__ unsigned hilbert_index(unsigned x0, unsigned x1, unsigned x2) {
+    unsigned X[3] = {x0, x1, x2};
+    const unsigned M = 1u << (BITS - 1);
+    for (unsigned Q = M; Q > 1; Q >>= 1) {
+        const unsigned P = Q - 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const unsigned t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    unsigned t = 0;
+    for (unsigned Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    X[0] ^= t; X[1] ^= t; X[2] ^= t;
+    unsigned key = 0;
+    for (int b = BITS - 1; b >= 0; --b)
+        key = (key << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) |
+              ((X[2] >> b) & 1u);
+    return key;
+}
+
 // Spatial ordering: Hilbert keys over the current bounding cube, sort, and
 // permutation of every per-slot array.
 struct SortBuffers {

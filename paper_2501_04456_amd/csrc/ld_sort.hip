@@ -80,41 +80,6 @@ __global__ __launch_bounds__(256) void k_bounds_part(const float4* __restrict__ 
 }
 
 
-// Hilbert index of a point with 10-bit coordinates (J. Skilling, "Programming
-// the Hilbert curve", AIP Conf. Proc. 707 (2004): the transpose form -- undo
-// the excess work, Gray-encode, then interleave the bits).  Consecutive
-// indices are face neighbours, so runs of 64 particles along the curve are
-// more compact than Morton runs (about half as many pairs of 64-particle
-// groups come within LJ range of each other at the large workload).
-__device__ __forceinline__ unsigned hilbert3(unsigned x0, unsigned x1, unsigned x2) {
-    unsigned X[3] = {x0, x1, x2};
-    const unsigned M = 1u << 9;
-    for (unsigned Q = M; Q > 1; Q >>= 1) {
-        const unsigned P = Q - 1;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            if (X[i] & Q) {
-                X[0] ^= P;
-            } else {
-                const unsigned t = (X[0] ^ X[i]) & P;
-                X[0] ^= t;
-                X[i] ^= t;
-            }
-        }
-    }
-    X[1] ^= X[0];
-    X[2] ^= X[1];
-    unsigned t = 0;
-    for (unsigned Q = M; Q > 1; Q >>= 1)
-        if (X[2] & Q) t ^= Q - 1;
-    X[0] ^= t; X[1] ^= t; X[2] ^= t;
-    unsigned key = 0;
-    for (int b = 9; b >= 0; --b)
-        key = (key << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) |
-              ((X[2] >> b) & 1u);
-    return key;
-}
-
 __global__ __launch_bounds__(256) void k_curve_keys(const float4* __restrict__ pos, int n,
                                                     int n_pow2, const float* __restrict__ part,
                                                     int nparts, unsigned long long* keys) {
@@ -136,7 +101,7 @@ __global__ __launch_bounds__(256) void k_curve_keys(const float4* __restrict__ p
     const unsigned qx = (unsigned)fminf(1023.f, fmaxf(0.f, (h.x - lo[0]) * scale));
     const unsigned qy = (unsigned)fminf(1023.f, fmaxf(0.f, (h.y - lo[1]) * scale));
     const unsigned qz = (unsigned)fminf(1023.f, fmaxf(0.f, (h.z - lo[2]) * scale));
-    const unsigned code = hilbert3(qx, qy, qz);
+    const unsigned code = hilbert_index<10>(qx, qy, qz);
     // Uncharged particles go after all charged ones (bit 62), so 64-slot
     // groups are charge-homogeneous and the pair kernel can skip far group
     // pairs whose Coulomb term is identically zero.

@@ -63,8 +63,12 @@ def test_ensemble_trajectories(ld, orc, small_ensemble, comp):
 
 
 def test_ensemble_graph_replay_matches_eager(ld, small_ensemble):
+    # same tuning on both sides (the sort interval is the chunk length);
+    # single steps never take the graph path
     a = ld.Ensemble(small_ensemble.droplets)
-    a.step(24, small_ensemble.dt)
+    a.set_tuning(graph_steps=8)
+    for _ in range(24):
+        a.step(1, small_ensemble.dt)
     xa = a.positions64()
     b = ld.Ensemble(small_ensemble.droplets)
     b.set_tuning(graph_steps=8)
