@@ -128,6 +128,35 @@ __device__ __forceinline__ __bf16 bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_round(float f) { return (float)bf16_rne(f); }
 
+// Exclusive scan of one int per thread over a workgroup of 1024 (16
+// wavefronts): shuffle scan inside each wavefront, then across the wavefront
+// totals.  Returns the thread's exclusive prefix; *total receives the sum.
+__device__ __forceinline__ int scan1024(int v, int* wsum, int* total) {
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        int a = threadIdx.x < 16 ? wsum[threadIdx.x] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int y = __shfl_up(a, o);
+            if (lane >= o) a += y;
+        }
+        if (threadIdx.x < 16) wsum[16 + threadIdx.x] = a;   // inclusive over wavefronts
+    }
+    __syncthreads();
+    const int before = wv > 0 ? wsum[16 + wv - 1] : 0;
+    *total = wsum[31];
+    __syncthreads();                                    // wsum is reused by the next call
+    return before + x - v;
+}
+
 // ---- grid --------------------------------------------------------------
 
 __global__ __launch_bounds__(kB) void k_absmax_part(const float4* __restrict__ pos, int n,
@@ -300,53 +329,41 @@ __global__ __launch_bounds__(kB) void k_near(const float4* __restrict__ pos,
 
 // One workgroup of 1024: cfirst[c] = slots in cells before c (cfirst[M] = n),
 // then the row tiles: every (y, z) row's slot range cut into pieces of at
-// most 64 slots, tile = (row, first slot, end slot).
+// most 64 slots, tile = (row, first slot, end slot).  Both scans walk the
+// arrays 1024 consecutive entries at a time (coalesced).
 __global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cstart,
                                                       const int* __restrict__ cend, int G,
                                                       int* cfirst, int4* tiles, int* ntiles) {
-    __shared__ int part[1024];
+    __shared__ int wsum[32];
     const int t = threadIdx.x;
     const int M = G * G * G, R = G * G;
-    // exclusive scan of the cell counts
-    const int per = (M + 1023) / 1024;
-    const int c0 = min(M, t * per), c1 = min(M, c0 + per);
-    int mine = 0;
-    for (int c = c0; c < c1; ++c) mine += cend[c] - cstart[c];
-    part[t] = mine;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    int carry = 0;
+    for (int base = 0; base < M; base += 1024) {
+        const int c = base + t;
+        const int cnt = c < M ? cend[c] - cstart[c] : 0;
+        int tot;
+        const int ex = scan1024(cnt, wsum, &tot);
+        if (c < M) cfirst[c] = carry + ex;
+        carry += tot;
     }
-    int run = part[t] - mine;
-    for (int c = c0; c < c1; ++c) {
-        cfirst[c] = run;
-        run += cend[c] - cstart[c];
-    }
-    if (t == 1023) cfirst[M] = part[1023];
+    if (t == 0) cfirst[M] = carry;
     __syncthreads();
-    // tiles per row, scanned the same way
-    const int rper = (R + 1023) / 1024;
-    const int r0 = min(R, t * rper), r1 = min(R, r0 + rper);
-    int nt = 0;
-    for (int r = r0; r < r1; ++r) nt += (cfirst[(r + 1) * G] - cfirst[r * G] + 63) / 64;
-    __syncthreads();
-    part[t] = nt;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int k = part[t] - nt;
-    for (int r = r0; r < r1; ++r) {
-        const int a = cfirst[r * G], b = cfirst[(r + 1) * G];
+    int tcarry = 0;
+    for (int base = 0; base < R; base += 1024) {
+        const int r = base + t;
+        int a = 0, b = 0, nt = 0;
+        if (r < R) {
+            a = cfirst[r * G];
+            b = cfirst[(r + 1) * G];
+            nt = (b - a + 63) / 64;
+        }
+        int tot;
+        const int ex = scan1024(nt, wsum, &tot);
+        int k = tcarry + ex;
         for (int s0 = a; s0 < b; s0 += 64) tiles[k++] = make_int4(r, s0, min(b, s0 + 64), 0);
+        tcarry += tot;
     }
-    if (t == 1023) *ntiles = part[1023];
+    if (t == 0) *ntiles = tcarry;
 }
 
 // Block near field, one wavefront per row tile: Coulomb of every j in the
@@ -476,33 +493,58 @@ __global__ __launch_bounds__(kB) void k_moments(const float4* __restrict__ pos,
     atomicAdd(&count[c], 1);
 }
 
-// Deterministic compaction of occupied cells (one workgroup of 1024).
+// Block mode: the slots are sorted by grid cell, so each cell's moments are a
+// sum over its slot range (one work-item per cell, fixed order, no atomics).
+__global__ __launch_bounds__(kB) void k_moments_sorted(const float4* __restrict__ pos,
+                                                       const float4* __restrict__ lo, int M,
+                                                       int G, const FFGrid* g,
+                                                       const int* __restrict__ cfirst,
+                                                       double* mom, int* count) {
+    const int c = blockIdx.x * kB + threadIdx.x;
+    if (c >= M) return;
+    const int a = cfirst[c], b = cfirst[c + 1];
+    const double L = g->L, hh = g->h;
+    const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+    const double ox = -L + (cx + 0.5) * hh, oy = -L + (cy + 0.5) * hh, oz = -L + (cz + 0.5) * hh;
+    double Q = 0.0, Px = 0.0, Py = 0.0, Pz = 0.0;
+    for (int s = a; s < b; ++s) {
+        const float4 h = pos[s], l = lo[s];
+        const double q = (double)h.w;
+        Q += q;
+        Px += q * (((double)h.x + (double)l.x) - ox);
+        Py += q * (((double)h.y + (double)l.y) - oy);
+        Pz += q * (((double)h.z + (double)l.z) - oz);
+    }
+    mom[4 * (size_t)c] = Q;
+    mom[4 * (size_t)c + 1] = Px;
+    mom[4 * (size_t)c + 2] = Py;
+    mom[4 * (size_t)c + 3] = Pz;
+    count[c] = b - a;
+}
+
+// Deterministic compaction of occupied cells (one workgroup of 1024, 1024
+// consecutive cells per pass).
 __global__ __launch_bounds__(1024) void k_compact(const int* __restrict__ count, int M, int* occ,
                                                   int* cell2occ, int* nocc) {
-    __shared__ int part[1024];
+    __shared__ int wsum[32];
     const int t = threadIdx.x;
-    const int per = (M + 1023) / 1024;
-    const int c0 = t * per, c1 = min(M, c0 + per);
-    int mine = 0;
-    for (int c = c0; c < c1; ++c) mine += count[c] > 0;
-    part[t] = mine;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {     // inclusive scan (Hillis-Steele)
-        const int v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int k = part[t] - mine;
-    for (int c = c0; c < c1; ++c) {
-        if (count[c] > 0) {
-            occ[k] = c;
-            cell2occ[c] = k++;
-        } else {
-            cell2occ[c] = -1;
+    int carry = 0;
+    for (int base = 0; base < M; base += 1024) {
+        const int c = base + t;
+        const int f = (c < M && count[c] > 0) ? 1 : 0;
+        int tot;
+        const int ex = scan1024(f, wsum, &tot);
+        if (c < M) {
+            if (f) {
+                occ[carry + ex] = c;
+                cell2occ[c] = carry + ex;
+            } else {
+                cell2occ[c] = -1;
+            }
         }
+        carry += tot;
     }
-    if (t == 1023) *nocc = part[1023];
+    if (t == 0) *nocc = carry;
 }
 
 // Field at every occupied cell centre from the monopole + dipole of every
@@ -791,6 +833,127 @@ __global__ __launch_bounds__(kB) void k_layer1(const float4* __restrict__ pos,
     h1[e] = silu_f(z);
 }
 
+// The network's per-particle part fused into one kernel for hidden width 128:
+// finish layer 1 (A_cell + W1_offset o + b1, SiLU), layer 2 (128 x 128,
+// SiLU) and layer 3 (128 x 16) on the matrix cores, and
+// F = F_near + q (E_coarse + scale y).  W2 and W3 are staged once per
+// workgroup in LDS as BF16, column-major (the B operand of
+// v_mfma_f32_16x16x32_bf16: 8 consecutive K values of one column per lane);
+// each workgroup then walks 64-particle tiles.  Activations are rounded to
+// BF16 where the unfused path rounds them (as the next product stages them),
+// so the two paths compute the same products.  The hidden activations never
+// leave the CU.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int kMT = 64;                 // particles per tile (4 wavefronts x 16 rows)
+constexpr int kFH = 128;                // hidden width of the fused kernel
+constexpr int kFHP = kFH + 8;           // padded LDS row (BF16 elements)
+
+__global__ __launch_bounds__(256) void k_mlp_fused(
+    const float4* __restrict__ pos, const float4* __restrict__ lo, int n, int G,
+    const FFGrid* g, const int* __restrict__ cell2occ, const float* __restrict__ Ac,
+    const float* __restrict__ W1o, const float* __restrict__ b1, const float* __restrict__ W2,
+    const float* __restrict__ b2, const float* __restrict__ W3, const float* __restrict__ b3,
+    float scale, const double* __restrict__ Fn, const double* __restrict__ Ep, double* Fpart,
+    double* Fc, double* Fm) {
+    __shared__ __attribute__((aligned(16))) __bf16 sW2[kFH][kFHP];   // [out column][k]
+    __shared__ __attribute__((aligned(16))) __bf16 sW3[16][kFHP];    // [out column][k]
+    __shared__ __attribute__((aligned(16))) __bf16 sA[kMT][kFHP];    // layer-1 activations
+    __shared__ __attribute__((aligned(16))) __bf16 sB[kMT][kFHP];    // layer-2 activations
+    __shared__ float sY[kMT][4];
+    __shared__ float sOff[kMT][3];
+    __shared__ int sOcc[kMT];
+    const int t = threadIdx.x, w = t / 64, l = t % 64;
+    for (int e = t; e < kFH * kFH; e += 256) sW2[e % kFH][e / kFH] = bf16_rne(W2[e]);
+    for (int e = t; e < kFH * 16; e += 256) sW3[e % 16][e / 16] = bf16_rne(W3[e]);
+    // this thread's layer-1 column: offset weights and bias in registers
+    const int col = t % kFH;
+    const float w0 = bf16_round(W1o[col]), w1 = bf16_round(W1o[kFH + col]),
+                w2 = bf16_round(W1o[2 * kFH + col]), bias1 = b1[col];
+    for (int tile = blockIdx.x; tile * kMT < n; tile += gridDim.x) {
+        const int s0 = tile * kMT;
+        __syncthreads();                                // LDS of the previous tile is free
+        if (t < kMT) {
+            const int s = s0 + t;
+            int oc = -1;
+            float off[3] = {0.f, 0.f, 0.f};
+            if (s < n) {
+                int c;
+                particle_cell(pos[s], lo[s], G, g, &c, off);
+                oc = cell2occ[c];
+            }
+            sOcc[t] = oc;
+            sOff[t][0] = bf16_round(off[0]);
+            sOff[t][1] = bf16_round(off[1]);
+            sOff[t][2] = bf16_round(off[2]);
+        }
+        __syncthreads();
+        // layer 1: two rows per step, one column per thread
+        for (int row = t / kFH; row < kMT; row += 2) {
+            const int oc = sOcc[row];
+            float a = 0.f;
+            if (oc >= 0) {
+                const float z = Ac[(size_t)oc * kFH + col] + sOff[row][0] * w0 +
+                                sOff[row][1] * w1 + sOff[row][2] * w2 + bias1;
+                a = silu_f(z);
+            }
+            sA[row][col] = bf16_rne(a);
+        }
+        __syncthreads();
+        // layer 2: wavefront w owns rows 16w .. 16w+15, all 128 columns
+        f32x4_t acc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < kFH / 32; ++ks) {
+            const int kk = ks * 32 + 8 * (l / 16);
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&sA[w * 16 + l % 16][kk]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&sW2[j * 16 + l % 16][kk]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int c = j * 16 + l % 16;
+            const float bb = b2[c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sB[w * 16 + 4 * (l / 16) + r][c] = bf16_rne(silu_f(acc[j][r] + bb));
+        }
+        __syncthreads();
+        // layer 3: the wavefront's 16 rows x 16 output columns (3 used)
+        f32x4_t y = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < kFH / 32; ++ks) {
+            const int kk = ks * 32 + 8 * (l / 16);
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&sB[w * 16 + l % 16][kk]);
+            const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&sW3[l % 16][kk]);
+            y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, y, 0, 0, 0);
+        }
+        if (l % 16 < 3) {
+            const float bb = b3[l % 16];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sY[w * 16 + 4 * (l / 16) + r][l % 16] = y[r] + bb;
+        }
+        __syncthreads();
+        if (t < kMT) {
+            const int s = s0 + t;
+            if (s < n) {
+                const double q = (double)pos[s].w;
+                for (int k = 0; k < 3; ++k) {
+                    const double ec = q * Ep[(size_t)k * n + s];
+                    const double em = q * (double)scale * (double)sY[t][k];
+                    Fpart[(size_t)k * n + s] = Fn[(size_t)k * n + s] + ec + em;
+                    if (Fc) Fc[(size_t)k * n + s] = ec;
+                    if (Fm) Fm[(size_t)k * n + s] = em;
+                }
+            }
+        }
+    }
+}
+
 // F = F_near + q (E_coarse + scale y) into Fpart (slot order) and optional
 // parts.
 __global__ __launch_bounds__(kB) void k_combine(const float4* __restrict__ pos, int n,
@@ -1036,10 +1199,16 @@ ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
     KLAUNCH(k_absmax_part, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
     KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, f->cfg.near_cut, G,
             f->cfg.near_mode, f->cfg.block, f->rlj, f->grid);
-    KLAUNCH(k_zero_d, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, 4 * M);
-    KLAUNCH(k_zero_i, dim3((M + kB - 1) / kB), dim3(kB), s, f->count, M);
-    KLAUNCH(k_moments, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid, f->mom,
-            f->count);
+    if (f->cfg.near_mode == 1) {
+        // slots are in grid-cell order (ff_near ran first): per-cell sums
+        KLAUNCH(k_moments_sorted, dim3((M + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, M, G,
+                f->grid, f->cfirst, f->mom, f->count);
+    } else {
+        KLAUNCH(k_zero_d, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, 4 * M);
+        KLAUNCH(k_zero_i, dim3((M + kB - 1) / kB), dim3(kB), s, f->count, M);
+        KLAUNCH(k_moments, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid,
+                f->mom, f->count);
+    }
     KLAUNCH(k_compact, dim3(1), dim3(1024), s, f->count, M, f->occ, f->cell2occ, f->nocc);
     if (f->cfg.near_mode == 1) {
         KLAUNCH(k_coarse_local, dim3((M + kLB - 1) / kLB, f->loc_split), dim3(kLB), s, f->mom,
@@ -1130,6 +1299,19 @@ ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
     st = gemm(s, f->Xc, f->Kp, 0, f->W + f->offW1, H, 0, f->Ac, H, M, H, f->Kp, nullptr, 0,
               nullptr, 0, 0, f->nocc);
     if (st != LD_OK) return st;
+    if (H == kFH) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int tiles = (n + kMT - 1) / kMT;
+        KLAUNCH(k_mlp_fused, dim3(std::max(1, std::min(tiles, 2 * cus))), dim3(256), s, c->pos,
+                c->lo, n, G, f->grid, f->cell2occ, f->Ac,
+                f->W + f->offW1 + (size_t)(f->K - 3) * H, f->W + f->offb1, f->W + f->offW2,
+                f->W + f->offb2, f->W + f->offW3, f->W + f->offb3, f->out_scale, f->Fnear,
+                f->Ep, c->Fpart, Fc, Fm);
+        HIP_TRY(ld::launch_boxes(c->pos, n, c->box, s));
+        return LD_OK;
+    }
     KLAUNCH(k_layer1, dim3((unsigned)(((size_t)n * H + kB - 1) / kB)), dim3(kB), s, c->pos, c->lo,
             n, G, f->grid, f->cell2occ, f->Ac,
             f->W + f->offW1 + (size_t)(f->K - 3) * H, f->W + f->offb1, H, f->h1);

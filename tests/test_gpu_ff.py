@@ -206,9 +206,12 @@ def test_mlp_inference_and_gradients(ld, orc, sysw):
         assert err <= 1e-2, (k, err)
 
 
-def test_mlp_part_on_particles(ld, orc, sysw):
-    s = make_sys(ld, sysw, hidden=64)
-    K, H = 4 * B ** 3 + 3, 64
+@pytest.mark.parametrize("H", [64, 128])
+def test_mlp_part_on_particles(ld, orc, sysw, H):
+    """The network's per-particle term (H = 128 runs the fused layer-1 /
+    layer-2 / layer-3 kernel, H = 64 the separate products)."""
+    s = make_sys(ld, sysw, hidden=H)
+    K = 4 * B ** 3 + 3
     w, sq, _ = s.ff_weights()
     wp = random_packed(w.size, K, H, 9)
     s.ff_set_weights(wp, sq, 0.05)
