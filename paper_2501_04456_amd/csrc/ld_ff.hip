@@ -382,7 +382,6 @@ __global__ __launch_bounds__(64) void k_near_block(const float4* __restrict__ po
                                                    PairTable tab, double* F) {
     __shared__ float4 sp[64];
     __shared__ int sx[64];
-    __shared__ int st[64];
     __shared__ float ttab[3 * kMaxTypes * kMaxTypes];
     const int lane = threadIdx.x;
     if ((int)blockIdx.x >= *ntiles) return;            // uniform per workgroup
@@ -420,31 +419,31 @@ __global__ __launch_bounds__(64) void k_near_block(const float4* __restrict__ po
                 const int j = jt + lane;
                 if (j < j1) {
                     sp[lane] = pos[j];
-                    sx[lane] = (int)((unsigned)(keys[j] >> 32) % (unsigned)G);
-                    st[lane] = typ[j];
+                    sx[lane] = (int)((unsigned)(keys[j] >> 32) % (unsigned)G) | (typ[j] << 16);
                 } else {
                     sp[lane] = make_float4(kFarAway, kFarAway, kFarAway, 0.f);
-                    sx[lane] = -(1 << 20);
-                    st[lane] = 0;
+                    sx[lane] = 0xFFFF;
                 }
                 __syncthreads();
                 const int cnt = min(64, j1 - jt);
                 for (int kb = 0; kb < cnt; kb += 32) {
                     const int ke = min(cnt, kb + 32);
                     float bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll 4
                     for (int k = kb; k < ke; ++k) {
                         const float4 pj = sp[k];
                         const float ddx = pj.x - pi.x, ddy = pj.y - pi.y, ddz = pj.z - pi.z;
                         const float r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
                         const bool self = jt + k == i;
-                        const bool inb = row_in && abs(sx[k] - ix) <= half && !self;
+                        const int info = sx[k];
+                        const bool inb = row_in && abs((info & 0xFFFF) - ix) <= half && !self;
                         const float ri = __builtin_amdgcn_rsqf(r2);
                         const float w = inb ? (pj.w * ri) * (ri * ri) : 0.f;
                         bx = fmaf(w, ddx, bx);
                         by = fmaf(w, ddy, by);
                         bz = fmaf(w, ddz, bz);
                         if (r2 < rc2max && !self) {
-                            const int pidx = ti * T + st[k];
+                            const int pidx = ti * T + (info >> 16);
                             if (r2 < ttab[kMaxTypes * kMaxTypes + pidx]) {
                                 const float ir2 = 1.0f / r2;
                                 const float s2 = ttab[pidx] * ir2;
@@ -617,7 +616,10 @@ __global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
 //                                                    U = b R + 3 u^5 P
 // (E = -grad of Q/|R| + P.R/|R|^3; J and H its derivatives).  Stored per
 // cell: E (3), J (xx xy xz yy yz zz), H (xxx xxy xxz xyy xyz xzz yyy yyz yzz
-// zzz).  FP32 terms summed over one LDS tile, FP64 totals.  The sources are
+// zzz).  The field is harmonic outside its sources, so J and H are traceless:
+// J_zz, H_xzz, H_yzz and H_zzz are not accumulated here but follow from the
+// other components where the expansion is evaluated.  FP32 terms summed over
+// one LDS tile, FP64 totals.  The sources are
 // split over gridDim.y workgroups (one partial sum each, reduced in a fixed
 // order by k_loc_reduce) so that a few hundred target tiles still fill the
 // chip.
@@ -686,7 +688,7 @@ __global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__
             f[5] += fmaf(Ux, Rz, Tz * Rx);
             f[6] += fmaf(Uy, Ry, fmaf(Ty, Ry, a));
             f[7] += fmaf(Uy, Rz, Tz * Ry);
-            f[8] += fmaf(Uz, Rz, fmaf(Tz, Rz, a));
+            // zz follows from the trace (k_coarse_eval)
             // H: S_cd Y_e - W_c S_de - W_d S_ce + delta terms, S = R R^T,
             // W = 15 u^7 P, Y = c R - W
             const float Wx = c2 * m.y, Wy = c2 * m.z, Wz = c2 * m.w;
@@ -698,11 +700,9 @@ __global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__
             f[11] += fmaf(Sxx, Yz, fmaf(-2.0f * Wx, Sxz, Uz));                 // xxz
             f[12] += fmaf(Sxy, Yy, fmaf(-Wx, Syy, fmaf(-Wy, Sxy, Ux)));        // xyy
             f[13] += fmaf(Sxy, Yz, fmaf(-Wx, Syz, -Wy * Sxz));                 // xyz
-            f[14] += fmaf(Sxz, Yz, fmaf(-Wx, Szz, fmaf(-Wz, Sxz, Ux)));        // xzz
             f[15] += fmaf(Syy, Yy, fmaf(-2.0f * Wy, Syy, 3.0f * Uy));          // yyy
             f[16] += fmaf(Syy, Yz, fmaf(-2.0f * Wy, Syz, Uz));                 // yyz
-            f[17] += fmaf(Syz, Yz, fmaf(-Wy, Szz, fmaf(-Wz, Syz, Uy)));        // yzz
-            f[18] += fmaf(Szz, Yz, fmaf(-2.0f * Wz, Szz, 3.0f * Uz));          // zzz
+            // xzz, yzz, zzz follow from the traces (k_coarse_eval)
         }
 #pragma unroll
         for (int k = 0; k < kLoc; ++k) acc[k] += (double)f[k];
@@ -748,7 +748,13 @@ __global__ __launch_bounds__(kB) void k_coarse_eval(const float4* __restrict__ p
     if (!block_mode) {
         E[0] = Ec[3 * c]; E[1] = Ec[3 * c + 1]; E[2] = Ec[3 * c + 2];
     } else {
-        const double* o = Ec + kLoc * c;
+        double o[kLoc];
+        for (int k = 0; k < kLoc; ++k) o[k] = Ec[kLoc * c + k];
+        // the components the expansion kernel leaves to Laplace's equation
+        o[8] = -(o[3] + o[6]);             // J_zz
+        o[14] = -(o[9] + o[12]);           // H_xzz = -(H_xxx + H_xyy)
+        o[17] = -(o[10] + o[15]);          // H_yzz = -(H_xxy + H_yyy)
+        o[18] = -(o[11] + o[16]);          // H_zzz = -(H_xxz + H_yyz)
         const double dx = x - (-L + (cx + 0.5) * hh), dy = y - (-L + (cy + 0.5) * hh),
                      dz = z - (-L + (cz + 0.5) * hh);
         const double xx = 0.5 * dx * dx, yy = 0.5 * dy * dy, zz = 0.5 * dz * dz;
