@@ -99,6 +99,7 @@ def lib():
                                          C.POINTER(_Params), C.c_int, C.c_double, C.c_int,
                                          C.POINTER(C.c_int64), C.c_int64, dp, dp]
         L.ldo_ff_local.argtypes = [C.c_int, C.c_double, C.c_int, dp, dp]
+        L.ldo_ff_local2.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, dp, dp]
         L.ldo_ff_local_eval.argtypes = [C.c_int64, dp, C.c_int, C.c_double, dp, dp]
         L.ldo_ff_features.argtypes = [C.c_int64, dp, C.c_int, C.c_double, C.c_int, dp,
                                       C.c_double, dp]
@@ -346,6 +347,14 @@ def ff_local(mom, G: int, L: float, B: int = 5) -> np.ndarray:
     mom = np.ascontiguousarray(mom, np.float64)
     out = np.zeros((G ** 3, 19))
     lib().ldo_ff_local(G, L, B, _dp(mom), _dp(out))
+    return out
+
+
+def ff_local2(mom, G: int, L: float, B: int = 5, D: int = 2) -> np.ndarray:
+    """Two-level version of ff_local (parents beyond D enter as a whole)."""
+    mom = np.ascontiguousarray(mom, np.float64)
+    out = np.zeros((G ** 3, 19))
+    lib().ldo_ff_local2(G, L, B, D, _dp(mom), _dp(out))
     return out
 
 

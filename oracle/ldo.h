@@ -183,6 +183,13 @@ void ldo_ff_split_block(int64_t n, const double* x, const int32_t* type, const d
  * point-charge and point-dipole fields and by Laplace's equation. */
 void ldo_ff_local(int G, double L, int B, const double* mom, double* out);
 
+/* The same expansion with far cells grouped by 2x2x2 parent cells (G even):
+ * parents farther than D (Chebyshev, in parent cells) from the target's
+ * parent enter through their own monopole + dipole.  Pinned by D >= G/2
+ * reproducing ldo_ff_local, parent moments against ldo_ff_moments on the
+ * G/2 grid, and the method's accuracy on a droplet. */
+void ldo_ff_local2(int G, double L, int B, int D, const double* mom, double* out);
+
 /* E(x) = E + J d + (1/2) H d d, d = x - centre of x's cell, for n points. */
 void ldo_ff_local_eval(int64_t n, const double* x, int G, double L, const double* loc,
                        double* E);

@@ -245,6 +245,36 @@ static void inv_r_derivs(const double R[3], double T1[3], double T2[3][3], doubl
 #undef D
 }
 
+/* Adds one source's field, gradient and Hessian at R = target - source
+ * centre (see ldo_ff_local). */
+static void add_source(const double R[3], double Q, const double P[3], double E[3],
+                       double J[3][3], double H[3][3][3]) {
+    double T1[3], T2[3][3], T3[3][3][3], T4[3][3][3][3];
+    inv_r_derivs(R, T1, T2, T3, T4);
+    for (int c = 0; c < 3; ++c) {
+        E[c] += -Q * T1[c];
+        for (int a = 0; a < 3; ++a) E[c] += P[a] * T2[a][c];
+        for (int d = 0; d < 3; ++d) {
+            J[c][d] += -Q * T2[c][d];
+            for (int a = 0; a < 3; ++a) J[c][d] += P[a] * T3[a][c][d];
+            for (int e = 0; e < 3; ++e) {
+                H[c][d][e] += -Q * T3[c][d][e];
+                for (int a = 0; a < 3; ++a) H[c][d][e] += P[a] * T4[a][c][d][e];
+            }
+        }
+    }
+}
+
+static const int J_IDX[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+static const int H_IDX[10][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2},
+                                 {0, 2, 2}, {1, 1, 1}, {1, 1, 2}, {1, 2, 2}, {2, 2, 2}};
+
+static void pack_local(const double E[3], double J[3][3], double H[3][3][3], double* o) {
+    for (int k = 0; k < 3; ++k) o[k] = E[k];
+    for (int k = 0; k < 6; ++k) o[3 + k] = J[J_IDX[k][0]][J_IDX[k][1]];
+    for (int k = 0; k < 10; ++k) o[9 + k] = H[H_IDX[k][0]][H_IDX[k][1]][H_IDX[k][2]];
+}
+
 /* Local expansion at each cell centre.  A source cell with moments (Q, P)
  * about its centre c_s has the potential phi(x) = Q g(R) - P_a d_a g(R),
  * R = x - c_s (the expansion of sum q_hat / |x - x_j| to dipole order), so
@@ -255,9 +285,6 @@ static void inv_r_derivs(const double R[3], double T1[3], double T2[3][3], doubl
 void ldo_ff_local(int G, double L, int B, const double* mom, double* out) {
     const int half = B / 2;
     const size_t M = (size_t)G * G * G;
-    static const int J_IDX[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
-    static const int H_IDX[10][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2},
-                                     {0, 2, 2}, {1, 1, 1}, {1, 1, 2}, {1, 2, 2}, {2, 2, 2}};
 #pragma omp parallel for schedule(dynamic, 16)
     for (size_t t = 0; t < M; ++t) {
         const int tc[3] = {(int)(t % G), (int)((t / G) % G), (int)(t / ((size_t)G * G))};
@@ -269,27 +296,70 @@ void ldo_ff_local(int G, double L, int B, const double* mom, double* out) {
                 continue;
             const double Q = mom[4 * s], P[3] = {mom[4 * s + 1], mom[4 * s + 2], mom[4 * s + 3]};
             if (Q == 0.0 && P[0] == 0.0 && P[1] == 0.0 && P[2] == 0.0) continue;
-            double R[3], T1[3], T2[3][3], T3[3][3][3], T4[3][3][3][3];
+            double R[3];
             for (int k = 0; k < 3; ++k) R[k] = centre(tc[k], G, L) - centre(sc[k], G, L);
-            inv_r_derivs(R, T1, T2, T3, T4);
-            for (int c = 0; c < 3; ++c) {
-                E[c] += -Q * T1[c];
-                for (int a = 0; a < 3; ++a) E[c] += P[a] * T2[a][c];
-                for (int d = 0; d < 3; ++d) {
-                    J[c][d] += -Q * T2[c][d];
-                    for (int a = 0; a < 3; ++a) J[c][d] += P[a] * T3[a][c][d];
-                    for (int e = 0; e < 3; ++e) {
-                        H[c][d][e] += -Q * T3[c][d][e];
-                        for (int a = 0; a < 3; ++a) H[c][d][e] += P[a] * T4[a][c][d][e];
-                    }
-                }
+            add_source(R, Q, P, E, J, H);
+        }
+        pack_local(E, J, H, out + 19 * t);
+    }
+}
+
+/* Two-level version (G even).  Parent cells are the 2x2x2 blocks of cells
+ * (a (G/2)^3 grid of side 2h); a parent's moments are its children's moments
+ * moved to the parent centre, Q_p = sum Q_c, P_p = sum (P_c + Q_c (c_c - c_p))
+ * -- exactly the monopole and dipole of its particles about c_p.  For target
+ * cell t with parent T, a parent within Chebyshev distance D of T contributes
+ * its children one by one (those outside t's B^3 block, as in
+ * ldo_ff_local); every other parent contributes through its own moments.
+ * Each cell outside the block is counted once (a parent farther than D >= 1
+ * holds no cell of the block); D >= G/2 gives ldo_ff_local. */
+void ldo_ff_local2(int G, double L, int B, int D, const double* mom, double* out) {
+    const int half = B / 2;
+    const int Gp = G / 2;
+    const size_t M = (size_t)G * G * G, Mp = (size_t)Gp * Gp * Gp;
+    double* pm = (double*)calloc(4 * Mp, sizeof(double));
+    for (size_t c = 0; c < M; ++c) {
+        const int cc[3] = {(int)(c % G), (int)((c / G) % G), (int)(c / ((size_t)G * G))};
+        const size_t p = ((size_t)(cc[2] / 2) * Gp + cc[1] / 2) * Gp + cc[0] / 2;
+        pm[4 * p] += mom[4 * c];
+        for (int k = 0; k < 3; ++k)
+            pm[4 * p + 1 + k] += mom[4 * c + 1 + k] +
+                                 mom[4 * c] * (centre(cc[k], G, L) - centre(cc[k] / 2, Gp, L));
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (size_t t = 0; t < M; ++t) {
+        const int tc[3] = {(int)(t % G), (int)((t / G) % G), (int)(t / ((size_t)G * G))};
+        const int T[3] = {tc[0] / 2, tc[1] / 2, tc[2] / 2};
+        double E[3] = {0, 0, 0}, J[3][3] = {{0}}, H[3][3][3] = {{{0}}};
+        for (size_t p = 0; p < Mp; ++p) {
+            const int pc[3] = {(int)(p % Gp), (int)((p / Gp) % Gp), (int)(p / ((size_t)Gp * Gp))};
+            const int near = abs(pc[0] - T[0]) <= D && abs(pc[1] - T[1]) <= D &&
+                             abs(pc[2] - T[2]) <= D;
+            if (!near) {
+                const double Q = pm[4 * p], P[3] = {pm[4 * p + 1], pm[4 * p + 2], pm[4 * p + 3]};
+                if (Q == 0.0 && P[0] == 0.0 && P[1] == 0.0 && P[2] == 0.0) continue;
+                double R[3];
+                for (int k = 0; k < 3; ++k) R[k] = centre(tc[k], G, L) - centre(pc[k], Gp, L);
+                add_source(R, Q, P, E, J, H);
+                continue;
+            }
+            for (int ch = 0; ch < 8; ++ch) {
+                const int sc[3] = {2 * pc[0] + (ch & 1), 2 * pc[1] + ((ch >> 1) & 1),
+                                   2 * pc[2] + (ch >> 2)};
+                if (abs(sc[0] - tc[0]) <= half && abs(sc[1] - tc[1]) <= half &&
+                    abs(sc[2] - tc[2]) <= half)
+                    continue;
+                const size_t s = ((size_t)sc[2] * G + sc[1]) * G + sc[0];
+                const double Q = mom[4 * s], P[3] = {mom[4 * s + 1], mom[4 * s + 2], mom[4 * s + 3]};
+                if (Q == 0.0 && P[0] == 0.0 && P[1] == 0.0 && P[2] == 0.0) continue;
+                double R[3];
+                for (int k = 0; k < 3; ++k) R[k] = centre(tc[k], G, L) - centre(sc[k], G, L);
+                add_source(R, Q, P, E, J, H);
             }
         }
-        double* o = out + 19 * t;
-        for (int k = 0; k < 3; ++k) o[k] = E[k];
-        for (int k = 0; k < 6; ++k) o[3 + k] = J[J_IDX[k][0]][J_IDX[k][1]];
-        for (int k = 0; k < 10; ++k) o[9 + k] = H[H_IDX[k][0]][H_IDX[k][1]][H_IDX[k][2]];
+        pack_local(E, J, H, out + 19 * t);
     }
+    free(pm);
 }
 
 void ldo_ff_local_eval(int64_t n, const double* x, int G, double L, const double* loc,

@@ -255,6 +255,63 @@ def test_local_expansion_is_harmonic_and_converges(oracle_lib):
     assert np.allclose(oracle_lib.ff_local_eval(ct[None], G, L, loc)[0], loc[t, :3], rtol=1e-15)
 
 
+def test_two_level_expansion(oracle_lib):
+    """Two-level grouping: a reach covering the whole parent grid is the
+    one-level expansion; a point charge at a parent centre (so the parent's
+    monopole is exact and its dipole zero) gives, at targets whose parent is
+    beyond the reach, the exact field and its derivatives (finite
+    differences of Coulomb's law); and every reach keeps the method's
+    accuracy on a droplet (error within a few tens of percent of one level
+    for reach >= 2)."""
+    G, L = 12, 30.0
+    x = ball(2500, 28.0, 9)
+    q = np.where(np.arange(2500) % 3 == 0, 1.0, -0.6)
+    m = oracle_lib.ff_moments(x, q, G, L)
+    one = oracle_lib.ff_local(m, G, L, 5)
+    assert np.allclose(oracle_lib.ff_local2(m, G, L, 5, G // 2), one, rtol=1e-11,
+                       atol=1e-13 * np.abs(one).max())
+    # a point charge at the centre of parent (1, 1, 1): the corner shared by
+    # cells 2..3 along each axis
+    G, L = 16, 32.0
+    h = 2 * L / G
+    src = np.array([[-L + 3 * h, -L + 3 * h, -L + 3 * h]])
+    m = oracle_lib.ff_moments(src, np.array([1.3]), G, L)
+    D = 2
+    loc = oracle_lib.ff_local2(m, G, L, 5, D)
+
+    def field(pt):
+        r = pt - src[0]
+        return 1.3 * r / np.linalg.norm(r) ** 3
+
+    for t in ((12, 9, 13), (14, 2, 3), (9, 15, 15), (2, 13, 1)):
+        tx, ty, tz = t
+        assert max(abs(tx // 2 - 1), abs(ty // 2 - 1), abs(tz // 2 - 1)) > D
+        k = (tz * G + ty) * G + tx
+        ct = np.array([-L + (tx + 0.5) * h, -L + (ty + 0.5) * h, -L + (tz + 0.5) * h])
+        E, J, H = _unpack(loc[k])
+        E0, J0, H0 = _fd_derivs(field, ct, 0.005 * h)
+        assert np.allclose(E, E0, rtol=0, atol=1e-9 * np.abs(E0).max())
+        assert np.allclose(J, J0, rtol=0, atol=1e-4 * np.abs(J0).max())
+        assert np.allclose(H, H0, rtol=0, atol=1e-4 * np.abs(H0).max())
+    # accuracy on a droplet against the exact far field
+    w = W.config_medium(n=6000, seed=6)
+    x = w.pos.astype(np.float64)
+    qh = oracle_lib.qhat(w.charge, w.params)
+    L = float(np.float32(np.abs(w.pos).max()) * np.float32(1 + 2 ** -10))
+    G, B = 16, 5
+    rows = np.arange(0, 6000, 7)
+    Fn, Ef = oracle_lib.ff_split_block(x, w.type, w.charge, w.params, G, L, B, rows=rows)
+    F = Fn + qh[rows, None] * Ef
+    m = oracle_lib.ff_moments(x, qh, G, L)
+    med = {}
+    for D in (0, 2, 3):
+        loc = oracle_lib.ff_local(m, G, L, B) if D == 0 else oracle_lib.ff_local2(m, G, L, B, D)
+        El = oracle_lib.ff_local_eval(x[rows], G, L, loc)
+        rel = np.linalg.norm(qh[rows, None] * (El - Ef), axis=1) / np.linalg.norm(F, axis=1)
+        med[D] = np.median(rel)
+    assert med[0] < 3e-3 and med[2] < 1.3 * med[0] and med[3] < 1.2 * med[0], med
+
+
 def test_local_expansion_accuracy_on_a_droplet(oracle_lib):
     """The method's own error: exact block near field plus the local
     expansion of the far cells' monopoles and dipoles reproduces the exact
