@@ -262,9 +262,10 @@ ld_status ld_kernel_time(ld_ctx* ctx, int64_t* launches, double* total_ms);
  * near_mode 1 (block): the Coulomb pairs with j in i's block^3 neighbourhood
  *   (and every LJ pair) are summed exactly; E_coarse is the second-order
  *   Taylor expansion about i's cell centre of the monopole + dipole field of
- *   every cell outside the neighbourhood, evaluated at x_i; the network
- *   predicts the rest of the field of the particles outside the block.
- *   near_cut is unused.
+ *   every cell outside the neighbourhood (the cells of 2x2x2 parents beyond
+ *   parent_reach taken together through the parent's moments), evaluated at
+ *   x_i; the network predicts the rest of the field of the particles outside
+ *   the block.  near_cut is unused.
  *
  * The MLP (K = 4 block^3 + 3 inputs -> hidden -> hidden -> 3, SiLU, BF16
  * operands, FP32 accumulation) reads the neighbourhood's (Q / sq,
@@ -279,7 +280,9 @@ typedef struct {
     int32_t judge_every;    /* steps between judge evaluations (mode 2) */
     double judge_tol;       /* median relative force error allowed */
     int32_t near_mode;      /* 0 radial cutoff r_c, 1 the block^3 cells */
-    int32_t reserved;       /* 0 */
+    int32_t parent_reach;   /* block mode, even grid: > 0 groups far cells by 2x2x2
+                               parent cells beyond this Chebyshev distance (in parent
+                               cells) from the target's parent; 0 = one level */
 } ld_ff_config;
 
 typedef struct {

@@ -82,6 +82,11 @@ struct FarField {
     int4* tiles = nullptr;             // row tiles (block mode)
     double* loc_part = nullptr;        // [loc_split][G^3][19] partial expansions
     int loc_split = 1;
+    double* pmom = nullptr;            // [(G/2)^3 * 4] parent moments (two-level)
+    int* pcount = nullptr;             // [(G/2)^3]
+    int* pocc = nullptr;               // [(G/2)^3] compacted occupied parents
+    int* pcell2occ = nullptr;          // [(G/2)^3]
+    int* npocc = nullptr;              // [1]
     int* ntiles = nullptr;
     int max_tiles = 0;
     float* Xc = nullptr;               // [G^3 * Kp]
@@ -624,6 +629,49 @@ __global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
 // order by k_loc_reduce) so that a few hundred target tiles still fill the
 // chip.
 constexpr int kLB = 128;
+
+// One source cell (moments Q, P about its centre) seen from a target centre
+// at R = target - source: adds its E, J and H (the 12 accumulated components)
+// to f.  valid = false adds nothing (u = 0 zeroes every term).
+__device__ __forceinline__ void loc_add(float* f, float Rx, float Ry, float Rz, float Q, float Px,
+                                        float Py, float Pz, bool valid) {
+    const float r2 = fmaf(Rz, Rz, fmaf(Ry, Ry, Rx * Rx));
+    const float u = valid ? __builtin_amdgcn_rsqf(r2) : 0.f;
+    const float u2 = u * u, u3 = u2 * u, u5 = u3 * u2, u7 = u5 * u2, u9 = u7 * u2;
+    const float p = fmaf(Pz, Rz, fmaf(Py, Ry, Px * Rx));
+    const float a = fmaf(3.0f * p, u5, Q * u3);
+    const float b = fmaf(-15.0f * p, u7, -3.0f * Q * u5);
+    const float c = fmaf(105.0f * p, u9, 15.0f * Q * u7);
+    const float t5 = 3.0f * u5, c2 = 15.0f * u7;
+    // E
+    f[0] = fmaf(a, Rx, fmaf(-u3, Px, f[0]));
+    f[1] = fmaf(a, Ry, fmaf(-u3, Py, f[1]));
+    f[2] = fmaf(a, Rz, fmaf(-u3, Pz, f[2]));
+    // J: (b R_c + 3u^5 P_c) R_d + 3u^5 P_d R_c (+ a on the diagonal)
+    const float Tx = t5 * Px, Ty = t5 * Py, Tz = t5 * Pz;
+    const float Ux = fmaf(b, Rx, Tx), Uy = fmaf(b, Ry, Ty), Uz = fmaf(b, Rz, Tz);
+    f[3] += fmaf(Ux, Rx, fmaf(Tx, Rx, a));
+    f[4] += fmaf(Ux, Ry, Ty * Rx);
+    f[5] += fmaf(Ux, Rz, Tz * Rx);
+    f[6] += fmaf(Uy, Ry, fmaf(Ty, Ry, a));
+    f[7] += fmaf(Uy, Rz, Tz * Ry);
+    // zz follows from the trace (k_coarse_eval)
+    // H: S_cd Y_e - W_c S_de - W_d S_ce + delta terms, S = R R^T,
+    // W = 15 u^7 P, Y = c R - W
+    const float Wx = c2 * Px, Wy = c2 * Py, Wz = c2 * Pz;
+    const float Yx = fmaf(c, Rx, -Wx), Yy = fmaf(c, Ry, -Wy), Yz = fmaf(c, Rz, -Wz);
+    const float Sxx = Rx * Rx, Sxy = Rx * Ry, Sxz = Rx * Rz, Syy = Ry * Ry, Syz = Ry * Rz;
+    f[9] += fmaf(Sxx, Yx, fmaf(-2.0f * Wx, Sxx, 3.0f * Ux));            // xxx
+    f[10] += fmaf(Sxx, Yy, fmaf(-2.0f * Wx, Sxy, Uy));                 // xxy
+    f[11] += fmaf(Sxx, Yz, fmaf(-2.0f * Wx, Sxz, Uz));                 // xxz
+    f[12] += fmaf(Sxy, Yy, fmaf(-Wx, Syy, fmaf(-Wy, Sxy, Ux)));        // xyy
+    f[13] += fmaf(Sxy, Yz, fmaf(-Wx, Syz, -Wy * Sxz));                 // xyz
+    f[15] += fmaf(Syy, Yy, fmaf(-2.0f * Wy, Syy, 3.0f * Uy));          // yyy
+    f[16] += fmaf(Syy, Yz, fmaf(-2.0f * Wy, Syz, Uz));                 // yyz
+    // xzz, yzz, zzz follow from the traces (k_coarse_eval)
+}
+
+
 __global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__ mom,
                                                       const int* __restrict__ occ,
                                                       const int* __restrict__ nocc, int G, int B,
@@ -667,42 +715,7 @@ __global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__
             const float dx = tx - cs.x, dy = ty - cs.y, dz = tz - cs.z;
             const bool outside = fmaxf(fabsf(dx), fmaxf(fabsf(dy), fabsf(dz))) > half;
             const float4 m = sm[k];
-            const float Rx = dx * h, Ry = dy * h, Rz = dz * h;
-            const float r2 = fmaf(Rz, Rz, fmaf(Ry, Ry, Rx * Rx));
-            const float u = outside ? __builtin_amdgcn_rsqf(r2) : 0.f;
-            const float u2 = u * u, u3 = u2 * u, u5 = u3 * u2, u7 = u5 * u2, u9 = u7 * u2;
-            const float p = fmaf(m.w, Rz, fmaf(m.z, Ry, m.y * Rx));
-            const float a = fmaf(3.0f * p, u5, m.x * u3);
-            const float b = fmaf(-15.0f * p, u7, -3.0f * m.x * u5);
-            const float c = fmaf(105.0f * p, u9, 15.0f * m.x * u7);
-            const float t5 = 3.0f * u5, c2 = 15.0f * u7;
-            // E
-            f[0] = fmaf(a, Rx, fmaf(-u3, m.y, f[0]));
-            f[1] = fmaf(a, Ry, fmaf(-u3, m.z, f[1]));
-            f[2] = fmaf(a, Rz, fmaf(-u3, m.w, f[2]));
-            // J: (b R_c + 3u^5 P_c) R_d + 3u^5 P_d R_c (+ a on the diagonal)
-            const float Tx = t5 * m.y, Ty = t5 * m.z, Tz = t5 * m.w;
-            const float Ux = fmaf(b, Rx, Tx), Uy = fmaf(b, Ry, Ty), Uz = fmaf(b, Rz, Tz);
-            f[3] += fmaf(Ux, Rx, fmaf(Tx, Rx, a));
-            f[4] += fmaf(Ux, Ry, Ty * Rx);
-            f[5] += fmaf(Ux, Rz, Tz * Rx);
-            f[6] += fmaf(Uy, Ry, fmaf(Ty, Ry, a));
-            f[7] += fmaf(Uy, Rz, Tz * Ry);
-            // zz follows from the trace (k_coarse_eval)
-            // H: S_cd Y_e - W_c S_de - W_d S_ce + delta terms, S = R R^T,
-            // W = 15 u^7 P, Y = c R - W
-            const float Wx = c2 * m.y, Wy = c2 * m.z, Wz = c2 * m.w;
-            const float Yx = fmaf(c, Rx, -Wx), Yy = fmaf(c, Ry, -Wy), Yz = fmaf(c, Rz, -Wz);
-            const float Sxx = Rx * Rx, Sxy = Rx * Ry, Sxz = Rx * Rz, Syy = Ry * Ry, Syz = Ry * Rz,
-                        Szz = Rz * Rz;
-            f[9] += fmaf(Sxx, Yx, fmaf(-2.0f * Wx, Sxx, 3.0f * Ux));            // xxx
-            f[10] += fmaf(Sxx, Yy, fmaf(-2.0f * Wx, Sxy, Uy));                 // xxy
-            f[11] += fmaf(Sxx, Yz, fmaf(-2.0f * Wx, Sxz, Uz));                 // xxz
-            f[12] += fmaf(Sxy, Yy, fmaf(-Wx, Syy, fmaf(-Wy, Sxy, Ux)));        // xyy
-            f[13] += fmaf(Sxy, Yz, fmaf(-Wx, Syz, -Wy * Sxz));                 // xyz
-            f[15] += fmaf(Syy, Yy, fmaf(-2.0f * Wy, Syy, 3.0f * Uy));          // yyy
-            f[16] += fmaf(Syy, Yz, fmaf(-2.0f * Wy, Syz, Uz));                 // yyz
-            // xzz, yzz, zzz follow from the traces (k_coarse_eval)
+            loc_add(f, dx * h, dy * h, dz * h, m.x, m.y, m.z, m.w, outside);
         }
 #pragma unroll
         for (int k = 0; k < kLoc; ++k) acc[k] += (double)f[k];
@@ -712,6 +725,135 @@ __global__ __launch_bounds__(kLB) void k_coarse_local(const double* __restrict__
 #pragma unroll
         for (int k = 0; k < kLoc; ++k) o[k] = acc[k];
     }
+}
+
+// Two-level version of k_coarse_local (G even).  Parent cells are the
+// 2x2x2 blocks of cells; pmom holds their monopole and dipole about the
+// parent centre.  For a target whose parent is T, parents farther than D
+// (Chebyshev, parent cells) from T enter through pmom, streamed through LDS
+// over the occupied-parent list; the children of the (2D+1)^3 parents around
+// T are gathered per lane (cells outside the grid or inside the target's
+// block add nothing).  Both parts are shared out over gridDim.y source splits
+// like the one-level kernel; partials are reduced by k_loc_reduce.
+__global__ __launch_bounds__(kLB) void k_coarse_local2(
+    const double* __restrict__ mom, const int* __restrict__ occ, const int* __restrict__ nocc,
+    int G, int B, const double* __restrict__ pmom, const int* __restrict__ pocc,
+    const int* __restrict__ npocc, int D, const FFGrid* g, int M, double* part) {
+    __shared__ float4 sm[kLB];         // parent (Q, Px, Py, Pz)
+    __shared__ float4 sc[kLB];         // parent index (x, y, z) as floats
+    const int no = *nocc;
+    if ((int)blockIdx.x * kLB >= no) return;           // uniform per workgroup
+    const int nsplit = gridDim.y, split = blockIdx.y;
+    const int t = blockIdx.x * kLB + threadIdx.x;
+    const bool live = t < no;
+    const int tc = live ? occ[t] : 0;
+    const int tx = tc % G, ty = (tc / G) % G, tz = tc / (G * G);
+    const int Gp = G / 2;
+    const int Tx = tx / 2, Ty = ty / 2, Tz = tz / 2;
+    const float h = (float)g->h;
+    const int half = B / 2;
+    double acc[kLoc];
+#pragma unroll
+    for (int k = 0; k < kLoc; ++k) acc[k] = 0.0;
+    float f[kLoc];
+    // far parents
+    const int np = *npocc;
+    const int per = ((np + nsplit - 1) / nsplit + kLB - 1) / kLB * kLB;
+    const int jb = split * per, je = min(np, jb + per);
+    for (int j0 = jb; j0 < je; j0 += kLB) {
+        __syncthreads();
+        const int j = j0 + threadIdx.x;
+        if (j < je) {
+            const int p = pocc[j];
+            sm[threadIdx.x] = make_float4((float)pmom[4 * p], (float)pmom[4 * p + 1],
+                                          (float)pmom[4 * p + 2], (float)pmom[4 * p + 3]);
+            sc[threadIdx.x] = make_float4((float)(p % Gp), (float)((p / Gp) % Gp),
+                                          (float)(p / (Gp * Gp)), 0.f);
+        } else {
+            sm[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+            sc[threadIdx.x] = make_float4(-1e6f, -1e6f, -1e6f, 0.f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kLoc; ++k) f[k] = 0.f;
+        const int cnt = min(kLB, je - j0);
+        for (int k = 0; k < cnt; ++k) {
+            const float4 cs = sc[k];
+            const bool far = fmaxf(fabsf((float)Tx - cs.x),
+                                   fmaxf(fabsf((float)Ty - cs.y), fabsf((float)Tz - cs.z))) >
+                             (float)D + 0.5f;
+            const float4 m = sm[k];
+            // child centre minus parent centre: (t + 1/2 - 2 (p + 1/2)) h
+            loc_add(f, ((float)tx - 2.f * cs.x - 0.5f) * h, ((float)ty - 2.f * cs.y - 0.5f) * h,
+                    ((float)tz - 2.f * cs.z - 0.5f) * h, m.x, m.y, m.z, m.w, far);
+        }
+#pragma unroll
+        for (int k = 0; k < kLoc; ++k) acc[k] += (double)f[k];
+    }
+    // children of the near parents, this split's share of them
+    const int side = 2 * D + 1, nnear = side * side * side;
+    for (int kp = split; kp < nnear; kp += nsplit) {
+        const int px = Tx + kp % side - D, py = Ty + (kp / side) % side - D,
+                  pz = Tz + kp / (side * side) - D;
+        const bool pin = px >= 0 && py >= 0 && pz >= 0 && px < Gp && py < Gp && pz < Gp;
+#pragma unroll
+        for (int k = 0; k < kLoc; ++k) f[k] = 0.f;
+#pragma unroll 2
+        for (int ch = 0; ch < 8; ++ch) {
+            const int sx = 2 * px + (ch & 1), sy = 2 * py + ((ch >> 1) & 1), sz = 2 * pz + (ch >> 2);
+            const bool use = live && pin &&
+                             (abs(sx - tx) > half || abs(sy - ty) > half || abs(sz - tz) > half);
+            float Q = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f;
+            if (use) {
+                const size_t c = ((size_t)sz * G + sy) * G + sx;
+                Q = (float)mom[4 * c];
+                Px = (float)mom[4 * c + 1];
+                Py = (float)mom[4 * c + 2];
+                Pz = (float)mom[4 * c + 3];
+            }
+            loc_add(f, (float)(tx - sx) * h, (float)(ty - sy) * h, (float)(tz - sz) * h, Q, Px, Py,
+                    Pz, use);
+        }
+#pragma unroll
+        for (int k = 0; k < kLoc; ++k) acc[k] += (double)f[k];
+    }
+    if (live) {
+        double* o = part + ((size_t)blockIdx.y * M + tc) * kLoc;
+#pragma unroll
+        for (int k = 0; k < kLoc; ++k) o[k] = acc[k];
+    }
+}
+
+// Parent cells (2x2x2 blocks of cells): the children's moments moved to the
+// parent centre, Q_p = sum Q_c, P_p = sum (P_c + Q_c (c_c - c_p)), and the
+// particle count.
+__global__ __launch_bounds__(kB) void k_parent_moments(const double* __restrict__ mom,
+                                                       const int* __restrict__ count, int G,
+                                                       const FFGrid* g, double* pmom,
+                                                       int* pcount) {
+    const int Gp = G / 2, Mp = Gp * Gp * Gp;
+    const int p = blockIdx.x * kB + threadIdx.x;
+    if (p >= Mp) return;
+    const int px = p % Gp, py = (p / Gp) % Gp, pz = p / (Gp * Gp);
+    const double h = g->h;
+    double Q = 0.0, Px = 0.0, Py = 0.0, Pz = 0.0;
+    int n = 0;
+    for (int ch = 0; ch < 8; ++ch) {
+        const int dx = ch & 1, dy = (ch >> 1) & 1, dz = ch >> 2;
+        const size_t c = ((size_t)(2 * pz + dz) * G + (2 * py + dy)) * G + (2 * px + dx);
+        const double q = mom[4 * c];
+        Q += q;
+        // child centre - parent centre = (d - 1/2) h per axis
+        Px += mom[4 * c + 1] + q * (dx - 0.5) * h;
+        Py += mom[4 * c + 2] + q * (dy - 0.5) * h;
+        Pz += mom[4 * c + 3] + q * (dz - 0.5) * h;
+        n += count[c];
+    }
+    pmom[4 * (size_t)p] = Q;
+    pmom[4 * (size_t)p + 1] = Px;
+    pmom[4 * (size_t)p + 2] = Py;
+    pmom[4 * (size_t)p + 3] = Pz;
+    pcount[p] = n;
 }
 
 // out[cell] = sum over the source splits of the partial expansions, in split
@@ -1183,7 +1325,8 @@ bool dalloc(T** p, size_t count) {
 
 void ff_free_bufs(FarField* f) {
     void* b[] = {f->grid, f->cstart, f->cend, f->Fnear, f->mom, f->count, f->occ, f->cell2occ,
-                 f->nocc, f->Ecell, f->Ep, f->cfirst, f->tiles, f->ntiles, f->loc_part, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->grad, f->adam_m,
+                 f->nocc, f->Ecell, f->Ep, f->cfirst, f->tiles, f->ntiles, f->loc_part, f->pmom,
+                 f->pcount, f->pocc, f->pcell2occ, f->npocc, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->grad, f->adam_m,
                  f->adam_v, f->rel, f->Efar, f->snap_mom, f->s_snap, f->s_cell, f->s_off,
                  f->s_tgt, f->bX, f->bT, f->bZ1, f->bA1, f->bZ2, f->bA2, f->bY, f->bdY, f->bd2,
                  f->bd1, f->bidx, f->loss_part};
@@ -1216,7 +1359,17 @@ ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
                 f->mom, f->count);
     }
     KLAUNCH(k_compact, dim3(1), dim3(1024), s, f->count, M, f->occ, f->cell2occ, f->nocc);
-    if (f->cfg.near_mode == 1) {
+    if (f->cfg.near_mode == 1 && f->cfg.parent_reach > 0) {
+        const int Mp = (G / 2) * (G / 2) * (G / 2);
+        KLAUNCH(k_parent_moments, dim3((Mp + kB - 1) / kB), dim3(kB), s, f->mom, f->count, G,
+                f->grid, f->pmom, f->pcount);
+        KLAUNCH(k_compact, dim3(1), dim3(1024), s, f->pcount, Mp, f->pocc, f->pcell2occ, f->npocc);
+        KLAUNCH(k_coarse_local2, dim3((M + kLB - 1) / kLB, f->loc_split), dim3(kLB), s, f->mom,
+                f->occ, f->nocc, G, f->cfg.block, f->pmom, f->pocc, f->npocc,
+                f->cfg.parent_reach, f->grid, M, f->loc_part);
+        KLAUNCH(k_loc_reduce, dim3((M * kLoc + kB - 1) / kB), dim3(kB), s, f->loc_part, f->occ,
+                f->nocc, M, f->loc_split, f->Ecell);
+    } else if (f->cfg.near_mode == 1) {
         KLAUNCH(k_coarse_local, dim3((M + kLB - 1) / kLB, f->loc_split), dim3(kLB), s, f->mom,
                 f->occ, f->nocc, G, f->cfg.block, f->grid, M, f->loc_part);
         KLAUNCH(k_loc_reduce, dim3((M * kLoc + kB - 1) / kB), dim3(kB), s, f->loc_part, f->occ,
@@ -1522,7 +1675,10 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
     if (!(cfg->judge_tol > 0.0)) return fail(LD_EINVAL, "judge_tol must be positive");
     if (cfg->near_mode != 0 && cfg->near_mode != 1)
         return fail(LD_EINVAL, "near_mode must be 0 (radial) or 1 (block)");
-    if (cfg->reserved != 0) return fail(LD_EINVAL, "reserved must be 0");
+    if (cfg->parent_reach < 0 || cfg->parent_reach > 31)
+        return fail(LD_EINVAL, "parent_reach must be in [0, 31]");
+    if (cfg->near_mode == 1 && cfg->parent_reach > 0 && cfg->grid % 2)
+        return fail(LD_EINVAL, "the two-level expansion (parent_reach > 0) needs an even grid");
     double maxlj = 0.0;
     for (int a = 0; a < c->p.n_types; ++a)
         for (int b = 0; b < c->p.n_types; ++b)
@@ -1560,6 +1716,9 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
               dalloc(&f->tiles, (n + 63) / 64 + (size_t)cfg->grid * cfg->grid) &&
               dalloc(&f->ntiles, 1) &&
               dalloc(&f->loc_part, cfg->near_mode == 1 ? (size_t)f->loc_split * M * kLoc : 1) &&
+              dalloc(&f->pmom, 4 * (M / 8 + 1)) && dalloc(&f->pcount, M / 8 + 1) &&
+              dalloc(&f->pocc, M / 8 + 1) && dalloc(&f->pcell2occ, M / 8 + 1) &&
+              dalloc(&f->npocc, 1) &&
               dalloc(&f->Xc, M * f->Kp) && dalloc(&f->Ac, M * f->H) &&
               dalloc(&f->h1, n * f->H) && dalloc(&f->h2, n * f->H) && dalloc(&f->y, n * f->Op) &&
               dalloc(&f->W, f->nW) && dalloc(&f->grad, f->nW) && dalloc(&f->adam_m, f->nW) &&

@@ -67,7 +67,7 @@ TUNING_FIELDS = ("block", "j_split", "comp", "sort_every", "cull", "graph_steps"
 class ld_ff_config(C.Structure):
     _fields_ = [("near_cut", C.c_double), ("grid", C.c_int32), ("block", C.c_int32),
                 ("hidden", C.c_int32), ("judge_every", C.c_int32), ("judge_tol", C.c_double),
-                ("near_mode", C.c_int32), ("reserved", C.c_int32)]
+                ("near_mode", C.c_int32), ("parent_reach", C.c_int32)]
 
 
 class ld_ff_train_cfg(C.Structure):
@@ -82,7 +82,7 @@ class ld_ff_train_report(C.Structure):
 
 
 FF_DEFAULT = dict(near_cut=8.0, grid=32, block=5, hidden=128, judge_every=500, judge_tol=1e-3,
-                  near_mode=0)
+                  near_mode=0, parent_reach=3)
 NEAR_RADIAL, NEAR_BLOCK = 0, 1
 
 

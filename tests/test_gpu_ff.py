@@ -99,23 +99,26 @@ def test_block_near_ragged_small(ld, orc):
     _, S, _ = orc.pair_forces(x, w.type, w.charge, w.params)
     for grid in (4, 9, 32):
         s = ld.System.from_workload(w)
-        s.ff_enable(grid=grid, block=3, hidden=16, near_mode=ld.NEAR_BLOCK)
+        s.ff_enable(grid=grid, block=3, hidden=16, near_mode=ld.NEAR_BLOCK,
+                    parent_reach=0 if grid % 2 else 3)
         L, _ = s.ff_grid()
         Fn, Ef = orc.ff_split_block(x, w.type, w.charge, w.params, grid, L, 3)
         assert np.all(np.linalg.norm(s.ff_forces(0) - Fn, axis=1) <= 1e-5 * S), grid
 
 
-def test_block_coarse_part(ld, orc, sysw):
+@pytest.mark.parametrize("reach", [0, 1, 3])
+def test_block_coarse_part(ld, orc, sysw, reach):
     """Block mode: q times the second-order local expansion of the far cells'
-    monopole + dipole field at every particle."""
+    monopole + dipole field at every particle (reach 0: one level; reach > 0:
+    cells of 2x2x2 parents beyond the reach grouped by parent)."""
     s = ld.System.from_workload(sysw)
-    s.ff_enable(grid=G, block=B, hidden=64, near_mode=ld.NEAR_BLOCK)
+    s.ff_enable(grid=G, block=B, hidden=64, near_mode=ld.NEAR_BLOCK, parent_reach=reach)
     Fc_g = s.ff_forces(1)
     x = sysw.pos.astype(np.float64)
     L = grid_L(sysw.pos)
     qh = orc.qhat(sysw.charge, sysw.params)
     mom = orc.ff_moments(x, qh, G, L)
-    loc = orc.ff_local(mom, G, L, B)
+    loc = orc.ff_local(mom, G, L, B) if reach == 0 else orc.ff_local2(mom, G, L, B, reach)
     Fc = qh[:, None] * orc.ff_local_eval(x, G, L, loc)
     scale = np.sqrt(np.mean(np.sum(Fc ** 2, 1)))
     assert np.abs(Fc_g - Fc).max() <= 1e-4 * scale
