@@ -375,8 +375,8 @@ __global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cs
 // B^3 block of i's cell, LJ of every pair within its range.  The tile's
 // lanes share one (y, z) row, so the rows dy, dz in [-W, W] around it hold
 // every partner; cells x_first - W .. x_last + W of such a row are one
-// contiguous slot range.  FP32 pair terms in blocks of at most 32, FP64
-// totals; LJ terms go to FP64 directly (rare).
+// contiguous slot range.  FP32 pair terms (Coulomb and LJ apart) in blocks
+// of at most 32, FP64 totals.
 __global__ __launch_bounds__(64) void k_near_block(const float4* __restrict__ pos,
                                                    const int* __restrict__ typ,
                                                    const unsigned long long* __restrict__ keys,
@@ -415,7 +415,11 @@ __global__ __launch_bounds__(64) void k_near_block(const float4* __restrict__ po
         for (int dy = -W; dy <= W; ++dy) {
             const int y = ry + dy;
             if (y < 0 || y >= G) continue;
+            // Coulomb partners of this row: cell x within half of the lane's
+            // own (an empty window when the row is outside the block)
             const bool row_in = abs(dy) <= half && abs(dz) <= half;
+            const int xlo = row_in ? ix - half : (1 << 20);
+            const int xhi = row_in ? ix + half : -(1 << 20);
             const int base = (z * G + y) * G;
             const int j0 = cfirst[base + max(0, x_first - W)];
             const int j1 = cfirst[base + min(G - 1, x_last + W) + 1];
@@ -431,39 +435,43 @@ __global__ __launch_bounds__(64) void k_near_block(const float4* __restrict__ po
                 }
                 __syncthreads();
                 const int cnt = min(64, j1 - jt);
+                const int self = i - jt;               // LDS index of i itself, if present
                 for (int kb = 0; kb < cnt; kb += 32) {
                     const int ke = min(cnt, kb + 32);
-                    float bx = 0.f, by = 0.f, bz = 0.f;
+                    float bx = 0.f, by = 0.f, bz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
 #pragma unroll 4
                     for (int k = kb; k < ke; ++k) {
                         const float4 pj = sp[k];
+                        const int info = sx[k];
+                        const int jx = info & 0xFFFF;
                         const float ddx = pj.x - pi.x, ddy = pj.y - pi.y, ddz = pj.z - pi.z;
                         const float r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-                        const bool self = jt + k == i;
-                        const int info = sx[k];
-                        const bool inb = row_in && abs((info & 0xFFFF) - ix) <= half && !self;
                         const float ri = __builtin_amdgcn_rsqf(r2);
+                        const bool inb = jx >= xlo && jx <= xhi && k != self;
                         const float w = inb ? (pj.w * ri) * (ri * ri) : 0.f;
                         bx = fmaf(w, ddx, bx);
                         by = fmaf(w, ddy, by);
                         bz = fmaf(w, ddz, bz);
-                        if (r2 < rc2max && !self) {
+                        if (r2 < rc2max && k != self) {
                             const int pidx = ti * T + (info >> 16);
                             if (r2 < ttab[kMaxTypes * kMaxTypes + pidx]) {
-                                const float ir2 = 1.0f / r2;
+                                const float ir2 = ri * ri;
                                 const float s2 = ttab[pidx] * ir2;
                                 const float s6 = s2 * s2 * s2;
                                 const float gg = ttab[2 * kMaxTypes * kMaxTypes + pidx] * s6 *
                                                  (2.0f * s6 - 1.0f) * ir2;
-                                Lx += (double)(gg * ddx);
-                                Ly += (double)(gg * ddy);
-                                Lz += (double)(gg * ddz);
+                                lx = fmaf(gg, ddx, lx);
+                                ly = fmaf(gg, ddy, ly);
+                                lz = fmaf(gg, ddz, lz);
                             }
                         }
                     }
                     Fx += (double)bx;
                     Fy += (double)by;
                     Fz += (double)bz;
+                    Lx += (double)lx;
+                    Ly += (double)ly;
+                    Lz += (double)lz;
                 }
             }
         }
