@@ -50,6 +50,9 @@ def parse():
                     help="learned: direct steps between training snapshots")
     ap.add_argument("--epochs", type=int, default=20, help="learned: training epochs")
     ap.add_argument("--near-cut", type=float, default=8.0, help="learned: near cutoff r_c")
+    ap.add_argument("--train-from", default="droplets", choices=["droplets", "trajectory"],
+                    help="learned: snapshots from independent droplets (each stepped "
+                         "snap-every steps) or from one trajectory")
     ap.add_argument("--near-mode", default="block", choices=["block", "radial"],
                     help="learned: exact near part over the 5^3 block of grid cells, or r < r_c")
     ap.add_argument("--autotune", action="store_true",
@@ -189,15 +192,23 @@ def bench_learned(a, torch, ldrop, W):
     tr = ldrop.System.from_workload(wt)
     mode = ldrop.NEAR_BLOCK if a.near_mode == "block" else ldrop.NEAR_RADIAL
     tr.ff_enable(near_cut=a.near_cut, near_mode=mode)
-    tr.ff_collect(reset=True, max_snapshots=a.snapshots)
-    for _ in range(a.snapshots - 1):
-        tr.step(a.snap_every, wt.dt)
-        tr.ff_collect()
+    if a.train_from == "trajectory":
+        tr.ff_collect(reset=True, max_snapshots=a.snapshots)
+        for _ in range(a.snapshots - 1):
+            tr.step(a.snap_every, wt.dt)
+            tr.ff_collect()
+    else:
+        # independent droplets of the same composition (seeds 105, 106, ...),
+        # each stepped snap_every steps from its own random start
+        for k in range(a.snapshots):
+            tr.set_positions(W.config_learned(n=a.n, seed=105 + k).pos)
+            tr.step(a.snap_every, wt.dt)
+            tr.ff_collect(reset=(k == 0), max_snapshots=a.snapshots)
     collect_s = time.perf_counter() - t0
     t1 = time.perf_counter()
     rep = tr.ff_train(epochs=a.epochs, batch=8192, lr=1e-3, seed=105, val_fraction=0.1)
     train_s = time.perf_counter() - t1
-    weights, sq, scale = tr.ff_weights()
+    weights, sq, scale = tr.ff_weights()      # scale includes the held-out gain
     del tr
     we = W.config_learned(n=a.n, seed=5)
     ev = ldrop.System.from_workload(we)
@@ -231,7 +242,8 @@ def bench_learned(a, torch, ldrop, W):
                    "near_mode": a.near_mode,
                    "near_cut": a.near_cut if a.near_mode == "radial" else None,
                    "snapshots": a.snapshots,
-                   "snap_every": a.snap_every, "epochs": a.epochs},
+                   "snap_every": a.snap_every, "epochs": a.epochs,
+                   "train_from": a.train_from},
         "training": {**rep, "collect_s": collect_s, "train_s": train_s},
         "direct_pair_interactions_per_s": pairs * 1e3 / ms_direct,
     }), flush=True)

@@ -172,6 +172,14 @@ ld_status ld_sync(ld_ctx* ctx);
  * (either may be NULL).  Waits for the stream. */
 ld_status ld_get_positions(ld_ctx* ctx, float* pos, float* pos_lo);
 
+/* Replace the positions: pos [n*3] FP32 in original order (host or device),
+ * pos_lo [n*3] the low parts of the FP32 pairs or NULL for zeros.  Types,
+ * charges, parameters, the step clock and the noise stream are kept (section
+ * 2.2: a run restarts from a given configuration).  The slots are re-sorted
+ * at the next step; group boxes are rebuilt at once.  Errors: LD_EINVAL
+ * (NULL pos, non-finite coordinate), LD_EHIP. */
+ld_status ld_set_positions(ld_ctx* ctx, const float* pos, const float* pos_lo);
+
 /* Global step counter, time t and current radius R(t) (any may be NULL). */
 ld_status ld_get_state(ld_ctx* ctx, int64_t* step, double* t, double* R);
 
@@ -292,14 +300,18 @@ typedef struct {
     uint64_t seed;          /* shuffle stream (Philox, tag 3) */
     double val_fraction;    /* last fraction of the samples held out */
     int32_t reset_scale;    /* 1: set out_scale to the RMS of the targets */
-    int32_t reserved;
+    int32_t calibrate;      /* 1: after training, scale the output by the least-squares
+                               gain on the held-out samples, clipped to [0, 1] */
 } ld_ff_train_cfg;
 
 typedef struct {
     int64_t samples, iterations;
     double final_loss;      /* MSE of the scaled residual, last batch */
-    double val_rel_rms;     /* relative RMS error of the residual, held out */
-    double out_scale;
+    double val_rel_rms;     /* relative RMS error of the residual, held out (after
+                               the gain) */
+    double out_scale;       /* final output scale (gain included) */
+    double gain;            /* the fitted gain (1 without calibration) */
+    double val_rel_rms_raw; /* held-out relative RMS error before the gain */
 } ld_ff_train_report;
 
 /* Allocate the learned far field for this context (weights get small

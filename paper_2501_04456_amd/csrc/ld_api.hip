@@ -520,6 +520,36 @@ ld_status ld_sync(ld_ctx* c) {
     return take_pending_error(c);
 }
 
+ld_status ld_set_positions(ld_ctx* c, const float* pos, const float* pos_lo) {
+    g_err.clear();
+    if (!c || !pos) return fail(LD_EINVAL, "ctx and pos are required");
+    const size_t N = (size_t)c->n;
+    std::vector<float> x, xl;
+    ld_status st = read_host(x, pos, 3 * N, c->stream);
+    if (st != LD_OK) return st;
+    if (pos_lo && (st = read_host(xl, pos_lo, 3 * N, c->stream)) != LD_OK) return st;
+    for (size_t k = 0; k < 3 * N; ++k)
+        if (!std::isfinite(x[k]) || (pos_lo && !std::isfinite(xl[k])))
+            return fail(LD_EINVAL, "coordinate %zu of particle %zu is not finite", k % 3, k / 3);
+    std::vector<float4> h(N), l(N);
+    std::vector<int> ids(N);
+    HIP_TRY(hipMemcpyAsync(h.data(), c->pos, sizeof(float4) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(ids.data(), c->oid, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (size_t s = 0; s < N; ++s) {
+        const size_t o = (size_t)ids[s];
+        h[s] = make_float4(x[3 * o], x[3 * o + 1], x[3 * o + 2], h[s].w);   // q_hat stays
+        l[s] = pos_lo ? make_float4(xl[3 * o], xl[3 * o + 1], xl[3 * o + 2], 0.f)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    HIP_TRY(hipMemcpyAsync(c->pos, h.data(), sizeof(float4) * N, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->lo, l.data(), sizeof(float4) * N, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(ld::launch_boxes(c->pos, (int)N, c->box, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->tune.sort_every > 0) c->steps_since_sort = c->tune.sort_every;
+    return LD_OK;
+}
+
 ld_status ld_get_positions(ld_ctx* c, float* pos, float* pos_lo) {
     g_err.clear();
     if (!c) return fail(LD_EINVAL, "ctx is NULL");

@@ -1782,7 +1782,8 @@ ld_status ld_ff_set_weights(ld_ctx* c, const float* w, int64_t count, double sq,
     if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
     if (!w || count != (int64_t)c->ff->nW)
         return fail(LD_EINVAL, "weights need exactly %lld floats", (long long)c->ff->nW);
-    if (!(sq > 0.0) || !(out_scale > 0.0)) return fail(LD_EINVAL, "scales must be positive");
+    if (!(sq > 0.0) || !(out_scale >= 0.0) || !std::isfinite(out_scale))
+        return fail(LD_EINVAL, "sq must be positive and out_scale >= 0 (0: network off)");
     HIP_TRY(copy_in(c->ff->W, w, sizeof(float) * count, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->ff->sq = (float)sq;
@@ -1974,7 +1975,8 @@ ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* 
     double ss = 0.0;
     for (float v : tg) ss += (double)v * v;
     const double rms = std::sqrt(ss / (double)tg.size());
-    if (tc->reset_scale || f->out_scale == 1.f) f->out_scale = (float)(rms > 0.0 ? rms : 1.0);
+    if (tc->reset_scale || f->out_scale == 1.f || !(f->out_scale > 0.f))
+        f->out_scale = (float)(rms > 0.0 ? rms : 1.0);
     const float inv_scale = 1.0f / f->out_scale;
     // split: the last val_fraction of the samples is held out
     const int64_t nval = (int64_t)(tc->val_fraction * (double)f->samples);
@@ -2019,10 +2021,11 @@ ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* 
         }
         if (nb) last = ep_loss;
     }
-    // validation: relative RMS error of the residual on the held-out samples
-    double val_rel = NAN;
+    // validation: relative RMS error of the residual on the held-out samples,
+    // and the least-squares gain of the output there (sums of y t, y y, t t)
+    double val_rel = NAN, val_raw = NAN, gain = 1.0;
     if (st == LD_OK && nval >= 16) {
-        double num = 0.0, den = 0.0;
+        double num = 0.0, den = 0.0, sty = 0.0, syy = 0.0;
         std::vector<int> vidx;
         for (int64_t k = ntr; k < f->samples; ++k) vidx.push_back((int)k);
         for (size_t v0 = 0; v0 + 16 <= vidx.size() && st == LD_OK; v0 += B_) {
@@ -2050,12 +2053,23 @@ ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* 
                 hipStreamSynchronize(s) != hipSuccess) { st = fail(LD_EHIP, "readback"); break; }
             for (int r = 0; r < bsz; ++r)
                 for (int k = 0; k < 3; ++k) {
-                    const double d = (double)y[(size_t)r * Op + k] - t[3 * r + k];
+                    const double yv = (double)y[(size_t)r * Op + k], tv = t[3 * r + k];
+                    const double d = yv - tv;
                     num += d * d;
-                    den += (double)t[3 * r + k] * t[3 * r + k];
+                    den += tv * tv;
+                    sty += yv * tv;
+                    syy += yv * yv;
                 }
         }
-        if (den > 0.0) val_rel = std::sqrt(num / den);
+        if (den > 0.0) {
+            val_raw = std::sqrt(num / den);
+            val_rel = val_raw;
+            if (tc->calibrate) {
+                gain = syy > 0.0 ? std::min(1.0, std::max(0.0, sty / syy)) : 0.0;
+                val_rel = std::sqrt(std::max(0.0, den - 2.0 * gain * sty + gain * gain * syy) / den);
+                f->out_scale = (float)((double)f->out_scale * gain);
+            }
+        }
     }
     (void)hipFree(dperm);
     if (st != LD_OK) return st;
@@ -2065,6 +2079,8 @@ ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* 
         rep->final_loss = last;
         rep->val_rel_rms = val_rel;
         rep->out_scale = f->out_scale;
+        rep->gain = gain;
+        rep->val_rel_rms_raw = val_raw;
     }
     return LD_OK;
 }

@@ -73,12 +73,13 @@ class ld_ff_config(C.Structure):
 class ld_ff_train_cfg(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
                 ("seed", C.c_uint64), ("val_fraction", C.c_double), ("reset_scale", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("calibrate", C.c_int32)]
 
 
 class ld_ff_train_report(C.Structure):
     _fields_ = [("samples", C.c_int64), ("iterations", C.c_int64), ("final_loss", C.c_double),
-                ("val_rel_rms", C.c_double), ("out_scale", C.c_double)]
+                ("val_rel_rms", C.c_double), ("out_scale", C.c_double), ("gain", C.c_double),
+                ("val_rel_rms_raw", C.c_double)]
 
 
 FF_DEFAULT = dict(near_cut=8.0, grid=32, block=5, hidden=128, judge_every=500, judge_tol=1e-3,
@@ -90,7 +91,7 @@ SYMBOLS = [
     "ld_init", "ld_destroy", "ld_last_error", "ld_forces", "ld_step", "ld_sync",
     "ld_get_positions", "ld_get_state", "ld_set_params", "ld_diagnostics", "ld_rdf",
     "ld_fractal", "ld_get_tuning", "ld_set_tuning", "ld_kernel_timing", "ld_kernel_time",
-    "ld_autotune", "ld_checkpoint_save", "ld_checkpoint_load",
+    "ld_autotune", "ld_checkpoint_save", "ld_checkpoint_load", "ld_set_positions",
     "ld_ff_enable", "ld_ff_mode", "ld_ff_weights_size", "ld_ff_set_weights", "ld_ff_get_weights",
     "ld_ff_grid", "ld_ff_forces", "ld_ff_mlp", "ld_ff_grads", "ld_ff_collect", "ld_ff_train",
     "ld_ff_judge", "ld_ff_stats",
@@ -119,6 +120,7 @@ def lib():
         L.ld_step.argtypes = [vp, C.c_double, C.c_int64]
         L.ld_sync.argtypes = [vp]
         L.ld_get_positions.argtypes = [vp, fp, fp]
+        L.ld_set_positions.argtypes = [vp, vp, vp]
         L.ld_get_state.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]
         L.ld_set_params.argtypes = [vp, C.POINTER(ld_params), C.POINTER(ld_radius)]
@@ -313,6 +315,14 @@ class System:
         hi, lo = self.positions()
         return hi.astype(np.float64) + lo.astype(np.float64)
 
+    def set_positions(self, x, x_lo=None):
+        """Replace the positions ([n,3] in original order; x_lo the low FP32
+        parts or None)."""
+        hi = np.ascontiguousarray(x, np.float32).reshape(self.n, 3)
+        lo = None if x_lo is None else np.ascontiguousarray(x_lo, np.float32).reshape(self.n, 3)
+        _check(lib().ld_set_positions(self.h, hi.ctypes.data_as(C.c_void_p),
+                                      None if lo is None else lo.ctypes.data_as(C.c_void_p)))
+
     def state(self):
         s, t, R = C.c_int64(), C.c_double(), C.c_double()
         _check(lib().ld_get_state(self.h, C.byref(s), C.byref(t), C.byref(R)))
@@ -426,9 +436,10 @@ class System:
         _check(lib().ld_ff_collect(self.h, 1 if reset else 0, int(max_snapshots)))
 
     def ff_train(self, epochs=20, batch=8192, lr=1e-3, seed=105, val_fraction=0.1,
-                 reset_scale=True) -> dict:
+                 reset_scale=True, calibrate=True) -> dict:
         c = ld_ff_train_cfg(epochs=epochs, batch=batch, lr=lr, seed=seed,
-                            val_fraction=val_fraction, reset_scale=1 if reset_scale else 0)
+                            val_fraction=val_fraction, reset_scale=1 if reset_scale else 0,
+                            calibrate=1 if calibrate else 0)
         r = ld_ff_train_report()
         _check(lib().ld_ff_train(self.h, C.byref(c), C.byref(r)))
         return {k: getattr(r, k) for k, _ in r._fields_}

@@ -256,6 +256,10 @@ def test_training_gain_and_judge(ld, sysw):
     rep = s.ff_train(epochs=40, batch=512, lr=2e-3, seed=105, val_fraction=0.25)
     assert rep["samples"] == 16000 and rep["iterations"] > 0
     assert rep["val_rel_rms"] < 1.0          # better than predicting zero residual
+    # the held-out gain is a clipped least-squares fit: it never makes the
+    # held-out error worse than the raw network's or than no network at all
+    assert 0.0 <= rep["gain"] <= 1.0
+    assert rep["val_rel_rms"] <= min(rep["val_rel_rms_raw"], 1.0) + 1e-12
     err1 = s.ff_judge()
     assert err1 < err0, (err0, err1)
     # judge / fallback: an impossible tolerance forces direct windows

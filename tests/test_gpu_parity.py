@@ -352,3 +352,26 @@ def test_blowup_reported(ld):
     with pytest.raises(ld.NonFinite) as e:
         s.sync()
     assert "step 0" in str(e.value)
+
+
+def test_set_positions_restart(ld, orc):
+    """Replacing the positions of a running context (after steps that
+    re-sorted its slots) gives the forces of a fresh context at those
+    positions, and the positions (and low parts) read back exactly."""
+    w = W.config_small()
+    s = ld.System.from_workload(w)
+    s.step(60, w.dt)                        # slots re-sorted at step 50
+    w2 = W.config_small(seed=7)
+    s.set_positions(w2.pos)
+    hi, lo = s.positions()
+    assert np.array_equal(hi, w2.pos.astype(np.float32)) and not lo.any()
+    Fo, So, _ = orc.pair_forces(w2.pos, w2.type, w2.charge, w2.params)
+    Fg = s.forces()["pair"].cpu().numpy()
+    assert (np.linalg.norm(Fg - Fo, axis=1) / So).max() <= 1e-5
+    x_lo = np.random.default_rng(1).uniform(-1e-7, 1e-7, w2.pos.shape).astype(np.float32)
+    s.set_positions(w2.pos, x_lo)
+    assert np.array_equal(s.positions()[1], x_lo)
+    with pytest.raises(ld.LdError):
+        bad = w2.pos.copy()
+        bad[3, 1] = np.nan
+        s.set_positions(bad)
