@@ -560,14 +560,19 @@ __global__ __launch_bounds__(1024) void k_compact(const int* __restrict__ count,
 }
 
 // Field at every occupied cell centre from the monopole + dipole of every
-// occupied cell outside its B^3 block.  FP32 terms, FP64 totals.
+// occupied cell outside its B^3 block.  FP32 terms, FP64 totals; the sources
+// are split over gridDim.y workgroups (partials reduced by k_coarse_reduce).
 __global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
                                                const int* __restrict__ occ,
                                                const int* __restrict__ nocc, int G, int B,
-                                               const FFGrid* g, double* E) {
+                                               const FFGrid* g, int M, double* part) {
     __shared__ float4 sm[kB];          // (Q, Px, Py, Pz)
     __shared__ float4 sc[kB];          // cell index (x, y, z) as floats
     const int no = *nocc;
+    if ((int)blockIdx.x * kB >= no) return;            // uniform per workgroup
+    const int nsplit = gridDim.y;
+    const int per = ((no + nsplit - 1) / nsplit + kB - 1) / kB * kB;
+    const int jb = blockIdx.y * per, je = min(no, jb + per);
     const int t = blockIdx.x * kB + threadIdx.x;
     const bool live = t < no;
     const int tc = live ? occ[t] : 0;
@@ -575,10 +580,10 @@ __global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
     const float h = (float)g->h;
     const float half = (float)(B / 2) + 0.5f;
     double Ex = 0.0, Ey = 0.0, Ez = 0.0;
-    for (int j0 = 0; j0 < no; j0 += kB) {
+    for (int j0 = jb; j0 < je; j0 += kB) {
         __syncthreads();
         const int j = j0 + threadIdx.x;
-        if (j < no) {
+        if (j < je) {
             const int c = occ[j];
             sm[threadIdx.x] = make_float4((float)mom[4 * c], (float)mom[4 * c + 1],
                                           (float)mom[4 * c + 2], (float)mom[4 * c + 3]);
@@ -610,9 +615,10 @@ __global__ __launch_bounds__(kB) void k_coarse(const double* __restrict__ mom,
         Ex += (double)ex; Ey += (double)ey; Ez += (double)ez;
     }
     if (live) {
-        E[3 * tc] = Ex;
-        E[3 * tc + 1] = Ey;
-        E[3 * tc + 2] = Ez;
+        double* o = part + ((size_t)blockIdx.y * M + tc) * 3;
+        o[0] = Ex;
+        o[1] = Ey;
+        o[2] = Ez;
     }
 }
 
@@ -921,6 +927,21 @@ __global__ __launch_bounds__(kB) void k_coarse_eval(const float4* __restrict__ p
     Ep[s] = E[0];
     Ep[(size_t)n + s] = E[1];
     Ep[2 * (size_t)n + s] = E[2];
+}
+
+// E[cell] = sum over the source splits of k_coarse's partial fields, in split
+// order, for every occupied cell.
+__global__ __launch_bounds__(kB) void k_coarse_reduce(const double* __restrict__ part,
+                                                      const int* __restrict__ occ,
+                                                      const int* __restrict__ nocc, int M,
+                                                      int nsplit, double* E) {
+    const int e = blockIdx.x * kB + threadIdx.x;
+    if (e >= *nocc * 3) return;
+    const size_t c = (size_t)occ[e / 3];
+    const int k = e % 3;
+    double v = 0.0;
+    for (int p = 0; p < nsplit; ++p) v += part[((size_t)p * M + c) * 3 + k];
+    E[c * 3 + k] = v;
 }
 
 // Moment rows of the B^3 block around each occupied cell (first 4 B^3
@@ -1383,8 +1404,10 @@ ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
         KLAUNCH(k_loc_reduce, dim3((M * kLoc + kB - 1) / kB), dim3(kB), s, f->loc_part, f->occ,
                 f->nocc, M, f->loc_split, f->Ecell);
     } else {
-        KLAUNCH(k_coarse, dim3((M + kB - 1) / kB), dim3(kB), s, f->mom, f->occ, f->nocc, G,
-                f->cfg.block, f->grid, f->Ecell);
+        KLAUNCH(k_coarse, dim3((M + kB - 1) / kB, f->loc_split), dim3(kB), s, f->mom, f->occ,
+                f->nocc, G, f->cfg.block, f->grid, M, f->loc_part);
+        KLAUNCH(k_coarse_reduce, dim3((M * 3 + kB - 1) / kB), dim3(kB), s, f->loc_part, f->occ,
+                f->nocc, M, f->loc_split, f->Ecell);
     }
     KLAUNCH(k_coarse_eval, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid,
             f->Ecell, f->cfg.near_mode, f->Ep);
@@ -1705,7 +1728,7 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
     {
         const size_t Mc = (size_t)cfg->grid * cfg->grid * cfg->grid;
         const size_t cap = ((size_t)128 << 20) / (sizeof(double) * kLoc * Mc);
-        f->loc_split = cfg->near_mode == 1 ? (int)std::max<size_t>(1, std::min<size_t>(16, cap)) : 1;
+        f->loc_split = (int)std::max<size_t>(1, std::min<size_t>(16, cap));
     }
     const size_t n = (size_t)c->n;
     const size_t M = (size_t)cfg->grid * cfg->grid * cfg->grid;
@@ -1723,7 +1746,7 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
               dalloc(&f->Ecell, kLoc * M) && dalloc(&f->Ep, 3 * n) && dalloc(&f->cfirst, M + 1) &&
               dalloc(&f->tiles, (n + 63) / 64 + (size_t)cfg->grid * cfg->grid) &&
               dalloc(&f->ntiles, 1) &&
-              dalloc(&f->loc_part, cfg->near_mode == 1 ? (size_t)f->loc_split * M * kLoc : 1) &&
+              dalloc(&f->loc_part, (size_t)f->loc_split * M * kLoc) &&
               dalloc(&f->pmom, 4 * (M / 8 + 1)) && dalloc(&f->pcount, M / 8 + 1) &&
               dalloc(&f->pocc, M / 8 + 1) && dalloc(&f->pcell2occ, M / 8 + 1) &&
               dalloc(&f->npocc, 1) &&
