@@ -521,11 +521,16 @@ class Ensemble:
         _check(lib().ld_ens_forces(self.h, _ptr(F)))
         return F
 
-    def positions64(self):
+    def positions(self):
+        """(hi, lo) FP32 numpy arrays [total,3] in original order."""
         hi = np.zeros((self.total, 3), np.float32)
         lo = np.zeros((self.total, 3), np.float32)
         _check(lib().ld_ens_get_positions(self.h, hi.ctypes.data_as(C.c_void_p),
                                           lo.ctypes.data_as(C.c_void_p)))
+        return hi, lo
+
+    def positions64(self):
+        hi, lo = self.positions()
         return hi.astype(np.float64) + lo.astype(np.float64)
 
     def state(self):

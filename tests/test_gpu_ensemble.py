@@ -104,6 +104,41 @@ def test_ensemble_uneven_sizes_and_single_droplet(ld, orc):
     assert np.abs(one.positions64() - s.positions64()).max() <= 1e-6
 
 
+def test_ensemble_with_uncharged_particles(ld, orc):
+    """Droplets of the large workload's three-type composition (charges
+    +1 / -1 / 0): the per-droplet sort puts uncharged particles after the
+    charged ones, so whole tiles are uncharged and far tile pairs with an
+    uncharged side are skipped; forces and a short trajectory still match
+    the oracle droplet by droplet."""
+    drops = [W.config_large(n=n, seed=60 + k) for k, n in enumerate((900, 2600, 130, 1500))]
+    ens = ld.Ensemble(drops)
+    F = ens.forces().cpu().numpy()
+    off = ens.offsets
+    # uncharged particles without an LJ partner have S = F = 0: compare
+    # |dF| <= 1e-5 S rather than a ratio
+    for d, w in enumerate(drops):
+        Fo, So, _ = orc.pair_forces(w.pos, w.type, w.charge, w.params)
+        dF = np.linalg.norm(F[off[d]:off[d + 1]] - Fo, axis=1)
+        assert np.all(dF <= 1e-5 * So), d
+    ens.step(12, drops[0].dt)              # re-sorts at the first step
+    ens.sync()
+    xg = ens.positions64()
+    for d, w in enumerate(drops):
+        st = orc.State(w)
+        assert st.run(12, w.dt) == -1
+        assert np.abs(xg[off[d]:off[d + 1]] - st.x).max() <= 1e-4, d
+    # forces after the re-sort, in the original order, at the positions the
+    # pair math uses: the FP32 high parts (near an LJ contact half an FP32
+    # ulp of position moves the force by more than 1e-5 S)
+    F2 = ens.forces().cpu().numpy()
+    hi, _ = ens.positions()
+    for d, w in enumerate(drops):
+        Fo, So, _ = orc.pair_forces(hi[off[d]:off[d + 1]].astype(np.float64), w.type, w.charge,
+                                    w.params)
+        dF = np.linalg.norm(F2[off[d]:off[d + 1]] - Fo, axis=1)
+        assert np.all(dF <= 1e-5 * So), d
+
+
 def test_single_droplet_graph_matches_eager(ld):
     w = W.config_small()
     a = ld.System.from_workload(w)
