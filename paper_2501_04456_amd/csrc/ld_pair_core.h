@@ -47,7 +47,7 @@ __device__ __forceinline__ void group_far(const float4* __restrict__ sp, const f
 #pragma unroll
     for (int kb = 0; kb < kGroup; kb += KB) {
         float bx = 0.f, by = 0.f, bz = 0.f;
-#pragma unroll 16
+#pragma unroll 32
         for (int k = 0; k < KB; ++k) {
             const float4 pj = sp[kb + k];
             const float dx = pj.x - pi.x;
