@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
             if (near)
                 pair::group_near<COMP, false>(sp[w], stp[w], ttab[w], T, rc2max, jt, i, ti, pi, a);
             else
-                pair::group_far<COMP>(sp[w], pi, a);
+                pair::group_far<COMP, 16>(sp[w], pi, a);
         }
         if constexpr (COMP == 1) {
             a.Fx = (double)a.sx - (double)a.cx;

@@ -41,13 +41,15 @@ __device__ __forceinline__ void flush(Acc& a, float bx, float by, float bz) {
 }
 
 // 64 j particles with no LJ partner in range and no self pair: Coulomb only.
-template <int COMP>
+// UNROLL: pairs in flight per lane; full unrolling (32) suits the
+// single-droplet kernel's register budget, the ensemble kernel takes fewer.
+template <int COMP, int UNROLL = 32>
 __device__ __forceinline__ void group_far(const float4* __restrict__ sp, const float4 pi,
                                           Acc& a) {
 #pragma unroll
     for (int kb = 0; kb < kGroup; kb += KB) {
         float bx = 0.f, by = 0.f, bz = 0.f;
-#pragma unroll 32
+#pragma unroll UNROLL
         for (int k = 0; k < KB; ++k) {
             const float4 pj = sp[kb + k];
             const float dx = pj.x - pi.x;
