@@ -149,15 +149,16 @@ void default_tuning(ld_ctx* c) {
     ld_tuning& t = c->tune;
     std::memset(&t, 0, sizeof t);
     const int64_t n = c->n;
-    // Enough workgroups to fill 256 CUs many times over (a short tail), but
-    // at least 256 j per split so each workgroup streams whole LDS tiles.
+    // Enough workgroups to fill 256 CUs (7 resident per CU) many times over
+    // (a short tail), but at least 256 j per split so each workgroup streams
+    // whole LDS tiles.
     t.block = n >= 16384 ? 256 : 64;
     const int64_t tiles = (n + t.block - 1) / t.block;
-    int64_t split = (16384 + tiles - 1) / tiles;
+    int64_t split = (32768 + tiles - 1) / tiles;
     int64_t cap = n / 256;
     if (cap < 1) cap = 1;
     if (split > cap) split = cap;
-    if (split > 16) split = 16;
+    if (split > 32) split = 32;
     if (split < 1) split = 1;
     t.j_split = (int)split;
     t.comp = 0;
