@@ -51,6 +51,7 @@ struct FFGrid {
     double hn;      // near cell side: 2L / Gn (>= r_c), or h in block mode
     int Gn;         // near cells per axis (G in block mode)
     int W;          // block mode: rows searched around a tile (>= B/2, covers LJ)
+    int Wlj;        // block mode: rows within the LJ range, ceil(rlj / h)
 };
 
 constexpr int kLoc = 19;               // E (3), J (6), H (10) per cell
@@ -195,9 +196,10 @@ __global__ void k_grid(const float* part, int nparts, double rc, int G, int bloc
     g->L = L;
     g->h = h;
     if (block_mode) {
-        int W = (int)ceil(rlj / h);
-        W = W < B / 2 ? B / 2 : W;
+        const int wl = (int)ceil(rlj / h);
+        const int W = wl < B / 2 ? B / 2 : wl;
         g->W = W > G ? G : W;
+        g->Wlj = wl;
         g->hn = h;
         g->Gn = G;
     } else {
@@ -206,6 +208,7 @@ __global__ void k_grid(const float* part, int nparts, double rc, int G, int bloc
         g->hn = 2.0 * L / Gn;
         g->Gn = Gn;
         g->W = 0;
+        g->Wlj = 0;
     }
 }
 
@@ -375,8 +378,83 @@ __global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cs
 // B^3 block of i's cell, LJ of every pair within its range.  The tile's
 // lanes share one (y, z) row, so the rows dy, dz in [-W, W] around it hold
 // every partner; cells x_first - W .. x_last + W of such a row are one
-// contiguous slot range.  FP32 pair terms (Coulomb and LJ apart) in blocks
-// of at most 32, FP64 totals.
+// contiguous slot range.  Two ways to walk it:
+//
+// Lane windows (the LJ range fits in the block, W = B/2): each row's range
+// is staged in LDS and every lane walks only its own window, the slots of
+// cells ix - B/2 .. ix + B/2 of that row (one contiguous piece), so no pair
+// is evaluated only to be masked; i itself is skipped by cutting its own
+// row's window in two, and LJ terms are tried only in the rows within
+// ceil(rlj / h) of the tile's.
+//
+// Row windows (LJ range beyond the block): every lane walks the tile's
+// whole range of each row with per-pair tests of the block and the self
+// pair.
+//
+// FP32 pair terms (Coulomb and LJ apart) in blocks of at most 32, FP64 totals.
+constexpr int kNbChunk = 192;          // staged slots per piece of a row's range
+
+struct NbAcc {
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, Lx = 0.0, Ly = 0.0, Lz = 0.0;
+};
+
+template <bool LJ>
+__device__ __forceinline__ void nb_pair(const float4* sp, const int* st, int k, const float4 pi,
+                                        int trow, const float* ttab, float rc2max, float& bx,
+                                        float& by, float& bz, float& lx, float& ly, float& lz) {
+    const float4 pj = sp[k];
+    const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float w = (pj.w * ri) * (ri * ri);
+    bx = fmaf(w, dx, bx);
+    by = fmaf(w, dy, by);
+    bz = fmaf(w, dz, bz);
+    if constexpr (LJ) {
+        if (r2 < rc2max) {
+            const int pidx = trow + st[k];
+            if (r2 < ttab[kMaxTypes * kMaxTypes + pidx]) {
+                const float ir2 = ri * ri;
+                const float s2 = ttab[pidx] * ir2;
+                const float s6 = s2 * s2 * s2;
+                const float gg =
+                    ttab[2 * kMaxTypes * kMaxTypes + pidx] * s6 * (2.0f * s6 - 1.0f) * ir2;
+                lx = fmaf(gg, dx, lx);
+                ly = fmaf(gg, dy, ly);
+                lz = fmaf(gg, dz, lz);
+            }
+        }
+    }
+}
+
+// This lane's terms of the staged slots [lo, hi).
+template <bool LJ>
+__device__ __forceinline__ void nb_range(const float4* sp, const int* st, int lo, int hi,
+                                         const float4 pi, int trow, const float* ttab,
+                                         float rc2max, NbAcc& a) {
+    int k = lo;
+    while (k < hi) {
+        const int ke = min(hi, k + 32);
+        float bx = 0.f, by = 0.f, bz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
+        constexpr int U = LJ ? 4 : 8;          // pairs in flight per lane
+        for (; k + U <= ke; k += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                nb_pair<LJ>(sp, st, k + u, pi, trow, ttab, rc2max, bx, by, bz, lx, ly, lz);
+        }
+        for (; k < ke; ++k)
+            nb_pair<LJ>(sp, st, k, pi, trow, ttab, rc2max, bx, by, bz, lx, ly, lz);
+        a.Fx += (double)bx;
+        a.Fy += (double)by;
+        a.Fz += (double)bz;
+        if constexpr (LJ) {
+            a.Lx += (double)lx;
+            a.Ly += (double)ly;
+            a.Lz += (double)lz;
+        }
+    }
+}
+
 __global__ __launch_bounds__(64) void k_near_block(const float4* __restrict__ pos,
                                                    const int* __restrict__ typ,
                                                    const unsigned long long* __restrict__ keys,
@@ -385,8 +463,8 @@ __global__ __launch_bounds__(64) void k_near_block(const float4* __restrict__ po
                                                    const int4* __restrict__ tiles,
                                                    const int* __restrict__ ntiles, int n,
                                                    PairTable tab, double* F) {
-    __shared__ float4 sp[64];
-    __shared__ int sx[64];
+    __shared__ float4 sp[kNbChunk];
+    __shared__ int st[kNbChunk];
     __shared__ float ttab[3 * kMaxTypes * kMaxTypes];
     const int lane = threadIdx.x;
     if ((int)blockIdx.x >= *ntiles) return;            // uniform per workgroup
@@ -408,79 +486,125 @@ __global__ __launch_bounds__(64) void k_near_block(const float4* __restrict__ po
     const int W = g->W;
     const int T = tab.T;
     const float rc2max = tab.rc2max;
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0, Lx = 0.0, Ly = 0.0, Lz = 0.0;
-    for (int dz = -W; dz <= W; ++dz) {
-        const int z = rz + dz;
-        if (z < 0 || z >= G) continue;
-        for (int dy = -W; dy <= W; ++dy) {
-            const int y = ry + dy;
-            if (y < 0 || y >= G) continue;
-            // Coulomb partners of this row: cell x within half of the lane's
-            // own (an empty window when the row is outside the block)
-            const bool row_in = abs(dy) <= half && abs(dz) <= half;
-            const int xlo = row_in ? ix - half : (1 << 20);
-            const int xhi = row_in ? ix + half : -(1 << 20);
-            const int base = (z * G + y) * G;
-            const int j0 = cfirst[base + max(0, x_first - W)];
-            const int j1 = cfirst[base + min(G - 1, x_last + W) + 1];
-            for (int jt = j0; jt < j1; jt += 64) {
-                __syncthreads();
-                const int j = jt + lane;
-                if (j < j1) {
-                    sp[lane] = pos[j];
-                    sx[lane] = (int)((unsigned)(keys[j] >> 32) % (unsigned)G) | (typ[j] << 16);
-                } else {
-                    sp[lane] = make_float4(kFarAway, kFarAway, kFarAway, 0.f);
-                    sx[lane] = 0xFFFF;
+    NbAcc a;
+    if (W == half) {
+        const int wlj = g->Wlj;
+        const int trow = ti * T;
+        for (int dz = -half; dz <= half; ++dz) {
+            const int z = rz + dz;
+            if (z < 0 || z >= G) continue;
+            for (int dy = -half; dy <= half; ++dy) {
+                const int y = ry + dy;
+                if (y < 0 || y >= G) continue;
+                const int base = (z * G + y) * G;
+                const int J0 = cfirst[base + max(0, x_first - half)];
+                const int J1 = cfirst[base + min(G - 1, x_last + half) + 1];
+                int ja = J0, jb = J0;
+                if (live) {
+                    ja = cfirst[base + max(0, ix - half)];
+                    jb = cfirst[base + min(G - 1, ix + half) + 1];
                 }
-                __syncthreads();
-                const int cnt = min(64, j1 - jt);
-                const int self = i - jt;               // LDS index of i itself, if present
-                for (int kb = 0; kb < cnt; kb += 32) {
-                    const int ke = min(cnt, kb + 32);
-                    float bx = 0.f, by = 0.f, bz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
+                const bool lj = abs(dy) <= wlj && abs(dz) <= wlj;
+                const bool own = dy == 0 && dz == 0;
+                for (int c0 = J0; c0 < J1; c0 += kNbChunk) {
+                    const int S = min(kNbChunk, J1 - c0);
+                    __syncthreads();
+                    for (int t = lane; t < S; t += 64) {
+                        sp[t] = pos[c0 + t];
+                        st[t] = typ[c0 + t];
+                    }
+                    __syncthreads();
+                    const int lo = min(max(ja - c0, 0), S), hi = min(max(jb - c0, 0), S);
+                    int m1 = hi, m2 = hi;                // [lo, m1) and [m2, hi): i skipped
+                    const int si = i - c0;
+                    if (own && si >= lo && si < hi) {
+                        m1 = si;
+                        m2 = si + 1;
+                    }
+                    if (lj) {
+                        nb_range<true>(sp, st, lo, m1, pi, trow, ttab, rc2max, a);
+                        nb_range<true>(sp, st, m2, hi, pi, trow, ttab, rc2max, a);
+                    } else {
+                        nb_range<false>(sp, st, lo, m1, pi, trow, ttab, rc2max, a);
+                        nb_range<false>(sp, st, m2, hi, pi, trow, ttab, rc2max, a);
+                    }
+                }
+            }
+        }
+    } else {
+        for (int dz = -W; dz <= W; ++dz) {
+            const int z = rz + dz;
+            if (z < 0 || z >= G) continue;
+            for (int dy = -W; dy <= W; ++dy) {
+                const int y = ry + dy;
+                if (y < 0 || y >= G) continue;
+                // Coulomb partners of this row: cell x within half of the
+                // lane's own (an empty window when the row is outside the block)
+                const bool row_in = abs(dy) <= half && abs(dz) <= half;
+                const int xlo = row_in ? ix - half : (1 << 20);
+                const int xhi = row_in ? ix + half : -(1 << 20);
+                const int base = (z * G + y) * G;
+                const int j0 = cfirst[base + max(0, x_first - W)];
+                const int j1 = cfirst[base + min(G - 1, x_last + W) + 1];
+                for (int jt = j0; jt < j1; jt += 64) {
+                    __syncthreads();
+                    const int j = jt + lane;
+                    if (j < j1) {
+                        sp[lane] = pos[j];
+                        st[lane] = (int)((unsigned)(keys[j] >> 32) % (unsigned)G) | (typ[j] << 16);
+                    } else {
+                        sp[lane] = make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+                        st[lane] = 0xFFFF;
+                    }
+                    __syncthreads();
+                    const int cnt = min(64, j1 - jt);
+                    const int self = i - jt;           // LDS index of i itself, if present
+                    for (int kb = 0; kb < cnt; kb += 32) {
+                        const int ke = min(cnt, kb + 32);
+                        float bx = 0.f, by = 0.f, bz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
 #pragma unroll 4
-                    for (int k = kb; k < ke; ++k) {
-                        const float4 pj = sp[k];
-                        const int info = sx[k];
-                        const int jx = info & 0xFFFF;
-                        const float ddx = pj.x - pi.x, ddy = pj.y - pi.y, ddz = pj.z - pi.z;
-                        const float r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-                        const float ri = __builtin_amdgcn_rsqf(r2);
-                        const bool inb = jx >= xlo && jx <= xhi && k != self;
-                        const float w = inb ? (pj.w * ri) * (ri * ri) : 0.f;
-                        bx = fmaf(w, ddx, bx);
-                        by = fmaf(w, ddy, by);
-                        bz = fmaf(w, ddz, bz);
-                        if (r2 < rc2max && k != self) {
-                            const int pidx = ti * T + (info >> 16);
-                            if (r2 < ttab[kMaxTypes * kMaxTypes + pidx]) {
-                                const float ir2 = ri * ri;
-                                const float s2 = ttab[pidx] * ir2;
-                                const float s6 = s2 * s2 * s2;
-                                const float gg = ttab[2 * kMaxTypes * kMaxTypes + pidx] * s6 *
-                                                 (2.0f * s6 - 1.0f) * ir2;
-                                lx = fmaf(gg, ddx, lx);
-                                ly = fmaf(gg, ddy, ly);
-                                lz = fmaf(gg, ddz, lz);
+                        for (int k = kb; k < ke; ++k) {
+                            const float4 pj = sp[k];
+                            const int info = st[k];
+                            const int jx = info & 0xFFFF;
+                            const float ddx = pj.x - pi.x, ddy = pj.y - pi.y, ddz = pj.z - pi.z;
+                            const float r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+                            const float ri = __builtin_amdgcn_rsqf(r2);
+                            const bool inb = jx >= xlo && jx <= xhi && k != self;
+                            const float w = inb ? (pj.w * ri) * (ri * ri) : 0.f;
+                            bx = fmaf(w, ddx, bx);
+                            by = fmaf(w, ddy, by);
+                            bz = fmaf(w, ddz, bz);
+                            if (r2 < rc2max && k != self) {
+                                const int pidx = ti * T + (info >> 16);
+                                if (r2 < ttab[kMaxTypes * kMaxTypes + pidx]) {
+                                    const float ir2 = ri * ri;
+                                    const float s2 = ttab[pidx] * ir2;
+                                    const float s6 = s2 * s2 * s2;
+                                    const float gg = ttab[2 * kMaxTypes * kMaxTypes + pidx] * s6 *
+                                                     (2.0f * s6 - 1.0f) * ir2;
+                                    lx = fmaf(gg, ddx, lx);
+                                    ly = fmaf(gg, ddy, ly);
+                                    lz = fmaf(gg, ddz, lz);
+                                }
                             }
                         }
+                        a.Fx += (double)bx;
+                        a.Fy += (double)by;
+                        a.Fz += (double)bz;
+                        a.Lx += (double)lx;
+                        a.Ly += (double)ly;
+                        a.Lz += (double)lz;
                     }
-                    Fx += (double)bx;
-                    Fy += (double)by;
-                    Fz += (double)bz;
-                    Lx += (double)lx;
-                    Ly += (double)ly;
-                    Lz += (double)lz;
                 }
             }
         }
     }
     if (live) {
         const double qi = (double)pi.w;
-        F[i] = -qi * Fx - Lx;
-        F[(size_t)n + i] = -qi * Fy - Ly;
-        F[2 * (size_t)n + i] = -qi * Fz - Lz;
+        F[i] = -qi * a.Fx - a.Lx;
+        F[(size_t)n + i] = -qi * a.Fy - a.Ly;
+        F[2 * (size_t)n + i] = -qi * a.Fz - a.Lz;
     }
 }
 

@@ -106,6 +106,20 @@ def test_block_near_ragged_small(ld, orc):
         assert np.all(np.linalg.norm(s.ff_forces(0) - Fn, axis=1) <= 1e-5 * S), grid
 
 
+@pytest.mark.parametrize("grid,block", [(4, 3), (6, 5), (8, 1)])
+def test_block_near_dense_rows(ld, orc, sysw, grid, block):
+    """Coarse grids: hundreds of slots per row, so a row's range is staged in
+    several pieces, tiles lie inside one cell, and i's own slot falls in a
+    later piece; block 1 takes the row-window walk (LJ reach beyond it)."""
+    s = ld.System.from_workload(sysw)
+    s.ff_enable(grid=grid, block=block, hidden=16, near_mode=ld.NEAR_BLOCK, parent_reach=0)
+    L, _ = s.ff_grid()
+    x = sysw.pos.astype(np.float64)
+    Fn, _ = orc.ff_split_block(x, sysw.type, sysw.charge, sysw.params, grid, L, block)
+    _, S, _ = orc.pair_forces(x, sysw.type, sysw.charge, sysw.params)
+    assert np.all(np.linalg.norm(s.ff_forces(0) - Fn, axis=1) <= 1e-5 * S)
+
+
 @pytest.mark.parametrize("reach", [0, 1, 3])
 def test_block_coarse_part(ld, orc, sysw, reach):
     """Block mode: q times the second-order local expansion of the far cells'
