@@ -55,6 +55,10 @@ def parse():
                          "snap-every steps) or from one trajectory")
     ap.add_argument("--near-mode", default="block", choices=["block", "radial"],
                     help="learned: exact near part over the 5^3 block of grid cells, or r < r_c")
+    ap.add_argument("--parent-reach", type=int, default=None,
+                    help="learned, block mode: 0 = one-level expansion (FFT convolution for "
+                         "grids up to 32), > 0 = two-level with that reach (default: the "
+                         "library's)")
     ap.add_argument("--autotune", action="store_true",
                     help="search the pair kernel launch shape before timing")
     ap.add_argument("--graph", type=int, default=0,
@@ -191,7 +195,11 @@ def bench_learned(a, torch, ldrop, W):
     wt = W.config_learned(n=a.n, seed=105)
     tr = ldrop.System.from_workload(wt)
     mode = ldrop.NEAR_BLOCK if a.near_mode == "block" else ldrop.NEAR_RADIAL
-    tr.ff_enable(near_cut=a.near_cut, near_mode=mode)
+    ffkw = dict(near_cut=a.near_cut, near_mode=mode)
+    if a.parent_reach is not None:
+        ffkw["parent_reach"] = a.parent_reach
+    reach = ffkw.get("parent_reach", ldrop.FF_DEFAULT["parent_reach"])
+    tr.ff_enable(**ffkw)
     if a.train_from == "trajectory":
         tr.ff_collect(reset=True, max_snapshots=a.snapshots)
         for _ in range(a.snapshots - 1):
@@ -212,7 +220,7 @@ def bench_learned(a, torch, ldrop, W):
     del tr
     we = W.config_learned(n=a.n, seed=5)
     ev = ldrop.System.from_workload(we)
-    ev.ff_enable(near_cut=a.near_cut, near_mode=mode)
+    ev.ff_enable(**ffkw)
     ev.ff_set_weights(weights, sq, scale)
     ev.step(a.warmup, we.dt)
     ms_direct = timed(ev, a.steps, we.dt)
@@ -240,6 +248,7 @@ def bench_learned(a, torch, ldrop, W):
         "config": {"workload": "learned: N=250000 medium composition, 32^3 moments, 5^3 block, "
                                "MLP 503-128-128-3",
                    "near_mode": a.near_mode,
+                   "parent_reach": reach if a.near_mode == "block" else None,
                    "near_cut": a.near_cut if a.near_mode == "radial" else None,
                    "snapshots": a.snapshots,
                    "snap_every": a.snap_every, "epochs": a.epochs,

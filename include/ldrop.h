@@ -290,7 +290,9 @@ typedef struct {
     int32_t near_mode;      /* 0 radial cutoff r_c, 1 the block^3 cells */
     int32_t parent_reach;   /* block mode, even grid: > 0 groups far cells by 2x2x2
                                parent cells beyond this Chebyshev distance (in parent
-                               cells) from the target's parent; 0 = one level */
+                               cells) from the target's parent; 0 = one level, every
+                               far cell on its own (a grid convolution evaluated by
+                               FFT for grid <= 32, direct sums above) */
 } ld_ff_config;
 
 typedef struct {

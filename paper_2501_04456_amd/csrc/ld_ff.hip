@@ -32,8 +32,10 @@
 // summation.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <new>
 
+#include "ld_ffconv.h"
 #include "ld_gemm.h"
 #include "ld_host.h"
 #include "ld_pair_core.h"
@@ -88,6 +90,8 @@ struct FarField {
     int* pocc = nullptr;               // [(G/2)^3] compacted occupied parents
     int* pcell2occ = nullptr;          // [(G/2)^3]
     int* npocc = nullptr;              // [1]
+    LocalConv conv;                    // one-level block expansion by FFT (G <= 32)
+    bool use_conv = false;
     int* ntiles = nullptr;
     int max_tiles = 0;
     float* Xc = nullptr;               // [G^3 * Kp]
@@ -1485,6 +1489,7 @@ void ff_free_bufs(FarField* f) {
                  f->bd1, f->bidx, f->loss_part};
     for (void* p : b)
         if (p) (void)hipFree(p);
+    conv_free(&f->conv);
 }
 
 #define KLAUNCH(kernel, grid, block, ...)                                                 \
@@ -1522,6 +1527,9 @@ ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
                 f->cfg.parent_reach, f->grid, M, f->loc_part);
         KLAUNCH(k_loc_reduce, dim3((M * kLoc + kB - 1) / kB), dim3(kB), s, f->loc_part, f->occ,
                 f->nocc, M, f->loc_split, f->Ecell);
+    } else if (f->cfg.near_mode == 1 && f->use_conv) {
+        const double* h = (const double*)((const char*)f->grid + offsetof(FFGrid, h));
+        HIP_TRY(conv_local(&f->conv, f->mom, G, h, f->Ecell, s));
     } else if (f->cfg.near_mode == 1) {
         KLAUNCH(k_coarse_local, dim3((M + kLB - 1) / kLB, f->loc_split), dim3(kLB), s, f->mom,
                 f->occ, f->nocc, G, f->cfg.block, f->grid, M, f->loc_part);
@@ -1878,6 +1886,10 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
               dalloc(&f->h1, n * f->H) && dalloc(&f->h2, n * f->H) && dalloc(&f->y, n * f->Op) &&
               dalloc(&f->W, f->nW) && dalloc(&f->grad, f->nW) && dalloc(&f->adam_m, f->nW) &&
               dalloc(&f->adam_v, f->nW) && dalloc(&f->rel, n) && dalloc(&f->Efar, 3 * n);
+    if (ok && cfg->near_mode == 1 && cfg->parent_reach == 0 && cfg->grid <= kConvMaxGrid) {
+        ok = conv_setup(&f->conv, cfg->block, c->stream) == hipSuccess;
+        f->use_conv = ok;
+    }
     if (!ok) {
         ff_free_bufs(f);
         delete f;

@@ -83,7 +83,7 @@ class ld_ff_train_report(C.Structure):
 
 
 FF_DEFAULT = dict(near_cut=8.0, grid=32, block=5, hidden=128, judge_every=500, judge_tol=1e-3,
-                  near_mode=0, parent_reach=3)
+                  near_mode=0, parent_reach=0)
 NEAR_RADIAL, NEAR_BLOCK = 0, 1
 
 

@@ -120,20 +120,21 @@ def test_block_near_dense_rows(ld, orc, sysw, grid, block):
     assert np.all(np.linalg.norm(s.ff_forces(0) - Fn, axis=1) <= 1e-5 * S)
 
 
-@pytest.mark.parametrize("reach", [0, 1, 3])
-def test_block_coarse_part(ld, orc, sysw, reach):
+@pytest.mark.parametrize("grid,reach", [(16, 0), (16, 1), (16, 3), (9, 0), (32, 0), (34, 0)])
+def test_block_coarse_part(ld, orc, sysw, grid, reach):
     """Block mode: q times the second-order local expansion of the far cells'
-    monopole + dipole field at every particle (reach 0: one level; reach > 0:
-    cells of 2x2x2 parents beyond the reach grouped by parent)."""
+    monopole + dipole field at every particle (reach 0: one level, by FFT
+    convolution up to grid 32 and by direct sums above; reach > 0: cells of
+    2x2x2 parents beyond the reach grouped by parent)."""
     s = ld.System.from_workload(sysw)
-    s.ff_enable(grid=G, block=B, hidden=64, near_mode=ld.NEAR_BLOCK, parent_reach=reach)
+    s.ff_enable(grid=grid, block=B, hidden=64, near_mode=ld.NEAR_BLOCK, parent_reach=reach)
     Fc_g = s.ff_forces(1)
     x = sysw.pos.astype(np.float64)
     L = grid_L(sysw.pos)
     qh = orc.qhat(sysw.charge, sysw.params)
-    mom = orc.ff_moments(x, qh, G, L)
-    loc = orc.ff_local(mom, G, L, B) if reach == 0 else orc.ff_local2(mom, G, L, B, reach)
-    Fc = qh[:, None] * orc.ff_local_eval(x, G, L, loc)
+    mom = orc.ff_moments(x, qh, grid, L)
+    loc = orc.ff_local(mom, grid, L, B) if reach == 0 else orc.ff_local2(mom, grid, L, B, reach)
+    Fc = qh[:, None] * orc.ff_local_eval(x, grid, L, loc)
     scale = np.sqrt(np.mean(np.sum(Fc ** 2, 1)))
     assert np.abs(Fc_g - Fc).max() <= 1e-4 * scale
 
