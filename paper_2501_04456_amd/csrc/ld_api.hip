@@ -421,7 +421,7 @@ ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* ch
     ds.step = 0;
     ds.t = 0.0;
     ds.bad_step = ~0ull;
-    ds.done = 0;
+    ds.pad0 = 0;
     hipError_t e = hipMemcpyAsync(c->pos, h4.data(), sizeof(float4) * N, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->lo, l4.data(), sizeof(float4) * N, hipMemcpyHostToDevice, s);

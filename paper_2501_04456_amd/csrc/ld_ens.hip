@@ -147,17 +147,6 @@ __global__ __launch_bounds__(256) void k_ens_update(float4* pos, float4* lo,
         pos[s] = h;
         lo[s] = l;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&st->done, 1u);
-        if (prev == gridDim.x - 1) {
-            st->step = step + 1;
-            st->t = tn;
-            st->done = 0u;
-            __threadfence();
-        }
-    }
 }
 
 // Bounding box and charged flag of every 64-slot tile (one wavefront each).
@@ -389,6 +378,7 @@ ld_status enqueue_step(ld_ens* e, double dt, hipStream_t s, bool timed) {
                        e->lo, e->typ, e->did, e->lid, e->F, e->total, e->ext, e->seeds, dt,
                        e->st);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(ld::launch_advance(e->st, dt, s));
     return LD_OK;
 }
 

@@ -129,7 +129,11 @@ namespace {
 
 constexpr int kB = 256;
 
-__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+// SiLU z sigmoid(z) with the hardware exponential and reciprocal (about 1
+// ulp each; the activations are rounded to BF16 next).
+__device__ __forceinline__ float silu_f(float z) {
+    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 
 __device__ __forceinline__ __bf16 bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -341,41 +345,40 @@ __global__ __launch_bounds__(kB) void k_near(const float4* __restrict__ pos,
 
 // One workgroup of 1024: cfirst[c] = slots in cells before c (cfirst[M] = n),
 // then the row tiles: every (y, z) row's slot range cut into pieces of at
-// most 64 slots, tile = (row, first slot, end slot).  Both scans walk the
-// arrays 1024 consecutive entries at a time (coalesced).
+// most 64 slots, tile = (row, first slot, end slot).  Each thread takes a
+// contiguous run of cells (rows): its total, one workgroup scan of the
+// totals, then the run again with its offset.
 __global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cstart,
                                                       const int* __restrict__ cend, int G,
                                                       int* cfirst, int4* tiles, int* ntiles) {
     __shared__ int wsum[32];
     const int t = threadIdx.x;
     const int M = G * G * G, R = G * G;
-    int carry = 0;
-    for (int base = 0; base < M; base += 1024) {
-        const int c = base + t;
-        const int cnt = c < M ? cend[c] - cstart[c] : 0;
+    {
+        const int per = (M + 1023) / 1024;
+        const int c0 = min(M, t * per), c1 = min(M, c0 + per);
+        int sum = 0;
+        for (int c = c0; c < c1; ++c) sum += cend[c] - cstart[c];
         int tot;
-        const int ex = scan1024(cnt, wsum, &tot);
-        if (c < M) cfirst[c] = carry + ex;
-        carry += tot;
-    }
-    if (t == 0) cfirst[M] = carry;
-    __syncthreads();
-    int tcarry = 0;
-    for (int base = 0; base < R; base += 1024) {
-        const int r = base + t;
-        int a = 0, b = 0, nt = 0;
-        if (r < R) {
-            a = cfirst[r * G];
-            b = cfirst[(r + 1) * G];
-            nt = (b - a + 63) / 64;
+        int run = scan1024(sum, wsum, &tot);
+        for (int c = c0; c < c1; ++c) {
+            cfirst[c] = run;
+            run += cend[c] - cstart[c];
         }
-        int tot;
-        const int ex = scan1024(nt, wsum, &tot);
-        int k = tcarry + ex;
-        for (int s0 = a; s0 < b; s0 += 64) tiles[k++] = make_int4(r, s0, min(b, s0 + 64), 0);
-        tcarry += tot;
+        if (t == 0) cfirst[M] = tot;
     }
-    if (t == 0) *ntiles = tcarry;
+    __syncthreads();
+    const int per = (R + 1023) / 1024;
+    const int r0 = min(R, t * per), r1 = min(R, r0 + per);
+    int sum = 0;
+    for (int r = r0; r < r1; ++r) sum += (cfirst[(r + 1) * G] - cfirst[r * G] + 63) / 64;
+    int tot;
+    int k = scan1024(sum, wsum, &tot);
+    for (int r = r0; r < r1; ++r) {
+        const int a = cfirst[r * G], b = cfirst[(r + 1) * G];
+        for (int s0 = a; s0 < b; s0 += 64) tiles[k++] = make_int4(r, s0, min(b, s0 + 64), 0);
+    }
+    if (t == 0) *ntiles = tot;
 }
 
 // Block near field, one wavefront per row tile: Coulomb of every j in the
@@ -662,29 +665,27 @@ __global__ __launch_bounds__(kB) void k_moments_sorted(const float4* __restrict_
     count[c] = b - a;
 }
 
-// Deterministic compaction of occupied cells (one workgroup of 1024, 1024
-// consecutive cells per pass).
+// Deterministic compaction of occupied cells in cell order (one workgroup
+// of 1024; each thread takes a contiguous run of cells).
 __global__ __launch_bounds__(1024) void k_compact(const int* __restrict__ count, int M, int* occ,
                                                   int* cell2occ, int* nocc) {
     __shared__ int wsum[32];
     const int t = threadIdx.x;
-    int carry = 0;
-    for (int base = 0; base < M; base += 1024) {
-        const int c = base + t;
-        const int f = (c < M && count[c] > 0) ? 1 : 0;
-        int tot;
-        const int ex = scan1024(f, wsum, &tot);
-        if (c < M) {
-            if (f) {
-                occ[carry + ex] = c;
-                cell2occ[c] = carry + ex;
-            } else {
-                cell2occ[c] = -1;
-            }
+    const int per = (M + 1023) / 1024;
+    const int c0 = min(M, t * per), c1 = min(M, c0 + per);
+    int sum = 0;
+    for (int c = c0; c < c1; ++c) sum += count[c] > 0 ? 1 : 0;
+    int tot;
+    int run = scan1024(sum, wsum, &tot);
+    for (int c = c0; c < c1; ++c) {
+        if (count[c] > 0) {
+            occ[run] = c;
+            cell2occ[c] = run++;
+        } else {
+            cell2occ[c] = -1;
         }
-        carry += tot;
     }
-    if (t == 0) *nocc = carry;
+    if (t == 0) *nocc = tot;
 }
 
 // Field at every occupied cell centre from the monopole + dipole of every
@@ -1143,118 +1144,199 @@ __global__ __launch_bounds__(kB) void k_layer1(const float4* __restrict__ pos,
 // SiLU) and layer 3 (128 x 16) on the matrix cores, and
 // F = F_near + q (E_coarse + scale y).  W2 and W3 are staged once per
 // workgroup in LDS as BF16, column-major (the B operand of
-// v_mfma_f32_16x16x32_bf16: 8 consecutive K values of one column per lane);
-// each workgroup then walks 64-particle tiles.  Activations are rounded to
-// BF16 where the unfused path rounds them (as the next product stages them),
-// so the two paths compute the same products.  The hidden activations never
-// leave the CU.
+// v_mfma_f32_16x16x32_bf16: 8 consecutive K values of one column per lane).
+// Every wavefront then walks 16-particle tiles on its own: the tile's
+// activations (16 x 128, layer 1 and then layer 2 in the same rows) live in
+// the wavefront's own LDS rows, so a tile needs no workgroup barrier.
+// Activations are rounded to BF16 where the unfused path rounds them (as the
+// next product stages them), so the two paths compute the same products.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
-constexpr int kMT = 64;                 // particles per tile (4 wavefronts x 16 rows)
+constexpr int kMW = 16;                 // particles per wavefront tile (one MFMA row block)
+constexpr int kFW = 8;                  // wavefronts per workgroup
 constexpr int kFH = 128;                // hidden width of the fused kernel
 constexpr int kFHP = kFH + 8;           // padded LDS row (BF16 elements)
 
-__global__ __launch_bounds__(256) void k_mlp_fused(
+__global__ __launch_bounds__(kFW * 64) void k_mlp_fused(
     const float4* __restrict__ pos, const float4* __restrict__ lo, int n, int G,
     const FFGrid* g, const int* __restrict__ cell2occ, const float* __restrict__ Ac,
     const float* __restrict__ W1o, const float* __restrict__ b1, const float* __restrict__ W2,
     const float* __restrict__ b2, const float* __restrict__ W3, const float* __restrict__ b3,
     float scale, const double* __restrict__ Fn, const double* __restrict__ Ep, double* Fpart,
     double* Fc, double* Fm) {
-    __shared__ __attribute__((aligned(16))) __bf16 sW2[kFH][kFHP];   // [out column][k]
-    __shared__ __attribute__((aligned(16))) __bf16 sW3[16][kFHP];    // [out column][k]
-    __shared__ __attribute__((aligned(16))) __bf16 sA[kMT][kFHP];    // layer-1 activations
-    __shared__ __attribute__((aligned(16))) __bf16 sB[kMT][kFHP];    // layer-2 activations
-    __shared__ float sY[kMT][4];
-    __shared__ float sOff[kMT][3];
-    __shared__ int sOcc[kMT];
+    __shared__ __attribute__((aligned(16))) __bf16 sW2[kFH][kFHP];        // [out column][k]
+    __shared__ __attribute__((aligned(16))) __bf16 sW3[16][kFHP];         // [out column][k]
+    __shared__ __attribute__((aligned(16))) __bf16 sAct[kFW][kMW][kFHP];  // per wavefront
     const int t = threadIdx.x, w = t / 64, l = t % 64;
-    for (int e = t; e < kFH * kFH; e += 256) sW2[e % kFH][e / kFH] = bf16_rne(W2[e]);
-    for (int e = t; e < kFH * 16; e += 256) sW3[e % 16][e / 16] = bf16_rne(W3[e]);
-    // this thread's layer-1 column: offset weights and bias in registers
-    const int col = t % kFH;
-    const float w0 = bf16_round(W1o[col]), w1 = bf16_round(W1o[kFH + col]),
-                w2 = bf16_round(W1o[2 * kFH + col]), bias1 = b1[col];
-    for (int tile = blockIdx.x; tile * kMT < n; tile += gridDim.x) {
-        const int s0 = tile * kMT;
-        __syncthreads();                                // LDS of the previous tile is free
-        if (t < kMT) {
-            const int s = s0 + t;
-            int oc = -1;
-            float off[3] = {0.f, 0.f, 0.f};
-            if (s < n) {
-                int c;
-                particle_cell(pos[s], lo[s], G, g, &c, off);
-                oc = cell2occ[c];
-            }
-            sOcc[t] = oc;
-            sOff[t][0] = bf16_round(off[0]);
-            sOff[t][1] = bf16_round(off[1]);
-            sOff[t][2] = bf16_round(off[2]);
+    for (int e = t; e < kFH * kFH; e += kFW * 64) sW2[e % kFH][e / kFH] = bf16_rne(W2[e]);
+    for (int e = t; e < kFH * 16; e += kFW * 64) sW3[e % 16][e / 16] = bf16_rne(W3[e]);
+    // this lane's layer-1 columns l and l + 64: offset weights and bias
+    float wo[2][3], bias1[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int col = l + 64 * hh;
+        wo[hh][0] = bf16_round(W1o[col]);
+        wo[hh][1] = bf16_round(W1o[kFH + col]);
+        wo[hh][2] = bf16_round(W1o[2 * kFH + col]);
+        bias1[hh] = b1[col];
+    }
+    __syncthreads();
+    __bf16 (*act)[kFHP] = sAct[w];
+    const int ntiles = (n + kMW - 1) / kMW;
+    for (int tile = blockIdx.x * kFW + w; tile < ntiles; tile += gridDim.x * kFW) {
+        const int s0 = tile * kMW;
+        // lanes 0..15: the tile's particles (occupied-cell index, offset)
+        int oc = -1;
+        float o0 = 0.f, o1 = 0.f, o2 = 0.f;
+        if (l < kMW && s0 + l < n) {
+            int c;
+            float off[3];
+            particle_cell(pos[s0 + l], lo[s0 + l], G, g, &c, off);
+            oc = cell2occ[c];
+            o0 = bf16_round(off[0]);
+            o1 = bf16_round(off[1]);
+            o2 = bf16_round(off[2]);
         }
-        __syncthreads();
-        // layer 1: two rows per step, one column per thread
-        for (int row = t / kFH; row < kMT; row += 2) {
-            const int oc = sOcc[row];
-            float a = 0.f;
-            if (oc >= 0) {
-                const float z = Ac[(size_t)oc * kFH + col] + sOff[row][0] * w0 +
-                                sOff[row][1] * w1 + sOff[row][2] * w2 + bias1;
-                a = silu_f(z);
+        // layer 1: the 16 rows, columns l and l + 64
+        for (int r = 0; r < kMW; ++r) {
+            const int ocr = __shfl(oc, r);
+            const float f0 = __shfl(o0, r), f1 = __shfl(o1, r), f2 = __shfl(o2, r);
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int col = l + 64 * hh;
+                float a = 0.f;
+                if (ocr >= 0) {
+                    const float z = Ac[(size_t)ocr * kFH + col] + f0 * wo[hh][0] +
+                                    f1 * wo[hh][1] + f2 * wo[hh][2] + bias1[hh];
+                    a = silu_f(z);
+                }
+                act[r][col] = bf16_rne(a);
             }
-            sA[row][col] = bf16_rne(a);
         }
-        __syncthreads();
-        // layer 2: wavefront w owns rows 16w .. 16w+15, all 128 columns
+        __builtin_amdgcn_wave_barrier();
+        // layer 2: 16 rows x 128 columns
         f32x4_t acc[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < kFH / 32; ++ks) {
             const int kk = ks * 32 + 8 * (l / 16);
-            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&sA[w * 16 + l % 16][kk]);
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&act[l % 16][kk]);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&sW2[j * 16 + l % 16][kk]);
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
             }
         }
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int c = j * 16 + l % 16;
             const float bb = b2[c];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                sB[w * 16 + 4 * (l / 16) + r][c] = bf16_rne(silu_f(acc[j][r] + bb));
+                act[4 * (l / 16) + r][c] = bf16_rne(silu_f(acc[j][r] + bb));
         }
-        __syncthreads();
-        // layer 3: the wavefront's 16 rows x 16 output columns (3 used)
+        __builtin_amdgcn_wave_barrier();
+        // layer 3: 16 rows x 16 output columns (3 used)
         f32x4_t y = (f32x4_t){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < kFH / 32; ++ks) {
             const int kk = ks * 32 + 8 * (l / 16);
-            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&sB[w * 16 + l % 16][kk]);
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&act[l % 16][kk]);
             const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&sW3[l % 16][kk]);
             y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, y, 0, 0, 0);
         }
-        if (l % 16 < 3) {
-            const float bb = b3[l % 16];
+        __builtin_amdgcn_wave_barrier();
+        // lane (k = l % 16 < 3, l / 16) holds output k of rows 4 (l / 16) + 0..3
+        const int k = l % 16;
+        if (k < 3) {
+            const float bb = b3[k];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sY[w * 16 + 4 * (l / 16) + r][l % 16] = y[r] + bb;
-        }
-        __syncthreads();
-        if (t < kMT) {
-            const int s = s0 + t;
-            if (s < n) {
-                const double q = (double)pos[s].w;
-                for (int k = 0; k < 3; ++k) {
+            for (int r = 0; r < 4; ++r) {
+                const int s = s0 + 4 * (l / 16) + r;
+                if (s < n) {
+                    const double q = (double)pos[s].w;
                     const double ec = q * Ep[(size_t)k * n + s];
-                    const double em = q * (double)scale * (double)sY[t][k];
+                    const double em = q * (double)scale * (double)(y[r] + bb);
                     Fpart[(size_t)k * n + s] = Fn[(size_t)k * n + s] + ec + em;
                     if (Fc) Fc[(size_t)k * n + s] = ec;
                     if (Fm) Fm[(size_t)k * n + s] = em;
                 }
             }
+        }
+    }
+}
+
+// Layer 1, moment part, for hidden width 128: Ac[oc][col] = sum over the
+// B^3 block's features k = 4 b + comp of bf16(nm[cell b][comp])
+// bf16(W1[k][col]) (zero outside the grid), one row per occupied cell, on the
+// matrix cores.  The features are gathered from the normalised moment grid
+// nm as the A operand is formed (8 consecutive features = two neighbour
+// cells per lane); W1 passes through LDS as BF16, column-major, 128 rows of
+// K at a time.  Workgroup: 64 cells (4 wavefronts x 16 rows) x 128 columns.
+__global__ __launch_bounds__(256) void k_cell_layer(const float4* __restrict__ nm,
+                                                    const int* __restrict__ occ,
+                                                    const int* __restrict__ nocc, int G, int B,
+                                                    const float* __restrict__ W1, int Kp,
+                                                    float* __restrict__ Ac) {
+    __shared__ __attribute__((aligned(16))) __bf16 sB[kFH][kFHP];   // [column][k - k0]
+    __shared__ int nb[7 * 7 * 7];                                   // block offsets, packed
+    const int no = *nocc;
+    const int m0 = blockIdx.x * 64;
+    if (m0 >= no) return;                               // uniform per workgroup
+    const int t = threadIdx.x, w = t / 64, l = t % 64;
+    const int B3 = B * B * B, half = B / 2;
+    for (int b = t; b < B3; b += 256)
+        nb[b] = (b % B - half + 8) | (((b / B) % B - half + 8) << 8) | ((b / (B * B) - half + 8) << 16);
+    const int row = m0 + w * 16 + l % 16;
+    const bool live = row < no;
+    const int c = occ[live ? row : m0];
+    const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+    f32x4_t acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Kp; k0 += kFH) {
+        __syncthreads();
+        for (int e = t; e < kFH * kFH; e += 256) {
+            const int k = e / kFH, col = e % kFH;
+            sB[col][k] = bf16_rne(k0 + k < Kp ? W1[(size_t)(k0 + k) * kFH + col] : 0.f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kFH / 32; ++ks) {
+            const int kk = k0 + ks * 32 + 8 * (l / 16);   // features kk .. kk+7
+            bf16x8_t a;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int b = kk / 4 + hh;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (live && b < B3) {
+                    const int o = nb[b];
+                    const int x = cx + (o & 255) - 8, y = cy + ((o >> 8) & 255) - 8,
+                              z = cz + (o >> 16) - 8;
+                    if (x >= 0 && y >= 0 && z >= 0 && x < G && y < G && z < G)
+                        v = nm[(z * G + y) * G + x];
+                }
+                a[4 * hh] = bf16_rne(v.x);
+                a[4 * hh + 1] = bf16_rne(v.y);
+                a[4 * hh + 2] = bf16_rne(v.z);
+                a[4 * hh + 3] = bf16_rne(v.w);
+            }
+            const int kl = ks * 32 + 8 * (l / 16);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bf16x8_t bv = *reinterpret_cast<const bf16x8_t*>(&sB[j * 16 + l % 16][kl]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rr = m0 + w * 16 + 4 * (l / 16) + r;
+            if (rr < no) Ac[(size_t)rr * kFH + j * 16 + l % 16] = acc[j][r];
         }
     }
 }
@@ -1498,14 +1580,12 @@ void ff_free_bufs(FarField* f) {
         HIP_TRY(hipGetLastError());                                                       \
     } while (0)
 
-// Grid, moments, occupancy and coarse field at the current positions.
+// Moments, occupancy and coarse field at the current positions (after ff_near).
 ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
     FarField* f = FF(c);
     const int n = (int)c->n;
     const int G = f->cfg.grid, M = G * G * G;
-    KLAUNCH(k_absmax_part, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
-    KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, f->cfg.near_cut, G,
-            f->cfg.near_mode, f->cfg.block, f->rlj, f->grid);
+    // the grid is the one ff_near set for these positions
     if (f->cfg.near_mode == 1) {
         // slots are in grid-cell order (ff_near ran first): per-cell sums
         KLAUNCH(k_moments_sorted, dim3((M + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, M, G,
@@ -1615,18 +1695,28 @@ ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
     if (st != LD_OK) return st;
     st = ff_grid_and_coarse(c, s);
     if (st != LD_OK) return st;
-    KLAUNCH(k_cell_features, dim3(M), dim3(kB), s, f->mom, f->occ, f->nocc, G, f->cfg.block,
-            f->grid, f->sq, f->Kp, f->Xc);
     // layer 1, moment part, once per occupied cell (no bias: added per particle)
-    st = gemm(s, f->Xc, f->Kp, 0, f->W + f->offW1, H, 0, f->Ac, H, M, H, f->Kp, nullptr, 0,
-              nullptr, 0, 0, f->nocc);
-    if (st != LD_OK) return st;
+    if (H == kFH) {
+        // normalised moments (as the training snapshots store them) in Xc
+        KLAUNCH(k_snap_mom, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, M, f->grid, f->sq,
+                f->Xc);
+        KLAUNCH(k_cell_layer, dim3((M + 63) / 64), dim3(256), s,
+                reinterpret_cast<const float4*>(f->Xc), f->occ, f->nocc, G, f->cfg.block,
+                f->W + f->offW1, f->Kp, f->Ac);
+    } else {
+        KLAUNCH(k_cell_features, dim3(M), dim3(kB), s, f->mom, f->occ, f->nocc, G, f->cfg.block,
+                f->grid, f->sq, f->Kp, f->Xc);
+        st = gemm(s, f->Xc, f->Kp, 0, f->W + f->offW1, H, 0, f->Ac, H, M, H, f->Kp, nullptr, 0,
+                  nullptr, 0, 0, f->nocc);
+        if (st != LD_OK) return st;
+    }
     if (H == kFH) {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const int tiles = (n + kMT - 1) / kMT;
-        KLAUNCH(k_mlp_fused, dim3(std::max(1, std::min(tiles, 2 * cus))), dim3(256), s, c->pos,
+        const int groups = (n + kMW * kFW - 1) / (kMW * kFW);
+        KLAUNCH(k_mlp_fused, dim3(std::max(1, std::min(groups, 2 * cus))), dim3(kFW * 64), s,
+                c->pos,
                 c->lo, n, G, f->grid, f->cell2occ, f->Ac,
                 f->W + f->offW1 + (size_t)(f->K - 3) * H, f->W + f->offb1, f->W + f->offW2,
                 f->W + f->offb2, f->W + f->offW3, f->W + f->offb3, f->out_scale, f->Fnear,

@@ -30,7 +30,10 @@ __device__ __forceinline__ __bf16 to_bf16(float f) {
     return __builtin_bit_cast(__bf16, (unsigned short)(u >> 16));
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+// SiLU as in the fused kernel: hardware exponential and reciprocal.
+__device__ __forceinline__ float silu(float z) {
+    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) __bf16 As[BM][BK + PAD];
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(256) void k_silu_bwd(const float* __restrict__ Z, f
     const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (size_t)R * cols) return;
     const float z = Z[e];
-    const float s = 1.0f / (1.0f + expf(-z));
+    const float s = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
     dA[e] *= s * (1.0f + z * (1.0f - s));
 }
 

@@ -54,7 +54,7 @@ struct DevState {
     long long step;                      // global step counter n
     double t;                            // time t_n
     unsigned long long bad_step;         // first step with a blow-up (~0: none)
-    unsigned int done;                   // workgroups finished in the update
+    unsigned int pad0;                   // unused
     unsigned int pad;
 };
 
@@ -108,6 +108,8 @@ struct StepLaunch {
     Box* box;                            // refreshed for the new positions
 };
 hipError_t launch_update(const StepLaunch& L, const ExtParams& P, hipStream_t s);
+// Step counter + 1 and t + dt (enqueued after an update).
+hipError_t launch_advance(DevState* st, double dt, hipStream_t s);
 
 hipError_t launch_boxes(const float4* pos, int n, Box* box, hipStream_t s);
 

@@ -37,18 +37,14 @@ __global__ __launch_bounds__(kBlock) void k_update(StepLaunch L, ExtParams P) {
         L.lo[s] = nl;
     }
     if (L.box) write_box(h, live, s, L.box);
-    // The last workgroup to finish advances the step counter and time.
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&L.st->done, 1u);
-        if (prev == gridDim.x - 1) {
-            L.st->step = step + 1;
-            L.st->t = tn;
-            L.st->done = 0u;
-            __threadfence();
-        }
-    }
+}
+
+// Step counter and time advance after the update (a launch of its own: a
+// per-workgroup completion count would serialise one device-scope atomic
+// and fence per workgroup).  t_{n+1} = t_n + dt as the update computed it.
+__global__ void k_advance(DevState* st, double dt) {
+    st->t = st->t + dt;
+    st->step = st->step + 1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_boxes(const float4* __restrict__ pos, int n,
@@ -172,6 +168,12 @@ __global__ void k_diag_finish(const double* sums, const double* maxes, const dou
 hipError_t launch_update(const StepLaunch& L, const ExtParams& P, hipStream_t s) {
     const int blocks = (L.n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_update, dim3(blocks), dim3(kBlock), 0, s, L, P);
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, L.st, L.dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(DevState* st, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, st, dt);
     return hipGetLastError();
 }
 
