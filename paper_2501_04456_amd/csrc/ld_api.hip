@@ -327,7 +327,8 @@ ld_status take_pending_error(ld_ctx* c) {
 void free_all(ld_ctx* c) {
     void* bufs[] = {c->pos,     c->lo,     c->typ,         c->oid,       c->box,  c->aux,
                     c->Fpart,   c->S_slot, c->U_slot,      c->work,      c->st,
-                    c->sb.keys, c->sb.tmp4, c->sb.tmp_i,   c->sb.bounds, c->sb.bounds_part};
+                    c->sb.keys, c->sb.tmp4, c->sb.tmp_i,   c->sb.bounds, c->sb.bounds_part,
+                    c->sb.hist};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -402,7 +403,9 @@ ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* ch
               hipMalloc(&c->sb.tmp4, sizeof(float4) * N) == hipSuccess &&
               hipMalloc(&c->sb.tmp_i, sizeof(int) * N) == hipSuccess &&
               hipMalloc(&c->sb.bounds, sizeof(float) * 8) == hipSuccess &&
-              hipMalloc(&c->sb.bounds_part, sizeof(float) * 6 * 64) == hipSuccess;
+              hipMalloc(&c->sb.bounds_part, sizeof(float) * 6 * 64) == hipSuccess &&
+              hipMalloc(&c->sb.hist, sizeof(unsigned) * 256 * ld::radix_tiles((int)n)) ==
+                  hipSuccess;
     if (!ok || ensure_split_capacity(c, c->tune.j_split) != LD_OK) {
         free_all(c);
         delete c;

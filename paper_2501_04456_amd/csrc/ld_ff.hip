@@ -100,6 +100,8 @@ struct FarField {
     float* h2 = nullptr;               // [n * H]
     float* y = nullptr;                // [n * Op]
     float* W = nullptr;                // packed FP32 master weights
+    __bf16* w1bf = nullptr;            // [128][Kp] BF16 copy of W1, column-major (hidden 128)
+    bool w1bf_stale = true;            // W changed since w1bf was made
     float* grad = nullptr;             // packed gradients
     float* adam_m = nullptr;
     float* adam_v = nullptr;
@@ -169,6 +171,78 @@ __device__ __forceinline__ int scan1024(int v, int* wsum, int* total) {
     *total = wsum[31];
     __syncthreads();                                    // wsum is reused by the next call
     return before + x - v;
+}
+
+// Exclusive scan of load(0 .. n-1) in index order by one workgroup of 1024:
+// 8192 values at a time are read coalesced into LDS (buf), each thread takes
+// 8 consecutive ones, and emit(e, prefix, value) is called for every e.
+// Returns the total.
+template <class Load, class Emit>
+__device__ __forceinline__ int scan_runs(int n, Load load, Emit emit, int* buf, int* wsum) {
+    const int t = threadIdx.x;
+    int carry = 0;
+    for (int base = 0; base < n; base += 8 * 1024) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = base + i * 1024 + t;
+            buf[i * 1024 + t] = e < n ? load(e) : 0;
+        }
+        __syncthreads();
+        int v[8], sum = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            v[i] = buf[8 * t + i];
+            sum += v[i];
+        }
+        int tot;
+        int run = carry + scan1024(sum, wsum, &tot);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = base + 8 * t + i;
+            if (e < n) emit(e, run, v[i]);
+            run += v[i];
+        }
+        carry += tot;
+    }
+    return carry;
+}
+
+// scan_runs for two values at once (load returns int2; both scanned).
+template <class Load, class Emit>
+__device__ __forceinline__ int2 scan_runs2(int n, Load load, Emit emit, int2* buf, int* wsum) {
+    const int t = threadIdx.x;
+    int2 carry = make_int2(0, 0);
+    for (int base = 0; base < n; base += 4 * 1024) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = base + i * 1024 + t;
+            buf[i * 1024 + t] = e < n ? load(e) : make_int2(0, 0);
+        }
+        __syncthreads();
+        int2 v[4], sum = make_int2(0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[i] = buf[4 * t + i];
+            sum.x += v[i].x;
+            sum.y += v[i].y;
+        }
+        int tx, ty;
+        const int px = scan1024(sum.x, wsum, &tx);
+        const int py = scan1024(sum.y, wsum, &ty);
+        int2 run = make_int2(carry.x + px, carry.y + py);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = base + 4 * t + i;
+            if (e < n) emit(e, run, v[i]);
+            run.x += v[i].x;
+            run.y += v[i].y;
+        }
+        carry.x += tx;
+        carry.y += ty;
+    }
+    return carry;
 }
 
 // ---- grid --------------------------------------------------------------
@@ -343,42 +417,43 @@ __global__ __launch_bounds__(kB) void k_near(const float4* __restrict__ pos,
 
 // ---- block mode: row tiles and the block near field ----------------------
 
-// One workgroup of 1024: cfirst[c] = slots in cells before c (cfirst[M] = n),
-// then the row tiles: every (y, z) row's slot range cut into pieces of at
-// most 64 slots, tile = (row, first slot, end slot).  Each thread takes a
-// contiguous run of cells (rows): its total, one workgroup scan of the
-// totals, then the run again with its offset.
+// One workgroup of 1024: cfirst[c] = slots in cells before c (cfirst[M] = n)
+// and the occupied cells in cell order (occ, cell2occ, nocc, as k_compact
+// makes them), then the row tiles: every (y, z) row's slot range cut into
+// pieces of at most 64 slots, tile = (row, first slot, end slot).
 __global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cstart,
                                                       const int* __restrict__ cend, int G,
-                                                      int* cfirst, int4* tiles, int* ntiles) {
+                                                      int* cfirst, int* occ, int* cell2occ,
+                                                      int* nocc, int4* tiles, int* ntiles) {
+    __shared__ int2 buf[4 * 1024];
     __shared__ int wsum[32];
-    const int t = threadIdx.x;
     const int M = G * G * G, R = G * G;
-    {
-        const int per = (M + 1023) / 1024;
-        const int c0 = min(M, t * per), c1 = min(M, c0 + per);
-        int sum = 0;
-        for (int c = c0; c < c1; ++c) sum += cend[c] - cstart[c];
-        int tot;
-        int run = scan1024(sum, wsum, &tot);
-        for (int c = c0; c < c1; ++c) {
-            cfirst[c] = run;
-            run += cend[c] - cstart[c];
-        }
-        if (t == 0) cfirst[M] = tot;
+    const int2 tot = scan_runs2(
+        M,
+        [&](int c) {
+            const int k = cend[c] - cstart[c];
+            return make_int2(k, k > 0 ? 1 : 0);
+        },
+        [&](int c, int2 pre, int2 v) {
+            cfirst[c] = pre.x;
+            if (v.y) occ[pre.y] = c;
+            cell2occ[c] = v.y ? pre.y : -1;
+        },
+        buf, wsum);
+    if (threadIdx.x == 0) {
+        cfirst[M] = tot.x;
+        *nocc = tot.y;
     }
     __syncthreads();
-    const int per = (R + 1023) / 1024;
-    const int r0 = min(R, t * per), r1 = min(R, r0 + per);
-    int sum = 0;
-    for (int r = r0; r < r1; ++r) sum += (cfirst[(r + 1) * G] - cfirst[r * G] + 63) / 64;
-    int tot;
-    int k = scan1024(sum, wsum, &tot);
-    for (int r = r0; r < r1; ++r) {
-        const int a = cfirst[r * G], b = cfirst[(r + 1) * G];
-        for (int s0 = a; s0 < b; s0 += 64) tiles[k++] = make_int4(r, s0, min(b, s0 + 64), 0);
-    }
-    if (t == 0) *ntiles = tot;
+    const int nt = scan_runs(
+        R, [&](int r) { return (cfirst[(r + 1) * G] - cfirst[r * G] + 63) / 64; },
+        [&](int r, int pre, int cnt) {
+            const int a = cfirst[r * G], b = cfirst[(r + 1) * G];
+            for (int k = 0; k < cnt; ++k)
+                tiles[pre + k] = make_int4(r, a + 64 * k, min(b, a + 64 * (k + 1)), 0);
+        },
+        reinterpret_cast<int*>(buf), wsum);
+    if (threadIdx.x == 0) *ntiles = nt;
 }
 
 // Block near field, one wavefront per row tile: Coulomb of every j in the
@@ -666,26 +741,19 @@ __global__ __launch_bounds__(kB) void k_moments_sorted(const float4* __restrict_
 }
 
 // Deterministic compaction of occupied cells in cell order (one workgroup
-// of 1024; each thread takes a contiguous run of cells).
+// of 1024).
 __global__ __launch_bounds__(1024) void k_compact(const int* __restrict__ count, int M, int* occ,
                                                   int* cell2occ, int* nocc) {
+    __shared__ int buf[8 * 1024];
     __shared__ int wsum[32];
-    const int t = threadIdx.x;
-    const int per = (M + 1023) / 1024;
-    const int c0 = min(M, t * per), c1 = min(M, c0 + per);
-    int sum = 0;
-    for (int c = c0; c < c1; ++c) sum += count[c] > 0 ? 1 : 0;
-    int tot;
-    int run = scan1024(sum, wsum, &tot);
-    for (int c = c0; c < c1; ++c) {
-        if (count[c] > 0) {
-            occ[run] = c;
-            cell2occ[c] = run++;
-        } else {
-            cell2occ[c] = -1;
-        }
-    }
-    if (t == 0) *nocc = tot;
+    const int tot = scan_runs(
+        M, [&](int c) { return count[c] > 0 ? 1 : 0; },
+        [&](int c, int pre, int f) {
+            if (f) occ[pre] = c;
+            cell2occ[c] = f ? pre : -1;
+        },
+        buf, wsum);
+    if (threadIdx.x == 0) *nocc = tot;
 }
 
 // Field at every occupied cell centre from the monopole + dipole of every
@@ -1268,17 +1336,29 @@ __global__ __launch_bounds__(kFW * 64) void k_mlp_fused(
     }
 }
 
+// W1 of hidden width 128 as BF16, column-major: wbf[col][k] (k < Kp), the
+// B operand layout of the cell layer (8 consecutive K of one column = 16 B).
+__global__ __launch_bounds__(kB) void k_w1_bf16(const float* __restrict__ W1, int Kp,
+                                                __bf16* __restrict__ wbf) {
+    const int e = blockIdx.x * kB + threadIdx.x;
+    if (e >= kFH * Kp) return;
+    const int col = e / Kp, k = e % Kp;
+    wbf[e] = bf16_rne(W1[(size_t)k * kFH + col]);
+}
+
 // Layer 1, moment part, for hidden width 128: Ac[oc][col] = sum over the
 // B^3 block's features k = 4 b + comp of bf16(nm[cell b][comp])
 // bf16(W1[k][col]) (zero outside the grid), one row per occupied cell, on the
 // matrix cores.  The features are gathered from the normalised moment grid
 // nm as the A operand is formed (8 consecutive features = two neighbour
-// cells per lane); W1 passes through LDS as BF16, column-major, 128 rows of
-// K at a time.  Workgroup: 64 cells (4 wavefronts x 16 rows) x 128 columns.
+// cells per lane), a chunk of 128 K ahead of the LDS staging of the BF16
+// W1 copy wbf (column-major, 128 K at a time), so the gathers and the
+// staging overlap.  Workgroup: 64 cells (4 wavefronts x 16 rows) x 128
+// columns.
 __global__ __launch_bounds__(256) void k_cell_layer(const float4* __restrict__ nm,
                                                     const int* __restrict__ occ,
                                                     const int* __restrict__ nocc, int G, int B,
-                                                    const float* __restrict__ W1, int Kp,
+                                                    const __bf16* __restrict__ wbf, int Kp,
                                                     float* __restrict__ Ac) {
     __shared__ __attribute__((aligned(16))) __bf16 sB[kFH][kFHP];   // [column][k - k0]
     __shared__ int nb[7 * 7 * 7];                                   // block offsets, packed
@@ -1289,6 +1369,7 @@ __global__ __launch_bounds__(256) void k_cell_layer(const float4* __restrict__ n
     const int B3 = B * B * B, half = B / 2;
     for (int b = t; b < B3; b += 256)
         nb[b] = (b % B - half + 8) | (((b / B) % B - half + 8) << 8) | ((b / (B * B) - half + 8) << 16);
+    __syncthreads();
     const int row = m0 + w * 16 + l % 16;
     const bool live = row < no;
     const int c = occ[live ? row : m0];
@@ -1297,31 +1378,41 @@ __global__ __launch_bounds__(256) void k_cell_layer(const float4* __restrict__ n
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < Kp; k0 += kFH) {
-        __syncthreads();
-        for (int e = t; e < kFH * kFH; e += 256) {
-            const int k = e / kFH, col = e % kFH;
-            sB[col][k] = bf16_rne(k0 + k < Kp ? W1[(size_t)(k0 + k) * kFH + col] : 0.f);
-        }
-        __syncthreads();
+        // this lane's features of the chunk: 4 steps x 2 cells
+        float4 v[4][2];
 #pragma unroll
         for (int ks = 0; ks < kFH / 32; ++ks) {
-            const int kk = k0 + ks * 32 + 8 * (l / 16);   // features kk .. kk+7
-            bf16x8_t a;
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
-                const int b = kk / 4 + hh;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                const int b = (k0 + ks * 32 + 8 * (l / 16)) / 4 + hh;
+                v[ks][hh] = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (live && b < B3) {
                     const int o = nb[b];
                     const int x = cx + (o & 255) - 8, y = cy + ((o >> 8) & 255) - 8,
                               z = cz + (o >> 16) - 8;
                     if (x >= 0 && y >= 0 && z >= 0 && x < G && y < G && z < G)
-                        v = nm[(z * G + y) * G + x];
+                        v[ks][hh] = nm[(z * G + y) * G + x];
                 }
-                a[4 * hh] = bf16_rne(v.x);
-                a[4 * hh + 1] = bf16_rne(v.y);
-                a[4 * hh + 2] = bf16_rne(v.z);
-                a[4 * hh + 3] = bf16_rne(v.w);
+            }
+        }
+        __syncthreads();                                // sB of the previous chunk is free
+        for (int e = t; e < kFH * kFH / 8; e += 256) {
+            const int col = e / (kFH / 8), q = e % (kFH / 8);
+            bf16x8_t x = {};
+            if (k0 + 8 * q < Kp)
+                x = *reinterpret_cast<const bf16x8_t*>(wbf + (size_t)col * Kp + k0 + 8 * q);
+            *reinterpret_cast<bf16x8_t*>(&sB[col][8 * q]) = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kFH / 32; ++ks) {
+            bf16x8_t a;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                a[4 * hh] = bf16_rne(v[ks][hh].x);
+                a[4 * hh + 1] = bf16_rne(v[ks][hh].y);
+                a[4 * hh + 2] = bf16_rne(v[ks][hh].z);
+                a[4 * hh + 3] = bf16_rne(v[ks][hh].w);
             }
             const int kl = ks * 32 + 8 * (l / 16);
 #pragma unroll
@@ -1565,7 +1656,7 @@ bool dalloc(T** p, size_t count) {
 void ff_free_bufs(FarField* f) {
     void* b[] = {f->grid, f->cstart, f->cend, f->Fnear, f->mom, f->count, f->occ, f->cell2occ,
                  f->nocc, f->Ecell, f->Ep, f->cfirst, f->tiles, f->ntiles, f->loc_part, f->pmom,
-                 f->pcount, f->pocc, f->pcell2occ, f->npocc, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->grad, f->adam_m,
+                 f->pcount, f->pocc, f->pcell2occ, f->npocc, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->w1bf, f->grad, f->adam_m,
                  f->adam_v, f->rel, f->Efar, f->snap_mom, f->s_snap, f->s_cell, f->s_off,
                  f->s_tgt, f->bX, f->bT, f->bZ1, f->bA1, f->bZ2, f->bA2, f->bY, f->bdY, f->bd2,
                  f->bd1, f->bidx, f->loss_part};
@@ -1596,7 +1687,8 @@ ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
         KLAUNCH(k_moments, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid,
                 f->mom, f->count);
     }
-    KLAUNCH(k_compact, dim3(1), dim3(1024), s, f->count, M, f->occ, f->cell2occ, f->nocc);
+    if (f->cfg.near_mode != 1)   // block mode: k_block_tiles made the list with cfirst
+        KLAUNCH(k_compact, dim3(1), dim3(1024), s, f->count, M, f->occ, f->cell2occ, f->nocc);
     if (f->cfg.near_mode == 1 && f->cfg.parent_reach > 0) {
         const int Mp = (G / 2) * (G / 2) * (G / 2);
         KLAUNCH(k_parent_moments, dim3((Mp + kB - 1) / kB), dim3(kB), s, f->mom, f->count, G,
@@ -1635,15 +1727,21 @@ ld_status ff_near(ld_ctx* c, hipStream_t s) {
             f->cfg.near_mode, f->cfg.block, f->rlj, f->grid);
     KLAUNCH(k_near_keys, dim3((c->sb.n_pow2 + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n,
             c->sb.n_pow2, f->grid, c->sb.keys);
-    HIP_TRY(ld::launch_sort_by_keys(c->pos, c->lo, c->typ, c->oid, n, c->sb, s));
     const int NC = kMaxNearCells * kMaxNearCells * kMaxNearCells;
+    {
+        // cell indices stay below G^3 (block) or 64^3 (radial near cells)
+        const int cells = f->cfg.near_mode == 1 ? f->cfg.grid * f->cfg.grid * f->cfg.grid : NC;
+        int bits = 1;
+        while ((1 << bits) < cells) ++bits;
+        HIP_TRY(ld::launch_sort_small_keys(c->pos, c->lo, c->typ, c->oid, n, bits, c->sb, s));
+    }
     KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cstart, NC);
     KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cend, NC);
     KLAUNCH(k_cell_ranges, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, f->cstart, f->cend);
     if (f->cfg.near_mode == 1) {
         const int G = f->cfg.grid;
-        KLAUNCH(k_block_tiles, dim3(1), dim3(1024), s, f->cstart, f->cend, G, f->cfirst, f->tiles,
-                f->ntiles);
+        KLAUNCH(k_block_tiles, dim3(1), dim3(1024), s, f->cstart, f->cend, G, f->cfirst, f->occ,
+                f->cell2occ, f->nocc, f->tiles, f->ntiles);
         KLAUNCH(k_near_block, dim3(f->max_tiles), dim3(64), s, c->pos, c->typ, c->sb.keys, f->grid,
                 G, f->cfg.block / 2, f->cfirst, f->tiles, f->ntiles, n, c->tab, f->Fnear);
     } else {
@@ -1700,9 +1798,14 @@ ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
         // normalised moments (as the training snapshots store them) in Xc
         KLAUNCH(k_snap_mom, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, M, f->grid, f->sq,
                 f->Xc);
+        if (f->w1bf_stale) {
+            KLAUNCH(k_w1_bf16, dim3((kFH * f->Kp + kB - 1) / kB), dim3(kB), s, f->W + f->offW1,
+                    f->Kp, f->w1bf);
+            f->w1bf_stale = false;
+        }
         KLAUNCH(k_cell_layer, dim3((M + 63) / 64), dim3(256), s,
                 reinterpret_cast<const float4*>(f->Xc), f->occ, f->nocc, G, f->cfg.block,
-                f->W + f->offW1, f->Kp, f->Ac);
+                f->w1bf, f->Kp, f->Ac);
     } else {
         KLAUNCH(k_cell_features, dim3(M), dim3(kB), s, f->mom, f->occ, f->nocc, G, f->cfg.block,
                 f->grid, f->sq, f->Kp, f->Xc);
@@ -1975,7 +2078,8 @@ ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
               dalloc(&f->Xc, M * f->Kp) && dalloc(&f->Ac, M * f->H) &&
               dalloc(&f->h1, n * f->H) && dalloc(&f->h2, n * f->H) && dalloc(&f->y, n * f->Op) &&
               dalloc(&f->W, f->nW) && dalloc(&f->grad, f->nW) && dalloc(&f->adam_m, f->nW) &&
-              dalloc(&f->adam_v, f->nW) && dalloc(&f->rel, n) && dalloc(&f->Efar, 3 * n);
+              dalloc(&f->adam_v, f->nW) && dalloc(&f->rel, n) && dalloc(&f->Efar, 3 * n) &&
+              dalloc(&f->w1bf, f->H == kFH ? (size_t)kFH * f->Kp : 1);
     if (ok && cfg->near_mode == 1 && cfg->parent_reach == 0 && cfg->grid <= kConvMaxGrid) {
         ok = conv_setup(&f->conv, cfg->block, c->stream) == hipSuccess;
         f->use_conv = ok;
@@ -2034,6 +2138,7 @@ ld_status ld_ff_set_weights(ld_ctx* c, const float* w, int64_t count, double sq,
     if (!(sq > 0.0) || !(out_scale >= 0.0) || !std::isfinite(out_scale))
         return fail(LD_EINVAL, "sq must be positive and out_scale >= 0 (0: network off)");
     HIP_TRY(copy_in(c->ff->W, w, sizeof(float) * count, c->stream));
+    c->ff->w1bf_stale = true;
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->ff->sq = (float)sq;
     c->ff->out_scale = (float)out_scale;
@@ -2260,6 +2365,7 @@ ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* 
             st = fwd_bwd(f, B_, s, want ? &l : nullptr);
             if (st != LD_OK) break;
             ++f->adam_step;
+            f->w1bf_stale = true;
             if (ld::launch_adam(f->W, f->grad, f->adam_m, f->adam_v, (int)f->nW, (float)tc->lr,
                                 f->adam_step, s) != hipSuccess) {
                 st = fail(LD_EHIP, "adam");

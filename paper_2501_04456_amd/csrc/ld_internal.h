@@ -185,6 +185,7 @@ struct SortBuffers {
     float* bounds;                       // [8] device scratch
     float* bounds_part;                  // per-block partial min/max
     int bounds_parts;
+    unsigned* hist;                      // [256 * radix_tiles(n)] radix digit counts (or null)
 };
 hipError_t launch_sort(float4* pos, float4* lo, int* typ, int* oid, int n,
                        const SortBuffers& B, hipStream_t s);
@@ -196,6 +197,24 @@ hipError_t launch_sort_by_keys(float4* pos, float4* lo, int* typ, int* oid, int 
 
 // 64-bit bitonic sort of n_pow2 keys (ascending).
 hipError_t launch_bitonic(unsigned long long* keys, int n_pow2, hipStream_t s);
+
+// Slot arrays permuted by B.keys (low word of keys[s] = source slot of s).
+hipError_t permute_slots(float4* pos, float4* lo, int* typ, int* oid, int n,
+                         const SortBuffers& B, hipStream_t s);
+
+// Workgroup tiles of the radix sort for n keys (B.hist holds 256 per tile).
+int radix_tiles(int n);
+
+// Stable sort of keys[0, n) by the high word, which is below 2^bits (LSD
+// radix, 8-bit digits; tmp holds n keys, hist 256 * radix_tiles(n)).
+hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tmp, int n, int bits,
+                                unsigned* hist, hipStream_t s);
+
+// B.keys[0, n) (high word < 2^bits, low word = slot; the slots are in key
+// order within equal high words) sorted stably by the radix sort, then the
+// slot arrays permuted.
+hipError_t launch_sort_small_keys(float4* pos, float4* lo, int* typ, int* oid, int n, int bits,
+                                  const SortBuffers& B, hipStream_t s);
 
 // Post-processing.
 hipError_t launch_rdf(const float4* pos, const float4* lo, int n, double r_max, int n_bins,

@@ -6,6 +6,9 @@
 //
 // Sorting is a 64-bit bitonic network: 2048-key chunks are sorted and merged
 // inside LDS, longer strides run as one global compare-exchange pass each.
+// Keys whose sort word is a small integer (a cell index) take a stable LSD
+// radix sort instead: 8-bit digits, per-workgroup digit counts, one scan,
+// and a scatter that ranks equal digits in slot order.
 #include "ld_internal.h"
 
 namespace ld {
@@ -123,6 +126,113 @@ __global__ __launch_bounds__(256) void k_permute1(const unsigned long long* __re
     if (s < n) b[s] = a[(int)(unsigned)keys[s]];
 }
 
+// ---- radix sort of keys by their high word ---------------------------------
+
+constexpr int kRT = 256;                   // threads of the histogram and scatter kernels
+constexpr int kRRounds = 16;               // 256-key rounds per tile
+constexpr int kRTile = kRT * kRRounds;     // keys per workgroup tile
+
+// Digit counts of one tile: hist[digit * nwg + tile].
+__global__ __launch_bounds__(kRT) void k_radix_hist(const unsigned long long* __restrict__ in,
+                                                    int n, int shift, unsigned* hist, int nwg) {
+    __shared__ unsigned h[256];
+    const int t = threadIdx.x;
+    h[t] = 0u;
+    __syncthreads();
+    for (int r = 0; r < kRRounds; ++r) {
+        const int e = blockIdx.x * kRTile + r * kRT + t;
+        if (e < n) atomicAdd(&h[(unsigned)(in[e] >> (32 + shift)) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)t * nwg + blockIdx.x] = h[t];
+}
+
+// In-place exclusive scan of m counters by one workgroup of 1024, four
+// consecutive counters per thread and pass.
+__global__ __launch_bounds__(1024) void k_radix_scan(unsigned* a, int m) {
+    __shared__ unsigned wsum[16];
+    const int t = threadIdx.x, lane = t % 64, wv = t / 64;
+    unsigned carry = 0u;
+    for (int base = 0; base < m; base += 4 * 1024) {
+        unsigned v[4], sum = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = base + 4 * t + i;
+            v[i] = e < m ? a[e] : 0u;
+            sum += v[i];
+        }
+        unsigned x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        unsigned before = 0u, total = 0u;
+        for (int k = 0; k < 16; ++k) {
+            const unsigned ws = wsum[k];
+            if (k < wv) before += ws;
+            total += ws;
+        }
+        unsigned run = carry + before + x - sum;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = base + 4 * t + i;
+            if (e < m) a[e] = run;
+            run += v[i];
+        }
+        carry += total;
+        __syncthreads();                               // wsum is reused by the next pass
+    }
+}
+
+// Stable scatter of one tile by digit: a key's destination is its digit's
+// offset (scanned counts of all earlier tiles and digits) plus the number
+// of equal digits before it in the tile -- earlier rounds, earlier
+// wavefronts of its round, earlier lanes of its wavefront (matched with
+// eight ballots).
+__global__ __launch_bounds__(kRT) void k_radix_scatter(const unsigned long long* __restrict__ in,
+                                                       unsigned long long* __restrict__ out,
+                                                       int n, int shift,
+                                                       const unsigned* __restrict__ hist,
+                                                       int nwg) {
+    __shared__ unsigned base[256];
+    __shared__ unsigned wcnt[kRT / 64][256];
+    const int t = threadIdx.x, w = t / 64, l = t % 64;
+    base[t] = hist[(size_t)t * nwg + blockIdx.x];
+    const unsigned long long below = (1ull << l) - 1ull;
+    for (int r = 0; r < kRRounds; ++r) {
+        const int e = blockIdx.x * kRTile + r * kRT + t;
+        const bool valid = e < n;
+        const unsigned long long key = valid ? in[e] : 0ull;
+        const unsigned d = (unsigned)(key >> (32 + shift)) & 255u;
+#pragma unroll
+        for (int k = 0; k < kRT / 64; ++k) wcnt[k][t] = 0u;
+        unsigned long long same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long m = __ballot(valid && bit);
+            same &= bit ? m : ~m;
+        }
+        const unsigned rank = (unsigned)__popcll(same & below);
+        __syncthreads();                               // wcnt cleared, base current
+        if (valid && rank == 0u) wcnt[w][d] = (unsigned)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            unsigned pos = base[d] + rank;
+            for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+            out[pos] = key;
+        }
+        __syncthreads();
+        unsigned add = 0u;
+#pragma unroll
+        for (int k = 0; k < kRT / 64; ++k) add += wcnt[k][t];
+        base[t] += add;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_bitonic(unsigned long long* keys, int n_pow2, hipStream_t s) {
@@ -149,10 +259,9 @@ hipError_t launch_sort(float4* pos, float4* lo, int* typ, int* oid, int n, const
     return launch_sort_by_keys(pos, lo, typ, oid, n, B, s);
 }
 
-hipError_t launch_sort_by_keys(float4* pos, float4* lo, int* typ, int* oid, int n,
-                               const SortBuffers& B, hipStream_t s) {
-    hipError_t e = launch_bitonic(B.keys, B.n_pow2, s);
-    if (e != hipSuccess) return e;
+hipError_t permute_slots(float4* pos, float4* lo, int* typ, int* oid, int n,
+                         const SortBuffers& B, hipStream_t s) {
+    hipError_t e;
     const dim3 g((n + 255) / 256);
     hipLaunchKernelGGL(k_permute4, g, dim3(256), 0, s, B.keys, n, pos, B.tmp4);
     e = hipMemcpyAsync(pos, B.tmp4, sizeof(float4) * n, hipMemcpyDeviceToDevice, s);
@@ -167,6 +276,47 @@ hipError_t launch_sort_by_keys(float4* pos, float4* lo, int* typ, int* oid, int 
     e = hipMemcpyAsync(oid, B.tmp_i, sizeof(int) * n, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
+}
+
+hipError_t launch_sort_by_keys(float4* pos, float4* lo, int* typ, int* oid, int n,
+                               const SortBuffers& B, hipStream_t s) {
+    const hipError_t e = launch_bitonic(B.keys, B.n_pow2, s);
+    if (e != hipSuccess) return e;
+    return permute_slots(pos, lo, typ, oid, n, B, s);
+}
+
+int radix_tiles(int n) { return (n + kRTile - 1) / kRTile; }
+
+hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tmp, int n, int bits,
+                                unsigned* hist, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nwg = radix_tiles(n);
+    unsigned long long* src = keys;
+    unsigned long long* dst = tmp;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(nwg), dim3(kRT), 0, s, src, n, shift, hist, nwg);
+        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, hist, 256 * nwg);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nwg), dim3(kRT), 0, s, src, dst, n, shift, hist,
+                           nwg);
+        unsigned long long* x = src;
+        src = dst;
+        dst = x;
+    }
+    if (src != keys) {
+        const hipError_t e = hipMemcpyAsync(keys, src, sizeof(unsigned long long) * n,
+                                            hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_small_keys(float4* pos, float4* lo, int* typ, int* oid, int n, int bits,
+                                  const SortBuffers& B, hipStream_t s) {
+    if (!B.hist) return hipErrorInvalidValue;
+    hipError_t e = launch_radix_by_high(B.keys, reinterpret_cast<unsigned long long*>(B.tmp4), n,
+                                        bits, B.hist, s);
+    if (e != hipSuccess) return e;
+    return permute_slots(pos, lo, typ, oid, n, B, s);
 }
 
 }  // namespace ld
