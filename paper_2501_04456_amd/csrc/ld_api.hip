@@ -328,7 +328,7 @@ void free_all(ld_ctx* c) {
     void* bufs[] = {c->pos,     c->lo,     c->typ,         c->oid,       c->box,  c->aux,
                     c->Fpart,   c->S_slot, c->U_slot,      c->work,      c->st,
                     c->sb.keys, c->sb.tmp4, c->sb.tmp_i,   c->sb.bounds, c->sb.bounds_part,
-                    c->sb.hist};
+                    c->sb.hist, c->pos2,  c->lo2,   c->typ2,       c->oid2};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

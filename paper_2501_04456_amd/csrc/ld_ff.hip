@@ -208,43 +208,6 @@ __device__ __forceinline__ int scan_runs(int n, Load load, Emit emit, int* buf, 
     return carry;
 }
 
-// scan_runs for two values at once (load returns int2; both scanned).
-template <class Load, class Emit>
-__device__ __forceinline__ int2 scan_runs2(int n, Load load, Emit emit, int2* buf, int* wsum) {
-    const int t = threadIdx.x;
-    int2 carry = make_int2(0, 0);
-    for (int base = 0; base < n; base += 4 * 1024) {
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = base + i * 1024 + t;
-            buf[i * 1024 + t] = e < n ? load(e) : make_int2(0, 0);
-        }
-        __syncthreads();
-        int2 v[4], sum = make_int2(0, 0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            v[i] = buf[4 * t + i];
-            sum.x += v[i].x;
-            sum.y += v[i].y;
-        }
-        int tx, ty;
-        const int px = scan1024(sum.x, wsum, &tx);
-        const int py = scan1024(sum.y, wsum, &ty);
-        int2 run = make_int2(carry.x + px, carry.y + py);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = base + 4 * t + i;
-            if (e < n) emit(e, run, v[i]);
-            run.x += v[i].x;
-            run.y += v[i].y;
-        }
-        carry.x += tx;
-        carry.y += ty;
-    }
-    return carry;
-}
-
 // ---- grid --------------------------------------------------------------
 
 __global__ __launch_bounds__(kB) void k_absmax_part(const float4* __restrict__ pos, int n,
@@ -267,31 +230,38 @@ __global__ __launch_bounds__(kB) void k_absmax_part(const float4* __restrict__ p
 // L = max |coordinate| x (1 + 2^-10) in FP32, then the cell sides.  In
 // block mode the near cells are the grid cells and W rows around a tile
 // cover both the block (B/2) and the largest LJ range rlj.
-__global__ void k_grid(const float* part, int nparts, double rc, int G, int block_mode, int B,
-                       double rlj, FFGrid* g) {
-    float m = 0.f;
-    for (int b = 0; b < nparts; ++b) m = fmaxf(m, part[b]);
+__device__ __forceinline__ FFGrid make_grid(float m, double rc, int G, int block_mode, int B,
+                                            double rlj) {
+    FFGrid g{};
     m = fmaxf(m, 1e-3f);
     const float Lf = m * 1.0009765625f;
     const double L = (double)Lf;
     const double h = 2.0 * L / G;
-    g->L = L;
-    g->h = h;
+    g.L = L;
+    g.h = h;
     if (block_mode) {
         const int wl = (int)ceil(rlj / h);
         const int W = wl < B / 2 ? B / 2 : wl;
-        g->W = W > G ? G : W;
-        g->Wlj = wl;
-        g->hn = h;
-        g->Gn = G;
+        g.W = W > G ? G : W;
+        g.Wlj = wl;
+        g.hn = h;
+        g.Gn = G;
     } else {
         int Gn = (int)floor(2.0 * L / rc);
         Gn = Gn < 1 ? 1 : (Gn > kMaxNearCells ? kMaxNearCells : Gn);
-        g->hn = 2.0 * L / Gn;
-        g->Gn = Gn;
-        g->W = 0;
-        g->Wlj = 0;
+        g.hn = 2.0 * L / Gn;
+        g.Gn = Gn;
+        g.W = 0;
+        g.Wlj = 0;
     }
+    return g;
+}
+
+__global__ void k_grid(const float* part, int nparts, double rc, int G, int block_mode, int B,
+                       double rlj, FFGrid* g) {
+    float m = 0.f;
+    for (int b = 0; b < nparts; ++b) m = fmaxf(m, part[b]);
+    *g = make_grid(m, rc, G, block_mode, B, rlj);
 }
 
 __device__ __forceinline__ int cell1(double x, double L, double h, int G) {
@@ -303,23 +273,59 @@ __device__ __forceinline__ int cell1(double x, double L, double h, int G) {
 
 // Cell keys from the FP64 positions (hi + lo), so that cell membership
 // agrees with the moments and offsets.
+static_assert(kB == ld::kRadixThreads, "k_near_keys counts digits per radix tile");
+
+// Cell keys (cell << 32 | slot) of the slots, with the grid made from the
+// 64 partial maxima (block 0 stores it for the later kernels) and the
+// digit counts of the first radix pass over each 4096-slot tile.
 __global__ __launch_bounds__(kB) void k_near_keys(const float4* __restrict__ pos,
                                                   const float4* __restrict__ lo, int n,
-                                                  int n_pow2, const FFGrid* g,
-                                                  unsigned long long* keys) {
-    const int s = blockIdx.x * kB + threadIdx.x;
-    if (s >= n_pow2) return;
-    if (s >= n) {
-        keys[s] = ~0ull;
-        return;
+                                                  const float* __restrict__ part, double rc,
+                                                  int G, int block_mode, int B, double rlj,
+                                                  FFGrid* g, unsigned long long* keys,
+                                                  unsigned* hist, int nwg) {
+    __shared__ FFGrid sg;
+    __shared__ unsigned h[256];
+    const int t = threadIdx.x;
+    h[t] = 0u;
+    if (t < 64) {
+        float m = part[t];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if (t == 0) {
+            sg = make_grid(m, rc, G, block_mode, B, rlj);
+            if (blockIdx.x == 0) *g = sg;
+        }
     }
-    const float4 h = pos[s], l = lo[s];
-    const int Gn = g->Gn;
-    const int cx = cell1((double)h.x + (double)l.x, g->L, g->hn, Gn),
-              cy = cell1((double)h.y + (double)l.y, g->L, g->hn, Gn),
-              cz = cell1((double)h.z + (double)l.z, g->L, g->hn, Gn);
-    const unsigned c = (unsigned)((cz * Gn + cy) * Gn + cx);
-    keys[s] = ((unsigned long long)c << 32) | (unsigned)s;
+    __syncthreads();
+    const int Gn = sg.Gn;
+    for (int r = 0; r < ld::kRadixRounds; ++r) {
+        const int s = blockIdx.x * ld::kRadixTile + r * kB + t;
+        if (s < n) {
+            const float4 hp = pos[s], l = lo[s];
+            const int cx = cell1((double)hp.x + (double)l.x, sg.L, sg.hn, Gn),
+                      cy = cell1((double)hp.y + (double)l.y, sg.L, sg.hn, Gn),
+                      cz = cell1((double)hp.z + (double)l.z, sg.L, sg.hn, Gn);
+            const unsigned c = (unsigned)((cz * Gn + cy) * Gn + cx);
+            keys[s] = ((unsigned long long)c << 32) | (unsigned)s;
+            atomicAdd(&h[c & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(size_t)t * nwg + blockIdx.x] = h[t];
+}
+
+// Block mode: cfirst[c] = first slot of cell c in the cell-sorted slots,
+// cfirst[M] = n; an empty cell gets the first slot after it.
+__global__ __launch_bounds__(kB) void k_cell_first(const unsigned long long* __restrict__ keys,
+                                                   int n, int M, int* cfirst) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    const int c = (int)(keys[s] >> 32);
+    const int p = s == 0 ? -1 : (int)(keys[s - 1] >> 32);
+    for (int q = p + 1; q <= c; ++q) cfirst[q] = s;
+    if (s == n - 1)
+        for (int q = c + 1; q <= M; ++q) cfirst[q] = n;
 }
 
 __global__ __launch_bounds__(kB) void k_zero_i(int* a, int m) {
@@ -417,42 +423,21 @@ __global__ __launch_bounds__(kB) void k_near(const float4* __restrict__ pos,
 
 // ---- block mode: row tiles and the block near field ----------------------
 
-// One workgroup of 1024: cfirst[c] = slots in cells before c (cfirst[M] = n)
-// and the occupied cells in cell order (occ, cell2occ, nocc, as k_compact
-// makes them), then the row tiles: every (y, z) row's slot range cut into
-// pieces of at most 64 slots, tile = (row, first slot, end slot).
-__global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cstart,
-                                                      const int* __restrict__ cend, int G,
-                                                      int* cfirst, int* occ, int* cell2occ,
-                                                      int* nocc, int4* tiles, int* ntiles) {
-    __shared__ int2 buf[4 * 1024];
+// Row tiles (one workgroup of 1024): every (y, z) row's slot range, from
+// cfirst, cut into pieces of at most 64 slots, tile = (row, first slot, end
+// slot).
+__global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cfirst, int G,
+                                                      int4* tiles, int* ntiles) {
+    __shared__ int buf[8 * 1024];
     __shared__ int wsum[32];
-    const int M = G * G * G, R = G * G;
-    const int2 tot = scan_runs2(
-        M,
-        [&](int c) {
-            const int k = cend[c] - cstart[c];
-            return make_int2(k, k > 0 ? 1 : 0);
-        },
-        [&](int c, int2 pre, int2 v) {
-            cfirst[c] = pre.x;
-            if (v.y) occ[pre.y] = c;
-            cell2occ[c] = v.y ? pre.y : -1;
-        },
-        buf, wsum);
-    if (threadIdx.x == 0) {
-        cfirst[M] = tot.x;
-        *nocc = tot.y;
-    }
-    __syncthreads();
     const int nt = scan_runs(
-        R, [&](int r) { return (cfirst[(r + 1) * G] - cfirst[r * G] + 63) / 64; },
+        G * G, [&](int r) { return (cfirst[(r + 1) * G] - cfirst[r * G] + 63) / 64; },
         [&](int r, int pre, int cnt) {
             const int a = cfirst[r * G], b = cfirst[(r + 1) * G];
             for (int k = 0; k < cnt; ++k)
                 tiles[pre + k] = make_int4(r, a + 64 * k, min(b, a + 64 * (k + 1)), 0);
         },
-        reinterpret_cast<int*>(buf), wsum);
+        buf, wsum);
     if (threadIdx.x == 0) *ntiles = nt;
 }
 
@@ -712,12 +697,14 @@ __global__ __launch_bounds__(kB) void k_moments(const float4* __restrict__ pos,
 }
 
 // Block mode: the slots are sorted by grid cell, so each cell's moments are a
-// sum over its slot range (one work-item per cell, fixed order, no atomics).
+// sum over its slot range (one work-item per cell, fixed order, no atomics);
+// nm (optional) receives (Q / sq, P / (sq h)).
 __global__ __launch_bounds__(kB) void k_moments_sorted(const float4* __restrict__ pos,
                                                        const float4* __restrict__ lo, int M,
                                                        int G, const FFGrid* g,
                                                        const int* __restrict__ cfirst,
-                                                       double* mom, int* count) {
+                                                       double* mom, int* count, float sq,
+                                                       float4* nm) {
     const int c = blockIdx.x * kB + threadIdx.x;
     if (c >= M) return;
     const int a = cfirst[c], b = cfirst[c + 1];
@@ -738,6 +725,10 @@ __global__ __launch_bounds__(kB) void k_moments_sorted(const float4* __restrict_
     mom[4 * (size_t)c + 2] = Py;
     mom[4 * (size_t)c + 3] = Pz;
     count[c] = b - a;
+    if (nm) {   // the network's normalised moments, as the training snapshots store them
+        const double sh = (double)sq * hh;
+        nm[c] = make_float4((float)(Q / sq), (float)(Px / sh), (float)(Py / sh), (float)(Pz / sh));
+    }
 }
 
 // Deterministic compaction of occupied cells in cell order (one workgroup
@@ -1227,11 +1218,11 @@ constexpr int kFHP = kFH + 8;           // padded LDS row (BF16 elements)
 
 __global__ __launch_bounds__(kFW * 64) void k_mlp_fused(
     const float4* __restrict__ pos, const float4* __restrict__ lo, int n, int G,
-    const FFGrid* g, const int* __restrict__ cell2occ, const float* __restrict__ Ac,
-    const float* __restrict__ W1o, const float* __restrict__ b1, const float* __restrict__ W2,
-    const float* __restrict__ b2, const float* __restrict__ W3, const float* __restrict__ b3,
-    float scale, const double* __restrict__ Fn, const double* __restrict__ Ep, double* Fpart,
-    double* Fc, double* Fm) {
+    const FFGrid* g, const float* __restrict__ Ac, const float* __restrict__ W1o,
+    const float* __restrict__ b1, const float* __restrict__ W2, const float* __restrict__ b2,
+    const float* __restrict__ W3, const float* __restrict__ b3, float scale,
+    const double* __restrict__ Fn, const double* __restrict__ Ep, double* Fpart, double* Fc,
+    double* Fm) {
     __shared__ __attribute__((aligned(16))) __bf16 sW2[kFH][kFHP];        // [out column][k]
     __shared__ __attribute__((aligned(16))) __bf16 sW3[16][kFHP];         // [out column][k]
     __shared__ __attribute__((aligned(16))) __bf16 sAct[kFW][kMW][kFHP];  // per wavefront
@@ -1253,14 +1244,12 @@ __global__ __launch_bounds__(kFW * 64) void k_mlp_fused(
     const int ntiles = (n + kMW - 1) / kMW;
     for (int tile = blockIdx.x * kFW + w; tile < ntiles; tile += gridDim.x * kFW) {
         const int s0 = tile * kMW;
-        // lanes 0..15: the tile's particles (occupied-cell index, offset)
+        // lanes 0..15: the tile's particles (cell, offset)
         int oc = -1;
         float o0 = 0.f, o1 = 0.f, o2 = 0.f;
         if (l < kMW && s0 + l < n) {
-            int c;
             float off[3];
-            particle_cell(pos[s0 + l], lo[s0 + l], G, g, &c, off);
-            oc = cell2occ[c];
+            particle_cell(pos[s0 + l], lo[s0 + l], G, g, &oc, off);
             o0 = bf16_round(off[0]);
             o1 = bf16_round(off[1]);
             o2 = bf16_round(off[2]);
@@ -1346,25 +1335,22 @@ __global__ __launch_bounds__(kB) void k_w1_bf16(const float* __restrict__ W1, in
     wbf[e] = bf16_rne(W1[(size_t)k * kFH + col]);
 }
 
-// Layer 1, moment part, for hidden width 128: Ac[oc][col] = sum over the
+// Layer 1, moment part, for hidden width 128: Ac[c][col] = sum over the
 // B^3 block's features k = 4 b + comp of bf16(nm[cell b][comp])
-// bf16(W1[k][col]) (zero outside the grid), one row per occupied cell, on the
+// bf16(W1[k][col]) (zero outside the grid), one row per grid cell, on the
 // matrix cores.  The features are gathered from the normalised moment grid
 // nm as the A operand is formed (8 consecutive features = two neighbour
 // cells per lane), a chunk of 128 K ahead of the LDS staging of the BF16
 // W1 copy wbf (column-major, 128 K at a time), so the gathers and the
 // staging overlap.  Workgroup: 64 cells (4 wavefronts x 16 rows) x 128
 // columns.
-__global__ __launch_bounds__(256) void k_cell_layer(const float4* __restrict__ nm,
-                                                    const int* __restrict__ occ,
-                                                    const int* __restrict__ nocc, int G, int B,
+__global__ __launch_bounds__(256) void k_cell_layer(const float4* __restrict__ nm, int G, int B,
                                                     const __bf16* __restrict__ wbf, int Kp,
                                                     float* __restrict__ Ac) {
     __shared__ __attribute__((aligned(16))) __bf16 sB[kFH][kFHP];   // [column][k - k0]
     __shared__ int nb[7 * 7 * 7];                                   // block offsets, packed
-    const int no = *nocc;
+    const int no = G * G * G;
     const int m0 = blockIdx.x * 64;
-    if (m0 >= no) return;                               // uniform per workgroup
     const int t = threadIdx.x, w = t / 64, l = t % 64;
     const int B3 = B * B * B, half = B / 2;
     for (int b = t; b < B3; b += 256)
@@ -1372,7 +1358,7 @@ __global__ __launch_bounds__(256) void k_cell_layer(const float4* __restrict__ n
     __syncthreads();
     const int row = m0 + w * 16 + l % 16;
     const bool live = row < no;
-    const int c = occ[live ? row : m0];
+    const int c = live ? row : m0;
     const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
     f32x4_t acc[8];
 #pragma unroll
@@ -1680,14 +1666,17 @@ ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
     if (f->cfg.near_mode == 1) {
         // slots are in grid-cell order (ff_near ran first): per-cell sums
         KLAUNCH(k_moments_sorted, dim3((M + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, M, G,
-                f->grid, f->cfirst, f->mom, f->count);
+                f->grid, f->cfirst, f->mom, f->count, f->sq,
+                f->H == kFH ? reinterpret_cast<float4*>(f->Xc) : nullptr);
     } else {
         KLAUNCH(k_zero_d, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, 4 * M);
         KLAUNCH(k_zero_i, dim3((M + kB - 1) / kB), dim3(kB), s, f->count, M);
         KLAUNCH(k_moments, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n, G, f->grid,
                 f->mom, f->count);
     }
-    if (f->cfg.near_mode != 1)   // block mode: k_block_tiles made the list with cfirst
+    // the occupied-cell list serves the direct coarse sums and the unfused
+    // network (the FFT expansion and the hidden-128 kernels work per cell)
+    if (!(f->cfg.near_mode == 1 && f->use_conv && f->H == kFH))
         KLAUNCH(k_compact, dim3(1), dim3(1024), s, f->count, M, f->occ, f->cell2occ, f->nocc);
     if (f->cfg.near_mode == 1 && f->cfg.parent_reach > 0) {
         const int Mp = (G / 2) * (G / 2) * (G / 2);
@@ -1722,29 +1711,47 @@ ld_status ff_grid_and_coarse(ld_ctx* c, hipStream_t s) {
 ld_status ff_near(ld_ctx* c, hipStream_t s) {
     FarField* f = FF(c);
     const int n = (int)c->n;
+    const int G = f->cfg.grid, M = G * G * G;
+    const bool block = f->cfg.near_mode == 1;
     KLAUNCH(k_absmax_part, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
-    KLAUNCH(k_grid, dim3(1), dim3(1), s, c->sb.bounds_part, 64, f->cfg.near_cut, f->cfg.grid,
-            f->cfg.near_mode, f->cfg.block, f->rlj, f->grid);
-    KLAUNCH(k_near_keys, dim3((c->sb.n_pow2 + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, n,
-            c->sb.n_pow2, f->grid, c->sb.keys);
+    const int nwg = ld::radix_tiles(n);
+    KLAUNCH(k_near_keys, dim3(nwg), dim3(kB), s, c->pos, c->lo, n, c->sb.bounds_part,
+            f->cfg.near_cut, G, f->cfg.near_mode, f->cfg.block, f->rlj, f->grid, c->sb.keys,
+            c->sb.hist, nwg);
     const int NC = kMaxNearCells * kMaxNearCells * kMaxNearCells;
     {
         // cell indices stay below G^3 (block) or 64^3 (radial near cells)
-        const int cells = f->cfg.near_mode == 1 ? f->cfg.grid * f->cfg.grid * f->cfg.grid : NC;
+        const int cells = block ? M : NC;
         int bits = 1;
         while ((1 << bits) < cells) ++bits;
-        HIP_TRY(ld::launch_sort_small_keys(c->pos, c->lo, c->typ, c->oid, n, bits, c->sb, s));
+        HIP_TRY(ld::launch_radix_by_high(c->sb.keys,
+                                         reinterpret_cast<unsigned long long*>(c->sb.tmp4), n,
+                                         bits, c->sb.hist, s, true));
+        // permute into the second slot arrays and swap (no copy back); a
+        // captured step graph holds the old addresses and is recaptured
+        if (!c->pos2) {
+            if (!(dalloc(&c->pos2, (size_t)n) && dalloc(&c->lo2, (size_t)n) &&
+                  dalloc(&c->typ2, (size_t)n) && dalloc(&c->oid2, (size_t)n)))
+                return fail(LD_ENOMEM, "cannot allocate the second slot arrays");
+        }
+        HIP_TRY(ld::permute_slots_into(c->sb.keys, n, c->pos, c->lo, c->typ, c->oid, c->pos2,
+                                       c->lo2, c->typ2, c->oid2, s));
+        std::swap(c->pos, c->pos2);
+        std::swap(c->lo, c->lo2);
+        std::swap(c->typ, c->typ2);
+        std::swap(c->oid, c->oid2);
+        c->graph_len = -1;
     }
-    KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cstart, NC);
-    KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cend, NC);
-    KLAUNCH(k_cell_ranges, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, f->cstart, f->cend);
-    if (f->cfg.near_mode == 1) {
-        const int G = f->cfg.grid;
-        KLAUNCH(k_block_tiles, dim3(1), dim3(1024), s, f->cstart, f->cend, G, f->cfirst, f->occ,
-                f->cell2occ, f->nocc, f->tiles, f->ntiles);
+    if (block) {
+        KLAUNCH(k_cell_first, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, M, f->cfirst);
+        KLAUNCH(k_block_tiles, dim3(1), dim3(1024), s, f->cfirst, G, f->tiles, f->ntiles);
         KLAUNCH(k_near_block, dim3(f->max_tiles), dim3(64), s, c->pos, c->typ, c->sb.keys, f->grid,
                 G, f->cfg.block / 2, f->cfirst, f->tiles, f->ntiles, n, c->tab, f->Fnear);
     } else {
+        KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cstart, NC);
+        KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cend, NC);
+        KLAUNCH(k_cell_ranges, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, f->cstart,
+                f->cend);
         const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
         KLAUNCH(k_near, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->typ, n, f->grid,
                 f->cstart, f->cend, rc2, c->tab, f->Fnear);
@@ -1785,7 +1792,9 @@ ld_status gemm(hipStream_t s, const float* A, int lda, int tA, const float* B, i
 }
 
 // The learned pair forces of every slot into Fpart[0] (and optional parts).
-ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
+// boxes: refresh the 64-slot group boxes for the new slot order (not needed
+// when the update, which rewrites them, follows).
+ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm, bool boxes) {
     FarField* f = FF(c);
     const int n = (int)c->n;
     const int G = f->cfg.grid, M = G * G * G, H = f->H;
@@ -1793,19 +1802,20 @@ ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
     if (st != LD_OK) return st;
     st = ff_grid_and_coarse(c, s);
     if (st != LD_OK) return st;
-    // layer 1, moment part, once per occupied cell (no bias: added per particle)
+    // layer 1, moment part, once per cell (no bias: added per particle)
     if (H == kFH) {
-        // normalised moments (as the training snapshots store them) in Xc
-        KLAUNCH(k_snap_mom, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, M, f->grid, f->sq,
-                f->Xc);
+        // normalised moments (as the training snapshots store them) in Xc;
+        // block mode: k_moments_sorted wrote them
+        if (f->cfg.near_mode != 1)
+            KLAUNCH(k_snap_mom, dim3((4 * M + kB - 1) / kB), dim3(kB), s, f->mom, M, f->grid,
+                    f->sq, f->Xc);
         if (f->w1bf_stale) {
             KLAUNCH(k_w1_bf16, dim3((kFH * f->Kp + kB - 1) / kB), dim3(kB), s, f->W + f->offW1,
                     f->Kp, f->w1bf);
             f->w1bf_stale = false;
         }
         KLAUNCH(k_cell_layer, dim3((M + 63) / 64), dim3(256), s,
-                reinterpret_cast<const float4*>(f->Xc), f->occ, f->nocc, G, f->cfg.block,
-                f->w1bf, f->Kp, f->Ac);
+                reinterpret_cast<const float4*>(f->Xc), G, f->cfg.block, f->w1bf, f->Kp, f->Ac);
     } else {
         KLAUNCH(k_cell_features, dim3(M), dim3(kB), s, f->mom, f->occ, f->nocc, G, f->cfg.block,
                 f->grid, f->sq, f->Kp, f->Xc);
@@ -1820,11 +1830,10 @@ ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
         const int groups = (n + kMW * kFW - 1) / (kMW * kFW);
         KLAUNCH(k_mlp_fused, dim3(std::max(1, std::min(groups, 2 * cus))), dim3(kFW * 64), s,
                 c->pos,
-                c->lo, n, G, f->grid, f->cell2occ, f->Ac,
-                f->W + f->offW1 + (size_t)(f->K - 3) * H, f->W + f->offb1, f->W + f->offW2,
-                f->W + f->offb2, f->W + f->offW3, f->W + f->offb3, f->out_scale, f->Fnear,
-                f->Ep, c->Fpart, Fc, Fm);
-        HIP_TRY(ld::launch_boxes(c->pos, n, c->box, s));
+                c->lo, n, G, f->grid, f->Ac, f->W + f->offW1 + (size_t)(f->K - 3) * H,
+                f->W + f->offb1, f->W + f->offW2, f->W + f->offb2, f->W + f->offW3,
+                f->W + f->offb3, f->out_scale, f->Fnear, f->Ep, c->Fpart, Fc, Fm);
+        if (boxes) HIP_TRY(ld::launch_boxes(c->pos, n, c->box, s));
         return LD_OK;
     }
     KLAUNCH(k_layer1, dim3((unsigned)(((size_t)n * H + kB - 1) / kB)), dim3(kB), s, c->pos, c->lo,
@@ -1838,7 +1847,7 @@ ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm) {
     if (st != LD_OK) return st;
     KLAUNCH(k_combine, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, f->Fnear, f->Ep, f->y,
             f->Op, f->out_scale, c->Fpart, Fc, Fm);
-    HIP_TRY(ld::launch_boxes(c->pos, n, c->box, s));
+    if (boxes) HIP_TRY(ld::launch_boxes(c->pos, n, c->box, s));
     return LD_OK;
 }
 
@@ -1859,7 +1868,7 @@ ld_status ff_judge_now(ld_ctx* c, double* med) {
     FarField* f = FF(c);
     const int n = (int)c->n;
     hipStream_t s = c->stream;
-    ld_status st = ff_learned_forces(c, s, nullptr, nullptr);   // re-sorts, Fpart[0]
+    ld_status st = ff_learned_forces(c, s, nullptr, nullptr, true);   // re-sorts, Fpart[0]
     if (st != LD_OK) return st;
     double* Fl = c->work;                  // [3][n]
     double* Fd = c->work + 3 * (size_t)n;  // [3][n]
@@ -1998,7 +2007,8 @@ ld_status ff_step_forces(ld_ctx* c, hipStream_t s, int* j_split_used) {
     }
     ++f->window_steps;
     if (f->mode == 1 || f->active) {
-        ld_status st = ff_learned_forces(c, s, nullptr, nullptr);
+        // the update that follows rewrites the group boxes
+        ld_status st = ff_learned_forces(c, s, nullptr, nullptr, false);
         if (st != LD_OK) return st;
         *j_split_used = 1;
         ++f->learned_steps;
@@ -2189,7 +2199,7 @@ ld_status ld_ff_forces(ld_ctx* c, int32_t part, double* out) {
         KLAUNCH(k_q_times, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, n, f->Efar, Fc);
         src = Fc;
     } else {
-        ld_status st = ff_learned_forces(c, s, Fc, Fm);
+        ld_status st = ff_learned_forces(c, s, Fc, Fm, true);
         if (st != LD_OK) return st;
         src = part == 0 ? f->Fnear : part == 1 ? Fc : part == 2 ? Fm : c->Fpart;
     }

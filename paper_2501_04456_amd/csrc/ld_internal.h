@@ -202,19 +202,23 @@ hipError_t launch_bitonic(unsigned long long* keys, int n_pow2, hipStream_t s);
 hipError_t permute_slots(float4* pos, float4* lo, int* typ, int* oid, int n,
                          const SortBuffers& B, hipStream_t s);
 
-// Workgroup tiles of the radix sort for n keys (B.hist holds 256 per tile).
+// Radix sort geometry: a workgroup of 256 handles a tile of 16 rounds x 256
+// keys; B.hist holds 256 digit counts per tile (digit-major).
+constexpr int kRadixThreads = 256;
+constexpr int kRadixRounds = 16;
+constexpr int kRadixTile = kRadixThreads * kRadixRounds;
 int radix_tiles(int n);
 
 // Stable sort of keys[0, n) by the high word, which is below 2^bits (LSD
 // radix, 8-bit digits; tmp holds n keys, hist 256 * radix_tiles(n)).
+// first_counted: hist already holds the first pass's digit counts.
 hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tmp, int n, int bits,
-                                unsigned* hist, hipStream_t s);
+                                unsigned* hist, hipStream_t s, bool first_counted = false);
 
-// B.keys[0, n) (high word < 2^bits, low word = slot; the slots are in key
-// order within equal high words) sorted stably by the radix sort, then the
-// slot arrays permuted.
-hipError_t launch_sort_small_keys(float4* pos, float4* lo, int* typ, int* oid, int n, int bits,
-                                  const SortBuffers& B, hipStream_t s);
+// dst arrays[s] = src arrays[low word of keys[s]] for s < n, one launch.
+hipError_t permute_slots_into(const unsigned long long* keys, int n, const float4* pos,
+                              const float4* lo, const int* typ, const int* oid, float4* pos2,
+                              float4* lo2, int* typ2, int* oid2, hipStream_t s);
 
 // Post-processing.
 hipError_t launch_rdf(const float4* pos, const float4* lo, int n, double r_max, int n_bins,
@@ -246,6 +250,12 @@ struct ld_ctx {
     float4* lo = nullptr;                // [n] {x_lo, y_lo, z_lo, 0}
     int* typ = nullptr;                  // [n] type per slot
     int* oid = nullptr;                  // [n] original index per slot
+    // second slot arrays (allocated by the learned path: its cell sort
+    // permutes into them and swaps them with the four above)
+    float4* pos2 = nullptr;
+    float4* lo2 = nullptr;
+    int* typ2 = nullptr;
+    int* oid2 = nullptr;
     ld::Box* box = nullptr;              // [ceil(n/64)] group boxes
     double* Fpart = nullptr;             // [j_split_cap][3][n]
     int j_split_cap = 0;

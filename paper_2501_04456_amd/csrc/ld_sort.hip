@@ -119,6 +119,20 @@ __global__ __launch_bounds__(256) void k_permute4(const unsigned long long* __re
     if (s < n) b[s] = a[(int)(unsigned)keys[s]];
 }
 
+__global__ __launch_bounds__(256) void k_permute_all(
+    const unsigned long long* __restrict__ keys, int n, const float4* __restrict__ pos,
+    const float4* __restrict__ lo, const int* __restrict__ typ, const int* __restrict__ oid,
+    float4* __restrict__ pos2, float4* __restrict__ lo2, int* __restrict__ typ2,
+    int* __restrict__ oid2) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const int src = (int)(unsigned)keys[s];
+    pos2[s] = pos[src];
+    lo2[s] = lo[src];
+    typ2[s] = typ[src];
+    oid2[s] = oid[src];
+}
+
 __global__ __launch_bounds__(256) void k_permute1(const unsigned long long* __restrict__ keys,
                                                   int n, const int* __restrict__ a,
                                                   int* __restrict__ b) {
@@ -128,9 +142,9 @@ __global__ __launch_bounds__(256) void k_permute1(const unsigned long long* __re
 
 // ---- radix sort of keys by their high word ---------------------------------
 
-constexpr int kRT = 256;                   // threads of the histogram and scatter kernels
-constexpr int kRRounds = 16;               // 256-key rounds per tile
-constexpr int kRTile = kRT * kRRounds;     // keys per workgroup tile
+constexpr int kRT = kRadixThreads;         // threads of the histogram and scatter kernels
+constexpr int kRRounds = kRadixRounds;     // 256-key rounds per tile
+constexpr int kRTile = kRadixTile;         // keys per workgroup tile
 
 // Digit counts of one tile: hist[digit * nwg + tile].
 __global__ __launch_bounds__(kRT) void k_radix_hist(const unsigned long long* __restrict__ in,
@@ -288,13 +302,14 @@ hipError_t launch_sort_by_keys(float4* pos, float4* lo, int* typ, int* oid, int 
 int radix_tiles(int n) { return (n + kRTile - 1) / kRTile; }
 
 hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tmp, int n, int bits,
-                                unsigned* hist, hipStream_t s) {
+                                unsigned* hist, hipStream_t s, bool first_counted) {
     if (n <= 0) return hipSuccess;
     const int nwg = radix_tiles(n);
     unsigned long long* src = keys;
     unsigned long long* dst = tmp;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nwg), dim3(kRT), 0, s, src, n, shift, hist, nwg);
+        if (shift > 0 || !first_counted)
+            hipLaunchKernelGGL(k_radix_hist, dim3(nwg), dim3(kRT), 0, s, src, n, shift, hist, nwg);
         hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, hist, 256 * nwg);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nwg), dim3(kRT), 0, s, src, dst, n, shift, hist,
                            nwg);
@@ -310,13 +325,13 @@ hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tm
     return hipGetLastError();
 }
 
-hipError_t launch_sort_small_keys(float4* pos, float4* lo, int* typ, int* oid, int n, int bits,
-                                  const SortBuffers& B, hipStream_t s) {
-    if (!B.hist) return hipErrorInvalidValue;
-    hipError_t e = launch_radix_by_high(B.keys, reinterpret_cast<unsigned long long*>(B.tmp4), n,
-                                        bits, B.hist, s);
-    if (e != hipSuccess) return e;
-    return permute_slots(pos, lo, typ, oid, n, B, s);
+hipError_t permute_slots_into(const unsigned long long* keys, int n, const float4* pos,
+                              const float4* lo, const int* typ, const int* oid, float4* pos2,
+                              float4* lo2, int* typ2, int* oid2, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_all, dim3((n + 255) / 256), dim3(256), 0, s, keys, n, pos, lo,
+                       typ, oid, pos2, lo2, typ2, oid2);
+    return hipGetLastError();
 }
 
 }  // namespace ld
