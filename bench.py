@@ -365,6 +365,10 @@ def main():
             "charged_pairs_per_launch": eval_pairs,
             "avg_launch_ms": avg_pair_ms,
             "launches": launches,
+            # the all-ordered-pairs count: 19 FLOPs x N(N-1) per launch (pairs
+            # with an uncharged particle have no Coulomb term and are skipped)
+            "frac_all_ordered_pairs": (19.0 * pairs / (avg_pair_ms * 1e-3) / 1e12
+                                       / PEAK_FP32_TFLOPS) if avg_pair_ms else None,
         },
     }
     if a.graph:

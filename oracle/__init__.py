@@ -26,7 +26,7 @@ CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-s
 
 def build(verbose: bool = False) -> str:
     """Compile ldo.c into libldo.so with gcc (generic x86-64, no fast-math)."""
-    srcs = [os.path.join(_HERE, f) for f in ("ldo.c", "ldo_ff.c")]
+    srcs = [os.path.join(_HERE, f) for f in ("ldo.c", "ldo_ff.c", "ldo_paper.c")]
     srcs = [s for s in srcs if os.path.exists(s)]
     cmd = ["gcc", *CFLAGS, "-o", _LIB_PATH, *srcs, "-lm"]
     if verbose:
@@ -47,6 +47,11 @@ class _Params(C.Structure):
         ("rotation", C.c_int32), ("wall_band", C.c_int32), ("noise", C.c_int32),
         ("reserved", C.c_int32), ("jump_max", C.c_double),
     ]
+
+
+class _Paper(C.Structure):
+    _fields_ = [("range_factor", C.c_double), ("kick", C.c_double),
+                ("inertial_mass", C.c_double * MAX_TYPES)]
 
 
 class _Radius(C.Structure):
@@ -108,6 +113,13 @@ def lib():
         L.ldo_mlp_backward.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp,
                                        dp, dp, dp, C.c_int, dp, dp, dp, dp, dp, dp]
         L.ldo_mlp_backward.restype = C.c_double
+        L.ldo_paper_forces.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp,
+                                       C.POINTER(_Params), C.POINTER(_Paper), dp, dp]
+        L.ldo_paper_run.argtypes = [C.c_int64, dp, dp, C.POINTER(C.c_int32), dp,
+                                    C.POINTER(C.c_int64), C.POINTER(_Params), C.POINTER(_Paper),
+                                    C.POINTER(_Radius), C.c_double, C.c_int64, C.c_uint64,
+                                    C.POINTER(C.c_int64), dp]
+        L.ldo_paper_run.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -403,3 +415,58 @@ def mlp_backward(X, T, W, bf16_mode: bool = False):
                                   1 if bf16_mode else 0,
                                   *[_dp(g[k]) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
     return loss, g
+
+
+# ---------------------------------------------------------------------------
+# The paper's own scheme (section 2.2 steps (i)-(vi) read literally)
+# ---------------------------------------------------------------------------
+
+def make_paper(range_factor: float, kick: float, inertial_mass) -> _Paper:
+    s = _Paper()
+    s.range_factor = float(range_factor)
+    s.kick = float(kick)
+    for t, m in enumerate(inertial_mass):
+        s.inertial_mass[t] = float(m)
+    return s
+
+
+def paper_forces(pos, type_, charge, params, range_factor: float):
+    """Pair forces truncated at range_factor (r_i + r_j), r = sigma/2 (section
+    2.2 steps (i)-(ii)): returns (F [n,3], S [n])."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    type_ = np.ascontiguousarray(type_, dtype=np.int32)
+    q = np.ascontiguousarray(charge, dtype=np.float64)
+    n = len(type_)
+    F = np.zeros((n, 3))
+    S = np.zeros(n)
+    m = make_paper(range_factor, 0.0, [1.0] * MAX_TYPES)
+    lib().ldo_paper_forces(n, _dp(pos), _ip(type_), _dp(q), C.byref(make_params(params)),
+                           C.byref(m), _dp(F), _dp(S))
+    return F, S
+
+
+class PaperState:
+    """Oracle state of the paper's scheme: FP64 positions and velocities."""
+
+    def __init__(self, w, range_factor: float, kick: float, inertial_mass, pos=None, vel=None):
+        self.w = w
+        self.x = np.array(w.pos if pos is None else pos, dtype=np.float64).reshape(-1, 3).copy()
+        self.v = (np.zeros_like(self.x) if vel is None
+                  else np.array(vel, dtype=np.float64).reshape(-1, 3).copy())
+        self.type = np.ascontiguousarray(w.type, dtype=np.int32)
+        self.q = np.ascontiguousarray(w.charge, dtype=np.float64)
+        self.m = make_paper(range_factor, kick, inertial_mass)
+        self.step = 0
+        self.t = 0.0
+
+    def run(self, n_steps: int, dt: float = None) -> int:
+        """Steps (iii)-(vi): Newton + Stokes drag, velocity kick, x += dt v."""
+        dt = self.w.dt if dt is None else dt
+        st = C.c_int64(self.step)
+        tt = C.c_double(self.t)
+        bad = lib().ldo_paper_run(len(self.type), _dp(self.x), _dp(self.v), _ip(self.type),
+                                  _dp(self.q), None, C.byref(make_params(self.w.params)),
+                                  C.byref(self.m), C.byref(make_radius(self.w.radius)), dt,
+                                  n_steps, self.w.seed, C.byref(st), C.byref(tt))
+        self.step, self.t = st.value, tt.value
+        return bad

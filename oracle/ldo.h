@@ -110,6 +110,36 @@ int64_t ldo_run(int64_t n, double* x, const int32_t* type, const double* q,
                 const int64_t* ids, const ldo_params* p, const ldo_radius* R,
                 double dt, int64_t n_steps, uint64_t seed, int64_t* step, double* t);
 
+/* The paper's own scheme (section 2.2 steps (i)-(vi) read literally):
+ * pairs interact when closer than range_factor (r_i + r_j), r = sigma / 2,
+ * LJ and Coulomb both truncated there without shift; Newton's equation with
+ * Stokes drag and a random velocity vector of fixed magnitude `kick` in a
+ * uniformly random direction. */
+typedef struct {
+    double range_factor;                 /* 4 in the paper */
+    double kick;                         /* |random velocity| added per step */
+    double inertial_mass[LDO_MAX_TYPES]; /* mass in Newton's equation per type */
+} ldo_paper;
+
+/* Truncated pair forces F [n*3] and S [n] = sum_j |f_LJ| + |f_C| of the pairs
+ * in range (either may be NULL).  Pinned against ldo_pair_forces where the two
+ * definitions coincide, by Newton's third law and by truncation invariance. */
+void ldo_paper_forces(int64_t n, const double* pos, const int32_t* type, const double* q,
+                      const ldo_params* p, const ldo_paper* m, double* F, double* S);
+
+/* Steps of the paper's scheme; x and v [n*3] FP64 updated in place:
+ *   v <- v + dt (F_pair + F_ext(R(t + dt)) - gamma v) / m;  v <- v + kick u;
+ *   x <- x + dt v,
+ * u = the normalised ldo_gauss3 triple (tag 0) of particle ids[i] (NULL: i).
+ * Returns the first step whose move was non-finite or beyond jump_max, or
+ * -1.  Pinned by the drag decay and terminal velocity (closed forms), the
+ * damped harmonic trap (the scheme's 2x2 linear map raised to the n-th power)
+ * and the kick's magnitude and isotropy. */
+int64_t ldo_paper_run(int64_t n, double* x, double* v, const int32_t* type, const double* q,
+                      const int64_t* ids, const ldo_params* p, const ldo_paper* m,
+                      const ldo_radius* R, double dt, int64_t n_steps, uint64_t seed,
+                      int64_t* step, double* t);
+
 /* One step for the listed rows only (pair forces from all n particles at the
  * current positions); writes the rows' new positions, leaves x unchanged.
  * Returns step if a listed row blew up, else -1.  Same formulas as ldo_run,
