@@ -415,6 +415,48 @@ ld_status ld_ens_sync(ld_ens* e);
 ld_status ld_ens_kernel_timing(ld_ens* e, int32_t enable);
 ld_status ld_ens_kernel_time(ld_ens* e, int64_t* launches, double* total_ms);
 
+/* ---------------------------------------------------------------------- */
+/* The paper's own scheme (section 2.2 steps (i)-(vi) read literally)      */
+/* ---------------------------------------------------------------------- */
+
+/* Pairs interact when closer than range_factor (r_i + r_j), r = sigma / 2
+ * (step (i): the paper uses 4); LJ and Coulomb are both truncated there
+ * without shift (step (ii)).  Each ld_step of the context then does: slots
+ * sorted by cells of side >= the largest range (step (i)); the truncated pair
+ * forces over the 27 neighbouring cells, FP64 (step (ii)); R(t + dt) (step
+ * (iii)); surface spring, gravity and centrifugal force of ld_params
+ * (steps (iv)-(v); wall_band = 1 with wall_offset = sigma/2 is the paper's
+ * spring acting within one radius of the surface); then Newton's equation
+ * with Stokes drag and the random velocity vector (step (vi)):
+ *   v <- v + dt (F_pair + F_ext - gamma v) / inertial_mass,
+ *   v <- v + kick u,   u = the normalised Box-Muller triple of the ld_init
+ *                      noise stream (uniform on the unit sphere),
+ *   x <- x + dt v.
+ * ld_params.noise is not used (kT still scales Coulomb through l_B).
+ * Velocities are FP64, kept in slot order on the device. */
+typedef struct {
+    double range_factor;                 /* > 0 (the paper: 4) */
+    double kick;                         /* >= 0: magnitude of the random velocity */
+    double inertial_mass[LD_MAX_TYPES];  /* > 0 for every type in use */
+} ld_paper_config;
+
+/* Switch ld_step to the paper's scheme, velocities zero.  Graph replay is off
+ * meanwhile and checkpoints are refused (they hold no velocities).
+ * Errors: LD_EINVAL (cfg), LD_ESTATE (learned far field on), LD_ENOMEM. */
+ld_status ld_paper_enable(ld_ctx* ctx, const ld_paper_config* cfg);
+
+/* Back to the overdamped scheme (velocities dropped).  NULL-safe context. */
+ld_status ld_paper_disable(ld_ctx* ctx);
+
+/* Truncated pair forces F [n*3] FP64 (original order) at the current
+ * positions (re-sorts the slots by cell).  Errors: LD_EINVAL, LD_ESTATE. */
+ld_status ld_paper_forces(ld_ctx* ctx, double* F);
+
+/* Velocities v [n*3] FP64 in original order (host or device pointers).
+ * set: every value must be finite.  Errors: LD_EINVAL, LD_ESTATE. */
+ld_status ld_paper_get_velocities(ld_ctx* ctx, double* v);
+ld_status ld_paper_set_velocities(ld_ctx* ctx, const double* v);
+
 #ifdef __cplusplus
 }
 #endif

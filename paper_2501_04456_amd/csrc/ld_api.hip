@@ -250,6 +250,7 @@ ld::StepLaunch step_launch(ld_ctx* c, double dt) {
 
 // One step (re-sorting first when due) on stream s.
 ld_status enqueue_step(ld_ctx* c, double dt, hipStream_t s, bool timed) {
+    if (c->pm) return ld::pm_step(c, dt, s);   // the paper's scheme sorts by cell itself
     if (c->tune.sort_every > 0 && c->steps_since_sort >= c->tune.sort_every) {
         ld_status st = run_sort(c, s);
         if (st != LD_OK) return st;
@@ -325,6 +326,7 @@ ld_status take_pending_error(ld_ctx* c) {
 }
 
 void free_all(ld_ctx* c) {
+    ld::pm_free(c);
     void* bufs[] = {c->pos,     c->lo,     c->typ,         c->oid,       c->box,  c->aux,
                     c->Fpart,   c->S_slot, c->U_slot,      c->work,      c->st,
                     c->sb.keys, c->sb.tmp4, c->sb.tmp_i,   c->sb.bounds, c->sb.bounds_part,
@@ -494,7 +496,7 @@ ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LD_EINVAL, "dt=%g must be positive", dt);
     if (n_steps < 0) return fail(LD_EINVAL, "n_steps must be >= 0");
     int64_t left = n_steps;
-    const bool use_graph = c->tune.graph_steps > 0 && !c->timing && !ld::ff_active(c);
+    const bool use_graph = c->tune.graph_steps > 0 && !c->timing && !ld::ff_active(c) && !c->pm;
     const int len = c->tune.sort_every > 0 ? c->tune.sort_every : c->tune.graph_steps;
     while (left > 0) {
         // A captured chunk starts with a re-sort when sorting is on, so it is
@@ -816,6 +818,7 @@ constexpr char kMagic[8] = {'L', 'D', 'R', 'O', 'P', 'C', 'K', '1'};
 ld_status ld_checkpoint_save(ld_ctx* c, const char* path) {
     g_err.clear();
     if (!c || !path) return fail(LD_EINVAL, "ctx and path are required");
+    if (c->pm) return fail(LD_ESTATE, "checkpoints hold no velocities (ld_paper_disable first)");
     const size_t N = (size_t)c->n;
     std::vector<float4> h(N), l(N);
     std::vector<int> ty(N), ids(N);

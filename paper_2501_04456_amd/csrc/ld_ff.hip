@@ -2031,6 +2031,7 @@ extern "C" {
 ld_status ld_ff_enable(ld_ctx* c, const ld_ff_config* cfg) {
     g_err.clear();
     if (!c || !cfg) return fail(LD_EINVAL, "ctx and cfg are required");
+    if (c->pm) return fail(LD_ESTATE, "the paper's scheme is enabled (ld_paper_disable first)");
     if (!(cfg->near_cut > 0.0)) return fail(LD_EINVAL, "near_cut must be positive");
     if (cfg->grid < 4 || cfg->grid > 64) return fail(LD_EINVAL, "grid must be in [4, 64]");
     if (cfg->block < 1 || cfg->block > 7 || cfg->block % 2 == 0)
@@ -2129,6 +2130,7 @@ ld_status ld_ff_mode(ld_ctx* c, int32_t mode) {
     if (!c) return fail(LD_EINVAL, "ctx is NULL");
     if (mode < 0 || mode > 2) return fail(LD_EINVAL, "mode must be 0, 1 or 2");
     if (mode != 0 && !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    if (mode != 0 && c->pm) return fail(LD_ESTATE, "the paper's scheme is enabled");
     if (c->ff) {
         c->ff->mode = mode;
         c->ff->window_steps = 0;

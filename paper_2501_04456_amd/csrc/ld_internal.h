@@ -231,6 +231,7 @@ hipError_t launch_boxcount(const float4* pos, const float4* lo, int n, const dou
                            unsigned long long* count, hipStream_t s);
 
 struct FarField;
+struct PaperMode;
 
 }  // namespace ld
 
@@ -280,6 +281,8 @@ struct ld_ctx {
 
     // learned far field (null until ld_ff_enable)
     ld::FarField* ff = nullptr;
+    // the paper's own scheme (null until ld_paper_enable)
+    ld::PaperMode* pm = nullptr;
 };
 
 namespace ld {
@@ -289,4 +292,7 @@ bool ff_active(const ld_ctx* c);
 // Pair forces of one step into Fpart: the learned path (one partial) or the
 // direct path; *j_split_used says how many partials the update must sum.
 ld_status ff_step_forces(ld_ctx* c, hipStream_t s, int* j_split_used);
+// The paper's own scheme (defined in ld_paper.hip): one step, and release.
+ld_status pm_step(ld_ctx* c, double dt, hipStream_t s);
+void pm_free(ld_ctx* c);
 }  // namespace ld

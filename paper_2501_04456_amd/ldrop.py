@@ -82,6 +82,11 @@ class ld_ff_train_report(C.Structure):
                 ("val_rel_rms_raw", C.c_double)]
 
 
+class ld_paper_config(C.Structure):
+    _fields_ = [("range_factor", C.c_double), ("kick", C.c_double),
+                ("inertial_mass", C.c_double * MAX_TYPES)]
+
+
 FF_DEFAULT = dict(near_cut=8.0, grid=32, block=5, hidden=128, judge_every=500, judge_tol=1e-3,
                   near_mode=0, parent_reach=0)
 NEAR_RADIAL, NEAR_BLOCK = 0, 1
@@ -98,6 +103,8 @@ SYMBOLS = [
     "ld_ens_init", "ld_ens_destroy", "ld_ens_set_tuning", "ld_ens_step", "ld_ens_forces",
     "ld_ens_get_positions", "ld_ens_get_state", "ld_ens_sync", "ld_ens_kernel_timing",
     "ld_ens_kernel_time",
+    "ld_paper_enable", "ld_paper_disable", "ld_paper_forces", "ld_paper_get_velocities",
+    "ld_paper_set_velocities",
 ]
 
 _lib = None
@@ -161,6 +168,11 @@ def lib():
         L.ld_ff_train.argtypes = [vp, C.POINTER(ld_ff_train_cfg), C.POINTER(ld_ff_train_report)]
         L.ld_ff_judge.argtypes = [vp, C.POINTER(C.c_double)]
         L.ld_ff_stats.argtypes = [vp, vp, C.POINTER(C.c_double)]
+        L.ld_paper_enable.argtypes = [vp, C.POINTER(ld_paper_config)]
+        L.ld_paper_disable.argtypes = [vp]
+        L.ld_paper_forces.argtypes = [vp, dp]
+        L.ld_paper_get_velocities.argtypes = [vp, dp]
+        L.ld_paper_set_velocities.argtypes = [vp, dp]
         for name in SYMBOLS:
             if name not in ("ld_destroy", "ld_last_error", "ld_ens_destroy",
                             "ld_ff_weights_size"):
@@ -322,6 +334,36 @@ class System:
         lo = None if x_lo is None else np.ascontiguousarray(x_lo, np.float32).reshape(self.n, 3)
         _check(lib().ld_set_positions(self.h, hi.ctypes.data_as(C.c_void_p),
                                       None if lo is None else lo.ctypes.data_as(C.c_void_p)))
+
+    # -- the paper's own scheme ------------------------------------------
+    def paper_enable(self, range_factor: float = 4.0, kick: float = 0.0, inertial_mass=None):
+        """Switch ld_step to the paper's scheme (pairs truncated at
+        range_factor (r_i + r_j); Newton + Stokes drag; random velocity kick).
+        inertial_mass per type (default: the parameters' mass)."""
+        c = ld_paper_config()
+        c.range_factor = float(range_factor)
+        c.kick = float(kick)
+        m = self.params.mass if inertial_mass is None else inertial_mass
+        for t, v in enumerate(m):
+            c.inertial_mass[t] = float(v)
+        _check(lib().ld_paper_enable(self.h, C.byref(c)))
+
+    def paper_disable(self):
+        _check(lib().ld_paper_disable(self.h))
+
+    def paper_forces(self) -> np.ndarray:
+        F = np.zeros((self.n, 3))
+        _check(lib().ld_paper_forces(self.h, F.ctypes.data_as(C.c_void_p)))
+        return F
+
+    def velocities(self) -> np.ndarray:
+        v = np.zeros((self.n, 3))
+        _check(lib().ld_paper_get_velocities(self.h, v.ctypes.data_as(C.c_void_p)))
+        return v
+
+    def set_velocities(self, v):
+        v = np.ascontiguousarray(v, np.float64).reshape(self.n, 3)
+        _check(lib().ld_paper_set_velocities(self.h, v.ctypes.data_as(C.c_void_p)))
 
     def state(self):
         s, t, R = C.c_int64(), C.c_double(), C.c_double()

@@ -45,7 +45,8 @@ def test_struct_layouts_match_header():
     for cname, py in (("ld_params", ldrop.ld_params), ("ld_radius", ldrop.ld_radius),
                       ("ld_tuning", ldrop.ld_tuning), ("ld_ff_config", ldrop.ld_ff_config),
                       ("ld_ff_train_cfg", ldrop.ld_ff_train_cfg),
-                      ("ld_ff_train_report", ldrop.ld_ff_train_report)):
+                      ("ld_ff_train_report", ldrop.ld_ff_train_report),
+                      ("ld_paper_config", ldrop.ld_paper_config)):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", txt).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = []
@@ -60,6 +61,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(ldrop.ld_params) == 8 + 6 * 8 * 8 + 64 * 8 + 4 * 8 + 3 * 8 + 8 + 16 + 8
     assert C.sizeof(ldrop.ld_radius) == 48
     assert C.sizeof(ldrop.ld_ff_config) == 40
+    assert C.sizeof(ldrop.ld_paper_config) == 16 + 8 * 8
 
 
 def test_no_torch_in_signatures():
