@@ -42,8 +42,11 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="large",
-                    choices=["large", "ensemble", "small", "learned"],
-                    help="large (default, the headline) / ensemble / small / learned")
+                    choices=["large", "ensemble", "small", "learned", "paper"],
+                    help="large (default, the headline) / ensemble / small / learned / "
+                         "paper (the paper's own truncated-range inertial scheme)")
+    ap.add_argument("--kick", type=float, default=0.05,
+                    help="paper: magnitude of the random velocity vector per step")
     ap.add_argument("--snapshots", type=int, default=8,
                     help="learned: training snapshots (N samples each)")
     ap.add_argument("--snap-every", type=int, default=100,
@@ -121,6 +124,43 @@ def cpu_baseline(w, target_s: float):
         "sample": f"pair forces of {m} random rows x all {w.n} particles "
                   f"({el:.1f} s), scaled by N/rows to one step",
     }
+
+
+def bench_paper(a, torch, ldrop, W):
+    """The paper's own scheme (section 2.2 steps (i)-(vi) read literally) on
+    the headline droplet: pairs truncated at 4 (r_i + r_j) over a cell list,
+    Newton + Stokes drag, fixed-magnitude random velocity kick, spring acting
+    within one radius of the surface."""
+    w = W.config_large(n=a.n)
+    p = w.params
+    p.wall_band = 1
+    p.wall_offset = [0.5 * sg for sg in p.sigma]
+    s = ldrop.System.from_workload(w)
+    s.paper_enable(range_factor=4.0, kick=a.kick, inertial_mass=p.mass)
+    s.step(a.warmup, w.dt)
+    s.sync()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    s.step(a.steps, w.dt)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.sync()
+    ms = ev0.elapsed_time(ev1)
+    print(json.dumps({
+        "metric": "paper scheme steps/s at N=2.5e5 (truncated range, inertial)",
+        "value": a.steps * 1e3 / ms, "unit": "steps/s",
+        "particle_steps_per_s": w.n * a.steps * 1e3 / ms,
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps,
+        "wall_s": wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 pair math and velocities", "data": "synthetic",
+        "config": {"workload": "paper: N=250000 three-type droplet, LJ + Coulomb truncated at "
+                               "4 (r_i + r_j), band spring, Newton + Stokes drag, velocity kick",
+                   "n": w.n, "dt": w.dt, "kick": a.kick, "range_factor": 4.0},
+    }), flush=True)
 
 
 def bench_ensemble(a, torch, ldrop, W):
@@ -287,6 +327,8 @@ def main():
         return bench_ensemble(a, torch, ldrop, W)
     if a.workload == "learned":
         return bench_learned(a, torch, ldrop, W)
+    if a.workload == "paper":
+        return bench_paper(a, torch, ldrop, W)
     w = W.config_large(n=a.n) if a.workload == "large" else W.config_small()
     s = ldrop.System.from_workload(w)
     if a.autotune:

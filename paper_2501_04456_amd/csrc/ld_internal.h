@@ -212,8 +212,11 @@ int radix_tiles(int n);
 // Stable sort of keys[0, n) by the high word, which is below 2^bits (LSD
 // radix, 8-bit digits; tmp holds n keys, hist 256 * radix_tiles(n)).
 // first_counted: hist already holds the first pass's digit counts.
+// sorted: if given, receives the buffer holding the result (keys or tmp);
+// otherwise the result is copied into keys.
 hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tmp, int n, int bits,
-                                unsigned* hist, hipStream_t s, bool first_counted = false);
+                                unsigned* hist, hipStream_t s, bool first_counted = false,
+                                unsigned long long** sorted = nullptr);
 
 // dst arrays[s] = src arrays[low word of keys[s]] for s < n, one launch.
 hipError_t permute_slots_into(const unsigned long long* keys, int n, const float4* pos,

@@ -314,16 +314,17 @@ ld_status pm_forces(ld_ctx* c, hipStream_t s) {
               m->tab.rmax, m->grid, c->sb.keys, c->sb.hist, nwg);
     int bits = 1;
     while ((1 << bits) < kNC) ++bits;
+    unsigned long long* keys = nullptr;    // the buffer the sorted keys end in
     HIP_TRY(launch_radix_by_high(c->sb.keys, reinterpret_cast<unsigned long long*>(c->sb.tmp4),
-                                 n, bits, c->sb.hist, s, true));
+                                 n, bits, c->sb.hist, s, true, &keys));
     if (!c->pos2) {
         if (!(pm_alloc(&c->pos2, (size_t)n) && pm_alloc(&c->lo2, (size_t)n) &&
               pm_alloc(&c->typ2, (size_t)n) && pm_alloc(&c->oid2, (size_t)n)))
             return fail(LD_ENOMEM, "cannot allocate the second slot arrays");
     }
-    HIP_TRY(permute_slots_into(c->sb.keys, n, c->pos, c->lo, c->typ, c->oid, c->pos2, c->lo2,
+    HIP_TRY(permute_slots_into(keys, n, c->pos, c->lo, c->typ, c->oid, c->pos2, c->lo2,
                                c->typ2, c->oid2, s));
-    PM_LAUNCH(k_pm_permute_v, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, m->v, m->v2);
+    PM_LAUNCH(k_pm_permute_v, dim3((n + kB - 1) / kB), dim3(kB), s, keys, n, m->v, m->v2);
     std::swap(c->pos, c->pos2);
     std::swap(c->lo, c->lo2);
     std::swap(c->typ, c->typ2);
@@ -332,10 +333,9 @@ ld_status pm_forces(ld_ctx* c, hipStream_t s) {
     c->graph_len = -1;                 // a captured graph holds the old addresses
     PM_LAUNCH(k_pm_zero, dim3((kNC + kB - 1) / kB), dim3(kB), s, m->cstart, kNC);
     PM_LAUNCH(k_pm_zero, dim3((kNC + kB - 1) / kB), dim3(kB), s, m->cend, kNC);
-    PM_LAUNCH(k_pm_ranges, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, m->cstart,
-              m->cend);
-    PM_LAUNCH(k_pm_forces, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, c->typ,
-              c->sb.keys, m->grid, m->cstart, m->cend, n, m->tab, m->F);
+    PM_LAUNCH(k_pm_ranges, dim3((n + kB - 1) / kB), dim3(kB), s, keys, n, m->cstart, m->cend);
+    PM_LAUNCH(k_pm_forces, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, c->typ, keys,
+              m->grid, m->cstart, m->cend, n, m->tab, m->F);
     c->steps_since_sort = 0;
     return LD_OK;
 }

@@ -161,20 +161,31 @@ __global__ __launch_bounds__(kRT) void k_radix_hist(const unsigned long long* __
     hist[(size_t)t * nwg + blockIdx.x] = h[t];
 }
 
-// In-place exclusive scan of m counters by one workgroup of 1024, four
-// consecutive counters per thread and pass.
+// In-place exclusive scan of m counters by one workgroup of 1024: each
+// thread takes 16 consecutive counters per pass (four 16-byte loads), so the
+// 256 x tiles counters of a 250 000-key sort take one pass.
 __global__ __launch_bounds__(1024) void k_radix_scan(unsigned* a, int m) {
     __shared__ unsigned wsum[16];
     const int t = threadIdx.x, lane = t % 64, wv = t / 64;
     unsigned carry = 0u;
-    for (int base = 0; base < m; base += 4 * 1024) {
-        unsigned v[4], sum = 0u;
+    for (int base = 0; base < m; base += 16 * 1024) {
+        const int e0 = base + 16 * t;
+        unsigned v[16], sum = 0u;
+        if (e0 + 16 <= m) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = base + 4 * t + i;
-            v[i] = e < m ? a[e] : 0u;
-            sum += v[i];
+            for (int q = 0; q < 4; ++q) {
+                const uint4 x = *reinterpret_cast<const uint4*>(a + e0 + 4 * q);
+                v[4 * q] = x.x;
+                v[4 * q + 1] = x.y;
+                v[4 * q + 2] = x.z;
+                v[4 * q + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = e0 + i < m ? a[e0 + i] : 0u;
         }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sum += v[i];
         unsigned x = sum;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -190,11 +201,22 @@ __global__ __launch_bounds__(1024) void k_radix_scan(unsigned* a, int m) {
             total += ws;
         }
         unsigned run = carry + before + x - sum;
+        if (e0 + 16 <= m) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = base + 4 * t + i;
-            if (e < m) a[e] = run;
-            run += v[i];
+            for (int q = 0; q < 4; ++q) {
+                uint4 o;
+                o.x = run; run += v[4 * q];
+                o.y = run; run += v[4 * q + 1];
+                o.z = run; run += v[4 * q + 2];
+                o.w = run; run += v[4 * q + 3];
+                *reinterpret_cast<uint4*>(a + e0 + 4 * q) = o;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if (e0 + i < m) a[e0 + i] = run;
+                run += v[i];
+            }
         }
         carry += total;
         __syncthreads();                               // wsum is reused by the next pass
@@ -302,7 +324,9 @@ hipError_t launch_sort_by_keys(float4* pos, float4* lo, int* typ, int* oid, int 
 int radix_tiles(int n) { return (n + kRTile - 1) / kRTile; }
 
 hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tmp, int n, int bits,
-                                unsigned* hist, hipStream_t s, bool first_counted) {
+                                unsigned* hist, hipStream_t s, bool first_counted,
+                                unsigned long long** sorted) {
+    if (sorted) *sorted = keys;
     if (n <= 0) return hipSuccess;
     const int nwg = radix_tiles(n);
     unsigned long long* src = keys;
@@ -317,7 +341,9 @@ hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tm
         src = dst;
         dst = x;
     }
-    if (src != keys) {
+    if (sorted) {
+        *sorted = src;                 // no copy: the caller reads the sorted keys there
+    } else if (src != keys) {
         const hipError_t e = hipMemcpyAsync(keys, src, sizeof(unsigned long long) * n,
                                             hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
