@@ -26,7 +26,7 @@ CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-s
 
 def build(verbose: bool = False) -> str:
     """Compile ldo.c into libldo.so with gcc (generic x86-64, no fast-math)."""
-    srcs = [os.path.join(_HERE, f) for f in ("ldo.c", "ldo_ff.c", "ldo_paper.c")]
+    srcs = [os.path.join(_HERE, f) for f in ("ldo.c", "ldo_ff.c", "ldo_paper.c", "ldo_agg.c")]
     srcs = [s for s in srcs if os.path.exists(s)]
     cmd = ["gcc", *CFLAGS, "-o", _LIB_PATH, *srcs, "-lm"]
     if verbose:
@@ -120,6 +120,11 @@ def lib():
                                     C.POINTER(_Radius), C.c_double, C.c_int64, C.c_uint64,
                                     C.POINTER(C.c_int64), dp]
         L.ldo_paper_run.restype = C.c_int64
+        L.ldo_components.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), C.POINTER(_Params),
+                                     C.c_double, C.POINTER(C.c_int64)]
+        L.ldo_components.restype = C.c_int64
+        L.ldo_surface_count.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), C.POINTER(_Params),
+                                        C.c_double, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -470,3 +475,28 @@ class PaperState:
                                   n_steps, self.w.seed, C.byref(st), C.byref(tt))
         self.step, self.t = st.value, tt.value
         return bad
+
+
+# ---------------------------------------------------------------------------
+# Aggregate statistics (section 2.1: number of sub-aggregates; section 1: N_surf)
+# ---------------------------------------------------------------------------
+
+def components(x, type_, params, contact_factor: float = 1.1):
+    """Connected components of the contact graph (r < contact_factor
+    sigma_ij): returns (count, labels = smallest index of each component)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    type_ = np.ascontiguousarray(type_, dtype=np.int32)
+    labels = np.zeros(len(type_), np.int64)
+    n = lib().ldo_components(len(type_), _dp(x), _ip(type_), C.byref(make_params(params)),
+                             contact_factor, _lp(labels))
+    return n, labels
+
+
+def surface_count(x, type_, params, R: float) -> np.ndarray:
+    """N_surf per type: NPs with | |x| - R | < sigma_t / 2."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    type_ = np.ascontiguousarray(type_, dtype=np.int32)
+    counts = np.zeros(len(params.sigma), np.int64)
+    lib().ldo_surface_count(len(type_), _dp(x), _ip(type_), C.byref(make_params(params)), R,
+                            _lp(counts))
+    return counts

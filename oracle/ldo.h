@@ -140,6 +140,20 @@ int64_t ldo_paper_run(int64_t n, double* x, double* v, const int32_t* type, cons
                       const ldo_radius* R, double dt, int64_t n_steps, uint64_t seed,
                       int64_t* step, double* t);
 
+/* Sub-aggregates (section 2.1 names their number among the post-processing
+ * outputs): connected components of the contact graph, a pair in contact
+ * when r < contact_factor sigma_ij.  labels[i] (may be NULL) = the smallest
+ * index in i's component.  Returns the number of components.  Pinned
+ * against scipy's kd-tree pairs + connected components and hand-built
+ * chains. */
+int64_t ldo_components(int64_t n, const double* x, const int32_t* type, const ldo_params* p,
+                       double contact_factor, int64_t* labels);
+
+/* N_surf (section 1): NPs with | |x| - R | < sigma_t / 2, per type into
+ * counts[n_types].  Pinned by constructed shells. */
+void ldo_surface_count(int64_t n, const double* x, const int32_t* type, const ldo_params* p,
+                       double R, int64_t* counts);
+
 /* One step for the listed rows only (pair forces from all n particles at the
  * current positions); writes the rows' new positions, leaves x unchanged.
  * Returns step if a listed row blew up, else -1.  Same formulas as ldo_run,
