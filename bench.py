@@ -42,9 +42,10 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="large",
-                    choices=["large", "ensemble", "small", "learned", "paper"],
+                    choices=["large", "ensemble", "small", "learned", "paper", "analysis"],
                     help="large (default, the headline) / ensemble / small / learned / "
-                         "paper (the paper's own truncated-range inertial scheme)")
+                         "paper (the paper's own truncated-range inertial scheme) / analysis "
+                         "(post-processing calls at N=2.5e5)")
     ap.add_argument("--kick", type=float, default=0.05,
                     help="paper: magnitude of the random velocity vector per step")
     ap.add_argument("--snapshots", type=int, default=8,
@@ -161,6 +162,47 @@ def bench_paper(a, torch, ldrop, W):
                                "4 (r_i + r_j), band spring, Newton + Stokes drag, velocity kick",
                    "n": w.n, "dt": w.dt, "kick": a.kick, "range_factor": 4.0},
     }), flush=True)
+
+
+def bench_analysis(a, torch, ldrop, W):
+    """Post-processing at N = 250000: RDF + C-bar (Eqs. 6, 8), box-counting
+    and radius-of-gyration fractal dimensions (Eqs. 2-4), sub-aggregates
+    (contact-graph components) and N_surf, on the headline droplet as
+    initialised (dispersed) and on a packed one (a jittered cubic lattice of
+    spacing 1.02 sigma: one giant component)."""
+    import numpy as np
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps, r
+
+    w = W.config_large(n=a.n)
+    s = ldrop.System.from_workload(w)
+    out = {}
+    out["rdf_ms"], _ = timed(lambda: s.rdf(10.0, 200))
+    out["fractal_ms"], _ = timed(lambda: s.fractal())
+    out["aggregates_dispersed_ms"], g = timed(lambda: s.aggregates(1.1))
+    out["aggregates_dispersed"] = g
+    out["surface_count_ms"], _ = timed(lambda: s.surface_count())
+    k = int(round(a.n ** (1.0 / 3.0))) + 1
+    rng = np.random.default_rng(7)
+    grid = np.stack(np.meshgrid(*[np.arange(k)] * 3, indexing="ij"), -1).reshape(-1, 3)[:a.n]
+    xp = (grid - k / 2) * 1.02 + rng.uniform(-0.01, 0.01, grid.shape)
+    wp = W.Workload("packed", a.n, np.zeros(a.n, np.int32), np.zeros(a.n),
+                    xp.astype(np.float32), W.config_small().params, w.radius, w.dt, 1, 1)
+    sp = ldrop.System.from_workload(wp)
+    out["aggregates_packed_ms"], g = timed(lambda: sp.aggregates(1.1))
+    out["aggregates_packed"] = g
+    print(json.dumps({
+        "metric": "post-processing call times at N=2.5e5", "value": out["aggregates_dispersed_ms"],
+        "unit": "ms (sub-aggregates, dispersed droplet)", "higher_is_better": False,
+        "n_gpus": 1, "data": "synthetic", "config": {"workload": "analysis", "n": a.n},
+        "times": out}), flush=True)
 
 
 def bench_ensemble(a, torch, ldrop, W):
@@ -329,6 +371,8 @@ def main():
         return bench_learned(a, torch, ldrop, W)
     if a.workload == "paper":
         return bench_paper(a, torch, ldrop, W)
+    if a.workload == "analysis":
+        return bench_analysis(a, torch, ldrop, W)
     w = W.config_large(n=a.n) if a.workload == "large" else W.config_small()
     s = ldrop.System.from_workload(w)
     if a.autotune:

@@ -415,6 +415,22 @@ ld_status ld_ens_sync(ld_ens* e);
 ld_status ld_ens_kernel_timing(ld_ens* e, int32_t enable);
 ld_status ld_ens_kernel_time(ld_ens* e, int64_t* launches, double* total_ms);
 
+/* Sub-aggregates (section 2.1 lists their number and aggregate statistics
+ * among the model's post-processing outputs): the connected components of
+ * the contact graph at the current positions, two NPs in contact when
+ * r < contact_factor sigma_ij (FP64 distances).  stats (host) receives
+ * [components, aggregates = components of >= 2 NPs, size of the largest];
+ * labels (optional, [n] int32, host or device, original order) the smallest
+ * original index of each NP's component, so the result is unique.  The
+ * slot order is not changed.  Errors: LD_EINVAL, LD_ENOMEM, LD_EHIP. */
+ld_status ld_aggregates(ld_ctx* ctx, double contact_factor, int64_t stats[3], int32_t* labels);
+
+/* N_surf (section 1: the number of NPs at the droplet surface): per type,
+ * the NPs with | |x| - R | < sigma_t / 2, into counts[n_types] (host).  R < 0
+ * means the droplet's radius at the current time.  Errors: LD_EINVAL,
+ * LD_ENOMEM, LD_EHIP. */
+ld_status ld_surface_count(ld_ctx* ctx, double R, int64_t* counts);
+
 /* ---------------------------------------------------------------------- */
 /* The paper's own scheme (section 2.2 steps (i)-(vi) read literally)      */
 /* ---------------------------------------------------------------------- */

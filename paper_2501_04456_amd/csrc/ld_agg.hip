@@ -1,0 +1,459 @@
+// Aggregate statistics the paper extracts in post-processing (section 2.1:
+// the number of sub-aggregates and aggregate statistics; section 1: N_surf,
+// the number of NPs at the droplet surface).
+//
+// Sub-aggregates are the connected components of the contact graph, a pair
+// in contact when r < contact_factor sigma_ij.  Candidates come from a cell
+// list (cells of side >= the largest contact distance, radix-sorted keys;
+// the context's slot order is left alone) and are united lock-free: a union
+// hangs the larger root under the smaller with a compare-and-swap, so parent
+// indices only decrease, no cycle can form and every component ends with
+// its smallest (cell-sorted) index as root.  The label reported is the
+// smallest original index of the component.  Every wait-free retry loop is
+// bounded; exceeding the bound raises an error flag instead of spinning.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "ld_host.h"
+
+namespace ld {
+
+using host::fail;
+
+namespace {
+
+constexpr int kB = 256;
+constexpr int kAMaxCells = 64;
+constexpr int kANC = kAMaxCells * kAMaxCells * kAMaxCells;
+constexpr int kAMaxIter = 1 << 16;      // bound of every retry loop
+
+struct AgGrid {
+    double L, hc;
+    int Gc, pad;
+};
+
+struct AgTable {
+    int T;
+    double rc2[kMaxTypes * kMaxTypes];  // (contact_factor sigma_ij)^2
+    double half_sigma[kMaxTypes];
+};
+
+__global__ __launch_bounds__(kB) void k_ag_absmax(const float4* __restrict__ pos, int n,
+                                                  float* part) {
+    __shared__ float red[kB];
+    float m = 0.f;
+    for (int s = blockIdx.x * kB + threadIdx.x; s < n; s += gridDim.x * kB) {
+        const float4 h = pos[s];
+        m = fmaxf(m, fmaxf(fabsf(h.x), fmaxf(fabsf(h.y), fabsf(h.z))));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kB / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__device__ __forceinline__ int ag_cell1(double x, double L, double h, int G) {
+    int c = (int)floor((x + L) / h);
+    return c < 0 ? 0 : (c > G - 1 ? G - 1 : c);
+}
+
+// Grid (block 0 stores it), cell keys (cell << 32 | slot) from the FP64
+// positions and the first radix pass's digit counts per 4096-slot tile.
+__global__ __launch_bounds__(kB) void k_ag_keys(const float4* __restrict__ pos,
+                                                const float4* __restrict__ lo, int n,
+                                                const float* __restrict__ part, double rc,
+                                                AgGrid* g, unsigned long long* keys,
+                                                unsigned* hist, int nwg) {
+    __shared__ AgGrid sg;
+    __shared__ unsigned h[256];
+    const int t = threadIdx.x;
+    h[t] = 0u;
+    if (t < 64) {
+        float m = part[t];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if (t == 0) {
+            m = fmaxf(m, 1e-3f);
+            const double L = (double)(m * 1.0009765625f);
+            int G = (int)floor(2.0 * L / rc);
+            G = G < 1 ? 1 : (G > kAMaxCells ? kAMaxCells : G);
+            sg.L = L;
+            sg.Gc = G;
+            sg.hc = 2.0 * L / G;
+            sg.pad = 0;
+            if (blockIdx.x == 0) *g = sg;
+        }
+    }
+    __syncthreads();
+    const int G = sg.Gc;
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int s = blockIdx.x * kRadixTile + r * kB + t;
+        if (s < n) {
+            const float4 hp = pos[s], l = lo[s];
+            const int cx = ag_cell1((double)hp.x + (double)l.x, sg.L, sg.hc, G),
+                      cy = ag_cell1((double)hp.y + (double)l.y, sg.L, sg.hc, G),
+                      cz = ag_cell1((double)hp.z + (double)l.z, sg.L, sg.hc, G);
+            const unsigned c = (unsigned)((cz * G + cy) * G + cx);
+            keys[s] = ((unsigned long long)c << 32) | (unsigned)s;
+            atomicAdd(&h[c & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(size_t)t * nwg + blockIdx.x] = h[t];
+}
+
+__global__ __launch_bounds__(kB) void k_ag_fill(int* a, int m, int v) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k < m) a[k] = v;
+}
+
+__global__ __launch_bounds__(kB) void k_ag_iota(int* a, int m) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k < m) a[k] = k;
+}
+
+// Cell ranges [cstart, cend) over the sorted keys.
+__global__ __launch_bounds__(kB) void k_ag_ranges(const unsigned long long* __restrict__ keys,
+                                                  int n, int* cstart, int* cend) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k >= n) return;
+    const unsigned c = (unsigned)(keys[k] >> 32);
+    if (k == 0 || (unsigned)(keys[k - 1] >> 32) != c) cstart[c] = k;
+    if (k == n - 1 || (unsigned)(keys[k + 1] >> 32) != c) cend[c] = k + 1;
+}
+
+// Root of a: a bounded walk up the parent links with path halving (a
+// non-root's link is moved to its grandparent, still an ancestor with a
+// smaller index, so no cycle can form and roots are never written here).
+__device__ __forceinline__ int ag_find(int* parent, int a, int* err) {
+    for (int it = 0; it < kAMaxIter; ++it) {
+        const int p = __hip_atomic_load(&parent[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == a) return a;
+        const int gp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (gp != p)
+            __hip_atomic_store(&parent[a], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a = gp;
+    }
+    atomicOr(err, 1);
+    return a;
+}
+
+__device__ __forceinline__ void ag_unite(int* parent, int a, int b, int* err) {
+    for (int it = 0; it < kAMaxIter; ++it) {
+        a = ag_find(parent, a, err);
+        b = ag_find(parent, b, err);
+        if (a == b) return;
+        if (a > b) {
+            const int x = a;
+            a = b;
+            b = x;
+        }
+        if (atomicCAS(&parent[b], b, a) == b) return;   // b was still a root: hung under a
+    }
+    atomicOr(err, 1);
+}
+
+// Every contact pair (k, m), m > k in cell-sorted order, from the 27 cells
+// around k's cell.
+__global__ __launch_bounds__(kB) void k_ag_hook(const float4* __restrict__ pos,
+                                                const float4* __restrict__ lo,
+                                                const int* __restrict__ typ,
+                                                const unsigned long long* __restrict__ keys,
+                                                const AgGrid* __restrict__ g,
+                                                const int* __restrict__ cstart,
+                                                const int* __restrict__ cend, int n, AgTable tb,
+                                                int* parent, int* err) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k >= n) return;
+    const unsigned long long key = keys[k];
+    const int i = (int)(unsigned)key;
+    const float4 hi = pos[i], li = lo[i];
+    const double xi = (double)hi.x + (double)li.x, yi = (double)hi.y + (double)li.y,
+                 zi = (double)hi.z + (double)li.z;
+    const int ti = typ[i];
+    const int G = g->Gc;
+    const int c = (int)(key >> 32);
+    const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z = cz + dz;
+        if (z < 0 || z >= G) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = cy + dy;
+            if (y < 0 || y >= G) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = cx + dx;
+                if (x < 0 || x >= G) continue;
+                const int cc = (z * G + y) * G + x;
+                const int m1 = cend[cc];
+                for (int m = max(cstart[cc], k + 1); m < m1; ++m) {
+                    const int j = (int)(unsigned)keys[m];
+                    const float4 hj = pos[j], lj = lo[j];
+                    const double ddx = xi - ((double)hj.x + (double)lj.x);
+                    const double ddy = yi - ((double)hj.y + (double)lj.y);
+                    const double ddz = zi - ((double)hj.z + (double)lj.z);
+                    if (ddx * ddx + ddy * ddy + ddz * ddz < tb.rc2[ti * tb.T + typ[j]])
+                        ag_unite(parent, k, m, err);
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_ag_flatten(int* parent, int n, int* root, int* err) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k < n) root[k] = ag_find(parent, k, err);
+}
+
+// Per root: the smallest original index (label) and the size.  Lanes of a
+// wavefront with the same root combine first (one atomic per root per
+// wavefront, so a giant component costs one atomic per wavefront).
+__global__ __launch_bounds__(kB) void k_ag_roots(const int* __restrict__ root,
+                                                 const unsigned long long* __restrict__ keys,
+                                                 const int* __restrict__ oid, int n, int* minoid,
+                                                 int* size) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    const bool live = k < n;
+    const int r = live ? root[k] : -1;
+    const int o = live ? oid[(int)(unsigned)keys[k]] : INT_MAX;
+    unsigned long long todo = __ballot(live);
+    const int lane = threadIdx.x % 64;
+    for (int it = 0; it < 64 && todo; ++it) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int rl = __shfl(r, leader);
+        const unsigned long long same = __ballot(live && r == rl);
+        int mo = (same >> lane) & 1ull ? o : INT_MAX;
+#pragma unroll
+        for (int w = 32; w >= 1; w >>= 1) mo = min(mo, __shfl_xor(mo, w));
+        if (lane == leader) {
+            atomicMin(&minoid[rl], mo);
+            atomicAdd(&size[rl], __popcll(same));
+        }
+        todo &= ~same;
+    }
+}
+
+// labels (original order) and per-workgroup partial statistics:
+// [components, aggregates (size >= 2), largest size].
+__global__ __launch_bounds__(kB) void k_ag_label(const int* __restrict__ root,
+                                                 const unsigned long long* __restrict__ keys,
+                                                 const int* __restrict__ oid,
+                                                 const int* __restrict__ minoid,
+                                                 const int* __restrict__ size, int n,
+                                                 int* labels, long long* part) {
+    __shared__ long long red[3][kB];
+    const int k = blockIdx.x * kB + threadIdx.x;
+    long long comp = 0, agg = 0, big = 0;
+    if (k < n) {
+        const int r = root[k];
+        if (labels) labels[oid[(int)(unsigned)keys[k]]] = minoid[r];
+        if (r == k) {
+            comp = 1;
+            agg = size[k] >= 2 ? 1 : 0;
+            big = size[k];
+        }
+    }
+    red[0][threadIdx.x] = comp;
+    red[1][threadIdx.x] = agg;
+    red[2][threadIdx.x] = big;
+    __syncthreads();
+    for (int w = kB / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+            red[2][threadIdx.x] = max(red[2][threadIdx.x], red[2][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// N_surf partials per workgroup and type: | |x| - R | < sigma_t / 2.
+__global__ __launch_bounds__(kB) void k_ag_surface(const float4* __restrict__ pos,
+                                                   const float4* __restrict__ lo,
+                                                   const int* __restrict__ typ, int n, double R,
+                                                   AgTable tb, long long* part) {
+    __shared__ int cnt[kMaxTypes];
+    if (threadIdx.x < kMaxTypes) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s < n) {
+        const float4 h = pos[s], l = lo[s];
+        const double x = (double)h.x + (double)l.x, y = (double)h.y + (double)l.y,
+                     z = (double)h.z + (double)l.z;
+        const int t = typ[s];
+        if (fabs(sqrt(x * x + y * y + z * z) - R) < tb.half_sigma[t]) atomicAdd(&cnt[t], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxTypes) part[(size_t)blockIdx.x * kMaxTypes + threadIdx.x] = cnt[threadIdx.x];
+}
+
+#define AG_LAUNCH(kernel, grid, block, ...)                                               \
+    do {                                                                                  \
+        hipLaunchKernelGGL(kernel, grid, block, 0, __VA_ARGS__);                          \
+        HIP_TRY(hipGetLastError());                                                       \
+    } while (0)
+
+// Scratch of the aggregate calls (allocated on first use, kept by the context).
+struct AgBufs {
+    int* cstart;     // [kANC]
+    int* cend;       // [kANC]
+    int* parent;     // [n]
+    int* root;       // [n]
+    int* minoid;     // [n]
+    int* size;       // [n]
+    int* labels;     // [n]
+    int* err;        // [1]
+    long long* part; // [blocks * kMaxTypes]
+    AgGrid* grid;    // [1]
+};
+
+// Carve the scratch out of one allocation, every piece 256-byte aligned;
+// with base == nullptr only the total size is computed.
+size_t ag_layout(char* base, size_t n, AgBufs* b) {
+    const size_t blocks = (n + kB - 1) / kB;
+    size_t off = 0;
+    auto take = [&](size_t nbytes) {
+        char* q = base ? base + off : nullptr;
+        off += (nbytes + 255) / 256 * 256;
+        return q;
+    };
+    b->grid = reinterpret_cast<AgGrid*>(take(sizeof(AgGrid)));
+    b->part = reinterpret_cast<long long*>(take(blocks * kMaxTypes * sizeof(long long)));
+    b->cstart = reinterpret_cast<int*>(take(kANC * sizeof(int)));
+    b->cend = reinterpret_cast<int*>(take(kANC * sizeof(int)));
+    b->parent = reinterpret_cast<int*>(take(n * sizeof(int)));
+    b->root = reinterpret_cast<int*>(take(n * sizeof(int)));
+    b->minoid = reinterpret_cast<int*>(take(n * sizeof(int)));
+    b->size = reinterpret_cast<int*>(take(n * sizeof(int)));
+    b->labels = reinterpret_cast<int*>(take(n * sizeof(int)));
+    b->err = reinterpret_cast<int*>(take(sizeof(int)));
+    return off;
+}
+
+ld_status ag_buffers(ld_ctx* c, AgBufs* b) {
+    const size_t n = (size_t)c->n;
+    if (!c->agg) {
+        const size_t bytes = ag_layout(nullptr, n, b);
+        if (hipMalloc(&c->agg, bytes) != hipSuccess) {
+            c->agg = nullptr;
+            return fail(LD_ENOMEM, "cannot allocate the aggregate scratch");
+        }
+    }
+    ag_layout(reinterpret_cast<char*>(c->agg), n, b);
+    return LD_OK;
+}
+
+}  // namespace
+
+void ag_free(ld_ctx* c) {
+    if (c->agg) (void)hipFree(c->agg);
+    c->agg = nullptr;
+}
+
+}  // namespace ld
+
+using namespace ld;
+using namespace ld::host;
+
+extern "C" {
+
+ld_status ld_aggregates(ld_ctx* c, double contact_factor, int64_t stats[3], int32_t* labels) {
+    g_err.clear();
+    if (!c || !stats) return fail(LD_EINVAL, "ctx and stats are required");
+    if (!(contact_factor > 0.0) || !std::isfinite(contact_factor))
+        return fail(LD_EINVAL, "contact_factor must be positive");
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    AgBufs b{};
+    ld_status st = ag_buffers(c, &b);
+    if (st != LD_OK) return st;
+    AgTable tb{};
+    tb.T = c->p.n_types;
+    double rc = 0.0;
+    for (int a = 0; a < tb.T; ++a) {
+        for (int q = 0; q < tb.T; ++q) {
+            const double d = contact_factor * 0.5 * (c->p.sigma[a] + c->p.sigma[q]);
+            tb.rc2[a * tb.T + q] = d * d;
+            rc = std::max(rc, d);
+        }
+        tb.half_sigma[a] = 0.5 * c->p.sigma[a];
+    }
+    const int blocks = (n + kB - 1) / kB;
+    AG_LAUNCH(k_ag_absmax, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
+    const int nwg = radix_tiles(n);
+    AG_LAUNCH(k_ag_keys, dim3(nwg), dim3(kB), s, c->pos, c->lo, n, c->sb.bounds_part, rc, b.grid,
+              c->sb.keys, c->sb.hist, nwg);
+    int bits = 1;
+    while ((1 << bits) < kANC) ++bits;
+    unsigned long long* keys = nullptr;
+    HIP_TRY(launch_radix_by_high(c->sb.keys, reinterpret_cast<unsigned long long*>(c->sb.tmp4), n,
+                                 bits, c->sb.hist, s, true, &keys));
+    AG_LAUNCH(k_ag_fill, dim3((kANC + kB - 1) / kB), dim3(kB), s, b.cstart, kANC, 0);
+    AG_LAUNCH(k_ag_fill, dim3((kANC + kB - 1) / kB), dim3(kB), s, b.cend, kANC, 0);
+    AG_LAUNCH(k_ag_ranges, dim3(blocks), dim3(kB), s, keys, n, b.cstart, b.cend);
+    AG_LAUNCH(k_ag_iota, dim3(blocks), dim3(kB), s, b.parent, n);
+    AG_LAUNCH(k_ag_fill, dim3(1), dim3(kB), s, b.err, 1, 0);
+    AG_LAUNCH(k_ag_hook, dim3(blocks), dim3(kB), s, c->pos, c->lo, c->typ, keys, b.grid, b.cstart,
+              b.cend, n, tb, b.parent, b.err);
+    AG_LAUNCH(k_ag_flatten, dim3(blocks), dim3(kB), s, b.parent, n, b.root, b.err);
+    AG_LAUNCH(k_ag_fill, dim3(blocks), dim3(kB), s, b.minoid, n, INT_MAX);
+    AG_LAUNCH(k_ag_fill, dim3(blocks), dim3(kB), s, b.size, n, 0);
+    AG_LAUNCH(k_ag_roots, dim3(blocks), dim3(kB), s, b.root, keys, c->oid, n, b.minoid, b.size);
+    AG_LAUNCH(k_ag_label, dim3(blocks), dim3(kB), s, b.root, keys, c->oid, b.minoid, b.size, n,
+              labels ? b.labels : nullptr, b.part);
+    std::vector<long long> part(3 * (size_t)blocks);
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(part.data(), b.part, sizeof(long long) * part.size(),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&err, b.err, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (labels) HIP_TRY(copy_out(labels, b.labels, sizeof(int32_t) * (size_t)n, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err) return fail(LD_EHIP, "contact-graph union did not settle within its bound");
+    long long comp = 0, agg = 0, big = 0;
+    for (int k = 0; k < blocks; ++k) {
+        comp += part[3 * (size_t)k];
+        agg += part[3 * (size_t)k + 1];
+        big = std::max(big, part[3 * (size_t)k + 2]);
+    }
+    stats[0] = comp;
+    stats[1] = agg;
+    stats[2] = big;
+    return LD_OK;
+}
+
+ld_status ld_surface_count(ld_ctx* c, double R, int64_t* counts) {
+    g_err.clear();
+    if (!c || !counts) return fail(LD_EINVAL, "ctx and counts are required");
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    if (!(R >= 0.0)) {      // negative: the droplet's radius at the current time
+        DevState ds;
+        HIP_TRY(hipMemcpyAsync(&ds, c->st, sizeof ds, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        R = radius_at(c->R, ds.t);
+    }
+    AgBufs b{};
+    ld_status st = ag_buffers(c, &b);
+    if (st != LD_OK) return st;
+    AgTable tb{};
+    tb.T = c->p.n_types;
+    for (int a = 0; a < tb.T; ++a) tb.half_sigma[a] = 0.5 * c->p.sigma[a];
+    const int blocks = (n + kB - 1) / kB;
+    AG_LAUNCH(k_ag_surface, dim3(blocks), dim3(kB), s, c->pos, c->lo, c->typ, n, R, tb, b.part);
+    std::vector<long long> part((size_t)blocks * kMaxTypes);
+    HIP_TRY(hipMemcpyAsync(part.data(), b.part, sizeof(long long) * part.size(),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int t = 0; t < tb.T; ++t) {
+        long long v = 0;
+        for (int k = 0; k < blocks; ++k) v += part[(size_t)k * kMaxTypes + t];
+        counts[t] = v;
+    }
+    return LD_OK;
+}
+
+}  // extern "C"

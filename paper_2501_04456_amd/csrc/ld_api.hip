@@ -327,6 +327,7 @@ ld_status take_pending_error(ld_ctx* c) {
 
 void free_all(ld_ctx* c) {
     ld::pm_free(c);
+    ld::ag_free(c);
     void* bufs[] = {c->pos,     c->lo,     c->typ,         c->oid,       c->box,  c->aux,
                     c->Fpart,   c->S_slot, c->U_slot,      c->work,      c->st,
                     c->sb.keys, c->sb.tmp4, c->sb.tmp_i,   c->sb.bounds, c->sb.bounds_part,

@@ -286,6 +286,8 @@ struct ld_ctx {
     ld::FarField* ff = nullptr;
     // the paper's own scheme (null until ld_paper_enable)
     ld::PaperMode* pm = nullptr;
+    // scratch of the aggregate statistics (null until first used)
+    void* agg = nullptr;
 };
 
 namespace ld {
@@ -298,4 +300,6 @@ ld_status ff_step_forces(ld_ctx* c, hipStream_t s, int* j_split_used);
 // The paper's own scheme (defined in ld_paper.hip): one step, and release.
 ld_status pm_step(ld_ctx* c, double dt, hipStream_t s);
 void pm_free(ld_ctx* c);
+// Aggregate statistics scratch (ld_agg.hip).
+void ag_free(ld_ctx* c);
 }  // namespace ld

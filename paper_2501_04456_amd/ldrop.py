@@ -104,7 +104,7 @@ SYMBOLS = [
     "ld_ens_get_positions", "ld_ens_get_state", "ld_ens_sync", "ld_ens_kernel_timing",
     "ld_ens_kernel_time",
     "ld_paper_enable", "ld_paper_disable", "ld_paper_forces", "ld_paper_get_velocities",
-    "ld_paper_set_velocities",
+    "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count",
 ]
 
 _lib = None
@@ -173,6 +173,8 @@ def lib():
         L.ld_paper_forces.argtypes = [vp, dp]
         L.ld_paper_get_velocities.argtypes = [vp, dp]
         L.ld_paper_set_velocities.argtypes = [vp, dp]
+        L.ld_aggregates.argtypes = [vp, C.c_double, vp, vp]
+        L.ld_surface_count.argtypes = [vp, C.c_double, vp]
         for name in SYMBOLS:
             if name not in ("ld_destroy", "ld_last_error", "ld_ens_destroy",
                             "ld_ff_weights_size"):
@@ -334,6 +336,26 @@ class System:
         lo = None if x_lo is None else np.ascontiguousarray(x_lo, np.float32).reshape(self.n, 3)
         _check(lib().ld_set_positions(self.h, hi.ctypes.data_as(C.c_void_p),
                                       None if lo is None else lo.ctypes.data_as(C.c_void_p)))
+
+    # -- aggregate statistics -------------------------------------------
+    def aggregates(self, contact_factor: float = 1.1, labels: bool = False):
+        """Contact-graph components: returns dict(components, aggregates,
+        largest[, labels = smallest original index of each NP's component])."""
+        st = np.zeros(3, np.int64)
+        lab = np.zeros(self.n, np.int32) if labels else None
+        _check(lib().ld_aggregates(self.h, float(contact_factor),
+                                   st.ctypes.data_as(C.c_void_p),
+                                   lab.ctypes.data_as(C.c_void_p) if labels else None))
+        out = {"components": int(st[0]), "aggregates": int(st[1]), "largest": int(st[2])}
+        if labels:
+            out["labels"] = lab
+        return out
+
+    def surface_count(self, R: float = -1.0) -> np.ndarray:
+        """N_surf per type (R < 0: the droplet's current radius)."""
+        c = np.zeros(len(self.params.sigma), np.int64)
+        _check(lib().ld_surface_count(self.h, float(R), c.ctypes.data_as(C.c_void_p)))
+        return c
 
     # -- the paper's own scheme ------------------------------------------
     def paper_enable(self, range_factor: float = 4.0, kick: float = 0.0, inertial_mass=None):

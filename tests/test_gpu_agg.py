@@ -1,0 +1,97 @@
+"""GPU aggregate statistics against the CPU oracle through the C ABI: the
+contact-graph components (labels are the smallest original index of each
+component, so they are unique: compared bit-exactly) and N_surf per type."""
+import numpy as np
+import pytest
+
+from paper_2501_04456_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ld():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_04456_amd import ldrop
+    ldrop.lib()
+    return ldrop
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def clumped(n, seed, sigma, box=8.0):
+    """Random positions with clumps: a fraction of NPs sits next to an
+    earlier one, so components of many sizes exist."""
+    rng = np.random.default_rng(seed)
+    x = np.empty((n, 3))
+    typ = (rng.random(n) < 0.3).astype(np.int32)
+    for i in range(n):
+        if i > 0 and rng.random() < 0.6:
+            j = rng.integers(0, i)
+            d = rng.normal(size=3)
+            x[i] = x[j] + d / np.linalg.norm(d) * rng.uniform(0.9, 1.2) * sigma[typ[i]]
+        else:
+            x[i] = rng.uniform(-box, box, 3)
+    return x, typ
+
+
+def system(ld, x, typ, sigma, R0=50.0):
+    T = len(sigma)
+    p = W.Params(sigma=list(sigma), eps=[1.0] * T, mass=[1.0] * T, gamma=[1.0] * T,
+                 k_wall=[0.0] * T, wall_offset=[0.0] * T, bjerrum=0.7, kT=1.0)
+    R = W.Radius(kind=W.RADIUS_CONST, R0=R0)
+    w = W.Workload("agg", len(x), typ, np.zeros(len(x)), x.astype(np.float32), p, R, 1e-3, 1, 1)
+    return ld.System.from_workload(w), w
+
+
+@pytest.mark.parametrize("n,seed,f", [(3000, 1, 1.1), (3000, 2, 1.3), (700, 3, 2.5), (2, 4, 1.1)])
+def test_components_match_oracle(ld, orc, n, seed, f):
+    sigma = [1.0, 1.6]
+    x, typ = clumped(n, seed, sigma, box=8.0 * (n / 3000) ** (1 / 3) + 1.0)
+    s, w = system(ld, x, typ, sigma)
+    g = s.aggregates(f, labels=True)
+    xo = w.pos.astype(np.float64)      # the FP32 positions both sides use
+    nc, lab = orc.components(xo, w.type, w.params, f)
+    assert g["components"] == nc
+    assert np.array_equal(g["labels"].astype(np.int64), lab)
+    sizes = np.bincount(lab, minlength=n)
+    assert g["aggregates"] == int((sizes >= 2).sum())
+    assert g["largest"] == int(sizes.max())
+    # the slot order is unchanged: a second call gives the same answer
+    assert s.aggregates(f)["components"] == nc
+
+
+def test_components_on_the_headline_droplet(ld, orc):
+    """The large composition (three types) after a few steps, contact 1.1."""
+    w = W.config_large(n=4000, seed=9)
+    s = ld.System.from_workload(w)
+    s.step(10, w.dt)
+    s.sync()
+    x = s.positions64()
+    g = s.aggregates(1.1, labels=True)
+    # compare at the positions the GPU used (FP64 hi + lo)
+    nc, lab = orc.components(x, w.type, w.params, 1.1)
+    assert g["components"] == nc and np.array_equal(g["labels"].astype(np.int64), lab)
+
+
+def test_surface_count(ld, orc):
+    sigma = [1.0, 2.0]
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=(4000, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    r = rng.uniform(45.0, 55.0, 4000)
+    x = u * r[:, None]
+    typ = (rng.random(4000) < 0.4).astype(np.int32)
+    s, w = system(ld, x, typ, sigma, R0=50.0)
+    want = orc.surface_count(w.pos.astype(np.float64), w.type, w.params, 50.0)
+    assert np.array_equal(s.surface_count(), want)       # the droplet's own radius
+    assert np.array_equal(s.surface_count(47.0),
+                          orc.surface_count(w.pos.astype(np.float64), w.type, w.params, 47.0))
+    assert want.sum() > 0
