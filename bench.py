@@ -48,6 +48,9 @@ def parse():
                          "(post-processing calls at N=2.5e5)")
     ap.add_argument("--kick", type=float, default=0.05,
                     help="paper: magnitude of the random velocity vector per step")
+    ap.add_argument("--record-every", type=int, default=0,
+                    help="paper: record every k-th step's positions to a trajectory file "
+                         "under $TMPDIR (0: off)")
     ap.add_argument("--snapshots", type=int, default=8,
                     help="learned: training snapshots (N samples each)")
     ap.add_argument("--snap-every", type=int, default=100,
@@ -140,6 +143,11 @@ def bench_paper(a, torch, ldrop, W):
     s.paper_enable(range_factor=4.0, kick=a.kick, inertial_mass=p.mass)
     s.step(a.warmup, w.dt)
     s.sync()
+    trj = None
+    if a.record_every > 0:
+        import tempfile
+        trj = os.path.join(tempfile.gettempdir(), f"ld_bench_{os.getpid()}.trj")
+        s.record_open(trj, a.record_every)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -151,8 +159,15 @@ def bench_paper(a, torch, ldrop, W):
     wall = time.perf_counter() - t0
     s.sync()
     ms = ev0.elapsed_time(ev1)
+    rec = None
+    if trj:
+        frames = s.record_close()
+        rec = {"every": a.record_every, "frames": frames, "bytes": os.path.getsize(trj),
+               "wall_s_incl_writer": time.perf_counter() - t0}
+        os.remove(trj)
     print(json.dumps({
         "metric": "paper scheme steps/s at N=2.5e5 (truncated range, inertial)",
+        "recording": rec,
         "value": a.steps * 1e3 / ms, "unit": "steps/s",
         "particle_steps_per_s": w.n * a.steps * 1e3 / ms,
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps,

@@ -415,6 +415,21 @@ ld_status ld_ens_sync(ld_ens* e);
 ld_status ld_ens_kernel_timing(ld_ens* e, int32_t enable);
 ld_status ld_ens_kernel_time(ld_ens* e, int64_t* launches, double* total_ms);
 
+/* Trajectory recording (section 2.2: results recorded in a binary file for
+ * viewing and post-processing, every j-th frame).  After every `every`-th
+ * step of ld_step (global step count a multiple of every) the positions --
+ * FP32 of hi + lo, original order -- are copied asynchronously and appended
+ * to `path` by a writer thread, so stepping continues meanwhile (graph
+ * replay is off while recording).  File: "LDTRAJ01", int64 n, int32
+ * n_types, int32 every, int32 type[n]; then per frame int64 step, FP64 t,
+ * FP64 R(t), float32 x[n][3].  Errors: LD_EINVAL (path, every), LD_ESTATE
+ * (already recording), LD_ENOMEM, LD_EHIP. */
+ld_status ld_record_open(ld_ctx* ctx, const char* path, int32_t every);
+
+/* Finish writing (waits for frames in flight) and close; *frames (may be
+ * NULL) receives the number written.  Errors: LD_ESTATE, LD_EHIP. */
+ld_status ld_record_close(ld_ctx* ctx, int64_t* frames);
+
 /* Sub-aggregates (section 2.1 lists their number and aggregate statistics
  * among the model's post-processing outputs): the connected components of
  * the contact graph at the current positions, two NPs in contact when

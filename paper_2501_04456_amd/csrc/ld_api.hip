@@ -326,6 +326,7 @@ ld_status take_pending_error(ld_ctx* c) {
 }
 
 void free_all(ld_ctx* c) {
+    ld::rec_free(c);
     ld::pm_free(c);
     ld::ag_free(c);
     void* bufs[] = {c->pos,     c->lo,     c->typ,         c->oid,       c->box,  c->aux,
@@ -497,7 +498,8 @@ ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LD_EINVAL, "dt=%g must be positive", dt);
     if (n_steps < 0) return fail(LD_EINVAL, "n_steps must be >= 0");
     int64_t left = n_steps;
-    const bool use_graph = c->tune.graph_steps > 0 && !c->timing && !ld::ff_active(c) && !c->pm;
+    const bool use_graph = c->tune.graph_steps > 0 && !c->timing && !ld::ff_active(c) && !c->pm &&
+                           !c->rec;
     const int len = c->tune.sort_every > 0 ? c->tune.sort_every : c->tune.graph_steps;
     while (left > 0) {
         // A captured chunk starts with a re-sort when sorting is on, so it is
@@ -516,6 +518,7 @@ ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
         }
         ld_status st = enqueue_step(c, dt, c->stream, c->timing);
         if (st != LD_OK) return st;
+        if (c->rec && (st = ld::rec_after_step(c, dt, c->stream)) != LD_OK) return st;
         --left;
     }
     return LD_OK;

@@ -235,6 +235,7 @@ hipError_t launch_boxcount(const float4* pos, const float4* lo, int n, const dou
 
 struct FarField;
 struct PaperMode;
+struct Recorder;
 
 }  // namespace ld
 
@@ -288,6 +289,8 @@ struct ld_ctx {
     ld::PaperMode* pm = nullptr;
     // scratch of the aggregate statistics (null until first used)
     void* agg = nullptr;
+    // open trajectory recording (null when none)
+    ld::Recorder* rec = nullptr;
 };
 
 namespace ld {
@@ -302,4 +305,7 @@ ld_status pm_step(ld_ctx* c, double dt, hipStream_t s);
 void pm_free(ld_ctx* c);
 // Aggregate statistics scratch (ld_agg.hip).
 void ag_free(ld_ctx* c);
+// Trajectory recording (ld_record.hip): after each enqueued step.
+ld_status rec_after_step(ld_ctx* c, double dt, hipStream_t s);
+void rec_free(ld_ctx* c);
 }  // namespace ld

@@ -104,7 +104,8 @@ SYMBOLS = [
     "ld_ens_get_positions", "ld_ens_get_state", "ld_ens_sync", "ld_ens_kernel_timing",
     "ld_ens_kernel_time",
     "ld_paper_enable", "ld_paper_disable", "ld_paper_forces", "ld_paper_get_velocities",
-    "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count",
+    "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count", "ld_record_open",
+    "ld_record_close",
 ]
 
 _lib = None
@@ -175,6 +176,8 @@ def lib():
         L.ld_paper_set_velocities.argtypes = [vp, dp]
         L.ld_aggregates.argtypes = [vp, C.c_double, vp, vp]
         L.ld_surface_count.argtypes = [vp, C.c_double, vp]
+        L.ld_record_open.argtypes = [vp, C.c_char_p, C.c_int32]
+        L.ld_record_close.argtypes = [vp, C.POINTER(C.c_int64)]
         for name in SYMBOLS:
             if name not in ("ld_destroy", "ld_last_error", "ld_ens_destroy",
                             "ld_ff_weights_size"):
@@ -336,6 +339,16 @@ class System:
         lo = None if x_lo is None else np.ascontiguousarray(x_lo, np.float32).reshape(self.n, 3)
         _check(lib().ld_set_positions(self.h, hi.ctypes.data_as(C.c_void_p),
                                       None if lo is None else lo.ctypes.data_as(C.c_void_p)))
+
+    # -- trajectory recording -------------------------------------------
+    def record_open(self, path: str, every: int = 1):
+        """Record every `every`-th step's positions into `path` (binary)."""
+        _check(lib().ld_record_open(self.h, os.fsencode(path), int(every)))
+
+    def record_close(self) -> int:
+        f = C.c_int64()
+        _check(lib().ld_record_close(self.h, C.byref(f)))
+        return f.value
 
     # -- aggregate statistics -------------------------------------------
     def aggregates(self, contact_factor: float = 1.1, labels: bool = False):
@@ -609,3 +622,24 @@ class Ensemble:
         n, ms = C.c_int64(), C.c_double()
         _check(lib().ld_ens_kernel_time(self.h, C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+
+def read_trajectory(path: str) -> dict:
+    """Parse a file written by ld_record_open: dict(n, n_types, every, type
+    [n], step [F], t [F], R [F], x [F, n, 3] float32)."""
+    raw = np.fromfile(path, dtype=np.uint8)
+    if raw[:8].tobytes() != b"LDTRAJ01":
+        raise ValueError(f"{path}: not a trajectory file")
+    n = int(raw[8:16].view(np.int64)[0])
+    n_types, every = (int(v) for v in raw[16:24].view(np.int32))
+    off = 24
+    typ = raw[off:off + 4 * n].view(np.int32).copy()
+    off += 4 * n
+    fb = 24 + 12 * n
+    F = (len(raw) - off) // fb
+    frames = raw[off:off + F * fb].reshape(F, fb)
+    return {"n": n, "n_types": n_types, "every": every, "type": typ,
+            "step": frames[:, 0:8].copy().view(np.int64)[:, 0],
+            "t": frames[:, 8:16].copy().view(np.float64)[:, 0],
+            "R": frames[:, 16:24].copy().view(np.float64)[:, 0],
+            "x": frames[:, 24:].copy().view(np.float32).reshape(F, n, 3)}
