@@ -219,6 +219,14 @@ ld_status ld_diagnostics(ld_ctx* ctx, double out[10]);
 ld_status ld_rdf(ld_ctx* ctx, double r_max, int32_t n_bins, double V, int32_t centre,
                  uint64_t* counts, double* g, uint64_t* ccounts, double* cbar);
 
+/* Eq. (8) for the NPs of one type (the survey's per-type C-bar): ccounts
+ * [n_bins] uint64 counts of type-`type` NPs at distance [b dr, (b+1) dr)
+ * from the centre (0 droplet centre, 1 centre of mass of all NPs), cbar
+ * [n_bins] = (count / N_type) / (dV_b / V), V <= 0: the droplet volume.
+ * Outputs host or device, either may be NULL.  Errors: LD_EINVAL, LD_EHIP. */
+ld_status ld_cbar_type(ld_ctx* ctx, int32_t type, double r_max, int32_t n_bins, double V,
+                       int32_t centre, uint64_t* ccounts, double* cbar);
+
 /* Fractal dimension, section 3.1: out[0] R_g (Eq. 3, about the centre of
  * mass, Eq. 4), out[1] D_f solving Eq. (2) with prefactor k_f and mean NP
  * diameter d (d <= 0: number-mean sigma), out[2] box-counting dimension over

@@ -723,6 +723,56 @@ ld_status ld_rdf(ld_ctx* c, double r_max, int32_t n_bins, double V, int32_t cent
     return wait_stream(c);
 }
 
+ld_status ld_cbar_type(ld_ctx* c, int32_t type, double r_max, int32_t n_bins, double V,
+                       int32_t centre, uint64_t* ccounts, double* cbar) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    if (type < 0 || type >= c->p.n_types) return fail(LD_EINVAL, "type %d out of range", type);
+    if (!(r_max > 0.0) || !std::isfinite(r_max)) return fail(LD_EINVAL, "r_max must be > 0");
+    if (n_bins < 1 || n_bins > 4096) return fail(LD_EINVAL, "n_bins must be in [1, 4096]");
+    if (centre != 0 && centre != 1) return fail(LD_EINVAL, "centre must be 0 or 1");
+    const size_t N = (size_t)c->n;
+    unsigned long long* dcc = reinterpret_cast<unsigned long long*>(c->aux) + 4096;
+    double* dctr = reinterpret_cast<double*>(dcc + 4096);
+    double* mom = dctr + 4;
+    if (centre == 1) {
+        HIP_TRY(ld::launch_moments(c->pos, c->lo, (int)N, c->work, mom, c->stream));
+        HIP_TRY(hipMemcpyAsync(dctr, mom, sizeof(double) * 3, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        const double z[4] = {0.0, 0.0, 0.0, 0.0};
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        HIP_TRY(hipMemcpy(dctr, z, sizeof z, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(ld::launch_centre_hist(c->pos, c->lo, c->typ, type, (int)N, r_max, n_bins, dctr, dcc,
+                                   c->stream));
+    std::vector<unsigned long long> hcc(n_bins);
+    std::vector<int32_t> ht(N);
+    HIP_TRY(hipMemcpyAsync(hcc.data(), dcc, sizeof(unsigned long long) * n_bins,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(ht.data(), c->typ, sizeof(int32_t) * N, hipMemcpyDeviceToHost,
+                           c->stream));
+    ld::DevState ds;
+    HIP_TRY(hipMemcpyAsync(&ds, c->st, sizeof ds, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (!(V > 0.0)) {
+        const double Rn = ld::radius_at(c->R, ds.t);
+        V = 4.0 / 3.0 * M_PI * Rn * Rn * Rn;
+    }
+    double nt = 0.0;
+    for (int32_t t : ht) nt += t == type ? 1.0 : 0.0;
+    const double dr = r_max / n_bins;
+    std::vector<double> hb(n_bins);
+    for (int b = 0; b < n_bins; ++b) {
+        const double r0 = b * dr, r1 = (b + 1) * dr;
+        const double dV = 4.0 / 3.0 * M_PI * (r1 * r1 * r1 - r0 * r0 * r0);
+        // Eq. (8) over the NPs of this type: (psi / N_t) / (dV / V)
+        hb[b] = nt > 0.0 ? ((double)hcc[b] / nt) / (dV / V) : 0.0;
+    }
+    if (ccounts) HIP_TRY(put_out(ccounts, hcc.data(), sizeof(uint64_t) * n_bins, c->stream));
+    if (cbar) HIP_TRY(put_out(cbar, hb.data(), sizeof(double) * n_bins, c->stream));
+    return wait_stream(c);
+}
+
 ld_status ld_fractal(ld_ctx* c, double k_f, double d, double eps0, int32_t max_scales,
                      double out[4], int64_t* box_counts) {
     g_err.clear();

@@ -227,6 +227,10 @@ hipError_t permute_slots_into(const unsigned long long* keys, int n, const float
 hipError_t launch_rdf(const float4* pos, const float4* lo, int n, double r_max, int n_bins,
                       const double* centre, unsigned long long* counts,
                       unsigned long long* ccounts, hipStream_t s);
+// Eq. (8) counts of the NPs of type `want` only (typ in slot order).
+hipError_t launch_centre_hist(const float4* pos, const float4* lo, const int* typ, int want, int n,
+                              double r_max, int n_bins, const double* centre,
+                              unsigned long long* ccounts, hipStream_t s);
 hipError_t launch_moments(const float4* pos, const float4* lo, int n, double* work,
                           double* out4, hipStream_t s);
 hipError_t launch_boxcount(const float4* pos, const float4* lo, int n, const double* lo3,

@@ -64,14 +64,17 @@ __global__ __launch_bounds__(kRdfBlock) void k_rdf(const float4* __restrict__ po
         if (hist[b]) atomicAdd(&counts[b], (unsigned long long)hist[b]);
 }
 
+// Distances from the centre into bins; typ != null keeps type `want` only.
 __global__ __launch_bounds__(256) void k_centre_hist(const float4* __restrict__ pos,
                                                      const float4* __restrict__ lo, int n,
                                                      double r_max, int n_bins, double dr,
                                                      const double* __restrict__ centre,
-                                                     unsigned long long* counts) {
+                                                     unsigned long long* counts,
+                                                     const int* __restrict__ typ, int want) {
 #pragma clang fp contract(off)
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
+    if (typ && typ[s] != want) return;
     double x[3];
     full_pos(pos, lo, s, x);
     const double dx = x[0] - centre[0], dy = x[1] - centre[1], dz = x[2] - centre[2];
@@ -171,7 +174,18 @@ hipError_t launch_rdf(const float4* pos, const float4* lo, int n, double r_max, 
     hipLaunchKernelGGL(k_rdf, dim3((n + kRdfBlock - 1) / kRdfBlock), dim3(kRdfBlock), 0, s, pos,
                        lo, n, r_max, n_bins, dr, counts);
     hipLaunchKernelGGL(k_centre_hist, dim3((n + 255) / 256), dim3(256), 0, s, pos, lo, n, r_max,
-                       n_bins, dr, centre, ccounts);
+                       n_bins, dr, centre, ccounts, nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_centre_hist(const float4* pos, const float4* lo, const int* typ, int want, int n,
+                              double r_max, int n_bins, const double* centre,
+                              unsigned long long* ccounts, hipStream_t s) {
+    if (n_bins < 1 || n_bins > kMaxBins) return hipErrorInvalidValue;
+    const double dr = r_max / n_bins;
+    hipLaunchKernelGGL(k_zero_u64, dim3((n_bins + 255) / 256), dim3(256), 0, s, ccounts, n_bins);
+    hipLaunchKernelGGL(k_centre_hist, dim3((n + 255) / 256), dim3(256), 0, s, pos, lo, n, r_max,
+                       n_bins, dr, centre, ccounts, typ, want);
     return hipGetLastError();
 }
 

@@ -105,7 +105,7 @@ SYMBOLS = [
     "ld_ens_kernel_time",
     "ld_paper_enable", "ld_paper_disable", "ld_paper_forces", "ld_paper_get_velocities",
     "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count", "ld_record_open",
-    "ld_record_close",
+    "ld_record_close", "ld_cbar_type",
 ]
 
 _lib = None
@@ -178,6 +178,8 @@ def lib():
         L.ld_surface_count.argtypes = [vp, C.c_double, vp]
         L.ld_record_open.argtypes = [vp, C.c_char_p, C.c_int32]
         L.ld_record_close.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.ld_cbar_type.argtypes = [vp, C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_int32,
+                                   vp, vp]
         for name in SYMBOLS:
             if name not in ("ld_destroy", "ld_last_error", "ld_ens_destroy",
                             "ld_ff_weights_size"):
@@ -430,6 +432,14 @@ class System:
                             g.ctypes.data_as(C.c_void_p), cc.ctypes.data_as(C.c_void_p),
                             cbar.ctypes.data_as(C.c_void_p)))
         return counts, cc, g, cbar
+
+    def cbar_type(self, t: int, r_max: float, n_bins: int, V: float = 0.0, centre: int = 0):
+        """Eq. (8) for the NPs of type t: (counts [n_bins] uint64, cbar [n_bins])."""
+        cc = np.zeros(n_bins, np.uint64)
+        cb = np.zeros(n_bins)
+        _check(lib().ld_cbar_type(self.h, int(t), r_max, n_bins, V, centre,
+                                  cc.ctypes.data_as(C.c_void_p), cb.ctypes.data_as(C.c_void_p)))
+        return cc, cb
 
     def fractal(self, k_f: float = 1.593, d: float = 0.0, eps0: float = 0.0,
                 max_scales: int = 32):

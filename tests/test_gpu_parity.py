@@ -309,6 +309,25 @@ def test_rdf_exact_counts(ld, orc):
     assert np.abs(cc2.astype(np.int64) - occ2.astype(np.int64)).max() <= 2
 
 
+@pytest.mark.parametrize("t", [0, 1, 2])
+def test_cbar_per_type(ld, orc, t):
+    """Eq. (8) over the NPs of one type equals the oracle's Eq. (8) on that
+    type's subset (its N is the subset's): counts exact about the droplet
+    centre, within edge flips about the centre of mass of all NPs."""
+    w = W.config_large(n=5000, seed=14)
+    s = ld.System.from_workload(w)
+    V = 4 / 3 * math.pi * w.radius.R0 ** 3
+    sub = w.pos[w.type == t]
+    cc, cb = s.cbar_type(t, w.radius.R0, 60, V=V, centre=0)
+    _, occ, _, ocb = orc.rdf(sub, w.radius.R0, 60, V)
+    assert np.array_equal(cc, occ) and cc.sum() == len(sub)
+    assert np.allclose(cb, ocb, rtol=1e-12)
+    cc2, _ = s.cbar_type(t, w.radius.R0, 60, V=V, centre=1)
+    com = w.pos.astype(np.float64).mean(0)
+    _, occ2, _, _ = orc.rdf(sub, w.radius.R0, 60, V, centre=com)
+    assert np.abs(cc2.astype(np.int64) - occ2.astype(np.int64)).max() <= 2
+
+
 def test_fractal(ld, orc):
     w = W.config_medium(n=4000, seed=5)
     s = ld.System.from_workload(w)
