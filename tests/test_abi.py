@@ -73,3 +73,19 @@ def test_error_text_without_gpu(libldrop):
     # ld_last_error is callable without a device and starts empty
     libldrop.ld_last_error.restype = C.c_char_p
     assert libldrop.ld_last_error() is not None
+
+
+def test_oracle_exports_every_declared_function():
+    """The checker's shared library, as built, carries every function its
+    header declares (a build step that compiled only part of its sources
+    would leave tests failing with missing symbols)."""
+    import oracle
+    txt = open(os.path.join(ROOT, "oracle", "ldo.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = sorted(set(re.findall(r"^\s*(?:void|int64_t|double)\s+(ldo_\w+)\s*\(", txt, flags=re.M)))
+    assert len(names) >= 25
+    if not os.path.exists(oracle._LIB_PATH):
+        oracle.build()
+    L = C.CDLL(oracle._LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in ldo.h but not in {oracle._LIB_PATH}"
