@@ -11,6 +11,7 @@ themselves are in ``ldo.c``.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -125,6 +126,10 @@ def lib():
         L.ldo_components.restype = C.c_int64
         L.ldo_surface_count.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), C.POINTER(_Params),
                                         C.c_double, C.POINTER(C.c_int64)]
+        L.ldo_surface_fractal.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32),
+                                          C.POINTER(_Params), C.c_double, C.c_double,
+                                          C.c_double, C.c_double, C.POINTER(C.c_int64), dp,
+                                          C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -490,6 +495,21 @@ def components(x, type_, params, contact_factor: float = 1.1):
     n = lib().ldo_components(len(type_), _dp(x), _ip(type_), C.byref(make_params(params)),
                              contact_factor, _lp(labels))
     return n, labels
+
+
+def surface_fractal(x, type_, params, R: float, contact_factor: float = 1.1,
+                    k_f: float = math.pi / math.sqrt(3.0), d: float = 0.0):
+    """Surface fractal dimension of the largest surface aggregate: returns
+    (stats [components, largest size, its label], out [R_g, d, D_f],
+    labels (-1 off the surface))."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    type_ = np.ascontiguousarray(type_, dtype=np.int32)
+    stats = np.zeros(3, np.int64)
+    out = np.zeros(3)
+    labels = np.zeros(len(type_), np.int64)
+    lib().ldo_surface_fractal(len(type_), _dp(x), _ip(type_), C.byref(make_params(params)), R,
+                              contact_factor, k_f, d, _lp(stats), _dp(out), _lp(labels))
+    return stats, out, labels
 
 
 def surface_count(x, type_, params, R: float) -> np.ndarray:

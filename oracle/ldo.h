@@ -154,6 +154,22 @@ int64_t ldo_components(int64_t n, const double* x, const int32_t* type, const ld
 void ldo_surface_count(int64_t n, const double* x, const int32_t* type, const ldo_params* p,
                        double R, int64_t* counts);
 
+/* Surface fractal dimension (section 3.1's fractal equation at dimension two
+ * on the sphere).  Surface NPs as ldo_surface_count; their contact-graph
+ * components (r < contact_factor sigma_ij); stats = [components, size of the
+ * largest, its label] (label = smallest original index; ties between sizes:
+ * the smaller label; no surface NP: [0, 0, -1]).  For the largest: u_i =
+ * x_i / |x_i|, u_0 = the normalised sum of the u_i, out[0] = R_g =
+ * sqrt(mean (R angle(u_i, u_0))^2), out[1] = d (d <= 0: the component's
+ * number-mean sigma), out[2] = D_f = ln(N / k_f) / ln(2 R_g / d) (NaN below
+ * two NPs; all NaN without surface NPs or when the u_i sum to zero).
+ * labels[n] (may be NULL): the component label of surface NPs, -1 elsewhere.
+ * Pinned by two-NP and ring closed forms, the flat-plane limit, rotation
+ * invariance, and the components against scipy. */
+void ldo_surface_fractal(int64_t n, const double* x, const int32_t* type, const ldo_params* p,
+                         double R, double contact_factor, double k_f, double d, int64_t stats[3],
+                         double out[3], int64_t* labels);
+
 /* One step for the listed rows only (pair forces from all n particles at the
  * current positions); writes the rows' new positions, leaves x unchanged.
  * Returns step if a listed row blew up, else -1.  Same formulas as ldo_run,
