@@ -184,7 +184,8 @@ def bench_analysis(a, torch, ldrop, W):
     and radius-of-gyration fractal dimensions (Eqs. 2-4), sub-aggregates
     (contact-graph components) and N_surf, on the headline droplet as
     initialised (dispersed) and on a packed one (a jittered cubic lattice of
-    spacing 1.02 sigma: one giant component)."""
+    spacing 1.02 sigma: one giant component); the surface fractal dimension
+    on a droplet with 50000 NPs in surface patches."""
     import numpy as np
 
     def timed(fn, reps=5):
@@ -213,6 +214,15 @@ def bench_analysis(a, torch, ldrop, W):
     sp = ldrop.System.from_workload(wp)
     out["aggregates_packed_ms"], g = timed(lambda: sp.aggregates(1.1))
     out["aggregates_packed"] = g
+    # a droplet with a fifth of its NPs in 400 patches on the surface
+    pm = W.config_medium(n=a.n, with_positions=False).params
+    xs, ts = W.surface_clusters(a.n // 5, a.n - a.n // 5, 300.0, pm.sigma, 31, n_centres=400,
+                                spread=4.0)
+    ws = W.Workload("surface", a.n, ts, np.zeros(a.n), xs.astype(np.float32), pm,
+                    W.Radius(kind=W.RADIUS_CONST, R0=300.0), w.dt, 1, 1)
+    ss = ldrop.System.from_workload(ws)
+    out["surface_fractal_ms"], g = timed(lambda: ss.surface_fractal(-1.0, 1.1))
+    out["surface_fractal"] = g
     print(json.dumps({
         "metric": "post-processing call times at N=2.5e5", "value": out["aggregates_dispersed_ms"],
         "unit": "ms (sub-aggregates, dispersed droplet)", "higher_is_better": False,

@@ -454,6 +454,26 @@ ld_status ld_aggregates(ld_ctx* ctx, double contact_factor, int64_t stats[3], in
  * LD_ENOMEM, LD_EHIP. */
 ld_status ld_surface_count(ld_ctx* ctx, double R, int64_t* counts);
 
+/* Surface fractal dimension (section 3.1: the fractal equation, Eqs. (2)-(4),
+ * holds at dimension two for the NP structure on the droplet surface, with
+ * the sphere's geometry taken into account).  Surface NPs as
+ * ld_surface_count (R < 0: the current radius); surface aggregates = the
+ * components of the contact graph among them (r < contact_factor sigma_ij,
+ * FP64).  For the largest (equal sizes: the smallest label): u_i = x_i/|x_i|,
+ * u_0 = the normalised sum of the u_i, R_g^2 = mean over its NPs of
+ * (R angle(u_i, u_0))^2 (geodesic distances on the sphere of radius R),
+ * D_f = ln(N / k_f) / ln(2 R_g / d), d <= 0: the aggregate's number-mean
+ * sigma.  k_f = pi / sqrt(3) makes a compact hexagonal disk two-dimensional
+ * (the planar counterpart of the compact prefactor 1.593 the paper takes in
+ * three dimensions).  stats (host) = [surface aggregates, size of the
+ * largest, its label] ([0, 0, -1] without surface NPs); out (host) = [R_g,
+ * d, D_f]: D_f NaN below two NPs, all NaN without surface NPs.  labels
+ * (optional, [n] int32, host or device, original order): the smallest
+ * original index of a surface NP's aggregate, -1 for NPs off the surface.
+ * The slot order is not changed.  Errors: LD_EINVAL, LD_ENOMEM, LD_EHIP. */
+ld_status ld_surface_fractal(ld_ctx* ctx, double R, double contact_factor, double k_f, double d,
+                             int64_t stats[3], double out[3], int32_t* labels);
+
 /* ---------------------------------------------------------------------- */
 /* The paper's own scheme (section 2.2 steps (i)-(vi) read literally)      */
 /* ---------------------------------------------------------------------- */

@@ -1,6 +1,8 @@
 // Aggregate statistics the paper extracts in post-processing (section 2.1:
 // the number of sub-aggregates and aggregate statistics; section 1: N_surf,
-// the number of NPs at the droplet surface).
+// the number of NPs at the droplet surface; section 3.1: the surface
+// fractal dimension, the fractal equation taken at dimension two on the
+// sphere).
 //
 // Sub-aggregates are the connected components of the contact graph, a pair
 // in contact when r < contact_factor sigma_ij.  Candidates come from a cell
@@ -14,6 +16,8 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <limits>
+#include <vector>
 
 #include "ld_host.h"
 
@@ -158,7 +162,8 @@ __device__ __forceinline__ void ag_unite(int* parent, int a, int b, int* err) {
 }
 
 // Every contact pair (k, m), m > k in cell-sorted order, from the 27 cells
-// around k's cell.
+// around k's cell; with SURF only pairs of two surface NPs (surf[slot] != 0).
+template <bool SURF>
 __global__ __launch_bounds__(kB) void k_ag_hook(const float4* __restrict__ pos,
                                                 const float4* __restrict__ lo,
                                                 const int* __restrict__ typ,
@@ -166,11 +171,13 @@ __global__ __launch_bounds__(kB) void k_ag_hook(const float4* __restrict__ pos,
                                                 const AgGrid* __restrict__ g,
                                                 const int* __restrict__ cstart,
                                                 const int* __restrict__ cend, int n, AgTable tb,
-                                                int* parent, int* err) {
+                                                const int* __restrict__ surf, int* parent,
+                                                int* err) {
     const int k = blockIdx.x * kB + threadIdx.x;
     if (k >= n) return;
     const unsigned long long key = keys[k];
     const int i = (int)(unsigned)key;
+    if (SURF && !surf[i]) return;
     const float4 hi = pos[i], li = lo[i];
     const double xi = (double)hi.x + (double)li.x, yi = (double)hi.y + (double)li.y,
                  zi = (double)hi.z + (double)li.z;
@@ -191,6 +198,7 @@ __global__ __launch_bounds__(kB) void k_ag_hook(const float4* __restrict__ pos,
                 const int m1 = cend[cc];
                 for (int m = max(cstart[cc], k + 1); m < m1; ++m) {
                     const int j = (int)(unsigned)keys[m];
+                    if (SURF && !surf[j]) continue;
                     const float4 hj = pos[j], lj = lo[j];
                     const double ddx = xi - ((double)hj.x + (double)lj.x);
                     const double ddy = yi - ((double)hj.y + (double)lj.y);
@@ -211,14 +219,17 @@ __global__ __launch_bounds__(kB) void k_ag_flatten(int* parent, int n, int* root
 // Per root: the smallest original index (label) and the size.  Lanes of a
 // wavefront with the same root combine first (one atomic per root per
 // wavefront, so a giant component costs one atomic per wavefront).
+// With a surface mask only surface NPs count.
 __global__ __launch_bounds__(kB) void k_ag_roots(const int* __restrict__ root,
                                                  const unsigned long long* __restrict__ keys,
-                                                 const int* __restrict__ oid, int n, int* minoid,
+                                                 const int* __restrict__ oid,
+                                                 const int* __restrict__ surf, int n, int* minoid,
                                                  int* size) {
     const int k = blockIdx.x * kB + threadIdx.x;
-    const bool live = k < n;
+    const int slot = k < n ? (int)(unsigned)keys[k] : 0;
+    const bool live = k < n && (!surf || surf[slot]);
     const int r = live ? root[k] : -1;
-    const int o = live ? oid[(int)(unsigned)keys[k]] : INT_MAX;
+    const int o = live ? oid[slot] : INT_MAX;
     unsigned long long todo = __ballot(live);
     const int lane = threadIdx.x % 64;
     for (int it = 0; it < 64 && todo; ++it) {
@@ -291,6 +302,147 @@ __global__ __launch_bounds__(kB) void k_ag_surface(const float4* __restrict__ po
     if (threadIdx.x < kMaxTypes) part[(size_t)blockIdx.x * kMaxTypes + threadIdx.x] = cnt[threadIdx.x];
 }
 
+// Surface flag per slot: | |x| - R | < sigma_t / 2 (as k_ag_surface).
+__global__ __launch_bounds__(kB) void k_sf_flag(const float4* __restrict__ pos,
+                                                const float4* __restrict__ lo,
+                                                const int* __restrict__ typ, int n, double R,
+                                                AgTable tb, int* surf) {
+    const int s = blockIdx.x * kB + threadIdx.x;
+    if (s >= n) return;
+    const float4 h = pos[s], l = lo[s];
+    const double x = (double)h.x + (double)l.x, y = (double)h.y + (double)l.y,
+                 z = (double)h.z + (double)l.z;
+    surf[s] = fabs(sqrt(x * x + y * y + z * z) - R) < tb.half_sigma[typ[s]] ? 1 : 0;
+}
+
+// Labels of surface NPs (-1 elsewhere) and per-workgroup partials:
+// [surface components, the largest packed as size << 32 | (INT_MAX - label)],
+// so the maximum is the largest size and, among equal sizes, the smallest
+// label.
+__global__ __launch_bounds__(kB) void k_sf_label(const int* __restrict__ root,
+                                                 const unsigned long long* __restrict__ keys,
+                                                 const int* __restrict__ oid,
+                                                 const int* __restrict__ surf,
+                                                 const int* __restrict__ minoid,
+                                                 const int* __restrict__ size, int n,
+                                                 int* labels, long long* part) {
+    __shared__ long long red[2][kB];
+    const int k = blockIdx.x * kB + threadIdx.x;
+    long long comp = 0, best = -1;
+    if (k < n) {
+        const int slot = (int)(unsigned)keys[k];
+        const int r = root[k];
+        const bool on = surf[slot] != 0;
+        if (labels) labels[oid[slot]] = on ? minoid[r] : -1;
+        if (on && r == k) {
+            comp = 1;
+            best = ((long long)size[k] << 32) | (long long)(unsigned)(INT_MAX - minoid[k]);
+        }
+    }
+    red[0][threadIdx.x] = comp;
+    red[1][threadIdx.x] = best;
+    __syncthreads();
+    for (int w = kB / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) part[2 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Direction of a surface NP (FP64 hi + lo) and whether it belongs to the
+// component labelled `label`.
+__device__ __forceinline__ bool sf_member(const float4* __restrict__ pos,
+                                          const float4* __restrict__ lo,
+                                          const unsigned long long* __restrict__ keys,
+                                          const int* __restrict__ root,
+                                          const int* __restrict__ surf,
+                                          const int* __restrict__ minoid, int k, int label,
+                                          double u[3], int* slot) {
+    const int sl = (int)(unsigned)keys[k];
+    *slot = sl;
+    if (!surf[sl] || minoid[root[k]] != label) return false;
+    const float4 h = pos[sl], l = lo[sl];
+    const double x = (double)h.x + (double)l.x, y = (double)h.y + (double)l.y,
+                 z = (double)h.z + (double)l.z;
+    const double r = sqrt(x * x + y * y + z * z);
+    u[0] = x / r;
+    u[1] = y / r;
+    u[2] = z / r;
+    return true;
+}
+
+// Per-workgroup sums over the component's NPs of the unit direction and of
+// sigma: dpart[4 * block + {0, 1, 2, 3}].
+__global__ __launch_bounds__(kB) void k_sf_sums(const float4* __restrict__ pos,
+                                                const float4* __restrict__ lo,
+                                                const int* __restrict__ typ,
+                                                const unsigned long long* __restrict__ keys,
+                                                const int* __restrict__ root,
+                                                const int* __restrict__ surf,
+                                                const int* __restrict__ minoid, int n, int label,
+                                                AgTable tb, double* dpart) {
+    __shared__ double red[4][kB];
+    const int k = blockIdx.x * kB + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (k < n) {
+        double u[3];
+        int sl;
+        if (sf_member(pos, lo, keys, root, surf, minoid, k, label, u, &sl)) {
+            v[0] = u[0];
+            v[1] = u[1];
+            v[2] = u[2];
+            v[3] = 2.0 * tb.half_sigma[typ[sl]];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = kB / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) dpart[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Per-workgroup sums of the squared angle between each member's direction
+// and u0 (from the sine and cosine, accurate for small angles).
+__global__ __launch_bounds__(kB) void k_sf_theta(const float4* __restrict__ pos,
+                                                 const float4* __restrict__ lo,
+                                                 const unsigned long long* __restrict__ keys,
+                                                 const int* __restrict__ root,
+                                                 const int* __restrict__ surf,
+                                                 const int* __restrict__ minoid, int n, int label,
+                                                 double u0x, double u0y, double u0z,
+                                                 double* dpart) {
+    __shared__ double red[kB];
+    const int k = blockIdx.x * kB + threadIdx.x;
+    double v = 0.0;
+    if (k < n) {
+        double u[3];
+        int sl;
+        if (sf_member(pos, lo, keys, root, surf, minoid, k, label, u, &sl)) {
+            const double cx = u[1] * u0z - u[2] * u0y, cy = u[2] * u0x - u[0] * u0z,
+                         cz = u[0] * u0y - u[1] * u0x;
+            const double th = atan2(sqrt(cx * cx + cy * cy + cz * cz),
+                                    u[0] * u0x + u[1] * u0y + u[2] * u0z);
+            v = th * th;
+        }
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kB / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dpart[blockIdx.x] = red[0];
+}
+
 #define AG_LAUNCH(kernel, grid, block, ...)                                               \
     do {                                                                                  \
         hipLaunchKernelGGL(kernel, grid, block, 0, __VA_ARGS__);                          \
@@ -308,6 +460,8 @@ struct AgBufs {
     int* labels;     // [n]
     int* err;        // [1]
     long long* part; // [blocks * kMaxTypes]
+    double* dpart;   // [blocks * 4]
+    int* surf;       // [n] surface flag per slot
     AgGrid* grid;    // [1]
 };
 
@@ -323,6 +477,8 @@ size_t ag_layout(char* base, size_t n, AgBufs* b) {
     };
     b->grid = reinterpret_cast<AgGrid*>(take(sizeof(AgGrid)));
     b->part = reinterpret_cast<long long*>(take(blocks * kMaxTypes * sizeof(long long)));
+    b->dpart = reinterpret_cast<double*>(take(blocks * 4 * sizeof(double)));
+    b->surf = reinterpret_cast<int*>(take(n * sizeof(int)));
     b->cstart = reinterpret_cast<int*>(take(kANC * sizeof(int)));
     b->cend = reinterpret_cast<int*>(take(kANC * sizeof(int)));
     b->parent = reinterpret_cast<int*>(take(n * sizeof(int)));
@@ -345,6 +501,68 @@ ld_status ag_buffers(ld_ctx* c, AgBufs* b) {
     }
     ag_layout(reinterpret_cast<char*>(c->agg), n, b);
     return LD_OK;
+}
+
+// Contact distances (contact_factor sigma_ij)^2 and half diameters; returns
+// the largest contact distance.
+double ag_table(const ld_ctx* c, double contact_factor, AgTable* tb) {
+    tb->T = c->p.n_types;
+    double rc = 0.0;
+    for (int a = 0; a < tb->T; ++a) {
+        for (int q = 0; q < tb->T; ++q) {
+            const double d = contact_factor * 0.5 * (c->p.sigma[a] + c->p.sigma[q]);
+            tb->rc2[a * tb->T + q] = d * d;
+            rc = std::max(rc, d);
+        }
+        tb->half_sigma[a] = 0.5 * c->p.sigma[a];
+    }
+    return rc;
+}
+
+// Cell sort, lock-free union of the contact pairs (with surf: only pairs of
+// two surface NPs), roots, and per root the size and smallest original index
+// (counting only surface NPs with surf).  *keys_out: the cell-sorted keys.
+hipError_t ag_union(ld_ctx* c, const AgBufs& b, const AgTable& tb, double rc, const int* surf,
+                    unsigned long long** keys_out) {
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    const int blocks = (n + kB - 1) / kB;
+#define AG_RUN(kernel, grid, ...)                                                         \
+    do {                                                                                  \
+        hipLaunchKernelGGL(kernel, grid, dim3(kB), 0, s, __VA_ARGS__);                    \
+        const hipError_t e_ = hipGetLastError();                                          \
+        if (e_ != hipSuccess) return e_;                                                  \
+    } while (0)
+    AG_RUN(k_ag_absmax, dim3(64), c->pos, n, c->sb.bounds_part);
+    const int nwg = radix_tiles(n);
+    AG_RUN(k_ag_keys, dim3(nwg), c->pos, c->lo, n, c->sb.bounds_part, rc, b.grid, c->sb.keys,
+           c->sb.hist, nwg);
+    int bits = 1;
+    while ((1 << bits) < kANC) ++bits;
+    unsigned long long* keys = nullptr;
+    const hipError_t e = launch_radix_by_high(
+        c->sb.keys, reinterpret_cast<unsigned long long*>(c->sb.tmp4), n, bits, c->sb.hist, s,
+        true, &keys);
+    if (e != hipSuccess) return e;
+    const dim3 gc((kANC + kB - 1) / kB), gn(blocks);
+    AG_RUN(k_ag_fill, gc, b.cstart, kANC, 0);
+    AG_RUN(k_ag_fill, gc, b.cend, kANC, 0);
+    AG_RUN(k_ag_ranges, gn, keys, n, b.cstart, b.cend);
+    AG_RUN(k_ag_iota, gn, b.parent, n);
+    AG_RUN(k_ag_fill, dim3(1), b.err, 1, 0);
+    if (surf)
+        AG_RUN(k_ag_hook<true>, gn, c->pos, c->lo, c->typ, keys, b.grid, b.cstart, b.cend, n, tb,
+               surf, b.parent, b.err);
+    else
+        AG_RUN(k_ag_hook<false>, gn, c->pos, c->lo, c->typ, keys, b.grid, b.cstart, b.cend, n, tb,
+               nullptr, b.parent, b.err);
+    AG_RUN(k_ag_flatten, gn, b.parent, n, b.root, b.err);
+    AG_RUN(k_ag_fill, gn, b.minoid, n, INT_MAX);
+    AG_RUN(k_ag_fill, gn, b.size, n, 0);
+    AG_RUN(k_ag_roots, gn, b.root, keys, c->oid, surf, n, b.minoid, b.size);
+#undef AG_RUN
+    *keys_out = keys;
+    return hipSuccess;
 }
 
 }  // namespace
@@ -372,37 +590,10 @@ ld_status ld_aggregates(ld_ctx* c, double contact_factor, int64_t stats[3], int3
     ld_status st = ag_buffers(c, &b);
     if (st != LD_OK) return st;
     AgTable tb{};
-    tb.T = c->p.n_types;
-    double rc = 0.0;
-    for (int a = 0; a < tb.T; ++a) {
-        for (int q = 0; q < tb.T; ++q) {
-            const double d = contact_factor * 0.5 * (c->p.sigma[a] + c->p.sigma[q]);
-            tb.rc2[a * tb.T + q] = d * d;
-            rc = std::max(rc, d);
-        }
-        tb.half_sigma[a] = 0.5 * c->p.sigma[a];
-    }
-    const int blocks = (n + kB - 1) / kB;
-    AG_LAUNCH(k_ag_absmax, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
-    const int nwg = radix_tiles(n);
-    AG_LAUNCH(k_ag_keys, dim3(nwg), dim3(kB), s, c->pos, c->lo, n, c->sb.bounds_part, rc, b.grid,
-              c->sb.keys, c->sb.hist, nwg);
-    int bits = 1;
-    while ((1 << bits) < kANC) ++bits;
+    const double rc = ag_table(c, contact_factor, &tb);
     unsigned long long* keys = nullptr;
-    HIP_TRY(launch_radix_by_high(c->sb.keys, reinterpret_cast<unsigned long long*>(c->sb.tmp4), n,
-                                 bits, c->sb.hist, s, true, &keys));
-    AG_LAUNCH(k_ag_fill, dim3((kANC + kB - 1) / kB), dim3(kB), s, b.cstart, kANC, 0);
-    AG_LAUNCH(k_ag_fill, dim3((kANC + kB - 1) / kB), dim3(kB), s, b.cend, kANC, 0);
-    AG_LAUNCH(k_ag_ranges, dim3(blocks), dim3(kB), s, keys, n, b.cstart, b.cend);
-    AG_LAUNCH(k_ag_iota, dim3(blocks), dim3(kB), s, b.parent, n);
-    AG_LAUNCH(k_ag_fill, dim3(1), dim3(kB), s, b.err, 1, 0);
-    AG_LAUNCH(k_ag_hook, dim3(blocks), dim3(kB), s, c->pos, c->lo, c->typ, keys, b.grid, b.cstart,
-              b.cend, n, tb, b.parent, b.err);
-    AG_LAUNCH(k_ag_flatten, dim3(blocks), dim3(kB), s, b.parent, n, b.root, b.err);
-    AG_LAUNCH(k_ag_fill, dim3(blocks), dim3(kB), s, b.minoid, n, INT_MAX);
-    AG_LAUNCH(k_ag_fill, dim3(blocks), dim3(kB), s, b.size, n, 0);
-    AG_LAUNCH(k_ag_roots, dim3(blocks), dim3(kB), s, b.root, keys, c->oid, n, b.minoid, b.size);
+    HIP_TRY(ag_union(c, b, tb, rc, nullptr, &keys));
+    const int blocks = (n + kB - 1) / kB;
     AG_LAUNCH(k_ag_label, dim3(blocks), dim3(kB), s, b.root, keys, c->oid, b.minoid, b.size, n,
               labels ? b.labels : nullptr, b.part);
     std::vector<long long> part(3 * (size_t)blocks);
@@ -422,6 +613,88 @@ ld_status ld_aggregates(ld_ctx* c, double contact_factor, int64_t stats[3], int3
     stats[0] = comp;
     stats[1] = agg;
     stats[2] = big;
+    return LD_OK;
+}
+
+ld_status ld_surface_fractal(ld_ctx* c, double R, double contact_factor, double k_f, double d,
+                             int64_t stats[3], double out[3], int32_t* labels) {
+    g_err.clear();
+    if (!c || !stats || !out) return fail(LD_EINVAL, "ctx, stats and out are required");
+    if (!(contact_factor > 0.0) || !std::isfinite(contact_factor))
+        return fail(LD_EINVAL, "contact_factor must be positive");
+    if (!(k_f > 0.0) || !std::isfinite(k_f)) return fail(LD_EINVAL, "k_f must be positive");
+    if (std::isnan(d)) return fail(LD_EINVAL, "d is NaN");
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    if (!(R >= 0.0)) {      // negative: the droplet's radius at the current time
+        DevState ds;
+        HIP_TRY(hipMemcpyAsync(&ds, c->st, sizeof ds, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        R = radius_at(c->R, ds.t);
+    }
+    AgBufs b{};
+    ld_status st = ag_buffers(c, &b);
+    if (st != LD_OK) return st;
+    AgTable tb{};
+    const double rc = ag_table(c, contact_factor, &tb);
+    const int blocks = (n + kB - 1) / kB;
+    AG_LAUNCH(k_sf_flag, dim3(blocks), dim3(kB), s, c->pos, c->lo, c->typ, n, R, tb, b.surf);
+    unsigned long long* keys = nullptr;
+    HIP_TRY(ag_union(c, b, tb, rc, b.surf, &keys));
+    AG_LAUNCH(k_sf_label, dim3(blocks), dim3(kB), s, b.root, keys, c->oid, b.surf, b.minoid,
+              b.size, n, labels ? b.labels : nullptr, b.part);
+    std::vector<long long> part(2 * (size_t)blocks);
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(part.data(), b.part, sizeof(long long) * part.size(),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&err, b.err, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (labels) HIP_TRY(copy_out(labels, b.labels, sizeof(int32_t) * (size_t)n, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err) return fail(LD_EHIP, "contact-graph union did not settle within its bound");
+    long long comp = 0, best = -1;
+    for (int k = 0; k < blocks; ++k) {
+        comp += part[2 * (size_t)k];
+        best = std::max(best, part[2 * (size_t)k + 1]);
+    }
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    out[0] = out[1] = out[2] = nan;
+    stats[0] = comp;
+    if (comp == 0) {
+        stats[1] = 0;
+        stats[2] = -1;
+        return LD_OK;
+    }
+    const long long m = best >> 32;
+    const int label = INT_MAX - (int)(unsigned)(best & 0xffffffffLL);
+    stats[1] = m;
+    stats[2] = label;
+    // the component's mean direction and mean diameter (partials summed in
+    // workgroup order, so the result does not depend on timing)
+    std::vector<double> dp(4 * (size_t)blocks);
+    AG_LAUNCH(k_sf_sums, dim3(blocks), dim3(kB), s, c->pos, c->lo, c->typ, keys, b.root, b.surf,
+              b.minoid, n, label, tb, b.dpart);
+    HIP_TRY(hipMemcpyAsync(dp.data(), b.dpart, sizeof(double) * dp.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double su[3] = {0.0, 0.0, 0.0}, ssig = 0.0;
+    for (int k = 0; k < blocks; ++k) {
+        su[0] += dp[4 * (size_t)k];
+        su[1] += dp[4 * (size_t)k + 1];
+        su[2] += dp[4 * (size_t)k + 2];
+        ssig += dp[4 * (size_t)k + 3];
+    }
+    const double nu = std::sqrt(su[0] * su[0] + su[1] * su[1] + su[2] * su[2]);
+    if (!(nu > 0.0)) return LD_OK;
+    const double dm = d > 0.0 ? d : ssig / (double)m;
+    AG_LAUNCH(k_sf_theta, dim3(blocks), dim3(kB), s, c->pos, c->lo, keys, b.root, b.surf,
+              b.minoid, n, label, su[0] / nu, su[1] / nu, su[2] / nu, b.dpart);
+    HIP_TRY(hipMemcpyAsync(dp.data(), b.dpart, sizeof(double) * blocks, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double s2 = 0.0;
+    for (int k = 0; k < blocks; ++k) s2 += dp[(size_t)k];
+    const double Rg = R * std::sqrt(s2 / (double)m);
+    out[0] = Rg;
+    out[1] = dm;
+    if (m >= 2) out[2] = std::log((double)m / k_f) / std::log(2.0 * Rg / dm);
     return LD_OK;
 }
 

@@ -8,6 +8,7 @@ is visible, construction fails loudly -- there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -105,7 +106,7 @@ SYMBOLS = [
     "ld_ens_kernel_time",
     "ld_paper_enable", "ld_paper_disable", "ld_paper_forces", "ld_paper_get_velocities",
     "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count", "ld_record_open",
-    "ld_record_close", "ld_cbar_type",
+    "ld_record_close", "ld_cbar_type", "ld_surface_fractal",
 ]
 
 _lib = None
@@ -176,6 +177,8 @@ def lib():
         L.ld_paper_set_velocities.argtypes = [vp, dp]
         L.ld_aggregates.argtypes = [vp, C.c_double, vp, vp]
         L.ld_surface_count.argtypes = [vp, C.c_double, vp]
+        L.ld_surface_fractal.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                         vp, vp, vp]
         L.ld_record_open.argtypes = [vp, C.c_char_p, C.c_int32]
         L.ld_record_close.argtypes = [vp, C.POINTER(C.c_int64)]
         L.ld_cbar_type.argtypes = [vp, C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_int32,
@@ -371,6 +374,26 @@ class System:
         c = np.zeros(len(self.params.sigma), np.int64)
         _check(lib().ld_surface_count(self.h, float(R), c.ctypes.data_as(C.c_void_p)))
         return c
+
+    def surface_fractal(self, R: float = -1.0, contact_factor: float = 1.1,
+                        k_f: float = math.pi / math.sqrt(3.0), d: float = 0.0,
+                        labels: bool = False):
+        """Surface fractal dimension of the largest surface aggregate (the
+        fractal equation at dimension two, geodesic R_g on the sphere of
+        radius R; R < 0: the current radius).  Returns dict(components,
+        largest, label, R_g, d, D_f[, labels: -1 off the surface])."""
+        st = np.zeros(3, np.int64)
+        o = np.zeros(3)
+        lab = np.zeros(self.n, np.int32) if labels else None
+        _check(lib().ld_surface_fractal(self.h, float(R), float(contact_factor), float(k_f),
+                                        float(d), st.ctypes.data_as(C.c_void_p),
+                                        o.ctypes.data_as(C.c_void_p),
+                                        lab.ctypes.data_as(C.c_void_p) if labels else None))
+        out = {"components": int(st[0]), "largest": int(st[1]), "label": int(st[2]),
+               "R_g": float(o[0]), "d": float(o[1]), "D_f": float(o[2])}
+        if labels:
+            out["labels"] = lab
+        return out
 
     # -- the paper's own scheme ------------------------------------------
     def paper_enable(self, range_factor: float = 4.0, kick: float = 0.0, inertial_mass=None):

@@ -23,6 +23,8 @@ in reduced units (lengths in units of the type-0 diameter, energies in kT):
   per-droplet rate multiplier in [0.5, 2].
 * ``config_learned`` - the medium system's composition scaled to N=250000
   for the learned far field.
+* ``surface_clusters`` - positions and types only: patches of NPs on the
+  droplet surface plus interior NPs, for the surface statistics.
 
 Type fractions are assigned in index blocks (the first round(f0 N) particles
 are type 0, ...); positions are i.i.d., so this is equal in law to a shuffle.
@@ -283,3 +285,34 @@ CONFIGS = {
     "large": config_large,
     "learned": config_learned,
 }
+
+
+def surface_clusters(n_surf: int, n_in: int, R: float, sigma=(1.0, 1.6), seed: int = 0,
+                     n_centres: int = 12, spread: float = 3.0, frac1: float = 0.3):
+    """Positions (FP64, [n, 3]) and types of NPs in patches on the surface of
+    a droplet of radius R plus NPs inside it, in a random order.
+
+    Patch centres are uniform on the sphere; each surface NP picks a centre,
+    moves from it by a Gaussian tangential offset of scale ``spread`` (a
+    length) and sits within a quarter diameter of the surface radially.
+    Interior NPs are uniform in the ball of radius 0.9 R.  Type 1 with
+    probability ``frac1``.  NPs may overlap (inputs for post-processing, not
+    for stepping)."""
+    rng = np.random.default_rng(seed)
+    sig = np.asarray(sigma, dtype=np.float64)
+    centres = rng.normal(size=(n_centres, 3))
+    centres /= np.linalg.norm(centres, axis=1)[:, None]
+    k = rng.integers(0, n_centres, n_surf)
+    d = centres[k] + rng.normal(scale=spread / R, size=(n_surf, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    typ_s = (rng.random(n_surf) < frac1).astype(np.int32)
+    r = R + rng.uniform(-0.24, 0.24, n_surf) * sig[typ_s]
+    xs = d * r[:, None]
+    u = rng.normal(size=(n_in, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    xi = u * (0.9 * R * rng.random(n_in) ** (1.0 / 3.0))[:, None]
+    typ_i = (rng.random(n_in) < frac1).astype(np.int32)
+    x = np.concatenate([xs, xi])
+    typ = np.concatenate([typ_s, typ_i])
+    perm = rng.permutation(n_surf + n_in)
+    return x[perm], typ[perm]

@@ -1,6 +1,10 @@
 """GPU aggregate statistics against the CPU oracle through the C ABI: the
 contact-graph components (labels are the smallest original index of each
-component, so they are unique: compared bit-exactly) and N_surf per type."""
+component, so they are unique: compared bit-exactly), N_surf per type, and
+the surface fractal dimension (surface aggregates bit-exact; R_g, d and
+D_f to 1e-10 relative: FP64 sums in another order, the same formulas)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -95,3 +99,59 @@ def test_surface_count(ld, orc):
     assert np.array_equal(s.surface_count(47.0),
                           orc.surface_count(w.pos.astype(np.float64), w.type, w.params, 47.0))
     assert want.sum() > 0
+
+
+def check_surface_fractal(g, st, out, lab):
+    assert [g["components"], g["largest"], g["label"]] == [int(v) for v in st]
+    if "labels" in g:
+        assert np.array_equal(g["labels"].astype(np.int64), lab)
+    for key, want in zip(("R_g", "d", "D_f"), out):
+        if math.isnan(want):
+            assert math.isnan(g[key]), key
+        else:
+            assert g[key] == pytest.approx(want, rel=1e-10, abs=1e-12), key
+
+
+@pytest.mark.parametrize("n_surf,n_in,seed,f", [(3000, 1500, 21, 1.1), (3000, 1500, 22, 1.4),
+                                                (777, 0, 23, 1.2), (2500, 2500, 24, 2.0)])
+def test_surface_fractal_matches_oracle(ld, orc, n_surf, n_in, seed, f):
+    sigma = [1.0, 1.6]
+    R = 25.0
+    x, typ = W.surface_clusters(n_surf, n_in, R, sigma, seed)
+    s, w = system(ld, x, typ, sigma, R0=R)
+    xo = w.pos.astype(np.float64)      # the FP32 positions both sides use
+    st, out, lab = orc.surface_fractal(xo, w.type, w.params, R, f)
+    g = s.surface_fractal(-1.0, f, labels=True)       # the droplet's own radius
+    check_surface_fractal(g, st, out, lab)
+    assert st[0] > 1 and st[1] >= 2
+    # explicit radius, prefactor and diameter; no labels requested
+    st, out, lab = orc.surface_fractal(xo, w.type, w.params, R - 0.2, f, 1.593, 1.3)
+    check_surface_fractal(s.surface_fractal(R - 0.2, f, 1.593, 1.3), st, out, lab)
+
+
+def test_surface_fractal_full_size(ld, orc):
+    """N = 250000: 50000 NPs in 400 surface patches plus 200000 inside."""
+    sigma = [1.0, 1.6]
+    R = 300.0
+    x, typ = W.surface_clusters(50000, 200000, R, sigma, 31, n_centres=400, spread=4.0)
+    s, w = system(ld, x, typ, sigma, R0=R)
+    g = s.surface_fractal(-1.0, 1.1, labels=True)
+    st, out, lab = orc.surface_fractal(w.pos.astype(np.float64), w.type, w.params, R, 1.1)
+    check_surface_fractal(g, st, out, lab)
+    assert (lab >= 0).sum() == 50000
+
+
+def test_surface_fractal_degenerate(ld, orc):
+    sigma = [1.0]
+    x = np.array([[0.0, 0.0, 5.0], [0.0, 3.0, 0.0], [1.0, 1.0, 1.0], [0.0, -7.0, 0.0]])
+    typ = np.zeros(4, np.int32)
+    s, w = system(ld, x, typ, sigma, R0=9.0)
+    xo = w.pos.astype(np.float64)
+    for R in (9.0, 5.2, 7.0):          # no surface NP; one; one again (another label)
+        st, out, lab = orc.surface_fractal(xo, w.type, w.params, R, 1.1)
+        check_surface_fractal(s.surface_fractal(R, 1.1, labels=True), st, out, lab)
+    assert s.surface_fractal(9.0)["label"] == -1
+    with pytest.raises(RuntimeError):
+        s.surface_fractal(9.0, k_f=0.0)
+    with pytest.raises(RuntimeError):
+        s.surface_fractal(9.0, contact_factor=-1.0)

@@ -182,26 +182,8 @@ def test_surface_fractal_compact_hex_disk_is_two_dimensional(R):
     assert math.pi / (3 * math.sqrt(2.0)) * (5.0 / 3.0) ** 1.5 == pytest.approx(1.593, abs=5e-4)
 
 
-def clustered_surface(seed, n_surf=1200, n_in=600, R=25.0, sigma=(1.0, 1.6)):
-    """Clusters of NPs on the shell |x| = R (radial jitter within a quarter
-    radius) plus interior NPs."""
-    rng = np.random.default_rng(seed)
-    centres = rng.normal(size=(12, 3))
-    centres /= np.linalg.norm(centres, axis=1)[:, None]
-    k = rng.integers(0, 12, n_surf)
-    d = centres[k] + rng.normal(scale=0.12, size=(n_surf, 3))
-    d /= np.linalg.norm(d, axis=1)[:, None]
-    typ_s = (rng.random(n_surf) < 0.3).astype(np.int32)
-    r = R + rng.uniform(-0.24, 0.24, n_surf) * np.asarray(sigma)[typ_s]
-    xs = d * r[:, None]
-    u = rng.normal(size=(n_in, 3))
-    u /= np.linalg.norm(u, axis=1)[:, None]
-    xi = u * (R * rng.random(n_in) ** (1 / 3) * 0.9)[:, None]
-    typ_i = (rng.random(n_in) < 0.3).astype(np.int32)
-    x = np.concatenate([xs, xi])
-    typ = np.concatenate([typ_s, typ_i])
-    perm = rng.permutation(len(x))
-    return x[perm], typ[perm]
+def clustered_surface(seed, sigma, R=25.0):
+    return W.surface_clusters(1200, 600, R, sigma, seed)
 
 
 @pytest.mark.parametrize("seed,f", [(11, 1.1), (12, 1.4)])
