@@ -315,36 +315,10 @@ __global__ __launch_bounds__(kB) void k_near_keys(const float4* __restrict__ pos
     hist[(size_t)t * nwg + blockIdx.x] = h[t];
 }
 
-// Block mode: cfirst[c] = first slot of cell c in the cell-sorted slots,
-// cfirst[M] = n; an empty cell gets the first slot after it.  Slot s that
-// starts cell c (previous slot in cell p < c) fills cells p+1 .. c; the last
-// slot also fills c+1 .. M with n.  A wavefront fills each of its gaps
-// together, 64 cells per pass, so long runs of empty cells cost little.
+// Gap-filled first slot of every cell (fill_cell_first), M cells.
 __global__ __launch_bounds__(kB) void k_cell_first(const unsigned long long* __restrict__ keys,
                                                    int n, int M, int* cfirst) {
-    const int s = blockIdx.x * kB + threadIdx.x;
-    const int lane = threadIdx.x % 64;
-    int p = 0, c = 0;
-    bool gap = false, tail = false;
-    if (s < n) {
-        c = (int)(keys[s] >> 32);
-        p = s == 0 ? -1 : (int)(keys[s - 1] >> 32);
-        gap = c != p;
-        tail = s == n - 1;
-    }
-    unsigned long long todo = __ballot(gap);
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int gp = __shfl(p, leader), gc = __shfl(c, leader), gs = __shfl(s, leader);
-        for (int q = gp + 1 + lane; q <= gc; q += 64) cfirst[q] = gs;
-        todo &= todo - 1ull;
-    }
-    const unsigned long long last = __ballot(tail);
-    if (last) {
-        const int leader = __ffsll((long long)last) - 1;
-        const int gc = __shfl(c, leader);
-        for (int q = gc + 1 + lane; q <= M; q += 64) cfirst[q] = n;
-    }
+    fill_cell_first(keys, n, M, blockIdx.x * kB + threadIdx.x, cfirst);
 }
 
 __global__ __launch_bounds__(kB) void k_zero_i(int* a, int m) {

@@ -218,6 +218,39 @@ hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tm
                                 unsigned* hist, hipStream_t s, bool first_counted = false,
                                 unsigned long long** sorted = nullptr);
 
+// First slots of the cells of keys sorted by cell (cell << 32 | slot):
+// cfirst[c] = the first slot whose cell is >= c, for c <= M (n past the last
+// key), so the slots of cells a..b are [cfirst[a], cfirst[b + 1]).  Called
+// by every work-item s of a one-dimensional launch over the keys; the slot
+// that starts cell c (previous slot in cell p < c) fills cells p+1 .. c, the
+// last slot cells c+1 .. M, and a wavefront fills each of its gaps together,
+// 64 cells per pass, so long runs of empty cells cost little.
+__device__ __forceinline__ void fill_cell_first(const unsigned long long* __restrict__ keys, int n,
+                                                int M, int s, int* cfirst) {
+    const int lane = threadIdx.x % 64;
+    int p = 0, c = 0;
+    bool gap = false, tail = false;
+    if (s < n) {
+        c = (int)(keys[s] >> 32);
+        p = s == 0 ? -1 : (int)(keys[s - 1] >> 32);
+        gap = c != p;
+        tail = s == n - 1;
+    }
+    unsigned long long todo = __ballot(gap);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int gp = __shfl(p, leader), gc = __shfl(c, leader), gs = __shfl(s, leader);
+        for (int q = gp + 1 + lane; q <= gc; q += 64) cfirst[q] = gs;
+        todo &= todo - 1ull;
+    }
+    const unsigned long long last = __ballot(tail);
+    if (last) {
+        const int leader = __ffsll((long long)last) - 1;
+        const int gc = __shfl(c, leader);
+        for (int q = gc + 1 + lane; q <= M; q += 64) cfirst[q] = n;
+    }
+}
+
 // dst arrays[s] = src arrays[low word of keys[s]] for s < n, one launch.
 hipError_t permute_slots_into(const unsigned long long* keys, int n, const float4* pos,
                               const float4* lo, const int* typ, const int* oid, float4* pos2,

@@ -57,8 +57,7 @@ struct PaperMode {
     double* v2 = nullptr;               // [3][n] second buffer (re-sort)
     double* F = nullptr;                // [3][n] pair forces, slot order
     PmGrid* grid = nullptr;             // device
-    int* cstart = nullptr;              // [64^3]
-    int* cend = nullptr;                // [64^3]
+    int* cfirst = nullptr;              // [64^3 + 1] first slot of every cell
 };
 
 namespace {
@@ -134,19 +133,12 @@ __global__ __launch_bounds__(kB) void k_pm_keys(const float4* __restrict__ pos,
     hist[(size_t)t * nwg + blockIdx.x] = h[t];
 }
 
-__global__ __launch_bounds__(kB) void k_pm_zero(int* a, int m) {
-    const int k = blockIdx.x * kB + threadIdx.x;
-    if (k < m) a[k] = 0;
-}
-
-// Slot range [cstart, cend) of every occupied cell of the sorted keys.
-__global__ __launch_bounds__(kB) void k_pm_ranges(const unsigned long long* __restrict__ keys,
-                                                  int n, int* cstart, int* cend) {
-    const int s = blockIdx.x * kB + threadIdx.x;
-    if (s >= n) return;
-    const unsigned c = (unsigned)(keys[s] >> 32);
-    if (s == 0 || (unsigned)(keys[s - 1] >> 32) != c) cstart[c] = s;
-    if (s == n - 1 || (unsigned)(keys[s + 1] >> 32) != c) cend[c] = s + 1;
+// First slot of every cell of the grid (G^3 cells, G from the device grid).
+__global__ __launch_bounds__(kB) void k_pm_first(const unsigned long long* __restrict__ keys,
+                                                 int n, const PmGrid* __restrict__ g,
+                                                 int* cfirst) {
+    const int G = g->Gc;
+    fill_cell_first(keys, n, G * G * G, blockIdx.x * kB + threadIdx.x, cfirst);
 }
 
 // Velocities follow the slots: v2[.][s] = v[.][src(s)].
@@ -162,25 +154,35 @@ __global__ __launch_bounds__(kB) void k_pm_permute_v(const unsigned long long* _
 }
 
 // Step (ii): the truncated pair forces on slot i from the 27 cells around
-// its cell, in cell order and slot order within a cell (FP64).
+// its cell, in cell order and slot order within a cell (FP64).  The three
+// cells of an x-row are consecutive in key order, so their slots form one
+// range [cfirst[a], cfirst[b + 1]) and nine ranges cover the 27 cells.  Each
+// candidate is first screened in FP32 from its hi word against the largest
+// range widened by the screen's worst rounding (coordinates within L: hi
+// rounding and the FP32 difference move each component by <= L 2^-22, the
+// squared sum by a few ulp), so every pair the FP64 test keeps passes the
+// screen; only the survivors load lo and the type.
 __global__ __launch_bounds__(kB) void k_pm_forces(const float4* __restrict__ pos,
                                                   const float4* __restrict__ lo,
                                                   const int* __restrict__ typ,
                                                   const unsigned long long* __restrict__ keys,
                                                   const PmGrid* __restrict__ g,
-                                                  const int* __restrict__ cstart,
-                                                  const int* __restrict__ cend, int n, PmTable tb,
-                                                  double* F) {
+                                                  const int* __restrict__ cfirst, int n,
+                                                  PmTable tb, double* F) {
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= n) return;
+    const PmGrid gr = *g;
+    const double wide = tb.rmax + gr.L * 0x1p-20;
+    const float screen2 = (float)(wide * wide * (1.0 + 0x1p-18));
     const float4 hi = pos[i], li = lo[i];
     const double xi = (double)hi.x + (double)li.x, yi = (double)hi.y + (double)li.y,
                  zi = (double)hi.z + (double)li.z;
     const int ti = typ[i];
     const double qi = (double)hi.w;                 // q_hat = q sqrt(kT l_B)
-    const int G = g->Gc;
+    const int G = gr.Gc;
     const int c = (int)(keys[i] >> 32);
     const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+    const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < G - 1 ? cx + 1 : G - 1;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int dz = -1; dz <= 1; ++dz) {
         const int z = cz + dz;
@@ -188,29 +190,27 @@ __global__ __launch_bounds__(kB) void k_pm_forces(const float4* __restrict__ pos
         for (int dy = -1; dy <= 1; ++dy) {
             const int y = cy + dy;
             if (y < 0 || y >= G) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int x = cx + dx;
-                if (x < 0 || x >= G) continue;
-                const int cc = (z * G + y) * G + x;
-                const int j1 = cend[cc];
-                for (int j = cstart[cc]; j < j1; ++j) {
-                    if (j == i) continue;
-                    const float4 hj = pos[j], lj = lo[j];
-                    const double ddx = xi - ((double)hj.x + (double)lj.x);
-                    const double ddy = yi - ((double)hj.y + (double)lj.y);
-                    const double ddz = zi - ((double)hj.z + (double)lj.z);
-                    const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                    const int p = ti * tb.T + typ[j];
-                    if (!(r2 < tb.rint2[p])) continue;
-                    const double ir2 = 1.0 / r2;
-                    const double s2 = tb.sig2[p] * ir2, s6 = s2 * s2 * s2;
-                    const double glj = tb.e24[p] * (2.0 * s6 * s6 - s6) * ir2;
-                    const double gc = qi * (double)hj.w * ir2 * sqrt(ir2);
-                    const double gg = glj + gc;
-                    fx += gg * ddx;
-                    fy += gg * ddy;
-                    fz += gg * ddz;
-                }
+            const int row = (z * G + y) * G;
+            const int j1 = cfirst[row + x1 + 1];
+            for (int j = cfirst[row + x0]; j < j1; ++j) {
+                const float4 hj = pos[j];
+                const float sx = hj.x - hi.x, sy = hj.y - hi.y, sz = hj.z - hi.z;
+                if (!(fmaf(sz, sz, fmaf(sy, sy, sx * sx)) < screen2) || j == i) continue;
+                const float4 lj = lo[j];
+                const double ddx = xi - ((double)hj.x + (double)lj.x);
+                const double ddy = yi - ((double)hj.y + (double)lj.y);
+                const double ddz = zi - ((double)hj.z + (double)lj.z);
+                const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                const int p = ti * tb.T + typ[j];
+                if (!(r2 < tb.rint2[p])) continue;
+                const double ir2 = 1.0 / r2;
+                const double s2 = tb.sig2[p] * ir2, s6 = s2 * s2 * s2;
+                const double glj = tb.e24[p] * (2.0 * s6 * s6 - s6) * ir2;
+                const double gc = qi * (double)hj.w * ir2 * sqrt(ir2);
+                const double gg = glj + gc;
+                fx += gg * ddx;
+                fy += gg * ddy;
+                fz += gg * ddz;
             }
         }
     }
@@ -331,11 +331,9 @@ ld_status pm_forces(ld_ctx* c, hipStream_t s) {
     std::swap(c->oid, c->oid2);
     std::swap(m->v, m->v2);
     c->graph_len = -1;                 // a captured graph holds the old addresses
-    PM_LAUNCH(k_pm_zero, dim3((kNC + kB - 1) / kB), dim3(kB), s, m->cstart, kNC);
-    PM_LAUNCH(k_pm_zero, dim3((kNC + kB - 1) / kB), dim3(kB), s, m->cend, kNC);
-    PM_LAUNCH(k_pm_ranges, dim3((n + kB - 1) / kB), dim3(kB), s, keys, n, m->cstart, m->cend);
+    PM_LAUNCH(k_pm_first, dim3((n + kB - 1) / kB), dim3(kB), s, keys, n, m->grid, m->cfirst);
     PM_LAUNCH(k_pm_forces, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->lo, c->typ, keys,
-              m->grid, m->cstart, m->cend, n, m->tab, m->F);
+              m->grid, m->cfirst, n, m->tab, m->F);
     c->steps_since_sort = 0;
     return LD_OK;
 }
@@ -345,7 +343,7 @@ ld_status pm_forces(ld_ctx* c, hipStream_t s) {
 void pm_free(ld_ctx* c) {
     if (!c->pm) return;
     PaperMode* m = c->pm;
-    void* b[] = {m->v, m->v2, m->F, m->grid, m->cstart, m->cend};
+    void* b[] = {m->v, m->v2, m->F, m->grid, m->cfirst};
     for (void* p : b)
         if (p) (void)hipFree(p);
     delete m;
@@ -408,8 +406,7 @@ ld_status ld_paper_enable(ld_ctx* c, const ld_paper_config* cfg) {
     tb.kick = cfg->kick;
     const size_t N = (size_t)c->n;
     bool ok = pm_alloc(&m->v, 3 * N) && pm_alloc(&m->v2, 3 * N) && pm_alloc(&m->F, 3 * N) &&
-              pm_alloc(&m->grid, 1) && pm_alloc(&m->cstart, (size_t)kNC) &&
-              pm_alloc(&m->cend, (size_t)kNC);
+              pm_alloc(&m->grid, 1) && pm_alloc(&m->cfirst, (size_t)kNC + 1);
     if (ok) {
         std::vector<double> zero(3 * N, 0.0);
         ok = hipMemcpy(m->v, zero.data(), sizeof(double) * 3 * N, hipMemcpyHostToDevice) ==
