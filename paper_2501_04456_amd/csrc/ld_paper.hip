@@ -183,19 +183,33 @@ __global__ __launch_bounds__(kB) void k_pm_forces(const float4* __restrict__ pos
     const int c = (int)(keys[i] >> 32);
     const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
     const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < G - 1 ? cx + 1 : G - 1;
+    // the nine row ranges first (independent loads), empty where the row
+    // falls outside the grid
+    int r0[9], r1[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int z = cz + k / 3 - 1, y = cy + k % 3 - 1;
+        const bool in = z >= 0 && z < G && y >= 0 && y < G;
+        const int row = (z * G + y) * G;
+        r0[k] = in ? cfirst[row + x0] : 0;
+        r1[k] = in ? cfirst[row + x1 + 1] : 0;
+    }
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int z = cz + dz;
-        if (z < 0 || z >= G) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int y = cy + dy;
-            if (y < 0 || y >= G) continue;
-            const int row = (z * G + y) * G;
-            const int j1 = cfirst[row + x1 + 1];
-            for (int j = cfirst[row + x0]; j < j1; ++j) {
-                const float4 hj = pos[j];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int j1 = r1[k];
+        for (int jb = r0[k]; jb < j1; jb += 4) {
+            // four candidates' hi words in flight, then screened in order
+            float4 hq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) hq[u] = pos[min(jb + u, j1 - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = jb + u;
+                const float4 hj = hq[u];
                 const float sx = hj.x - hi.x, sy = hj.y - hi.y, sz = hj.z - hi.z;
-                if (!(fmaf(sz, sz, fmaf(sy, sy, sx * sx)) < screen2) || j == i) continue;
+                if (j >= j1 || !(fmaf(sz, sz, fmaf(sy, sy, sx * sx)) < screen2) || j == i)
+                    continue;
                 const float4 lj = lo[j];
                 const double ddx = xi - ((double)hj.x + (double)lj.x);
                 const double ddy = yi - ((double)hj.y + (double)lj.y);

@@ -152,11 +152,17 @@ __global__ __launch_bounds__(kRT) void k_radix_hist(const unsigned long long* __
     __shared__ unsigned h[256];
     const int t = threadIdx.x;
     h[t] = 0u;
-    __syncthreads();
+    // every round's key in flight at once
+    unsigned d[kRRounds];
+#pragma unroll
     for (int r = 0; r < kRRounds; ++r) {
         const int e = blockIdx.x * kRTile + r * kRT + t;
-        if (e < n) atomicAdd(&h[(unsigned)(in[e] >> (32 + shift)) & 255u], 1u);
+        d[r] = e < n ? (unsigned)(in[e] >> (32 + shift)) & 255u : 256u;
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRRounds; ++r)
+        if (d[r] < 256u) atomicAdd(&h[d[r]], 1u);
     __syncthreads();
     hist[(size_t)t * nwg + blockIdx.x] = h[t];
 }
@@ -238,10 +244,18 @@ __global__ __launch_bounds__(kRT) void k_radix_scatter(const unsigned long long*
     const int t = threadIdx.x, w = t / 64, l = t % 64;
     base[t] = hist[(size_t)t * nwg + blockIdx.x];
     const unsigned long long below = (1ull << l) - 1ull;
+    // every round's key in flight at once (the rounds below wait on barriers)
+    unsigned long long kr[kRRounds];
+#pragma unroll
+    for (int r = 0; r < kRRounds; ++r) {
+        const int e = blockIdx.x * kRTile + r * kRT + t;
+        kr[r] = e < n ? in[e] : 0ull;
+    }
+#pragma unroll
     for (int r = 0; r < kRRounds; ++r) {
         const int e = blockIdx.x * kRTile + r * kRT + t;
         const bool valid = e < n;
-        const unsigned long long key = valid ? in[e] : 0ull;
+        const unsigned long long key = kr[r];
         const unsigned d = (unsigned)(key >> (32 + shift)) & 255u;
 #pragma unroll
         for (int k = 0; k < kRT / 64; ++k) wcnt[k][t] = 0u;
