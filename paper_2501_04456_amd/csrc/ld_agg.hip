@@ -66,7 +66,7 @@ __device__ __forceinline__ int ag_cell1(double x, double L, double h, int G) {
 }
 
 // Grid (block 0 stores it), cell keys (cell << 32 | slot) from the FP64
-// positions and the first radix pass's digit counts per 4096-slot tile.
+// positions and the first radix pass's digit counts per radix tile.
 __global__ __launch_bounds__(kB) void k_ag_keys(const float4* __restrict__ pos,
                                                 const float4* __restrict__ lo, int n,
                                                 const float* __restrict__ part, double rc,

@@ -277,7 +277,7 @@ static_assert(kB == ld::kRadixThreads, "k_near_keys counts digits per radix tile
 
 // Cell keys (cell << 32 | slot) of the slots, with the grid made from the
 // 64 partial maxima (block 0 stores it for the later kernels) and the
-// digit counts of the first radix pass over each 4096-slot tile.
+// digit counts of the first radix pass over each radix tile.
 __global__ __launch_bounds__(kB) void k_near_keys(const float4* __restrict__ pos,
                                                   const float4* __restrict__ lo, int n,
                                                   const float* __restrict__ part, double rc,

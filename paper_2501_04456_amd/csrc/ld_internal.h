@@ -202,10 +202,10 @@ hipError_t launch_bitonic(unsigned long long* keys, int n_pow2, hipStream_t s);
 hipError_t permute_slots(float4* pos, float4* lo, int* typ, int* oid, int n,
                          const SortBuffers& B, hipStream_t s);
 
-// Radix sort geometry: a workgroup of 256 handles a tile of 16 rounds x 256
+// Radix sort geometry: a workgroup of 256 handles a tile of 8 rounds x 256
 // keys; B.hist holds 256 digit counts per tile (digit-major).
 constexpr int kRadixThreads = 256;
-constexpr int kRadixRounds = 16;
+constexpr int kRadixRounds = 8;
 constexpr int kRadixTile = kRadixThreads * kRadixRounds;
 int radix_tiles(int n);
 

@@ -89,7 +89,7 @@ __device__ __forceinline__ int pm_cell1(double x, double L, double h, int G) {
 
 // Grid from the 64 partial maxima (block 0 stores it), cell keys
 // (cell << 32 | slot) from the FP64 positions, and the first radix pass's
-// digit counts of each 4096-slot tile.
+// digit counts of each radix tile.
 __global__ __launch_bounds__(kB) void k_pm_keys(const float4* __restrict__ pos,
                                                 const float4* __restrict__ lo, int n,
                                                 const float* __restrict__ part, double rmax,

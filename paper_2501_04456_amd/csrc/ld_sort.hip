@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kRT) void k_radix_hist(const unsigned long long* __
 
 // In-place exclusive scan of m counters by one workgroup of 1024: each
 // thread takes 16 consecutive counters per pass (four 16-byte loads), so the
-// 256 x tiles counters of a 250 000-key sort take one pass.
+// 256 x tiles counters of a 250 000-key sort (2048-key tiles) take two passes.
 __global__ __launch_bounds__(1024) void k_radix_scan(unsigned* a, int m) {
     __shared__ unsigned wsum[16];
     const int t = threadIdx.x, lane = t % 64, wv = t / 64;
