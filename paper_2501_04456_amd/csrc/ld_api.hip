@@ -408,7 +408,7 @@ ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* ch
               hipMalloc(&c->sb.tmp_i, sizeof(int) * N) == hipSuccess &&
               hipMalloc(&c->sb.bounds, sizeof(float) * 8) == hipSuccess &&
               hipMalloc(&c->sb.bounds_part, sizeof(float) * 6 * 64) == hipSuccess &&
-              hipMalloc(&c->sb.hist, sizeof(unsigned) * 256 * ld::radix_tiles((int)n)) ==
+              hipMalloc(&c->sb.hist, sizeof(unsigned) * 256 * (ld::radix_tiles((int)n) + 1)) ==
                   hipSuccess;
     if (!ok || ensure_split_capacity(c, c->tune.j_split) != LD_OK) {
         free_all(c);

@@ -185,7 +185,8 @@ struct SortBuffers {
     float* bounds;                       // [8] device scratch
     float* bounds_part;                  // per-block partial min/max
     int bounds_parts;
-    unsigned* hist;                      // [256 * radix_tiles(n)] radix digit counts (or null)
+    unsigned* hist;                      // [256 * (radix_tiles(n) + 1)] radix digit counts
+                                         // and the 256 digit totals (or null)
 };
 hipError_t launch_sort(float4* pos, float4* lo, int* typ, int* oid, int n,
                        const SortBuffers& B, hipStream_t s);
@@ -210,7 +211,7 @@ constexpr int kRadixTile = kRadixThreads * kRadixRounds;
 int radix_tiles(int n);
 
 // Stable sort of keys[0, n) by the high word, which is below 2^bits (LSD
-// radix, 8-bit digits; tmp holds n keys, hist 256 * radix_tiles(n)).
+// radix, 8-bit digits; tmp holds n keys, hist 256 * (radix_tiles(n) + 1)).
 // first_counted: hist already holds the first pass's digit counts.
 // sorted: if given, receives the buffer holding the result (keys or tmp);
 // otherwise the result is copied into keys.

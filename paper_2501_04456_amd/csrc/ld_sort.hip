@@ -7,8 +7,10 @@
 // Sorting is a 64-bit bitonic network: 2048-key chunks are sorted and merged
 // inside LDS, longer strides run as one global compare-exchange pass each.
 // Keys whose sort word is a small integer (a cell index) take a stable LSD
-// radix sort instead: 8-bit digits, per-workgroup digit counts, one scan,
-// and a scatter that ranks equal digits in slot order.
+// radix sort instead: 8-bit digits, per-workgroup digit counts, a scan of
+// each digit's counts over the tiles (one wavefront per digit), and a
+// scatter that adds the digits' own prefix and ranks equal digits in slot
+// order.
 #include "ld_internal.h"
 
 namespace ld {
@@ -167,66 +169,28 @@ __global__ __launch_bounds__(kRT) void k_radix_hist(const unsigned long long* __
     hist[(size_t)t * nwg + blockIdx.x] = h[t];
 }
 
-// In-place exclusive scan of m counters by one workgroup of 1024: each
-// thread takes 16 consecutive counters per pass (four 16-byte loads), so the
-// 256 x tiles counters of a 250 000-key sort (2048-key tiles) take two passes.
-__global__ __launch_bounds__(1024) void k_radix_scan(unsigned* a, int m) {
-    __shared__ unsigned wsum[16];
-    const int t = threadIdx.x, lane = t % 64, wv = t / 64;
+// Per-digit exclusive scan of the tile counts, one wavefront per digit:
+// hist[d * nwg + b] becomes the count of digit d in tiles before b, and
+// hist[256 * nwg + d] the digit's total.  The digits' own prefix is taken
+// by each scatter workgroup, so no single-workgroup pass over all counters
+// remains.
+__global__ __launch_bounds__(256) void k_radix_rows(unsigned* hist, int nwg) {
+    const int d = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
+    unsigned* row = hist + (size_t)d * nwg;
     unsigned carry = 0u;
-    for (int base = 0; base < m; base += 16 * 1024) {
-        const int e0 = base + 16 * t;
-        unsigned v[16], sum = 0u;
-        if (e0 + 16 <= m) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint4 x = *reinterpret_cast<const uint4*>(a + e0 + 4 * q);
-                v[4 * q] = x.x;
-                v[4 * q + 1] = x.y;
-                v[4 * q + 2] = x.z;
-                v[4 * q + 3] = x.w;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = e0 + i < m ? a[e0 + i] : 0u;
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) sum += v[i];
-        unsigned x = sum;
+    for (int b0 = 0; b0 < nwg; b0 += 64) {
+        const int b = b0 + lane;
+        const unsigned v = b < nwg ? row[b] : 0u;
+        unsigned x = v;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const unsigned y = __shfl_up(x, o);
             if (lane >= o) x += y;
         }
-        if (lane == 63) wsum[wv] = x;
-        __syncthreads();
-        unsigned before = 0u, total = 0u;
-        for (int k = 0; k < 16; ++k) {
-            const unsigned ws = wsum[k];
-            if (k < wv) before += ws;
-            total += ws;
-        }
-        unsigned run = carry + before + x - sum;
-        if (e0 + 16 <= m) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint4 o;
-                o.x = run; run += v[4 * q];
-                o.y = run; run += v[4 * q + 1];
-                o.z = run; run += v[4 * q + 2];
-                o.w = run; run += v[4 * q + 3];
-                *reinterpret_cast<uint4*>(a + e0 + 4 * q) = o;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                if (e0 + i < m) a[e0 + i] = run;
-                run += v[i];
-            }
-        }
-        carry += total;
-        __syncthreads();                               // wsum is reused by the next pass
+        if (b < nwg) row[b] = carry + x - v;
+        carry += __shfl(x, 63);
     }
+    if (lane == 0) hist[256 * (size_t)nwg + d] = carry;
 }
 
 // Stable scatter of one tile by digit: a key's destination is its digit's
@@ -242,7 +206,23 @@ __global__ __launch_bounds__(kRT) void k_radix_scatter(const unsigned long long*
     __shared__ unsigned base[256];
     __shared__ unsigned wcnt[kRT / 64][256];
     const int t = threadIdx.x, w = t / 64, l = t % 64;
-    base[t] = hist[(size_t)t * nwg + blockIdx.x];
+    // digit offset = the totals of all smaller digits (an exclusive scan of
+    // the 256 totals) + this digit's count in earlier tiles
+    {
+        const unsigned tot = hist[256 * (size_t)nwg + t];
+        unsigned x = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned y = __shfl_up(x, o);
+            if (l >= o) x += y;
+        }
+        if (l == 63) wcnt[0][w] = x;
+        __syncthreads();
+        unsigned before = 0u;
+        for (int k = 0; k < w; ++k) before += wcnt[0][k];
+        base[t] = before + x - tot + hist[(size_t)t * nwg + blockIdx.x];
+        __syncthreads();                               // wcnt is cleared below
+    }
     const unsigned long long below = (1ull << l) - 1ull;
     // every round's key in flight at once (the rounds below wait on barriers)
     unsigned long long kr[kRRounds];
@@ -348,7 +328,7 @@ hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tm
     for (int shift = 0; shift < bits; shift += 8) {
         if (shift > 0 || !first_counted)
             hipLaunchKernelGGL(k_radix_hist, dim3(nwg), dim3(kRT), 0, s, src, n, shift, hist, nwg);
-        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, hist, 256 * nwg);
+        hipLaunchKernelGGL(k_radix_rows, dim3(64), dim3(256), 0, s, hist, nwg);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nwg), dim3(kRT), 0, s, src, dst, n, shift, hist,
                            nwg);
         unsigned long long* x = src;
