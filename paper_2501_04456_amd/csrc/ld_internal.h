@@ -224,8 +224,9 @@ hipError_t launch_radix_by_high(unsigned long long* keys, unsigned long long* tm
 // key), so the slots of cells a..b are [cfirst[a], cfirst[b + 1]).  Called
 // by every work-item s of a one-dimensional launch over the keys; the slot
 // that starts cell c (previous slot in cell p < c) fills cells p+1 .. c, the
-// last slot cells c+1 .. M, and a wavefront fills each of its gaps together,
-// 64 cells per pass, so long runs of empty cells cost little.
+// last slot cells c+1 .. M.  Gaps of up to 8 cells are filled by their own
+// lane; a wavefront fills each longer gap together, 64 cells per pass, so
+// long runs of empty cells cost little.
 __device__ __forceinline__ void fill_cell_first(const unsigned long long* __restrict__ keys, int n,
                                                 int M, int s, int* cfirst) {
     const int lane = threadIdx.x % 64;
@@ -237,7 +238,10 @@ __device__ __forceinline__ void fill_cell_first(const unsigned long long* __rest
         gap = c != p;
         tail = s == n - 1;
     }
-    unsigned long long todo = __ballot(gap);
+    const bool own = gap && c - p <= 8;
+    if (own)
+        for (int q = p + 1; q <= c; ++q) cfirst[q] = s;
+    unsigned long long todo = __ballot(gap && !own);
     while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
         const int gp = __shfl(p, leader), gc = __shfl(c, leader), gs = __shfl(s, leader);
