@@ -64,6 +64,7 @@ namespace {
 
 constexpr int kB = 256;
 constexpr int kNC = kPmMaxCells * kPmMaxCells * kPmMaxCells;
+constexpr int kPmWin = 4;               // candidates loaded together (2 and 8 are slower)
 
 __global__ __launch_bounds__(kB) void k_pm_absmax(const float4* __restrict__ pos, int n,
                                                   float* part) {
@@ -198,13 +199,13 @@ __global__ __launch_bounds__(kB) void k_pm_forces(const float4* __restrict__ pos
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const int j1 = r1[k];
-        for (int jb = r0[k]; jb < j1; jb += 4) {
-            // four candidates' hi words in flight, then screened in order
-            float4 hq[4];
+        for (int jb = r0[k]; jb < j1; jb += kPmWin) {
+            // kPmWin candidates' hi words in flight, then screened in order
+            float4 hq[kPmWin];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) hq[u] = pos[min(jb + u, j1 - 1)];
+            for (int u = 0; u < kPmWin; ++u) hq[u] = pos[min(jb + u, j1 - 1)];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kPmWin; ++u) {
                 const int j = jb + u;
                 const float4 hj = hq[u];
                 const float sx = hj.x - hi.x, sy = hj.y - hi.y, sz = hj.z - hi.z;
