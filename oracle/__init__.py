@@ -115,7 +115,8 @@ def lib():
                                        dp, dp, dp, C.c_int, dp, dp, dp, dp, dp, dp]
         L.ldo_mlp_backward.restype = C.c_double
         L.ldo_paper_forces.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp,
-                                       C.POINTER(_Params), C.POINTER(_Paper), dp, dp]
+                                       C.POINTER(_Params), C.POINTER(_Paper),
+                                       C.POINTER(C.c_int64), C.c_int64, dp, dp]
         L.ldo_paper_run.argtypes = [C.c_int64, dp, dp, C.POINTER(C.c_int32), dp,
                                     C.POINTER(C.c_int64), C.POINTER(_Params), C.POINTER(_Paper),
                                     C.POINTER(_Radius), C.c_double, C.c_int64, C.c_uint64,
@@ -440,18 +441,21 @@ def make_paper(range_factor: float, kick: float, inertial_mass) -> _Paper:
     return s
 
 
-def paper_forces(pos, type_, charge, params, range_factor: float):
+def paper_forces(pos, type_, charge, params, range_factor: float, rows=None):
     """Pair forces truncated at range_factor (r_i + r_j), r = sigma/2 (section
-    2.2 steps (i)-(ii)): returns (F [n,3], S [n])."""
+    2.2 steps (i)-(ii)): returns (F [m,3], S [m]) for all particles or the
+    listed rows."""
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     type_ = np.ascontiguousarray(type_, dtype=np.int32)
     q = np.ascontiguousarray(charge, dtype=np.float64)
     n = len(type_)
-    F = np.zeros((n, 3))
-    S = np.zeros(n)
+    rows_a = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    k = n if rows is None else len(rows_a)
+    F = np.zeros((k, 3))
+    S = np.zeros(k)
     m = make_paper(range_factor, 0.0, [1.0] * MAX_TYPES)
     lib().ldo_paper_forces(n, _dp(pos), _ip(type_), _dp(q), C.byref(make_params(params)),
-                           C.byref(m), _dp(F), _dp(S))
+                           C.byref(m), None if rows is None else _lp(rows_a), k, _dp(F), _dp(S))
     return F, S
 
 

@@ -121,11 +121,14 @@ typedef struct {
     double inertial_mass[LDO_MAX_TYPES]; /* mass in Newton's equation per type */
 } ldo_paper;
 
-/* Truncated pair forces F [n*3] and S [n] = sum_j |f_LJ| + |f_C| of the pairs
- * in range (either may be NULL).  Pinned against ldo_pair_forces where the two
- * definitions coincide, by Newton's third law and by truncation invariance. */
+/* Truncated pair forces F [m*3] and S [m] = sum_j |f_LJ| + |f_C| of the pairs
+ * in range (either may be NULL) for the rows listed (rows NULL: all n, m = n;
+ * else m = n_rows, each row against all n particles).  Pinned against
+ * ldo_pair_forces where the two definitions coincide, by Newton's third law
+ * and by truncation invariance. */
 void ldo_paper_forces(int64_t n, const double* pos, const int32_t* type, const double* q,
-                      const ldo_params* p, const ldo_paper* m, double* F, double* S);
+                      const ldo_params* p, const ldo_paper* m, const int64_t* rows,
+                      int64_t n_rows, double* F, double* S);
 
 /* Steps of the paper's scheme; x and v [n*3] FP64 updated in place:
  *   v <- v + dt (F_pair + F_ext(R(t + dt)) - gamma v) / m;  v <- v + kick u;

@@ -44,10 +44,13 @@ static double p_eps(const ldo_params* p, int a, int b) {
 }
 
 void ldo_paper_forces(int64_t n, const double* pos, const int32_t* type, const double* q,
-                      const ldo_params* p, const ldo_paper* m, double* F, double* S) {
+                      const ldo_params* p, const ldo_paper* m, const int64_t* rows,
+                      int64_t n_rows, double* F, double* S) {
     const double cq = p->kT * p->bjerrum;
+    const int64_t nr = rows ? n_rows : n;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = 0; k < nr; ++k) {
+        const int64_t i = rows ? rows[k] : k;
         psum fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, ss = {0, 0};
         const int ti = type[i];
         for (int64_t j = 0; j < n; ++j) {
@@ -74,11 +77,11 @@ void ldo_paper_forces(int64_t n, const double* pos, const int32_t* type, const d
             psum_add(&ss, fabs(glj) * r + fabs(k) / r2);
         }
         if (F) {
-            F[3 * i] = psum_get(&fx);
-            F[3 * i + 1] = psum_get(&fy);
-            F[3 * i + 2] = psum_get(&fz);
+            F[3 * k] = psum_get(&fx);
+            F[3 * k + 1] = psum_get(&fy);
+            F[3 * k + 2] = psum_get(&fz);
         }
-        if (S) S[i] = psum_get(&ss);
+        if (S) S[k] = psum_get(&ss);
     }
 }
 
@@ -92,7 +95,7 @@ int64_t ldo_paper_run(int64_t n, double* x, double* v, const int32_t* type, cons
         const int64_t n_now = *step;
         const double t_new = *t + dt;
         const double Rn = ldo_radius_at(R, t_new);   /* step (iii) before step (iv) */
-        ldo_paper_forces(n, x, type, q, p, m, Fp, NULL);
+        ldo_paper_forces(n, x, type, q, p, m, NULL, 0, Fp, NULL);
         int flag = 0;
 #pragma omp parallel for schedule(static) reduction(| : flag)
         for (int64_t i = 0; i < n; ++i) {

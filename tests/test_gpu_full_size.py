@@ -1,0 +1,122 @@
+"""Parity at the benchmark's full sizes, in the configurations bench.py
+times, on sampled rows that the oracle computes one by one:
+
+* the learned far field at N = 250000 (32^3 grid, 5^3 block, MLP
+  503-128-128-3): the exact near part and the exact far part (1e-5 of
+  S_i), the coarse local expansion (1e-4 of its RMS) and the network's
+  per-particle term with BF16 operands (median 1e-4, max 5e-3 of its RMS);
+* the paper's scheme at N = 250000, range 4 (r_i + r_j): truncated pair
+  forces within 2.5e-7 S_i (the FP32 charge slot; see test_gpu_paper);
+* the 256-droplet ensemble: forces of the smallest, median and largest
+  droplet (1e-5 of S_i) and their positions after 20 steps (1e-4)."""
+import math
+
+import numpy as np
+import pytest
+
+from ffweights import oracle_weights, random_packed
+from paper_2501_04456_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ld():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_04456_amd import ldrop
+    ldrop.lib()
+    return ldrop
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def grid_L(pos):
+    m = np.float32(np.abs(np.asarray(pos, np.float32)).max())
+    return float(np.float32(m * np.float32(1.0009765625)))
+
+
+def sample_rows(n, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
+
+
+def test_learned_parts_full_size(ld, orc):
+    w = W.config_learned(n=250000, seed=5)        # the benchmark's evaluation droplet
+    s = ld.System.from_workload(w)
+    s.ff_enable(near_mode=ld.NEAR_BLOCK)           # grid 32, block 5, hidden 128
+    G, B, H = 32, 5, 128
+    L, gn = s.ff_grid()
+    assert gn == G and L == grid_L(w.pos)
+    rows = sample_rows(w.n, 1500, 21)
+    x = w.pos.astype(np.float64)
+    qh = orc.qhat(w.charge, w.params)
+    print(f"learned N={w.n} rows={len(rows)}", flush=True)
+    Fn, Ef = orc.ff_split_block(x, w.type, w.charge, w.params, G, L, B, rows=rows)
+    _, S, _ = orc.pair_forces(x, w.type, w.charge, w.params, rows=rows)
+    assert np.all(np.linalg.norm(s.ff_forces(0)[rows] - Fn, axis=1) <= 1e-5 * S)
+    assert np.all(np.linalg.norm(s.ff_forces(4)[rows] - qh[rows, None] * Ef, axis=1) <= 1e-5 * S)
+    # the coarse part: the oracle's local expansion of every cell, at the rows
+    mom = orc.ff_moments(x, qh, G, L)
+    loc = orc.ff_local(mom, G, L, B)
+    Fc = qh[rows, None] * orc.ff_local_eval(x[rows], G, L, loc)
+    scale = np.sqrt(np.mean(np.sum(Fc ** 2, 1)))
+    assert np.abs(s.ff_forces(1)[rows] - Fc).max() <= 1e-4 * scale
+    # the network's term with random weights
+    K = 4 * B ** 3 + 3
+    wts, sq, _ = s.ff_weights()
+    wp = random_packed(wts.size, K, H, 13)
+    s.ff_set_weights(wp, sq, 0.05)
+    sq32 = float(np.abs((w.charge * math.sqrt(w.params.kT * w.params.bjerrum))
+                        .astype(np.float32)).max())
+    X = orc.ff_features(x[rows], G, L, B, mom, sq32)
+    Fm = qh[rows, None] * 0.05 * orc.mlp_forward(X, oracle_weights(wp, K, H), bf16_mode=True)
+    scale = np.sqrt(np.mean(np.sum(Fm ** 2, 1)))
+    err = np.linalg.norm(s.ff_forces(2)[rows] - Fm, axis=1) / scale
+    assert np.median(err) <= 1e-4 and err.max() <= 5e-3
+
+
+def test_paper_forces_full_size(ld, orc):
+    w = W.config_large(n=250000)
+    s = ld.System.from_workload(w)
+    s.paper_enable(range_factor=4.0, kick=0.05)
+    rows = sample_rows(w.n, 2000, 22)
+    print(f"paper N={w.n} rows={len(rows)}", flush=True)
+    Fg = s.paper_forces()[rows]
+    Fo, So = orc.paper_forces(w.pos, w.type, w.charge, w.params, 4.0, rows=rows)
+    dF = np.linalg.norm(Fg - Fo, axis=1)
+    assert np.all(dF <= 2.5e-7 * So), (dF / np.maximum(So, 1e-300)).max()
+    assert (So > 0).sum() > 100          # the sample holds pairs in range
+
+
+def test_ensemble_full_three_droplets(ld, orc):
+    e = W.config_ensemble()
+    ns = np.array([d.n for d in e.droplets])
+    order = np.argsort(ns, kind="stable")
+    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    print(f"ensemble droplets={len(ns)} picked={pick} n={ns[pick].tolist()}", flush=True)
+    ens = ld.Ensemble(e.droplets)
+    off = ens.offsets
+    F = ens.forces().cpu().numpy()
+    for d in pick:
+        w = e.droplets[d]
+        Fo, So, _ = orc.pair_forces(w.pos, w.type, w.charge, w.params)
+        err = (np.linalg.norm(F[off[d]:off[d + 1]] - Fo, axis=1) / So).max()
+        assert err <= 1e-5, (d, err)
+    steps = 20
+    ens.step(steps, e.dt)
+    try:
+        ens.sync()
+    except ld.NonFinite:
+        pass                              # a jump flag elsewhere in the ensemble is not fatal here
+    xg = ens.positions64()
+    for d in pick:
+        st = orc.State(e.droplets[d])
+        assert st.run(steps, e.dt) == -1
+        err = np.abs(xg[off[d]:off[d + 1]] - st.x).max()
+        assert err <= 1e-4, (d, err)

@@ -172,3 +172,14 @@ def test_kick_magnitude_and_isotropy(oracle_lib):
     assert np.abs(u.mean(0)).max() < 4.0 / np.sqrt(n)
     assert np.allclose((u ** 2).mean(0), 1.0 / 3.0, atol=0.03)
     assert np.allclose(st.x, x0 + dt * st.v, rtol=1e-12)
+
+
+def test_paper_forces_rows_select():
+    """Rows mode returns exactly the listed rows of the all-rows result."""
+    import oracle
+    oracle.lib()
+    w = W.config_small(n=400, seed=9)
+    F, S = oracle.paper_forces(w.pos, w.type, w.charge, w.params, 4.0)
+    rows = np.array([399, 0, 17, 17, 250])
+    Fr, Sr = oracle.paper_forces(w.pos, w.type, w.charge, w.params, 4.0, rows=rows)
+    assert np.array_equal(Fr, F[rows]) and np.array_equal(Sr, S[rows])
