@@ -70,6 +70,9 @@ def parse():
                     help="search the pair kernel launch shape before timing")
     ap.add_argument("--graph", type=int, default=0,
                     help="replay steps from captured HIP graphs (graph_steps)")
+    ap.add_argument("--compare", action="store_true",
+                    help="ensemble: also time the droplets as separate contexts and one "
+                         "droplet with the same sum of N^2")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -275,6 +278,45 @@ def bench_ensemble(a, torch, ldrop, W):
     avg = pair_ms / max(launches, 1)
     achieved = FLOPS_PER_PAIR * pairs / (avg / 1e3) / 1e12
     sps = a.steps / (ms / 1e3)
+    compare = None
+    if a.compare:
+        def timed_ms(fn):
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            fn()
+            t1.record()
+            torch.cuda.synchronize()
+            return t0.elapsed_time(t1)
+
+        # the same droplets as separate contexts, one after another per step
+        systems = [ldrop.System.from_workload(d) for d in e.droplets]
+
+        def naive():
+            for _ in range(a.steps):
+                for sy in systems:
+                    sy.step(1, e.dt)
+
+        for sy in systems:
+            sy.step(1, e.dt)
+        naive_ms = timed_ms(naive)
+        for sy in systems:
+            sy.close()
+        # one droplet of the same composition recipe with N^2 = sum N_d^2
+        n1 = int(round(pairs ** 0.5))
+        d1 = W.config_ensemble(n_drop=1, n_min=n1, n_max=n1, seed=4).droplets[0]
+        s1 = ldrop.System.from_workload(d1)
+        s1.step(max(a.warmup, 1), e.dt)
+        one_ms = timed_ms(lambda: s1.step(a.steps, e.dt))
+        p1 = float(d1.n) * (d1.n - 1)
+        compare = {
+            "naive_per_droplet_steps_per_s": a.steps / (naive_ms / 1e3),
+            "persistent_over_naive": naive_ms / ms,
+            "single_droplet": {"n": d1.n, "steps_per_s": a.steps / (one_ms / 1e3),
+                               "pair_interactions_per_s": p1 * a.steps / (one_ms / 1e3)},
+            "efficiency_vs_single_droplet": (pairs * sps) / (p1 * a.steps / (one_ms / 1e3)),
+        }
     print(json.dumps({
         "metric": "ensemble steps/s & pair-interactions/s",
         "value": sps, "unit": "steps/s", "pair_interactions_per_s": pairs * sps,
@@ -289,6 +331,7 @@ def bench_ensemble(a, torch, ldrop, W):
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED,
                      "traffic": None, "avg_launch_ms": avg, "launches": launches},
+        "compare": compare,
     }), flush=True)
 
 
