@@ -42,7 +42,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="large",
-                    choices=["large", "ensemble", "small", "learned", "paper", "analysis"],
+                    choices=["large", "ensemble", "small", "learned", "paper", "analysis",
+                             "medium"],
                     help="large (default, the headline) / ensemble / small / learned / "
                          "paper (the paper's own truncated-range inertial scheme) / analysis "
                          "(post-processing calls at N=2.5e5)")
@@ -70,6 +71,8 @@ def parse():
                     help="search the pair kernel launch shape before timing")
     ap.add_argument("--graph", type=int, default=0,
                     help="replay steps from captured HIP graphs (graph_steps)")
+    ap.add_argument("--medium-steps", type=int, default=12000,
+                    help="medium: steps of the drying to run and time")
     ap.add_argument("--compare", action="store_true",
                     help="ensemble: also time the droplets as separate contexts and one "
                          "droplet with the same sum of N^2")
@@ -239,6 +242,52 @@ def bench_analysis(a, torch, ldrop, W):
         "unit": "ms (sub-aggregates, dispersed droplet)", "higher_is_better": False,
         "n_gpus": 1, "data": "synthetic", "config": {"workload": "analysis", "n": a.n},
         "times": out}), flush=True)
+
+
+def bench_medium(a, torch, ldrop, W):
+    """The medium droplet (N = 32768, 70/30 charged mix, gravity, rotation,
+    square-law drying from R0 = 120): the drying from its start over
+    --medium-steps steps (default 12000, 60 % of the way to the dry radius;
+    at dt = 5e-4 the compression towards random close packing makes LJ
+    contacts too stiff for the step -- the first too-large move comes at
+    step 13501), timed whole, with the RDF (r_max 10 sigma, 200 bins) and
+    both fractal dimensions of the end state."""
+    import numpy as np
+    w = W.config_medium()
+    s = ldrop.System.from_workload(w)
+    steps = a.medium_steps
+    flagged = []
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    s.step(steps, w.dt)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    try:
+        s.sync()
+    except ldrop.NonFinite as err:
+        flagged.append(str(err))
+    t0 = time.perf_counter()
+    _, _, g, cbar = s.rdf(10.0, 200)
+    rg, df, dbox, K, _ = s.fractal()
+    post_ms = (time.perf_counter() - t0) * 1e3
+    step, t, R = s.state()
+    r = (np.arange(200) + 0.5) * 0.05
+    sps = steps / (ms / 1e3)
+    pairs = float(w.n) * (w.n - 1)
+    print(json.dumps({
+        "metric": "medium droplet drying: steps/s & pair-interactions/s",
+        "value": sps, "unit": "steps/s", "pair_interactions_per_s": pairs * sps,
+        "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": ms / steps,
+        "higher_is_better": True, "dtype": "f32 pair math, f64 totals", "data": "synthetic",
+        "config": {"workload": "medium: N=32768 70/30 droplet, square-law drying, dt=5e-4",
+                   "n": w.n, "dt": w.dt, "jump_flags": flagged},
+        "end_state": {"step": step, "t": t, "R": R, "R_g": rg, "D_f": df, "D_box": dbox,
+                      "box_scales": K, "rdf_first_peak_r": float(r[int(np.argmax(g[:40]))]),
+                      "rdf_first_peak_g": float(np.max(g[:40])), "post_ms": post_ms},
+    }), flush=True)
 
 
 def bench_ensemble(a, torch, ldrop, W):
@@ -457,6 +506,8 @@ def main():
         return bench_learned(a, torch, ldrop, W)
     if a.workload == "paper":
         return bench_paper(a, torch, ldrop, W)
+    if a.workload == "medium":
+        return bench_medium(a, torch, ldrop, W)
     if a.workload == "analysis":
         return bench_analysis(a, torch, ldrop, W)
     w = W.config_large(n=a.n) if a.workload == "large" else W.config_small()
