@@ -610,6 +610,19 @@ def main():
         out["pair_interactions_per_s"] = pairs * out["value"]
         out["ms_per_step"] = ms_g / a.steps
         out["ms_per_step_eager"] = ms / a.steps
+    # informative: the whole state handed back to the host (ld_get_positions,
+    # hi and lo FP32 words of every coordinate) after a step, and the step
+    # rate if every step did that; `value` keeps the inputs resident
+    import numpy as np
+    hp = np.empty((w.n, 3), np.float32)
+    lp = np.empty((w.n, 3), np.float32)
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.positions_into(hp, lp)
+    rb_ms = (time.perf_counter() - t0) * 1e3 / reps
+    out["positions_to_host_ms"] = rb_ms
+    out["steps_per_s_with_positions_to_host"] = 1e3 / (out["ms_per_step"] + rb_ms)
     if not a.no_cpu_baseline and a.workload == "large":
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -337,6 +337,16 @@ class System:
         hi, lo = self.positions()
         return hi.astype(np.float64) + lo.astype(np.float64)
 
+    def positions_into(self, hi: np.ndarray, lo: np.ndarray = None):
+        """Write the FP32 (hi, lo) positions, original order, into given
+        C-contiguous float32 host arrays of shape [n, 3] (lo may be None)."""
+        for a in (hi, lo):
+            if a is not None and (a.dtype != np.float32 or a.shape != (self.n, 3)
+                                  or not a.flags.c_contiguous):
+                raise ValueError("positions_into needs C-contiguous float32 [n, 3] arrays")
+        _check(lib().ld_get_positions(self.h, hi.ctypes.data_as(C.c_void_p),
+                                      None if lo is None else lo.ctypes.data_as(C.c_void_p)))
+
     def set_positions(self, x, x_lo=None):
         """Replace the positions ([n,3] in original order; x_lo the low FP32
         parts or None)."""
