@@ -1250,7 +1250,16 @@ __global__ __launch_bounds__(kFW * 64) void k_mlp_fused(
             o1 = bf16_round(off[1]);
             o2 = bf16_round(off[2]);
         }
-        // layer 1: the 16 rows, columns l and l + 64
+        // layer 1: the 16 rows, columns l and l + 64; every row's cell term
+        // is loaded before the arithmetic so the gathers overlap
+        float av[kMW][2];
+#pragma unroll
+        for (int r = 0; r < kMW; ++r) {
+            const int ocr = __shfl(oc, r);
+            av[r][0] = ocr >= 0 ? Ac[(size_t)ocr * kFH + l] : 0.f;
+            av[r][1] = ocr >= 0 ? Ac[(size_t)ocr * kFH + l + 64] : 0.f;
+        }
+#pragma unroll
         for (int r = 0; r < kMW; ++r) {
             const int ocr = __shfl(oc, r);
             const float f0 = __shfl(o0, r), f1 = __shfl(o1, r), f2 = __shfl(o2, r);
@@ -1259,8 +1268,8 @@ __global__ __launch_bounds__(kFW * 64) void k_mlp_fused(
                 const int col = l + 64 * hh;
                 float a = 0.f;
                 if (ocr >= 0) {
-                    const float z = Ac[(size_t)ocr * kFH + col] + f0 * wo[hh][0] +
-                                    f1 * wo[hh][1] + f2 * wo[hh][2] + bias1[hh];
+                    const float z = av[r][hh] + f0 * wo[hh][0] + f1 * wo[hh][1] +
+                                    f2 * wo[hh][2] + bias1[hh];
                     a = silu_f(z);
                 }
                 act[r][col] = bf16_rne(a);
