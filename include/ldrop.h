@@ -343,6 +343,16 @@ ld_status ld_ff_set_weights(ld_ctx* ctx, const float* w, int64_t count, double s
                             double out_scale);
 ld_status ld_ff_get_weights(ld_ctx* ctx, float* w, int64_t count, double* sq, double* out_scale);
 
+/* Save the trained model (the configuration that fixes its inputs: grid,
+ * block, hidden, near mode, parent reach, near cut; sq, out_scale and the
+ * packed weights) to a binary file, and load it into a context whose
+ * ld_ff_enable configuration matches (else LD_EINVAL naming both).  File:
+ * "LDFFW001", int32 grid, block, hidden, near_mode, parent_reach, 0; FP64
+ * near_cut, sq, out_scale; int64 count; FP32 weights[count].  Errors:
+ * LD_ESTATE (no learned field), LD_EINVAL (path, I/O, format, mismatch). */
+ld_status ld_ff_save(ld_ctx* ctx, const char* path);
+ld_status ld_ff_load(ld_ctx* ctx, const char* path);
+
 /* The cube half width L and near cells per axis for the current positions. */
 ld_status ld_ff_grid(ld_ctx* ctx, double* L, int32_t* near_cells);
 

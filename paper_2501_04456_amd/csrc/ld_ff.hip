@@ -33,6 +33,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <vector>
 #include <new>
 
 #include "ld_ffconv.h"
@@ -2173,6 +2176,63 @@ ld_status ld_ff_get_weights(ld_ctx* c, float* w, int64_t count, double* sq, doub
     if (sq) *sq = c->ff->sq;
     if (out_scale) *out_scale = c->ff->out_scale;
     return LD_OK;
+}
+
+// Model file: "LDFFW001", int32 grid, block, hidden, near_mode, parent_reach,
+// reserved; FP64 near_cut, sq, out_scale; int64 count; FP32 weights[count].
+ld_status ld_ff_save(ld_ctx* c, const char* path) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    if (!path) return fail(LD_EINVAL, "path is NULL");
+    FarField* f = c->ff;
+    std::vector<float> w(f->nW);
+    HIP_TRY(copy_out(w.data(), f->W, sizeof(float) * w.size(), c->stream));
+    const int32_t hdr[6] = {f->cfg.grid, f->cfg.block, f->cfg.hidden, f->cfg.near_mode,
+                            f->cfg.parent_reach, 0};
+    const double dv[3] = {f->cfg.near_cut, (double)f->sq, (double)f->out_scale};
+    const int64_t count = (int64_t)w.size();
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return fail(LD_EINVAL, "cannot open %s for writing", path);
+    const bool ok = std::fwrite("LDFFW001", 1, 8, fp) == 8 && std::fwrite(hdr, 4, 6, fp) == 6 &&
+                    std::fwrite(dv, 8, 3, fp) == 3 && std::fwrite(&count, 8, 1, fp) == 1 &&
+                    std::fwrite(w.data(), 4, w.size(), fp) == w.size();
+    const bool closed = std::fclose(fp) == 0;
+    if (!ok || !closed) return fail(LD_EINVAL, "writing %s failed", path);
+    return LD_OK;
+}
+
+ld_status ld_ff_load(ld_ctx* c, const char* path) {
+    g_err.clear();
+    if (!c || !c->ff) return fail(LD_ESTATE, "ld_ff_enable first");
+    if (!path) return fail(LD_EINVAL, "path is NULL");
+    FarField* f = c->ff;
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(LD_EINVAL, "cannot open %s", path);
+    char magic[8];
+    int32_t hdr[6];
+    double dv[3];
+    int64_t count = 0;
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "LDFFW001", 8) == 0 &&
+              std::fread(hdr, 4, 6, fp) == 6 && std::fread(dv, 8, 3, fp) == 3 &&
+              std::fread(&count, 8, 1, fp) == 1;
+    if (!ok) {
+        std::fclose(fp);
+        return fail(LD_EINVAL, "%s is not a model file", path);
+    }
+    if (hdr[0] != f->cfg.grid || hdr[1] != f->cfg.block || hdr[2] != f->cfg.hidden ||
+        hdr[3] != f->cfg.near_mode || hdr[4] != f->cfg.parent_reach ||
+        (f->cfg.near_mode == 0 && dv[0] != f->cfg.near_cut) || count != (int64_t)f->nW) {
+        std::fclose(fp);
+        return fail(LD_EINVAL,
+                    "%s holds a model for grid %d, block %d, hidden %d, near mode %d, parent "
+                    "reach %d (near cut %g), not this configuration",
+                    path, hdr[0], hdr[1], hdr[2], hdr[3], hdr[4], dv[0]);
+    }
+    std::vector<float> w((size_t)count);
+    ok = std::fread(w.data(), 4, w.size(), fp) == w.size();
+    std::fclose(fp);
+    if (!ok) return fail(LD_EINVAL, "%s is truncated", path);
+    return ld_ff_set_weights(c, w.data(), count, dv[1], dv[2]);
 }
 
 ld_status ld_ff_grid(ld_ctx* c, double* L, int32_t* near_cells) {

@@ -106,7 +106,7 @@ SYMBOLS = [
     "ld_ens_kernel_time",
     "ld_paper_enable", "ld_paper_disable", "ld_paper_forces", "ld_paper_get_velocities",
     "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count", "ld_record_open",
-    "ld_record_close", "ld_cbar_type", "ld_surface_fractal",
+    "ld_record_close", "ld_cbar_type", "ld_surface_fractal", "ld_ff_save", "ld_ff_load",
 ]
 
 _lib = None
@@ -177,6 +177,8 @@ def lib():
         L.ld_paper_set_velocities.argtypes = [vp, dp]
         L.ld_aggregates.argtypes = [vp, C.c_double, vp, vp]
         L.ld_surface_count.argtypes = [vp, C.c_double, vp]
+        L.ld_ff_save.argtypes = [vp, C.c_char_p]
+        L.ld_ff_load.argtypes = [vp, C.c_char_p]
         L.ld_surface_fractal.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double,
                                          vp, vp, vp]
         L.ld_record_open.argtypes = [vp, C.c_char_p, C.c_int32]
@@ -519,6 +521,15 @@ class System:
         _check(lib().ld_ff_get_weights(self.h, w.ctypes.data_as(C.c_void_p), n, C.byref(sq),
                                        C.byref(sc)))
         return w, sq.value, sc.value
+
+    def ff_save(self, path: str):
+        """Write the learned model (configuration, scales, weights) to path."""
+        _check(lib().ld_ff_save(self.h, os.fsencode(path)))
+
+    def ff_load(self, path: str):
+        """Load a model written by ff_save; the learned field must be
+        enabled with the same configuration."""
+        _check(lib().ld_ff_load(self.h, os.fsencode(path)))
 
     def ff_set_weights(self, w, sq: float, out_scale: float):
         w = np.ascontiguousarray(w, np.float32)

@@ -264,3 +264,31 @@ def test_training_gain_and_judge(ld, sysw):
     assert st["fallbacks"] == 0 and st["learned_steps"] == 12
     x = s.positions64()
     assert np.all(np.isfinite(x))
+
+
+def test_model_save_load(ld, sysw, tmp_path):
+    """A saved model loads into a context with the same configuration and
+    gives the same weights, scales and learned forces; another configuration
+    or a damaged file is refused."""
+    s = make_sys(ld, sysw, hidden=64)
+    K = 4 * B ** 3 + 3
+    w, sq, _ = s.ff_weights()
+    s.ff_set_weights(random_packed(w.size, K, 64, 17), sq, 0.05)
+    path = str(tmp_path / "model.ldff")
+    s.ff_save(path)
+    s2 = make_sys(ld, sysw, hidden=64)
+    s2.ff_load(path)
+    w1, sq1, sc1 = s.ff_weights()
+    w2, sq2, sc2 = s2.ff_weights()
+    assert np.array_equal(w1, w2) and sq1 == sq2 and sc1 == sc2
+    assert np.array_equal(s.ff_forces(3), s2.ff_forces(3))
+    s3 = make_sys(ld, sysw, hidden=128)
+    with pytest.raises(RuntimeError):
+        s3.ff_load(path)
+    bad = tmp_path / "bad.ldff"
+    bad.write_bytes(open(path, "rb").read()[:100])
+    with pytest.raises(RuntimeError):
+        s2.ff_load(str(bad))
+    bad.write_bytes(b"not a model at all")
+    with pytest.raises(RuntimeError):
+        s2.ff_load(str(bad))
