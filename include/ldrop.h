@@ -90,14 +90,20 @@ typedef struct {
 
 /* Droplet radius schedule (section 2.1: radius-square law with a freely
  * defined rate, or no movement; section 2.2 step (iii)).  Step n uses the
- * radius at the end of the step, R(t_n + dt). */
-enum { LD_R_CONST = 0, LD_R_LINEAR = 1, LD_R_SQUARE_LAW = 2 };
+ * radius at the end of the step, R(t_n + dt).  LD_R_TABLE: a freely defined
+ * history, piecewise linear between n_knots knots (tab_t strictly
+ * increasing), R(t) = tab_R[0] before the first knot and tab_R[n_knots - 1]
+ * after the last. */
+enum { LD_R_CONST = 0, LD_R_LINEAR = 1, LD_R_SQUARE_LAW = 2, LD_R_TABLE = 3 };
+#define LD_R_TABLE_MAX 16
 typedef struct {
     int32_t kind;
-    int32_t reserved;
+    int32_t n_knots;       /* table: knots used, 2..LD_R_TABLE_MAX (else ignored) */
     double R0, R1, T;      /* linear: R0 -> R1 over time T, then constant */
     double a;              /* square law: R^2 = R0^2 - 2 a t  (dR/dt = -a/R) */
     double R_min;          /* square law: R is clamped at R_min */
+    double tab_t[LD_R_TABLE_MAX];  /* table: knot times */
+    double tab_R[LD_R_TABLE_MAX];  /* table: radii at the knots (>= 0) */
 } ld_radius;
 
 /* Launch configuration of the pair kernel (filled in by ld_autotune or set

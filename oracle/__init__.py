@@ -55,10 +55,14 @@ class _Paper(C.Structure):
                 ("inertial_mass", C.c_double * MAX_TYPES)]
 
 
+R_TABLE_MAX = 16
+
+
 class _Radius(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("R0", C.c_double),
+    _fields_ = [("kind", C.c_int32), ("n_knots", C.c_int32), ("R0", C.c_double),
                 ("R1", C.c_double), ("T", C.c_double), ("a", C.c_double),
-                ("R_min", C.c_double)]
+                ("R_min", C.c_double), ("tab_t", C.c_double * R_TABLE_MAX),
+                ("tab_R", C.c_double * R_TABLE_MAX)]
 
 
 _lib = None
@@ -178,6 +182,12 @@ def make_params(p) -> _Params:
 def make_radius(r) -> _Radius:
     s = _Radius()
     s.kind, s.R0, s.R1, s.T, s.a, s.R_min = r.kind, r.R0, r.R1, r.T, r.a, r.R_min
+    kt, kr = tuple(getattr(r, "knots_t", ())), tuple(getattr(r, "knots_R", ()))
+    if len(kt) != len(kr) or len(kt) > R_TABLE_MAX:
+        raise ValueError("radius table: knots_t and knots_R of equal length <= 16")
+    s.n_knots = len(kt)
+    for k, (tk, rk) in enumerate(zip(kt, kr)):
+        s.tab_t[k], s.tab_R[k] = tk, rk
     return s
 
 

@@ -89,6 +89,16 @@ double ldo_radius_at(const ldo_radius* R, double t) {
         if (r2 < m2) r2 = m2;
         return sqrt(r2);
     }
+    if (R->kind == LDO_R_TABLE) {
+        /* the knot interval holding t, by a plain scan from the end */
+        const int m = R->n_knots;
+        if (t >= R->tab_t[m - 1]) return R->tab_R[m - 1];
+        if (t <= R->tab_t[0]) return R->tab_R[0];
+        int k = m - 1;
+        while (R->tab_t[k - 1] > t) --k;
+        const double w = (t - R->tab_t[k - 1]) / (R->tab_t[k] - R->tab_t[k - 1]);
+        return (1.0 - w) * R->tab_R[k - 1] + w * R->tab_R[k];
+    }
     return R->R0;
 }
 

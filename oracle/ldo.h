@@ -60,13 +60,16 @@ typedef struct {
 
 /* Droplet radius schedule (section 2.1: radius-square law with a freely set
  * rate; section 2.2 step (iii)). */
-enum { LDO_R_CONST = 0, LDO_R_LINEAR = 1, LDO_R_SQUARE_LAW = 2 };
+enum { LDO_R_CONST = 0, LDO_R_LINEAR = 1, LDO_R_SQUARE_LAW = 2, LDO_R_TABLE = 3 };
+#define LDO_R_TABLE_MAX 16
 typedef struct {
     int32_t kind;
-    int32_t reserved;
+    int32_t n_knots;    /* table: knots used */
     double R0, R1, T;   /* linear: R0 -> R1 over time T, then constant */
     double a;           /* square law: R^2 = R0^2 - 2 a t (a < 0: condensation) */
     double R_min;       /* square law: clamp R >= R_min (dry aggregate) */
+    double tab_t[LDO_R_TABLE_MAX];  /* table: increasing knot times */
+    double tab_R[LDO_R_TABLE_MAX];  /* table: radii; linear in between, end values outside */
 } ldo_radius;
 
 /* --- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Pinned against

@@ -88,8 +88,19 @@ ld_status check_params(const ld_params* p) {
 
 ld_status check_radius(const ld_radius* R) {
     if (!R) return fail(LD_EINVAL, "radius schedule is NULL");
-    if (R->kind < LD_R_CONST || R->kind > LD_R_SQUARE_LAW)
+    if (R->kind < LD_R_CONST || R->kind > LD_R_TABLE)
         return fail(LD_EINVAL, "radius kind %d unknown", R->kind);
+    if (R->kind == LD_R_TABLE) {
+        if (R->n_knots < 2 || R->n_knots > LD_R_TABLE_MAX)
+            return fail(LD_EINVAL, "a radius table needs 2..%d knots", LD_R_TABLE_MAX);
+        for (int k = 0; k < R->n_knots; ++k) {
+            if (!std::isfinite(R->tab_t[k]) || !std::isfinite(R->tab_R[k]) || R->tab_R[k] < 0.0)
+                return fail(LD_EINVAL, "radius table knot %d: finite time and radius >= 0", k);
+            if (k > 0 && !(R->tab_t[k] > R->tab_t[k - 1]))
+                return fail(LD_EINVAL, "radius table times must increase strictly");
+        }
+        return LD_OK;
+    }
     if (!std::isfinite(R->R0) || R->R0 < 0.0) return fail(LD_EINVAL, "R0 must be >= 0");
     if (R->kind == LD_R_LINEAR && (!std::isfinite(R->R1) || R->R1 < 0.0 || !(R->T >= 0.0)))
         return fail(LD_EINVAL, "linear schedule needs R1 >= 0 and T >= 0");
@@ -866,7 +877,7 @@ ld_status ld_set_tuning(ld_ctx* c, const ld_tuning* t) {
 }
 
 namespace {
-constexpr char kMagic[8] = {'L', 'D', 'R', 'O', 'P', 'C', 'K', '1'};
+constexpr char kMagic[8] = {'L', 'D', 'R', 'O', 'P', 'C', 'K', '2'};
 }
 
 ld_status ld_checkpoint_save(ld_ctx* c, const char* path) {

@@ -47,9 +47,8 @@ struct ExtParams {
     ld_radius R;
 };
 
-// Device-resident step state.  Kernels of a step read it; the last
-// workgroup of the update kernel advances it, so captured graphs replay
-// correctly.
+// Device-resident step state.  Kernels of a step read it; a one-thread
+// kernel after the update advances it, so captured graphs replay correctly.
 struct DevState {
     long long step;                      // global step counter n
     double t;                            // time t_n
@@ -73,6 +72,16 @@ __host__ __device__ inline double radius_at(const ld_radius& R, double t) {
         double r2 = R.R0 * R.R0 - 2.0 * R.a * t;
         double m2 = R.R_min * R.R_min;
         return sqrt(r2 < m2 ? m2 : r2);
+    }
+    if (R.kind == LD_R_TABLE) {
+        const int m = R.n_knots;
+        if (t <= R.tab_t[0]) return R.tab_R[0];
+        for (int k = 1; k < m; ++k)
+            if (t < R.tab_t[k]) {
+                const double f = (t - R.tab_t[k - 1]) / (R.tab_t[k] - R.tab_t[k - 1]);
+                return R.tab_R[k - 1] + (R.tab_R[k] - R.tab_R[k - 1]) * f;
+            }
+        return R.tab_R[m - 1];
     }
     return R.R0;
 }

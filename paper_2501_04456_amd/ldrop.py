@@ -51,9 +51,10 @@ class ld_params(C.Structure):
 
 
 class ld_radius(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("R0", C.c_double),
+    _fields_ = [("kind", C.c_int32), ("n_knots", C.c_int32), ("R0", C.c_double),
                 ("R1", C.c_double), ("T", C.c_double), ("a", C.c_double),
-                ("R_min", C.c_double)]
+                ("R_min", C.c_double), ("tab_t", C.c_double * W.RADIUS_TABLE_MAX),
+                ("tab_R", C.c_double * W.RADIUS_TABLE_MAX)]
 
 
 class ld_tuning(C.Structure):
@@ -223,6 +224,11 @@ def make_params(p: W.Params) -> ld_params:
 def make_radius(r: W.Radius) -> ld_radius:
     s = ld_radius()
     s.kind, s.R0, s.R1, s.T, s.a, s.R_min = r.kind, r.R0, r.R1, r.T, r.a, r.R_min
+    if len(r.knots_t) != len(r.knots_R) or len(r.knots_t) > W.RADIUS_TABLE_MAX:
+        raise ValueError("radius table: knots_t and knots_R of equal length <= 16")
+    s.n_knots = len(r.knots_t)
+    for k, (tk, rk) in enumerate(zip(r.knots_t, r.knots_R)):
+        s.tab_t[k], s.tab_R[k] = tk, rk
     return s
 
 

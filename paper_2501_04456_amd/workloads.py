@@ -48,6 +48,8 @@ MAX_TYPES = 8
 RADIUS_CONST = 0
 RADIUS_LINEAR = 1
 RADIUS_SQUARE_LAW = 2
+RADIUS_TABLE = 3
+RADIUS_TABLE_MAX = 16
 
 NOISE_OFF = 0
 NOISE_GAUSS = 1
@@ -88,6 +90,8 @@ class Radius:
     T: float = 0.0
     a: float = 0.0
     R_min: float = 0.0
+    knots_t: tuple = ()      # RADIUS_TABLE: increasing knot times
+    knots_R: tuple = ()      # RADIUS_TABLE: radii at the knots
 
 
 @dataclasses.dataclass

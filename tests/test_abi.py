@@ -59,7 +59,7 @@ def test_struct_layouts_match_header():
                 fields.append(re.sub(r"\[.*\]", "", f).strip())
         assert [f[0] for f in py._fields_] == fields, cname
     assert C.sizeof(ldrop.ld_params) == 8 + 6 * 8 * 8 + 64 * 8 + 4 * 8 + 3 * 8 + 8 + 16 + 8
-    assert C.sizeof(ldrop.ld_radius) == 48
+    assert C.sizeof(ldrop.ld_radius) == 48 + 2 * 16 * 8
     assert C.sizeof(ldrop.ld_ff_config) == 40
     assert C.sizeof(ldrop.ld_paper_config) == 16 + 8 * 8
 

@@ -218,6 +218,25 @@ def test_trajectory_band_wall_axial_rotation(ld, orc):
     assert np.abs(xg - xo).max() <= POS_TOL
 
 
+def test_trajectory_radius_table(ld, orc):
+    """A tabulated radius history (fast shrink, hold, re-growth within the
+    run): positions against the oracle and R(t) against its schedule; a bad
+    table is refused."""
+    w = W.config_small(n=800, seed=31)
+    R0 = w.radius.R0
+    w.radius = W.Radius(kind=W.RADIUS_TABLE, knots_t=(0.0, 0.01, 0.02, 0.03),
+                        knots_R=(R0, 0.6 * R0, 0.6 * R0, 0.8 * R0))
+    xg, xo = trajectory(ld, orc, w, 40)
+    assert np.abs(xg - xo).max() <= POS_TOL
+    s = ld.System.from_workload(w)
+    s.step(25, w.dt)
+    step, t, R = s.state()
+    assert R == pytest.approx(orc.radius_at(w.radius, t), rel=1e-14)
+    bad = W.Radius(kind=W.RADIUS_TABLE, knots_t=(0.0, 0.02, 0.01), knots_R=(R0, R0, R0))
+    with pytest.raises(ld.LdError):
+        ld.System(w.type, w.charge, w.pos, w.params, bad, 1)
+
+
 def test_determinism_and_split_invariance(ld):
     w = W.config_large(n=4000, seed=2)
     a = ld.System.from_workload(w)

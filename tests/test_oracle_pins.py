@@ -81,6 +81,23 @@ def test_gauss3_statistics(oracle_lib):
 # Radius schedule
 # ---------------------------------------------------------------------------
 
+def test_radius_table(oracle_lib):
+    """A piecewise-linear history (shrink, hold, condense) equals numpy's
+    linear interpolation with the end values held outside the knots, and
+    passes through every knot exactly."""
+    kt = (0.0, 1.0, 2.0, 3.5, 4.0)
+    kr = (40.0, 30.0, 30.0, 45.0, 44.0)
+    r = W.Radius(kind=W.RADIUS_TABLE, knots_t=kt, knots_R=kr)
+    for tk, rk in zip(kt, kr):
+        assert oracle_lib.radius_at(r, tk) == rk
+    assert oracle_lib.radius_at(r, 0.25) == pytest.approx(37.5, abs=1e-13)
+    assert oracle_lib.radius_at(r, 1.5) == 30.0
+    assert oracle_lib.radius_at(r, -3.0) == 40.0 and oracle_lib.radius_at(r, 9.0) == 44.0
+    ts = np.random.default_rng(3).uniform(-1.0, 5.0, 500)
+    got = np.array([oracle_lib.radius_at(r, t) for t in ts])
+    assert np.allclose(got, np.interp(ts, kt, kr), rtol=0, atol=1e-12)
+
+
 def test_radius_closed_forms(oracle_lib):
     r = W.Radius(kind=W.RADIUS_LINEAR, R0=40.0, R1=15.0, T=1.0)
     assert oracle_lib.radius_at(r, 0.0) == 40.0
