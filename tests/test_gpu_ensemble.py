@@ -179,3 +179,24 @@ def test_autotune_and_cache(ld, orc, tmp_path):
     s2 = ld.System.from_workload(w)
     t2 = s2.autotune(cache_path=cache)
     assert (t2["block"], t2["j_split"]) == (t1["block"], t1["j_split"])
+
+
+def test_ensemble_radius_tables(ld, orc):
+    """Droplets with tabulated radius histories (shrink then hold, or grow)
+    beside a square-law one, each against its own oracle run."""
+    e = W.config_ensemble(n_drop=3, n_min=300, n_max=900, seed=13)
+    for d, f in ((0, 0.95), (2, 1.3)):
+        R0 = e.droplets[d].radius.R0
+        e.droplets[d].radius = W.Radius(kind=W.RADIUS_TABLE, knots_t=(0.0, 0.02, 0.05),
+                                        knots_R=(R0, f * R0, f * R0))
+    ens = ld.Ensemble(e.droplets)
+    steps = 20
+    ens.step(steps, e.dt)
+    ens.sync()
+    xg = ens.positions64()
+    off = ens.offsets
+    for d, w in enumerate(e.droplets):
+        st = orc.State(w)
+        assert st.run(steps, e.dt) == -1
+        err = np.abs(xg[off[d]:off[d + 1]] - st.x).max()
+        assert err <= 1e-4, (d, err)
