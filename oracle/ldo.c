@@ -91,7 +91,8 @@ double ldo_radius_at(const ldo_radius* R, double t) {
     }
     if (R->kind == LDO_R_TABLE) {
         /* the knot interval holding t, by a plain scan from the end */
-        const int m = R->n_knots;
+        const int m = R->n_knots < LDO_R_TABLE_MAX ? R->n_knots : LDO_R_TABLE_MAX;
+        if (m < 1) return R->R0;      /* no table: the library refuses such a schedule */
         if (t >= R->tab_t[m - 1]) return R->tab_R[m - 1];
         if (t <= R->tab_t[0]) return R->tab_R[0];
         int k = m - 1;
