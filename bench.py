@@ -478,7 +478,7 @@ def bench_learned(a, torch, ldrop, W):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "ldrop runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
 

@@ -225,7 +225,7 @@ ld_status ld_diagnostics(ld_ctx* ctx, double out[10]);
 ld_status ld_rdf(ld_ctx* ctx, double r_max, int32_t n_bins, double V, int32_t centre,
                  uint64_t* counts, double* g, uint64_t* ccounts, double* cbar);
 
-/* Eq. (8) for the NPs of one type (the survey's per-type C-bar): ccounts
+/* Eq. (8) for the NPs of one type (C-bar of a single type): ccounts
  * [n_bins] uint64 counts of type-`type` NPs at distance [b dr, (b+1) dr)
  * from the centre (0 droplet centre, 1 centre of mass of all NPs), cbar
  * [n_bins] = (count / N_type) / (dV_b / V), V <= 0: the droplet volume.
