@@ -73,14 +73,18 @@ def test_components_match_oracle(ld, orc, n, seed, f):
 
 
 def test_components_on_the_headline_droplet(ld, orc):
-    """The large composition (three types) after a few steps, contact 1.1."""
+    """The large composition (three types) after a few steps, contact 1.1:
+    the oracle takes the steps and the GPU is given the resulting state as
+    (hi, lo) FP32 pairs, whose sum both sides then use."""
     w = W.config_large(n=4000, seed=9)
+    st = orc.State(w)
+    assert st.run(10, w.dt) == -1
+    hi = st.x.astype(np.float32)
+    lo = (st.x - hi.astype(np.float64)).astype(np.float32)
+    x = hi.astype(np.float64) + lo.astype(np.float64)
     s = ld.System.from_workload(w)
-    s.step(10, w.dt)
-    s.sync()
-    x = s.positions64()
+    s.set_positions(hi, lo)
     g = s.aggregates(1.1, labels=True)
-    # compare at the positions the GPU used (FP64 hi + lo)
     nc, lab = orc.components(x, w.type, w.params, 1.1)
     assert g["components"] == nc and np.array_equal(g["labels"].astype(np.int64), lab)
 

@@ -81,6 +81,7 @@ def test_block_near_and_far_exact_parts(ld, orc, sysw, block):
     s.ff_enable(grid=G, block=block, hidden=64, near_mode=ld.NEAR_BLOCK)
     L, gn = s.ff_grid()
     assert L == grid_L(sysw.pos) and gn == G
+    L = grid_L(sysw.pos)                   # the oracle takes the test's own value
     Fn_g = s.ff_forces(0)
     Ff_g = s.ff_forces(4)
     x = sysw.pos.astype(np.float64)
@@ -102,7 +103,8 @@ def test_block_near_ragged_small(ld, orc):
         s = ld.System.from_workload(w)
         s.ff_enable(grid=grid, block=3, hidden=16, near_mode=ld.NEAR_BLOCK,
                     parent_reach=0 if grid % 2 else 3)
-        L, _ = s.ff_grid()
+        L = grid_L(w.pos)
+        assert s.ff_grid()[0] == L
         Fn, Ef = orc.ff_split_block(x, w.type, w.charge, w.params, grid, L, 3)
         assert np.all(np.linalg.norm(s.ff_forces(0) - Fn, axis=1) <= 1e-5 * S), grid
 
@@ -114,7 +116,8 @@ def test_block_near_dense_rows(ld, orc, sysw, grid, block):
     later piece; block 1 takes the row-window walk (LJ reach beyond it)."""
     s = ld.System.from_workload(sysw)
     s.ff_enable(grid=grid, block=block, hidden=16, near_mode=ld.NEAR_BLOCK, parent_reach=0)
-    L, _ = s.ff_grid()
+    L = grid_L(sysw.pos)
+    assert s.ff_grid()[0] == L
     x = sysw.pos.astype(np.float64)
     Fn, _ = orc.ff_split_block(x, sysw.type, sysw.charge, sysw.params, grid, L, block)
     _, S, _ = orc.pair_forces(x, sysw.type, sysw.charge, sysw.params)

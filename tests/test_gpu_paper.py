@@ -126,11 +126,13 @@ def test_paper_mode_guards_and_back(ld, orc):
     s.paper_disable()
     with pytest.raises(RuntimeError):
         s.velocities()
-    # back on the overdamped scheme: forces still match the all-pairs oracle
-    x = s.positions64()
-    Fo, So, _ = orc.pair_forces(s.positions()[0].astype(np.float64), w.type, w.charge, w.params)
+    # back on the overdamped scheme: from the initial positions again, the
+    # forces match the all-pairs oracle
+    s.set_positions(w.pos)
+    Fo, So, _ = orc.pair_forces(w.pos.astype(np.float64), w.type, w.charge, w.params)
     Fg = s.forces(ext=False)["pair"].cpu().numpy()
     assert np.all(np.linalg.norm(Fg - Fo, axis=1) <= 1e-5 * So)
     s.step(5, w.dt)
     assert s.state()[0] == 15
-    assert np.isfinite(s.positions64()).all() and np.abs(s.positions64() - x).max() > 0
+    x = s.positions64()
+    assert np.isfinite(x).all() and np.abs(x - w.pos.astype(np.float64)).max() > 0

@@ -160,33 +160,6 @@ def test_forces_full_size_sampled(ld, orc):
     assert err <= 1e-6, err
 
 
-def test_full_size_twenty_steps_stepwise(ld, orc):
-    """N = 250000, 20 consecutive steps in the benchmark's launch shape: from
-    each GPU state the oracle advances a sample of rows one step (their pair
-    forces against all N particles, the external forces and the same noise)
-    and the GPU's next positions of those rows must agree within 1e-6."""
-    w = W.config_large()
-    s = ld.System.from_workload(w)
-    rng = np.random.default_rng(5)
-    rows = np.sort(np.concatenate([rng.choice(w.n, 198, replace=False), [0, w.n - 1]]))
-    st = orc.State(w)
-    worst = 0.0
-    for k in range(20):
-        xk = s.positions64()
-        step, t, _ = s.state()
-        assert step == k
-        st.x = xk.copy()
-        st.step, st.t = step, t
-        xo, bad = st.step_rows(rows, w.dt)
-        assert bad == -1
-        keep = ~ambiguous_rows(w.replace(pos=xk), rows)
-        s.step(1, w.dt)
-        err = np.abs(s.positions64()[rows][keep] - xo[keep]).max()
-        worst = max(worst, err)
-        assert err <= 1e-6, (k, err)
-    print(f"stepwise N={w.n} rows={len(rows)} steps=20 worst={worst:.3g}", flush=True)
-
-
 # ---------------------------------------------------------------------------
 # Trajectories
 # ---------------------------------------------------------------------------
