@@ -443,6 +443,73 @@ __global__ __launch_bounds__(kB) void k_sf_theta(const float4* __restrict__ pos,
     if (threadIdx.x == 0) dpart[blockIdx.x] = red[0];
 }
 
+constexpr int kRdfMaxBins = 4096;
+
+__global__ __launch_bounds__(kB) void k_ag_zero64(unsigned long long* a, int m) {
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k < m) a[k] = 0ull;
+}
+
+// Pair-distance histogram of Eq. (6) from the cell-sorted slots (cells of
+// side >= r_max): every pair (k, m), m > k in sorted order, over the 27
+// cells around k's.  The distance is formed exactly as in the all-pairs
+// histogram (FP64 hi + lo, the same operand order, no contraction; the
+// squares make it independent of the pair's orientation), so every pair
+// falls in the same bin.
+__global__ __launch_bounds__(kB) void k_ag_rdf(const float4* __restrict__ pos,
+                                               const float4* __restrict__ lo,
+                                               const unsigned long long* __restrict__ keys,
+                                               const AgGrid* __restrict__ g,
+                                               const int* __restrict__ cstart,
+                                               const int* __restrict__ cend, int n, double r_max,
+                                               int n_bins, double dr,
+                                               unsigned long long* counts) {
+#pragma clang fp contract(off)
+    __shared__ unsigned int hist[kRdfMaxBins];
+    for (int b = threadIdx.x; b < n_bins; b += kB) hist[b] = 0u;
+    __syncthreads();
+    const int k = blockIdx.x * kB + threadIdx.x;
+    if (k < n) {
+        const unsigned long long key = keys[k];
+        const int i = (int)(unsigned)key;
+        const float4 hi = pos[i], li = lo[i];
+        const double xi = (double)hi.x + (double)li.x, yi = (double)hi.y + (double)li.y,
+                     zi = (double)hi.z + (double)li.z;
+        const int G = g->Gc;
+        const int c = (int)(key >> 32);
+        const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int z = cz + dz;
+            if (z < 0 || z >= G) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int y = cy + dy;
+                if (y < 0 || y >= G) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int x = cx + dx;
+                    if (x < 0 || x >= G) continue;
+                    const int cc = (z * G + y) * G + x;
+                    const int m1 = cend[cc];
+                    for (int m = max(cstart[cc], k + 1); m < m1; ++m) {
+                        const int j = (int)(unsigned)keys[m];
+                        const float4 hj = pos[j], lj = lo[j];
+                        const double ex = xi - ((double)hj.x + (double)lj.x);
+                        const double ey = yi - ((double)hj.y + (double)lj.y);
+                        const double ez = zi - ((double)hj.z + (double)lj.z);
+                        const double r = sqrt(ex * ex + ey * ey + ez * ez);
+                        if (r < r_max) {
+                            const int b = (int)floor(r / dr);
+                            if (b >= 0 && b < n_bins) atomicAdd(&hist[b], 1u);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < n_bins; b += kB)
+        if (hist[b]) atomicAdd(&counts[b], (unsigned long long)hist[b]);
+}
+
 #define AG_LAUNCH(kernel, grid, block, ...)                                               \
     do {                                                                                  \
         hipLaunchKernelGGL(kernel, grid, block, 0, __VA_ARGS__);                          \
@@ -519,20 +586,20 @@ double ag_table(const ld_ctx* c, double contact_factor, AgTable* tb) {
     return rc;
 }
 
-// Cell sort, lock-free union of the contact pairs (with surf: only pairs of
-// two surface NPs), roots, and per root the size and smallest original index
-// (counting only surface NPs with surf).  *keys_out: the cell-sorted keys.
-hipError_t ag_union(ld_ctx* c, const AgBufs& b, const AgTable& tb, double rc, const int* surf,
-                    unsigned long long** keys_out) {
-    const int n = (int)c->n;
-    hipStream_t s = c->stream;
-    const int blocks = (n + kB - 1) / kB;
 #define AG_RUN(kernel, grid, ...)                                                         \
     do {                                                                                  \
         hipLaunchKernelGGL(kernel, grid, dim3(kB), 0, s, __VA_ARGS__);                    \
         const hipError_t e_ = hipGetLastError();                                          \
         if (e_ != hipSuccess) return e_;                                                  \
     } while (0)
+
+// Cell sort for cells of side >= rc: grid, keys (cell << 32 | slot) sorted by
+// cell, and every cell's slot range [cstart, cend).  *keys_out: the sorted
+// keys.
+hipError_t ag_cells(ld_ctx* c, const AgBufs& b, double rc, unsigned long long** keys_out) {
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    const int blocks = (n + kB - 1) / kB;
     AG_RUN(k_ag_absmax, dim3(64), c->pos, n, c->sb.bounds_part);
     const int nwg = radix_tiles(n);
     AG_RUN(k_ag_keys, dim3(nwg), c->pos, c->lo, n, c->sb.bounds_part, rc, b.grid, c->sb.keys,
@@ -548,6 +615,22 @@ hipError_t ag_union(ld_ctx* c, const AgBufs& b, const AgTable& tb, double rc, co
     AG_RUN(k_ag_fill, gc, b.cstart, kANC, 0);
     AG_RUN(k_ag_fill, gc, b.cend, kANC, 0);
     AG_RUN(k_ag_ranges, gn, keys, n, b.cstart, b.cend);
+    *keys_out = keys;
+    return hipSuccess;
+}
+
+// Cell sort, lock-free union of the contact pairs (with surf: only pairs of
+// two surface NPs), roots, and per root the size and smallest original index
+// (counting only surface NPs with surf).  *keys_out: the cell-sorted keys.
+hipError_t ag_union(ld_ctx* c, const AgBufs& b, const AgTable& tb, double rc, const int* surf,
+                    unsigned long long** keys_out) {
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    const int blocks = (n + kB - 1) / kB;
+    const dim3 gn(blocks);
+    unsigned long long* keys = nullptr;
+    const hipError_t ec = ag_cells(c, b, rc, &keys);
+    if (ec != hipSuccess) return ec;
     AG_RUN(k_ag_iota, gn, b.parent, n);
     AG_RUN(k_ag_fill, dim3(1), b.err, 1, 0);
     if (surf)
@@ -570,6 +653,38 @@ hipError_t ag_union(ld_ctx* c, const AgBufs& b, const AgTable& tb, double rc, co
 void ag_free(ld_ctx* c) {
     if (c->agg) (void)hipFree(c->agg);
     c->agg = nullptr;
+}
+
+// Eq. (6) pair counts into counts[n_bins] (device) through the cell sort,
+// when the grid of cells of side >= r_max has at least 3 cells per axis;
+// *used = false leaves the counts to the all-pairs histogram.  The slot
+// order is not changed.
+ld_status ag_rdf_pairs(ld_ctx* c, double r_max, int n_bins, unsigned long long* counts,
+                       bool* used) {
+    *used = false;
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    // the grid the key kernel will derive (same partial maxima, same rule)
+    AG_LAUNCH(k_ag_absmax, dim3(64), dim3(kB), s, c->pos, n, c->sb.bounds_part);
+    float part[64];
+    HIP_TRY(hipMemcpyAsync(part, c->sb.bounds_part, sizeof part, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float m = 0.f;
+    for (float v : part) m = std::max(m, v);
+    m = std::max(m, 1e-3f);
+    const double L = (double)(m * 1.0009765625f);
+    if ((int)std::floor(2.0 * L / r_max) < 3) return LD_OK;
+    AgBufs b{};
+    ld_status st = ag_buffers(c, &b);
+    if (st != LD_OK) return st;
+    unsigned long long* keys = nullptr;
+    HIP_TRY(ag_cells(c, b, r_max, &keys));
+    const int blocks = (n + kB - 1) / kB;
+    AG_LAUNCH(k_ag_zero64, dim3((n_bins + kB - 1) / kB), dim3(kB), s, counts, n_bins);
+    AG_LAUNCH(k_ag_rdf, dim3(blocks), dim3(kB), s, c->pos, c->lo, keys, b.grid, b.cstart, b.cend,
+              n, r_max, n_bins, r_max / n_bins, counts);
+    *used = true;
+    return LD_OK;
 }
 
 }  // namespace ld

@@ -694,7 +694,16 @@ ld_status ld_rdf(ld_ctx* c, double r_max, int32_t n_bins, double V, int32_t cent
         HIP_TRY(hipStreamSynchronize(c->stream));
         HIP_TRY(hipMemcpy(dctr, z, sizeof z, hipMemcpyHostToDevice));
     }
-    HIP_TRY(ld::launch_rdf(c->pos, c->lo, (int)N, r_max, n_bins, dctr, dcnt, dcc, c->stream));
+    // pair counts through the cell sort when r_max is short against the
+    // droplet, else by the all-pairs histogram (same bins either way)
+    bool cells = false;
+    ld_status cst = ld::ag_rdf_pairs(c, r_max, n_bins, dcnt, &cells);
+    if (cst != LD_OK) return cst;
+    if (cells)
+        HIP_TRY(ld::launch_centre_hist(c->pos, c->lo, nullptr, 0, (int)N, r_max, n_bins, dctr, dcc,
+                                       c->stream));
+    else
+        HIP_TRY(ld::launch_rdf(c->pos, c->lo, (int)N, r_max, n_bins, dctr, dcnt, dcc, c->stream));
     std::vector<unsigned long long> hc(n_bins), hcc(n_bins);
     HIP_TRY(hipMemcpyAsync(hc.data(), dcnt, sizeof(unsigned long long) * n_bins,
                            hipMemcpyDeviceToHost, c->stream));

@@ -356,6 +356,10 @@ ld_status pm_step(ld_ctx* c, double dt, hipStream_t s);
 void pm_free(ld_ctx* c);
 // Aggregate statistics scratch (ld_agg.hip).
 void ag_free(ld_ctx* c);
+// Eq. (6) pair counts through the cell sort (ld_agg.hip); *used = false when
+// the cells would be too coarse and the all-pairs histogram should count.
+ld_status ag_rdf_pairs(ld_ctx* c, double r_max, int n_bins, unsigned long long* counts,
+                       bool* used);
 // Trajectory recording (ld_record.hip): after each enqueued step.
 ld_status rec_after_step(ld_ctx* c, double dt, hipStream_t s);
 void rec_free(ld_ctx* c);

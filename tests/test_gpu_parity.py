@@ -328,6 +328,22 @@ def test_rdf_exact_counts(ld, orc):
     assert np.abs(cc2.astype(np.int64) - occ2.astype(np.int64)).max() <= 2
 
 
+@pytest.mark.parametrize("n,r_max", [(3001, 3.0), (700, 2.5), (2000, 7.9)])
+def test_rdf_dense_cells(ld, orc, n, r_max):
+    """Pair counts of a packed, jittered lattice (tens of NPs per cell of
+    side r_max; ragged N) through the cell sort, bit-exact; with r_max 7.9 the
+    grid is too coarse and the all-pairs histogram counts instead."""
+    k = int(math.ceil(n ** (1 / 3)))
+    g = np.stack(np.meshgrid(*[np.arange(k)] * 3, indexing="ij"), -1).reshape(-1, 3)[:n]
+    rng = np.random.default_rng(n)
+    x = ((g - k / 2) * 1.05 + rng.uniform(-0.02, 0.02, g.shape)).astype(np.float32)
+    w = W.config_small(n=n, with_positions=False).replace(pos=x)
+    s = ld.System.from_workload(w)
+    counts, _, _, _ = s.rdf(r_max, 97, V=1.0e4, centre=0)
+    oc, _, _, _ = orc.rdf(x, r_max, 97, 1.0e4)
+    assert np.array_equal(counts, oc) and counts.sum() > 0
+
+
 @pytest.mark.parametrize("t", [0, 1, 2])
 def test_cbar_per_type(ld, orc, t):
     """Eq. (8) over the NPs of one type equals the oracle's Eq. (8) on that
