@@ -259,3 +259,26 @@ def test_surface_fractal_tie_takes_the_smaller_label():
     st, out, lab = oracle.surface_fractal(x, np.zeros(60, np.int32), params([1.0]), R, 1.1)
     assert list(st) == [2, 30, 0]
     assert np.all(lab[:30] == 0) and np.all(lab[30:] == 30)
+
+
+def test_surface_fractal_membership_band():
+    """Only NPs within half a diameter of the surface take part: NPs at
+    0.4 and 0.6 diameters from it (inside and outside, two types), spread
+    over the sphere so that none are in contact, are labelled exactly by
+    | |x| - R | < sigma_t / 2."""
+    import oracle
+    oracle.lib()
+    p = params([1.0, 2.0])
+    R = 30.0
+    rng = np.random.default_rng(8)
+    u = rng.normal(size=(16, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    typ = np.array([0, 1] * 8, np.int32)
+    sig = np.array([1.0, 2.0])[typ]
+    f = np.array([0.4, -0.4, 0.6, -0.6] * 4)
+    r = R + f * sig
+    x = u * r[:, None]
+    st, out, lab = oracle.surface_fractal(x, typ, p, R, 1.1)
+    want = np.abs(r - R) < 0.5 * sig
+    assert np.array_equal(lab >= 0, want) and want.sum() == 8
+    assert st[0] == 8                      # all singletons
