@@ -183,3 +183,17 @@ def test_paper_forces_rows_select():
     rows = np.array([399, 0, 17, 17, 250])
     Fr, Sr = oracle.paper_forces(w.pos, w.type, w.charge, w.params, 4.0, rows=rows)
     assert np.array_equal(Fr, F[rows]) and np.array_equal(Sr, S[rows])
+
+
+def test_wall_uses_the_new_radius(oracle_lib):
+    """Step (iii) precedes step (iv): with R shrinking linearly 10 -> 5 over
+    T = 1 and dt = 0.1, an NP at |x| = 9.8 (inside R(0) = 10, outside
+    R(0.1) = 9.5) gets v_1 = -dt k (9.8 - 9.5) / m along x from the first
+    step."""
+    k, m, dt = 50.0, 2.0, 0.1
+    w = lone(one(k_wall=[k]), [[9.8, 0.0, 0.0]], dt, 1)
+    w.radius = W.Radius(kind=W.RADIUS_LINEAR, R0=10.0, R1=5.0, T=1.0)
+    st = oracle_lib.PaperState(w, 4.0, 0.0, [m])
+    assert st.run(1, dt) == -1
+    assert st.v[0, 0] == pytest.approx(-dt * k * (9.8 - 9.5) / m, rel=1e-12)
+    assert st.v[0, 1] == 0.0 and st.v[0, 2] == 0.0
