@@ -120,14 +120,23 @@ __global__ __launch_bounds__(kB) void k_ag_iota(int* a, int m) {
     if (k < m) a[k] = k;
 }
 
-// Cell ranges [cstart, cend) over the sorted keys.
-__global__ __launch_bounds__(kB) void k_ag_ranges(const unsigned long long* __restrict__ keys,
-                                                  int n, int* cstart, int* cend) {
-    const int k = blockIdx.x * kB + threadIdx.x;
-    if (k >= n) return;
-    const unsigned c = (unsigned)(keys[k] >> 32);
-    if (k == 0 || (unsigned)(keys[k - 1] >> 32) != c) cstart[c] = k;
-    if (k == n - 1 || (unsigned)(keys[k + 1] >> 32) != c) cend[c] = k + 1;
+// First slot of every cell of the grid (G^3 cells, G from the device grid):
+// the slots of cells a..b of the sorted keys are [cfirst[a], cfirst[b + 1]).
+__global__ __launch_bounds__(kB) void k_ag_first(const unsigned long long* __restrict__ keys,
+                                                 int n, const AgGrid* __restrict__ g,
+                                                 int* cfirst) {
+    const int G = g->Gc;
+    fill_cell_first(keys, n, G * G * G, blockIdx.x * kB + threadIdx.x, cfirst);
+}
+
+// Squared FP32 screen for candidate pairs: the range widened by the worst
+// rounding of an FP32 difference of hi words (coordinates within the cube
+// half width L: hi rounding and the difference move each component by at
+// most L 2^-22, the squared sum by a few ulp), so every pair the FP64 test
+// keeps passes it.
+__device__ __forceinline__ float ag_screen2(double range, double L) {
+    const double w = range + L * 0x1p-20;
+    return (float)(w * w * (1.0 + 0x1p-18));
 }
 
 // Root of a: a bounded walk up the parent links with path halving (a
@@ -169,10 +178,9 @@ __global__ __launch_bounds__(kB) void k_ag_hook(const float4* __restrict__ pos,
                                                 const int* __restrict__ typ,
                                                 const unsigned long long* __restrict__ keys,
                                                 const AgGrid* __restrict__ g,
-                                                const int* __restrict__ cstart,
-                                                const int* __restrict__ cend, int n, AgTable tb,
-                                                const int* __restrict__ surf, int* parent,
-                                                int* err) {
+                                                const int* __restrict__ cfirst, int n,
+                                                AgTable tb, const int* __restrict__ surf,
+                                                int* parent, int* err) {
     const int k = blockIdx.x * kB + threadIdx.x;
     if (k >= n) return;
     const unsigned long long key = keys[k];
@@ -195,8 +203,8 @@ __global__ __launch_bounds__(kB) void k_ag_hook(const float4* __restrict__ pos,
                 const int x = cx + dx;
                 if (x < 0 || x >= G) continue;
                 const int cc = (z * G + y) * G + x;
-                const int m1 = cend[cc];
-                for (int m = max(cstart[cc], k + 1); m < m1; ++m) {
+                const int m1 = cfirst[cc + 1];
+                for (int m = max(cfirst[cc], k + 1); m < m1; ++m) {
                     const int j = (int)(unsigned)keys[m];
                     if (SURF && !surf[j]) continue;
                     const float4 hj = pos[j], lj = lo[j];
@@ -460,9 +468,8 @@ __global__ __launch_bounds__(kB) void k_ag_rdf(const float4* __restrict__ pos,
                                                const float4* __restrict__ lo,
                                                const unsigned long long* __restrict__ keys,
                                                const AgGrid* __restrict__ g,
-                                               const int* __restrict__ cstart,
-                                               const int* __restrict__ cend, int n, double r_max,
-                                               int n_bins, double dr,
+                                               const int* __restrict__ cfirst, int n,
+                                               double r_max, int n_bins, double dr,
                                                unsigned long long* counts) {
 #pragma clang fp contract(off)
     __shared__ unsigned int hist[kRdfMaxBins];
@@ -476,30 +483,30 @@ __global__ __launch_bounds__(kB) void k_ag_rdf(const float4* __restrict__ pos,
         const double xi = (double)hi.x + (double)li.x, yi = (double)hi.y + (double)li.y,
                      zi = (double)hi.z + (double)li.z;
         const int G = g->Gc;
+        const float screen2 = ag_screen2(r_max, g->L);
         const int c = (int)(key >> 32);
         const int cx = c % G, cy = (c / G) % G, cz = c / (G * G);
+        const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < G - 1 ? cx + 1 : G - 1;
         for (int dz = -1; dz <= 1; ++dz) {
             const int z = cz + dz;
             if (z < 0 || z >= G) continue;
             for (int dy = -1; dy <= 1; ++dy) {
                 const int y = cy + dy;
                 if (y < 0 || y >= G) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int x = cx + dx;
-                    if (x < 0 || x >= G) continue;
-                    const int cc = (z * G + y) * G + x;
-                    const int m1 = cend[cc];
-                    for (int m = max(cstart[cc], k + 1); m < m1; ++m) {
-                        const int j = (int)(unsigned)keys[m];
-                        const float4 hj = pos[j], lj = lo[j];
-                        const double ex = xi - ((double)hj.x + (double)lj.x);
-                        const double ey = yi - ((double)hj.y + (double)lj.y);
-                        const double ez = zi - ((double)hj.z + (double)lj.z);
-                        const double r = sqrt(ex * ex + ey * ey + ez * ez);
-                        if (r < r_max) {
-                            const int b = (int)floor(r / dr);
-                            if (b >= 0 && b < n_bins) atomicAdd(&hist[b], 1u);
-                        }
+                const int row = (z * G + y) * G;
+                const int m1 = cfirst[row + x1 + 1];
+                for (int m = max(cfirst[row + x0], k + 1); m < m1; ++m) {
+                    const int j = (int)(unsigned)keys[m];
+                    const float4 hj = pos[j], lj = lo[j];
+                    const float sx = hj.x - hi.x, sy = hj.y - hi.y, sz = hj.z - hi.z;
+                    if (!(fmaf(sz, sz, fmaf(sy, sy, sx * sx)) < screen2)) continue;
+                    const double ex = xi - ((double)hj.x + (double)lj.x);
+                    const double ey = yi - ((double)hj.y + (double)lj.y);
+                    const double ez = zi - ((double)hj.z + (double)lj.z);
+                    const double r = sqrt(ex * ex + ey * ey + ez * ez);
+                    if (r < r_max) {
+                        const int b = (int)floor(r / dr);
+                        if (b >= 0 && b < n_bins) atomicAdd(&hist[b], 1u);
                     }
                 }
             }
@@ -518,8 +525,7 @@ __global__ __launch_bounds__(kB) void k_ag_rdf(const float4* __restrict__ pos,
 
 // Scratch of the aggregate calls (allocated on first use, kept by the context).
 struct AgBufs {
-    int* cstart;     // [kANC]
-    int* cend;       // [kANC]
+    int* cfirst;     // [kANC + 1] first slot of every cell
     int* parent;     // [n]
     int* root;       // [n]
     int* minoid;     // [n]
@@ -546,8 +552,7 @@ size_t ag_layout(char* base, size_t n, AgBufs* b) {
     b->part = reinterpret_cast<long long*>(take(blocks * kMaxTypes * sizeof(long long)));
     b->dpart = reinterpret_cast<double*>(take(blocks * 4 * sizeof(double)));
     b->surf = reinterpret_cast<int*>(take(n * sizeof(int)));
-    b->cstart = reinterpret_cast<int*>(take(kANC * sizeof(int)));
-    b->cend = reinterpret_cast<int*>(take(kANC * sizeof(int)));
+    b->cfirst = reinterpret_cast<int*>(take((kANC + 1) * sizeof(int)));
     b->parent = reinterpret_cast<int*>(take(n * sizeof(int)));
     b->root = reinterpret_cast<int*>(take(n * sizeof(int)));
     b->minoid = reinterpret_cast<int*>(take(n * sizeof(int)));
@@ -594,8 +599,7 @@ double ag_table(const ld_ctx* c, double contact_factor, AgTable* tb) {
     } while (0)
 
 // Cell sort for cells of side >= rc: grid, keys (cell << 32 | slot) sorted by
-// cell, and every cell's slot range [cstart, cend).  *keys_out: the sorted
-// keys.
+// cell, and every cell's first slot.  *keys_out: the sorted keys.
 hipError_t ag_cells(ld_ctx* c, const AgBufs& b, double rc, unsigned long long** keys_out) {
     const int n = (int)c->n;
     hipStream_t s = c->stream;
@@ -611,10 +615,7 @@ hipError_t ag_cells(ld_ctx* c, const AgBufs& b, double rc, unsigned long long** 
         c->sb.keys, reinterpret_cast<unsigned long long*>(c->sb.tmp4), n, bits, c->sb.hist, s,
         true, &keys);
     if (e != hipSuccess) return e;
-    const dim3 gc((kANC + kB - 1) / kB), gn(blocks);
-    AG_RUN(k_ag_fill, gc, b.cstart, kANC, 0);
-    AG_RUN(k_ag_fill, gc, b.cend, kANC, 0);
-    AG_RUN(k_ag_ranges, gn, keys, n, b.cstart, b.cend);
+    AG_RUN(k_ag_first, dim3(blocks), keys, n, b.grid, b.cfirst);
     *keys_out = keys;
     return hipSuccess;
 }
@@ -634,10 +635,10 @@ hipError_t ag_union(ld_ctx* c, const AgBufs& b, const AgTable& tb, double rc, co
     AG_RUN(k_ag_iota, gn, b.parent, n);
     AG_RUN(k_ag_fill, dim3(1), b.err, 1, 0);
     if (surf)
-        AG_RUN(k_ag_hook<true>, gn, c->pos, c->lo, c->typ, keys, b.grid, b.cstart, b.cend, n, tb,
-               surf, b.parent, b.err);
+        AG_RUN(k_ag_hook<true>, gn, c->pos, c->lo, c->typ, keys, b.grid, b.cfirst, n, tb, surf,
+               b.parent, b.err);
     else
-        AG_RUN(k_ag_hook<false>, gn, c->pos, c->lo, c->typ, keys, b.grid, b.cstart, b.cend, n, tb,
+        AG_RUN(k_ag_hook<false>, gn, c->pos, c->lo, c->typ, keys, b.grid, b.cfirst, n, tb,
                nullptr, b.parent, b.err);
     AG_RUN(k_ag_flatten, gn, b.parent, n, b.root, b.err);
     AG_RUN(k_ag_fill, gn, b.minoid, n, INT_MAX);
@@ -681,8 +682,8 @@ ld_status ag_rdf_pairs(ld_ctx* c, double r_max, int n_bins, unsigned long long* 
     HIP_TRY(ag_cells(c, b, r_max, &keys));
     const int blocks = (n + kB - 1) / kB;
     AG_LAUNCH(k_ag_zero64, dim3((n_bins + kB - 1) / kB), dim3(kB), s, counts, n_bins);
-    AG_LAUNCH(k_ag_rdf, dim3(blocks), dim3(kB), s, c->pos, c->lo, keys, b.grid, b.cstart, b.cend,
-              n, r_max, n_bins, r_max / n_bins, counts);
+    AG_LAUNCH(k_ag_rdf, dim3(blocks), dim3(kB), s, c->pos, c->lo, keys, b.grid, b.cfirst, n,
+              r_max, n_bins, r_max / n_bins, counts);
     *used = true;
     return LD_OK;
 }
