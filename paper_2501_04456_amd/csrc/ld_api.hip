@@ -825,13 +825,35 @@ ld_status ld_fractal(ld_ctx* c, double k_f, double d, double eps0, int32_t max_s
     out[1] = std::log((double)N / k_f) / std::log(2.0 * Rg / d);
     HIP_TRY(ld::launch_pos_rows(c->pos, c->lo, (int)N, c->work, c->stream));
     HIP_TRY(ld::launch_rowmin(c->work, 3, (int)N, lo3, c->stream));
+    // the extents decide, per scale, whether the box indices fit 32 bits
+    double* hi3 = reinterpret_cast<double*>(cnt + 1);
+    HIP_TRY(ld::launch_rowmax(c->work, 3, (int)N, hi3, c->stream));
+    double hlo[3], hhi[3];
+    HIP_TRY(copy_out(hlo, lo3, sizeof hlo, c->stream));
+    HIP_TRY(copy_out(hhi, hi3, sizeof hhi, c->stream));
     std::vector<double> lx, ly;
     int K = 0;
     for (int k = 0; k < max_scales; ++k) {
         const double e = eps0 * std::ldexp(1.0, k);
         if (e > Rg) break;
-        HIP_TRY(ld::launch_boxcount(c->pos, c->lo, (int)N, lo3, e, c->sb.keys, c->sb.n_pow2, cnt,
-                                    c->stream));
+        // boxes per axis: the largest index floor((hi - lo) / e) plus one, and one more
+        double nb[3], prod = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            nb[a] = std::floor((hhi[a] - hlo[a]) / e) + 2.0;
+            prod *= nb[a];
+        }
+        if (prod <= 4294967296.0) {
+            int bits = 1;
+            while (bits < 32 && std::ldexp(1.0, bits) < prod) ++bits;
+            HIP_TRY(ld::launch_boxcount_radix(c->pos, c->lo, (int)N, lo3, e,
+                                              (unsigned long long)nb[1],
+                                              (unsigned long long)nb[2], bits, c->sb.keys,
+                                              reinterpret_cast<unsigned long long*>(c->sb.tmp4),
+                                              c->sb.hist, cnt, c->stream));
+        } else {
+            HIP_TRY(ld::launch_boxcount(c->pos, c->lo, (int)N, lo3, e, c->sb.keys,
+                                        c->sb.n_pow2, cnt, c->stream));
+        }
         unsigned long long hc = 0;
         HIP_TRY(copy_out(&hc, cnt, sizeof hc, c->stream));
         if (box_counts) box_counts[k] = (int64_t)hc;

@@ -132,6 +132,7 @@ hipError_t launch_gather(const float4* pos, const float4* lo, const int* typ, co
 // Deterministic FP64 sum of m rows of length n: out[r] = sum_s in[r*n + s].
 hipError_t launch_rowsum(const double* in, int rows, int n, double* out, hipStream_t s);
 hipError_t launch_rowmin(const double* in, int rows, int n, double* out, hipStream_t s);
+hipError_t launch_rowmax(const double* in, int rows, int n, double* out, hipStream_t s);
 
 // Positions hi + lo as FP64 rows work[0..2][n].
 hipError_t launch_pos_rows(const float4* pos, const float4* lo, int n, double* work,
@@ -283,6 +284,13 @@ hipError_t launch_moments(const float4* pos, const float4* lo, int n, double* wo
 hipError_t launch_boxcount(const float4* pos, const float4* lo, int n, const double* lo3,
                            double eps, unsigned long long* keys, int n_pow2,
                            unsigned long long* count, hipStream_t s);
+// Box counting by compact box indices below 2^bits <= 2^32 (ny, nz boxes
+// along y and z) and the radix sort; keys and tmp hold n keys each, hist as
+// for the radix sort.
+hipError_t launch_boxcount_radix(const float4* pos, const float4* lo, int n, const double* lo3,
+                                 double eps, unsigned long long ny, unsigned long long nz,
+                                 int bits, unsigned long long* keys, unsigned long long* tmp,
+                                 unsigned* hist, unsigned long long* count, hipStream_t s);
 
 struct FarField;
 struct PaperMode;

@@ -141,6 +141,40 @@ __global__ __launch_bounds__(256) void k_box_keys(const float4* __restrict__ pos
     keys[s] = (ix << 42) | (iy << 21) | iz;
 }
 
+// Compact box keys: (box index << 32) | slot, box index = (ix ny + iy) nz + iz
+// with ix, iy, iz formed exactly as in k_box_keys; the caller guarantees
+// nx ny nz <= 2^32.
+__global__ __launch_bounds__(256) void k_box_keys32(const float4* __restrict__ pos,
+                                                    const float4* __restrict__ lo, int n,
+                                                    const double* __restrict__ lo3, double eps,
+                                                    unsigned long long ny, unsigned long long nz,
+                                                    unsigned long long* keys) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    double x[3];
+    full_pos(pos, lo, s, x);
+    const unsigned long long ix = (unsigned long long)floor((x[0] - lo3[0]) / eps);
+    const unsigned long long iy = (unsigned long long)floor((x[1] - lo3[1]) / eps);
+    const unsigned long long iz = (unsigned long long)floor((x[2] - lo3[2]) / eps);
+    keys[s] = (((ix * ny + iy) * nz + iz) << 32) | (unsigned long long)(unsigned)s;
+}
+
+// Distinct high words of keys sorted by them.
+__global__ __launch_bounds__(256) void k_count_distinct_high(const unsigned long long* keys, int n,
+                                                             unsigned long long* count) {
+    __shared__ unsigned int red[256];
+    unsigned int c = 0;
+    for (int s = blockIdx.x * 256 + threadIdx.x; s < n; s += gridDim.x * 256)
+        c += (s == 0 || (keys[s] >> 32) != (keys[s - 1] >> 32)) ? 1u : 0u;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(count, (unsigned long long)red[0]);
+}
+
 __global__ __launch_bounds__(256) void k_count_distinct(const unsigned long long* keys, int n,
                                                         unsigned long long* count) {
     __shared__ unsigned int red[256];
@@ -213,6 +247,20 @@ hipError_t launch_moments(const float4* pos, const float4* lo, int n, double* wo
     e = launch_rowsum(work, 1, n, s2, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_moments_finish, dim3(1), dim3(1), 0, s, sums, s2, n, out4);
+    return hipGetLastError();
+}
+
+hipError_t launch_boxcount_radix(const float4* pos, const float4* lo, int n, const double* lo3,
+                                 double eps, unsigned long long ny, unsigned long long nz,
+                                 int bits, unsigned long long* keys, unsigned long long* tmp,
+                                 unsigned* hist, unsigned long long* count, hipStream_t s) {
+    hipLaunchKernelGGL(k_box_keys32, dim3((n + 255) / 256), dim3(256), 0, s, pos, lo, n, lo3, eps,
+                       ny, nz, keys);
+    unsigned long long* sorted = nullptr;
+    hipError_t e = launch_radix_by_high(keys, tmp, n, bits, hist, s, false, &sorted);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, count, 1);
+    hipLaunchKernelGGL(k_count_distinct_high, dim3(64), dim3(256), 0, s, sorted, n, count);
     return hipGetLastError();
 }
 

@@ -203,6 +203,11 @@ hipError_t launch_rowmin(const double* in, int rows, int n, double* out, hipStre
     return hipGetLastError();
 }
 
+hipError_t launch_rowmax(const double* in, int rows, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_rowreduce<1>, dim3(rows), dim3(1024), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_diag(const float4* pos, const float4* lo, const int* typ,
                        const double* Fpart, int j_split, const double* U_slot, int n,
                        const DevState* st, const ExtParams& P, double* work, double* out,

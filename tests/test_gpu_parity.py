@@ -375,6 +375,21 @@ def test_fractal(ld, orc):
     assert Db == pytest.approx(oDb, rel=1e-12)
 
 
+def test_fractal_fine_boxes(ld, orc):
+    """Box sides from 0.02 sigma: the finest scales have more than 2^32 boxes
+    in the bounding box (counted by the 64-bit key sort), the coarser ones
+    fewer (compact keys and the radix sort); counts exact at every scale."""
+    w = W.config_medium(n=4000, seed=6)
+    s = ld.System.from_workload(w)
+    _, _, Db, K, bc = s.fractal(1.593, 0.0, 0.02, max_scales=16)
+    sig = np.asarray(w.params.sigma)[w.type]
+    _, _, oDb, oK, obc = orc.fractal(w.pos, 1.593, sig.mean(), 0.02)
+    ext = w.pos.astype(np.float64).max(0) - w.pos.astype(np.float64).min(0)
+    assert np.prod(ext / 0.02) > 2.0 ** 32 and np.prod(ext / (0.02 * 2 ** (K - 1))) < 2.0 ** 32
+    assert K == oK and np.array_equal(bc, obc)
+    assert Db == pytest.approx(oDb, rel=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # Error paths
 # ---------------------------------------------------------------------------
