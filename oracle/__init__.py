@@ -29,10 +29,14 @@ def build(verbose: bool = False) -> str:
     """Compile ldo.c into libldo.so with gcc (generic x86-64, no fast-math)."""
     srcs = [os.path.join(_HERE, f) for f in ("ldo.c", "ldo_ff.c", "ldo_paper.c", "ldo_agg.c")]
     srcs = [s for s in srcs if os.path.exists(s)]
-    cmd = ["gcc", *CFLAGS, "-o", _LIB_PATH, *srcs, "-lm"]
+    # written beside and renamed into place, so that a process that has the
+    # old library loaded keeps its own copy
+    tmp = f"{_LIB_PATH}.{os.getpid()}.tmp"
+    cmd = ["gcc", *CFLAGS, "-o", tmp, *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
 
@@ -95,6 +99,8 @@ def lib():
         L.ldo_step_rows.restype = C.c_int64
         L.ldo_diagnostics.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp,
                                       C.POINTER(_Params), C.c_double, dp]
+        L.ldo_msd.argtypes = [C.c_int64, dp, dp]
+        L.ldo_msd.restype = C.c_double
         L.ldo_rdf.argtypes = [C.c_int64, dp, C.c_double, C.c_int32, C.c_double, dp,
                               C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), dp, dp]
         L.ldo_fractal.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_double,
@@ -286,6 +292,15 @@ class State:
         lib().ldo_diagnostics(len(self.type), _dp(self.x), _ip(self.type), _dp(self.q),
                               C.byref(make_params(self.params)), R, _dp(out))
         return out
+
+
+def msd(x, x0) -> float:
+    """Mean square displacement mean_i |x_i - x0_i|^2 (the diagnostics'
+    mean square displacement; free diffusion gives 6 D t)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    x0 = np.ascontiguousarray(x0, dtype=np.float64).reshape(-1, 3)
+    assert x.shape == x0.shape
+    return float(lib().ldo_msd(len(x), _dp(x), _dp(x0)))
 
 
 def rdf(x, r_max: float, n_bins: int, V: float, centre=(0.0, 0.0, 0.0)):

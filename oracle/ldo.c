@@ -359,6 +359,17 @@ void ldo_diagnostics(int64_t n, const double* x, const int32_t* type, const doub
     free(F);
 }
 
+double ldo_msd(int64_t n, const double* x, const double* x0) {
+    nsum s = {0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        double dx = x[3 * i] - x0[3 * i];
+        double dy = x[3 * i + 1] - x0[3 * i + 1];
+        double dz = x[3 * i + 2] - x0[3 * i + 2];
+        nsum_add(&s, dx * dx + dy * dy + dz * dz);
+    }
+    return n > 0 ? nsum_get(&s) / (double)n : 0.0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* RDF, Eq. (6), and radial concentration, Eq. (8) (section 3.2).           */
 /* ------------------------------------------------------------------------ */

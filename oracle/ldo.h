@@ -178,8 +178,10 @@ void ldo_surface_fractal(int64_t n, const double* x, const int32_t* type, const 
 
 /* One step for the listed rows only (pair forces from all n particles at the
  * current positions); writes the rows' new positions, leaves x unchanged.
- * Returns step if a listed row blew up, else -1.  Same formulas as ldo_run,
- * pinned through it. */
+ * Returns step if a listed row blew up, else -1.  Pinned against whole
+ * ldo_run steps (bit for bit, with and without noise, band wall, a moving
+ * radius and a step counter other than zero) and against the noise stream
+ * for a free particle. */
 int64_t ldo_step_rows(int64_t n, const double* x, const int32_t* type, const double* q,
                       const int64_t* ids, const ldo_params* p, const ldo_radius* R,
                       double dt, uint64_t seed, int64_t step, double t,
@@ -187,9 +189,16 @@ int64_t ldo_step_rows(int64_t n, const double* x, const int32_t* type, const dou
 
 /* Diagnostics (FP64): out[0] U_LJ, out[1] U_C, out[2] U_wall, out[3] U_grav,
  * out[4] U_centrifugal, out[5..7] net pair force, out[8] max |F_pair_i|,
- * out[9] max |x_i|.  R is the radius used for the wall. */
+ * out[9] max |x_i|.  R is the radius used for the wall.  Pinned by the
+ * single-NP closed forms of the three external energies, by their negative
+ * gradient against ldo_external_force (central differences), by Newton's
+ * third law for the net force and by hand-built maxima. */
 void ldo_diagnostics(int64_t n, const double* x, const int32_t* type, const double* q,
                      const ldo_params* p, double R, double out[10]);
+
+/* Mean square displacement: the mean over particles of |x_i - x0_i|^2.
+ * Pinned by a hand-built case and by free diffusion (6 D t). */
+double ldo_msd(int64_t n, const double* x, const double* x0);
 
 /* Radial distribution function, Eq. (6), and radial concentration, Eq. (8).
  * Bins are [b*dr, (b+1)*dr) with dr = r_max / n_bins.  counts[b] is the

@@ -520,3 +520,146 @@ def test_box_counting_sierpinski_tetrahedron(oracle_lib):
     _, _, Db, K, bc = oracle_lib.fractal(pts, 1.593, 1.0, 1.0)
     assert K >= 4
     assert Db == pytest.approx(2.0, abs=0.05)
+
+
+# ---------------------------------------------------------------------------
+# One step for listed rows (the checker of sampled rows at full size)
+# ---------------------------------------------------------------------------
+
+def _moving_wall_workload(noise, band=0, n=240):
+    """A small charged droplet whose wall moves fast and sits inside many
+    particles, so that R(t) and R(t + dt) give visibly different forces."""
+    w = W.config_small(n=n, seed=5)
+    w.params.k_wall = [50.0]
+    w.params.noise = noise
+    w.params.wall_band = band
+    w.params.jump_max = 0.0
+    r0 = float(np.linalg.norm(w.pos.astype(np.float64), axis=1).max())
+    # the wall passes through the droplet: R(t) = 0.6 r0 -> 0.2 r0 over 40 dt
+    w.radius = W.Radius(kind=W.RADIUS_LINEAR, R0=0.6 * r0, R1=0.2 * r0, T=40 * w.dt)
+    return w
+
+
+@pytest.mark.parametrize("noise,band", [(W.NOISE_GAUSS, 0), (W.NOISE_OFF, 0),
+                                        (W.NOISE_FIXED, 0), (W.NOISE_GAUSS, 1)])
+def test_step_rows_is_one_run_step(oracle_lib, noise, band):
+    """ldo_step_rows from any state equals the listed rows of a whole ldo_run
+    step, bit for bit: the same radius R(t + dt), the same noise step index,
+    the same pair and external forces."""
+    w = _moving_wall_workload(noise, band)
+    st = oracle_lib.State(w)
+    st.run(7)                       # a step counter and time other than zero
+    rows = np.array([0, 3, 17, 88, 150, w.n - 1])
+    xo, bad = st.step_rows(rows)
+    assert bad == -1
+    ref = oracle_lib.State(w, pos=st.x)
+    ref.step, ref.t = st.step, st.t
+    assert ref.run(1) == -1
+    assert np.array_equal(xo, ref.x[rows])
+    # the wall acts on some of the listed rows, so the radius used matters
+    R_new = oracle_lib.radius_at(w.radius, st.t + w.dt)
+    r = np.linalg.norm(st.x[rows], axis=1)
+    assert np.any(r > R_new)
+    # the state itself is not advanced
+    assert st.step == 7
+
+
+def test_step_rows_noise_of_a_free_particle(oracle_lib):
+    """A lone force-free particle moves by sqrt(2 kT dt / gamma) times the
+    Gaussian triple of its own id at the current step."""
+    p = one_type(eps=[0.0], gamma=[2.0], kT=1.5, noise=W.NOISE_GAUSS)
+    R = W.Radius(kind=W.RADIUS_CONST, R0=1e9)
+    x0 = np.zeros((3, 3))
+    x0[:, 0] = [0.0, 1e4, 2e4]
+    w = W.Workload("t", 3, np.zeros(3, np.int32), np.zeros(3), x0, p, R, 1e-3, 10, 77)
+    st = oracle_lib.State(w, ids=[11, 12, 13])
+    st.step, st.t = 5, 5e-3
+    xo, _ = st.step_rows([1])
+    amp = math.sqrt(2 * 1.5 * 1e-3 / 2.0)
+    expect = x0[1] + amp * oracle_lib.gauss3(12, 5, 77)
+    assert np.allclose(xo[0], expect, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics and MSD
+# ---------------------------------------------------------------------------
+
+def test_diagnostics_external_energies_closed_forms(oracle_lib):
+    p = one_type(eps=[0.0], k_wall=[8.0], wall_offset=[0.5], mass=[2.0],
+                 gravity=(0.1, -0.2, -0.05), omega=0.3)
+    x = np.array([[3.0, 4.0, 0.0]])               # r = 5
+    st = oracle_lib.State(W.Workload("t", 1, np.zeros(1, np.int32), np.zeros(1), x, p,
+                                     W.Radius(kind=W.RADIUS_CONST, R0=4.0), 1e-3, 1, 1))
+    d = st.diagnostics(R=4.0)                      # R_w = 3.5
+    assert d[2] == pytest.approx(0.5 * 8.0 * 1.5 ** 2, rel=1e-14)
+    assert d[3] == pytest.approx(-2.0 * (0.1 * 3.0 - 0.2 * 4.0), rel=1e-14)
+    assert d[4] == pytest.approx(-0.5 * 2.0 * 0.09 * 25.0, rel=1e-14)
+    assert d[9] == 5.0
+    assert np.all(d[5:9] == 0) and d[0] == 0 and d[1] == 0
+    d = st.diagnostics(R=6.0)                      # inside R_w = 5.5: no wall energy
+    assert d[2] == 0
+    p.rotation = 1                                 # about z: rho^2 = x^2 + y^2
+    x2 = np.array([[3.0, 0.0, 4.0]])
+    st2 = oracle_lib.State(W.Workload("t", 1, np.zeros(1, np.int32), np.zeros(1), x2, p,
+                                      W.Radius(kind=W.RADIUS_CONST, R0=4.0), 1e-3, 1, 1))
+    assert st2.diagnostics(R=10.0)[4] == pytest.approx(-0.5 * 2.0 * 0.09 * 9.0, rel=1e-14)
+    p.rotation = 0
+    p.wall_band = 1                                # acts only within sigma/2 of R
+    assert st.diagnostics(R=4.0)[2] == 0
+    assert st.diagnostics(R=5.2)[2] == pytest.approx(0.5 * 8.0 * 0.3 ** 2, rel=1e-12)
+
+
+def test_diagnostics_energies_are_potentials_of_the_external_force(oracle_lib):
+    """-grad (U_wall + U_grav + U_cf) = the external force, by central
+    differences, at points away from the wall's kink."""
+    p = one_type(eps=[0.0], k_wall=[30.0], mass=[1.7], gravity=(0.0, 0.02, -0.05),
+                 omega=0.4)
+    R = 2.0
+    rng = np.random.default_rng(12)
+    for rotation in (0, 1):
+        p.rotation = rotation
+        for _ in range(6):
+            x = rng.normal(size=3) * 2.5
+            if abs(np.linalg.norm(x) - R) < 0.05:
+                continue
+
+            def U(y):
+                w = W.Workload("t", 1, np.zeros(1, np.int32), np.zeros(1), y[None], p,
+                               W.Radius(kind=W.RADIUS_CONST, R0=R), 1e-3, 1, 1)
+                return oracle_lib.State(w).diagnostics(R=R)[2:5].sum()
+            h = 1e-5
+            g = np.array([(U(x + h * e) - U(x - h * e)) / (2 * h) for e in np.eye(3)])
+            F = oracle_lib.external_force(x, 0, p, R)
+            assert np.allclose(-g, F, rtol=1e-6, atol=1e-8), (rotation, x, -g, F)
+
+
+def test_diagnostics_pair_outputs(oracle_lib):
+    """Pair energies and forces inside the diagnostics agree with the pinned
+    pair sum; the net pair force vanishes (Newton's third law); the maxima
+    are those of a hand-built set."""
+    w = W.config_large(n=300, seed=8)
+    x = w.pos.astype(np.float64)
+    x[5] = [0.0, 0.0, 123.25]                        # the farthest particle
+    st = oracle_lib.State(w, pos=x)
+    d = st.diagnostics(R=1e3)
+    F, S, U = oracle_lib.pair_forces(x, w.type, w.charge, w.params)
+    assert d[0] == pytest.approx(U[0], rel=1e-12, abs=1e-12)
+    assert d[1] == pytest.approx(U[1], rel=1e-12)
+    assert np.all(np.abs(d[5:8]) <= 1e-12 * S.sum())
+    assert d[8] == np.linalg.norm(F, axis=1).max()
+    assert d[9] == 123.25
+
+
+def test_msd(oracle_lib):
+    x0 = np.zeros((2, 3))
+    x = np.array([[1.0, 2.0, 2.0], [0.0, 0.0, 3.0]])
+    assert oracle_lib.msd(x, x0) == 9.0
+    assert oracle_lib.msd(x0, x0) == 0.0
+    # free diffusion: 6 D t
+    n = 4000
+    p = one_type(eps=[0.0], gamma=[0.5], kT=2.0, noise=W.NOISE_GAUSS, jump_max=0.0)
+    R = W.Radius(kind=W.RADIUS_CONST, R0=1e9)
+    start = np.zeros((n, 3))
+    end = independent(oracle_lib, p, R, start, 10, 2e-3, seed=5)
+    assert oracle_lib.msd(end, start) / (6 * 4.0 * 10 * 2e-3) == pytest.approx(
+        1.0, abs=3 * math.sqrt(2 / (3 * n)))
