@@ -159,11 +159,51 @@ const char* ld_last_error(void);
  * Waits for the stream.  Errors: LD_EINVAL, LD_EHIP. */
 ld_status ld_forces(ld_ctx* ctx, double* F_pair, double* F_ext, double* S, double* U);
 
+/* State and FP64 diagnostics after a call of ld_step (section 2.2; the
+ * energies and momentum balance of the overdamped model). */
+typedef struct {
+    int64_t step;          /* global step counter */
+    double t;              /* time */
+    double R;              /* droplet radius R(t) */
+    double U[5];           /* U_LJ, U_C, U_wall, U_grav, U_centrifugal at R(t) */
+    double net_force[3];   /* sum_i F_pair,i (zero up to rounding: Newton's third law) */
+    double max_force;      /* max_i |F_pair,i| */
+    double max_radius;     /* max_i |x_i| */
+    double msd;            /* mean_i |x_i - x_i,ref|^2 (reference: see ld_msd) */
+    int64_t bad_step;      /* first step with a non-finite or too large move
+                              since the previous report, or -1 */
+} ld_diag;
+
 /* Advance n_steps >= 0 steps of size dt > 0 (section 2.2 steps (ii)-(vi)):
  *   x <- x + mu dt (F_pair + F_ext(R(t+dt))) + sqrt(2 kT mu dt) xi,  mu = 1/gamma.
- * Asynchronous: returns once the work is enqueued.  Errors: LD_EINVAL,
+ *   R     radius schedule to use from the first of these steps on (section
+ *         2.1: a freely defined evaporation or condensation rate; section
+ *         2.2: a run can be restarted with new parameters); NULL keeps the
+ *         current one.  Same effect as ld_set_params(ctx, NULL, R).
+ *   seed  new Philox key for the noise from the first of these steps on
+ *         (the counter keeps running on the global step count); NULL keeps
+ *         the current one.  A checkpoint saves the key in use.
+ *   diag  NULL: asynchronous, returns once the work is enqueued (errors of
+ *         the steps themselves surface at the next synchronising call).
+ *         Non-NULL: waits for the steps and fills *diag at the state after
+ *         them (periodic diagnostics = chunks of ld_step with a diag); a
+ *         step that blew up is reported as LD_ENONFINITE with diag->bad_step
+ *         set and the rest of *diag filled.
+ * A new R or seed is applied on the stream before the steps; a captured
+ * step graph is re-captured with it.  Errors: LD_EINVAL (dt, n_steps, R),
+ * LD_EHIP, LD_ENONFINITE (diag only). */
+ld_status ld_step(ld_ctx* ctx, double dt, int64_t n_steps, const ld_radius* R,
+                  const uint64_t* seed, ld_diag* diag);
+
+/* Mean square displacement mean_i |x_i - x_i,ref|^2 (FP64, from the hi + lo
+ * positions) against the reference positions: the positions at ld_init,
+ * ld_checkpoint_load or the last ld_msd_reset.  Free diffusion gives
+ * 6 (kT / gamma) t.  Waits for the stream.  Errors: LD_EINVAL, LD_EHIP. */
+ld_status ld_msd(ld_ctx* ctx, double* msd);
+
+/* Take the current positions as the MSD reference.  Errors: LD_EINVAL,
  * LD_EHIP. */
-ld_status ld_step(ld_ctx* ctx, double dt, int64_t n_steps);
+ld_status ld_msd_reset(ld_ctx* ctx);
 
 /* Wait for the stream; report a pending device-side blow-up once and clear
  * it.  Errors: LD_EHIP, LD_ENONFINITE (ld_last_error names the first bad

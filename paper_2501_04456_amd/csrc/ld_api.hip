@@ -210,6 +210,7 @@ hipEvent_t next_event(ld_ctx* c) {
 ld_status run_pair(ld_ctx* c, bool diag, hipStream_t s, bool timed) {
     ld::PairLaunch L{};
     L.pos = c->pos;
+    L.lo = c->lo;
     L.typ = c->typ;
     L.box = c->box;
     L.n = (int)c->n;
@@ -317,6 +318,9 @@ bool same_tuning(const ld_tuning& a, const ld_tuning& b) {
            a.sort_every == b.sort_every && a.cull == b.cull && a.graph_steps == b.graph_steps;
 }
 
+ld_status step_loop(ld_ctx* c, double dt, int64_t n_steps);
+ld_status fill_diag(ld_ctx* c, ld_diag* d);
+
 ld_status wait_stream(ld_ctx* c) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     return LD_OK;
@@ -341,7 +345,7 @@ void free_all(ld_ctx* c) {
     ld::pm_free(c);
     ld::ag_free(c);
     void* bufs[] = {c->pos,     c->lo,     c->typ,         c->oid,       c->box,  c->aux,
-                    c->Fpart,   c->S_slot, c->U_slot,      c->work,      c->st,
+                    c->Fpart,   c->S_slot, c->U_slot,      c->work,      c->st,  c->ref,
                     c->sb.keys, c->sb.tmp4, c->sb.tmp_i,   c->sb.bounds, c->sb.bounds_part,
                     c->sb.hist, c->pos2,  c->lo2,   c->typ2,       c->oid2};
     for (void* b : bufs)
@@ -413,6 +417,7 @@ ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* ch
               hipMalloc(&c->U_slot, sizeof(double) * 2 * N) == hipSuccess &&
               hipMalloc(&c->work, sizeof(double) * (16 * N + 64)) == hipSuccess &&
               hipMalloc(&c->aux, sizeof(double) * ld::kAuxWords) == hipSuccess &&
+              hipMalloc(&c->ref, sizeof(double) * 3 * N) == hipSuccess &&
               hipMalloc(&c->st, sizeof(ld::DevState)) == hipSuccess &&
               hipMalloc(&c->sb.keys, sizeof(unsigned long long) * n_pow2) == hipSuccess &&
               hipMalloc(&c->sb.tmp4, sizeof(float4) * N) == hipSuccess &&
@@ -449,6 +454,7 @@ ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* ch
         e = hipMemcpyAsync(c->oid, ids.data(), sizeof(int) * N, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->st, &ds, sizeof ds, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = ld::launch_msd_ref(c->pos, c->lo, c->oid, (int)N, c->ref, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         free_all(c);
@@ -503,11 +509,50 @@ ld_status ld_forces(ld_ctx* c, double* F_pair, double* F_ext, double* S, double*
     return wait_stream(c);
 }
 
-ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
+ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps, const ld_radius* R,
+                  const uint64_t* seed, ld_diag* diag) {
     g_err.clear();
     if (!c) return fail(LD_EINVAL, "ctx is NULL");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LD_EINVAL, "dt=%g must be positive", dt);
     if (n_steps < 0) return fail(LD_EINVAL, "n_steps must be >= 0");
+    if (R) {
+        ld_status st = check_radius(R);
+        if (st != LD_OK) return st;
+        // kernels already enqueued hold the old schedule in their arguments
+        c->R = *R;
+        invalidate_graph(c);
+        build_tables(c);
+    }
+    if (seed && *seed != c->seed) {
+        c->seed = *seed;
+        invalidate_graph(c);
+    }
+    ld_status st = step_loop(c, dt, n_steps);
+    if (st != LD_OK || !diag) return st;
+    return fill_diag(c, diag);
+}
+
+ld_status ld_msd(ld_ctx* c, double* msd) {
+    g_err.clear();
+    if (!c || !msd) return fail(LD_EINVAL, "ctx and msd are required");
+    double* res = c->aux;
+    HIP_TRY(ld::launch_msd(c->pos, c->lo, c->oid, (int)c->n, c->ref, c->work, res, c->stream));
+    HIP_TRY(copy_out(msd, res, sizeof(double), c->stream));
+    return wait_stream(c);
+}
+
+ld_status ld_msd_reset(ld_ctx* c) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    HIP_TRY(ld::launch_msd_ref(c->pos, c->lo, c->oid, (int)c->n, c->ref, c->stream));
+    return wait_stream(c);
+}
+
+}  // extern "C"
+
+namespace {
+
+ld_status step_loop(ld_ctx* c, double dt, int64_t n_steps) {
     int64_t left = n_steps;
     const bool use_graph = c->tune.graph_steps > 0 && !c->timing && !ld::ff_active(c) && !c->pm &&
                            !c->rec;
@@ -534,6 +579,35 @@ ld_status ld_step(ld_ctx* c, double dt, int64_t n_steps) {
     }
     return LD_OK;
 }
+
+// Wait for the steps, then the state and FP64 diagnostics at R(t) into *d;
+// a pending blow-up is reported (once) as LD_ENONFINITE with d->bad_step.
+ld_status fill_diag(ld_ctx* c, ld_diag* d) {
+    double out[10];
+    ld_status st = ld_diagnostics(c, out);
+    if (st != LD_OK) return st;
+    double* res = c->aux + 16;
+    HIP_TRY(ld::launch_msd(c->pos, c->lo, c->oid, (int)c->n, c->ref, c->work, res, c->stream));
+    double msd = 0.0;
+    ld::DevState ds;
+    HIP_TRY(hipMemcpyAsync(&msd, res, sizeof msd, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&ds, c->st, sizeof ds, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    d->step = ds.step;
+    d->t = ds.t;
+    d->R = ld::radius_at(c->R, ds.t);
+    for (int k = 0; k < 5; ++k) d->U[k] = out[k];
+    for (int k = 0; k < 3; ++k) d->net_force[k] = out[5 + k];
+    d->max_force = out[8];
+    d->max_radius = out[9];
+    d->msd = msd;
+    d->bad_step = ds.bad_step == ~0ull ? -1 : (int64_t)ds.bad_step;
+    return d->bad_step >= 0 ? take_pending_error(c) : LD_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 ld_status ld_sync(ld_ctx* c) {
     g_err.clear();
@@ -1006,6 +1080,7 @@ ld_status ld_checkpoint_load(ld_ctx** out, const char* path, void* stream) {
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->oid, ids.data(), sizeof(int) * N, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->st, &ds, sizeof ds, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = ld::launch_msd_ref(c->pos, c->lo, c->oid, (int)N, c->ref, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         ld_destroy(c);

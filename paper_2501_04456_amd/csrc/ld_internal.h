@@ -90,6 +90,7 @@ __host__ __device__ inline double radius_at(const ld_radius& R, double t) {
 
 struct PairLaunch {
     const float4* pos;
+    const float4* lo;                    // low words of the positions
     const int* typ;
     const Box* box;                      // per 64-slot group, or nullptr
     int n;
@@ -102,6 +103,12 @@ struct PairLaunch {
     double* U;                           // [2][n] or nullptr (diagnostic mode)
 };
 hipError_t launch_pair(const PairLaunch& L, const PairTable& tab, hipStream_t s);
+// Mean square displacement against FP64 reference positions [3][n] in
+// original order: store the reference, or reduce the mean into out[0].
+hipError_t launch_msd_ref(const float4* pos, const float4* lo, const int* oid, int n,
+                          double* ref, hipStream_t s);
+hipError_t launch_msd(const float4* pos, const float4* lo, const int* oid, int n,
+                      const double* ref, double* work, double* out, hipStream_t s);
 
 struct StepLaunch {
     float4* pos;
@@ -327,6 +334,7 @@ struct ld_ctx {
     double* U_slot = nullptr;            // [2][n]
     double* work = nullptr;              // [16][n] FP64 scratch (outputs, reductions)
     double* aux = nullptr;               // [kAuxWords] histograms and small results
+    double* ref = nullptr;               // [3][n] MSD reference positions, original order
     ld::DevState* st = nullptr;
     ld::SortBuffers sb{};
     int64_t steps_since_sort = 0;

@@ -163,7 +163,56 @@ __global__ void k_diag_finish(const double* sums, const double* maxes, const dou
     out[9] = maxes[1];
 }
 
+// MSD reference: the FP64 position hi + lo of every NP, in original order
+// ([3][n]).
+__global__ __launch_bounds__(kBlock) void k_msd_ref(const float4* __restrict__ pos,
+                                                   const float4* __restrict__ lo,
+                                                   const int* __restrict__ oid, int n,
+                                                   double* __restrict__ ref) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const float4 h = pos[s], l = lo[s];
+    const size_t o = (size_t)oid[s], N = (size_t)n;
+    ref[o] = (double)h.x + (double)l.x;
+    ref[N + o] = (double)h.y + (double)l.y;
+    ref[2 * N + o] = (double)h.z + (double)l.z;
+}
+
+// Squared displacement of every slot from its reference position.
+__global__ __launch_bounds__(kBlock) void k_msd_terms(const float4* __restrict__ pos,
+                                                     const float4* __restrict__ lo,
+                                                     const int* __restrict__ oid, int n,
+                                                     const double* __restrict__ ref,
+                                                     double* __restrict__ work) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const float4 h = pos[s], l = lo[s];
+    const size_t o = (size_t)oid[s], N = (size_t)n;
+    const double dx = ((double)h.x + (double)l.x) - ref[o];
+    const double dy = ((double)h.y + (double)l.y) - ref[N + o];
+    const double dz = ((double)h.z + (double)l.z) - ref[2 * N + o];
+    work[s] = dx * dx + dy * dy + dz * dz;
+}
+
+__global__ void k_mean_finish(double* v, int n) { v[0] = v[0] / (double)n; }
+
 }  // namespace
+
+hipError_t launch_msd_ref(const float4* pos, const float4* lo, const int* oid, int n,
+                          double* ref, hipStream_t s) {
+    hipLaunchKernelGGL(k_msd_ref, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, lo,
+                       oid, n, ref);
+    return hipGetLastError();
+}
+
+hipError_t launch_msd(const float4* pos, const float4* lo, const int* oid, int n,
+                      const double* ref, double* work, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_msd_terms, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pos, lo,
+                       oid, n, ref, work);
+    hipLaunchKernelGGL(k_rowreduce<0>, dim3(1), dim3(1024), 0, s, work, n, out);
+    hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(1), 0, s, out, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_update(const StepLaunch& L, const ExtParams& P, hipStream_t s) {
     const int blocks = (L.n + kBlock - 1) / kBlock;

@@ -84,6 +84,12 @@ class ld_ff_train_report(C.Structure):
                 ("val_rel_rms_raw", C.c_double)]
 
 
+class ld_diag(C.Structure):
+    _fields_ = [("step", C.c_int64), ("t", C.c_double), ("R", C.c_double),
+                ("U", C.c_double * 5), ("net_force", C.c_double * 3), ("max_force", C.c_double),
+                ("max_radius", C.c_double), ("msd", C.c_double), ("bad_step", C.c_int64)]
+
+
 class ld_paper_config(C.Structure):
     _fields_ = [("range_factor", C.c_double), ("kick", C.c_double),
                 ("inertial_mass", C.c_double * MAX_TYPES)]
@@ -108,6 +114,7 @@ SYMBOLS = [
     "ld_paper_enable", "ld_paper_disable", "ld_paper_forces", "ld_paper_get_velocities",
     "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count", "ld_record_open",
     "ld_record_close", "ld_cbar_type", "ld_surface_fractal", "ld_ff_save", "ld_ff_load",
+    "ld_msd", "ld_msd_reset",
 ]
 
 _lib = None
@@ -127,7 +134,10 @@ def lib():
         L.ld_destroy.restype = None
         L.ld_last_error.restype = C.c_char_p
         L.ld_forces.argtypes = [vp, dp, dp, dp, dp]
-        L.ld_step.argtypes = [vp, C.c_double, C.c_int64]
+        L.ld_step.argtypes = [vp, C.c_double, C.c_int64, C.POINTER(ld_radius),
+                              C.POINTER(C.c_uint64), C.POINTER(ld_diag)]
+        L.ld_msd.argtypes = [vp, dp]
+        L.ld_msd_reset.argtypes = [vp]
         L.ld_sync.argtypes = [vp]
         L.ld_get_positions.argtypes = [vp, fp, fp]
         L.ld_set_positions.argtypes = [vp, vp, vp]
@@ -325,9 +335,34 @@ class System:
             out["U"] = Uu
         return out
 
-    def step(self, n_steps: int, dt: float = None):
+    def step(self, n_steps: int, dt: float = None, radius: W.Radius = None, seed: int = None,
+             diag: bool = False):
+        """n_steps steps of size dt; a new radius schedule and/or noise seed
+        apply from the first of them on.  diag=True waits and returns the
+        state and FP64 diagnostics after the steps (a dict); a blow-up then
+        raises NonFinite."""
         dt = self.dt if dt is None else dt
-        _check(lib().ld_step(self.h, float(dt), int(n_steps)))
+        r = C.byref(make_radius(radius)) if radius is not None else None
+        sd = C.byref(C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF)) if seed is not None else None
+        d = ld_diag() if diag else None
+        _check(lib().ld_step(self.h, float(dt), int(n_steps), r, sd,
+                             C.byref(d) if diag else None))
+        if radius is not None:
+            self.radius = radius
+        if not diag:
+            return None
+        return {"step": d.step, "t": d.t, "R": d.R, "U": np.array(d.U[:]),
+                "net_force": np.array(d.net_force[:]), "max_force": d.max_force,
+                "max_radius": d.max_radius, "msd": d.msd, "bad_step": d.bad_step}
+
+    def msd(self) -> float:
+        """Mean square displacement against the reference positions."""
+        v = C.c_double()
+        _check(lib().ld_msd(self.h, C.byref(v)))
+        return v.value
+
+    def msd_reset(self):
+        _check(lib().ld_msd_reset(self.h))
 
     def sync(self):
         _check(lib().ld_sync(self.h))

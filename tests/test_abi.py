@@ -46,7 +46,7 @@ def test_struct_layouts_match_header():
                       ("ld_tuning", ldrop.ld_tuning), ("ld_ff_config", ldrop.ld_ff_config),
                       ("ld_ff_train_cfg", ldrop.ld_ff_train_cfg),
                       ("ld_ff_train_report", ldrop.ld_ff_train_report),
-                      ("ld_paper_config", ldrop.ld_paper_config)):
+                      ("ld_paper_config", ldrop.ld_paper_config), ("ld_diag", ldrop.ld_diag)):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", txt).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = []
