@@ -46,8 +46,8 @@ __global__ void k_ens_reset(unsigned* counter) { *counter = 0u; }
 
 template <int COMP, bool CULL>
 __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
-    const float4* __restrict__ pos, const int* __restrict__ typ, const int* __restrict__ off,
-    const int2* __restrict__ items, int W, unsigned* counter, const PairTable* __restrict__ tabs,
+    const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
+    const int* __restrict__ off, const int2* __restrict__ items, int W, unsigned* counter, const PairTable* __restrict__ tabs,
     const Box* __restrict__ box, const int* __restrict__ tbase, double* __restrict__ F,
     int total) {
     __shared__ float4 sp[kWaves][kGroup];
@@ -75,6 +75,7 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
         const int i = it.y + lane;
         const bool live = i < nd;
         const float4 pi = live ? pos[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 li = live ? lo[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
         const int ti = live ? typ[o + i] : 0;
         pair::Acc a;
         Box bi;
@@ -105,7 +106,8 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
             }
             wave_sync();
             if (near)
-                pair::group_near<COMP, false>(sp[w], stp[w], ttab[w], T, rc2max, jt, i, ti, pi, a);
+                pair::group_near<COMP, false>(sp[w], stp[w], ttab[w], T, rc2max, jt, i, ti, pi,
+                                              lo + o + jt, min(kGroup, nd - jt), li, a);
             else
                 pair::group_far<COMP, 16>(sp[w], pi, a);
         }
@@ -332,12 +334,12 @@ template <int COMP>
 void launch_ens_pair(ld_ens* e, hipStream_t s) {
     if (e->cull)
         hipLaunchKernelGGL((k_ens_pair<COMP, true>), dim3(e->workgroups), dim3(kEnsBlock), 0, s,
-                           e->pos, e->typ, e->off, e->items, e->W, e->counter, e->tabs, e->box,
-                           e->tbase, e->F, e->total);
+                           e->pos, e->lo, e->typ, e->off, e->items, e->W, e->counter, e->tabs,
+                           e->box, e->tbase, e->F, e->total);
     else
         hipLaunchKernelGGL((k_ens_pair<COMP, false>), dim3(e->workgroups), dim3(kEnsBlock), 0, s,
-                           e->pos, e->typ, e->off, e->items, e->W, e->counter, e->tabs, e->box,
-                           e->tbase, e->F, e->total);
+                           e->pos, e->lo, e->typ, e->off, e->items, e->W, e->counter, e->tabs,
+                           e->box, e->tbase, e->F, e->total);
 }
 
 ld_status enqueue_pair(ld_ens* e, hipStream_t s) {

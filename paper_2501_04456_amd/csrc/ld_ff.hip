@@ -1862,7 +1862,7 @@ ld_status ff_learned_forces(ld_ctx* c, hipStream_t s, double* Fc, double* Fm, bo
 // Direct pair forces summed into one slot-order array dst [3][n].
 ld_status ff_direct_total(ld_ctx* c, hipStream_t s, double* dst) {
     ld::PairLaunch L{};
-    L.pos = c->pos; L.typ = c->typ; L.box = c->box; L.n = (int)c->n;
+    L.pos = c->pos; L.lo = c->lo; L.typ = c->typ; L.box = c->box; L.n = (int)c->n;
     L.block = c->tune.block; L.j_split = c->tune.j_split; L.comp = c->tune.comp;
     L.cull = c->tune.cull; L.Fpart = c->Fpart;
     HIP_TRY(ld::launch_pair(L, c->tab, s));
@@ -2022,7 +2022,7 @@ ld_status ff_step_forces(ld_ctx* c, hipStream_t s, int* j_split_used) {
         ++f->learned_steps;
     } else {
         ld::PairLaunch L{};
-        L.pos = c->pos; L.typ = c->typ; L.box = c->box; L.n = (int)c->n;
+        L.pos = c->pos; L.lo = c->lo; L.typ = c->typ; L.box = c->box; L.n = (int)c->n;
         L.block = c->tune.block; L.j_split = c->tune.j_split; L.comp = c->tune.comp;
         L.cull = c->tune.cull; L.Fpart = c->Fpart;
         HIP_TRY(ld::launch_pair(L, c->tab, s));

@@ -30,6 +30,7 @@ using namespace pair;
 
 template <int BLOCK, int COMP, bool DIAG, bool CULL>
 __global__ __launch_bounds__(BLOCK) void k_pair(const float4* __restrict__ pos,
+                                                const float4* __restrict__ lo,
                                                 const int* __restrict__ typ,
                                                 const Box* __restrict__ box, int n,
                                                 int j_per_split, double* __restrict__ Fpart,
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const float4* __restrict__ pos,
     const int i = blockIdx.x * BLOCK + tid;
     const bool live = i < n;
     const float4 pi = live ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 li = live ? lo[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int ti = live ? typ[i] : 0;
     const int ngroups = (n + kGroup - 1) / kGroup;
 
@@ -102,7 +104,8 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const float4* __restrict__ pos,
             if constexpr (DIAG) near = true;
             if (__builtin_amdgcn_readfirstlane((int)near)) {
                 group_near<COMP, DIAG>(sp + g * kGroup, stp + g * kGroup, ttab, T,
-                                       tab.rc2max, jg, i, ti, pi, a);
+                                       tab.rc2max, jg, i, ti, pi, lo + jg,
+                                       max(0, min(kGroup, j1 - jg)), li, a);
             } else {
                 group_far<COMP>(sp + g * kGroup, pi, a);
             }
@@ -133,7 +136,7 @@ hipError_t launch_t(const PairLaunch& L, const PairTable& tab, hipStream_t s) {
     const int tiles = (L.n + BLOCK - 1) / BLOCK;
     const int per = (tiles + L.j_split - 1) / L.j_split;
     dim3 grid(tiles, L.j_split);
-    hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL>), grid, dim3(BLOCK), 0, s, L.pos, L.typ,
+    hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL>), grid, dim3(BLOCK), 0, s, L.pos, L.lo, L.typ,
                        L.box, L.n, per * BLOCK, L.Fpart, L.S, L.U, tab);
     return hipGetLastError();
 }

@@ -67,11 +67,22 @@ __device__ __forceinline__ void group_far(const float4* __restrict__ sp, const f
 }
 
 // 64 j particles that may hold LJ partners or i itself.
+//
+// Distances here include the low words of the positions: the difference of
+// the FP32 high words of two nearby particles is exact, and adding the
+// difference of their low words gives r_ij to FP32 rounding of r_ij itself,
+// not of |x|.  Near |x| = 300 sigma one ulp of a coordinate is 3e-5 sigma,
+// which a stiff LJ contact (U'' ~ 57 eps / sigma^2) would turn into a force
+// error far above 1e-5 of S_i.  The low words are read from global memory
+// (a wavefront-uniform address per j) only for the first `nvalid` slots of
+// the group; the rest are padding far away.
 template <int COMP, bool DIAG>
 __device__ __forceinline__ void group_near(const float4* __restrict__ sp,
                                            const int* __restrict__ stp,
                                            const float* __restrict__ ttab, int T, float rc2max,
-                                           int jbase, int i, int ti, const float4 pi, Acc& a) {
+                                           int jbase, int i, int ti, const float4 pi,
+                                           const float4* __restrict__ lo_j, int nvalid,
+                                           const float4 li, Acc& a) {
     const float* sig2 = ttab;
     const float* rc2 = ttab + kMaxTypes * kMaxTypes;
     const float* e24 = ttab + 2 * kMaxTypes * kMaxTypes;
@@ -83,9 +94,11 @@ __device__ __forceinline__ void group_near(const float4* __restrict__ sp,
 #pragma unroll 4
         for (int k = 0; k < KB; ++k) {
             const float4 pj = sp[kb + k];
-            const float dx = pj.x - pi.x;
-            const float dy = pj.y - pi.y;
-            const float dz = pj.z - pi.z;
+            float4 lj = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (kb + k < nvalid) lj = lo_j[kb + k];
+            const float dx = (pj.x - pi.x) + (lj.x - li.x);
+            const float dy = (pj.y - pi.y) + (lj.y - li.y);
+            const float dz = (pj.z - pi.z) + (lj.z - li.z);
             const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
             const float ri = __builtin_amdgcn_rsqf(r2);
             float w = (pj.w * ri) * (ri * ri);
