@@ -35,8 +35,8 @@ PEAK_FP32_NONPACKED = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GH
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=250000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
@@ -76,6 +76,16 @@ def parse():
     ap.add_argument("--compare", action="store_true",
                     help="ensemble: also time the droplets as separate contexts and one "
                          "droplet with the same sum of N^2")
+    ap.add_argument("--comp", type=int, default=None, choices=[0, 1],
+                    help="pair sums: 0 = FP32 blocks of 32 terms into FP64 totals, 1 = blocked "
+                         "Kahan (default: the library's)")
+    ap.add_argument("--no-windows", action="store_true",
+                    help="large: skip the middle and late 500-step windows (steps 4750 and "
+                         "9500 of the 1e4-step run)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="large: skip the learned-vs-direct comparison")
+    ap.add_argument("--learned-steps", type=int, default=100,
+                    help="large: steps timed per path in the learned-vs-direct comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -294,8 +304,11 @@ def bench_ensemble(a, torch, ldrop, W):
     """256 independent droplets in one persistent launch per step."""
     e = W.config_ensemble()
     ens = ldrop.Ensemble(e.droplets)
-    if a.graph:
-        ens.set_tuning(graph_steps=a.graph)
+    if a.graph or a.comp is not None:
+        ens.set_tuning(graph_steps=a.graph, comp=a.comp or 0)
+    t_tune = time.perf_counter()
+    tuned = ens.autotune()                 # workgroups and unroll, timed on this ensemble
+    tune_s = time.perf_counter() - t_tune
     # warm-up covers at least one captured chunk, so capture and instantiation
     # stay outside the timed region
     ens.step(max(a.warmup, 2 * a.graph), e.dt)
@@ -374,7 +387,8 @@ def bench_ensemble(a, torch, ldrop, W):
         "dtype": "f32 pair math, f64 totals", "data": "synthetic",
         "config": {"workload": "ensemble: 256 droplets, N log-uniform in [500, 8000]",
                    "total_particles": int(sum(d.n for d in e.droplets)),
-                   "sum_N2": pairs, "graph_steps": a.graph, "jump_flags": flagged},
+                   "sum_N2": pairs, "graph_steps": a.graph, "tuning": tuned,
+                   "autotune_s": tune_s, "jump_flags": flagged},
         "roofline": {"kernel": "k_ens_pair (persistent)", "bound": "alu",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
@@ -384,10 +398,13 @@ def bench_ensemble(a, torch, ldrop, W):
     }), flush=True)
 
 
-def bench_learned(a, torch, ldrop, W):
+def learned_run(a, torch, ldrop, W, steps=None):
     """Learned far field vs direct summation at N = 250000 (medium
-    composition): train on snapshots of a training-seed trajectory, then time
-    both paths on an evaluation-seed system and judge the learned forces."""
+    composition): train on snapshots of training-seed droplets, then time
+    both paths on an evaluation-seed system and judge the learned forces.
+    Returns the result as a dict (the gain test: median error of the near
+    part alone, of near + coarse expansion, and of near + coarse + MLP)."""
+    steps = a.steps if steps is None else steps
     import numpy as np
 
     def timed(sys_, steps, dt):
@@ -432,11 +449,11 @@ def bench_learned(a, torch, ldrop, W):
     ev.ff_enable(**ffkw)
     ev.ff_set_weights(weights, sq, scale)
     ev.step(a.warmup, we.dt)
-    ms_direct = timed(ev, a.steps, we.dt)
+    ms_direct = timed(ev, steps, we.dt)
     err = ev.ff_judge()
     ev.ff_mode(1)
     ev.step(2, we.dt)
-    ms_learned = timed(ev, a.steps, we.dt)
+    ms_learned = timed(ev, steps, we.dt)
     # the method without the network (near + coarse only)
     K = 4 * 5 ** 3 + 3
     o = (K + 31) // 32 * 32 * 128 + 128 + 128 * 128 + 128
@@ -453,13 +470,18 @@ def bench_learned(a, torch, ldrop, W):
     err_near = float(np.median(np.linalg.norm(Ff, axis=1) / np.maximum(tot, 1e-300)))
     judge_stats = ev.ff_stats()
     pairs = float(we.n) * (we.n - 1)
-    print(json.dumps({
+    return {
         "metric": "learned vs direct steps/s at N=2.5e5 and median force error",
         "value": 1e3 / ms_learned, "unit": "steps/s",
         "direct_steps_per_s": 1e3 / ms_direct, "speedup": ms_direct / ms_learned,
         "median_rel_force_err": err, "median_rel_force_err_without_mlp": err_nonet,
-        "median_rel_force_err_near_only": err_near, "judge": judge_stats,
-        "judge_tol": 1e-3, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "median_rel_force_err_near_only": err_near,
+        "mlp_gain": {"near_only": err_near, "near_plus_coarse": err_nonet,
+                     "near_plus_coarse_plus_mlp": err,
+                     "mlp_lowers_error_by": (err_nonet - err) / err_nonet if err_nonet else None,
+                     "fitted_output_gain": rep.get("gain")},
+        "judge": judge_stats,
+        "judge_tol": 1e-3, "n_gpus": 1, "steps": steps, "warmup": a.warmup,
         "higher_is_better": True, "dtype": "f32 pair math, bf16 MLP, f64 totals",
         "data": "synthetic",
         "config": {"workload": "learned: N=250000 medium composition, 32^3 moments, 5^3 block, "
@@ -472,7 +494,11 @@ def bench_learned(a, torch, ldrop, W):
                    "train_from": a.train_from},
         "training": {**rep, "collect_s": collect_s, "train_s": train_s},
         "direct_pair_interactions_per_s": pairs * 1e3 / ms_direct,
-    }), flush=True)
+    }
+
+
+def bench_learned(a, torch, ldrop, W):
+    print(json.dumps(learned_run(a, torch, ldrop, W)), flush=True)
 
 
 def main():
@@ -516,6 +542,8 @@ def main():
         s.autotune()
     if a.graph:
         s.set_tuning(graph_steps=a.graph)
+    if a.comp is not None:
+        s.set_tuning(comp=a.comp)
     tune = s.tuning()
     flagged = []
 
@@ -610,6 +638,43 @@ def main():
         out["pair_interactions_per_s"] = pairs * out["value"]
         out["ms_per_step"] = ms_g / a.steps
         out["ms_per_step_eager"] = ms / a.steps
+    if a.workload == "large" and not a.no_windows:
+        # the same run carried on to the middle and the end of its 1e4 steps
+        # (the wall moves 300 -> 112.5 sigma and packs the NPs towards the
+        # surface): 500-step windows timed like the first one
+        def window(start, length=500):
+            step_now = s.state()[0]
+            if start > step_now:
+                s.step(start - step_now, w.dt)
+            sync()
+            torch.cuda.synchronize()
+            s.kernel_timing(True)
+            ev0.record()
+            s.step(length, w.dt)
+            ev1.record()
+            torch.cuda.synchronize()
+            wms = ev0.elapsed_time(ev1)
+            nl, pms = s.kernel_time()
+            s.kernel_timing(False)
+            nflag = len(flagged)
+            sync()
+            st_, t_, R_ = s.state()
+            apm = pms / max(nl, 1)
+            return {"steps": [int(st_ - length), int(st_)], "R_end": R_,
+                    "steps_per_s": length / (wms / 1e3),
+                    "pair_interactions_per_s": pairs * length / (wms / 1e3),
+                    "avg_pair_launch_ms": apm,
+                    "frac": flops_launch / (apm / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+                    "jump_flags": flagged[nflag:]}
+
+        first = {"steps": [int(max(a.warmup, 2 * a.graph)),
+                           int(max(a.warmup, 2 * a.graph) + a.steps)],
+                 "steps_per_s": out["value"], "avg_pair_launch_ms": avg_pair_ms,
+                 "frac": out["roofline"]["frac"]}
+        mid = window(4750)
+        late = window(9500)
+        out["windows"] = {"first": first, "middle": mid, "late": late}
+        out["late"] = late
     # informative: the whole state handed back to the host (ld_get_positions,
     # hi and lo FP32 words of every coordinate) after a step, and the step
     # rate if every step did that; `value` keeps the inputs resident
@@ -625,6 +690,22 @@ def main():
     out["steps_per_s_with_positions_to_host"] = 1e3 / (out["ms_per_step"] + rb_ms)
     if not a.no_cpu_baseline and a.workload == "large":
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+    if a.workload == "large" and not a.no_learned:
+        # the metric's second half: learned far field vs direct summation at
+        # N = 250000 (its own droplet, the medium composition), with the gain
+        # test of the trained network
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        r = learned_run(a, torch, ldrop, W, steps=a.learned_steps)
+        out["learned_vs_direct"] = {
+            k: r[k] for k in ("value", "direct_steps_per_s", "speedup", "median_rel_force_err",
+                              "mlp_gain", "judge", "judge_tol", "steps", "config")}
+        out["learned_vs_direct"]["unit"] = "steps/s"
+        out["learned_vs_direct"]["training"] = {
+            k: r["training"].get(k) for k in ("samples", "iterations", "val_rel_rms",
+                                             "val_rel_rms_raw", "gain", "collect_s",
+                                             "train_s")}
     print(json.dumps(out), flush=True)
 
 

@@ -127,14 +127,22 @@ typedef struct {
 /* Create a context for n >= 2 NPs.
  *   type   [n] int32 in [0, p->n_types)
  *   charge [n] FP64 charges in elementary charges
- *   pos    [n*3] FP32 positions (x0 y0 z0 x1 ...), all finite
+ *   pos    [n*3] FP32 positions (x0 y0 z0 x1 ...), all finite; or NULL:
+ *          sampled here, uniform in the ball of radius R(0) with no pair
+ *          closer than sigma_ij (section 2.1: NPs placed at random in the
+ *          droplet).  Particle i in index order takes its k-th candidate
+ *          (k = 0, 1, ...) from Philox4x32-10 with counter (i, k, 0, 1) and
+ *          the noise key: v_c = 2 ((u_c >> 9) + 1/2) 2^-23 - 1 from the
+ *          first three words; |v|^2 > 1 is dropped, else x = FP32(R(0) v) is
+ *          kept when |x - x_j|^2 >= sigma_ij^2 (FP64) for every kept j < i.
+ *          LD_EINVAL if a particle finds no place in 100000 candidates.
  *   p, R   parameters and radius schedule (copied)
  *   seed   Philox key of the Brownian noise stream
  *   stream hipStream_t to enqueue on (NULL: the null stream)
  * The noise for NP i at step k is Philox4x32-10 with counter (i, k mod 2^32,
  * k div 2^32, 0) and key (seed mod 2^32, seed div 2^32); the four words become
  * uniforms ((u >> 9) + 0.5) 2^-23 (exact in FP32) and then three normals by
- * Box-Muller: (sqrt(-2 ln U0) cos 2 pi U1, sqrt(-2 ln U0) sin 2 pi U1,
+ * Box-Muller in FP64: (sqrt(-2 ln U0) cos 2 pi U1, sqrt(-2 ln U0) sin 2 pi U1,
  * sqrt(-2 ln U2) cos 2 pi U3).
  * Errors: LD_EINVAL (n, types, parameters), LD_ENOMEM, LD_EHIP. */
 ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* charge,
@@ -299,10 +307,11 @@ ld_status ld_set_tuning(ld_ctx* ctx, const ld_tuning* t);
  * the step state unchanged.  Errors: LD_EINVAL, LD_EHIP. */
 ld_status ld_autotune(ld_ctx* ctx, const char* cache_path, int32_t force, ld_tuning* out);
 
-/* Time every pair-kernel launch with HIP events on the context's stream.
- * enable = 1 starts (and clears) the record, 0 stops it.  ld_kernel_time
- * waits for the stream and returns the number of timed launches and their
- * total duration in milliseconds. */
+/* Time every launch of the all-pairs Coulomb kernel with HIP events on the
+ * context's stream (the short-ranged Lennard-Jones kernel that follows it is
+ * not included).  enable = 1 starts (and clears) the record, 0 stops it.
+ * ld_kernel_time waits for the stream and returns the number of timed
+ * launches and their total duration in milliseconds. */
 ld_status ld_kernel_timing(ld_ctx* ctx, int32_t enable);
 ld_status ld_kernel_time(ld_ctx* ctx, int64_t* launches, double* total_ms);
 
@@ -458,6 +467,24 @@ void ld_ens_destroy(ld_ens* e);
  * Kahan), and the number of steps captured in one HIP graph (0: no graph).
  * Captured steps replay with the dt they were captured with. */
 ld_status ld_ens_set_tuning(ld_ens* e, int32_t workgroups, int32_t comp, int32_t graph_steps);
+
+/* out = {workgroups, comp, graph_steps, unroll}. */
+ld_status ld_ens_get_tuning(ld_ens* e, int32_t out[4]);
+
+/* Coulomb pairs in flight per lane in the persistent pair kernel: 8, 16
+ * (default) or 32.  Errors: LD_EINVAL. */
+ld_status ld_ens_set_unroll(ld_ens* e, int32_t unroll);
+
+/* Choose the persistent pair kernel's workgroup count (2..8 per compute
+ * unit) and unroll (8, 16, 32) by timing the pair step (forces only; the
+ * droplets do not move) with HIP events, keeping the compensation mode and
+ * graph length.  cache_path (or NULL): a text file of lines
+ * "key workgroups unroll ms"; the key holds the GPU architecture, the
+ * droplet count, quarter-octave buckets of sum_d N_d^2 and of the largest
+ * N_d, the culling and compensation modes.  A cached key is used without
+ * timing unless force != 0; new results are appended.  out (or NULL) as in
+ * ld_ens_get_tuning.  Errors: LD_EINVAL, LD_EHIP. */
+ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int32_t out[4]);
 
 /* Advance all droplets n_steps >= 0 steps of size dt > 0 (asynchronous). */
 ld_status ld_ens_step(ld_ens* e, double dt, int64_t n_steps);

@@ -82,6 +82,9 @@ def lib():
         L.ldo_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                         C.POINTER(C.c_uint32)]
         L.ldo_gauss3.argtypes = [C.c_int64, C.c_int64, C.c_uint64, C.c_uint32, dp]
+        L.ldo_sample_ball.argtypes = [C.c_int64, C.POINTER(C.c_int32), dp, C.c_double,
+                                      C.c_uint64, C.c_int64, dp]
+        L.ldo_sample_ball.restype = C.c_int64
         L.ldo_radius_at.argtypes = [C.POINTER(_Radius), C.c_double]
         L.ldo_radius_at.restype = C.c_double
         L.ldo_pair_forces.argtypes = [C.c_int64, dp, C.POINTER(C.c_int32), dp,
@@ -214,6 +217,20 @@ def gauss3(pid: int, step: int, seed: int, tag: int = 0) -> np.ndarray:
     out = np.zeros(3)
     lib().ldo_gauss3(pid, step, seed, tag, _dp(out))
     return out
+
+
+def sample_ball(type_, sigma, R0: float, seed: int, max_tries: int = 100000):
+    """Initial positions [n,3] (FP32 values as FP64): uniform in the ball of
+    radius R0, no pair closer than sigma_ij; raises if a particle finds no
+    place in max_tries candidates."""
+    type_ = np.ascontiguousarray(type_, dtype=np.int32)
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    x = np.zeros((len(type_), 3))
+    bad = lib().ldo_sample_ball(len(type_), _ip(type_), _dp(sig), float(R0),
+                                C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(max_tries), _dp(x))
+    if bad:
+        raise RuntimeError(f"particle {bad} found no place")
+    return x
 
 
 def radius_at(radius, t: float) -> float:

@@ -74,6 +74,39 @@ void ldo_gauss3(int64_t id, int64_t step, uint64_t seed, uint32_t tag, double xi
 }
 
 /* ------------------------------------------------------------------------ */
+/* Initial placement: uniform in the ball, no overlaps (section 2.1).       */
+/* ------------------------------------------------------------------------ */
+int64_t ldo_sample_ball(int64_t n, const int32_t* type, const double* sigma, double R0,
+                        uint64_t seed, int64_t max_tries, double* x) {
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < n; ++i) {
+        int placed = 0;
+        for (int64_t k = 0; k < max_tries && !placed; ++k) {
+            uint32_t ctr[4] = {(uint32_t)i, (uint32_t)k, 0u, 1u}, r[4];
+            ldo_philox4x32_10(ctr, key, r);
+            double v[3];
+            for (int c = 0; c < 3; ++c) v[c] = 2.0 * u23(r[c]) - 1.0;
+            if (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] > 1.0) continue;
+            double c3[3];
+            for (int c = 0; c < 3; ++c) c3[c] = (double)(float)(R0 * v[c]);
+            int clash = 0;
+            for (int64_t j = 0; j < i && !clash; ++j) {
+                const double s = 0.5 * (sigma[type[i]] + sigma[type[j]]);
+                const double dx = c3[0] - x[3 * j];
+                const double dy = c3[1] - x[3 * j + 1];
+                const double dz = c3[2] - x[3 * j + 2];
+                if (dx * dx + dy * dy + dz * dz < s * s) clash = 1;
+            }
+            if (clash) continue;
+            for (int c = 0; c < 3; ++c) x[3 * i + c] = c3[c];
+            placed = 1;
+        }
+        if (!placed) return i;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Droplet radius R(t) (section 2.1, section 2.2 step (iii)).               */
 /* ------------------------------------------------------------------------ */
 double ldo_radius_at(const ldo_radius* R, double t) {

@@ -81,6 +81,20 @@ void ldo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
  * moments and by the uniform mapping's exactness. */
 void ldo_gauss3(int64_t id, int64_t step, uint64_t seed, uint32_t tag, double xi[3]);
 
+/* Initial positions uniform in the ball of radius R0 with every pair at
+ * least sigma_ij = (sigma_a + sigma_b) / 2 apart (section 2.1: NPs placed at
+ * random in the droplet; no two may overlap).  Particle i (in index order)
+ * takes its k-th candidate (k = 0, 1, ...) from Philox4x32-10 with counter
+ * (i, k, 0, 1) and key (seed mod 2^32, seed div 2^32): the first three
+ * words give v_c = 2 ((u_c >> 9) + 1/2) 2^-23 - 1; a candidate with
+ * |v|^2 > 1 is outside the ball and is dropped; otherwise x = FP32(R0 v_c)
+ * per component, accepted when |x - x_j|^2 >= sigma_ij^2 (FP64 on the FP32
+ * values) for every accepted j < i.  x [n*3] receives the FP32 values as
+ * FP64.  Returns 0, or the first index that found no place in max_tries
+ * candidates (then x holds the particles before it).  Plain O(n^2). */
+int64_t ldo_sample_ball(int64_t n, const int32_t* type, const double* sigma, double R0,
+                        uint64_t seed, int64_t max_tries, double* x);
+
 /* R(t).  Pinned by closed forms. */
 double ldo_radius_at(const ldo_radius* R, double t);
 

@@ -181,6 +181,9 @@ __global__ __launch_bounds__(kB) void k_ag_hook(const float4* __restrict__ pos,
                                                 const int* __restrict__ cfirst, int n,
                                                 AgTable tb, const int* __restrict__ surf,
                                                 int* parent, int* err) {
+    // the oracle's operand order, no fused multiply-add: a pair within an ulp
+    // of the contact distance lands on the same side in both
+#pragma clang fp contract(off)
     const int k = blockIdx.x * kB + threadIdx.x;
     if (k >= n) return;
     const unsigned long long key = keys[k];
@@ -295,6 +298,7 @@ __global__ __launch_bounds__(kB) void k_ag_surface(const float4* __restrict__ po
                                                    const float4* __restrict__ lo,
                                                    const int* __restrict__ typ, int n, double R,
                                                    AgTable tb, long long* part) {
+#pragma clang fp contract(off)
     __shared__ int cnt[kMaxTypes];
     if (threadIdx.x < kMaxTypes) cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -315,6 +319,7 @@ __global__ __launch_bounds__(kB) void k_sf_flag(const float4* __restrict__ pos,
                                                 const float4* __restrict__ lo,
                                                 const int* __restrict__ typ, int n, double R,
                                                 AgTable tb, int* surf) {
+#pragma clang fp contract(off)
     const int s = blockIdx.x * kB + threadIdx.x;
     if (s >= n) return;
     const float4 h = pos[s], l = lo[s];

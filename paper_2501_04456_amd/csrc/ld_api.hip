@@ -124,6 +124,10 @@ void make_tables(const ld_params& p, const ld_radius& R, PairTable& tb, ExtParam
             tb.rc2[k] = (float)(rc * rc);
             tb.e24[k] = (float)(24.0 * e);
             tb.e4[k] = (float)(4.0 * e);
+            tb.sig2d[k] = s * s;
+            tb.e24d[k] = 24.0 * e;
+            tb.e4d[k] = 4.0 * e;
+            tb.rc2d[k] = rc * rc;
             if (rc * rc > rc2max) rc2max = rc * rc;
         }
     tb.rc2max = (float)rc2max;
@@ -163,7 +167,9 @@ void default_tuning(ld_ctx* c) {
     // Enough workgroups to fill 256 CUs (7 resident per CU) many times over
     // (a short tail), but at least 256 j per split so each workgroup streams
     // whole LDS tiles.
-    t.block = n >= 16384 ? 256 : 64;
+    // (block 64 with culling keeps a whole j tile in registers: one
+    // wavefront per SIMD; 128 keeps eight)
+    t.block = n >= 16384 ? 256 : 128;
     const int64_t tiles = (n + t.block - 1) / t.block;
     int64_t split = (32768 + tiles - 1) / tiles;
     int64_t cap = n / 256;
@@ -228,8 +234,8 @@ ld_status run_pair(ld_ctx* c, bool diag, hipStream_t s, bool timed) {
         if (!e0 || !e1) return fail(LD_EHIP, "cannot create timing events");
         HIP_TRY(hipEventRecord(e0, s));
     }
-    HIP_TRY(ld::launch_pair(L, c->tab, s));
-    if (timed) HIP_TRY(hipEventRecord(e1, s));
+    // timed: the Coulomb kernel alone (the Lennard-Jones kernel follows it)
+    HIP_TRY(ld::launch_pair(L, c->tab, s, timed ? e1 : nullptr));
     return LD_OK;
 }
 
@@ -358,6 +364,89 @@ void free_all(ld_ctx* c) {
 
 }  // namespace
 
+// ---- initial placement (ld_init with pos = NULL) -------------------------
+
+namespace {
+
+constexpr int64_t kSampleTries = 100000;
+
+// Philox4x32-10 on the host (Salmon, Moraes, Dror, Shaw, SC'11).
+void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Uniform in the ball of radius R0, no pair closer than sigma_ij (section
+// 2.1: NPs placed at random in the droplet without overlap).  Particle i in
+// index order draws candidate k = 0, 1, ... from the Philox counter
+// (i, k, 0, 1) with the noise key: v_c = 2 ((u_c >> 9) + 1/2) 2^-23 - 1 from
+// the first three words, dropped if |v|^2 > 1, else x = FP32(R0 v), kept if
+// |x - x_j|^2 >= sigma_ij^2 (FP64 on the FP32 values) for every kept j < i.
+// Earlier particles are found through a hash of cells of side max sigma.
+// Returns -1, or the first particle that found no place.
+int64_t sample_ball(int64_t n, const int32_t* type, const double* sigma, double R0,
+                    uint64_t seed, int64_t max_tries, float* x) {
+#pragma clang fp contract(off)
+    double smax = 0.0;
+    for (int64_t i = 0; i < n; ++i) smax = std::max(smax, sigma[type[i]]);
+    const double h = smax;                       // cell side >= any sigma_ij
+    size_t cap = 1;
+    while (cap < 2 * (size_t)n) cap <<= 1;
+    std::vector<int64_t> head(cap, -1), next((size_t)n, -1);
+    auto cell = [&](double v) { return (int64_t)std::floor(v / h); };
+    auto slot = [&](int64_t a, int64_t b, int64_t c) {
+        uint64_t k = (uint64_t)a * 0x9E3779B97F4A7C15ull ^ (uint64_t)b * 0xC2B2AE3D27D4EB4Full ^
+                     (uint64_t)c * 0x165667B19E3779F9ull;
+        return (size_t)((k ^ (k >> 29)) & (cap - 1));
+    };
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int64_t i = 0; i < n; ++i) {
+        bool placed = false;
+        for (int64_t k = 0; k < max_tries && !placed; ++k) {
+            uint32_t c[4] = {(uint32_t)i, (uint32_t)k, 0u, 1u};
+            philox_host(c, k0, k1);
+            double v[3];
+            for (int d = 0; d < 3; ++d)
+                v[d] = 2.0 * (((double)(c[d] >> 9) + 0.5) * (1.0 / 8388608.0)) - 1.0;
+            if (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] > 1.0) continue;
+            double y[3];
+            for (int d = 0; d < 3; ++d) y[d] = (double)(float)(R0 * v[d]);
+            const int64_t cx = cell(y[0]), cy = cell(y[1]), cz = cell(y[2]);
+            bool clash = false;
+            for (int64_t a = cx - 1; a <= cx + 1 && !clash; ++a)
+                for (int64_t b = cy - 1; b <= cy + 1 && !clash; ++b)
+                    for (int64_t e = cz - 1; e <= cz + 1 && !clash; ++e)
+                        for (int64_t j = head[slot(a, b, e)]; j >= 0 && !clash; j = next[j]) {
+                            const double sij = 0.5 * (sigma[type[i]] + sigma[type[j]]);
+                            const double dx = y[0] - (double)x[3 * j];
+                            const double dy = y[1] - (double)x[3 * j + 1];
+                            const double dz = y[2] - (double)x[3 * j + 2];
+                            if (dx * dx + dy * dy + dz * dz < sij * sij) clash = true;
+                        }
+            if (clash) continue;
+            for (int d = 0; d < 3; ++d) x[3 * i + d] = (float)y[d];
+            const size_t sl = slot(cx, cy, cz);
+            next[i] = head[sl];
+            head[sl] = i;
+            placed = true;
+        }
+        if (!placed) return i;
+    }
+    return -1;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* ld_last_error(void) { return g_err.c_str(); }
@@ -369,7 +458,7 @@ ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* ch
     if (!out) return fail(LD_EINVAL, "out is NULL");
     *out = nullptr;
     if (n < 2 || n > (1 << 27)) return fail(LD_EINVAL, "n=%lld outside [2, 2^27]", (long long)n);
-    if (!type || !charge || !pos) return fail(LD_EINVAL, "type, charge and pos are required");
+    if (!type || !charge) return fail(LD_EINVAL, "type and charge are required");
     ld_status st = check_params(p);
     if (st != LD_OK) return st;
     st = check_radius(R);
@@ -381,14 +470,25 @@ ld_status ld_init(ld_ctx** out, int64_t n, const int32_t* type, const double* ch
     std::vector<float> x;
     if ((st = read_host(ty, type, (size_t)n, s)) != LD_OK) return st;
     if ((st = read_host(q, charge, (size_t)n, s)) != LD_OK) return st;
-    if ((st = read_host(x, pos, (size_t)n * 3, s)) != LD_OK) return st;
     for (int64_t i = 0; i < n; ++i) {
         if (ty[i] < 0 || ty[i] >= p->n_types)
             return fail(LD_EINVAL, "type[%lld]=%d outside [0,%d)", (long long)i, ty[i], p->n_types);
         if (!std::isfinite(q[i])) return fail(LD_EINVAL, "charge[%lld] not finite", (long long)i);
-        for (int k = 0; k < 3; ++k)
-            if (!std::isfinite(x[3 * i + k]))
-                return fail(LD_EINVAL, "pos[%lld] not finite", (long long)i);
+    }
+    if (pos) {
+        if ((st = read_host(x, pos, (size_t)n * 3, s)) != LD_OK) return st;
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k)
+                if (!std::isfinite(x[3 * i + k]))
+                    return fail(LD_EINVAL, "pos[%lld] not finite", (long long)i);
+    } else {
+        const double R0 = ld::radius_at(*R, 0.0);
+        if (!(R0 > 0.0)) return fail(LD_EINVAL, "sampling needs R(0) > 0");
+        x.resize((size_t)n * 3);
+        const int64_t bad = sample_ball(n, ty.data(), p->sigma, R0, seed, kSampleTries, x.data());
+        if (bad >= 0)
+            return fail(LD_EINVAL, "no place for particle %lld in the ball of radius %g after %lld "
+                        "candidates (too dense)", (long long)bad, R0, (long long)kSampleTries);
     }
 
     ld_ctx* c = new (std::nothrow) ld_ctx();

@@ -20,6 +20,8 @@
 // side is uncharged.  Outputs are mapped back to the original order through
 // the per-droplet index, which travels with the particle.
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
 #include <cmath>
 #include <new>
 
@@ -44,15 +46,13 @@ __device__ __forceinline__ void wave_sync() {
 
 __global__ void k_ens_reset(unsigned* counter) { *counter = 0u; }
 
-template <int COMP, bool CULL>
-__global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
+template <int COMP, bool CULL, int UNROLL>
+__global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
     const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
     const int* __restrict__ off, const int2* __restrict__ items, int W, unsigned* counter, const PairTable* __restrict__ tabs,
     const Box* __restrict__ box, const int* __restrict__ tbase, double* __restrict__ F,
     int total) {
     __shared__ float4 sp[kWaves][kGroup];
-    __shared__ int stp[kWaves][kGroup];
-    __shared__ float ttab[kWaves][4 * kMaxTypes * kMaxTypes];
     const int w = threadIdx.x / kGroup;
     const int lane = threadIdx.x % kGroup;
     for (;;) {
@@ -64,19 +64,11 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
         const int d = it.x;
         const int o = off[d];
         const int nd = off[d + 1] - o;
-        const PairTable* tb = tabs + d;
-        wave_sync();
-        ttab[w][lane] = tb->sig2[lane];
-        ttab[w][kMaxTypes * kMaxTypes + lane] = tb->rc2[lane];
-        ttab[w][2 * kMaxTypes * kMaxTypes + lane] = tb->e24[lane];
-        ttab[w][3 * kMaxTypes * kMaxTypes + lane] = tb->e4[lane];
-        const int T = tb->T;
-        const float rc2max = tb->rc2max;
+        const float rc2max = tabs[d].rc2max;
         const int i = it.y + lane;
         const bool live = i < nd;
         const float4 pi = live ? pos[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
         const float4 li = live ? lo[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const int ti = live ? typ[o + i] : 0;
         pair::Acc a;
         Box bi;
         int t0 = 0;
@@ -97,19 +89,13 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
             }
             wave_sync();
             const int j = jt + lane;
-            if (j < nd) {
-                sp[w][lane] = pos[o + j];
-                stp[w][lane] = typ[o + j];
-            } else {
-                sp[w][lane] = make_float4(kFarAway, kFarAway, kFarAway, 0.f);
-                stp[w][lane] = 0;
-            }
+            sp[w][lane] = j < nd ? pos[o + j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
             wave_sync();
             if (near)
-                pair::group_near<COMP, false>(sp[w], stp[w], ttab[w], T, rc2max, jt, i, ti, pi,
-                                              lo + o + jt, min(kGroup, nd - jt), li, a);
+                pair::group_near<COMP, false>(sp[w], jt, i, pi, lo + o + jt,
+                                              min(kGroup, nd - jt), li, a);
             else
-                pair::group_far<COMP, 16>(sp[w], pi, a);
+                pair::group_far<COMP, UNROLL>(sp[w], pi, a);
         }
         if constexpr (COMP == 1) {
             a.Fx = (double)a.sx - (double)a.cx;
@@ -119,10 +105,79 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_pair(
         if (live) {
             const double qi = (double)pi.w;
             const size_t s = (size_t)(o + i);
-            F[s] = -qi * a.Fx - a.Lx;
-            F[(size_t)total + s] = -qi * a.Fy - a.Ly;
-            F[2 * (size_t)total + s] = -qi * a.Fz - a.Lz;
+            F[s] = -qi * a.Fx;
+            F[(size_t)total + s] = -qi * a.Fy;
+            F[2 * (size_t)total + s] = -qi * a.Fz;
         }
+    }
+}
+
+// Lennard-Jones forces of every tile of every droplet, in FP64, added into F
+// after k_ens_pair (one wavefront per 64-slot tile; j groups of the same
+// droplet whose boxes come within the largest LJ range, or all of them when
+// boxes are off).
+__global__ __launch_bounds__(kEnsBlock) void k_ens_lj(
+    const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
+    const int* __restrict__ off, const int2* __restrict__ tiles, int ntiles,
+    const PairTable* __restrict__ tabs, const Box* __restrict__ box,
+    const int* __restrict__ tbase, double* __restrict__ F, int total) {
+    __shared__ float4 sh[kWaves][kGroup];
+    __shared__ float4 sl[kWaves][kGroup];
+    __shared__ int st[kWaves][kGroup];
+    const int w = threadIdx.x / kGroup;
+    const int lane = threadIdx.x % kGroup;
+    const int t = blockIdx.x * kWaves + w;
+    if (t >= ntiles) return;                // whole wavefronts only; no block barrier below
+    const int2 tl = tiles[t];
+    const int d = tl.x;
+    const int o = off[d];
+    const int nd = off[d + 1] - o;
+    const int i = tl.y - o + lane;
+    const bool live = i < nd;
+    const PairTable* tb = tabs + d;
+    const double* t64 = tb->sig2d;           // sig2d, e24d, e4d, rc2d follow each other
+    const int T = tb->T;
+    const float4 pi = live ? pos[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 li = live ? lo[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int ti = live ? typ[o + i] : 0;
+    Box bi;
+    if (box) bi = box[t];
+    const float cull2 = tb->rc2max * 1.0001f;
+    const int ng = (nd + kGroup - 1) / kGroup;
+    const int t0 = tbase[d];
+    double L[3] = {0.0, 0.0, 0.0};
+    double S = 0.0, U = 0.0;
+    for (int c0 = 0; c0 < ng; c0 += kGroup) {
+        bool nb = c0 + lane < ng;
+        if (nb && box) nb = pair::box_dist2(bi, box[t0 + c0 + lane]) < cull2;
+        unsigned long long m = __ballot(nb);
+        while (m) {
+            const int g = c0 + __builtin_ctzll(m);
+            m &= m - 1ull;
+            const int j = g * kGroup + lane;
+            wave_sync();
+            sh[w][lane] = j < nd ? pos[o + j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+            sl[w][lane] = j < nd ? lo[o + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            st[w][lane] = j < nd ? typ[o + j] : 0;
+            wave_sync();
+#pragma unroll 1
+            for (int k = 0; k < kGroup; ++k) {
+                const float4 pj = sh[w][k];
+                const float4 lj = sl[w][k];
+                const float dx = (pj.x - pi.x) + (lj.x - li.x);
+                const float dy = (pj.y - pi.y) + (lj.y - li.y);
+                const float dz = (pj.z - pi.z) + (lj.z - li.z);
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                if (r2 < cull2 && live && g * kGroup + k != i)
+                    pair::lj_pair64<false>(pj, lj, pi, li, t64, ti * T + st[w][k], L, S, U);
+            }
+        }
+    }
+    if (live) {
+        const size_t s = (size_t)(o + i);
+        F[s] -= L[0];
+        F[(size_t)total + s] -= L[1];
+        F[2 * (size_t)total + s] -= L[2];
     }
 }
 
@@ -282,6 +337,7 @@ struct ld_ens {
     int workgroups = 0;
     int comp = 0;
     int graph_steps = 0;
+    int unroll = 16;                     // Coulomb pairs in flight per lane (8, 16 or 32)
     hipGraphExec_t graph = nullptr;
     double graph_dt = 0.0;
     int graph_len = 0;
@@ -330,16 +386,26 @@ ld_status enqueue_sort(ld_ens* e, hipStream_t s) {
     return LD_OK;
 }
 
+template <int COMP, int UNROLL>
+void launch_ens_pair_u(ld_ens* e, hipStream_t s) {
+    if (e->cull)
+        hipLaunchKernelGGL((k_ens_pair<COMP, true, UNROLL>), dim3(e->workgroups), dim3(kEnsBlock),
+                           0, s, e->pos, e->lo, e->typ, e->off, e->items, e->W, e->counter,
+                           e->tabs, e->box, e->tbase, e->F, e->total);
+    else
+        hipLaunchKernelGGL((k_ens_pair<COMP, false, UNROLL>), dim3(e->workgroups),
+                           dim3(kEnsBlock), 0, s, e->pos, e->lo, e->typ, e->off, e->items, e->W,
+                           e->counter, e->tabs, e->box, e->tbase, e->F, e->total);
+}
+
 template <int COMP>
 void launch_ens_pair(ld_ens* e, hipStream_t s) {
-    if (e->cull)
-        hipLaunchKernelGGL((k_ens_pair<COMP, true>), dim3(e->workgroups), dim3(kEnsBlock), 0, s,
-                           e->pos, e->lo, e->typ, e->off, e->items, e->W, e->counter, e->tabs,
-                           e->box, e->tbase, e->F, e->total);
+    if (e->unroll == 8)
+        launch_ens_pair_u<COMP, 8>(e, s);
+    else if (e->unroll == 32)
+        launch_ens_pair_u<COMP, 32>(e, s);
     else
-        hipLaunchKernelGGL((k_ens_pair<COMP, false>), dim3(e->workgroups), dim3(kEnsBlock), 0, s,
-                           e->pos, e->lo, e->typ, e->off, e->items, e->W, e->counter, e->tabs,
-                           e->box, e->tbase, e->F, e->total);
+        launch_ens_pair_u<COMP, 16>(e, s);
 }
 
 ld_status enqueue_pair(ld_ens* e, hipStream_t s) {
@@ -351,6 +417,10 @@ ld_status enqueue_pair(ld_ens* e, hipStream_t s) {
         launch_ens_pair<0>(e, s);
     else
         launch_ens_pair<1>(e, s);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_ens_lj, dim3((e->ntiles + kWaves - 1) / kWaves), dim3(kEnsBlock), 0, s,
+                       e->pos, e->lo, e->typ, e->off, e->tiles, e->ntiles, e->tabs,
+                       e->cull ? e->box : nullptr, e->tbase, e->F, e->total);
     HIP_TRY(hipGetLastError());
     return LD_OK;
 }
@@ -507,7 +577,9 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
               hipMalloc(&e->seeds, sizeof(unsigned long long) * n_drop) == hipSuccess &&
               hipMalloc(&e->F, sizeof(double) * 3 * N) == hipSuccess &&
               hipMalloc(&e->work, sizeof(double) * 3 * N) == hipSuccess &&
-              hipMalloc(&e->st, sizeof(DevState)) == hipSuccess;
+              hipMalloc(&e->st, sizeof(DevState)) == hipSuccess &&
+              hipMalloc(&e->tbase, sizeof(int) * n_drop) == hipSuccess &&
+              hipMalloc(&e->tiles, sizeof(int2) * tiles.size()) == hipSuccess;
     // spatial ordering needs the droplet index in 13 bits
     e->cull = n_drop <= (1 << 13);
     e->ntiles = (int)tiles.size();
@@ -516,8 +588,6 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
     e->sb.n_pow2 = n_pow2;
     if (ok && e->cull)
         ok = hipMalloc(&e->box, sizeof(Box) * tiles.size()) == hipSuccess &&
-             hipMalloc(&e->tbase, sizeof(int) * n_drop) == hipSuccess &&
-             hipMalloc(&e->tiles, sizeof(int2) * tiles.size()) == hipSuccess &&
              hipMalloc(&e->dbounds, sizeof(float) * 6 * n_drop) == hipSuccess &&
              hipMalloc(&e->sb.keys, sizeof(unsigned long long) * n_pow2) == hipSuccess &&
              hipMalloc(&e->sb.tmp4, sizeof(float4) * N) == hipSuccess &&
@@ -546,10 +616,8 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
     up(e->ext, exts.data(), sizeof(ExtParams) * n_drop);
     up(e->seeds, sd.data(), sizeof(unsigned long long) * n_drop);
     up(e->st, &ds, sizeof ds);
-    if (e->cull) {
-        up(e->tbase, tbase.data(), sizeof(int) * n_drop);
-        up(e->tiles, tiles.data(), sizeof(int2) * tiles.size());
-    }
+    up(e->tbase, tbase.data(), sizeof(int) * n_drop);
+    up(e->tiles, tiles.data(), sizeof(int2) * tiles.size());
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) {
         ens_free(e);
@@ -586,6 +654,132 @@ ld_status ld_ens_set_tuning(ld_ens* e, int32_t workgroups, int32_t comp, int32_t
     if (e->graph) {
         (void)hipGraphExecDestroy(e->graph);
         e->graph = nullptr;
+    }
+    return LD_OK;
+}
+
+ld_status ld_ens_get_tuning(ld_ens* e, int32_t out[4]) {
+    g_err.clear();
+    if (!e || !out) return fail(LD_EINVAL, "ensemble and out are required");
+    out[0] = e->workgroups;
+    out[1] = e->comp;
+    out[2] = e->graph_steps;
+    out[3] = e->unroll;
+    return LD_OK;
+}
+
+ld_status ld_ens_set_unroll(ld_ens* e, int32_t unroll) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    if (unroll != 8 && unroll != 16 && unroll != 32)
+        return fail(LD_EINVAL, "unroll must be 8, 16 or 32");
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    e->unroll = unroll;
+    if (e->graph) {
+        (void)hipGraphExecDestroy(e->graph);
+        e->graph = nullptr;
+    }
+    return LD_OK;
+}
+
+ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int32_t out[4]) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    // cache key: architecture, droplet count, quarter-octave buckets of the
+    // pair count sum_d N_d^2 and of the largest droplet, culling, compensation
+    int dev = 0, cus = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    char arch[64];
+    std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    for (char* q = arch; *q; ++q)
+        if (*q == ':' || *q == ' ') *q = '_';
+    double pairs = 0.0;
+    int64_t nmax = 0;
+    for (int d = 0; d + 1 < (int)e->off_h.size(); ++d) {
+        const int64_t nd = e->off_h[d + 1] - e->off_h[d];
+        pairs += (double)nd * (double)nd;
+        nmax = std::max(nmax, nd);
+    }
+    char key[192];
+    std::snprintf(key, sizeof key, "ens/%s/d%d/p%d/m%d/cull%d/comp%d", arch, e->n_drop,
+                  (int)std::floor(std::log2(pairs) * 4.0),
+                  (int)std::floor(std::log2((double)nmax) * 4.0), e->cull ? 1 : 0, e->comp);
+    int best_w = e->workgroups, best_u = e->unroll;
+    bool cached = false;
+    if (cache_path && !force) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char k[192];
+            int wg = 0, un = 0;
+            double ms = 0.0;
+            while (std::fscanf(f, "%191s %d %d %lf", k, &wg, &un, &ms) == 4)
+                if (std::strcmp(k, key) == 0) {
+                    best_w = wg;
+                    best_u = un;
+                    cached = true;
+                }
+            std::fclose(f);
+        }
+    }
+    double best_ms = INFINITY;
+    if (!cached) {
+        const bool saved_timing = e->timing;
+        e->timing = false;
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        const int per_cu[] = {2, 3, 4, 5, 6, 8};
+        const int unrolls[] = {8, 16, 32};
+        ld_status st = LD_OK;
+        for (int u : unrolls) {
+            for (int k : per_cu) {
+                e->unroll = u;
+                e->workgroups = std::max(1, std::min(cus * k, (e->W + kWaves - 1) / kWaves));
+                double ms_min = INFINITY;
+                for (int rep = 0; rep < 4 && st == LD_OK; ++rep) {
+                    if (hipEventRecord(e0, e->stream) != hipSuccess) st = LD_EHIP;
+                    if (st == LD_OK) st = enqueue_pair(e, e->stream);
+                    if (st == LD_OK && hipEventRecord(e1, e->stream) != hipSuccess) st = LD_EHIP;
+                    if (st == LD_OK && hipEventSynchronize(e1) != hipSuccess) st = LD_EHIP;
+                    float ms = 0.f;
+                    if (st == LD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                        st = LD_EHIP;
+                    if (rep > 0 && ms < ms_min) ms_min = ms;   // the first is a warm-up
+                }
+                if (st != LD_OK) break;
+                if (ms_min < best_ms) {
+                    best_ms = ms_min;
+                    best_w = e->workgroups;
+                    best_u = u;
+                }
+            }
+            if (st != LD_OK) break;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        e->timing = saved_timing;
+        if (st != LD_OK) return fail(LD_EHIP, "ensemble autotune launch failed");
+        if (cache_path) {
+            if (FILE* f = std::fopen(cache_path, "a")) {
+                std::fprintf(f, "%s %d %d %.6f\n", key, best_w, best_u, best_ms);
+                std::fclose(f);
+            }
+        }
+    }
+    e->workgroups = best_w;
+    e->unroll = best_u;
+    if (e->graph) {
+        (void)hipGraphExecDestroy(e->graph);
+        e->graph = nullptr;
+    }
+    if (out) {
+        out[0] = e->workgroups;
+        out[1] = e->comp;
+        out[2] = e->graph_steps;
+        out[3] = e->unroll;
     }
     return LD_OK;
 }

@@ -31,6 +31,12 @@ struct PairTable {
     float rc2[kMaxTypes * kMaxTypes];    // (lj_cut sigma_ij)^2
     float e24[kMaxTypes * kMaxTypes];    // 24 eps_ij
     float e4[kMaxTypes * kMaxTypes];     // 4 eps_ij
+    // FP64 copies for the Lennard-Jones arithmetic (near the minimum the
+    // force is a small difference of two large terms)
+    double sig2d[kMaxTypes * kMaxTypes];
+    double e24d[kMaxTypes * kMaxTypes];
+    double e4d[kMaxTypes * kMaxTypes];
+    double rc2d[kMaxTypes * kMaxTypes];
 };
 
 // Per-type constants and globals for the O(N) kernels, all FP64.
@@ -102,7 +108,10 @@ struct PairLaunch {
     double* S;                           // [n] or nullptr (diagnostic mode)
     double* U;                           // [2][n] or nullptr (diagnostic mode)
 };
-hipError_t launch_pair(const PairLaunch& L, const PairTable& tab, hipStream_t s);
+// The Coulomb kernel (k_pair) and then the FP64 Lennard-Jones kernel (k_lj);
+// after_coulomb, if given, is recorded between the two.
+hipError_t launch_pair(const PairLaunch& L, const PairTable& tab, hipStream_t s,
+                       hipEvent_t after_coulomb = nullptr);
 // Mean square displacement against FP64 reference positions [3][n] in
 // original order: store the reference, or reduce the mean into out[0].
 hipError_t launch_msd_ref(const float4* pos, const float4* lo, const int* oid, int n,

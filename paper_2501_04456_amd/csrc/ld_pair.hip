@@ -1,26 +1,33 @@
-// All-pairs force kernel: the O(N^2) part of each step (section 2.2, step
+// All-pairs force kernels: the O(N^2) part of each step (section 2.2, step
 // (ii): Lennard-Jones and Coulomb forces, both unshifted; Coulomb here runs
 // over all pairs).
 //
-// Layout.  One work-item owns one particle i (slot order).  A workgroup of
-// BLOCK work-items streams the j range of its split through LDS one tile of
-// BLOCK particles at a time; every lane reads the same LDS word per j (a
-// broadcast), so the j stream costs one ds_read per wavefront per j and the
-// VALU does the rest.
+// k_pair: the Coulomb sum.  One work-item owns one particle i (slot order).
+// A workgroup of BLOCK work-items streams the j range of its split through
+// LDS one tile of BLOCK particles at a time; every lane reads the same LDS
+// word per j (a broadcast), so the j stream costs one ds_read per wavefront
+// per j and the VALU does the rest.  Per pair: 12 FP32 VALU operations plus
+// one v_rsq_f32 (three subtractions, r^2 as mul+fma+fma, q_j r^-3 as three
+// multiplications, three fma into the block accumulators).  With tile
+// culling on, a 64-particle j group whose bounding box is farther than the
+// largest LJ range from the wavefront's own box takes the plain loop on the
+// FP32 high words; a nearer group takes the loop that adds the low words to
+// the differences; a far pair of groups one of which is uncharged is
+// skipped (no force at all).
 //
-// Per pair the Coulomb-only path is 12 FP32 VALU operations plus one
-// v_rsq_f32: three subtractions, r^2 as mul+fma+fma, q_j r^-3 as three
-// multiplications and three fma into the block accumulators.  Lennard-Jones is
-// short-ranged (lj_cut sigma_ij), so it lives in a rarely taken branch.  With
-// tile culling on, a 64-particle j group whose bounding box is farther than
-// the largest LJ range from the wavefront's own box skips even the range
-// test.
+// k_lj: the Lennard-Jones sum, which is short-ranged (lj_cut sigma_ij):
+// each wavefront takes one 64-slot i group, finds the j groups whose boxes
+// come within the largest LJ range (a ballot over 64 boxes at a time),
+// stages each such group in LDS and evaluates the pairs inside the cutoff
+// in FP64.  It adds its result into the first force partial of each slot
+// after k_pair has written it (same stream, one writer per slot).
 //
-// Precision.  The pair terms are FP32.  Each lane sums KB = 32 of them in an
-// FP32 block accumulator and then moves the block into FP64 totals (COMP=0)
-// or into a blocked Kahan pair (COMP=1, flushed to FP64 at the end).  The
-// worst-case rounding of a 32-term FP32 block is 31 u sum|f| ~ 1.8e-6 of the
-// conditioning scale S_i = sum_j |f_ij|.
+// Precision.  The Coulomb pair terms are FP32.  Each lane sums KB = 32 of
+// them in an FP32 block accumulator and then moves the block into FP64
+// totals (COMP=0) or into a blocked Kahan pair (COMP=1, flushed to FP64 at
+// the end).  The worst-case rounding of a 32-term FP32 block is
+// 31 u sum|f| ~ 1.8e-6 of the conditioning scale S_i = sum_j |f_ij|.  The
+// Lennard-Jones terms are FP64 throughout.
 #include "ld_pair_core.h"
 
 namespace ld {
@@ -29,30 +36,20 @@ namespace {
 using namespace pair;
 
 template <int BLOCK, int COMP, bool DIAG, bool CULL>
-__global__ __launch_bounds__(BLOCK) void k_pair(const float4* __restrict__ pos,
+__global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : 8) void k_pair(const float4* __restrict__ pos,
                                                 const float4* __restrict__ lo,
-                                                const int* __restrict__ typ,
                                                 const Box* __restrict__ box, int n,
-                                                int j_per_split, double* __restrict__ Fpart,
+                                                int j_per_split, float rc2max,
+                                                double* __restrict__ Fpart,
                                                 double* __restrict__ S_out,
-                                                double* __restrict__ U_out, PairTable tab) {
+                                                double* __restrict__ U_out) {
     __shared__ float4 sp[BLOCK];
-    __shared__ int stp[BLOCK];
-    __shared__ float ttab[4 * kMaxTypes * kMaxTypes];
 
     const int tid = threadIdx.x;
-    const int T = tab.T;
-    for (int k = tid; k < kMaxTypes * kMaxTypes; k += BLOCK) {
-        ttab[k] = tab.sig2[k];
-        ttab[kMaxTypes * kMaxTypes + k] = tab.rc2[k];
-        ttab[2 * kMaxTypes * kMaxTypes + k] = tab.e24[k];
-        ttab[3 * kMaxTypes * kMaxTypes + k] = tab.e4[k];
-    }
     const int i = blockIdx.x * BLOCK + tid;
     const bool live = i < n;
     const float4 pi = live ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 li = live ? lo[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const int ti = live ? typ[i] : 0;
     const int ngroups = (n + kGroup - 1) / kGroup;
 
     // This wavefront's bounding box (culling only).
@@ -66,23 +63,17 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const float4* __restrict__ pos,
             bi.hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
         }
     }
-    // Tile culling must never drop a pair that the range test would keep:
-    // a small margin covers FP32 rounding of box distances against r^2.
-    const float cull2 = tab.rc2max * 1.0001f;
+    // A small margin covers FP32 rounding of box distances against r^2.
+    const float cull2 = rc2max * 1.0001f;
 
     const int j0 = blockIdx.y * j_per_split;
     const int j1 = min(n, j0 + j_per_split);
     Acc a;
+#pragma unroll 1
     for (int jt = j0; jt < j1; jt += BLOCK) {
         __syncthreads();
         const int j = jt + tid;
-        if (j < j1) {
-            sp[tid] = pos[j];
-            stp[tid] = typ[j];
-        } else {
-            sp[tid] = make_float4(kFarAway, kFarAway, kFarAway, 0.f);
-            stp[tid] = 0;
-        }
+        sp[tid] = j < j1 ? pos[j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
         __syncthreads();
 #pragma unroll 1
         for (int g = 0; g < BLOCK / kGroup; ++g) {
@@ -95,16 +86,13 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const float4* __restrict__ pos,
                 if (jg < j1 && gj < ngroups) {
                     const Box bj = box[gj];
                     near = box_dist2(bi, bj) < cull2;
-                    // a far pair of groups one of which is uncharged has no
-                    // force at all: skip it
                     coulomb = bi.lo.w != 0.f && bj.lo.w != 0.f;
                 }
                 if (!near && !__builtin_amdgcn_readfirstlane((int)coulomb)) continue;
             }
             if constexpr (DIAG) near = true;
             if (__builtin_amdgcn_readfirstlane((int)near)) {
-                group_near<COMP, DIAG>(sp + g * kGroup, stp + g * kGroup, ttab, T,
-                                       tab.rc2max, jg, i, ti, pi, lo + jg,
+                group_near<COMP, DIAG>(sp + g * kGroup, jg, i, pi, lo + jg,
                                        max(0, min(kGroup, j1 - jg)), li, a);
             } else {
                 group_far<COMP>(sp + g * kGroup, pi, a);
@@ -117,16 +105,99 @@ __global__ __launch_bounds__(BLOCK) void k_pair(const float4* __restrict__ pos,
         a.Fz = (double)a.sz - (double)a.cz;
     }
     if (live) {
-        // F_i = -q_i sum_j q_j r^-3 (x_j - x_i) - sum_j g_ij (x_j - x_i)
+        // F_i = -q_i sum_j q_j r^-3 (x_j - x_i)
         const double qi = (double)pi.w;
         double* F = Fpart + (size_t)blockIdx.y * 3 * (size_t)n;
-        F[i] = -qi * a.Fx - a.Lx;
-        F[(size_t)n + i] = -qi * a.Fy - a.Ly;
-        F[2 * (size_t)n + i] = -qi * a.Fz - a.Lz;
+        F[i] = -qi * a.Fx;
+        F[(size_t)n + i] = -qi * a.Fy;
+        F[2 * (size_t)n + i] = -qi * a.Fz;
         if constexpr (DIAG) {
             S_out[i] = a.S;
-            U_out[i] = a.Ul;
+            U_out[i] = 0.0;
             U_out[(size_t)n + i] = a.Uc;
+        }
+    }
+}
+
+constexpr int kLjBlock = 256;
+constexpr int kLjWaves = kLjBlock / kGroup;
+
+// Lennard-Jones forces of every slot, added into partial 0 (and, with DIAG,
+// into S and the LJ energy row of U).  Without boxes every group is visited.
+template <bool DIAG>
+__global__ __launch_bounds__(kLjBlock) void k_lj(const float4* __restrict__ pos,
+                                                  const float4* __restrict__ lo,
+                                                  const int* __restrict__ typ,
+                                                  const Box* __restrict__ box, int n,
+                                                  double* __restrict__ F,
+                                                  double* __restrict__ S_out,
+                                                  double* __restrict__ U_out, PairTable tab) {
+    __shared__ float4 sh[kLjWaves][kGroup];
+    __shared__ float4 sl[kLjWaves][kGroup];
+    __shared__ int st[kLjWaves][kGroup];
+    __shared__ double t64[4 * kMaxTypes * kMaxTypes];
+    for (int k = threadIdx.x; k < kMaxTypes * kMaxTypes; k += kLjBlock) {
+        t64[k] = tab.sig2d[k];
+        t64[kMaxTypes * kMaxTypes + k] = tab.e24d[k];
+        t64[2 * kMaxTypes * kMaxTypes + k] = tab.e4d[k];
+        t64[3 * kMaxTypes * kMaxTypes + k] = tab.rc2d[k];
+    }
+    __syncthreads();
+    const int w = threadIdx.x / kGroup;
+    const int lane = threadIdx.x % kGroup;
+    const int ngroups = (n + kGroup - 1) / kGroup;
+    const int gi = blockIdx.x * kLjWaves + w;
+    if (gi >= ngroups) return;              // whole wavefronts only; no block barrier below
+    const int i = gi * kGroup + lane;
+    const bool live = i < n;
+    const float4 pi = live ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 li = live ? lo[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int ti = live ? typ[i] : 0;
+    const int T = tab.T;
+    Box bi;
+    if (box) bi = box[gi];
+    const float cull2 = tab.rc2max * 1.0001f;
+    // FP32 screen on the (hi, lo) difference: relative error ~1e-7 in r^2
+    const float screen2 = tab.rc2max * 1.0001f;
+    double L[3] = {0.0, 0.0, 0.0};
+    double S = 0.0, U = 0.0;
+    for (int c0 = 0; c0 < ngroups; c0 += kGroup) {
+        const int gj = c0 + lane;
+        bool nb = gj < ngroups;
+        if (nb && box) nb = box_dist2(bi, box[gj]) < cull2;
+        unsigned long long m = __ballot(nb);
+        while (m) {
+            const int g = c0 + __builtin_ctzll(m);
+            m &= m - 1ull;
+            const int j = g * kGroup + lane;
+            __builtin_amdgcn_wave_barrier();
+            sh[w][lane] = j < n ? pos[j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+            sl[w][lane] = j < n ? lo[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            st[w][lane] = j < n ? typ[j] : 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 1
+            for (int k = 0; k < kGroup; ++k) {
+                const float4 pj = sh[w][k];
+                const float4 lj = sl[w][k];
+                const float dx = (pj.x - pi.x) + (lj.x - li.x);
+                const float dy = (pj.y - pi.y) + (lj.y - li.y);
+                const float dz = (pj.z - pi.z) + (lj.z - li.z);
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                if (r2 < screen2 && live && g * kGroup + k != i)
+                    lj_pair64<DIAG>(pj, lj, pi, li, t64, ti * T + st[w][k], L, S, U);
+            }
+        }
+    }
+    if (live) {
+        // F_i += -sum_j g_ij (x_j - x_i)
+        F[i] -= L[0];
+        F[(size_t)n + i] -= L[1];
+        F[2 * (size_t)n + i] -= L[2];
+        if constexpr (DIAG) {
+            S_out[i] += S;
+            U_out[i] += U;
         }
     }
 }
@@ -136,8 +207,8 @@ hipError_t launch_t(const PairLaunch& L, const PairTable& tab, hipStream_t s) {
     const int tiles = (L.n + BLOCK - 1) / BLOCK;
     const int per = (tiles + L.j_split - 1) / L.j_split;
     dim3 grid(tiles, L.j_split);
-    hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL>), grid, dim3(BLOCK), 0, s, L.pos, L.lo, L.typ,
-                       L.box, L.n, per * BLOCK, L.Fpart, L.S, L.U, tab);
+    hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL>), grid, dim3(BLOCK), 0, s, L.pos, L.lo,
+                       L.box, L.n, per * BLOCK, tab.rc2max, L.Fpart, L.S, L.U);
     return hipGetLastError();
 }
 
@@ -153,9 +224,7 @@ hipError_t launch_b(const PairLaunch& L, const PairTable& tab, hipStream_t s) {
                   : launch_t<BLOCK, 1, false, false>(L, tab, s);
 }
 
-}  // namespace
-
-hipError_t launch_pair(const PairLaunch& L, const PairTable& tab, hipStream_t s) {
+hipError_t launch_coulomb(const PairLaunch& L, const PairTable& tab, hipStream_t s) {
     switch (L.block) {
         case 64: return launch_b<64>(L, tab, s);
         case 128: return launch_b<128>(L, tab, s);
@@ -163,6 +232,25 @@ hipError_t launch_pair(const PairLaunch& L, const PairTable& tab, hipStream_t s)
         case 512: return launch_b<512>(L, tab, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+}  // namespace
+
+hipError_t launch_pair(const PairLaunch& L, const PairTable& tab, hipStream_t s,
+                       hipEvent_t after_coulomb) {
+    hipError_t e = launch_coulomb(L, tab, s);
+    if (e != hipSuccess) return e;
+    if (after_coulomb && (e = hipEventRecord(after_coulomb, s)) != hipSuccess) return e;
+    const int ngroups = (L.n + kGroup - 1) / kGroup;
+    const dim3 grid((ngroups + kLjWaves - 1) / kLjWaves);
+    const Box* box = L.box;          // boxes are kept current by sort and update
+    if (L.S)
+        hipLaunchKernelGGL(k_lj<true>, grid, dim3(kLjBlock), 0, s, L.pos, L.lo, L.typ, box, L.n,
+                           L.Fpart, L.S, L.U, tab);
+    else
+        hipLaunchKernelGGL(k_lj<false>, grid, dim3(kLjBlock), 0, s, L.pos, L.lo, L.typ, box,
+                           L.n, L.Fpart, L.S, L.U, tab);
+    return hipGetLastError();
 }
 
 }  // namespace ld

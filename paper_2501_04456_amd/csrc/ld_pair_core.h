@@ -6,7 +6,7 @@
 // multiplications and three fma into FP32 block accumulators.  Each lane sums
 // KB = 32 pair terms in FP32 and then moves the block into FP64 totals
 // (COMP=0) or into a blocked Kahan pair (COMP=1); LJ terms (near groups
-// only) have FP32 blocks of their own, moved into FP64 the same way.  The
+// only) are computed and summed in FP64 by their own kernel.  The
 // worst-case rounding of a 32-term FP32 block is 31 u sum|f| ~ 1.8e-6 of
 // S_i = sum_j |f_ij|.
 #pragma once
@@ -22,8 +22,7 @@ struct Acc {
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;   // sum_j q_j r^-3 (x_j - x_i), FP64
     float sx = 0.f, sy = 0.f, sz = 0.f;    // Kahan sums (COMP == 1)
     float cx = 0.f, cy = 0.f, cz = 0.f;    // Kahan compensations
-    double Lx = 0.0, Ly = 0.0, Lz = 0.0;   // sum_j g_ij (x_j - x_i), LJ
-    double S = 0.0, Uc = 0.0, Ul = 0.0;    // diagnostic mode only
+    double S = 0.0, Uc = 0.0;              // diagnostic mode only (Coulomb part)
 };
 
 template <int COMP>
@@ -66,31 +65,25 @@ __device__ __forceinline__ void group_far(const float4* __restrict__ sp, const f
     }
 }
 
-// 64 j particles that may hold LJ partners or i itself.
+// 64 j particles near i's group (within the largest LJ range of its box) or
+// holding i itself: the Coulomb terms with the low words of the positions
+// in the differences, the self pair left out.
 //
-// Distances here include the low words of the positions: the difference of
-// the FP32 high words of two nearby particles is exact, and adding the
-// difference of their low words gives r_ij to FP32 rounding of r_ij itself,
-// not of |x|.  Near |x| = 300 sigma one ulp of a coordinate is 3e-5 sigma,
-// which a stiff LJ contact (U'' ~ 57 eps / sigma^2) would turn into a force
-// error far above 1e-5 of S_i.  The low words are read from global memory
-// (a wavefront-uniform address per j) only for the first `nvalid` slots of
-// the group; the rest are padding far away.
+// The difference of the FP32 high words of two nearby particles is exact,
+// and adding the difference of their low words gives r_ij to FP32 rounding
+// of r_ij itself, not of |x|.  Near |x| = 300 sigma one ulp of a coordinate
+// is 3e-5 sigma, which at contact distance would move a Coulomb term by
+// ~1e-4 of itself.  The low words are read from global memory (a
+// wavefront-uniform address per j) only for the first `nvalid` slots of the
+// group; the rest are padding far away.  The Lennard-Jones terms of these
+// groups are added by a kernel of their own (k_lj), in FP64.
 template <int COMP, bool DIAG>
-__device__ __forceinline__ void group_near(const float4* __restrict__ sp,
-                                           const int* __restrict__ stp,
-                                           const float* __restrict__ ttab, int T, float rc2max,
-                                           int jbase, int i, int ti, const float4 pi,
-                                           const float4* __restrict__ lo_j, int nvalid,
-                                           const float4 li, Acc& a) {
-    const float* sig2 = ttab;
-    const float* rc2 = ttab + kMaxTypes * kMaxTypes;
-    const float* e24 = ttab + 2 * kMaxTypes * kMaxTypes;
-    const float* e4 = ttab + 3 * kMaxTypes * kMaxTypes;
+__device__ __forceinline__ void group_near(const float4* __restrict__ sp, int jbase, int i,
+                                           const float4 pi, const float4* __restrict__ lo_j,
+                                           int nvalid, const float4 li, Acc& a) {
 #pragma unroll
     for (int kb = 0; kb < kGroup; kb += KB) {
         float bx = 0.f, by = 0.f, bz = 0.f;   // Coulomb, FP32 block
-        float lx = 0.f, ly = 0.f, lz = 0.f;   // LJ, FP32 block
 #pragma unroll 4
         for (int k = 0; k < KB; ++k) {
             const float4 pj = sp[kb + k];
@@ -101,31 +94,10 @@ __device__ __forceinline__ void group_near(const float4* __restrict__ sp,
             const float dz = (pj.z - pi.z) + (lj.z - li.z);
             const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
             const float ri = __builtin_amdgcn_rsqf(r2);
-            float w = (pj.w * ri) * (ri * ri);
-            const int j = jbase + kb + k;
-            if (r2 < rc2max) {
-                if (j == i) {
-                    w = 0.f;
-                } else {
-                    const int pidx = ti * T + stp[kb + k];
-                    if (r2 < rc2[pidx]) {
-                        // r^-2 from the reciprocal square root already at hand
-                        const float ir2 = ri * ri;
-                        const float s2 = sig2[pidx] * ir2;
-                        const float s6 = s2 * s2 * s2;
-                        const float g = e24[pidx] * s6 * (2.0f * s6 - 1.0f) * ir2;
-                        lx = fmaf(g, dx, lx);
-                        ly = fmaf(g, dy, ly);
-                        lz = fmaf(g, dz, lz);
-                        if constexpr (DIAG) {
-                            a.S += (double)fabsf(g) * (double)(r2 * ri);
-                            a.Ul += 0.5 * (double)(e4[pidx] * s6 * (s6 - 1.0f));
-                        }
-                    }
-                }
-            }
+            const bool self = jbase + kb + k == i;
+            const float w = self ? 0.f : (pj.w * ri) * (ri * ri);
             if constexpr (DIAG) {
-                if (j != i) {
+                if (!self) {
                     const float qq = pi.w * pj.w;
                     a.S += (double)(fabsf(qq) * ri * ri);
                     a.Uc += 0.5 * (double)(qq * ri);
@@ -136,9 +108,35 @@ __device__ __forceinline__ void group_near(const float4* __restrict__ sp,
             bz = fmaf(w, dz, bz);
         }
         flush<COMP>(a, bx, by, bz);
-        a.Lx += (double)lx;
-        a.Ly += (double)ly;
-        a.Lz += (double)lz;
+    }
+}
+
+// One Lennard-Jones pair (section 2.1: truncated at lj_cut sigma_ij, not
+// shifted) in FP64 from the exact difference of the (hi, lo) positions, if
+// it is within the cutoff.  t64: sigma_ij^2, 24 eps_ij, 4 eps_ij and
+// (lj_cut sigma_ij)^2, each kMaxTypes^2 long.  Near the minimum the force is
+// a small difference of two large terms; FP32 operands would leave an error
+// of ~1e-6 of 24 eps_ij / r there.  Accumulates sum_j g_ij (x_j - x_i) and,
+// with DIAG, |f_ij| and half the pair energy.
+template <bool DIAG>
+__device__ __forceinline__ void lj_pair64(const float4 pj, const float4 lj, const float4 pi,
+                                          const float4 li, const double* __restrict__ t64,
+                                          int pidx, double L[3], double& S, double& U) {
+    const double ex = ((double)pj.x - (double)pi.x) + ((double)lj.x - (double)li.x);
+    const double ey = ((double)pj.y - (double)pi.y) + ((double)lj.y - (double)li.y);
+    const double ez = ((double)pj.z - (double)pi.z) + ((double)lj.z - (double)li.z);
+    const double q2 = ex * ex + ey * ey + ez * ez;
+    if (!(q2 < t64[3 * kMaxTypes * kMaxTypes + pidx])) return;
+    const double ir2 = 1.0 / q2;
+    const double s2 = t64[pidx] * ir2;                         // sigma_ij^2 / r^2
+    const double s6 = s2 * s2 * s2;
+    const double g = t64[kMaxTypes * kMaxTypes + pidx] * s6 * (2.0 * s6 - 1.0) * ir2;
+    L[0] += g * ex;
+    L[1] += g * ey;
+    L[2] += g * ez;
+    if constexpr (DIAG) {
+        S += fabs(g) * sqrt(q2);
+        U += 0.5 * (t64[2 * kMaxTypes * kMaxTypes + pidx] * s6 * (s6 - 1.0));
     }
 }
 

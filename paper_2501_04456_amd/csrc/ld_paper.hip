@@ -253,10 +253,9 @@ __global__ __launch_bounds__(kB) void k_pm_update(float4* pos, float4* lo,
     upd::ext_force(x, ty, R, P, Fe);
     double u[3] = {0.0, 0.0, 0.0};
     if (tb.kick > 0.0) {
-        float xi[3];
+        double xi[3];
         upd::gauss3((uint32_t)oid[s], (unsigned long long)step, seed, xi);
-        const double len = sqrt((double)xi[0] * xi[0] + (double)xi[1] * xi[1] +
-                                (double)xi[2] * xi[2]);
+        const double len = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
         u[0] = xi[0] / len;
         u[1] = xi[1] / len;
         u[2] = xi[2] / len;

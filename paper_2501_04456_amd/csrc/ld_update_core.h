@@ -22,21 +22,24 @@ __device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c
     }
 }
 
-// ((u >> 9) + 1/2) 2^-23: exact in FP32.
-__device__ __forceinline__ float u23(uint32_t u) {
-    return ((float)(u >> 9) + 0.5f) * (1.0f / 8388608.0f);
+// ((u >> 9) + 1/2) 2^-23: exact in FP32 and FP64.
+__device__ __forceinline__ double u23(uint32_t u) {
+    return ((double)(u >> 9) + 0.5) * (1.0 / 8388608.0);
 }
 
-// Three standard normals for particle id at step n (Box-Muller, FP32).
+// Three standard normals for particle id at step n (Box-Muller in FP64: the
+// logarithm, square root and sine/cosine in FP32 would carry relative errors
+// of ~1e-7, which a stiff Lennard-Jones contact turns into a visible drift of
+// the trajectory; in FP64 they cost well under a microsecond per step).
 __device__ __forceinline__ void gauss3(uint32_t id, unsigned long long n, unsigned long long seed,
-                                       float xi[3]) {
+                                       double xi[3]) {
     uint32_t c0 = id, c1 = (uint32_t)n, c2 = (uint32_t)(n >> 32), c3 = 0u;
     philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const float a = sqrtf(-2.0f * logf(u23(c0)));
-    const float b = sqrtf(-2.0f * logf(u23(c2)));
-    float s1, k1, s3, k3;
-    sincospif(2.0f * u23(c1), &s1, &k1);
-    sincospif(2.0f * u23(c3), &s3, &k3);
+    const double a = sqrt(-2.0 * log(u23(c0)));
+    const double b = sqrt(-2.0 * log(u23(c2)));
+    double s1, k1, s3, k3;
+    sincospi(2.0 * u23(c1), &s1, &k1);
+    sincospi(2.0 * u23(c3), &s3, &k3);
     xi[0] = a * k1;
     xi[1] = a * s1;
     xi[2] = b * k3;
@@ -99,21 +102,21 @@ __device__ __forceinline__ bool advance(float4& h, float4& l, const double F[3],
     double Fe[3];
     ext_force(x, ty, R, P, Fe);
     const double mu = P.mu[ty];
-    float xi[3] = {0.f, 0.f, 0.f};
+    double xi[3] = {0.0, 0.0, 0.0};
     double amp = 0.0;
     if (P.noise != 0 && P.kT > 0.0) {
         gauss3(id, step, seed, xi);
         amp = sqrt(2.0 * P.kT * mu * dt);
         if (P.noise == 2) {
-            const float m = sqrtf(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
-            const float f = 1.7320508075688772f / m;
+            const double m = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+            const double f = 1.7320508075688772 / m;
             xi[0] *= f; xi[1] *= f; xi[2] *= f;
         }
     }
     bool ok = true;
     double xn[3];
     for (int c = 0; c < 3; ++c) {
-        const double d = mu * dt * (F[c] + Fe[c]) + amp * (double)xi[c];
+        const double d = mu * dt * (F[c] + Fe[c]) + amp * xi[c];
         if (!isfinite(d) || (P.jump_max > 0.0 && fabs(d) > P.jump_max)) ok = false;
         xn[c] = x[c] + d;
     }

@@ -114,7 +114,8 @@ SYMBOLS = [
     "ld_paper_enable", "ld_paper_disable", "ld_paper_forces", "ld_paper_get_velocities",
     "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count", "ld_record_open",
     "ld_record_close", "ld_cbar_type", "ld_surface_fractal", "ld_ff_save", "ld_ff_load",
-    "ld_msd", "ld_msd_reset",
+    "ld_msd", "ld_msd_reset", "ld_ens_get_tuning", "ld_ens_set_unroll",
+    "ld_ens_autotune",
 ]
 
 _lib = None
@@ -160,6 +161,9 @@ def lib():
         L.ld_ens_destroy.restype = None
         L.ld_ens_set_tuning.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
         L.ld_ens_step.argtypes = [vp, C.c_double, C.c_int64]
+        L.ld_ens_get_tuning.argtypes = [vp, vp]
+        L.ld_ens_set_unroll.argtypes = [vp, C.c_int32]
+        L.ld_ens_autotune.argtypes = [vp, C.c_char_p, C.c_int32, vp]
         L.ld_ens_forces.argtypes = [vp, vp]
         L.ld_ens_get_positions.argtypes = [vp, vp, vp]
         L.ld_ens_get_state.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
@@ -264,15 +268,17 @@ class System:
         self.stream = torch.cuda.current_stream() if stream is None else stream
         t = torch.as_tensor(np.ascontiguousarray(type_, dtype=np.int32), device=dev)
         q = torch.as_tensor(np.ascontiguousarray(charge, dtype=np.float64), device=dev)
-        x = torch.as_tensor(np.ascontiguousarray(np.asarray(pos, dtype=np.float32).reshape(-1, 3)),
-                            device=dev)
+        # pos None: the library samples the initial positions itself
+        x = None if pos is None else torch.as_tensor(
+            np.ascontiguousarray(np.asarray(pos, dtype=np.float32).reshape(-1, 3)), device=dev)
         self.n = int(t.numel())
         self.params = params
         self.radius = radius
         self._p = make_params(params)
         self._r = make_radius(radius)
         h = C.c_void_p()
-        _check(lib().ld_init(C.byref(h), self.n, _ptr(t), _ptr(q), _ptr(x), C.byref(self._p),
+        _check(lib().ld_init(C.byref(h), self.n, _ptr(t), _ptr(q),
+                             None if x is None else _ptr(x), C.byref(self._p),
                              C.byref(self._r), int(seed) & 0xFFFFFFFFFFFFFFFF,
                              C.c_void_p(self.stream.cuda_stream)))
         self.h = h
@@ -679,8 +685,22 @@ class Ensemble:
         except Exception:
             pass
 
-    def set_tuning(self, workgroups: int = 0, comp: int = 0, graph_steps: int = 0):
+    def set_tuning(self, workgroups: int = 0, comp: int = 0, graph_steps: int = 0,
+                   unroll: int = 0):
         _check(lib().ld_ens_set_tuning(self.h, workgroups, comp, graph_steps))
+        if unroll:
+            _check(lib().ld_ens_set_unroll(self.h, unroll))
+
+    def tuning(self) -> dict:
+        out = np.zeros(4, np.int32)
+        _check(lib().ld_ens_get_tuning(self.h, out.ctypes.data_as(C.c_void_p)))
+        return dict(zip(("workgroups", "comp", "graph_steps", "unroll"), map(int, out)))
+
+    def autotune(self, cache_path: str = None, force: bool = False) -> dict:
+        out = np.zeros(4, np.int32)
+        _check(lib().ld_ens_autotune(self.h, cache_path.encode() if cache_path else None,
+                                     1 if force else 0, out.ctypes.data_as(C.c_void_p)))
+        return dict(zip(("workgroups", "comp", "graph_steps", "unroll"), map(int, out)))
 
     def step(self, n_steps: int, dt: float):
         _check(lib().ld_ens_step(self.h, float(dt), int(n_steps)))

@@ -6,8 +6,12 @@ Langevin with dt = 5e-4, Philox seed 3) is stepped 20 times by the CPU FP64
 oracle alone.  For a fixed sample of rows the file keeps, at every step
 k = 0 .. 19 (before the k-th update), the oracle's pair force on the row and
 its conditioning scale S_i = sum_j |f_ij|, a flag for rows that have an LJ
-pair within 1e-5 (relative) of its cutoff at that state, and the rows'
-positions after step 20.
+pair within 1e-5 (relative) of its cutoff at that state, a stiffness bound
+D_i (how fast the row's pair force can change when the row or a partner
+moves: sum over partners of |df/dr| + |f|/r, Lennard-Jones within the cutoff
+plus Coulomb over all pairs), and the rows' positions before every step
+and after step 20.  D_i lets a test compare forces taken at two states that
+differ by a small distance delta: |F(x) - F(x')| <= 2 delta D_i.
 
 Rows: 160 drawn at random, the 64 rows whose nearest neighbour is closest
 relative to the pair's contact distance (the stiffest LJ pairs of the
@@ -70,6 +74,29 @@ def near_cutoff(w, x, rows, rel=1e-5) -> np.ndarray:
     return out
 
 
+def stiffness(w, x, rows) -> np.ndarray:
+    """D_i = sum_j |f'(r_ij)| + |f(r_ij)| / r_ij over the row's pairs (the
+    Lennard-Jones law within its cutoff, Coulomb for all pairs): a bound on
+    the change of the pair force per unit relative displacement."""
+    p = w.params
+    sig = np.asarray(p.sigma)[w.type]
+    eps = np.asarray(p.eps)[w.type]
+    qh = np.asarray(w.charge) * np.sqrt(p.kT * p.bjerrum)
+    out = np.zeros(len(rows))
+    for k, i in enumerate(rows):
+        r = np.linalg.norm(x - x[i], axis=1)
+        r[i] = np.inf
+        s_ij = 0.5 * (sig[i] + sig)
+        lj = r < p.lj_cut * s_ij
+        rl = r[lj]
+        s6 = (s_ij[lj] / rl) ** 6
+        e = 24.0 * np.sqrt(eps[i] * eps[lj])
+        f = e * (2.0 * s6 * s6 - s6) / rl
+        fp = e * (-26.0 * s6 * s6 + 7.0 * s6) / (rl * rl)
+        out[k] = np.sum(np.abs(fp) + np.abs(f) / rl) + np.sum(3.0 * np.abs(qh[i] * qh) / r ** 3)
+    return out
+
+
 def main(out_path: str = OUT) -> None:
     oracle.build()
     w = W.config_large()
@@ -79,15 +106,21 @@ def main(out_path: str = OUT) -> None:
     F = np.zeros((STEPS, m, 3))
     S = np.zeros((STEPS, m))
     amb = np.zeros((STEPS, m), bool)
+    D = np.zeros((STEPS, m))
+    X = np.zeros((STEPS + 1, m, 3))
     t0 = time.time()
     for k in range(STEPS):
+        X[k] = st.x[rows]
         F[k], S[k], _ = oracle.pair_forces(st.x, w.type, w.charge, w.params, rows=rows)
         amb[k] = near_cutoff(w, st.x, rows)
+        D[k] = stiffness(w, st.x, rows)
         bad = st.run(1, w.dt)
         if bad != -1:
             raise SystemExit(f"the oracle flagged step {bad}")
         print(f"step {k + 1}/{STEPS} done ({time.time() - t0:.0f} s)", flush=True)
-    np.savez_compressed(out_path, rows=rows, F=F, S=S, near_cutoff=amb, x20=st.x[rows],
+    X[STEPS] = st.x[rows]
+    np.savez_compressed(out_path, rows=rows, F=F, S=S, near_cutoff=amb, D=D, x=X,
+                        x20=st.x[rows],
                         n=np.int64(w.n), seed=np.int64(w.seed), dt=np.float64(w.dt),
                         steps=np.int64(STEPS), pos_sha256=np.array(pos_digest(w.pos)))
     print("wrote", out_path)

@@ -159,3 +159,95 @@ def test_surface_fractal_degenerate(ld, orc):
         s.surface_fractal(9.0, k_f=0.0)
     with pytest.raises(RuntimeError):
         s.surface_fractal(9.0, contact_factor=-1.0)
+
+
+def _fma_r2(dx, dy, dz):
+    """r^2 as a fused chain fma(dz, dz, fma(dy, dy, dx * dx)), each step
+    rounded once (exact rational arithmetic, then one rounding to FP64)."""
+    from fractions import Fraction as Fr
+    t = dx * dx
+    t = float(Fr(dy) * Fr(dy) + Fr(t))
+    return float(Fr(dz) * Fr(dz) + Fr(t))
+
+
+def _split(x):
+    hi = x.astype(np.float32)
+    lo = (x - hi.astype(np.float64)).astype(np.float32)
+    return hi, lo
+
+
+def test_contact_and_surface_thresholds_within_an_ulp(ld, orc):
+    """Pairs whose r^2 lies within a couple of FP64 ulps of (f sigma_ij)^2 and
+    NPs whose | |x| - R | lies that close to sigma_t / 2: the component labels
+    and the surface counts must still equal the oracle's, which evaluates
+    the sums of squares left to right without fused multiply-adds.  The
+    generator checks that a fused evaluation would decide some of these
+    cases the other way, so the test has teeth."""
+    f = 1.1
+    sigma = [1.0, 1.6]
+    rng = np.random.default_rng(77)
+    # one pair per lattice site, sites 6 apart: pairs never touch each other
+    g = np.arange(-4, 5) * 6.0
+    sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    m = len(sites)
+    ta = rng.integers(0, 2, m).astype(np.int32)
+    tb = rng.integers(0, 2, m).astype(np.int32)
+    s = f * 0.5 * (np.asarray(sigma)[ta] + np.asarray(sigma)[tb])
+    rc2 = s * s
+    tries = 4000
+    u = rng.normal(size=(tries, m, 3))
+    u /= np.linalg.norm(u, axis=2)[..., None]
+    a = sites[None] + rng.uniform(-0.5, 0.5, (tries, m, 3))
+    b = a + u * (s[None, :, None] * (1.0 + rng.uniform(-4e-15, 4e-15, (tries, m, 1))))
+    ah, al = _split(a)
+    bh, bl = _split(b)
+    xa = ah.astype(np.float64) + al
+    xb = bh.astype(np.float64) + bl
+    d = xa - xb
+    r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+    ulp = np.spacing(rc2)[None]
+    close = np.abs(r2 - rc2[None]) <= 2 * ulp
+    pick = np.full(m, -1)
+    flips = 0
+    for k in range(m):
+        cand = np.nonzero(close[:, k])[0]
+        for c in cand:
+            if (_fma_r2(*d[c, k]) < rc2[k]) != (r2[c, k] < rc2[k]):
+                pick[k] = c
+                flips += 1
+                break
+        if pick[k] < 0 and len(cand):
+            pick[k] = cand[0]
+    assert flips >= 20, flips
+    keep = pick >= 0
+    idx = pick[keep]
+    sel = np.nonzero(keep)[0]
+    hi = np.concatenate([ah[idx, sel], bh[idx, sel]])
+    lo = np.concatenate([al[idx, sel], bl[idx, sel]])
+    typ = np.concatenate([ta[sel], tb[sel]]).astype(np.int32)
+    x = hi.astype(np.float64) + lo
+    sysm, w = system(ld, x, typ, sigma, R0=60.0)
+    sysm.set_positions(hi, lo)
+    gres = sysm.aggregates(f, labels=True)
+    nc, lab = orc.components(x, typ, w.params, f)
+    assert gres["components"] == nc
+    assert np.array_equal(gres["labels"].astype(np.int64), lab)
+
+    # surface band: | |x| - R | against sigma_t / 2 at both edges of the band
+    R = 40.0
+    n = 20000
+    t2 = rng.integers(0, 2, n).astype(np.int32)
+    h = 0.5 * np.asarray(sigma)[t2]
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    edge = R + np.where(rng.random(n) < 0.5, -h, h) * (1.0 + rng.uniform(-2e-14, 2e-14, n))
+    ph, pl = _split(v * edge[:, None])
+    px = ph.astype(np.float64) + pl
+    r = np.sqrt((px[:, 0] * px[:, 0] + px[:, 1] * px[:, 1]) + px[:, 2] * px[:, 2])
+    inside = np.abs(r - R) < h
+    sflips = sum(int((abs(np.sqrt(_fma_r2(*px[i])) - R) < h[i]) != inside[i])
+                 for i in np.nonzero(np.abs(np.abs(r - R) - h) <= 4 * np.spacing(R))[0])
+    assert sflips >= 5, sflips
+    sysm, w = system(ld, px, t2, sigma, R0=R)
+    sysm.set_positions(ph, pl)
+    assert np.array_equal(sysm.surface_count(), orc.surface_count(px, t2, w.params, R))

@@ -123,20 +123,25 @@ def test_ensemble_with_uncharged_particles(ld, orc):
     ens.step(12, drops[0].dt)              # re-sorts at the first step
     ens.sync()
     xg = ens.positions64()
+    xo = []
     for d, w in enumerate(drops):
         st = orc.State(w)
         assert st.run(12, w.dt) == -1
         assert np.abs(xg[off[d]:off[d + 1]] - st.x).max() <= 1e-4, d
-    # forces after the re-sort, in the original order, at the positions the
-    # pair math uses: the FP32 high parts (near an LJ contact half an FP32
-    # ulp of position moves the force by more than 1e-5 S)
+        xo.append(st.x.copy())
+    # forces after the re-sort, in the original order, at the GPU's stepped
+    # state, against the oracle's forces at its own stepped state: near
+    # groups (LJ contacts) take the low words into the pair differences, far
+    # groups use the high words only (an FP32 ulp of |x| moves a Coulomb term
+    # at r >= 2.5 sigma by far less than 1e-5 of S)
     F2 = ens.forces().cpu().numpy()
-    hi, _ = ens.positions()
     for d, w in enumerate(drops):
-        Fo, So, _ = orc.pair_forces(hi[off[d]:off[d + 1]].astype(np.float64), w.type, w.charge,
-                                    w.params)
-        dF = np.linalg.norm(F2[off[d]:off[d + 1]] - Fo, axis=1)
-        assert np.all(dF <= 1e-5 * So), d
+        Fo, So, _ = orc.pair_forces(xo[d], w.type, w.charge, w.params)
+        Fd = F2[off[d]:off[d + 1]]
+        dF = np.linalg.norm(Fd - Fo, axis=1)
+        k = int(np.argmax(dF - 1e-5 * So))
+        dx = np.abs(xg[off[d]:off[d + 1]] - xo[d]).max()
+        assert np.all(dF <= 1e-5 * So), (d, k, int(w.type[k]), dF[k], So[k], Fd[k], Fo[k], dx)
 
 
 def test_single_droplet_graph_matches_eager(ld):
@@ -200,3 +205,66 @@ def test_ensemble_radius_tables(ld, orc):
         assert st.run(steps, e.dt) == -1
         err = np.abs(xg[off[d]:off[d + 1]] - st.x).max()
         assert err <= 1e-4, (d, err)
+
+
+@pytest.mark.parametrize("sort_every,graph_steps", [(10, 1), (-1, 16)])
+def test_single_droplet_graph_trajectory_vs_oracle(ld, orc, sort_every, graph_steps):
+    """100 steps of the small droplet replayed from captured graphs (chunks
+    of re-sort + steps), against the oracle's 100 steps (including the step
+    at which both flag a move above the jump limit)."""
+    w = W.config_small()
+    s = ld.System.from_workload(w)
+    s.set_tuning(sort_every=sort_every, graph_steps=graph_steps)
+    s.step(100, w.dt)
+    gbad = -1
+    try:
+        s.sync()
+    except ld.NonFinite as e:            # both sides must flag the same move
+        gbad = int(str(e).split("step ")[1].split()[0])
+    st = orc.State(w)
+    assert st.run(100, w.dt) == gbad
+    assert s.state()[0] == 100
+    err = np.abs(s.positions64() - st.x).max()
+    assert err <= 1e-4, err
+
+
+def test_ensemble_graph_trajectory_vs_oracle(ld, orc, small_ensemble):
+    """24 ensemble steps as three graph replays of 8, each droplet against its
+    own oracle run."""
+    ens = ld.Ensemble(small_ensemble.droplets)
+    ens.set_tuning(graph_steps=8)
+    for _ in range(3):
+        ens.step(8, small_ensemble.dt)
+    ens.sync()
+    xg = ens.positions64()
+    off = ens.offsets
+    for d, w in enumerate(small_ensemble.droplets):
+        st = orc.State(w)
+        assert st.run(24, small_ensemble.dt) == -1
+        err = np.abs(xg[off[d]:off[d + 1]] - st.x).max()
+        assert err <= 1e-4, (d, err)
+
+
+def test_ensemble_autotune_and_cache(ld, orc, small_ensemble, tmp_path):
+    """The ensemble tuner picks a workgroup count and unroll, writes them to
+    its cache and reuses them; forces stay within 1e-5 of S_i of the oracle
+    droplet by droplet (the droplets do not move while it times)."""
+    ens = ld.Ensemble(small_ensemble.droplets)
+    cache = str(tmp_path / "ens_tune.txt")
+    t1 = ens.autotune(cache_path=cache)
+    assert t1["unroll"] in (8, 16, 32) and t1["workgroups"] >= 1
+    assert ens.state()[0] == 0
+    F = ens.forces().cpu().numpy()
+    off = ens.offsets
+    for d, w in enumerate(small_ensemble.droplets):
+        Fo, So, _ = orc.pair_forces(w.pos, w.type, w.charge, w.params)
+        dF = np.linalg.norm(F[off[d]:off[d + 1]] - Fo, axis=1)
+        assert np.all(dF <= 1e-5 * So), d
+    line = open(cache).read().split()
+    assert line[0].startswith("ens/") and int(line[1]) == t1["workgroups"]
+    assert int(line[2]) == t1["unroll"]
+    e2 = ld.Ensemble(small_ensemble.droplets)
+    t2 = e2.autotune(cache_path=cache)
+    assert (t2["workgroups"], t2["unroll"]) == (t1["workgroups"], t1["unroll"])
+    with pytest.raises(RuntimeError):
+        e2.set_tuning(unroll=12)

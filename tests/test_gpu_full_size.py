@@ -121,3 +121,66 @@ def test_ensemble_full_three_droplets(ld, orc):
         assert st.run(steps, e.dt) == -1
         err = np.abs(xg[off[d]:off[d + 1]] - st.x).max()
         assert err <= 1e-4, (d, err)
+
+
+GOLDEN_LARGE = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden",
+                                          "large_first20.npz")
+
+
+def test_large_first20_steps(ld):
+    """The large droplet (N = 250000, R0 = 300) in the launch configuration
+    the benchmark times (library default: Hilbert re-sort on), 20 steps of
+    its own trajectory against the oracle's 20 steps, on sampled rows:
+
+    * before every step k = 0 .. 19 the rows' positions agree with the
+      oracle's state k to delta_k, and the pair forces on the rows (taken
+      at the GPU's own state) agree with the oracle's forces at its state
+      within 1e-5 S_i + 2 delta D_i, where D_i bounds how fast the row's
+      force changes per unit relative displacement (at k = 0 the states are
+      identical and the bound is 1e-5 S_i alone); the median of |dF|/|F| is
+      within 1e-5;
+    * after step 20 the rows' positions agree within 1e-4 sigma.
+
+    delta = 1e-7 sigma is an upper bound for every step's state difference,
+    checked on the rows (FP64 noise on both sides; what remains is the
+    FP32 pair sums' ~1e-6 S rounding times mu dt).  The expected values
+    were written by tests/golden/make_large_first20.py, which calls only
+    the oracle and the seeded generator.  Rows with an LJ pair within 1e-5
+    of its cutoff at a step are left out of that step's force check."""
+    import hashlib
+    if not __import__("os").path.exists(GOLDEN_LARGE):
+        pytest.skip("tests/golden/large_first20.npz not written")
+    z = np.load(GOLDEN_LARGE, allow_pickle=False)
+    w = W.config_large()
+    assert int(z["n"]) == w.n and int(z["seed"]) == w.seed and float(z["dt"]) == w.dt
+    digest = hashlib.sha256(np.ascontiguousarray(w.pos, np.float32).tobytes()).hexdigest()
+    assert digest == str(z["pos_sha256"]), "the seeded generator changed"
+    rows = z["rows"]
+    delta = 1e-7
+    s = ld.System.from_workload(w)
+    worst_f, worst_x, stiff = 0.0, 0.0, 0
+    for k in range(int(z["steps"])):
+        xg = s.positions64()[rows]
+        dx = float(np.abs(xg - z["x"][k]).max())
+        assert dx <= delta, f"step {k}: state difference {dx:.3e}"
+        Fg = s.forces(ext=False)["pair"].cpu().numpy()[rows]
+        keep = ~z["near_cutoff"][k]
+        dF = np.linalg.norm(Fg - z["F"][k], axis=1)[keep]
+        S = z["S"][k][keep]
+        tol = 1e-5 * S + (2.0 * delta * z["D"][k][keep] if k > 0 else 0.0)
+        assert np.all(dF <= tol), f"step {k}: max |dF|/tol = {(dF / tol).max():.3e}"
+        nrm = np.linalg.norm(z["F"][k], axis=1)[keep]
+        rel = dF[nrm > 0] / nrm[nrm > 0]
+        assert np.median(rel) <= 1e-5, f"step {k}: median |dF|/|F| = {np.median(rel):.3e}"
+        worst_f = max(worst_f, float((dF / np.maximum(S, 1e-300)).max()))
+        worst_x = max(worst_x, dx)
+        stiff += int((dF > 1e-5 * S).sum())
+        print(f"large first20: step {k} state {dx:.1e} force {(dF / S).max():.1e} S_i",
+              flush=True)
+        s.step(1, w.dt)
+    s.sync()                                # raises if the GPU flagged a step
+    err = np.abs(s.positions64()[rows] - z["x20"]).max()
+    print(f"large first20: worst state {worst_x:.2e}, worst force {worst_f:.2e} S_i "
+          f"({stiff} row-steps needed the stiffness term), positions {err:.2e} sigma",
+          flush=True)
+    assert err <= 1e-4, err

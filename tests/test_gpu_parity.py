@@ -444,3 +444,45 @@ def test_set_positions_restart(ld, orc):
         bad = w2.pos.copy()
         bad[3, 1] = np.nan
         s.set_positions(bad)
+
+
+# ---------------------------------------------------------------------------
+# Initial placement sampled by the library (ld_init with pos = NULL)
+# ---------------------------------------------------------------------------
+
+def sampled_system(ld, w):
+    return ld.System(w.type, w.charge, None, w.params, w.radius, w.seed)
+
+
+def test_init_sampler_matches_oracle(ld, orc):
+    """The three-type composition packed to a volume fraction near 0.2 (many
+    rejections): every position equals the oracle's bit for bit."""
+    w = W.config_large(n=2000, seed=23, with_positions=False)
+    R0 = 0.5 * float(np.cbrt(np.sum(np.asarray(w.params.sigma)[w.type] ** 3) / 0.2))
+    w.radius = W.Radius(kind=W.RADIUS_CONST, R0=R0)
+    s = sampled_system(ld, w)
+    xo = orc.sample_ball(w.type, w.params.sigma, R0, w.seed)
+    assert np.array_equal(s.positions64(), xo)
+
+
+def test_init_sampler_full_size(ld, orc):
+    """N = 250000 in the headline droplet (R0 = 300): the first 3000 positions
+    equal the oracle's (each particle depends only on those before it), all
+    lie in the ball, and no pair is closer than sigma_ij."""
+    from scipy.spatial import cKDTree
+    w = W.config_large(with_positions=False)
+    s = sampled_system(ld, w)
+    x = s.positions64()
+    R0 = orc.radius_at(w.radius, 0.0)
+    assert np.all(np.linalg.norm(x, axis=1) <= R0 * (1 + 1e-6))
+    xo = orc.sample_ball(w.type[:3000], w.params.sigma, R0, w.seed)
+    assert np.array_equal(x[:3000], xo)
+    sig = np.asarray(w.params.sigma)[w.type]
+    pairs = cKDTree(x).query_pairs(max(w.params.sigma), output_type="ndarray")
+    d = np.linalg.norm(x[pairs[:, 0]] - x[pairs[:, 1]], axis=1)
+    assert np.all(d >= 0.5 * (sig[pairs[:, 0]] + sig[pairs[:, 1]]))
+    # an impossible packing is refused
+    wd = W.config_small(n=400, seed=2, with_positions=False)
+    wd.radius = W.Radius(kind=W.RADIUS_CONST, R0=2.0)
+    with pytest.raises(RuntimeError):
+        sampled_system(ld, wd)

@@ -663,3 +663,56 @@ def test_msd(oracle_lib):
     end = independent(oracle_lib, p, R, start, 10, 2e-3, seed=5)
     assert oracle_lib.msd(end, start) / (6 * 4.0 * 10 * 2e-3) == pytest.approx(
         1.0, abs=3 * math.sqrt(2 / (3 * n)))
+
+
+# ---------------------------------------------------------------------------
+# Initial placement: uniform in the ball, no overlaps (section 2.1)
+# ---------------------------------------------------------------------------
+
+def test_sample_ball_inside_and_no_overlap(oracle_lib):
+    """Every point lies in the ball (up to FP32 rounding of R0 v), every pair
+    is at least sigma_ij apart (brute force over all pairs, two sizes mixed),
+    and the values are FP32 numbers."""
+    from scipy.spatial.distance import pdist
+    rng = np.random.default_rng(3)
+    n = 1500
+    typ = (rng.random(n) < 0.4).astype(np.int32)
+    sigma = [1.0, 2.0]
+    R0 = 13.0                                    # packing fraction ~0.26: many rejections
+    x = oracle_lib.sample_ball(typ, sigma, R0, seed=7)
+    assert np.all(np.linalg.norm(x, axis=1) <= R0 * (1 + 1e-6))
+    assert np.array_equal(x, x.astype(np.float32).astype(np.float64))
+    s = np.asarray(sigma)[typ]
+    sij = 0.5 * (s[:, None] + s[None, :])
+    iu = np.triu_indices(n, 1)
+    assert np.all(pdist(x) >= sij[iu] * (1 - 1e-12))
+    # the closest pairs sit near contact: the rejection step is doing the work
+    assert (pdist(x) / sij[iu]).min() < 1.05
+
+
+def test_sample_ball_uniform_in_volume(oracle_lib):
+    """At low density the radii follow P(r < a) = (a / R0)^3 and the
+    directions are isotropic (KS and mean tests)."""
+    from scipy import stats
+    n = 4000
+    typ = np.zeros(n, np.int32)
+    R0 = 400.0
+    x = oracle_lib.sample_ball(typ, [1.0], R0, seed=11)
+    r = np.linalg.norm(x, axis=1)
+    assert stats.kstest((r / R0) ** 3, "uniform").pvalue > 1e-3
+    u = x / r[:, None]
+    assert np.all(np.abs(u.mean(axis=0)) < 4.0 / np.sqrt(3 * n))
+    assert stats.kstest(u[:, 2], "uniform", args=(-1, 2)).pvalue > 1e-3
+
+
+def test_sample_ball_prefix_and_seed(oracle_lib):
+    """Particle i depends only on the particles before it: a shorter sample
+    is a prefix of a longer one; another seed gives other positions."""
+    typ = np.tile(np.array([0, 1, 1], np.int32), 300)
+    a = oracle_lib.sample_ball(typ, [1.0, 1.5], 12.0, seed=5)
+    b = oracle_lib.sample_ball(typ[:400], [1.0, 1.5], 12.0, seed=5)
+    assert np.array_equal(a[:400], b)
+    c = oracle_lib.sample_ball(typ[:400], [1.0, 1.5], 12.0, seed=6)
+    assert not np.any(np.all(b == c, axis=1))
+    with pytest.raises(RuntimeError):
+        oracle_lib.sample_ball(np.zeros(200, np.int32), [1.0], 1.5, seed=1, max_tries=200)
