@@ -167,6 +167,28 @@ const char* ld_last_error(void);
  * Waits for the stream.  Errors: LD_EINVAL, LD_EHIP. */
 ld_status ld_forces(ld_ctx* ctx, double* F_pair, double* F_ext, double* S, double* U);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the pair forces of
+ * ld_forces for one set of particles, with no context and no allocation.
+ * The pair kernels' scratch (packed positions and charges, low words,
+ * types, group boxes, the FP64 partial sums of 4 j splits) lives in a static
+ * device array of 8.3 MiB per GPU, held from the first call on that GPU
+ * until the process ends.  Same arithmetic as ld_forces (FP32 Coulomb
+ * terms, FP64 Lennard-Jones terms and totals, no spatial re-sort).
+ *   n       2 .. 65536 particles (larger n: LD_EINVAL)
+ *   type    [n] int32, device; values outside [0, p->n_types) are clamped
+ *   charge  [n] FP64 charges (units of e), device
+ *   pos     [n*3] FP32 positions, device
+ *   p       parameters (host; LJ, l_B and kT are used)
+ *   F_pair  [n*3] FP64 pair forces, device, same order as the inputs
+ *   stream  hipStream_t to enqueue on (NULL: the null stream)
+ * Asynchronous: nothing waits for the stream.  Every call on one GPU uses
+ * that GPU's one scratch array: calls that overlap on a GPU (other streams,
+ * other threads) race, so order them on one stream.  Errors: LD_EINVAL
+ * (n, a pointer that is not device memory, parameters), LD_EHIP. */
+ld_status ld_forces_noalloc(int64_t n, const int32_t* type, const double* charge,
+                            const float* pos, const ld_params* p, double* F_pair, void* stream);
+
 /* State and FP64 diagnostics after a call of ld_step (section 2.2; the
  * energies and momentum balance of the overdamped model). */
 typedef struct {

@@ -114,7 +114,7 @@ SYMBOLS = [
     "ld_paper_enable", "ld_paper_disable", "ld_paper_forces", "ld_paper_get_velocities",
     "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count", "ld_record_open",
     "ld_record_close", "ld_cbar_type", "ld_surface_fractal", "ld_ff_save", "ld_ff_load",
-    "ld_msd", "ld_msd_reset", "ld_ens_get_tuning", "ld_ens_set_unroll",
+    "ld_msd", "ld_msd_reset", "ld_forces_noalloc", "ld_ens_get_tuning", "ld_ens_set_unroll",
     "ld_ens_autotune",
 ]
 
@@ -137,6 +137,7 @@ def lib():
         L.ld_forces.argtypes = [vp, dp, dp, dp, dp]
         L.ld_step.argtypes = [vp, C.c_double, C.c_int64, C.POINTER(ld_radius),
                               C.POINTER(C.c_uint64), C.POINTER(ld_diag)]
+        L.ld_forces_noalloc.argtypes = [C.c_int64, vp, vp, vp, C.POINTER(ld_params), vp, vp]
         L.ld_msd.argtypes = [vp, dp]
         L.ld_msd_reset.argtypes = [vp]
         L.ld_sync.argtypes = [vp]
