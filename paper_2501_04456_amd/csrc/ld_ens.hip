@@ -53,6 +53,7 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
     const Box* __restrict__ box, const int* __restrict__ tbase, double* __restrict__ F,
     int total) {
     __shared__ float4 sp[kWaves][kGroup];
+    __shared__ float4 sl[kWaves][kGroup];
     const int w = threadIdx.x / kGroup;
     const int lane = threadIdx.x % kGroup;
     for (;;) {
@@ -90,10 +91,10 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
             wave_sync();
             const int j = jt + lane;
             sp[w][lane] = j < nd ? pos[o + j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+            if (near) sl[w][lane] = j < nd ? lo[o + j] : make_float4(0.f, 0.f, 0.f, 0.f);
             wave_sync();
             if (near)
-                pair::group_near<COMP, false>(sp[w], jt, i, pi, lo + o + jt,
-                                              min(kGroup, nd - jt), li, a);
+                (void)pair::group_near<COMP, false>(sp[w], sl[w], jt, i, pi, li, cull2, a);
             else
                 pair::group_far<COMP, UNROLL>(sp[w], pi, a);
         }
@@ -113,9 +114,10 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
 }
 
 // Lennard-Jones forces of every tile of every droplet, in FP64, added into F
-// after k_ens_pair (one wavefront per 64-slot tile; j groups of the same
-// droplet whose boxes come within the largest LJ range, or all of them when
-// boxes are off).
+// after k_ens_pair.  One workgroup per 64-slot tile: its four wavefronts
+// test the same boxes of the droplet's tiles (all of them when boxes are
+// off) and share the near ones round-robin; each stages its j tiles in its
+// own LDS slice, and the partial sums are added in wavefront order.
 __global__ __launch_bounds__(kEnsBlock) void k_ens_lj(
     const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
     const int* __restrict__ off, const int2* __restrict__ tiles, int ntiles,
@@ -124,10 +126,10 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_lj(
     __shared__ float4 sh[kWaves][kGroup];
     __shared__ float4 sl[kWaves][kGroup];
     __shared__ int st[kWaves][kGroup];
+    __shared__ double red[kWaves][3][kGroup];
     const int w = threadIdx.x / kGroup;
     const int lane = threadIdx.x % kGroup;
-    const int t = blockIdx.x * kWaves + w;
-    if (t >= ntiles) return;                // whole wavefronts only; no block barrier below
+    const int t = blockIdx.x;
     const int2 tl = tiles[t];
     const int d = tl.x;
     const int o = off[d];
@@ -147,6 +149,7 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_lj(
     const int t0 = tbase[d];
     double L[3] = {0.0, 0.0, 0.0};
     double S = 0.0, U = 0.0;
+    int rank = 0;
     for (int c0 = 0; c0 < ng; c0 += kGroup) {
         bool nb = c0 + lane < ng;
         if (nb && box) nb = pair::box_dist2(bi, box[t0 + c0 + lane]) < cull2;
@@ -154,13 +157,14 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_lj(
         while (m) {
             const int g = c0 + __builtin_ctzll(m);
             m &= m - 1ull;
+            if ((rank++ & (kWaves - 1)) != w) continue;
             const int j = g * kGroup + lane;
             wave_sync();
             sh[w][lane] = j < nd ? pos[o + j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
             sl[w][lane] = j < nd ? lo[o + j] : make_float4(0.f, 0.f, 0.f, 0.f);
             st[w][lane] = j < nd ? typ[o + j] : 0;
             wave_sync();
-#pragma unroll 1
+#pragma unroll 2
             for (int k = 0; k < kGroup; ++k) {
                 const float4 pj = sh[w][k];
                 const float4 lj = sl[w][k];
@@ -173,12 +177,18 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_lj(
             }
         }
     }
-    if (live) {
-        const size_t s = (size_t)(o + i);
-        F[s] -= L[0];
-        F[(size_t)total + s] -= L[1];
-        F[2 * (size_t)total + s] -= L[2];
-    }
+    red[w][0][lane] = L[0];
+    red[w][1][lane] = L[1];
+    red[w][2][lane] = L[2];
+    __syncthreads();
+    if (w != 0 || !live) return;
+    double Ls[3] = {0.0, 0.0, 0.0};
+    for (int v = 0; v < kWaves; ++v)
+        for (int c = 0; c < 3; ++c) Ls[c] += red[v][c][lane];
+    const size_t s = (size_t)(o + i);
+    F[s] -= Ls[0];
+    F[(size_t)total + s] -= Ls[1];
+    F[2 * (size_t)total + s] -= Ls[2];
 }
 
 __global__ __launch_bounds__(256) void k_ens_update(float4* pos, float4* lo,
@@ -418,7 +428,7 @@ ld_status enqueue_pair(ld_ens* e, hipStream_t s) {
     else
         launch_ens_pair<1>(e, s);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_ens_lj, dim3((e->ntiles + kWaves - 1) / kWaves), dim3(kEnsBlock), 0, s,
+    hipLaunchKernelGGL(k_ens_lj, dim3(e->ntiles), dim3(kEnsBlock), 0, s,
                        e->pos, e->lo, e->typ, e->off, e->tiles, e->ntiles, e->tabs,
                        e->cull ? e->box : nullptr, e->tbase, e->F, e->total);
     HIP_TRY(hipGetLastError());

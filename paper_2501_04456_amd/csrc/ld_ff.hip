@@ -126,6 +126,8 @@ struct FarField {
           *bA2 = nullptr, *bY = nullptr, *bdY = nullptr, *bd2 = nullptr, *bd1 = nullptr;
     int* bidx = nullptr;
     double* loss_part = nullptr;
+    float* gws = nullptr;              // split-K workspace of the weight gradients
+    size_t gws_floats = 0;
 };
 
 }  // namespace ld
@@ -1653,7 +1655,7 @@ void ff_free_bufs(FarField* f) {
                  f->pcount, f->pocc, f->pcell2occ, f->npocc, f->Xc, f->Ac, f->h1, f->h2, f->y, f->W, f->w1bf, f->grad, f->adam_m,
                  f->adam_v, f->rel, f->Efar, f->snap_mom, f->s_snap, f->s_cell, f->s_off,
                  f->s_tgt, f->bX, f->bT, f->bZ1, f->bA1, f->bZ2, f->bA2, f->bY, f->bdY, f->bd2,
-                 f->bd1, f->bidx, f->loss_part};
+                 f->bd1, f->bidx, f->loss_part, f->gws};
     for (void* p : b)
         if (p) (void)hipFree(p);
     conv_free(&f->conv);
@@ -1787,8 +1789,10 @@ ld_status ff_far_exact(ld_ctx* c, hipStream_t s) {
 
 ld_status gemm(hipStream_t s, const float* A, int lda, int tA, const float* B, int ldb, int tB,
                float* C, int ldc, int M, int N, int K, const float* bias, int act, float* Z,
-               int ldz, int acc, const int* M_dev) {
+               int ldz, int acc, const int* M_dev, float* work = nullptr,
+               size_t work_floats = 0) {
     ld::GemmArgs g{};
+    g.work = work; g.work_floats = work_floats;
     g.A = A; g.lda = lda; g.transA = tA;
     g.B = B; g.ldb = ldb; g.transB = tB;
     g.C = C; g.ldc = ldc;
@@ -1865,6 +1869,7 @@ ld_status ff_direct_total(ld_ctx* c, hipStream_t s, double* dst) {
     L.pos = c->pos; L.lo = c->lo; L.typ = c->typ; L.box = c->box; L.n = (int)c->n;
     L.block = c->tune.block; L.j_split = c->tune.j_split; L.comp = c->tune.comp;
     L.cull = c->tune.cull; L.Fpart = c->Fpart;
+    L.nearbits = c->nearbits; L.nb_words = c->nb_words;
     HIP_TRY(ld::launch_pair(L, c->tab, s));
     KLAUNCH(k_sum_parts, dim3((3 * (int)c->n + kB - 1) / kB), dim3(kB), s, c->Fpart,
             c->tune.j_split, (int)c->n, dst);
@@ -1918,8 +1923,12 @@ ld_status ensure_batch(FarField* f, int B_) {
         if (*b) { (void)hipFree(*b); *b = nullptr; }
     if (f->bidx) { (void)hipFree(f->bidx); f->bidx = nullptr; }
     if (f->loss_part) { (void)hipFree(f->loss_part); f->loss_part = nullptr; }
+    if (f->gws) { (void)hipFree(f->gws); f->gws = nullptr; }
     const size_t H = f->H;
-    bool ok = dalloc(&f->bX, (size_t)B_ * f->Kp) && dalloc(&f->bT, (size_t)B_ * 3) &&
+    // split-K pieces of the largest weight gradient (Kp x H), at most 64
+    f->gws_floats = (size_t)64 * f->Kp * H;
+    bool ok = dalloc(&f->gws, f->gws_floats) &&
+              dalloc(&f->bX, (size_t)B_ * f->Kp) && dalloc(&f->bT, (size_t)B_ * 3) &&
               dalloc(&f->bZ1, B_ * H) && dalloc(&f->bA1, B_ * H) && dalloc(&f->bZ2, B_ * H) &&
               dalloc(&f->bA2, B_ * H) && dalloc(&f->bY, (size_t)B_ * f->Op) &&
               dalloc(&f->bdY, (size_t)B_ * f->Op) && dalloc(&f->bd2, B_ * H) &&
@@ -1948,21 +1957,21 @@ ld_status fwd_bwd(FarField* f, int B_, hipStream_t s, double* loss) {
     HIP_TRY(ld::launch_mse(f->bY, Op, f->bT, B_, 3, f->bdY, f->loss_part, &nparts, s));
     // layer 3
     TRY(gemm(s, f->bA2, H, 1, f->bdY, Op, 0, gW + f->offW3, Op, H, Op, B_, nullptr, 0, nullptr, 0,
-             0, nullptr));
+             0, nullptr, f->gws, f->gws_floats));
     HIP_TRY(ld::launch_colsum(f->bdY, B_, Op, gW + f->offb3, s));
     TRY(gemm(s, f->bdY, Op, 0, W + f->offW3, Op, 1, f->bd2, H, B_, H, Op, nullptr, 0, nullptr, 0,
              0, nullptr));
     HIP_TRY(ld::launch_silu_bwd(f->bZ2, f->bd2, B_, H, nullptr, s));
     // layer 2
     TRY(gemm(s, f->bA1, H, 1, f->bd2, H, 0, gW + f->offW2, H, H, H, B_, nullptr, 0, nullptr, 0, 0,
-             nullptr));
+             nullptr, f->gws, f->gws_floats));
     HIP_TRY(ld::launch_colsum(f->bd2, B_, H, gW + f->offb2, s));
     TRY(gemm(s, f->bd2, H, 0, W + f->offW2, H, 1, f->bd1, H, B_, H, H, nullptr, 0, nullptr, 0, 0,
              nullptr));
     HIP_TRY(ld::launch_silu_bwd(f->bZ1, f->bd1, B_, H, nullptr, s));
     // layer 1
     TRY(gemm(s, f->bX, Kp, 1, f->bd1, H, 0, gW + f->offW1, H, Kp, H, B_, nullptr, 0, nullptr, 0, 0,
-             nullptr));
+             nullptr, f->gws, f->gws_floats));
     HIP_TRY(ld::launch_colsum(f->bd1, B_, H, gW + f->offb1, s));
 #undef TRY
     if (loss) {

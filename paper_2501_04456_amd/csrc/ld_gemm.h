@@ -25,6 +25,12 @@ struct GemmArgs {
     int act;          // 0 none, 1 SiLU
     int accumulate;   // 1: C += result
     const int* M_dev;
+    // Optional FP32 workspace for split-K: when C has few 64 x 64 tiles and
+    // K is long (the weight gradients, K = batch), K is cut into pieces
+    // computed by separate workgroups into work[piece][M][N] and summed in
+    // piece order by a second kernel.  Unused when NULL or too small.
+    float* work;
+    size_t work_floats;
 };
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);

@@ -13,6 +13,8 @@
 //
 // MFMA 16x16x32 operand layout (wave64): lane l supplies A[l % 16][8 (l/16)
 // + 0..7] and B[8 (l/16) + 0..7][l % 16]; it receives C[4 (l/16) + 0..3][l % 16].
+#include <algorithm>
+
 #include "ld_internal.h"
 #include "ld_gemm.h"
 
@@ -35,16 +37,21 @@ __device__ __forceinline__ float silu(float z) {
     return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
 }
 
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+// part == nullptr: the whole K range and the epilogue (bias, pre-activation,
+// SiLU, accumulate).  Otherwise piece blockIdx.z of the K range, [kb, ke),
+// raw sums into part[blockIdx.z][M][N].
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int kpiece, float* part) {
     __shared__ __attribute__((aligned(16))) __bf16 As[BM][BK + PAD];
     __shared__ __attribute__((aligned(16))) __bf16 Bt[BN][BK + PAD];
     const int M = g.M_dev ? min(g.M, *g.M_dev) : g.M;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     if (m0 >= M) return;
+    const int kb = part ? (int)blockIdx.z * kpiece : 0;
+    const int ke = part ? min(g.K, kb + kpiece) : g.K;
     const int t = threadIdx.x, w = t / 64, l = t % 64;
     f32x4 acc[4];
     for (int j = 0; j < 4; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
+    for (int k0 = kb; k0 < ke; k0 += BK) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < (BM * BK) / 256; ++r) {
@@ -54,7 +61,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             else { row = e / BK; kk = e % BK; }
             const int gr = m0 + row, gk = k0 + kk;
             float v = 0.f;
-            if (gr < M && gk < g.K)
+            if (gr < M && gk < ke)
                 v = g.transA ? g.A[(size_t)gk * g.lda + gr] : g.A[(size_t)gr * g.lda + gk];
             As[row][kk] = to_bf16(v);
         }
@@ -66,7 +73,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             else { col = e % BN; kk = e / BN; }
             const int gc = n0 + col, gk = k0 + kk;
             float v = 0.f;
-            if (gc < g.N && gk < g.K)
+            if (gc < g.N && gk < ke)
                 v = g.transB ? g.B[(size_t)gc * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gc];
             Bt[col][kk] = to_bf16(v);
         }
@@ -78,6 +85,19 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bt[j * 16 + l % 16][kk]);
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
         }
+    }
+    if (part) {
+        float* P = part + (size_t)blockIdx.z * (size_t)g.M * g.N;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + j * 16 + l % 16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + w * 16 + 4 * (l / 16) + r;
+                if (row < M && col < g.N) P[(size_t)row * g.N + col] = acc[j][r];
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -94,6 +114,22 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             *c = g.accumulate ? *c + v : v;
         }
     }
+}
+
+// Split-K epilogue: the pieces summed in order, then as k_gemm's epilogue.
+__global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g, int pieces,
+                                                     const float* __restrict__ part) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t mn = (size_t)g.M * g.N;
+    if (e >= mn) return;
+    const int row = (int)(e / g.N), col = (int)(e % g.N);
+    float v = 0.f;
+    for (int z = 0; z < pieces; ++z) v += part[(size_t)z * mn + e];
+    if (g.bias) v += g.bias[col];
+    if (g.Z) g.Z[(size_t)row * g.ldz + col] = v;
+    if (g.act == 1) v = silu(v);
+    float* c = g.C + (size_t)row * g.ldc + col;
+    *c = g.accumulate ? *c + v : v;
 }
 
 // dZ = dA * silu'(Z), elementwise over rows x cols (row strides ld).
@@ -168,7 +204,26 @@ __global__ __launch_bounds__(256) void k_adam(float* w, const float* __restrict_
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
     dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+    const int tiles = (int)(grid.x * grid.y);
+    // split K when C has too few tiles to fill the chip and K is long: pieces
+    // of at least 4 BK steps, about 1024 workgroups in all
+    int pieces = 1;
+    if (g.work && !g.M_dev && tiles < 256 && g.K >= 8 * BK) {
+        pieces = std::min(std::max(1, 1024 / tiles), g.K / (4 * BK));
+        const size_t mn = (size_t)g.M * g.N;
+        pieces = (int)std::min<size_t>((size_t)pieces, g.work_floats / std::max<size_t>(mn, 1));
+    }
+    if (pieces <= 1) {
+        hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g, 0, (float*)nullptr);
+        return hipGetLastError();
+    }
+    const int kpiece = ((g.K + pieces - 1) / pieces + BK - 1) / BK * BK;
+    pieces = (g.K + kpiece - 1) / kpiece;
+    grid.z = pieces;
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g, kpiece, g.work);
+    const size_t mn = (size_t)g.M * g.N;
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g,
+                       pieces, (const float*)g.work);
     return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@ namespace ld {
 
 constexpr int kMaxTypes = LD_MAX_TYPES;
 constexpr int kGroup = 64;            // one wavefront: the unit of tile culling
+// Largest n with a near-group bitmap (ceil(n/64)^2 bits: 32 MiB at 2^20)
+constexpr int64_t kNearBitsMaxN = 1 << 20;
 
 // Far-away, uncharged filler for the padded tail of a j tile: its Coulomb
 // weight is exactly zero and it never enters the LJ range.
@@ -107,6 +109,11 @@ struct PairLaunch {
     double* Fpart;                       // [j_split][3][n]
     double* S;                           // [n] or nullptr (diagnostic mode)
     double* U;                           // [2][n] or nullptr (diagnostic mode)
+    // Near-group bitmap [ceil(n/64)][nb_words] (or nullptr): the Coulomb
+    // kernel sets bit (gi, gj) for every group pair it takes as near, the
+    // Lennard-Jones kernel reads and clears row gi (all zero between launches).
+    unsigned* nearbits;
+    int nb_words;
 };
 // The Coulomb kernel (k_pair) and then the FP64 Lennard-Jones kernel (k_lj);
 // after_coulomb, if given, is recorded between the two.
@@ -214,8 +221,22 @@ struct SortBuffers {
     unsigned* hist;                      // [256 * (radix_tiles(n) + 1)] radix digit counts
                                          // and the 256 digit totals (or null)
 };
+// Hilbert-curve order of the slots over the particles' bounding box clipped
+// to [-clip, clip] per axis (INFINITY: no clip).
 hipError_t launch_sort(float4* pos, float4* lo, int* typ, int* oid, int n,
-                       const SortBuffers& B, hipStream_t s);
+                       const SortBuffers& B, hipStream_t s, float clip);
+
+// Largest radius a schedule reaches (INFINITY if it grows without bound).
+inline double schedule_max_radius(const ld_radius& R) {
+    if (R.kind == LD_R_LINEAR) return R.R0 > R.R1 ? R.R0 : R.R1;
+    if (R.kind == LD_R_SQUARE_LAW) return R.a >= 0.0 ? R.R0 : INFINITY;
+    if (R.kind == LD_R_TABLE) {
+        double m = 0.0;
+        for (int k = 0; k < R.n_knots; ++k) m = R.tab_R[k] > m ? R.tab_R[k] : m;
+        return m;
+    }
+    return R.R0;
+}
 
 // Sort B.keys (filled by the caller: high word = sort key, low word = slot;
 // padding keys ~0) and permute the slot arrays accordingly.
@@ -337,6 +358,8 @@ struct ld_ctx {
     int* typ2 = nullptr;
     int* oid2 = nullptr;
     ld::Box* box = nullptr;              // [ceil(n/64)] group boxes
+    unsigned* nearbits = nullptr;        // near-group bitmap (n <= kNearBitsMaxN), zero at rest
+    int nb_words = 0;
     double* Fpart = nullptr;             // [j_split_cap][3][n]
     int j_split_cap = 0;
     double* S_slot = nullptr;            // [n]

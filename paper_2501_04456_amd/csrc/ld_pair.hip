@@ -15,12 +15,13 @@
 // the differences; a far pair of groups one of which is uncharged is
 // skipped (no force at all).
 //
-// k_lj: the Lennard-Jones sum, which is short-ranged (lj_cut sigma_ij):
-// each wavefront takes one 64-slot i group, finds the j groups whose boxes
-// come within the largest LJ range (a ballot over 64 boxes at a time),
-// stages each such group in LDS and evaluates the pairs inside the cutoff
-// in FP64.  It adds its result into the first force partial of each slot
-// after k_pair has written it (same stream, one writer per slot).
+// k_lj: the Lennard-Jones sum, which is short-ranged (lj_cut sigma_ij): one
+// workgroup per 64-slot i group visits the j groups that k_pair found to
+// hold a pair within the largest LJ range (a bitmap k_pair fills and k_lj
+// clears; without it, the groups whose boxes come that close), stages each
+// in LDS and evaluates the pairs inside the cutoff in FP64.  It adds its
+// result into the first force partial of each slot after k_pair has
+// written it (same stream, one writer per slot).
 //
 // Precision.  The Coulomb pair terms are FP32.  Each lane sums KB = 32 of
 // them in an FP32 block accumulator and then moves the block into FP64
@@ -35,15 +36,23 @@ namespace {
 
 using namespace pair;
 
+// Wavefronts per SIMD the register allocation must allow (block 64 keeps a
+// whole j tile in registers whatever the bound; it is left unconstrained).
+#ifndef LD_PAIR_MIN_WAVES
+#define LD_PAIR_MIN_WAVES 6
+#endif
+
 template <int BLOCK, int COMP, bool DIAG, bool CULL>
-__global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : 8) void k_pair(const float4* __restrict__ pos,
+__global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_pair(const float4* __restrict__ pos,
                                                 const float4* __restrict__ lo,
                                                 const Box* __restrict__ box, int n,
                                                 int j_per_split, float rc2max,
                                                 double* __restrict__ Fpart,
                                                 double* __restrict__ S_out,
-                                                double* __restrict__ U_out) {
+                                                double* __restrict__ U_out,
+                                                unsigned* __restrict__ nearbits, int nb_words) {
     __shared__ float4 sp[BLOCK];
+    __shared__ float4 sl[BLOCK];             // low words (read by the near loop only)
 
     const int tid = threadIdx.x;
     const int i = blockIdx.x * BLOCK + tid;
@@ -74,6 +83,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : 8) void k_pair(const float
         __syncthreads();
         const int j = jt + tid;
         sp[tid] = j < j1 ? pos[j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+        sl[tid] = j < j1 ? lo[j] : make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
 #pragma unroll 1
         for (int g = 0; g < BLOCK / kGroup; ++g) {
@@ -92,8 +102,14 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : 8) void k_pair(const float
             }
             if constexpr (DIAG) near = true;
             if (__builtin_amdgcn_readfirstlane((int)near)) {
-                group_near<COMP, DIAG>(sp + g * kGroup, jg, i, pi, lo + jg,
-                                       max(0, min(kGroup, j1 - jg)), li, a);
+                const bool lj = group_near<COMP, DIAG>(sp + g * kGroup, sl + g * kGroup, jg, i,
+                                                       pi, li, cull2, a);
+                // record the pair of groups if it holds a Lennard-Jones
+                // candidate, for the Lennard-Jones kernel
+                if (nearbits && __ballot(lj && live) && (tid & (kGroup - 1)) == 0) {
+                    const int gi = (blockIdx.x * BLOCK + tid) / kGroup, gj = jg / kGroup;
+                    atomicOr(&nearbits[(size_t)gi * nb_words + (gj >> 5)], 1u << (gj & 31));
+                }
             } else {
                 group_far<COMP>(sp + g * kGroup, pi, a);
             }
@@ -123,7 +139,12 @@ constexpr int kLjBlock = 256;
 constexpr int kLjWaves = kLjBlock / kGroup;
 
 // Lennard-Jones forces of every slot, added into partial 0 (and, with DIAG,
-// into S and the LJ energy row of U).  Without boxes every group is visited.
+// into S and the LJ energy row of U).  One workgroup per 64-slot i group:
+// its four wavefronts test the same 64 boxes at a time and share the j
+// groups that come within the largest LJ range round-robin (the r-th near
+// group goes to wavefront r mod 4); each wavefront stages its j groups in
+// its own LDS slice, and the four partial sums are added in wavefront order
+// at the end.  Without boxes every group is visited.
 template <bool DIAG>
 __global__ __launch_bounds__(kLjBlock) void k_lj(const float4* __restrict__ pos,
                                                   const float4* __restrict__ lo,
@@ -131,11 +152,14 @@ __global__ __launch_bounds__(kLjBlock) void k_lj(const float4* __restrict__ pos,
                                                   const Box* __restrict__ box, int n,
                                                   double* __restrict__ F,
                                                   double* __restrict__ S_out,
-                                                  double* __restrict__ U_out, PairTable tab) {
+                                                  double* __restrict__ U_out, PairTable tab,
+                                                  unsigned* __restrict__ nearbits,
+                                                  int nb_words) {
     __shared__ float4 sh[kLjWaves][kGroup];
     __shared__ float4 sl[kLjWaves][kGroup];
     __shared__ int st[kLjWaves][kGroup];
     __shared__ double t64[4 * kMaxTypes * kMaxTypes];
+    __shared__ double red[kLjWaves][5][kGroup];
     for (int k = threadIdx.x; k < kMaxTypes * kMaxTypes; k += kLjBlock) {
         t64[k] = tab.sig2d[k];
         t64[kMaxTypes * kMaxTypes + k] = tab.e24d[k];
@@ -146,8 +170,7 @@ __global__ __launch_bounds__(kLjBlock) void k_lj(const float4* __restrict__ pos,
     const int w = threadIdx.x / kGroup;
     const int lane = threadIdx.x % kGroup;
     const int ngroups = (n + kGroup - 1) / kGroup;
-    const int gi = blockIdx.x * kLjWaves + w;
-    if (gi >= ngroups) return;              // whole wavefronts only; no block barrier below
+    const int gi = blockIdx.x;
     const int i = gi * kGroup + lane;
     const bool live = i < n;
     const float4 pi = live ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -156,20 +179,27 @@ __global__ __launch_bounds__(kLjBlock) void k_lj(const float4* __restrict__ pos,
     const int T = tab.T;
     Box bi;
     if (box) bi = box[gi];
+    // box test and FP32 screen (the (hi, lo) difference: relative error
+    // ~1e-7 in r^2) with a margin; the cutoff itself is decided in FP64
     const float cull2 = tab.rc2max * 1.0001f;
-    // FP32 screen on the (hi, lo) difference: relative error ~1e-7 in r^2
-    const float screen2 = tab.rc2max * 1.0001f;
     double L[3] = {0.0, 0.0, 0.0};
     double S = 0.0, U = 0.0;
+    int rank = 0;                                // near groups seen so far (all wavefronts)
+    const unsigned* row = nearbits ? nearbits + (size_t)gi * nb_words : nullptr;
     for (int c0 = 0; c0 < ngroups; c0 += kGroup) {
         const int gj = c0 + lane;
         bool nb = gj < ngroups;
-        if (nb && box) nb = box_dist2(bi, box[gj]) < cull2;
+        if (row)                                 // the pairs the Coulomb kernel found near
+            nb = nb && ((row[gj >> 5] >> (gj & 31)) & 1u);
+        else if (nb && box)
+            nb = box_dist2(bi, box[gj]) < cull2;
         unsigned long long m = __ballot(nb);
         while (m) {
             const int g = c0 + __builtin_ctzll(m);
             m &= m - 1ull;
+            if ((rank++ & (kLjWaves - 1)) != w) continue;
             const int j = g * kGroup + lane;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             sh[w][lane] = j < n ? pos[j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
             sl[w][lane] = j < n ? lo[j] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -177,7 +207,7 @@ __global__ __launch_bounds__(kLjBlock) void k_lj(const float4* __restrict__ pos,
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll 1
+#pragma unroll 2
             for (int k = 0; k < kGroup; ++k) {
                 const float4 pj = sh[w][k];
                 const float4 lj = sl[w][k];
@@ -185,20 +215,37 @@ __global__ __launch_bounds__(kLjBlock) void k_lj(const float4* __restrict__ pos,
                 const float dy = (pj.y - pi.y) + (lj.y - li.y);
                 const float dz = (pj.z - pi.z) + (lj.z - li.z);
                 const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                if (r2 < screen2 && live && g * kGroup + k != i)
+                if (r2 < cull2 && live && g * kGroup + k != i)
                     lj_pair64<DIAG>(pj, lj, pi, li, t64, ti * T + st[w][k], L, S, U);
             }
         }
     }
-    if (live) {
-        // F_i += -sum_j g_ij (x_j - x_i)
-        F[i] -= L[0];
-        F[(size_t)n + i] -= L[1];
-        F[2 * (size_t)n + i] -= L[2];
+    red[w][0][lane] = L[0];
+    red[w][1][lane] = L[1];
+    red[w][2][lane] = L[2];
+    if constexpr (DIAG) {
+        red[w][3][lane] = S;
+        red[w][4][lane] = U;
+    }
+    __syncthreads();
+    if (row)                                     // leave the bitmap all zero
+        for (int k = threadIdx.x; k < nb_words; k += kLjBlock) nearbits[(size_t)gi * nb_words + k] = 0u;
+    if (w != 0 || !live) return;
+    double Ls[3] = {0.0, 0.0, 0.0}, Ss = 0.0, Us = 0.0;
+    for (int v = 0; v < kLjWaves; ++v) {
+        for (int c = 0; c < 3; ++c) Ls[c] += red[v][c][lane];
         if constexpr (DIAG) {
-            S_out[i] += S;
-            U_out[i] += U;
+            Ss += red[v][3][lane];
+            Us += red[v][4][lane];
         }
+    }
+    // F_i += -sum_j g_ij (x_j - x_i)
+    F[i] -= Ls[0];
+    F[(size_t)n + i] -= Ls[1];
+    F[2 * (size_t)n + i] -= Ls[2];
+    if constexpr (DIAG) {
+        S_out[i] += Ss;
+        U_out[i] += Us;
     }
 }
 
@@ -208,7 +255,8 @@ hipError_t launch_t(const PairLaunch& L, const PairTable& tab, hipStream_t s) {
     const int per = (tiles + L.j_split - 1) / L.j_split;
     dim3 grid(tiles, L.j_split);
     hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL>), grid, dim3(BLOCK), 0, s, L.pos, L.lo,
-                       L.box, L.n, per * BLOCK, tab.rc2max, L.Fpart, L.S, L.U);
+                       L.box, L.n, per * BLOCK, tab.rc2max, L.Fpart, L.S, L.U, L.nearbits,
+                       L.nb_words);
     return hipGetLastError();
 }
 
@@ -242,14 +290,14 @@ hipError_t launch_pair(const PairLaunch& L, const PairTable& tab, hipStream_t s,
     if (e != hipSuccess) return e;
     if (after_coulomb && (e = hipEventRecord(after_coulomb, s)) != hipSuccess) return e;
     const int ngroups = (L.n + kGroup - 1) / kGroup;
-    const dim3 grid((ngroups + kLjWaves - 1) / kLjWaves);
+    const dim3 grid(ngroups);
     const Box* box = L.box;          // boxes are kept current by sort and update
     if (L.S)
         hipLaunchKernelGGL(k_lj<true>, grid, dim3(kLjBlock), 0, s, L.pos, L.lo, L.typ, box, L.n,
-                           L.Fpart, L.S, L.U, tab);
+                           L.Fpart, L.S, L.U, tab, L.nearbits, L.nb_words);
     else
         hipLaunchKernelGGL(k_lj<false>, grid, dim3(kLjBlock), 0, s, L.pos, L.lo, L.typ, box,
-                           L.n, L.Fpart, L.S, L.U, tab);
+                           L.n, L.Fpart, L.S, L.U, tab, L.nearbits, L.nb_words);
     return hipGetLastError();
 }
 

@@ -73,22 +73,23 @@ __device__ __forceinline__ void group_far(const float4* __restrict__ sp, const f
 // and adding the difference of their low words gives r_ij to FP32 rounding
 // of r_ij itself, not of |x|.  Near |x| = 300 sigma one ulp of a coordinate
 // is 3e-5 sigma, which at contact distance would move a Coulomb term by
-// ~1e-4 of itself.  The low words are read from global memory (a
-// wavefront-uniform address per j) only for the first `nvalid` slots of the
-// group; the rest are padding far away.  The Lennard-Jones terms of these
-// groups are added by a kernel of their own (k_lj), in FP64.
+// ~1e-4 of itself.  The low words are staged in LDS beside the high words
+// (zero in padding slots).  The Lennard-Jones terms of these groups are
+// added by a kernel of their own (k_lj), in FP64.
+// Returns whether any j of the group lies within sqrt(lj2) of i (i itself
+// excluded): the Lennard-Jones kernel visits only such group pairs.
 template <int COMP, bool DIAG>
-__device__ __forceinline__ void group_near(const float4* __restrict__ sp, int jbase, int i,
-                                           const float4 pi, const float4* __restrict__ lo_j,
-                                           int nvalid, const float4 li, Acc& a) {
+__device__ __forceinline__ bool group_near(const float4* __restrict__ sp,
+                                           const float4* __restrict__ sl, int jbase, int i,
+                                           const float4 pi, const float4 li, float lj2, Acc& a) {
+    bool lj_any = false;
 #pragma unroll
     for (int kb = 0; kb < kGroup; kb += KB) {
         float bx = 0.f, by = 0.f, bz = 0.f;   // Coulomb, FP32 block
 #pragma unroll 4
         for (int k = 0; k < KB; ++k) {
             const float4 pj = sp[kb + k];
-            float4 lj = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (kb + k < nvalid) lj = lo_j[kb + k];
+            const float4 lj = sl[kb + k];
             const float dx = (pj.x - pi.x) + (lj.x - li.x);
             const float dy = (pj.y - pi.y) + (lj.y - li.y);
             const float dz = (pj.z - pi.z) + (lj.z - li.z);
@@ -96,6 +97,7 @@ __device__ __forceinline__ void group_near(const float4* __restrict__ sp, int jb
             const float ri = __builtin_amdgcn_rsqf(r2);
             const bool self = jbase + kb + k == i;
             const float w = self ? 0.f : (pj.w * ri) * (ri * ri);
+            lj_any |= r2 < lj2 && !self;
             if constexpr (DIAG) {
                 if (!self) {
                     const float qq = pi.w * pj.w;
@@ -109,6 +111,7 @@ __device__ __forceinline__ void group_near(const float4* __restrict__ sp, int jb
         }
         flush<COMP>(a, bx, by, bz);
     }
+    return lj_any;
 }
 
 // One Lennard-Jones pair (section 2.1: truncated at lj_cut sigma_ij, not

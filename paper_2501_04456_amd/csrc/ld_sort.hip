@@ -85,9 +85,13 @@ __global__ __launch_bounds__(256) void k_bounds_part(const float4* __restrict__ 
 }
 
 
+// The curve runs over the particles' bounding box clipped to [-clip, clip]
+// per axis (particles outside take the edge cells), so a few stray
+// particles far outside the droplet cannot coarsen the order of the rest.
 __global__ __launch_bounds__(256) void k_curve_keys(const float4* __restrict__ pos, int n,
                                                     int n_pow2, const float* __restrict__ part,
-                                                    int nparts, unsigned long long* keys) {
+                                                    int nparts, float clip,
+                                                    unsigned long long* keys) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= n_pow2) return;
     if (s >= n) {
@@ -100,6 +104,10 @@ __global__ __launch_bounds__(256) void k_curve_keys(const float4* __restrict__ p
             lo[c] = fminf(lo[c], part[b * 6 + c]);
             hi[c] = fmaxf(hi[c], part[b * 6 + 3 + c]);
         }
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = fminf(fmaxf(lo[c], -clip), clip);
+        hi[c] = fmaxf(fminf(hi[c], clip), -clip);
+    }
     const float ext = fmaxf(fmaxf(hi[0] - lo[0], hi[1] - lo[1]), fmaxf(hi[2] - lo[2], 1e-30f));
     const float scale = 1023.0f / ext;
     const float4 h = pos[s];
@@ -281,11 +289,11 @@ hipError_t launch_bitonic(unsigned long long* keys, int n_pow2, hipStream_t s) {
 }
 
 hipError_t launch_sort(float4* pos, float4* lo, int* typ, int* oid, int n, const SortBuffers& B,
-                       hipStream_t s) {
+                       hipStream_t s, float clip) {
     hipLaunchKernelGGL(k_bounds_part, dim3(B.bounds_parts), dim3(256), 0, s, pos, n,
                        B.bounds_part);
     hipLaunchKernelGGL(k_curve_keys, dim3((B.n_pow2 + 255) / 256), dim3(256), 0, s, pos, n, B.n_pow2,
-                       B.bounds_part, B.bounds_parts, B.keys);
+                       B.bounds_part, B.bounds_parts, clip, B.keys);
     return launch_sort_by_keys(pos, lo, typ, oid, n, B, s);
 }
 

@@ -136,6 +136,8 @@ ld_status ld_forces_noalloc(int64_t n, const int32_t* type, const double* charge
     L.Fpart = part;
     L.S = nullptr;
     L.U = nullptr;
+    L.nearbits = nullptr;                    // the LJ kernel finds near groups by their boxes
+    L.nb_words = 0;
     HIP_TRY(ld::launch_pair(L, tab, s));
     hipLaunchKernelGGL(k_static_sum, grid, dim3(kStaticBlock), 0, s, (const double*)part,
                        kStaticSplit, N, F_pair);
