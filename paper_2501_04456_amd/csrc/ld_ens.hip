@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
     const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
     const int* __restrict__ off, const int2* __restrict__ items, int W, unsigned* counter, const PairTable* __restrict__ tabs,
     const Box* __restrict__ box, const int* __restrict__ tbase, double* __restrict__ F,
-    int total) {
+    int total, unsigned* __restrict__ nearbits, int nb_words) {
     __shared__ float4 sp[kWaves][kGroup];
     __shared__ float4 sl[kWaves][kGroup];
     const int w = threadIdx.x / kGroup;
@@ -72,9 +72,8 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
         const float4 li = live ? lo[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
         pair::Acc a;
         Box bi;
-        int t0 = 0;
+        const int t0 = tbase[d];
         if constexpr (CULL) {
-            t0 = tbase[d];
             bi = box[t0 + it.y / kGroup];
         }
         const float cull2 = rc2max * 1.0001f;
@@ -93,9 +92,16 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
             sp[w][lane] = j < nd ? pos[o + j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
             if (near) sl[w][lane] = j < nd ? lo[o + j] : make_float4(0.f, 0.f, 0.f, 0.f);
             wave_sync();
-            if (near)
-                (void)pair::group_near<COMP, false>(sp[w], sl[w], jt, i, pi, li, cull2, a);
-            else
+            if (near) {
+                const bool lj = pair::group_near<COMP, false>(sp[w], sl[w], jt, i, pi, li,
+                                                              cull2, a);
+                // tile pairs with a Lennard-Jones candidate, for k_ens_lj
+                if (__ballot(lj && live) && lane == 0) {
+                    const int gj = jt / kGroup;
+                    atomicOr(&nearbits[(size_t)(t0 + it.y / kGroup) * nb_words + (gj >> 5)],
+                             1u << (gj & 31));
+                }
+            } else
                 pair::group_far<COMP, UNROLL>(sp[w], pi, a);
         }
         if constexpr (COMP == 1) {
@@ -115,14 +121,16 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
 
 // Lennard-Jones forces of every tile of every droplet, in FP64, added into F
 // after k_ens_pair.  One workgroup per 64-slot tile: its four wavefronts
-// test the same boxes of the droplet's tiles (all of them when boxes are
-// off) and share the near ones round-robin; each stages its j tiles in its
-// own LDS slice, and the partial sums are added in wavefront order.
+// share round-robin the j tiles in which k_ens_pair found a pair within the
+// largest LJ range (a bitmap row per tile, cleared here); each stages its j
+// tiles in its own LDS slice, and the partial sums are added in wavefront
+// order.
 __global__ __launch_bounds__(kEnsBlock) void k_ens_lj(
     const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
     const int* __restrict__ off, const int2* __restrict__ tiles, int ntiles,
     const PairTable* __restrict__ tabs, const Box* __restrict__ box,
-    const int* __restrict__ tbase, double* __restrict__ F, int total) {
+    const int* __restrict__ tbase, double* __restrict__ F, int total,
+    unsigned* __restrict__ nearbits, int nb_words) {
     __shared__ float4 sh[kWaves][kGroup];
     __shared__ float4 sl[kWaves][kGroup];
     __shared__ int st[kWaves][kGroup];
@@ -150,9 +158,10 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_lj(
     double L[3] = {0.0, 0.0, 0.0};
     double S = 0.0, U = 0.0;
     int rank = 0;
+    unsigned* row = nearbits + (size_t)t * nb_words;   // tiles k_ens_pair found an LJ candidate in
     for (int c0 = 0; c0 < ng; c0 += kGroup) {
-        bool nb = c0 + lane < ng;
-        if (nb && box) nb = pair::box_dist2(bi, box[t0 + c0 + lane]) < cull2;
+        const int gj = c0 + lane;
+        const bool nb = gj < ng && ((row[gj >> 5] >> (gj & 31)) & 1u);
         unsigned long long m = __ballot(nb);
         while (m) {
             const int g = c0 + __builtin_ctzll(m);
@@ -181,6 +190,7 @@ __global__ __launch_bounds__(kEnsBlock) void k_ens_lj(
     red[w][1][lane] = L[1];
     red[w][2][lane] = L[2];
     __syncthreads();
+    for (int k = threadIdx.x; k < nb_words; k += kEnsBlock) row[k] = 0u;   // all zero at rest
     if (w != 0 || !live) return;
     double Ls[3] = {0.0, 0.0, 0.0};
     for (int v = 0; v < kWaves; ++v)
@@ -348,6 +358,8 @@ struct ld_ens {
     int comp = 0;
     int graph_steps = 0;
     int unroll = 16;                     // Coulomb pairs in flight per lane (8, 16 or 32)
+    unsigned* nearbits = nullptr;        // [ntiles][nb_words] tile pairs with an LJ candidate
+    int nb_words = 0;
     hipGraphExec_t graph = nullptr;
     double graph_dt = 0.0;
     int graph_len = 0;
@@ -371,7 +383,7 @@ void ens_free(ld_ens* e) {
     void* bufs[] = {e->pos,   e->lo,   e->typ,   e->did,     e->lid,   e->off,
                     e->items, e->counter, e->tabs, e->ext,   e->seeds, e->F,
                     e->work,  e->st,   e->box,   e->tbase,   e->tiles, e->dbounds,
-                    e->sb.keys, e->sb.tmp4, e->sb.tmp_i};
+                    e->sb.keys, e->sb.tmp4, e->sb.tmp_i, e->nearbits};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (e->graph) (void)hipGraphExecDestroy(e->graph);
@@ -401,11 +413,12 @@ void launch_ens_pair_u(ld_ens* e, hipStream_t s) {
     if (e->cull)
         hipLaunchKernelGGL((k_ens_pair<COMP, true, UNROLL>), dim3(e->workgroups), dim3(kEnsBlock),
                            0, s, e->pos, e->lo, e->typ, e->off, e->items, e->W, e->counter,
-                           e->tabs, e->box, e->tbase, e->F, e->total);
+                           e->tabs, e->box, e->tbase, e->F, e->total, e->nearbits, e->nb_words);
     else
         hipLaunchKernelGGL((k_ens_pair<COMP, false, UNROLL>), dim3(e->workgroups),
                            dim3(kEnsBlock), 0, s, e->pos, e->lo, e->typ, e->off, e->items, e->W,
-                           e->counter, e->tabs, e->box, e->tbase, e->F, e->total);
+                           e->counter, e->tabs, e->box, e->tbase, e->F, e->total, e->nearbits,
+                           e->nb_words);
 }
 
 template <int COMP>
@@ -418,19 +431,25 @@ void launch_ens_pair(ld_ens* e, hipStream_t s) {
         launch_ens_pair_u<COMP, 16>(e, s);
 }
 
-ld_status enqueue_pair(ld_ens* e, hipStream_t s) {
+// Boxes, the persistent Coulomb kernel, then the FP64 Lennard-Jones kernel;
+// t0 / t1 (or null) are recorded around the Coulomb kernel.
+ld_status enqueue_pair(ld_ens* e, hipStream_t s, hipEvent_t t0 = nullptr,
+                       hipEvent_t t1 = nullptr) {
     if (e->cull)
         hipLaunchKernelGGL(k_ens_boxes, dim3((e->ntiles + 3) / 4), dim3(256), 0, s, e->pos,
                            e->off, e->tiles, e->ntiles, e->box);
     hipLaunchKernelGGL(k_ens_reset, dim3(1), dim3(1), 0, s, e->counter);
+    if (t0) HIP_TRY(hipEventRecord(t0, s));
     if (e->comp == 0)
         launch_ens_pair<0>(e, s);
     else
         launch_ens_pair<1>(e, s);
     HIP_TRY(hipGetLastError());
+    if (t1) HIP_TRY(hipEventRecord(t1, s));
     hipLaunchKernelGGL(k_ens_lj, dim3(e->ntiles), dim3(kEnsBlock), 0, s,
                        e->pos, e->lo, e->typ, e->off, e->tiles, e->ntiles, e->tabs,
-                       e->cull ? e->box : nullptr, e->tbase, e->F, e->total);
+                       e->cull ? e->box : nullptr, e->tbase, e->F, e->total, e->nearbits,
+                       e->nb_words);
     HIP_TRY(hipGetLastError());
     return LD_OK;
 }
@@ -451,11 +470,9 @@ ld_status enqueue_step(ld_ens* e, double dt, hipStream_t s, bool timed) {
         }
         a = e->ev[e->ev_used++];
         b = e->ev[e->ev_used++];
-        HIP_TRY(hipEventRecord(a, s));
     }
-    ld_status st = enqueue_pair(e, s);
+    ld_status st = enqueue_pair(e, s, a, b);    // timed: the Coulomb kernel alone
     if (st != LD_OK) return st;
-    if (timed) HIP_TRY(hipEventRecord(b, s));
     hipLaunchKernelGGL(k_ens_update, dim3((e->total + 255) / 256), dim3(256), 0, s, e->pos,
                        e->lo, e->typ, e->did, e->lid, e->F, e->total, e->ext, e->seeds, dt,
                        e->st);
@@ -593,6 +610,15 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
     // spatial ordering needs the droplet index in 13 bits
     e->cull = n_drop <= (1 << 13);
     e->ntiles = (int)tiles.size();
+    {
+        int max_ng = 1;
+        for (int d = 0; d < n_drop; ++d)
+            max_ng = std::max(max_ng, (int)((offs[d + 1] - offs[d] + kGroup - 1) / kGroup));
+        e->nb_words = (max_ng + 31) / 32;
+        const size_t bytes = sizeof(unsigned) * tiles.size() * (size_t)e->nb_words;
+        ok = ok && hipMalloc(&e->nearbits, bytes) == hipSuccess &&
+             hipMemsetAsync(e->nearbits, 0, bytes, s) == hipSuccess;
+    }
     int n_pow2 = 2048;                                   // the bitonic sort's smallest size
     while (n_pow2 < (int)total) n_pow2 <<= 1;
     e->sb.n_pow2 = n_pow2;

@@ -486,3 +486,37 @@ def test_init_sampler_full_size(ld, orc):
     wd.radius = W.Radius(kind=W.RADIUS_CONST, R0=2.0)
     with pytest.raises(RuntimeError):
         sampled_system(ld, wd)
+
+
+def test_step_with_schedule_seed_and_diagnostics(ld, orc):
+    """ld_step's own arguments: from step 10 on a new radius schedule and a
+    new noise seed (both sides switch there), and the FP64 diagnostics the
+    call returns after the steps, against the oracle's trajectory and its
+    diagnostics at the same state (positions within 1e-4 sigma; energies,
+    net force, maxima and MSD as in test_diagnostics)."""
+    w = W.config_medium(n=1200, seed=43)
+    s = ld.System.from_workload(w)
+    s.step(10, w.dt)
+    st = orc.State(w)
+    assert st.run(10) == -1
+    x0 = w.pos.astype(np.float64)
+    r2 = W.Radius(kind=W.RADIUS_LINEAR, R0=w.radius.R0, R1=0.8 * w.radius.R0, T=0.02)
+    d = s.step(10, w.dt, radius=r2, seed=77, diag=True)
+    st.radius, st.seed = r2, 77
+    assert st.run(10) == -1
+    xg = s.positions64()
+    assert np.abs(xg - st.x).max() <= POS_TOL
+    assert d["step"] == 20 and d["bad_step"] == -1
+    assert d["t"] == pytest.approx(st.t, rel=1e-15)
+    assert d["R"] == pytest.approx(orc.radius_at(r2, st.t), rel=1e-15)
+    do = st.diagnostics()
+    assert d["U"][0] == pytest.approx(do[0], rel=1e-4, abs=1e-8)
+    assert d["U"][1] == pytest.approx(do[1], rel=1e-5)
+    assert np.allclose(d["U"][2:5], do[2:5], rtol=1e-6, atol=1e-9)
+    assert d["max_radius"] == pytest.approx(do[9], rel=1e-9)
+    assert d["msd"] == pytest.approx(orc.msd(st.x, x0), rel=1e-5)
+    # the new seed took effect: another seed gives another trajectory
+    s2 = ld.System.from_workload(w)
+    s2.step(10, w.dt)
+    s2.step(10, w.dt, radius=r2)
+    assert np.abs(s2.positions64() - xg).max() > 1e-3
