@@ -79,6 +79,15 @@ def parse():
     ap.add_argument("--comp", type=int, default=None, choices=[0, 1],
                     help="pair sums: 0 = FP32 blocks of 32 terms into FP64 totals, 1 = blocked "
                          "Kahan (default: the library's)")
+    ap.add_argument("--block", type=int, default=None, choices=[64, 128, 256, 512],
+                    help="pair kernel work-items per workgroup (default: the library's)")
+    ap.add_argument("--j-split", type=int, default=None,
+                    help="pair kernel j ranges per i tile (default: the library's)")
+    ap.add_argument("--cull", type=int, default=None, choices=[0, 1],
+                    help="pair kernel group-pair culling: 0 = every pair of groups takes the "
+                         "near loop (default: the library's)")
+    ap.add_argument("--sort-every", type=int, default=None,
+                    help="steps between spatial re-sorts (< 0: never; default: the library's)")
     ap.add_argument("--no-windows", action="store_true",
                     help="large: skip the middle and late 500-step windows (steps 4750 and "
                          "9500 of the 1e4-step run)")
@@ -461,7 +470,11 @@ def learned_run(a, torch, ldrop, W, steps=None):
     err = ev.ff_judge()
     ev.ff_mode(1)
     ev.step(2, we.dt)
+    ev.kernel_timing(True)
     ms_learned = timed(ev, steps, we.dt)
+    near_launches, near_ms = ev.near_kernel_time()
+    ev.kernel_timing(False)
+    near_pairs = near_block_pairs(ev.positions64(), G=32, B=5) if a.near_mode == "block" else None
     # the method without the network (near + coarse only)
     K = 4 * 5 ** 3 + 3
     o = (K + 31) // 32 * 32 * 128 + 128 + 128 * 128 + 128
@@ -511,7 +524,45 @@ def learned_run(a, torch, ldrop, W, steps=None):
                      "frac_of_bf16_peak": (train_flops / train_s / 1e12 / 2500.0
                                            if train_s else None)},
         "direct_pair_interactions_per_s": pairs * 1e3 / ms_direct,
+        "near_roofline": near_roofline(near_pairs, near_launches, near_ms),
     }
+
+
+def near_block_pairs(pos, G, B):
+    """Ordered pairs the block near field evaluates: every particle with
+    every other particle of the B^3 block of grid cells around its own cell
+    (cells of side 2L/G, L = 1.0009765625 max |coordinate|, clipped at the
+    grid's faces).  Host-side bookkeeping for the flop count only."""
+    import numpy as np
+    L = float(np.float32(np.abs(pos).max()) * np.float32(1.0009765625))
+    h = 2.0 * L / G
+    c = np.clip(np.floor((pos + L) / h).astype(np.int64), 0, G - 1)
+    cnt = np.zeros((G, G, G), np.int64)
+    np.add.at(cnt, (c[:, 2], c[:, 1], c[:, 0]), 1)
+    half = B // 2
+    box = cnt.copy()
+    for ax in range(3):             # sum over the window [-half, half] per axis
+        p = np.pad(box, [(half, half) if k == ax else (0, 0) for k in range(3)])
+        cs = np.cumsum(p, axis=ax)
+        cs = np.concatenate([np.zeros_like(np.take(cs, [0], axis=ax)), cs], axis=ax)
+        hi = np.take(cs, np.arange(B, G + B), axis=ax)
+        lo = np.take(cs, np.arange(0, G), axis=ax)
+        box = hi - lo
+    return int((cnt * box).sum() - len(pos))
+
+
+def near_roofline(pairs, launches, ms):
+    """Roofline object of the learned path's near-field pair kernels: 19
+    FP32 flops per evaluated ordered pair (the Coulomb term; the few LJ
+    pairs are extra) over their HIP-event duration."""
+    if not pairs or not launches or ms <= 0:
+        return None
+    avg = ms / launches
+    achieved = 19.0 * pairs / (avg * 1e-3) / 1e12
+    return {"kernel": "k_near_block", "bound": "alu", "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+            "pairs_per_launch": pairs, "avg_launch_ms": avg, "launches": launches,
+            "traffic": None}
 
 
 def bench_learned(a, torch, ldrop, W):
@@ -559,8 +610,9 @@ def main():
         s.autotune()
     if a.graph:
         s.set_tuning(graph_steps=a.graph)
-    if a.comp is not None:
-        s.set_tuning(comp=a.comp)
+    for key in ("comp", "block", "j_split", "cull", "sort_every"):
+        if getattr(a, key) is not None:
+            s.set_tuning(**{key: getattr(a, key)})
     tune = s.tuning()
     flagged = []
 

@@ -336,6 +336,12 @@ ld_status ld_autotune(ld_ctx* ctx, const char* cache_path, int32_t force, ld_tun
  * launches and their total duration in milliseconds. */
 ld_status ld_kernel_timing(ld_ctx* ctx, int32_t enable);
 ld_status ld_kernel_time(ld_ctx* ctx, int64_t* launches, double* total_ms);
+/* With the learned far field on (ld_ff_enable), the same record also times
+ * the near-field pair kernels of every step that builds the near part (from
+ * the first near kernel's start to the last one's end); this returns their
+ * count and total duration in milliseconds, as ld_kernel_time does for the
+ * Coulomb kernel.  Errors: LD_EINVAL, LD_EHIP. */
+ld_status ld_near_kernel_time(ld_ctx* ctx, int64_t* launches, double* total_ms);
 
 /* ---------------------------------------------------------------------- */
 /* Learned far field                                                        */

@@ -152,6 +152,20 @@ void make_tables(const ld_params& p, const ld_radius& R, PairTable& tb, ExtParam
 }
 
 }  // namespace host
+
+bool timing_events(ld_ctx* c, unsigned char kind, hipEvent_t* e0, hipEvent_t* e1) {
+    for (int k = 0; k < 2; ++k)
+        if (c->ev_used + k == c->ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return false;
+            c->ev_pool.push_back(e);
+        }
+    *e0 = c->ev_pool[c->ev_used];
+    *e1 = c->ev_pool[c->ev_used + 1];
+    c->ev_used += 2;
+    c->ev_kind.push_back(kind);
+    return true;
+}
 }  // namespace ld
 
 namespace {
@@ -204,14 +218,6 @@ ld_status ensure_split_capacity(ld_ctx* c, int split) {
     return LD_OK;
 }
 
-hipEvent_t next_event(ld_ctx* c) {
-    if (c->ev_used == c->ev_pool.size()) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        c->ev_pool.push_back(e);
-    }
-    return c->ev_pool[c->ev_used++];
-}
 
 ld_status run_pair(ld_ctx* c, bool diag, hipStream_t s, bool timed) {
     ld::PairLaunch L{};
@@ -231,9 +237,8 @@ ld_status run_pair(ld_ctx* c, bool diag, hipStream_t s, bool timed) {
     L.nb_words = c->nb_words;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
-        e0 = next_event(c);
-        e1 = next_event(c);
-        if (!e0 || !e1) return fail(LD_EHIP, "cannot create timing events");
+        if (!ld::timing_events(c, ld::kTimedCoulomb, &e0, &e1))
+            return fail(LD_EHIP, "cannot create timing events");
         HIP_TRY(hipEventRecord(e0, s));
     }
     // timed: the Coulomb kernel alone (the Lennard-Jones kernel follows it)
@@ -1318,23 +1323,41 @@ ld_status ld_kernel_timing(ld_ctx* c, int32_t enable) {
     if (!c) return fail(LD_EINVAL, "ctx is NULL");
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->timing = enable != 0;
-    if (enable) c->ev_used = 0;
+    if (enable) {
+        c->ev_used = 0;
+        c->ev_kind.clear();
+    }
     return LD_OK;
 }
+
+namespace {
+ld_status timed_total(ld_ctx* c, unsigned char kind, int64_t* launches, double* total_ms) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (size_t p = 0; p < c->ev_kind.size() && 2 * p + 1 < c->ev_used; ++p) {
+        if (c->ev_kind[p] != kind) continue;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[2 * p], c->ev_pool[2 * p + 1]));
+        tot += ms;
+        ++cnt;
+    }
+    if (launches) *launches = cnt;
+    if (total_ms) *total_ms = tot;
+    return LD_OK;
+}
+}  // namespace
 
 ld_status ld_kernel_time(ld_ctx* c, int64_t* launches, double* total_ms) {
     g_err.clear();
     if (!c) return fail(LD_EINVAL, "ctx is NULL");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    double tot = 0.0;
-    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
-        tot += ms;
-    }
-    if (launches) *launches = (int64_t)(c->ev_used / 2);
-    if (total_ms) *total_ms = tot;
-    return LD_OK;
+    return timed_total(c, ld::kTimedCoulomb, launches, total_ms);
+}
+
+ld_status ld_near_kernel_time(ld_ctx* c, int64_t* launches, double* total_ms) {
+    g_err.clear();
+    if (!c) return fail(LD_EINVAL, "ctx is NULL");
+    return timed_total(c, ld::kTimedNear, launches, total_ms);
 }
 
 }  // extern "C"

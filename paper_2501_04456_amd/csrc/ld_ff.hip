@@ -457,10 +457,12 @@ __global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cf
 // pair.
 //
 // FP32 pair terms (Coulomb and LJ apart) in blocks of at most 32, FP64 totals.
+//
+// The two walks are separate instances (LANE), both launched on the same
+// grid; the one that does not match the grid's W leaves at once.  Compiled
+// together the row walk's registers made the lane walk spill to scratch at
+// 6 wavefronts per SIMD; apart, the lane walk needs no scratch.
 constexpr int kNbChunk = 192;          // staged slots per piece of a row's range
-// 6 wavefronts per SIMD: a few cold registers spill to scratch, and the
-// extra occupancy hides the row loads better (measured 2 % on the learned
-// step against the unconstrained 5 wavefronts).
 
 struct NbAcc {
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, Lx = 0.0, Ly = 0.0, Lz = 0.0;
@@ -523,6 +525,7 @@ __device__ __forceinline__ void nb_range(const float4* sp, const int* st, int lo
     }
 }
 
+template <bool LANE>
 __global__ __launch_bounds__(64, 6) void k_near_block(const float4* __restrict__ pos,
                                                    const int* __restrict__ typ,
                                                    const unsigned long long* __restrict__ keys,
@@ -536,6 +539,8 @@ __global__ __launch_bounds__(64, 6) void k_near_block(const float4* __restrict__
     __shared__ float ttab[3 * kMaxTypes * kMaxTypes];
     const int lane = threadIdx.x;
     if ((int)blockIdx.x >= *ntiles) return;            // uniform per workgroup
+    const int W = g->W;
+    if ((W == half) != LANE) return;                   // the other walk's grid
     for (int k = lane; k < kMaxTypes * kMaxTypes; k += 64) {
         ttab[k] = tab.sig2[k];
         ttab[kMaxTypes * kMaxTypes + k] = tab.rc2[k];
@@ -551,11 +556,10 @@ __global__ __launch_bounds__(64, 6) void k_near_block(const float4* __restrict__
     const int x_first = (int)((unsigned)(keys[s0] >> 32) % (unsigned)G);
     const int x_last = (int)((unsigned)(keys[s1 - 1] >> 32) % (unsigned)G);
     const int ry = row % G, rz = row / G;
-    const int W = g->W;
     const int T = tab.T;
     const float rc2max = tab.rc2max;
     NbAcc a;
-    if (W == half) {
+    if constexpr (LANE) {
         const int wlj = g->Wlj;
         const int trow = ti * T;
         for (int dz = -half; dz <= half; ++dz) {
@@ -1752,19 +1756,29 @@ ld_status ff_near(ld_ctx* c, hipStream_t s) {
         std::swap(c->oid, c->oid2);
         c->graph_len = -1;
     }
+    // timed: the near-field pair kernels alone
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing && !ld::timing_events(c, ld::kTimedNear, &e0, &e1))
+        return fail(LD_EHIP, "cannot create timing events");
     if (block) {
         KLAUNCH(k_cell_first, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, M, f->cfirst);
         KLAUNCH(k_block_tiles, dim3(1), dim3(1024), s, f->cfirst, G, f->tiles, f->ntiles);
-        KLAUNCH(k_near_block, dim3(f->max_tiles), dim3(64), s, c->pos, c->typ, c->sb.keys, f->grid,
-                G, f->cfg.block / 2, f->cfirst, f->tiles, f->ntiles, n, c->tab, f->Fnear);
+        if (e0) HIP_TRY(hipEventRecord(e0, s));
+        KLAUNCH(k_near_block<true>, dim3(f->max_tiles), dim3(64), s, c->pos, c->typ, c->sb.keys,
+                f->grid, G, f->cfg.block / 2, f->cfirst, f->tiles, f->ntiles, n, c->tab, f->Fnear);
+        KLAUNCH(k_near_block<false>, dim3(f->max_tiles), dim3(64), s, c->pos, c->typ, c->sb.keys,
+                f->grid, G, f->cfg.block / 2, f->cfirst, f->tiles, f->ntiles, n, c->tab, f->Fnear);
+        if (e1) HIP_TRY(hipEventRecord(e1, s));
     } else {
         KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cstart, NC);
         KLAUNCH(k_zero_i, dim3((NC + kB - 1) / kB), dim3(kB), s, f->cend, NC);
         KLAUNCH(k_cell_ranges, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, f->cstart,
                 f->cend);
         const float rc2 = (float)(f->cfg.near_cut * f->cfg.near_cut);
+        if (e0) HIP_TRY(hipEventRecord(e0, s));
         KLAUNCH(k_near, dim3((n + kB - 1) / kB), dim3(kB), s, c->pos, c->typ, n, f->grid,
                 f->cstart, f->cend, rc2, c->tab, f->Fnear);
+        if (e1) HIP_TRY(hipEventRecord(e1, s));
     }
     c->steps_since_sort = 0;
     return LD_OK;
@@ -1790,9 +1804,10 @@ ld_status ff_far_exact(ld_ctx* c, hipStream_t s) {
 ld_status gemm(hipStream_t s, const float* A, int lda, int tA, const float* B, int ldb, int tB,
                float* C, int ldc, int M, int N, int K, const float* bias, int act, float* Z,
                int ldz, int acc, const int* M_dev, float* work = nullptr,
-               size_t work_floats = 0) {
+               size_t work_floats = 0, float* colsum_B = nullptr) {
     ld::GemmArgs g{};
     g.work = work; g.work_floats = work_floats;
+    g.colsum_B = colsum_B;
     g.A = A; g.lda = lda; g.transA = tA;
     g.B = B; g.ldb = ldb; g.transB = tB;
     g.C = C; g.ldc = ldc;
@@ -1955,24 +1970,20 @@ ld_status fwd_bwd(FarField* f, int B_, hipStream_t s, double* loss) {
              nullptr, 0, 0, nullptr));
     int nparts = 0;
     HIP_TRY(ld::launch_mse(f->bY, Op, f->bT, B_, 3, f->bdY, f->loss_part, &nparts, s));
-    // layer 3
+    // layer 3: weight and bias gradients in one product (the bias gradient
+    // is the column sums of dY), then dA2 times SiLU'(Z2) in its epilogue
     TRY(gemm(s, f->bA2, H, 1, f->bdY, Op, 0, gW + f->offW3, Op, H, Op, B_, nullptr, 0, nullptr, 0,
-             0, nullptr, f->gws, f->gws_floats));
-    HIP_TRY(ld::launch_colsum(f->bdY, B_, Op, gW + f->offb3, s));
-    TRY(gemm(s, f->bdY, Op, 0, W + f->offW3, Op, 1, f->bd2, H, B_, H, Op, nullptr, 0, nullptr, 0,
-             0, nullptr));
-    HIP_TRY(ld::launch_silu_bwd(f->bZ2, f->bd2, B_, H, nullptr, s));
+             0, nullptr, f->gws, f->gws_floats, gW + f->offb3));
+    TRY(gemm(s, f->bdY, Op, 0, W + f->offW3, Op, 1, f->bd2, H, B_, H, Op, nullptr, 2, f->bZ2, H, 0,
+             nullptr));
     // layer 2
     TRY(gemm(s, f->bA1, H, 1, f->bd2, H, 0, gW + f->offW2, H, H, H, B_, nullptr, 0, nullptr, 0, 0,
-             nullptr, f->gws, f->gws_floats));
-    HIP_TRY(ld::launch_colsum(f->bd2, B_, H, gW + f->offb2, s));
-    TRY(gemm(s, f->bd2, H, 0, W + f->offW2, H, 1, f->bd1, H, B_, H, H, nullptr, 0, nullptr, 0, 0,
+             nullptr, f->gws, f->gws_floats, gW + f->offb2));
+    TRY(gemm(s, f->bd2, H, 0, W + f->offW2, H, 1, f->bd1, H, B_, H, H, nullptr, 2, f->bZ1, H, 0,
              nullptr));
-    HIP_TRY(ld::launch_silu_bwd(f->bZ1, f->bd1, B_, H, nullptr, s));
     // layer 1
     TRY(gemm(s, f->bX, Kp, 1, f->bd1, H, 0, gW + f->offW1, H, Kp, H, B_, nullptr, 0, nullptr, 0, 0,
-             nullptr, f->gws, f->gws_floats));
-    HIP_TRY(ld::launch_colsum(f->bd1, B_, H, gW + f->offb1, s));
+             nullptr, f->gws, f->gws_floats, gW + f->offb1));
 #undef TRY
     if (loss) {
         std::vector<double> parts(nparts);

@@ -22,7 +22,7 @@ struct GemmArgs {
     float* Z;
     int ldz;
     int M, N, K;
-    int act;          // 0 none, 1 SiLU
+    int act;          // 0 none, 1 SiLU (Z stores the pre-activation), 2 times SiLU'(Z)
     int accumulate;   // 1: C += result
     const int* M_dev;
     // Optional FP32 workspace for split-K: when C has few 64 x 64 tiles and
@@ -31,12 +31,13 @@ struct GemmArgs {
     // piece order by a second kernel.  Unused when NULL or too small.
     float* work;
     size_t work_floats;
+    // Optional: the column sums of B (sum over k of B[k][n], FP32, N values;
+    // the bias gradient when B is the pre-activation gradient).  B must not
+    // be transposed.
+    float* colsum_B;
 };
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
-hipError_t launch_silu_bwd(const float* Z, float* dA, int rows, int cols, const int* rows_dev,
-                           hipStream_t s);
-hipError_t launch_colsum(const float* dZ, int rows, int cols, float* db, hipStream_t s);
 hipError_t launch_mse(const float* Y, int ld, const float* T, int rows, int out, float* dY,
                       double* part, int* nparts, hipStream_t s);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int n, float lr, int step,

@@ -1,7 +1,8 @@
 // Dense matrix products of the learned far field on the matrix cores:
-// C = op(A) op(B) (+ bias) (-> SiLU) with BF16 operands and FP32
-// accumulation (v_mfma_f32_16x16x32_bf16), plus the elementwise pieces of
-// training (SiLU derivative, bias gradients, mean-squared loss, Adam).
+// C = op(A) op(B) (+ bias) (-> SiLU, or times SiLU' of a stored
+// pre-activation) with BF16 operands and FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16), optionally with the column sums of B (the bias
+// gradients of training), plus the mean-squared loss and Adam.
 //
 // Tiling: a workgroup of 4 wavefronts owns a 64 x 64 tile of C; each
 // wavefront owns 16 rows x 64 columns (four 16 x 16 MFMA tiles).  K advances
@@ -13,6 +14,14 @@
 //
 // MFMA 16x16x32 operand layout (wave64): lane l supplies A[l % 16][8 (l/16)
 // + 0..7] and B[8 (l/16) + 0..7][l % 16]; it receives C[4 (l/16) + 0..3][l % 16].
+//
+// k_gemm_v is the same tiling for operands whose rows are 16-byte aligned
+// (every product of the far-field network): K advances 64 at a time, each
+// work-item fetches its share of the next A and B tiles as four 16-byte
+// loads each while the matrix cores work on the current tile (register
+// double buffering), and the tiles are written to LDS as BF16, transposed on
+// the way where K is the operand's strided index.  k_gemm is the general
+// fallback (any alignment).
 #include <algorithm>
 
 #include "ld_internal.h"
@@ -35,6 +44,20 @@ __device__ __forceinline__ __bf16 to_bf16(float f) {
 // SiLU as in the fused kernel: hardware exponential and reciprocal.
 __device__ __forceinline__ float silu(float z) {
     return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+
+// The product's epilogue: bias, then act 1 (store the pre-activation in Z if
+// given, apply SiLU) or act 2 (multiply by SiLU'(z) for the stored
+// pre-activation z = Z[row][col], the backward pass through the activation).
+__device__ __forceinline__ float epilogue(const GemmArgs& g, int row, int col, float v) {
+    if (g.bias) v += g.bias[col];
+    if (g.act == 2) {
+        const float z = g.Z[(size_t)row * g.ldz + col];
+        const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+        return v * (sg * (1.0f + z * (1.0f - sg)));
+    }
+    if (g.Z) g.Z[(size_t)row * g.ldz + col] = v;
+    return g.act == 1 ? silu(v) : v;
 }
 
 // part == nullptr: the whole K range and the epilogue (bias, pre-activation,
@@ -106,10 +129,185 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int kpiece, float* par
         for (int r = 0; r < 4; ++r) {
             const int row = m0 + w * 16 + 4 * (l / 16) + r;
             if (row >= M || col >= g.N) continue;
-            float v = acc[j][r];
-            if (g.bias) v += g.bias[col];
-            if (g.Z) g.Z[(size_t)row * g.ldz + col] = v;
-            if (g.act == 1) v = silu(v);
+            const float v = epilogue(g, row, col, acc[j][r]);
+            float* c = g.C + (size_t)row * g.ldc + col;
+            *c = g.accumulate ? *c + v : v;
+        }
+    }
+}
+
+constexpr int VK = 64;                 // K per stage of k_gemm_v
+
+// Pack two floats as adjacent BF16 values (the first at the lower address).
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    return (uint32_t)__builtin_bit_cast(unsigned short, to_bf16(lo)) |
+           ((uint32_t)__builtin_bit_cast(unsigned short, to_bf16(hi)) << 16);
+}
+
+// One operand tile, 64 rows (rows of A or columns of B) x VK values of k,
+// fetched into registers and stored to LDS as S[row][k] in BF16.  KC: k is
+// the contiguous index in memory (element (r, k) at P[r ld + k]); otherwise
+// rows are (element (r, k) at P[k ld + r]).  Elements outside [0, rlim) x
+// [0, klim) read as zero.
+template <bool KC>
+struct Tile {
+    float4 v[4];
+
+    __device__ __forceinline__ void load(const float* __restrict__ P, int ld, int r0, int rlim,
+                                         int k0, int klim, int t) {
+        if constexpr (KC) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int idx = t + 256 * q;
+                const int r = r0 + idx / 16, k = k0 + (idx % 16) * 4;
+                const float* src = P + (size_t)r * ld + k;
+                if (r < rlim && k + 3 < klim) {
+                    v[q] = *reinterpret_cast<const float4*>(src);
+                } else {
+                    const bool rr = r < rlim;
+                    v[q].x = rr && k < klim ? src[0] : 0.f;
+                    v[q].y = rr && k + 1 < klim ? src[1] : 0.f;
+                    v[q].z = rr && k + 2 < klim ? src[2] : 0.f;
+                    v[q].w = rr && k + 3 < klim ? src[3] : 0.f;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int idx = t + 256 * q;
+                const int r = r0 + (idx % 16) * 4;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int k = k0 + 2 * (idx / 16) + h;
+                    const float* src = P + (size_t)k * ld + r;
+                    float4& d = v[2 * q + h];
+                    if (k < klim && r + 3 < rlim) {
+                        d = *reinterpret_cast<const float4*>(src);
+                    } else {
+                        const bool kk = k < klim;
+                        d.x = kk && r < rlim ? src[0] : 0.f;
+                        d.y = kk && r + 1 < rlim ? src[1] : 0.f;
+                        d.z = kk && r + 2 < rlim ? src[2] : 0.f;
+                        d.w = kk && r + 3 < rlim ? src[3] : 0.f;
+                    }
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(__bf16 (*S)[VK + PAD], int t) const {
+        if constexpr (KC) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int idx = t + 256 * q;
+                uint2 w;
+                w.x = pack2(v[q].x, v[q].y);
+                w.y = pack2(v[q].z, v[q].w);
+                *reinterpret_cast<uint2*>(&S[idx / 16][(idx % 16) * 4]) = w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int idx = t + 256 * q;
+                const int r = (idx % 16) * 4, k = 2 * (idx / 16);
+                const float4 a = v[2 * q], b = v[2 * q + 1];
+                *reinterpret_cast<uint32_t*>(&S[r][k]) = pack2(a.x, b.x);
+                *reinterpret_cast<uint32_t*>(&S[r + 1][k]) = pack2(a.y, b.y);
+                *reinterpret_cast<uint32_t*>(&S[r + 2][k]) = pack2(a.z, b.z);
+                *reinterpret_cast<uint32_t*>(&S[r + 3][k]) = pack2(a.w, b.w);
+            }
+        }
+    }
+};
+
+// As k_gemm (same arguments, epilogue and split-K pieces), for 16-byte
+// aligned operands with leading dimensions divisible by 4.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g, int kpiece, float* part) {
+    __shared__ __attribute__((aligned(16))) __bf16 As[BM][VK + PAD];
+    __shared__ __attribute__((aligned(16))) __bf16 Bt[BN][VK + PAD];
+    const int M = g.M_dev ? min(g.M, *g.M_dev) : g.M;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    if (m0 >= M) return;
+    const int kb = part ? (int)blockIdx.z * kpiece : 0;
+    const int ke = part ? min(g.K, kb + kpiece) : g.K;
+    const int t = threadIdx.x, w = t / 64, l = t % 64;
+    f32x4 acc[4];
+    for (int j = 0; j < 4; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    Tile<!TA> ta;          // A is k-contiguous unless transposed
+    Tile<TB> tb;           // B (K x N) is k-contiguous only when transposed
+    ta.load(g.A, g.lda, m0, M, kb, ke, t);
+    tb.load(g.B, g.ldb, n0, g.N, kb, ke, t);
+    // column sums of B (FP32, before rounding): the first row of tiles only;
+    // this work-item's values all lie in columns n0 + 4 (t % 16) + 0..3
+    const bool csum = !TB && g.colsum_B && blockIdx.x == 0;
+    float4 cs = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int kk = 8 * (l / 16);
+    for (int k0 = kb; k0 < ke; k0 += VK) {
+        __syncthreads();
+        ta.store(As, t);
+        tb.store(Bt, t);
+        if (csum) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                cs.x += tb.v[q].x;
+                cs.y += tb.v[q].y;
+                cs.z += tb.v[q].z;
+                cs.w += tb.v[q].w;
+            }
+        }
+        __syncthreads();
+        if (k0 + VK < ke) {              // next tile in flight during the products
+            ta.load(g.A, g.lda, m0, M, k0 + VK, ke, t);
+            tb.load(g.B, g.ldb, n0, g.N, k0 + VK, ke, t);
+        }
+#pragma unroll
+        for (int ks = 0; ks < VK; ks += 32) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[w * 16 + l % 16][ks + kk]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bt[j * 16 + l % 16][ks + kk]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    if (csum) {
+        // the 16 work-items of each column quad, added in a fixed order; the
+        // result goes after the pieces' products (split K) or to colsum_B
+        float* red = reinterpret_cast<float*>(&As[0][0]);     // 16 x 64 floats
+        __syncthreads();
+        *reinterpret_cast<float4*>(&red[(t / 16) * 64 + (t % 16) * 4]) = cs;
+        __syncthreads();
+        if (t < 64 && n0 + t < g.N) {
+            float v = 0.f;
+            for (int r = 0; r < 16; ++r) v += red[r * 64 + t];
+            if (part)
+                part[(size_t)gridDim.z * g.M * g.N + (size_t)blockIdx.z * g.N + n0 + t] = v;
+            else
+                g.colsum_B[n0 + t] = v;
+        }
+    }
+    if (part) {
+        float* P = part + (size_t)blockIdx.z * (size_t)g.M * g.N;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + j * 16 + l % 16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + w * 16 + 4 * (l / 16) + r;
+                if (row < M && col < g.N) P[(size_t)row * g.N + col] = acc[j][r];
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = n0 + j * 16 + l % 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = m0 + w * 16 + 4 * (l / 16) + r;
+            if (row >= M || col >= g.N) continue;
+            const float v = epilogue(g, row, col, acc[j][r]);
             float* c = g.C + (size_t)row * g.ldc + col;
             *c = g.accumulate ? *c + v : v;
         }
@@ -121,26 +319,29 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g, int pieces,
                                                      const float* __restrict__ part) {
     const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
     const size_t mn = (size_t)g.M * g.N;
-    if (e >= mn) return;
+    if (e >= mn) {
+        // column sums of B: the pieces' sums in piece order
+        if (!g.colsum_B || e >= mn + (size_t)g.N) return;
+        const size_t c = e - mn;
+        float v = 0.f;
+        for (int z = 0; z < pieces; ++z) v += part[(size_t)pieces * mn + (size_t)z * g.N + c];
+        g.colsum_B[c] = v;
+        return;
+    }
     const int row = (int)(e / g.N), col = (int)(e % g.N);
     float v = 0.f;
-    for (int z = 0; z < pieces; ++z) v += part[(size_t)z * mn + e];
-    if (g.bias) v += g.bias[col];
-    if (g.Z) g.Z[(size_t)row * g.ldz + col] = v;
-    if (g.act == 1) v = silu(v);
+    int z = 0;
+    for (; z + 8 <= pieces; z += 8) {       // eight loads in flight, summed in order
+        float p[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] = part[(size_t)(z + u) * mn + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += p[u];
+    }
+    for (; z < pieces; ++z) v += part[(size_t)z * mn + e];
+    v = epilogue(g, row, col, v);
     float* c = g.C + (size_t)row * g.ldc + col;
     *c = g.accumulate ? *c + v : v;
-}
-
-// dZ = dA * silu'(Z), elementwise over rows x cols (row strides ld).
-__global__ __launch_bounds__(256) void k_silu_bwd(const float* __restrict__ Z, float* dA, int rows,
-                                                  int cols, const int* rows_dev) {
-    const int R = rows_dev ? min(rows, *rows_dev) : rows;
-    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (size_t)R * cols) return;
-    const float z = Z[e];
-    const float s = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
-    dA[e] *= s * (1.0f + z * (1.0f - s));
 }
 
 // db[c] = sum_r dZ[r][c] (one workgroup per column, fixed order).
@@ -202,41 +403,61 @@ __global__ __launch_bounds__(256) void k_adam(float* w, const float* __restrict_
 
 }  // namespace
 
-hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
+namespace {
+bool aligned16(const float* p, int ld) {
+    return ((uintptr_t)p & 15u) == 0 && ld % 4 == 0;
+}
+
+bool vector_path(const GemmArgs& g) { return aligned16(g.A, g.lda) && aligned16(g.B, g.ldb); }
+
+void launch_tile_kernel(const GemmArgs& g, dim3 grid, int kpiece, float* part, hipStream_t s) {
+    if (!vector_path(g)) {
+        hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g, kpiece, part);
+        return;
+    }
+    if (g.transA) {
+        if (g.transB) hipLaunchKernelGGL((k_gemm_v<true, true>), grid, dim3(256), 0, s, g, kpiece, part);
+        else hipLaunchKernelGGL((k_gemm_v<true, false>), grid, dim3(256), 0, s, g, kpiece, part);
+    } else {
+        if (g.transB) hipLaunchKernelGGL((k_gemm_v<false, true>), grid, dim3(256), 0, s, g, kpiece, part);
+        else hipLaunchKernelGGL((k_gemm_v<false, false>), grid, dim3(256), 0, s, g, kpiece, part);
+    }
+}
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs& g0, hipStream_t s) {
+    GemmArgs g = g0;
+    // column sums of B inside the tile kernel only on its vector path with B
+    // untransposed; otherwise by the column-sum kernel afterwards
+    const bool side_colsum = g.colsum_B && (g.transB || !vector_path(g));
+    if (side_colsum) g.colsum_B = nullptr;
     dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN);
     const int tiles = (int)(grid.x * grid.y);
+    const size_t mn = (size_t)g.M * g.N;
+    const size_t per_piece = mn + (g.colsum_B ? (size_t)g.N : 0);
     // split K when C has too few tiles to fill the chip and K is long: pieces
-    // of at least 4 BK steps, about 1024 workgroups in all
+    // of at least two 64-deep stages, about 512 workgroups in all
     int pieces = 1;
-    if (g.work && !g.M_dev && tiles < 256 && g.K >= 8 * BK) {
-        pieces = std::min(std::max(1, 1024 / tiles), g.K / (4 * BK));
-        const size_t mn = (size_t)g.M * g.N;
-        pieces = (int)std::min<size_t>((size_t)pieces, g.work_floats / std::max<size_t>(mn, 1));
+    if (g.work && !g.M_dev && tiles < 256 && g.K >= 4 * VK) {
+        pieces = std::min(std::max(1, 512 / tiles), g.K / (2 * VK));
+        pieces = (int)std::min<size_t>((size_t)pieces, g.work_floats / std::max<size_t>(per_piece, 1));
     }
     if (pieces <= 1) {
-        hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g, 0, (float*)nullptr);
-        return hipGetLastError();
+        launch_tile_kernel(g, grid, 0, nullptr, s);
+    } else {
+        const int kpiece = ((g.K + pieces - 1) / pieces + VK - 1) / VK * VK;
+        pieces = (g.K + kpiece - 1) / kpiece;
+        grid.z = pieces;
+        launch_tile_kernel(g, grid, kpiece, g.work, s);
+        const size_t outs = mn + (g.colsum_B ? (size_t)g.N : 0);
+        hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s,
+                           g, pieces, (const float*)g.work);
     }
-    const int kpiece = ((g.K + pieces - 1) / pieces + BK - 1) / BK * BK;
-    pieces = (g.K + kpiece - 1) / kpiece;
-    grid.z = pieces;
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g, kpiece, g.work);
-    const size_t mn = (size_t)g.M * g.N;
-    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g,
-                       pieces, (const float*)g.work);
-    return hipGetLastError();
-}
-
-hipError_t launch_silu_bwd(const float* Z, float* dA, int rows, int cols, const int* rows_dev,
-                           hipStream_t s) {
-    const size_t n = (size_t)rows * cols;
-    hipLaunchKernelGGL(k_silu_bwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Z, dA,
-                       rows, cols, rows_dev);
-    return hipGetLastError();
-}
-
-hipError_t launch_colsum(const float* dZ, int rows, int cols, float* db, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsum, dim3(cols), dim3(256), 0, s, dZ, rows, cols, db);
+    if (side_colsum) {
+        if (g.transB || g.ldb != g.N)    // the column-sum kernel reads packed rows
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_colsum, dim3(g.N), dim3(256), 0, s, g.B, g.K, g.N, g0.colsum_B);
+    }
     return hipGetLastError();
 }
 

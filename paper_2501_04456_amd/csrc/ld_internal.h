@@ -374,6 +374,9 @@ struct ld_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
+    // what each timed (start, end) event pair brackets: kTimedCoulomb or
+    // kTimedNear
+    std::vector<unsigned char> ev_kind;
 
     // captured step chunk (HIP graph)
     hipStream_t cap_stream = nullptr;
@@ -393,6 +396,11 @@ struct ld_ctx {
 };
 
 namespace ld {
+constexpr unsigned char kTimedCoulomb = 0;   // the all-pairs Coulomb kernel
+constexpr unsigned char kTimedNear = 1;      // the learned path's near-field kernels
+// A (start, end) pair of timing events from the context's pool, recorded as
+// bracketing `kind`; false when no event could be created.
+bool timing_events(ld_ctx* c, unsigned char kind, hipEvent_t* e0, hipEvent_t* e1);
 // Learned far field hooks used by the step loop (defined in ld_ff.hip).
 void ff_free(ld_ctx* c);
 bool ff_active(const ld_ctx* c);

@@ -104,7 +104,8 @@ SYMBOLS = [
     "ld_init", "ld_destroy", "ld_last_error", "ld_forces", "ld_step", "ld_sync",
     "ld_get_positions", "ld_get_state", "ld_set_params", "ld_diagnostics", "ld_rdf",
     "ld_fractal", "ld_get_tuning", "ld_set_tuning", "ld_kernel_timing", "ld_kernel_time",
-    "ld_autotune", "ld_checkpoint_save", "ld_checkpoint_load", "ld_set_positions",
+    "ld_near_kernel_time", "ld_autotune", "ld_checkpoint_save", "ld_checkpoint_load",
+    "ld_set_positions",
     "ld_ff_enable", "ld_ff_mode", "ld_ff_weights_size", "ld_ff_set_weights", "ld_ff_get_weights",
     "ld_ff_grid", "ld_ff_forces", "ld_ff_mlp", "ld_ff_grads", "ld_ff_collect", "ld_ff_train",
     "ld_ff_judge", "ld_ff_stats",
@@ -153,6 +154,7 @@ def lib():
         L.ld_set_tuning.argtypes = [vp, C.POINTER(ld_tuning)]
         L.ld_kernel_timing.argtypes = [vp, C.c_int32]
         L.ld_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.ld_near_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.ld_autotune.argtypes = [vp, C.c_char_p, C.c_int32, C.POINTER(ld_tuning)]
         L.ld_checkpoint_save.argtypes = [vp, C.c_char_p]
         L.ld_checkpoint_load.argtypes = [C.POINTER(C.c_void_p), C.c_char_p, vp]
@@ -641,6 +643,11 @@ class System:
     def kernel_time(self):
         n, ms = C.c_int64(), C.c_double()
         _check(lib().ld_kernel_time(self.h, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def near_kernel_time(self):
+        n, ms = C.c_int64(), C.c_double()
+        _check(lib().ld_near_kernel_time(self.h, C.byref(n), C.byref(ms)))
         return n.value, ms.value
 
     dt = 1e-3
