@@ -17,8 +17,11 @@
 // flag.  The pair kernel then treats a pair of tiles like the single-droplet
 // kernel treats a pair of groups: careful loop when the boxes come within the
 // largest LJ range, Coulomb-only loop when they do not, nothing when one
-// side is uncharged.  Outputs are mapped back to the original order through
-// the per-droplet index, which travels with the particle.
+// side is uncharged.  In the careful loop both sides' positions are taken
+// relative to the centre of the i tile's box, (hi - c) + lo rounded to FP32,
+// so a pair difference carries the rounding of a coordinate tens of sigma
+// from c rather than of |x|.  Outputs are mapped back to the original order
+// through the per-droplet index, which travels with the particle.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -53,7 +56,6 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
     const Box* __restrict__ box, const int* __restrict__ tbase, double* __restrict__ F,
     int total, unsigned* __restrict__ nearbits, int nb_words) {
     __shared__ float4 sp[kWaves][kGroup];
-    __shared__ float4 sl[kWaves][kGroup];
     const int w = threadIdx.x / kGroup;
     const int lane = threadIdx.x % kGroup;
     for (;;) {
@@ -73,9 +75,19 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
         pair::Acc a;
         Box bi;
         const int t0 = tbase[d];
+        // origin of the near tiles' positions: the centre of the tile's box,
+        // else its first particle
+        float4 c = make_float4(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.x))),
+                               __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.y))),
+                               __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.z))),
+                               0.f);
         if constexpr (CULL) {
             bi = box[t0 + it.y / kGroup];
+            c = make_float4(0.5f * (bi.lo.x + bi.hi.x), 0.5f * (bi.lo.y + bi.hi.y),
+                            0.5f * (bi.lo.z + bi.hi.z), 0.f);
         }
+        const float4 pr = make_float4((pi.x - c.x) + li.x, (pi.y - c.y) + li.y,
+                                      (pi.z - c.z) + li.z, pi.w);
         const float cull2 = rc2max * 1.0001f;
         for (int jt = 0; jt < nd; jt += kGroup) {
             bool near = true;
@@ -89,12 +101,16 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
             }
             wave_sync();
             const int j = jt + lane;
-            sp[w][lane] = j < nd ? pos[o + j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
-            if (near) sl[w][lane] = j < nd ? lo[o + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            float4 pj = j < nd ? pos[o + j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+            if (near && j < nd) {              // near tiles: relative to c, low words in
+                const float4 lj = lo[o + j];
+                pj = make_float4((pj.x - c.x) + lj.x, (pj.y - c.y) + lj.y, (pj.z - c.z) + lj.z,
+                                 pj.w);
+            }
+            sp[w][lane] = pj;
             wave_sync();
             if (near) {
-                const bool lj = pair::group_near<COMP, false>(sp[w], sl[w], jt, i, pi, li,
-                                                              cull2, a);
+                const bool lj = pair::group_near_rel<COMP>(sp[w], jt, i, pr, cull2, a);
                 // tile pairs with a Lennard-Jones candidate, for k_ens_lj
                 if (__ballot(lj && live) && lane == 0) {
                     const int gj = jt / kGroup;

@@ -458,11 +458,15 @@ __global__ __launch_bounds__(1024) void k_block_tiles(const int* __restrict__ cf
 //
 // FP32 pair terms (Coulomb and LJ apart) in blocks of at most 32, FP64 totals.
 //
-// The two walks are separate instances (LANE), both launched on the same
-// grid; the one that does not match the grid's W leaves at once.  Compiled
-// together the row walk's registers made the lane walk spill to scratch at
-// 6 wavefronts per SIMD; apart, the lane walk needs no scratch.
+// The two walks are separate kernels, both launched on the same grid of
+// tiles; the one that does not match the grid's W leaves at once.  The lane
+// walk (k_near_planes) gives each plane dz of the block a wavefront of its
+// own, B wavefronts per tile whose FP64 sums are added in plane order: a
+// tile's 25 rows on one wavefront left about four wavefronts per SIMD for
+// the whole launch, too few to hide the row loads.  Kept apart, neither
+// kernel spills registers to scratch at 6 wavefronts per SIMD.
 constexpr int kNbChunk = 192;          // staged slots per piece of a row's range
+constexpr int kNbMaxPlanes = 7;        // B <= 7
 
 struct NbAcc {
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, Lx = 0.0, Ly = 0.0, Lz = 0.0;
@@ -525,7 +529,119 @@ __device__ __forceinline__ void nb_range(const float4* sp, const int* st, int lo
     }
 }
 
-template <bool LANE>
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane windows (W = B/2): workgroup of B wavefronts per row tile, wavefront
+// p walks the B rows of plane dz = p - B/2 through its own LDS slice; the
+// slices hold the plane sums at the end.
+__global__ __launch_bounds__(64 * kNbMaxPlanes, 6) void k_near_planes(
+    const float4* __restrict__ pos, const int* __restrict__ typ,
+    const unsigned long long* __restrict__ keys, const FFGrid* g, int G, int half,
+    const int* __restrict__ cfirst, const int4* __restrict__ tiles,
+    const int* __restrict__ ntiles, int n, PairTable tab, double* F) {
+    __shared__ float4 sp_all[kNbMaxPlanes][kNbChunk];   // reused for the plane sums
+    __shared__ int st_all[kNbMaxPlanes][kNbChunk];
+    __shared__ float ttab[3 * kMaxTypes * kMaxTypes];
+    const int lane = threadIdx.x % 64;
+    const int p = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));   // wave-uniform
+    const int planes = 2 * half + 1;
+    if ((int)blockIdx.x >= *ntiles) return;            // uniform per workgroup
+    if (g->W != half) return;                          // the row walk's grid
+    float4* sp = sp_all[p];
+    int* st = st_all[p];
+    for (int k = threadIdx.x; k < kMaxTypes * kMaxTypes; k += blockDim.x) {
+        ttab[k] = tab.sig2[k];
+        ttab[kMaxTypes * kMaxTypes + k] = tab.rc2[k];
+        ttab[2 * kMaxTypes * kMaxTypes + k] = tab.e24[k];
+    }
+    __syncthreads();
+    const int4 tl = tiles[blockIdx.x];
+    const int row = tl.x, s0 = tl.y, s1 = tl.z;
+    const int i = s0 + lane;
+    const bool live = i < s1;
+    const float4 pi = live ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int ti = live ? typ[i] : 0;
+    const int ix = (int)((unsigned)((live ? keys[i] : keys[s0]) >> 32) % (unsigned)G);
+    const int x_first = (int)((unsigned)(keys[s0] >> 32) % (unsigned)G);
+    const int x_last = (int)((unsigned)(keys[s1 - 1] >> 32) % (unsigned)G);
+    const int ry = row % G, rz = row / G;
+    const int T = tab.T;
+    const float rc2max = tab.rc2max;
+    const int wlj = g->Wlj;
+    const int trow = ti * T;
+    NbAcc a;
+    const int dz = p - half;
+    const int z = rz + dz;
+    if (z >= 0 && z < G) {
+        for (int dy = -half; dy <= half; ++dy) {
+            const int y = ry + dy;
+            if (y < 0 || y >= G) continue;
+            const int base = (z * G + y) * G;
+            const int J0 = cfirst[base + max(0, x_first - half)];
+            const int J1 = cfirst[base + min(G - 1, x_last + half) + 1];
+            int ja = J0, jb = J0;
+            if (live) {
+                ja = cfirst[base + max(0, ix - half)];
+                jb = cfirst[base + min(G - 1, ix + half) + 1];
+            }
+            const bool lj = abs(dy) <= wlj && abs(dz) <= wlj;
+            const bool own = dy == 0 && dz == 0;
+            for (int c0 = J0; c0 < J1; c0 += kNbChunk) {
+                const int S = min(kNbChunk, J1 - c0);
+                wave_sync_lds();
+                for (int t = lane; t < S; t += 64) {
+                    sp[t] = pos[c0 + t];
+                    st[t] = typ[c0 + t];
+                }
+                wave_sync_lds();
+                const int lo = min(max(ja - c0, 0), S), hi = min(max(jb - c0, 0), S);
+                int m1 = hi, m2 = hi;                // [lo, m1) and [m2, hi): i skipped
+                const int si = i - c0;
+                if (own && si >= lo && si < hi) {
+                    m1 = si;
+                    m2 = si + 1;
+                }
+                if (lj) {
+                    nb_range<true>(sp, st, lo, m1, pi, trow, ttab, rc2max, a);
+                    nb_range<true>(sp, st, m2, hi, pi, trow, ttab, rc2max, a);
+                } else {
+                    nb_range<false>(sp, st, lo, m1, pi, trow, ttab, rc2max, a);
+                    nb_range<false>(sp, st, m2, hi, pi, trow, ttab, rc2max, a);
+                }
+            }
+        }
+    }
+    // plane sums, added in plane order (the slices are free after this barrier)
+    __syncthreads();
+    static_assert(sizeof(sp_all) >= kNbMaxPlanes * 6 * 64 * sizeof(double), "plane sums");
+    double* red = reinterpret_cast<double*>(&sp_all[0][0]);   // [planes][6][64]
+    double* r = red + (size_t)p * 6 * 64 + lane;
+    r[0] = a.Fx;
+    r[64] = a.Fy;
+    r[128] = a.Fz;
+    r[192] = a.Lx;
+    r[256] = a.Ly;
+    r[320] = a.Lz;
+    __syncthreads();
+    if (p != 0 || !live) return;
+    const double qi = (double)pi.w;
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        double fc = 0.0, lc = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < planes; ++q) {
+            fc += red[(size_t)q * 6 * 64 + c * 64 + lane];
+            lc += red[(size_t)q * 6 * 64 + (c + 3) * 64 + lane];
+        }
+        F[(size_t)c * n + i] = -qi * fc - lc;
+    }
+}
+
+// Row windows (W > B/2): one wavefront per row tile.
 __global__ __launch_bounds__(64, 6) void k_near_block(const float4* __restrict__ pos,
                                                    const int* __restrict__ typ,
                                                    const unsigned long long* __restrict__ keys,
@@ -540,7 +656,7 @@ __global__ __launch_bounds__(64, 6) void k_near_block(const float4* __restrict__
     const int lane = threadIdx.x;
     if ((int)blockIdx.x >= *ntiles) return;            // uniform per workgroup
     const int W = g->W;
-    if ((W == half) != LANE) return;                   // the other walk's grid
+    if (W == half) return;                             // the lane walk's grid
     for (int k = lane; k < kMaxTypes * kMaxTypes; k += 64) {
         ttab[k] = tab.sig2[k];
         ttab[kMaxTypes * kMaxTypes + k] = tab.rc2[k];
@@ -559,51 +675,7 @@ __global__ __launch_bounds__(64, 6) void k_near_block(const float4* __restrict__
     const int T = tab.T;
     const float rc2max = tab.rc2max;
     NbAcc a;
-    if constexpr (LANE) {
-        const int wlj = g->Wlj;
-        const int trow = ti * T;
-        for (int dz = -half; dz <= half; ++dz) {
-            const int z = rz + dz;
-            if (z < 0 || z >= G) continue;
-            for (int dy = -half; dy <= half; ++dy) {
-                const int y = ry + dy;
-                if (y < 0 || y >= G) continue;
-                const int base = (z * G + y) * G;
-                const int J0 = cfirst[base + max(0, x_first - half)];
-                const int J1 = cfirst[base + min(G - 1, x_last + half) + 1];
-                int ja = J0, jb = J0;
-                if (live) {
-                    ja = cfirst[base + max(0, ix - half)];
-                    jb = cfirst[base + min(G - 1, ix + half) + 1];
-                }
-                const bool lj = abs(dy) <= wlj && abs(dz) <= wlj;
-                const bool own = dy == 0 && dz == 0;
-                for (int c0 = J0; c0 < J1; c0 += kNbChunk) {
-                    const int S = min(kNbChunk, J1 - c0);
-                    __syncthreads();
-                    for (int t = lane; t < S; t += 64) {
-                        sp[t] = pos[c0 + t];
-                        st[t] = typ[c0 + t];
-                    }
-                    __syncthreads();
-                    const int lo = min(max(ja - c0, 0), S), hi = min(max(jb - c0, 0), S);
-                    int m1 = hi, m2 = hi;                // [lo, m1) and [m2, hi): i skipped
-                    const int si = i - c0;
-                    if (own && si >= lo && si < hi) {
-                        m1 = si;
-                        m2 = si + 1;
-                    }
-                    if (lj) {
-                        nb_range<true>(sp, st, lo, m1, pi, trow, ttab, rc2max, a);
-                        nb_range<true>(sp, st, m2, hi, pi, trow, ttab, rc2max, a);
-                    } else {
-                        nb_range<false>(sp, st, lo, m1, pi, trow, ttab, rc2max, a);
-                        nb_range<false>(sp, st, m2, hi, pi, trow, ttab, rc2max, a);
-                    }
-                }
-            }
-        }
-    } else {
+    {
         for (int dz = -W; dz <= W; ++dz) {
             const int z = rz + dz;
             if (z < 0 || z >= G) continue;
@@ -1764,9 +1836,12 @@ ld_status ff_near(ld_ctx* c, hipStream_t s) {
         KLAUNCH(k_cell_first, dim3((n + kB - 1) / kB), dim3(kB), s, c->sb.keys, n, M, f->cfirst);
         KLAUNCH(k_block_tiles, dim3(1), dim3(1024), s, f->cfirst, G, f->tiles, f->ntiles);
         if (e0) HIP_TRY(hipEventRecord(e0, s));
-        KLAUNCH(k_near_block<true>, dim3(f->max_tiles), dim3(64), s, c->pos, c->typ, c->sb.keys,
-                f->grid, G, f->cfg.block / 2, f->cfirst, f->tiles, f->ntiles, n, c->tab, f->Fnear);
-        KLAUNCH(k_near_block<false>, dim3(f->max_tiles), dim3(64), s, c->pos, c->typ, c->sb.keys,
+        // both walks on the same grid of tiles; the one that does not match
+        // the grid's W (known on the device only) leaves at once
+        KLAUNCH(k_near_planes, dim3(f->max_tiles), dim3(64 * f->cfg.block), s, c->pos, c->typ,
+                c->sb.keys, f->grid, G, f->cfg.block / 2, f->cfirst, f->tiles, f->ntiles, n,
+                c->tab, f->Fnear);
+        KLAUNCH(k_near_block, dim3(f->max_tiles), dim3(64), s, c->pos, c->typ, c->sb.keys,
                 f->grid, G, f->cfg.block / 2, f->cfirst, f->tiles, f->ntiles, n, c->tab, f->Fnear);
         if (e1) HIP_TRY(hipEventRecord(e1, s));
     } else {

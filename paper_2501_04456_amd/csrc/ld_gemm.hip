@@ -17,10 +17,10 @@
 //
 // k_gemm_v is the same tiling for operands whose rows are 16-byte aligned
 // (every product of the far-field network): K advances 64 at a time, each
-// work-item fetches its share of the next A and B tiles as four 16-byte
-// loads each while the matrix cores work on the current tile (register
-// double buffering), and the tiles are written to LDS as BF16, transposed on
-// the way where K is the operand's strided index.  k_gemm is the general
+// work-item fetches its share of an A and a B tile as four 16-byte loads
+// each, two stages ahead of the matrix cores (a ring of two register sets),
+// and the tiles are written to LDS as BF16, transposed on the way where K is
+// the operand's strided index.  k_gemm is the general
 // fallback (any alignment).
 #include <algorithm>
 
@@ -234,40 +234,52 @@ __global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g, int kpiece, float* p
     const int t = threadIdx.x, w = t / 64, l = t % 64;
     f32x4 acc[4];
     for (int j = 0; j < 4; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    Tile<!TA> ta;          // A is k-contiguous unless transposed
-    Tile<TB> tb;           // B (K x N) is k-contiguous only when transposed
-    ta.load(g.A, g.lda, m0, M, kb, ke, t);
-    tb.load(g.B, g.ldb, n0, g.N, kb, ke, t);
+    // two tiles in flight: while the matrix cores work on stage k, the loads
+    // of stages k + 1 and k + 2 are outstanding (a ring of two register sets)
+    Tile<!TA> ta[2];       // A is k-contiguous unless transposed
+    Tile<TB> tb[2];        // B (K x N) is k-contiguous only when transposed
+    ta[0].load(g.A, g.lda, m0, M, kb, ke, t);
+    tb[0].load(g.B, g.ldb, n0, g.N, kb, ke, t);
+    if (kb + VK < ke) {
+        ta[1].load(g.A, g.lda, m0, M, kb + VK, ke, t);
+        tb[1].load(g.B, g.ldb, n0, g.N, kb + VK, ke, t);
+    }
     // column sums of B (FP32, before rounding): the first row of tiles only;
     // this work-item's values all lie in columns n0 + 4 (t % 16) + 0..3
     const bool csum = !TB && g.colsum_B && blockIdx.x == 0;
     float4 cs = make_float4(0.f, 0.f, 0.f, 0.f);
     const int kk = 8 * (l / 16);
-    for (int k0 = kb; k0 < ke; k0 += VK) {
-        __syncthreads();
-        ta.store(As, t);
-        tb.store(Bt, t);
-        if (csum) {
+    for (int k0 = kb; k0 < ke; k0 += 2 * VK) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                cs.x += tb.v[q].x;
-                cs.y += tb.v[q].y;
-                cs.z += tb.v[q].z;
-                cs.w += tb.v[q].w;
+        for (int r = 0; r < 2; ++r) {
+            const int ks0 = k0 + r * VK;
+            if (ks0 >= ke) break;
+            __syncthreads();
+            ta[r].store(As, t);
+            tb[r].store(Bt, t);
+            if (csum) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    cs.x += tb[r].v[q].x;
+                    cs.y += tb[r].v[q].y;
+                    cs.z += tb[r].v[q].z;
+                    cs.w += tb[r].v[q].w;
+                }
             }
-        }
-        __syncthreads();
-        if (k0 + VK < ke) {              // next tile in flight during the products
-            ta.load(g.A, g.lda, m0, M, k0 + VK, ke, t);
-            tb.load(g.B, g.ldb, n0, g.N, k0 + VK, ke, t);
-        }
+            __syncthreads();
+            if (ks0 + 2 * VK < ke) {         // refill this set two stages ahead
+                ta[r].load(g.A, g.lda, m0, M, ks0 + 2 * VK, ke, t);
+                tb[r].load(g.B, g.ldb, n0, g.N, ks0 + 2 * VK, ke, t);
+            }
 #pragma unroll
-        for (int ks = 0; ks < VK; ks += 32) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[w * 16 + l % 16][ks + kk]);
+            for (int ks = 0; ks < VK; ks += 32) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[w * 16 + l % 16][ks + kk]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bt[j * 16 + l % 16][ks + kk]);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+                for (int j = 0; j < 4; ++j) {
+                    const bf16x8 b =
+                        *reinterpret_cast<const bf16x8*>(&Bt[j * 16 + l % 16][ks + kk]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+                }
             }
         }
     }
@@ -314,34 +326,52 @@ __global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g, int kpiece, float* p
     }
 }
 
-// Split-K epilogue: the pieces summed in order, then as k_gemm's epilogue.
+// Split-K epilogue.  A workgroup owns 32 outputs; its eight groups of 32
+// work-items each add one eighth of the pieces (all of their loads in flight
+// at once), and the eight group sums are added in group order: a fixed
+// summation order, whatever the timing.  Outputs mn .. mn + N - 1 are the
+// column sums of B (the pieces' column sums follow their products in part).
+constexpr int kRedOut = 32, kRedGroups = 8;
+
 __global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g, int pieces,
                                                      const float* __restrict__ part) {
-    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ float red[kRedGroups][kRedOut];
+    const int el = threadIdx.x % kRedOut, grp = threadIdx.x / kRedOut;
+    const size_t e = (size_t)blockIdx.x * kRedOut + el;
     const size_t mn = (size_t)g.M * g.N;
+    const size_t outs = mn + (g.colsum_B ? (size_t)g.N : 0);
+    const bool live = e < outs;
+    // piece z of output e sits at src[z * stride]
+    const float* src = e < mn ? part + e : part + (size_t)pieces * mn + (e - mn);
+    const size_t stride = e < mn ? mn : (size_t)g.N;
+    const int per = (pieces + kRedGroups - 1) / kRedGroups;
+    const int z0 = grp * per, z1 = min(pieces, z0 + per);
+    float v = 0.f;
+    if (live) {
+        int z = z0;
+        for (; z + 8 <= z1; z += 8) {
+            float p[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) p[u] = src[(size_t)(z + u) * stride];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v += p[u];
+        }
+        for (; z < z1; ++z) v += src[(size_t)z * stride];
+    }
+    red[grp][el] = v;
+    __syncthreads();
+    if (grp != 0 || !live) return;
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < kRedGroups; ++q) t += red[q][el];
     if (e >= mn) {
-        // column sums of B: the pieces' sums in piece order
-        if (!g.colsum_B || e >= mn + (size_t)g.N) return;
-        const size_t c = e - mn;
-        float v = 0.f;
-        for (int z = 0; z < pieces; ++z) v += part[(size_t)pieces * mn + (size_t)z * g.N + c];
-        g.colsum_B[c] = v;
+        g.colsum_B[e - mn] = t;
         return;
     }
     const int row = (int)(e / g.N), col = (int)(e % g.N);
-    float v = 0.f;
-    int z = 0;
-    for (; z + 8 <= pieces; z += 8) {       // eight loads in flight, summed in order
-        float p[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) p[u] = part[(size_t)(z + u) * mn + e];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v += p[u];
-    }
-    for (; z < pieces; ++z) v += part[(size_t)z * mn + e];
-    v = epilogue(g, row, col, v);
+    t = epilogue(g, row, col, t);
     float* c = g.C + (size_t)row * g.ldc + col;
-    *c = g.accumulate ? *c + v : v;
+    *c = g.accumulate ? *c + t : t;
 }
 
 // db[c] = sum_r dZ[r][c] (one workgroup per column, fixed order).
@@ -450,8 +480,8 @@ hipError_t launch_gemm(const GemmArgs& g0, hipStream_t s) {
         grid.z = pieces;
         launch_tile_kernel(g, grid, kpiece, g.work, s);
         const size_t outs = mn + (g.colsum_B ? (size_t)g.N : 0);
-        hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s,
-                           g, pieces, (const float*)g.work);
+        hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((outs + kRedOut - 1) / kRedOut)),
+                           dim3(kRedOut * kRedGroups), 0, s, g, pieces, (const float*)g.work);
     }
     if (side_colsum) {
         if (g.transB || g.ldb != g.N)    // the column-sum kernel reads packed rows

@@ -8,9 +8,11 @@ Tolerances (FP32 pair math with FP64 totals):
 * positions: max |dx| <= 1e-4 sigma after 100 steps (small system) or 20
   steps (large composition), same Philox stream;
 * integer outputs (RDF counts, box counts): exact.
-Particles with an LJ partner within 1e-5 (relative) of the cutoff are left
-out of force comparisons: FP32 and FP64 may legitimately disagree on which
-side of the cutoff such a pair is.
+Particles with an LJ partner within 1e-9 (relative) of the cutoff are left
+out of force comparisons.  The library decides the cutoff in FP64 from
+positions held as (hi, lo) FP32 pairs (48 significant bits), so a pair that
+close to the cutoff may fall on the other side of it from the oracle's
+53-bit positions.
 """
 import math
 
@@ -42,7 +44,7 @@ def orc():
     return oracle
 
 
-def ambiguous_rows(w, rows=None, rel=1e-5):
+def ambiguous_rows(w, rows=None, rel=1e-9):
     """Rows with an LJ pair within `rel` of its cutoff."""
     from scipy.spatial import cKDTree
     x = w.pos.astype(np.float64)
