@@ -492,10 +492,11 @@ def learned_run(a, torch, ldrop, W, steps=None):
     judge_stats = ev.ff_stats()
     pairs = float(we.n) * (we.n - 1)
     # matrix-core work of training: per sample, forward 2 (Kp H + H H + H Op)
-    # flops and backward twice that (input and weight gradients)
+    # flops, the weight gradients as much again, and the input gradients of
+    # layers 2 and 3 2 (H H + H Op) (layer 1's inputs need none)
     K = 4 * 5 ** 3 + 3
     Kp, H, Op = (K + 31) // 32 * 32, 128, 16
-    train_flops = 3.0 * 2.0 * (Kp * H + H * H + H * Op) * 8192 * rep["iterations"]
+    train_flops = 2.0 * (2 * (Kp * H + H * H + H * Op) + H * H + H * Op) * 8192 * rep["iterations"]
     return {
         "metric": "learned vs direct steps/s at N=2.5e5 and median force error",
         "value": 1e3 / ms_learned, "unit": "steps/s",

@@ -41,9 +41,6 @@ using namespace pair;
 #ifndef LD_PAIR_MIN_WAVES
 #define LD_PAIR_MIN_WAVES 6
 #endif
-#ifndef LD_PAIR_SCALAR_FAR
-#define LD_PAIR_SCALAR_FAR 0
-#endif
 
 template <int BLOCK, int COMP, bool DIAG, bool CULL>
 __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_pair(const float4* __restrict__ pos,
@@ -114,12 +111,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
                     atomicOr(&nearbits[(size_t)gi * nb_words + (gj >> 5)], 1u << (gj & 31));
                 }
             } else {
-#if LD_PAIR_SCALAR_FAR
-                if (jg + kGroup <= j1)
-                    group_far<COMP>(pos + jg, pi, a);
-                else
-#endif
-                    group_far<COMP>(sp + g * kGroup, pi, a);
+                group_far<COMP>(sp + g * kGroup, pi, a);
             }
         }
     }

@@ -114,36 +114,6 @@ __device__ __forceinline__ bool group_near(const float4* __restrict__ sp,
     return lj_any;
 }
 
-// As group_near, for positions already taken relative to an origin c near
-// both groups (the ensemble kernel uses the i tile's box centre): each
-// staged j and the lane's own i hold (hi - c) + lo rounded to FP32, so the
-// difference carries the rounding of |x - c| (tens of sigma inside one
-// droplet) instead of |x|, with one LDS read and three subtractions per pair.
-template <int COMP>
-__device__ __forceinline__ bool group_near_rel(const float4* __restrict__ sr, int jbase, int i,
-                                               const float4 ri4, float lj2, Acc& a) {
-    bool lj_any = false;
-#pragma unroll
-    for (int kb = 0; kb < kGroup; kb += KB) {
-        float bx = 0.f, by = 0.f, bz = 0.f;   // Coulomb, FP32 block
-#pragma unroll 4
-        for (int k = 0; k < KB; ++k) {
-            const float4 pj = sr[kb + k];
-            const float dx = pj.x - ri4.x, dy = pj.y - ri4.y, dz = pj.z - ri4.z;
-            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float ri = __builtin_amdgcn_rsqf(r2);
-            const bool self = jbase + kb + k == i;
-            const float w = self ? 0.f : (pj.w * ri) * (ri * ri);
-            lj_any |= r2 < lj2 && !self;
-            bx = fmaf(w, dx, bx);
-            by = fmaf(w, dy, by);
-            bz = fmaf(w, dz, bz);
-        }
-        flush<COMP>(a, bx, by, bz);
-    }
-    return lj_any;
-}
-
 // One Lennard-Jones pair (section 2.1: truncated at lj_cut sigma_ij, not
 // shifted) in FP64 from the exact difference of the (hi, lo) positions, if
 // it is within the cutoff.  t64: sigma_ij^2, 24 eps_ij, 4 eps_ij and
