@@ -781,7 +781,8 @@ def main():
         r = learned_run(a, torch, ldrop, W, steps=a.learned_steps)
         out["learned_vs_direct"] = {
             k: r[k] for k in ("value", "direct_steps_per_s", "speedup", "median_rel_force_err",
-                              "mlp_gain", "judge", "judge_tol", "steps", "config")}
+                              "mlp_gain", "judge", "judge_tol", "steps", "config",
+                              "near_roofline")}
         out["learned_vs_direct"]["unit"] = "steps/s"
         out["learned_vs_direct"]["note"] = (
             "timed path: exact near part over the 5^3 block of grid cells + the FFT local "
