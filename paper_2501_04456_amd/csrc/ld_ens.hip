@@ -49,36 +49,6 @@ __device__ __forceinline__ void wave_sync() {
 
 __global__ void k_ens_reset(unsigned* counter) { *counter = 0u; }
 
-// As pair::group_near, for positions already taken relative to an origin c
-// near both tiles (the centre of the i tile's box): each staged j and the
-// lane's own i hold (hi - c) + lo rounded to FP32, so the difference carries
-// the rounding of |x - c| (tens of sigma inside one droplet) instead of |x|,
-// with one LDS read and three subtractions per pair.
-template <int COMP>
-__device__ __forceinline__ bool group_near_rel(const float4* __restrict__ sr, int jbase, int i,
-                                               const float4 ri4, float lj2, pair::Acc& a) {
-    bool lj_any = false;
-#pragma unroll
-    for (int kb = 0; kb < kGroup; kb += pair::KB) {
-        float bx = 0.f, by = 0.f, bz = 0.f;   // Coulomb, FP32 block
-#pragma unroll 4
-        for (int k = 0; k < pair::KB; ++k) {
-            const float4 pj = sr[kb + k];
-            const float dx = pj.x - ri4.x, dy = pj.y - ri4.y, dz = pj.z - ri4.z;
-            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float ri = __builtin_amdgcn_rsqf(r2);
-            const bool self = jbase + kb + k == i;
-            const float w = self ? 0.f : (pj.w * ri) * (ri * ri);
-            lj_any |= r2 < lj2 && !self;
-            bx = fmaf(w, dx, bx);
-            by = fmaf(w, dy, by);
-            bz = fmaf(w, dz, bz);
-        }
-        pair::flush<COMP>(a, bx, by, bz);
-    }
-    return lj_any;
-}
-
 template <int COMP, bool CULL, int UNROLL>
 __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
     const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
@@ -140,7 +110,7 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
             sp[w][lane] = pj;
             wave_sync();
             if (near) {
-                const bool lj = group_near_rel<COMP>(sp[w], jt, i, pr, cull2, a);
+                const bool lj = pair::group_near_rel<COMP, false>(sp[w], jt, i, pr, cull2, a);
                 // tile pairs with a Lennard-Jones candidate, for k_ens_lj
                 if (__ballot(lj && live) && lane == 0) {
                     const int gj = jt / kGroup;

@@ -11,9 +11,11 @@
 // multiplications, three fma into the block accumulators).  With tile
 // culling on, a 64-particle j group whose bounding box is farther than the
 // largest LJ range from the wavefront's own box takes the plain loop on the
-// FP32 high words; a nearer group takes the loop that adds the low words to
-// the differences; a far pair of groups one of which is uncharged is
-// skipped (no force at all).
+// FP32 high words; a nearer group takes the loop on positions relative to
+// the centre c of the workgroup's box, (hi - c) + lo, staged beside the high
+// words (same instruction count, and the rounding of |x - c| instead of
+// |x|), which also leaves out the self pair and flags LJ candidates; a far
+// pair of groups one of which is uncharged is skipped (no force at all).
 //
 // k_lj: the Lennard-Jones sum, which is short-ranged (lj_cut sigma_ij): one
 // workgroup per 64-slot i group visits the j groups that k_pair found to
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
                                                 double* __restrict__ U_out,
                                                 unsigned* __restrict__ nearbits, int nb_words) {
     __shared__ float4 sp[BLOCK];
-    __shared__ float4 sl[BLOCK];             // low words (read by the near loop only)
+    __shared__ float4 sr[BLOCK];             // positions relative to c (near loop only)
 
     const int tid = threadIdx.x;
     const int i = blockIdx.x * BLOCK + tid;
@@ -74,6 +76,24 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
     }
     // A small margin covers FP32 rounding of box distances against r^2.
     const float cull2 = rc2max * 1.0001f;
+    // Origin of the near loop's positions: the centre of the box of the
+    // workgroup's BLOCK slots (culling), else its first particle.
+    float4 c = pos[blockIdx.x * BLOCK];
+    if constexpr (CULL) {
+        float3 blo = make_float3(INFINITY, INFINITY, INFINITY);
+        float3 bhi = make_float3(-INFINITY, -INFINITY, -INFINITY);
+        for (int q = 0; q < BLOCK / kGroup; ++q) {
+            const int gq = blockIdx.x * (BLOCK / kGroup) + q;
+            if (gq >= ngroups) break;
+            const Box bq = box[gq];
+            blo = make_float3(fminf(blo.x, bq.lo.x), fminf(blo.y, bq.lo.y), fminf(blo.z, bq.lo.z));
+            bhi = make_float3(fmaxf(bhi.x, bq.hi.x), fmaxf(bhi.y, bq.hi.y), fmaxf(bhi.z, bq.hi.z));
+        }
+        c = make_float4(0.5f * (blo.x + bhi.x), 0.5f * (blo.y + bhi.y), 0.5f * (blo.z + bhi.z),
+                        0.f);
+    }
+    const float4 pr = make_float4((pi.x - c.x) + li.x, (pi.y - c.y) + li.y, (pi.z - c.z) + li.z,
+                                  pi.w);
 
     const int j0 = blockIdx.y * j_per_split;
     const int j1 = min(n, j0 + j_per_split);
@@ -82,8 +102,16 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
     for (int jt = j0; jt < j1; jt += BLOCK) {
         __syncthreads();
         const int j = jt + tid;
-        sp[tid] = j < j1 ? pos[j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
-        sl[tid] = j < j1 ? lo[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        {
+            float4 h = make_float4(kFarAway, kFarAway, kFarAway, 0.f), r = h;
+            if (j < j1) {
+                h = pos[j];
+                const float4 l = lo[j];
+                r = make_float4((h.x - c.x) + l.x, (h.y - c.y) + l.y, (h.z - c.z) + l.z, h.w);
+            }
+            sp[tid] = h;
+            sr[tid] = r;
+        }
         __syncthreads();
 #pragma unroll 1
         for (int g = 0; g < BLOCK / kGroup; ++g) {
@@ -102,8 +130,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
             }
             if constexpr (DIAG) near = true;
             if (__builtin_amdgcn_readfirstlane((int)near)) {
-                const bool lj = group_near<COMP, DIAG>(sp + g * kGroup, sl + g * kGroup, jg, i,
-                                                       pi, li, cull2, a);
+                const bool lj = group_near_rel<COMP, DIAG>(sr + g * kGroup, jg, i, pr, cull2, a);
                 // record the pair of groups if it holds a Lennard-Jones
                 // candidate, for the Lennard-Jones kernel
                 if (nearbits && __ballot(lj && live) && (tid & (kGroup - 1)) == 0) {

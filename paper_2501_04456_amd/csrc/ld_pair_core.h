@@ -66,33 +66,30 @@ __device__ __forceinline__ void group_far(const float4* __restrict__ sp, const f
 }
 
 // 64 j particles near i's group (within the largest LJ range of its box) or
-// holding i itself: the Coulomb terms with the low words of the positions
-// in the differences, the self pair left out.
-//
-// The difference of the FP32 high words of two nearby particles is exact,
-// and adding the difference of their low words gives r_ij to FP32 rounding
-// of r_ij itself, not of |x|.  Near |x| = 300 sigma one ulp of a coordinate
-// is 3e-5 sigma, which at contact distance would move a Coulomb term by
-// ~1e-4 of itself.  The low words are staged in LDS beside the high words
-// (zero in padding slots).  The Lennard-Jones terms of these groups are
-// added by a kernel of their own (k_lj), in FP64.
-// Returns whether any j of the group lies within sqrt(lj2) of i (i itself
-// excluded): the Lennard-Jones kernel visits only such group pairs.
+// holding i itself: the Coulomb terms, the self pair left out, from
+// positions taken relative to an origin c near both groups (the centre of
+// the box of the workgroup's slots, or of the ensemble tile's box).  Each
+// staged j and the lane's own i hold (hi - c) + lo rounded to FP32, so a
+// difference carries the rounding of |x - c| (tens of sigma for the groups
+// this loop sees) instead of |x|: near |x| = 300 sigma one ulp of a
+// coordinate is 3e-5 sigma, which at contact distance would move a Coulomb
+// term by ~1e-4 of itself; at |x - c| = 64 sigma it is 8e-6 sigma.  One LDS
+// read and three subtractions per pair, as in the far loop.  The
+// Lennard-Jones terms of these groups are added by a kernel of their own
+// (k_lj), in FP64 from the exact (hi, lo) differences.  Returns whether any
+// j of the group lies within sqrt(lj2) of i (i itself excluded): the
+// Lennard-Jones kernel visits only such group pairs.
 template <int COMP, bool DIAG>
-__device__ __forceinline__ bool group_near(const float4* __restrict__ sp,
-                                           const float4* __restrict__ sl, int jbase, int i,
-                                           const float4 pi, const float4 li, float lj2, Acc& a) {
+__device__ __forceinline__ bool group_near_rel(const float4* __restrict__ sr, int jbase, int i,
+                                               const float4 ri4, float lj2, Acc& a) {
     bool lj_any = false;
 #pragma unroll
     for (int kb = 0; kb < kGroup; kb += KB) {
         float bx = 0.f, by = 0.f, bz = 0.f;   // Coulomb, FP32 block
 #pragma unroll 4
         for (int k = 0; k < KB; ++k) {
-            const float4 pj = sp[kb + k];
-            const float4 lj = sl[kb + k];
-            const float dx = (pj.x - pi.x) + (lj.x - li.x);
-            const float dy = (pj.y - pi.y) + (lj.y - li.y);
-            const float dz = (pj.z - pi.z) + (lj.z - li.z);
+            const float4 pj = sr[kb + k];
+            const float dx = pj.x - ri4.x, dy = pj.y - ri4.y, dz = pj.z - ri4.z;
             const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
             const float ri = __builtin_amdgcn_rsqf(r2);
             const bool self = jbase + kb + k == i;
@@ -100,7 +97,7 @@ __device__ __forceinline__ bool group_near(const float4* __restrict__ sp,
             lj_any |= r2 < lj2 && !self;
             if constexpr (DIAG) {
                 if (!self) {
-                    const float qq = pi.w * pj.w;
+                    const float qq = ri4.w * pj.w;
                     a.S += (double)(fabsf(qq) * ri * ri);
                     a.Uc += 0.5 * (double)(qq * ri);
                 }

@@ -260,6 +260,15 @@ def test_ensemble_autotune_and_cache(ld, orc, small_ensemble, tmp_path):
         Fo, So, _ = orc.pair_forces(w.pos, w.type, w.charge, w.params)
         dF = np.linalg.norm(F[off[d]:off[d + 1]] - Fo, axis=1)
         assert np.all(dF <= 1e-5 * So), d
+    # the searched settings only change which wavefront takes which tile and
+    # how many pairs are in flight, never the order of any sum: the forces
+    # are bit for bit those of an untuned ensemble, whatever the settings
+    e0 = ld.Ensemble(small_ensemble.droplets)
+    F0 = e0.forces().cpu().numpy()
+    assert np.array_equal(F, F0)
+    for wg, un in ((64, 8), (300, 32)):
+        e0.set_tuning(workgroups=wg, unroll=un)
+        assert np.array_equal(e0.forces().cpu().numpy(), F0), (wg, un)
     line = open(cache).read().split()
     assert line[0].startswith("ens/") and int(line[1]) == t1["workgroups"]
     assert int(line[2]) == t1["unroll"]
