@@ -496,23 +496,30 @@ void ld_ens_destroy(ld_ens* e);
  * Captured steps replay with the dt they were captured with. */
 ld_status ld_ens_set_tuning(ld_ens* e, int32_t workgroups, int32_t comp, int32_t graph_steps);
 
-/* out = {workgroups, comp, graph_steps, unroll}. */
-ld_status ld_ens_get_tuning(ld_ens* e, int32_t out[4]);
+/* out = {workgroups, comp, graph_steps, unroll, rows}. */
+ld_status ld_ens_get_tuning(ld_ens* e, int32_t out[5]);
 
 /* Coulomb pairs in flight per lane in the persistent pair kernel: 8, 16
  * (default) or 32.  Errors: LD_EINVAL. */
 ld_status ld_ens_set_unroll(ld_ens* e, int32_t unroll);
 
+/* Slots per work item of the persistent pair kernel: 64 (default; a
+ * wavefront per 64-slot tile, each staging its own j tiles) or 256 (a
+ * workgroup per block of four tiles, sharing staged j tiles of 256).  The
+ * forces are bit for bit the same either way.  Errors: LD_EINVAL. */
+ld_status ld_ens_set_rows(ld_ens* e, int32_t rows);
+
 /* Choose the persistent pair kernel's workgroup count (2..8 per compute
- * unit) and unroll (8, 16, 32) by timing the pair step (forces only; the
- * droplets do not move) with HIP events, keeping the compensation mode and
- * graph length.  cache_path (or NULL): a text file of lines
- * "key workgroups unroll ms"; the key holds the GPU architecture, the
+ * unit), unroll (8, 16, 32) and work-item rows (64, 256) by timing the pair
+ * step (forces only; the droplets do not move) with HIP events, keeping the
+ * compensation mode and graph length; none of the searched settings changes
+ * the forces.  cache_path (or NULL): a text file of lines
+ * "key workgroups unroll rows ms"; the key holds the GPU architecture, the
  * droplet count, quarter-octave buckets of sum_d N_d^2 and of the largest
  * N_d, the culling and compensation modes.  A cached key is used without
  * timing unless force != 0; new results are appended.  out (or NULL) as in
  * ld_ens_get_tuning.  Errors: LD_EINVAL, LD_EHIP. */
-ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int32_t out[4]);
+ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int32_t out[5]);
 
 /* Advance all droplets n_steps >= 0 steps of size dt > 0 (asynchronous). */
 ld_status ld_ens_step(ld_ens* e, double dt, int64_t n_steps);

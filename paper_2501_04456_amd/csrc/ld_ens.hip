@@ -135,6 +135,116 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
     }
 }
 
+// The same sums with 256-slot work items (droplet, block of four tiles): the
+// workgroup's four wavefronts own the four tiles and share each staged tile
+// of 256 j (high and low words), so a staging wait serves 4 x 256 pairs per
+// lane instead of 64.  A near j group is restaged by its wavefront alone, relative
+// to the centre of that wavefront's own tile box, exactly as in k_ens_pair;
+// every lane sees the same j groups in the same order with the same inputs,
+// so the forces are bit for bit those of k_ens_pair.
+template <int COMP, bool CULL, int UNROLL>
+__global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair_b(
+    const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ off,
+    const int2* __restrict__ items, int W, unsigned* counter,
+    const PairTable* __restrict__ tabs, const Box* __restrict__ box,
+    const int* __restrict__ tbase, double* __restrict__ F, int total,
+    unsigned* __restrict__ nearbits, int nb_words) {
+    __shared__ float4 sp[kEnsBlock];                 // shared j tile (high words)
+    __shared__ float4 sl[kEnsBlock];                 // and its low words
+    __shared__ float4 sr[kWaves][kGroup];            // a wavefront's near group, relative
+    __shared__ unsigned item_s;
+    const int w = threadIdx.x / kGroup;
+    const int lane = threadIdx.x % kGroup;
+    for (;;) {
+        __syncthreads();                             // item_s free to overwrite
+        if (threadIdx.x == 0) item_s = atomicAdd(counter, 1u);
+        __syncthreads();
+        const unsigned item = item_s;
+        if (item >= (unsigned)W) break;              // uniform per workgroup
+        const int2 it = items[item];
+        const int d = it.x;
+        const int o = off[d];
+        const int nd = off[d + 1] - o;
+        const float rc2max = tabs[d].rc2max;
+        const int i0 = it.y + w * kGroup;            // this wavefront's tile
+        const bool wlive = i0 < nd;
+        const int i = i0 + lane;
+        const bool live = i < nd;
+        const float4 pi = live ? pos[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 li = live ? lo[o + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        pair::Acc a;
+        Box bi;
+        const int t0 = tbase[d];
+        float4 c = make_float4(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.x))),
+                               __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.y))),
+                               __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.z))),
+                               0.f);
+        if constexpr (CULL) {
+            if (wlive) {
+                bi = box[t0 + i0 / kGroup];
+                c = make_float4(0.5f * (bi.lo.x + bi.hi.x), 0.5f * (bi.lo.y + bi.hi.y),
+                                0.5f * (bi.lo.z + bi.hi.z), 0.f);
+            }
+        }
+        const float4 pr = make_float4((pi.x - c.x) + li.x, (pi.y - c.y) + li.y,
+                                      (pi.z - c.z) + li.z, pi.w);
+        const float cull2 = rc2max * 1.0001f;
+        for (int jt = 0; jt < nd; jt += kEnsBlock) {
+            __syncthreads();
+            const int js = jt + (int)threadIdx.x;
+            sp[threadIdx.x] = js < nd ? pos[o + js] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+            sl[threadIdx.x] = js < nd ? lo[o + js] : make_float4(0.f, 0.f, 0.f, 0.f);
+            __syncthreads();
+            if (!wlive) continue;
+#pragma unroll 1
+            for (int g = 0; g < kWaves; ++g) {
+                const int jg = jt + g * kGroup;
+                if (jg >= nd) break;
+                bool near = true;
+                if constexpr (CULL) {
+                    const Box bj = box[t0 + jg / kGroup];
+                    near = __builtin_amdgcn_readfirstlane((int)(pair::box_dist2(bi, bj) < cull2));
+                    const bool coulomb =
+                        __builtin_amdgcn_readfirstlane((int)(bi.lo.w != 0.f && bj.lo.w != 0.f));
+                    if (!near && !coulomb) continue;
+                }
+                if (near) {
+                    const int j = jg + lane;
+                    float4 pj = sp[g * kGroup + lane];
+                    if (j < nd) {
+                        const float4 lj = sl[g * kGroup + lane];
+                        pj = make_float4((pj.x - c.x) + lj.x, (pj.y - c.y) + lj.y,
+                                         (pj.z - c.z) + lj.z, pj.w);
+                    }
+                    wave_sync();
+                    sr[w][lane] = pj;
+                    wave_sync();
+                    const bool lj = pair::group_near_rel<COMP, false>(sr[w], jg, i, pr, cull2, a);
+                    if (__ballot(lj && live) && lane == 0) {
+                        const int gj = jg / kGroup;
+                        atomicOr(&nearbits[(size_t)(t0 + i0 / kGroup) * nb_words + (gj >> 5)],
+                                 1u << (gj & 31));
+                    }
+                } else {
+                    pair::group_far<COMP, UNROLL>(sp + g * kGroup, pi, a);
+                }
+            }
+        }
+        if constexpr (COMP == 1) {
+            a.Fx = (double)a.sx - (double)a.cx;
+            a.Fy = (double)a.sy - (double)a.cy;
+            a.Fz = (double)a.sz - (double)a.cz;
+        }
+        if (live) {
+            const double qi = (double)pi.w;
+            const size_t sl = (size_t)(o + i);
+            F[sl] = -qi * a.Fx;
+            F[(size_t)total + sl] = -qi * a.Fy;
+            F[2 * (size_t)total + sl] = -qi * a.Fz;
+        }
+    }
+}
+
 // Lennard-Jones forces of every tile of every droplet, in FP64, added into F
 // after k_ens_pair.  One workgroup per 64-slot tile: its four wavefronts
 // share round-robin the j tiles in which k_ens_pair found a pair within the
@@ -361,8 +471,11 @@ struct ld_ens {
     int* did = nullptr;
     int* lid = nullptr;
     int* off = nullptr;
-    int2* items = nullptr;
+    int2* items = nullptr;               // (droplet, first slot) of every 64-slot tile
     int W = 0;
+    int2* items_b = nullptr;             // (droplet, first slot) of every 256-slot block
+    int W_b = 0;
+    int rows = 64;                       // slots per work item: 64 (k_ens_pair) or 256 (k_ens_pair_b)
     unsigned* counter = nullptr;
     PairTable* tabs = nullptr;
     ExtParams* ext = nullptr;
@@ -397,7 +510,7 @@ namespace {
 
 void ens_free(ld_ens* e) {
     void* bufs[] = {e->pos,   e->lo,   e->typ,   e->did,     e->lid,   e->off,
-                    e->items, e->counter, e->tabs, e->ext,   e->seeds, e->F,
+                    e->items, e->counter, e->tabs, e->ext,   e->seeds, e->F, e->items_b,
                     e->work,  e->st,   e->box,   e->tbase,   e->tiles, e->dbounds,
                     e->sb.keys, e->sb.tmp4, e->sb.tmp_i, e->nearbits};
     for (void* b : bufs)
@@ -424,8 +537,26 @@ ld_status enqueue_sort(ld_ens* e, hipStream_t s) {
     return LD_OK;
 }
 
+// Work items a workgroup can run at once: four tiles, or one block.
+int max_workgroups(const ld_ens* e) {
+    return e->rows == 256 ? e->W_b : (e->W + kWaves - 1) / kWaves;
+}
+
 template <int COMP, int UNROLL>
 void launch_ens_pair_u(ld_ens* e, hipStream_t s) {
+    if (e->rows == 256) {
+        if (e->cull)
+            hipLaunchKernelGGL((k_ens_pair_b<COMP, true, UNROLL>), dim3(e->workgroups),
+                               dim3(kEnsBlock), 0, s, e->pos, e->lo, e->off, e->items_b, e->W_b,
+                               e->counter, e->tabs, e->box, e->tbase, e->F, e->total,
+                               e->nearbits, e->nb_words);
+        else
+            hipLaunchKernelGGL((k_ens_pair_b<COMP, false, UNROLL>), dim3(e->workgroups),
+                               dim3(kEnsBlock), 0, s, e->pos, e->lo, e->off, e->items_b, e->W_b,
+                               e->counter, e->tabs, e->box, e->tbase, e->F, e->total,
+                               e->nearbits, e->nb_words);
+        return;
+    }
     if (e->cull)
         hipLaunchKernelGGL((k_ens_pair<COMP, true, UNROLL>), dim3(e->workgroups), dim3(kEnsBlock),
                            0, s, e->pos, e->lo, e->typ, e->off, e->items, e->W, e->counter,
@@ -571,7 +702,7 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
     std::vector<PairTable> tabs(n_drop);
     std::vector<ExtParams> exts(n_drop);
     std::vector<unsigned long long> sd(n_drop);
-    std::vector<int2> items, tiles;
+    std::vector<int2> items, items_b, tiles;
     std::vector<int> tbase(n_drop);
     for (int d = 0; d < n_drop; ++d) {
         make_tables(p[d], R[d], tabs[d], exts[d]);
@@ -599,12 +730,17 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
             items.push_back(make_int2(d, (int)i0));
             tiles.push_back(make_int2(d, (int)(offs[d] + i0)));
         }
+        for (int64_t i0 = 0; i0 < offs[d + 1] - offs[d]; i0 += kEnsBlock)
+            items_b.push_back(make_int2(d, (int)i0));
     }
     // longest item first: an item costs N_d pairs per lane
-    std::stable_sort(items.begin(), items.end(), [&](const int2& a, const int2& b) {
+    auto longer = [&](const int2& a, const int2& b) {
         return (offs[a.x + 1] - offs[a.x]) > (offs[b.x + 1] - offs[b.x]);
-    });
+    };
+    std::stable_sort(items.begin(), items.end(), longer);
+    std::stable_sort(items_b.begin(), items_b.end(), longer);
     e->W = (int)items.size();
+    e->W_b = (int)items_b.size();
     std::vector<int> off32(offs.begin(), offs.end());
     const size_t N = (size_t)total;
     bool ok = hipMalloc(&e->pos, sizeof(float4) * N) == hipSuccess &&
@@ -614,6 +750,7 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
               hipMalloc(&e->lid, sizeof(int) * N) == hipSuccess &&
               hipMalloc(&e->off, sizeof(int) * (n_drop + 1)) == hipSuccess &&
               hipMalloc(&e->items, sizeof(int2) * items.size()) == hipSuccess &&
+              hipMalloc(&e->items_b, sizeof(int2) * items_b.size()) == hipSuccess &&
               hipMalloc(&e->counter, sizeof(unsigned)) == hipSuccess &&
               hipMalloc(&e->tabs, sizeof(PairTable) * n_drop) == hipSuccess &&
               hipMalloc(&e->ext, sizeof(ExtParams) * n_drop) == hipSuccess &&
@@ -663,6 +800,7 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
     up(e->lid, lids.data(), sizeof(int) * N);
     up(e->off, off32.data(), sizeof(int) * (n_drop + 1));
     up(e->items, items.data(), sizeof(int2) * items.size());
+    up(e->items_b, items_b.data(), sizeof(int2) * items_b.size());
     up(e->counter, &zero, sizeof zero);
     up(e->tabs, tabs.data(), sizeof(PairTable) * n_drop);
     up(e->ext, exts.data(), sizeof(ExtParams) * n_drop);
@@ -679,7 +817,7 @@ ld_status ld_ens_init(ld_ens** out, int32_t n_drop, const int64_t* offsets, cons
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    e->workgroups = std::max(1, std::min(cus * 8, (e->W + kWaves - 1) / kWaves));
+    e->workgroups = std::max(1, std::min(cus * 8, max_workgroups(e)));
     e->steps_since_sort = sort_interval(e);              // sort before the first step
     *out = e;
     return LD_OK;
@@ -710,13 +848,14 @@ ld_status ld_ens_set_tuning(ld_ens* e, int32_t workgroups, int32_t comp, int32_t
     return LD_OK;
 }
 
-ld_status ld_ens_get_tuning(ld_ens* e, int32_t out[4]) {
+ld_status ld_ens_get_tuning(ld_ens* e, int32_t out[5]) {
     g_err.clear();
     if (!e || !out) return fail(LD_EINVAL, "ensemble and out are required");
     out[0] = e->workgroups;
     out[1] = e->comp;
     out[2] = e->graph_steps;
     out[3] = e->unroll;
+    out[4] = e->rows;
     return LD_OK;
 }
 
@@ -734,7 +873,20 @@ ld_status ld_ens_set_unroll(ld_ens* e, int32_t unroll) {
     return LD_OK;
 }
 
-ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int32_t out[4]) {
+ld_status ld_ens_set_rows(ld_ens* e, int32_t rows) {
+    g_err.clear();
+    if (!e) return fail(LD_EINVAL, "ensemble is NULL");
+    if (rows != 64 && rows != 256) return fail(LD_EINVAL, "rows must be 64 or 256");
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    e->rows = rows;
+    if (e->graph) {
+        (void)hipGraphExecDestroy(e->graph);
+        e->graph = nullptr;
+    }
+    return LD_OK;
+}
+
+ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int32_t out[5]) {
     g_err.clear();
     if (!e) return fail(LD_EINVAL, "ensemble is NULL");
     HIP_TRY(hipStreamSynchronize(e->stream));
@@ -757,20 +909,22 @@ ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int3
         nmax = std::max(nmax, nd);
     }
     char key[192];
-    std::snprintf(key, sizeof key, "ens/%s/d%d/p%d/m%d/cull%d/comp%d", arch, e->n_drop,
+    std::snprintf(key, sizeof key, "ens2/%s/d%d/p%d/m%d/cull%d/comp%d", arch, e->n_drop,
                   (int)std::floor(std::log2(pairs) * 4.0),
                   (int)std::floor(std::log2((double)nmax) * 4.0), e->cull ? 1 : 0, e->comp);
-    int best_w = e->workgroups, best_u = e->unroll;
+    int best_w = e->workgroups, best_u = e->unroll, best_r = e->rows;
     bool cached = false;
     if (cache_path && !force) {
         if (FILE* f = std::fopen(cache_path, "r")) {
             char k[192];
-            int wg = 0, un = 0;
+            int wg = 0, un = 0, ro = 0;
             double ms = 0.0;
-            while (std::fscanf(f, "%191s %d %d %lf", k, &wg, &un, &ms) == 4)
-                if (std::strcmp(k, key) == 0) {
+            while (std::fscanf(f, "%191s %d %d %d %lf", k, &wg, &un, &ro, &ms) == 5)
+                if (std::strcmp(k, key) == 0 && (ro == 64 || ro == 256) &&
+                    (un == 8 || un == 16 || un == 32) && wg > 0) {
                     best_w = wg;
                     best_u = un;
+                    best_r = ro;
                     cached = true;
                 }
             std::fclose(f);
@@ -783,13 +937,16 @@ ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int3
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        const int per_cu[] = {2, 3, 4, 5, 6, 8};
+        const int per_cu[] = {2, 3, 4, 5, 6, 7, 8};
         const int unrolls[] = {8, 16, 32};
+        const int item_rows[] = {64, 256};
         ld_status st = LD_OK;
-        for (int u : unrolls) {
+        for (int r : item_rows) {
+          for (int u : unrolls) {
             for (int k : per_cu) {
+                e->rows = r;
                 e->unroll = u;
-                e->workgroups = std::max(1, std::min(cus * k, (e->W + kWaves - 1) / kWaves));
+                e->workgroups = std::max(1, std::min(cus * k, max_workgroups(e)));
                 double ms_min = INFINITY;
                 for (int rep = 0; rep < 4 && st == LD_OK; ++rep) {
                     if (hipEventRecord(e0, e->stream) != hipSuccess) st = LD_EHIP;
@@ -806,9 +963,12 @@ ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int3
                     best_ms = ms_min;
                     best_w = e->workgroups;
                     best_u = u;
+                    best_r = r;
                 }
             }
             if (st != LD_OK) break;
+          }
+          if (st != LD_OK) break;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -816,24 +976,19 @@ ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int3
         if (st != LD_OK) return fail(LD_EHIP, "ensemble autotune launch failed");
         if (cache_path) {
             if (FILE* f = std::fopen(cache_path, "a")) {
-                std::fprintf(f, "%s %d %d %.6f\n", key, best_w, best_u, best_ms);
+                std::fprintf(f, "%s %d %d %d %.6f\n", key, best_w, best_u, best_r, best_ms);
                 std::fclose(f);
             }
         }
     }
     e->workgroups = best_w;
     e->unroll = best_u;
+    e->rows = best_r;
     if (e->graph) {
         (void)hipGraphExecDestroy(e->graph);
         e->graph = nullptr;
     }
-    if (out) {
-        out[0] = e->workgroups;
-        out[1] = e->comp;
-        out[2] = e->graph_steps;
-        out[3] = e->unroll;
-    }
-    return LD_OK;
+    return out ? ld_ens_get_tuning(e, out) : LD_OK;
 }
 
 ld_status ld_ens_step(ld_ens* e, double dt, int64_t n_steps) {

@@ -116,7 +116,7 @@ SYMBOLS = [
     "ld_paper_set_velocities", "ld_aggregates", "ld_surface_count", "ld_record_open",
     "ld_record_close", "ld_cbar_type", "ld_surface_fractal", "ld_ff_save", "ld_ff_load",
     "ld_msd", "ld_msd_reset", "ld_forces_noalloc", "ld_ens_get_tuning", "ld_ens_set_unroll",
-    "ld_ens_autotune",
+    "ld_ens_set_rows", "ld_ens_autotune",
 ]
 
 _lib = None
@@ -166,6 +166,7 @@ def lib():
         L.ld_ens_step.argtypes = [vp, C.c_double, C.c_int64]
         L.ld_ens_get_tuning.argtypes = [vp, vp]
         L.ld_ens_set_unroll.argtypes = [vp, C.c_int32]
+        L.ld_ens_set_rows.argtypes = [vp, C.c_int32]
         L.ld_ens_autotune.argtypes = [vp, C.c_char_p, C.c_int32, vp]
         L.ld_ens_forces.argtypes = [vp, vp]
         L.ld_ens_get_positions.argtypes = [vp, vp, vp]
@@ -693,22 +694,26 @@ class Ensemble:
         except Exception:
             pass
 
+    ENS_TUNING = ("workgroups", "comp", "graph_steps", "unroll", "rows")
+
     def set_tuning(self, workgroups: int = 0, comp: int = 0, graph_steps: int = 0,
-                   unroll: int = 0):
+                   unroll: int = 0, rows: int = 0):
         _check(lib().ld_ens_set_tuning(self.h, workgroups, comp, graph_steps))
         if unroll:
             _check(lib().ld_ens_set_unroll(self.h, unroll))
+        if rows:
+            _check(lib().ld_ens_set_rows(self.h, rows))
 
     def tuning(self) -> dict:
-        out = np.zeros(4, np.int32)
+        out = np.zeros(5, np.int32)
         _check(lib().ld_ens_get_tuning(self.h, out.ctypes.data_as(C.c_void_p)))
-        return dict(zip(("workgroups", "comp", "graph_steps", "unroll"), map(int, out)))
+        return dict(zip(self.ENS_TUNING, map(int, out)))
 
     def autotune(self, cache_path: str = None, force: bool = False) -> dict:
-        out = np.zeros(4, np.int32)
+        out = np.zeros(5, np.int32)
         _check(lib().ld_ens_autotune(self.h, cache_path.encode() if cache_path else None,
                                      1 if force else 0, out.ctypes.data_as(C.c_void_p)))
-        return dict(zip(("workgroups", "comp", "graph_steps", "unroll"), map(int, out)))
+        return dict(zip(self.ENS_TUNING, map(int, out)))
 
     def step(self, n_steps: int, dt: float):
         _check(lib().ld_ens_step(self.h, float(dt), int(n_steps)))

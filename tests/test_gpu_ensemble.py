@@ -44,10 +44,10 @@ def test_ensemble_forces_per_droplet(ld, orc, small_ensemble):
         assert err <= 1e-5, (d, err)
 
 
-@pytest.mark.parametrize("comp", [0, 1])
-def test_ensemble_trajectories(ld, orc, small_ensemble, comp):
+@pytest.mark.parametrize("comp,rows", [(0, 64), (1, 64), (1, 256)])
+def test_ensemble_trajectories(ld, orc, small_ensemble, comp, rows):
     ens = ld.Ensemble(small_ensemble.droplets)
-    ens.set_tuning(workgroups=37, comp=comp, graph_steps=0)
+    ens.set_tuning(workgroups=37, comp=comp, graph_steps=0, rows=rows)
     steps = 20
     ens.step(steps, small_ensemble.dt)
     ens.sync()
@@ -246,8 +246,8 @@ def test_ensemble_graph_trajectory_vs_oracle(ld, orc, small_ensemble):
 
 
 def test_ensemble_autotune_and_cache(ld, orc, small_ensemble, tmp_path):
-    """The ensemble tuner picks a workgroup count and unroll, writes them to
-    its cache and reuses them; forces stay within 1e-5 of S_i of the oracle
+    """The ensemble tuner picks a workgroup count, unroll and work-item rows,
+    writes them to its cache and reuses them; forces stay within 1e-5 of S_i of the oracle
     droplet by droplet (the droplets do not move while it times)."""
     ens = ld.Ensemble(small_ensemble.droplets)
     cache = str(tmp_path / "ens_tune.txt")
@@ -266,14 +266,16 @@ def test_ensemble_autotune_and_cache(ld, orc, small_ensemble, tmp_path):
     e0 = ld.Ensemble(small_ensemble.droplets)
     F0 = e0.forces().cpu().numpy()
     assert np.array_equal(F, F0)
-    for wg, un in ((64, 8), (300, 32)):
-        e0.set_tuning(workgroups=wg, unroll=un)
-        assert np.array_equal(e0.forces().cpu().numpy(), F0), (wg, un)
+    for wg, un, rows in ((64, 8, 64), (300, 32, 64), (7, 16, 256), (500, 8, 256)):
+        e0.set_tuning(workgroups=wg, unroll=un, rows=rows)
+        assert np.array_equal(e0.forces().cpu().numpy(), F0), (wg, un, rows)
     line = open(cache).read().split()
-    assert line[0].startswith("ens/") and int(line[1]) == t1["workgroups"]
-    assert int(line[2]) == t1["unroll"]
+    assert line[0].startswith("ens2/") and int(line[1]) == t1["workgroups"]
+    assert int(line[2]) == t1["unroll"] and int(line[3]) == t1["rows"]
     e2 = ld.Ensemble(small_ensemble.droplets)
     t2 = e2.autotune(cache_path=cache)
-    assert (t2["workgroups"], t2["unroll"]) == (t1["workgroups"], t1["unroll"])
+    assert t2 == t1
     with pytest.raises(RuntimeError):
         e2.set_tuning(unroll=12)
+    with pytest.raises(RuntimeError):
+        e2.set_tuning(rows=128)
