@@ -2509,19 +2509,51 @@ ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* 
     const int64_t ntr = f->samples - nval;
     std::vector<int> perm(ntr);
     for (int64_t k = 0; k < ntr; ++k) perm[k] = (int)k;
-    int* dperm = nullptr;
-    HIP_TRY(hipMalloc(&dperm, sizeof(int) * std::max<int64_t>(std::max<int64_t>(ntr, 1), B_)));
+    // Each epoch's permutation is uploaded from one of two pinned host
+    // buffers into one of two device buffers, stream-ordered before the
+    // epoch's batches, so the host shuffles epoch e + 1 while the GPU trains
+    // on epoch e; a host buffer is refilled only after its last copy ended.
+    const size_t pcount = (size_t)std::max<int64_t>(std::max<int64_t>(ntr, 1), B_);
+    int* dperm_buf[2] = {nullptr, nullptr};
+    int* hperm[2] = {nullptr, nullptr};
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    auto release = [&]() {
+        for (int k = 0; k < 2; ++k) {
+            if (dperm_buf[k]) (void)hipFree(dperm_buf[k]);
+            if (hperm[k]) (void)hipHostFree(hperm[k]);
+            if (copied[k]) (void)hipEventDestroy(copied[k]);
+        }
+    };
+    for (int k = 0; k < 2; ++k) {
+        if (hipMalloc(&dperm_buf[k], sizeof(int) * pcount) != hipSuccess ||
+            hipHostMalloc(&hperm[k], sizeof(int) * pcount) != hipSuccess ||
+            hipEventCreateWithFlags(&copied[k], hipEventDisableTiming) != hipSuccess) {
+            release();
+            return fail(LD_ENOMEM, "cannot allocate the batch permutations");
+        }
+    }
+    int* dperm = dperm_buf[0];
     double last = 0.0;
     int64_t iters = 0;
     const int G = f->cfg.grid;
     for (int ep = 0; ep < tc->epochs && st == LD_OK; ++ep) {
-        // Fisher-Yates with Philox words (stream tag 3)
+        // Fisher-Yates with Philox words (stream tag 3), applied to the
+        // previous epoch's order
         for (int64_t k = ntr - 1; k > 0; --k) {
             const uint64_t ctr = ((uint64_t)ep << 40) ^ (uint64_t)k;
             const int64_t j = (int64_t)(philox_word(tc->seed, ctr, 0) % (uint64_t)(k + 1));
             std::swap(perm[k], perm[j]);
         }
-        if (hipMemcpy(dperm, perm.data(), sizeof(int) * ntr, hipMemcpyHostToDevice) != hipSuccess) {
+        const int slot = ep & 1;
+        if (hipEventSynchronize(copied[slot]) != hipSuccess) {     // its last copy is done
+            st = fail(LD_EHIP, "wait for a permutation copy");
+            break;
+        }
+        std::memcpy(hperm[slot], perm.data(), sizeof(int) * ntr);
+        dperm = dperm_buf[slot];
+        if (hipMemcpyAsync(dperm, hperm[slot], sizeof(int) * ntr, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipEventRecord(copied[slot], s) != hipSuccess) {
             st = fail(LD_EHIP, "upload permutation");
             break;
         }
@@ -2533,7 +2565,9 @@ ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* 
                                inv_scale, f->bX, f->bT);
             if (hipGetLastError() != hipSuccess) { st = fail(LD_EHIP, "gather"); break; }
             double l = 0.0;
-            const bool want = (b0 + 2 * B_ > ntr);   // last batch of the epoch
+            // the reported loss is the last batch's of the last epoch (reading
+            // it waits for the GPU, so no other batch reads it back)
+            const bool want = ep + 1 == tc->epochs && b0 + 2 * B_ > ntr;
             st = fwd_bwd(f, B_, s, want ? &l : nullptr);
             if (st != LD_OK) break;
             ++f->adam_step;
@@ -2557,8 +2591,8 @@ ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* 
         for (int64_t k = ntr; k < f->samples; ++k) vidx.push_back((int)k);
         for (size_t v0 = 0; v0 + 16 <= vidx.size() && st == LD_OK; v0 += B_) {
             const int bsz = (int)std::min<size_t>(B_, vidx.size() - v0);
-            if (hipMemcpy(dperm, vidx.data() + v0, sizeof(int) * bsz, hipMemcpyHostToDevice) !=
-                hipSuccess) { st = fail(LD_EHIP, "upload"); break; }
+            if (hipMemcpyAsync(dperm, vidx.data() + v0, sizeof(int) * bsz, hipMemcpyHostToDevice,
+                               s) != hipSuccess) { st = fail(LD_EHIP, "upload"); break; }
             hipLaunchKernelGGL(k_gather_batch, dim3(bsz), dim3(kB), 0, s, dperm, bsz, f->s_snap,
                                f->s_cell, f->s_off, f->s_tgt, f->snap_mom, G, f->cfg.block, f->Kp,
                                inv_scale, f->bX, f->bT);
@@ -2598,7 +2632,8 @@ ld_status ld_ff_train(ld_ctx* c, const ld_ff_train_cfg* tc, ld_ff_train_report* 
             }
         }
     }
-    (void)hipFree(dperm);
+    (void)hipStreamSynchronize(s);
+    release();
     if (st != LD_OK) return st;
     if (rep) {
         rep->samples = f->samples;

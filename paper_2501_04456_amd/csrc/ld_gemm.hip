@@ -326,6 +326,105 @@ __global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g, int kpiece, float* p
     }
 }
 
+// A 32-row A tile, k contiguous (A untransposed): two 16-byte loads per
+// work-item per 64-deep stage.
+struct TileA32 {
+    float4 v[2];
+
+    __device__ __forceinline__ void load(const float* __restrict__ P, int ld, int r0, int rlim,
+                                         int k0, int klim, int t) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = t + 256 * q;
+            const int r = r0 + idx / 16, k = k0 + (idx % 16) * 4;
+            const float* src = P + (size_t)r * ld + k;
+            if (r < rlim && k + 3 < klim) {
+                v[q] = *reinterpret_cast<const float4*>(src);
+            } else {
+                const bool rr = r < rlim;
+                v[q].x = rr && k < klim ? src[0] : 0.f;
+                v[q].y = rr && k + 1 < klim ? src[1] : 0.f;
+                v[q].z = rr && k + 2 < klim ? src[2] : 0.f;
+                v[q].w = rr && k + 3 < klim ? src[3] : 0.f;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(__bf16 (*S)[VK + PAD], int t) const {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int idx = t + 256 * q;
+            uint2 w;
+            w.x = pack2(v[q].x, v[q].y);
+            w.y = pack2(v[q].z, v[q].w);
+            *reinterpret_cast<uint2*>(&S[idx / 16][(idx % 16) * 4]) = w;
+        }
+    }
+};
+
+// As k_gemm_v (untransposed A, no split K), with 32 x 64 output tiles: twice
+// the workgroups of the 64 x 64 tiling for the tall products (M = batch),
+// which otherwise run one wavefront per SIMD.  Wavefront w owns rows
+// 16 (w % 2) .. + 15 and columns 32 (w / 2) .. + 31 (two MFMA tiles).
+template <bool TB>
+__global__ __launch_bounds__(256) void k_gemm_v32(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) __bf16 As[32][VK + PAD];
+    __shared__ __attribute__((aligned(16))) __bf16 Bt[BN][VK + PAD];
+    const int M = g.M_dev ? min(g.M, *g.M_dev) : g.M;
+    const int m0 = blockIdx.x * 32, n0 = blockIdx.y * BN;
+    if (m0 >= M) return;
+    const int t = threadIdx.x, w = t / 64, l = t % 64;
+    const int wr = (w & 1) * 16, wc = (w >> 1) * 32;
+    f32x4 acc[2];
+    for (int j = 0; j < 2; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    TileA32 ta[2];
+    Tile<TB> tb[2];
+    ta[0].load(g.A, g.lda, m0, M, 0, g.K, t);
+    tb[0].load(g.B, g.ldb, n0, g.N, 0, g.K, t);
+    if (VK < g.K) {
+        ta[1].load(g.A, g.lda, m0, M, VK, g.K, t);
+        tb[1].load(g.B, g.ldb, n0, g.N, VK, g.K, t);
+    }
+    const int kk = 8 * (l / 16);
+    for (int k0 = 0; k0 < g.K; k0 += 2 * VK) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int ks0 = k0 + r * VK;
+            if (ks0 >= g.K) break;
+            __syncthreads();
+            ta[r].store(As, t);
+            tb[r].store(Bt, t);
+            __syncthreads();
+            if (ks0 + 2 * VK < g.K) {
+                ta[r].load(g.A, g.lda, m0, M, ks0 + 2 * VK, g.K, t);
+                tb[r].load(g.B, g.ldb, n0, g.N, ks0 + 2 * VK, g.K, t);
+            }
+#pragma unroll
+            for (int ks = 0; ks < VK; ks += 32) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wr + l % 16][ks + kk]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const bf16x8 b =
+                        *reinterpret_cast<const bf16x8*>(&Bt[wc + j * 16 + l % 16][ks + kk]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = n0 + wc + j * 16 + l % 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = m0 + wr + 4 * (l / 16) + r;
+            if (row >= M || col >= g.N) continue;
+            const float v = epilogue(g, row, col, acc[j][r]);
+            float* c = g.C + (size_t)row * g.ldc + col;
+            *c = g.accumulate ? *c + v : v;
+        }
+    }
+}
+
 // Split-K epilogue.  A workgroup owns 32 outputs; its eight groups of 32
 // work-items each add one eighth of the pieces (all of their loads in flight
 // at once), and the eight group sums are added in group order: a fixed
@@ -473,7 +572,14 @@ hipError_t launch_gemm(const GemmArgs& g0, hipStream_t s) {
         pieces = (int)std::min<size_t>((size_t)pieces, g.work_floats / std::max<size_t>(per_piece, 1));
     }
     if (pieces <= 1) {
-        launch_tile_kernel(g, grid, 0, nullptr, s);
+        if (!g.transA && !g.colsum_B && tiles <= 256 && vector_path(g)) {
+            // tall products: 32-row tiles, twice the workgroups
+            const dim3 g32((g.M + 31) / 32, (g.N + BN - 1) / BN);
+            if (g.transB) hipLaunchKernelGGL(k_gemm_v32<true>, g32, dim3(256), 0, s, g);
+            else hipLaunchKernelGGL(k_gemm_v32<false>, g32, dim3(256), 0, s, g);
+        } else {
+            launch_tile_kernel(g, grid, 0, nullptr, s);
+        }
     } else {
         const int kpiece = ((g.K + pieces - 1) / pieces + VK - 1) / VK * VK;
         pieces = (g.K + kpiece - 1) / kpiece;

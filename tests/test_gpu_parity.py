@@ -412,6 +412,16 @@ def test_invalid_arguments(ld):
         s.step(1, -1.0)
     with pytest.raises(ld.LdError):
         s.set_tuning(block=96)
+    # the degenerate sizes: a single particle has no pair, and is refused
+    # like an empty system (n must be at least 2), also as an ensemble droplet
+    with pytest.raises(ld.LdError) as e:
+        ld.System(w.type[:1], w.charge[:1], w.pos[:1], w.params, w.radius, 1)
+    assert "n=1" in str(e.value)
+    d1 = W.config_small(n=1000)
+    d1.n, d1.type, d1.charge, d1.pos = 1, d1.type[:1], d1.charge[:1], d1.pos[:1]
+    with pytest.raises(ld.LdError) as e:
+        ld.Ensemble([W.config_small(n=100), d1])
+    assert "fewer than 2" in str(e.value)
 
 
 def test_blowup_reported(ld):
