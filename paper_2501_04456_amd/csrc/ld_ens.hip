@@ -49,6 +49,17 @@ __device__ __forceinline__ void wave_sync() {
 
 __global__ void k_ens_reset(unsigned* counter) { *counter = 0u; }
 
+// The careful loop works on positions relative to the tile box's centre when
+// the box is compact (half-extent below kRelReach sigma: |x - c| < 256 sigma,
+// so (hi - c) + lo carries at most two FP32 roundings of 2^-17 sigma); a box
+// stretched by NPs thrown far out keeps the exact (hi, lo) differences.
+constexpr float kRelReach = 255.f;
+
+__device__ __forceinline__ bool tile_compact(const Box& b) {
+    const float ext = fmaxf(fmaxf(b.hi.x - b.lo.x, b.hi.y - b.lo.y), b.hi.z - b.lo.z);
+    return ext < 2.f * kRelReach;           // false for NaN or infinite boxes too
+}
+
 template <int COMP, bool CULL, int UNROLL>
 __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
     const float4* __restrict__ pos, const float4* __restrict__ lo, const int* __restrict__ typ,
@@ -56,6 +67,7 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
     const Box* __restrict__ box, const int* __restrict__ tbase, double* __restrict__ F,
     int total, unsigned* __restrict__ nearbits, int nb_words) {
     __shared__ float4 sp[kWaves][kGroup];
+    __shared__ float4 sl[kWaves][kGroup];          // low words (stretched tiles only)
     const int w = threadIdx.x / kGroup;
     const int lane = threadIdx.x % kGroup;
     for (;;) {
@@ -81,10 +93,12 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
                                __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.y))),
                                __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.z))),
                                0.f);
+        bool rel = false;
         if constexpr (CULL) {
             bi = box[t0 + it.y / kGroup];
             c = make_float4(0.5f * (bi.lo.x + bi.hi.x), 0.5f * (bi.lo.y + bi.hi.y),
                             0.5f * (bi.lo.z + bi.hi.z), 0.f);
+            rel = tile_compact(bi);
         }
         const float4 pr = make_float4((pi.x - c.x) + li.x, (pi.y - c.y) + li.y,
                                       (pi.z - c.z) + li.z, pi.w);
@@ -102,15 +116,22 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair(
             wave_sync();
             const int j = jt + lane;
             float4 pj = j < nd ? pos[o + j] : make_float4(kFarAway, kFarAway, kFarAway, 0.f);
-            if (near && j < nd) {              // near tiles: relative to c, low words in
+            if (near && j < nd) {              // near tiles: relative to c, or low words apart
                 const float4 lj = lo[o + j];
-                pj = make_float4((pj.x - c.x) + lj.x, (pj.y - c.y) + lj.y, (pj.z - c.z) + lj.z,
-                                 pj.w);
+                if (rel)
+                    pj = make_float4((pj.x - c.x) + lj.x, (pj.y - c.y) + lj.y,
+                                     (pj.z - c.z) + lj.z, pj.w);
+                else
+                    sl[w][lane] = lj;
+            } else if (near && !rel) {
+                sl[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
             sp[w][lane] = pj;
             wave_sync();
             if (near) {
-                const bool lj = pair::group_near_rel<COMP, false>(sp[w], jt, i, pr, cull2, a);
+                const bool lj =
+                    rel ? pair::group_near_rel<COMP, false>(sp[w], jt, i, pr, cull2, a)
+                        : pair::group_near<COMP, false>(sp[w], sl[w], jt, i, pi, li, cull2, a);
                 // tile pairs with a Lennard-Jones candidate, for k_ens_lj
                 if (__ballot(lj && live) && lane == 0) {
                     const int gj = jt / kGroup;
@@ -179,11 +200,13 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair_b(
                                __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.y))),
                                __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pi.z))),
                                0.f);
+        bool rel = false;
         if constexpr (CULL) {
             if (wlive) {
                 bi = box[t0 + i0 / kGroup];
                 c = make_float4(0.5f * (bi.lo.x + bi.hi.x), 0.5f * (bi.lo.y + bi.hi.y),
                                 0.5f * (bi.lo.z + bi.hi.z), 0.f);
+                rel = tile_compact(bi);
             }
         }
         const float4 pr = make_float4((pi.x - c.x) + li.x, (pi.y - c.y) + li.y,
@@ -209,17 +232,23 @@ __global__ __launch_bounds__(kEnsBlock, 6) void k_ens_pair_b(
                     if (!near && !coulomb) continue;
                 }
                 if (near) {
-                    const int j = jg + lane;
-                    float4 pj = sp[g * kGroup + lane];
-                    if (j < nd) {
-                        const float4 lj = sl[g * kGroup + lane];
-                        pj = make_float4((pj.x - c.x) + lj.x, (pj.y - c.y) + lj.y,
-                                         (pj.z - c.z) + lj.z, pj.w);
+                    bool lj;
+                    if (rel) {
+                        const int j = jg + lane;
+                        float4 pj = sp[g * kGroup + lane];
+                        if (j < nd) {
+                            const float4 lw = sl[g * kGroup + lane];
+                            pj = make_float4((pj.x - c.x) + lw.x, (pj.y - c.y) + lw.y,
+                                             (pj.z - c.z) + lw.z, pj.w);
+                        }
+                        wave_sync();
+                        sr[w][lane] = pj;
+                        wave_sync();
+                        lj = pair::group_near_rel<COMP, false>(sr[w], jg, i, pr, cull2, a);
+                    } else {
+                        lj = pair::group_near<COMP, false>(sp + g * kGroup, sl + g * kGroup, jg,
+                                                           i, pi, li, cull2, a);
                     }
-                    wave_sync();
-                    sr[w][lane] = pj;
-                    wave_sync();
-                    const bool lj = pair::group_near_rel<COMP, false>(sr[w], jg, i, pr, cull2, a);
                     if (__ballot(lj && live) && lane == 0) {
                         const int gj = jg / kGroup;
                         atomicOr(&nearbits[(size_t)(t0 + i0 / kGroup) * nb_words + (gj >> 5)],

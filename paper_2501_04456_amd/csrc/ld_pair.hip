@@ -44,7 +44,12 @@ using namespace pair;
 #define LD_PAIR_MIN_WAVES 6
 #endif
 
-template <int BLOCK, int COMP, bool DIAG, bool CULL>
+constexpr float kRelReach = 255.f;         // sigma; see the near-loop choice in k_pair
+#ifndef LD_PAIR_REL_GUARD
+#define LD_PAIR_REL_GUARD 1
+#endif
+
+template <int BLOCK, int COMP, bool DIAG, bool CULL, bool REL>
 __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_pair(const float4* __restrict__ pos,
                                                 const float4* __restrict__ lo,
                                                 const Box* __restrict__ box, int n,
@@ -53,15 +58,47 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
                                                 double* __restrict__ S_out,
                                                 double* __restrict__ U_out,
                                                 unsigned* __restrict__ nearbits, int nb_words) {
-    __shared__ float4 sp[BLOCK];
-    __shared__ float4 sr[BLOCK];             // positions relative to c (near loop only)
+    __shared__ float4 sp[BLOCK];             // j tile, high words
+    __shared__ float4 sr[BLOCK];             // near loop: positions relative to c, or low words
 
     const int tid = threadIdx.x;
+    const int ngroups = (n + kGroup - 1) / kGroup;
+    // A small margin covers FP32 rounding of box distances against r^2.
+    const float cull2 = rc2max * 1.0001f;
+    // Near loop on positions relative to c, the centre of the box of the
+    // workgroup's BLOCK slots, when that box is compact (half-extent below
+    // kRelReach: |x - c| < 256 sigma, so (hi - c) + lo carries at most two
+    // FP32 roundings of 2^-17 sigma, 1.5e-5 sigma, and in practice a few
+    // times less, most near pairs sitting tens of sigma from c); otherwise,
+    // and without culling (no boxes), on exact (hi, lo) differences, e.g.
+    // where a blown-up step has thrown NPs far out or the slots are not in
+    // spatial order.  The choice is uniform per workgroup and made before
+    // anything else is loaded; the two kinds are separate instances (REL)
+    // launched on the same grid, each leaving the other's workgroups at
+    // once, so each keeps its own register allocation.
+    bool rel = false;
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (CULL && !DIAG) {
+        float3 blo = make_float3(INFINITY, INFINITY, INFINITY);
+        float3 bhi = make_float3(-INFINITY, -INFINITY, -INFINITY);
+        for (int q = 0; q < BLOCK / kGroup; ++q) {
+            const int gq = blockIdx.x * (BLOCK / kGroup) + q;
+            if (gq >= ngroups) break;
+            const Box bq = box[gq];
+            blo = make_float3(fminf(blo.x, bq.lo.x), fminf(blo.y, bq.lo.y), fminf(blo.z, bq.lo.z));
+            bhi = make_float3(fmaxf(bhi.x, bq.hi.x), fmaxf(bhi.y, bq.hi.y), fmaxf(bhi.z, bq.hi.z));
+        }
+        c = make_float4(0.5f * (blo.x + bhi.x), 0.5f * (blo.y + bhi.y), 0.5f * (blo.z + bhi.z),
+                        0.f);
+        const float ext = fmaxf(fmaxf(bhi.x - blo.x, bhi.y - blo.y), bhi.z - blo.z);
+        rel = !LD_PAIR_REL_GUARD || ext < 2.f * kRelReach;    // false for NaN or infinite boxes
+    }
+    if (rel != REL) return;                      // uniform per workgroup
+
     const int i = blockIdx.x * BLOCK + tid;
     const bool live = i < n;
     const float4 pi = live ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 li = live ? lo[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const int ngroups = (n + kGroup - 1) / kGroup;
 
     // This wavefront's bounding box (culling only).
     Box bi;
@@ -74,24 +111,6 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
             bi.hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
         }
     }
-    // A small margin covers FP32 rounding of box distances against r^2.
-    const float cull2 = rc2max * 1.0001f;
-    // Origin of the near loop's positions: the centre of the box of the
-    // workgroup's BLOCK slots (culling), else its first particle.
-    float4 c = pos[blockIdx.x * BLOCK];
-    if constexpr (CULL) {
-        float3 blo = make_float3(INFINITY, INFINITY, INFINITY);
-        float3 bhi = make_float3(-INFINITY, -INFINITY, -INFINITY);
-        for (int q = 0; q < BLOCK / kGroup; ++q) {
-            const int gq = blockIdx.x * (BLOCK / kGroup) + q;
-            if (gq >= ngroups) break;
-            const Box bq = box[gq];
-            blo = make_float3(fminf(blo.x, bq.lo.x), fminf(blo.y, bq.lo.y), fminf(blo.z, bq.lo.z));
-            bhi = make_float3(fmaxf(bhi.x, bq.hi.x), fmaxf(bhi.y, bq.hi.y), fmaxf(bhi.z, bq.hi.z));
-        }
-        c = make_float4(0.5f * (blo.x + bhi.x), 0.5f * (blo.y + bhi.y), 0.5f * (blo.z + bhi.z),
-                        0.f);
-    }
     const float4 pr = make_float4((pi.x - c.x) + li.x, (pi.y - c.y) + li.y, (pi.z - c.z) + li.z,
                                   pi.w);
 
@@ -103,11 +122,13 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
         __syncthreads();
         const int j = jt + tid;
         {
-            float4 h = make_float4(kFarAway, kFarAway, kFarAway, 0.f), r = h;
+            float4 h = make_float4(kFarAway, kFarAway, kFarAway, 0.f);
+            float4 r = REL ? h : make_float4(0.f, 0.f, 0.f, 0.f);
             if (j < j1) {
                 h = pos[j];
                 const float4 l = lo[j];
-                r = make_float4((h.x - c.x) + l.x, (h.y - c.y) + l.y, (h.z - c.z) + l.z, h.w);
+                r = REL ? make_float4((h.x - c.x) + l.x, (h.y - c.y) + l.y, (h.z - c.z) + l.z, h.w)
+                        : l;
             }
             sp[tid] = h;
             sr[tid] = r;
@@ -130,7 +151,12 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
             }
             if constexpr (DIAG) near = true;
             if (__builtin_amdgcn_readfirstlane((int)near)) {
-                const bool lj = group_near_rel<COMP, DIAG>(sr + g * kGroup, jg, i, pr, cull2, a);
+                bool lj;
+                if constexpr (REL)
+                    lj = group_near_rel<COMP, DIAG>(sr + g * kGroup, jg, i, pr, cull2, a);
+                else
+                    lj = group_near<COMP, DIAG>(sp + g * kGroup, sr + g * kGroup, jg, i, pi, li,
+                                                cull2, a);
                 // record the pair of groups if it holds a Lennard-Jones
                 // candidate, for the Lennard-Jones kernel
                 if (nearbits && __ballot(lj && live) && (tid & (kGroup - 1)) == 0) {
@@ -281,8 +307,14 @@ hipError_t launch_t(const PairLaunch& L, const PairTable& tab, hipStream_t s) {
     const int tiles = (L.n + BLOCK - 1) / BLOCK;
     const int per = (tiles + L.j_split - 1) / L.j_split;
     dim3 grid(tiles, L.j_split);
-    hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL>), grid, dim3(BLOCK), 0, s, L.pos, L.lo,
-                       L.box, L.n, per * BLOCK, tab.rc2max, L.Fpart, L.S, L.U, L.nearbits,
+    if constexpr (CULL && !DIAG) {               // compact workgroups: relative positions
+        hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL, true>), grid, dim3(BLOCK), 0, s,
+                           L.pos, L.lo, L.box, L.n, per * BLOCK, tab.rc2max, L.Fpart, L.S, L.U,
+                           L.nearbits, L.nb_words);
+        if (!LD_PAIR_REL_GUARD) return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL, false>), grid, dim3(BLOCK), 0, s, L.pos,
+                       L.lo, L.box, L.n, per * BLOCK, tab.rc2max, L.Fpart, L.S, L.U, L.nearbits,
                        L.nb_words);
     return hipGetLastError();
 }

@@ -66,6 +66,50 @@ __device__ __forceinline__ void group_far(const float4* __restrict__ sp, const f
 }
 
 // 64 j particles near i's group (within the largest LJ range of its box) or
+// holding i itself: the Coulomb terms with the low words of the positions
+// in the differences, the self pair left out.  The difference of the FP32
+// high words of two nearby particles is exact, and adding the difference of
+// their low words gives r_ij to FP32 rounding of r_ij itself.  Used where
+// the relative positions below would lose too much (a workgroup whose box
+// is stretched by NPs thrown far out).  Returns whether any j of the group
+// lies within sqrt(lj2) of i (i itself excluded).
+template <int COMP, bool DIAG>
+__device__ __forceinline__ bool group_near(const float4* __restrict__ sp,
+                                           const float4* __restrict__ sl, int jbase, int i,
+                                           const float4 pi, const float4 li, float lj2, Acc& a) {
+    bool lj_any = false;
+#pragma unroll
+    for (int kb = 0; kb < kGroup; kb += KB) {
+        float bx = 0.f, by = 0.f, bz = 0.f;   // Coulomb, FP32 block
+#pragma unroll 4
+        for (int k = 0; k < KB; ++k) {
+            const float4 pj = sp[kb + k];
+            const float4 lj = sl[kb + k];
+            const float dx = (pj.x - pi.x) + (lj.x - li.x);
+            const float dy = (pj.y - pi.y) + (lj.y - li.y);
+            const float dz = (pj.z - pi.z) + (lj.z - li.z);
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const bool self = jbase + kb + k == i;
+            const float w = self ? 0.f : (pj.w * ri) * (ri * ri);
+            lj_any |= r2 < lj2 && !self;
+            if constexpr (DIAG) {
+                if (!self) {
+                    const float qq = pi.w * pj.w;
+                    a.S += (double)(fabsf(qq) * ri * ri);
+                    a.Uc += 0.5 * (double)(qq * ri);
+                }
+            }
+            bx = fmaf(w, dx, bx);
+            by = fmaf(w, dy, by);
+            bz = fmaf(w, dz, bz);
+        }
+        flush<COMP>(a, bx, by, bz);
+    }
+    return lj_any;
+}
+
+// 64 j particles near i's group (within the largest LJ range of its box) or
 // holding i itself: the Coulomb terms, the self pair left out, from
 // positions taken relative to an origin c near both groups (the centre of
 // the box of the workgroup's slots, or of the ensemble tile's box).  Each

@@ -123,6 +123,22 @@ def test_forces_tunings_ragged(ld, orc, n, tune):
     check_forces(w, Fg, orc=orc)
 
 
+def test_forces_with_far_outlier(ld, orc):
+    """One NP far outside the droplet (as a blown-up step leaves it): the
+    workgroup and ensemble tile whose boxes it stretches use the exact
+    (hi, lo) differences in their careful loops, the others positions
+    relative to their box centres; every row stays within tolerance."""
+    w = W.config_large(n=3001, seed=33)
+    w.pos = w.pos.copy()
+    w.pos[1234] = np.array([2500.0, -40.0, 10.0], np.float32)
+    s = ld.System.from_workload(w)
+    Fg = s.forces(ext=False)["pair"].cpu().numpy()
+    check_forces(w, Fg, orc=orc)
+    ens = ld.Ensemble([w, W.config_small(n=500)])
+    Fe = ens.forces().cpu().numpy()[:w.n]
+    check_forces(w, Fe, orc=orc)
+
+
 def test_forces_dense_lj(ld, orc):
     """A compact cluster so that many pairs are inside the LJ range, with an
     explicit (non-Lorentz-Berthelot) eps matrix."""
