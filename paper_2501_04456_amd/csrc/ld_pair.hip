@@ -73,9 +73,15 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
     // and without culling (no boxes), on exact (hi, lo) differences, e.g.
     // where a blown-up step has thrown NPs far out or the slots are not in
     // spatial order.  The choice is uniform per workgroup and made before
-    // anything else is loaded; the two kinds are separate instances (REL)
-    // launched on the same grid, each leaving the other's workgroups at
-    // once, so each keeps its own register allocation.
+    // anything else is loaded.  The two loops are separate instances (REL),
+    // so the common one keeps its own register allocation, launched on the
+    // same grid: first the exact one, which leaves compact workgroups at
+    // once and takes only the near group pairs of stretched ones; then the
+    // relative one, which takes compact workgroups whole and the far group
+    // pairs of stretched ones, adding them to what the exact one wrote.  A
+    // stretched workgroup thus adds no long serial tail after the relative
+    // launch.  Without culling, or in diagnostic mode, the exact instance
+    // runs alone and takes everything.
     bool rel = false;
     float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (CULL && !DIAG) {
@@ -93,7 +99,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
         const float ext = fmaxf(fmaxf(bhi.x - blo.x, bhi.y - blo.y), bhi.z - blo.z);
         rel = !LD_PAIR_REL_GUARD || ext < 2.f * kRelReach;    // false for NaN or infinite boxes
     }
-    if (rel != REL) return;                      // uniform per workgroup
+    constexpr bool SPLIT = CULL && !DIAG;
+    if (!REL && rel) return;                     // uniform per workgroup
 
     const int i = blockIdx.x * BLOCK + tid;
     const bool live = i < n;
@@ -144,10 +151,21 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
                 bool coulomb = false;
                 if (jg < j1 && gj < ngroups) {
                     const Box bj = box[gj];
-                    near = box_dist2(bi, bj) < cull2;
+                    if (REL && rel) {
+                        near = box_dist2(bi, bj) < cull2;
+                    } else {
+                        // the i group's own box may be stretched across the
+                        // droplet by one NP thrown out: test each lane's i
+                        near = __ballot(live && point_box_dist2(pi, bj) < cull2) != 0;
+                    }
                     coulomb = bi.lo.w != 0.f && bj.lo.w != 0.f;
                 }
                 if (!near && !__builtin_amdgcn_readfirstlane((int)coulomb)) continue;
+                // a stretched workgroup's near pairs go to the exact
+                // instance, its far ones to the relative instance
+                if constexpr (SPLIT) {
+                    if (REL ? (!rel && near) : !near) continue;
+                }
             }
             if constexpr (DIAG) near = true;
             if (__builtin_amdgcn_readfirstlane((int)near)) {
@@ -177,9 +195,15 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
         // F_i = -q_i sum_j q_j r^-3 (x_j - x_i)
         const double qi = (double)pi.w;
         double* F = Fpart + (size_t)blockIdx.y * 3 * (size_t)n;
-        F[i] = -qi * a.Fx;
-        F[(size_t)n + i] = -qi * a.Fy;
-        F[2 * (size_t)n + i] = -qi * a.Fz;
+        if (REL && !rel) {                       // after the exact instance's near part
+            F[i] += -qi * a.Fx;
+            F[(size_t)n + i] += -qi * a.Fy;
+            F[2 * (size_t)n + i] += -qi * a.Fz;
+        } else {
+            F[i] = -qi * a.Fx;
+            F[(size_t)n + i] = -qi * a.Fy;
+            F[2 * (size_t)n + i] = -qi * a.Fz;
+        }
         if constexpr (DIAG) {
             S_out[i] = a.S;
             U_out[i] = 0.0;
@@ -307,15 +331,17 @@ hipError_t launch_t(const PairLaunch& L, const PairTable& tab, hipStream_t s) {
     const int tiles = (L.n + BLOCK - 1) / BLOCK;
     const int per = (tiles + L.j_split - 1) / L.j_split;
     dim3 grid(tiles, L.j_split);
-    if constexpr (CULL && !DIAG) {               // compact workgroups: relative positions
+    // with culling: the exact instance (stretched workgroups' near pairs)
+    // first, then the relative one, which adds to it; otherwise the exact
+    // instance alone
+    if (!(CULL && !DIAG) || LD_PAIR_REL_GUARD)
+        hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL, false>), grid, dim3(BLOCK), 0, s,
+                           L.pos, L.lo, L.box, L.n, per * BLOCK, tab.rc2max, L.Fpart, L.S, L.U,
+                           L.nearbits, L.nb_words);
+    if constexpr (CULL && !DIAG)
         hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL, true>), grid, dim3(BLOCK), 0, s,
                            L.pos, L.lo, L.box, L.n, per * BLOCK, tab.rc2max, L.Fpart, L.S, L.U,
                            L.nearbits, L.nb_words);
-        if (!LD_PAIR_REL_GUARD) return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_pair<BLOCK, COMP, DIAG, CULL, false>), grid, dim3(BLOCK), 0, s, L.pos,
-                       L.lo, L.box, L.n, per * BLOCK, tab.rc2max, L.Fpart, L.S, L.U, L.nearbits,
-                       L.nb_words);
     return hipGetLastError();
 }
 

@@ -191,5 +191,13 @@ __device__ __forceinline__ float box_dist2(const Box& a, const Box& b) {
     return gx * gx + gy * gy + gz * gz;
 }
 
+// Squared distance from point p to box b (0 inside; NaN coordinates give 0).
+__device__ __forceinline__ float point_box_dist2(const float4& p, const Box& b) {
+    const float gx = fmaxf(0.f, fmaxf(b.lo.x - p.x, p.x - b.hi.x));
+    const float gy = fmaxf(0.f, fmaxf(b.lo.y - p.y, p.y - b.hi.y));
+    const float gz = fmaxf(0.f, fmaxf(b.lo.z - p.z, p.z - b.hi.z));
+    return gx * gx + gy * gy + gz * gz;
+}
+
 }  // namespace pair
 }  // namespace ld

@@ -123,17 +123,31 @@ def test_forces_tunings_ragged(ld, orc, n, tune):
     check_forces(w, Fg, orc=orc)
 
 
-def test_forces_with_far_outlier(ld, orc):
-    """One NP far outside the droplet (as a blown-up step leaves it): the
-    workgroup and ensemble tile whose boxes it stretches use the exact
-    (hi, lo) differences in their careful loops, the others positions
-    relative to their box centres; every row stays within tolerance."""
+@pytest.mark.parametrize("tune", [dict(), dict(block=128, j_split=3, comp=0),
+                                  dict(block=512, j_split=2, comp=1)])
+def test_forces_with_far_outliers(ld, orc, tune):
+    """Two NPs 1.24 sigma apart far outside the droplet (as a blown-up step
+    leaves them), every position carrying a low FP32 word: the workgroups
+    and the ensemble tile whose boxes they stretch take their near pairs on
+    the exact (hi, lo) differences (positions relative to a centre some 1250
+    sigma away would move the pair's own force by up to ~1e-4), the far
+    pairs and every other workgroup on positions relative to box centres;
+    every row stays within tolerance."""
     w = W.config_large(n=3001, seed=33)
-    w.pos = w.pos.copy()
-    w.pos[1234] = np.array([2500.0, -40.0, 10.0], np.float32)
+    hi = w.pos.astype(np.float32)
+    hi[1234] = (2500.0, -40.0, 10.0)
+    hi[77] = (2501.2, -40.3, 10.1)
+    rng = np.random.default_rng(7)
+    lo = (rng.uniform(-0.5, 0.5, hi.shape) * np.spacing(np.abs(hi))).astype(np.float32)
+    w.pos = hi
     s = ld.System.from_workload(w)
+    s.set_tuning(**tune)
+    s.set_positions(hi, lo)
+    w64 = w.replace(pos=hi.astype(np.float64) + lo.astype(np.float64))
     Fg = s.forces(ext=False)["pair"].cpu().numpy()
-    check_forces(w, Fg, orc=orc)
+    check_forces(w64, Fg, orc=orc)
+    if tune:
+        return
     ens = ld.Ensemble([w, W.config_small(n=500)])
     Fe = ens.forces().cpu().numpy()[:w.n]
     check_forces(w, Fe, orc=orc)
