@@ -123,20 +123,23 @@ def test_forces_tunings_ragged(ld, orc, n, tune):
     check_forces(w, Fg, orc=orc)
 
 
-@pytest.mark.parametrize("tune", [dict(), dict(block=128, j_split=3, comp=0),
-                                  dict(block=512, j_split=2, comp=1)])
-def test_forces_with_far_outliers(ld, orc, tune):
+@pytest.mark.parametrize("far,tune", [(2500.0, dict()),
+                                      (2500.0, dict(block=128, j_split=3, comp=0)),
+                                      (2500.0, dict(block=512, j_split=2, comp=1)),
+                                      (1.0e6, dict())])
+def test_forces_with_far_outliers(ld, orc, far, tune):
     """Two NPs 1.24 sigma apart far outside the droplet (as a blown-up step
     leaves them), every position carrying a low FP32 word: the workgroups
     and the ensemble tile whose boxes they stretch take their near pairs on
-    the exact (hi, lo) differences (positions relative to a centre some 1250
-    sigma away would move the pair's own force by up to ~1e-4), the far
-    pairs and every other workgroup on positions relative to box centres;
-    every row stays within tolerance."""
+    the exact (hi, lo) differences (positions relative to a centre some
+    far/2 away would move the pair's own force by up to ~1e-4 at 2500 sigma
+    and by several per cent at 1e6 sigma), the far pairs and every other
+    workgroup on positions relative to box centres; every row stays within
+    tolerance."""
     w = W.config_large(n=3001, seed=33)
     hi = w.pos.astype(np.float32)
-    hi[1234] = (2500.0, -40.0, 10.0)
-    hi[77] = (2501.2, -40.3, 10.1)
+    hi[1234] = (far, -40.0, 10.0)
+    hi[77] = (far + 1.2, -40.3, 10.1)
     rng = np.random.default_rng(7)
     lo = (rng.uniform(-0.5, 0.5, hi.shape) * np.spacing(np.abs(hi))).astype(np.float32)
     w.pos = hi
