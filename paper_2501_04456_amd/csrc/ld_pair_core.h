@@ -16,6 +16,13 @@
 namespace ld {
 namespace pair {
 
+// Upper bound on the FP32 1/r of the near loops: 1/r of any two distinct
+// particles is far below it (they never come within 1e-10 sigma), and
+// |q_j| kInvRCap^3 stays finite, so the self pair (r = 0) adds w * 0 = 0.
+// Two distinct particles at bitwise equal positions would get a zero
+// Coulomb term here (their Lennard-Jones term is still infinite).
+constexpr float kInvRCap = 1e10f;
+
 constexpr int KB = 32;
 
 struct Acc {
@@ -72,7 +79,8 @@ __device__ __forceinline__ void group_far(const float4* __restrict__ sp, const f
 // their low words gives r_ij to FP32 rounding of r_ij itself.  Used where
 // the relative positions below would lose too much (a workgroup whose box
 // is stretched by NPs thrown far out).  Returns whether any j of the group
-// lies within sqrt(lj2) of i (i itself excluded).
+// lies within sqrt(lj2) of i (i itself counts, so the group holding i is
+// always flagged; the Lennard-Jones kernels skip j = i).
 template <int COMP, bool DIAG>
 __device__ __forceinline__ bool group_near(const float4* __restrict__ sp,
                                            const float4* __restrict__ sl, int jbase, int i,
@@ -89,12 +97,13 @@ __device__ __forceinline__ bool group_near(const float4* __restrict__ sp,
             const float dy = (pj.y - pi.y) + (lj.y - li.y);
             const float dz = (pj.z - pi.z) + (lj.z - li.z);
             const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float ri = __builtin_amdgcn_rsqf(r2);
-            const bool self = jbase + kb + k == i;
-            const float w = self ? 0.f : (pj.w * ri) * (ri * ri);
-            lj_any |= r2 < lj2 && !self;
+            // the self pair has dx = dy = dz = 0 exactly; capping 1/r keeps
+            // its weight finite, so its term is 0 without a test
+            const float ri = fminf(__builtin_amdgcn_rsqf(r2), kInvRCap);
+            const float w = (pj.w * ri) * (ri * ri);
+            lj_any |= r2 < lj2;                 // the self pair flags the diagonal group
             if constexpr (DIAG) {
-                if (!self) {
+                if (jbase + kb + k != i) {
                     const float qq = pi.w * pj.w;
                     a.S += (double)(fabsf(qq) * ri * ri);
                     a.Uc += 0.5 * (double)(qq * ri);
@@ -121,8 +130,9 @@ __device__ __forceinline__ bool group_near(const float4* __restrict__ sp,
 // read and three subtractions per pair, as in the far loop.  The
 // Lennard-Jones terms of these groups are added by a kernel of their own
 // (k_lj), in FP64 from the exact (hi, lo) differences.  Returns whether any
-// j of the group lies within sqrt(lj2) of i (i itself excluded): the
-// Lennard-Jones kernel visits only such group pairs.
+// j of the group lies within sqrt(lj2) of i (i itself counts, so the group
+// holding i is always flagged): the Lennard-Jones kernel visits only such
+// group pairs and skips j = i.
 template <int COMP, bool DIAG>
 __device__ __forceinline__ bool group_near_rel(const float4* __restrict__ sr, int jbase, int i,
                                                const float4 ri4, float lj2, Acc& a) {
@@ -135,12 +145,13 @@ __device__ __forceinline__ bool group_near_rel(const float4* __restrict__ sr, in
             const float4 pj = sr[kb + k];
             const float dx = pj.x - ri4.x, dy = pj.y - ri4.y, dz = pj.z - ri4.z;
             const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float ri = __builtin_amdgcn_rsqf(r2);
-            const bool self = jbase + kb + k == i;
-            const float w = self ? 0.f : (pj.w * ri) * (ri * ri);
-            lj_any |= r2 < lj2 && !self;
+            // the self pair has dx = dy = dz = 0 exactly; capping 1/r keeps
+            // its weight finite, so its term is 0 without a test
+            const float ri = fminf(__builtin_amdgcn_rsqf(r2), kInvRCap);
+            const float w = (pj.w * ri) * (ri * ri);
+            lj_any |= r2 < lj2;                 // the self pair flags the diagonal group
             if constexpr (DIAG) {
-                if (!self) {
+                if (jbase + kb + k != i) {
                     const float qq = ri4.w * pj.w;
                     a.S += (double)(fabsf(qq) * ri * ri);
                     a.Uc += 0.5 * (double)(qq * ri);
