@@ -941,6 +941,16 @@ ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int3
     std::snprintf(key, sizeof key, "ens2/%s/d%d/p%d/m%d/cull%d/comp%d", arch, e->n_drop,
                   (int)std::floor(std::log2(pairs) * 4.0),
                   (int)std::floor(std::log2((double)nmax) * 4.0), e->cull ? 1 : 0, e->comp);
+    // Time the slot order the steps will use: a sort that is due (a new
+    // ensemble sorts before its first step) is done now, as that step would
+    // have done it, so the trajectory is unchanged; an unsorted ensemble
+    // would have most tile pairs take the careful loop and rank the far
+    // loop's settings wrongly.
+    if (e->cull && e->steps_since_sort >= sort_interval(e)) {
+        const ld_status st = enqueue_sort(e, e->stream);
+        if (st != LD_OK) return st;
+        e->steps_since_sort = 0;
+    }
     int best_w = e->workgroups, best_u = e->unroll, best_r = e->rows;
     bool cached = false;
     if (cache_path && !force) {
@@ -970,21 +980,22 @@ ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int3
         const int unrolls[] = {8, 16, 32};
         const int item_rows[] = {64, 256};
         ld_status st = LD_OK;
-        // fastest of `reps` timed launches (after one warm-up) of a setting
-        auto time_setting = [&](int w, int u, int r, int reps) {
+        // fastest of `reps` timed bursts of `burst` back-to-back launches
+        // (after one warm-up burst) of a setting, per launch
+        auto time_setting = [&](int w, int u, int r, int reps, int burst) {
             e->rows = r;
             e->unroll = u;
             e->workgroups = w;
             double ms_min = INFINITY;
             for (int rep = 0; rep <= reps && st == LD_OK; ++rep) {
                 if (hipEventRecord(e0, e->stream) != hipSuccess) st = LD_EHIP;
-                if (st == LD_OK) st = enqueue_pair(e, e->stream);
+                for (int b = 0; b < burst && st == LD_OK; ++b) st = enqueue_pair(e, e->stream);
                 if (st == LD_OK && hipEventRecord(e1, e->stream) != hipSuccess) st = LD_EHIP;
                 if (st == LD_OK && hipEventSynchronize(e1) != hipSuccess) st = LD_EHIP;
                 float ms = 0.f;
                 if (st == LD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                     st = LD_EHIP;
-                if (rep > 0 && ms < ms_min) ms_min = ms;
+                if (rep > 0 && ms / burst < ms_min) ms_min = ms / burst;
             }
             return ms_min;
         };
@@ -999,18 +1010,20 @@ ld_status ld_ens_autotune(ld_ens* e, const char* cache_path, int32_t force, int3
                     if (st != LD_OK) break;
                     e->rows = r;
                     const int w = std::max(1, std::min(cus * k, max_workgroups(e)));
-                    cands.push_back({time_setting(w, u, r, 3), w, u, r});
+                    cands.push_back({time_setting(w, u, r, 3, 1), w, u, r});
                 }
-        // One pass leaves settings within a few per cent of each other in an
-        // order the clock's drift can decide: the four best are timed again
-        // in three interleaved rounds and ranked by their summed times.
+        // One pass of single launches leaves settings within a few per cent
+        // of each other, in an order that the clock's state can decide and
+        // that need not hold under sustained load: the four best are timed
+        // again as bursts of launches in three interleaved rounds and
+        // ranked by their summed times.
         std::sort(cands.begin(), cands.end(),
                   [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
         const int top = std::min<int>(4, (int)cands.size());
         std::vector<double> sum(top, 0.0);
         for (int round = 0; round < 3 && st == LD_OK; ++round)
             for (int c = 0; c < top && st == LD_OK; ++c)
-                sum[c] += time_setting(cands[c].w, cands[c].u, cands[c].r, 3);
+                sum[c] += time_setting(cands[c].w, cands[c].u, cands[c].r, 2, 6);
         for (int c = 0; c < top && st == LD_OK; ++c)
             if (sum[c] / 3.0 < best_ms) {
                 best_ms = sum[c] / 3.0;

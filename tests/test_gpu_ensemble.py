@@ -260,21 +260,30 @@ def test_ensemble_autotune_and_cache(ld, orc, small_ensemble, tmp_path):
         Fo, So, _ = orc.pair_forces(w.pos, w.type, w.charge, w.params)
         dF = np.linalg.norm(F[off[d]:off[d + 1]] - Fo, axis=1)
         assert np.all(dF <= 1e-5 * So), d
-    # the searched settings only change which wavefront takes which tile and
-    # how many pairs are in flight, never the order of any sum: the forces
-    # are bit for bit those of an untuned ensemble, whatever the settings
-    e0 = ld.Ensemble(small_ensemble.droplets)
-    F0 = e0.forces().cpu().numpy()
-    assert np.array_equal(F, F0)
-    for wg, un, rows in ((64, 8, 64), (300, 32, 64), (7, 16, 256), (500, 8, 256)):
-        e0.set_tuning(workgroups=wg, unroll=un, rows=rows)
-        assert np.array_equal(e0.forces().cpu().numpy(), F0), (wg, un, rows)
     line = open(cache).read().split()
     assert line[0].startswith("ens2/") and int(line[1]) == t1["workgroups"]
     assert int(line[2]) == t1["unroll"] and int(line[3]) == t1["rows"]
+    # a cache hit takes the same settings and the same (sorted) slot order
     e2 = ld.Ensemble(small_ensemble.droplets)
     t2 = e2.autotune(cache_path=cache)
     assert t2 == t1
+    # the searched settings only change which wavefront takes which tile and
+    # how many pairs are in flight, never the order of any sum: the forces
+    # are bit for bit the same whatever the settings
+    assert np.array_equal(e2.forces().cpu().numpy(), F)
+    for wg, un, rows in ((64, 8, 64), (300, 32, 64), (7, 16, 256), (500, 8, 256)):
+        e2.set_tuning(workgroups=wg, unroll=un, rows=rows)
+        assert np.array_equal(e2.forces().cpu().numpy(), F), (wg, un, rows)
+    e2.set_tuning(**{k: t1[k] for k in ("workgroups", "comp", "graph_steps", "unroll", "rows")})
+    # tuning sorts only where the first step would have: an untuned ensemble
+    # stepped alongside a tuned one follows the same trajectory bit for bit
+    e3 = ld.Ensemble(small_ensemble.droplets)
+    e4 = ld.Ensemble(small_ensemble.droplets)
+    e4.autotune()
+    for e in (e3, e4):
+        e.step(3, 1e-3)
+    assert np.array_equal(e3.positions()[0], e4.positions()[0])
+    assert np.array_equal(e3.positions()[1], e4.positions()[1])
     with pytest.raises(RuntimeError):
         e2.set_tuning(unroll=12)
     with pytest.raises(RuntimeError):
