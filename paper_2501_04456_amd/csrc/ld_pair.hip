@@ -49,6 +49,17 @@ constexpr float kRelReach = 255.f;         // sigma; see the near-loop choice in
 #define LD_PAIR_REL_GUARD 1
 #endif
 
+// Workgroup -> (i tile, j split) on a one-dimensional grid.  Workgroups go
+// to the eight XCDs in turn (linear id mod 8), so XCD k takes i tiles k,
+// k + 8, k + 16, ... for every split, split after split: the i tiles one
+// XCD serves (about an eighth of them) stay in its L2 across the splits
+// instead of every tile being fetched again for each split.  Workgroups
+// past the last tile of an XCD's share leave at once.
+constexpr int kXcds = 8;
+__host__ __device__ inline int pair_grid(int tiles, int j_split) {
+    return kXcds * ((tiles + kXcds - 1) / kXcds) * j_split;
+}
+
 template <int BLOCK, int COMP, bool DIAG, bool CULL, bool REL>
 __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_pair(const float4* __restrict__ pos,
                                                 const float4* __restrict__ lo,
@@ -63,6 +74,12 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
 
     const int tid = threadIdx.x;
     const int ngroups = (n + kGroup - 1) / kGroup;
+    const int tiles = (n + BLOCK - 1) / BLOCK;
+    const int per_xcd = (tiles + kXcds - 1) / kXcds;
+    const int q = (int)blockIdx.x / kXcds;
+    const int tx = (int)blockIdx.x % kXcds + kXcds * (q % per_xcd);   // i tile
+    const int ty = q / per_xcd;                                         // j split
+    if (tx >= tiles) return;                     // uniform per workgroup
     // A small margin covers FP32 rounding of box distances against r^2.
     const float cull2 = rc2max * 1.0001f;
     // Near loop on positions relative to c, the centre of the box of the
@@ -87,8 +104,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
     if constexpr (CULL && !DIAG) {
         float3 blo = make_float3(INFINITY, INFINITY, INFINITY);
         float3 bhi = make_float3(-INFINITY, -INFINITY, -INFINITY);
-        for (int q = 0; q < BLOCK / kGroup; ++q) {
-            const int gq = blockIdx.x * (BLOCK / kGroup) + q;
+        for (int g4 = 0; g4 < BLOCK / kGroup; ++g4) {
+            const int gq = tx * (BLOCK / kGroup) + g4;
             if (gq >= ngroups) break;
             const Box bq = box[gq];
             blo = make_float3(fminf(blo.x, bq.lo.x), fminf(blo.y, bq.lo.y), fminf(blo.z, bq.lo.z));
@@ -102,7 +119,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
     constexpr bool SPLIT = CULL && !DIAG;
     if (!REL && rel) return;                     // uniform per workgroup
 
-    const int i = blockIdx.x * BLOCK + tid;
+    const int i = tx * BLOCK + tid;
     const bool live = i < n;
     const float4 pi = live ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 li = live ? lo[i] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -110,7 +127,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
     // This wavefront's bounding box (culling only).
     Box bi;
     if constexpr (CULL) {
-        const int gi = (blockIdx.x * BLOCK + (tid & ~(kGroup - 1))) / kGroup;
+        const int gi = (tx * BLOCK + (tid & ~(kGroup - 1))) / kGroup;
         if (gi < ngroups) {
             bi = box[gi];
         } else {
@@ -121,7 +138,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
     const float4 pr = make_float4((pi.x - c.x) + li.x, (pi.y - c.y) + li.y, (pi.z - c.z) + li.z,
                                   pi.w);
 
-    const int j0 = blockIdx.y * j_per_split;
+    const int j0 = ty * j_per_split;
     const int j1 = min(n, j0 + j_per_split);
     Acc a;
 #pragma unroll 1
@@ -178,7 +195,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
                 // record the pair of groups if it holds a Lennard-Jones
                 // candidate, for the Lennard-Jones kernel
                 if (nearbits && __ballot(lj && live) && (tid & (kGroup - 1)) == 0) {
-                    const int gi = (blockIdx.x * BLOCK + tid) / kGroup, gj = jg / kGroup;
+                    const int gi = (tx * BLOCK + tid) / kGroup, gj = jg / kGroup;
                     atomicOr(&nearbits[(size_t)gi * nb_words + (gj >> 5)], 1u << (gj & 31));
                 }
             } else {
@@ -194,7 +211,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 1 : LD_PAIR_MIN_WAVES) void k_
     if (live) {
         // F_i = -q_i sum_j q_j r^-3 (x_j - x_i)
         const double qi = (double)pi.w;
-        double* F = Fpart + (size_t)blockIdx.y * 3 * (size_t)n;
+        double* F = Fpart + (size_t)ty * 3 * (size_t)n;
         if (REL && !rel) {                       // after the exact instance's near part
             F[i] += -qi * a.Fx;
             F[(size_t)n + i] += -qi * a.Fy;
@@ -330,7 +347,7 @@ template <int BLOCK, int COMP, bool DIAG, bool CULL>
 hipError_t launch_t(const PairLaunch& L, const PairTable& tab, hipStream_t s) {
     const int tiles = (L.n + BLOCK - 1) / BLOCK;
     const int per = (tiles + L.j_split - 1) / L.j_split;
-    dim3 grid(tiles, L.j_split);
+    const dim3 grid(pair_grid(tiles, L.j_split));
     // with culling: the exact instance (stretched workgroups' near pairs)
     // first, then the relative one, which adds to it; otherwise the exact
     // instance alone
