@@ -513,7 +513,12 @@ ld_status ld_ens_set_rows(ld_ens* e, int32_t rows);
  * unit), unroll (8, 16, 32) and work-item rows (64, 256) by timing the pair
  * step (forces only; the droplets do not move) with HIP events, keeping the
  * compensation mode and graph length; none of the searched settings changes
- * the forces.  cache_path (or NULL): a text file of lines
+ * the forces.  A spatial re-sort that is due (a new ensemble's first, or
+ * one the sort interval calls for) is done first, as the next step would
+ * have done it, so the timings see the slot order the steps use and the
+ * trajectory is unchanged; forces read right after this call come in that
+ * order's summation.  The four fastest settings of one pass are timed again
+ * as bursts of launches.  cache_path (or NULL): a text file of lines
  * "key workgroups unroll rows ms"; the key holds the GPU architecture, the
  * droplet count, quarter-octave buckets of sum_d N_d^2 and of the largest
  * N_d, the culling and compensation modes.  A cached key is used without
