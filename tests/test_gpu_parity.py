@@ -234,6 +234,22 @@ def test_trajectory_large_composition_20_steps(ld, orc):
     assert err <= POS_TOL, err
 
 
+def test_trajectory_with_far_outliers(ld, orc):
+    """Two NPs 1.19 sigma apart 1e6 sigma out (as a blown-up step throws
+    them): both sides flag the same first oversized move, and every position,
+    the pair's and its workgroup's neighbours' included, follows the oracle
+    over 10 steps.  Positions relative to a workgroup centre 5e5 sigma away
+    would misplace the pair by ~0.03 sigma and its force by several per cent."""
+    w = W.config_large(n=3001, seed=34)
+    w.pos = w.pos.copy()
+    w.pos[1234] = (1.0e6, -40.0, 10.0)
+    w.pos[77] = (1.0e6 + 1.2, -40.3, 10.1)
+    xg, xo = trajectory(ld, orc, w, 10)
+    assert np.isfinite(xg).all()
+    err = np.abs(xg - xo).max()
+    assert err <= POS_TOL, err
+
+
 @pytest.mark.parametrize("noise", [W.NOISE_OFF, W.NOISE_FIXED])
 def test_trajectory_noise_modes(ld, orc, noise):
     w = W.config_medium(n=1500, seed=23)
